@@ -1,0 +1,177 @@
+"""Pins of the oracle's bubble dynamics (Sec. 2.1, eq. (1)-(4), Table 1) against values the paper
+prints (Table 4 force-balance and Mendelson columns), textbook terminal velocities in the viscous
+drag branches, and the exact discrete recursion of explicit Euler in the Stokes limit."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table4_terminal_velocity.txt")
+
+# Table 3 (air bubble in water) and standard gravity, SI units
+RHO_L, RHO_B, MU_L, SIGMA, G = 1000.0, 1.0, 1e-3, 0.073, 9.81
+
+
+def _terminal(P, nu, d, dt=1e-5, chunk=20000, tol=1e-12):
+    """Integrate the one-way ODE (quiescent liquid) until the velocity stops changing."""
+    ub = np.zeros(3)
+    xb = np.zeros(3)
+    z3 = np.zeros(3)
+    for _ in range(200):
+        prev = ub[2]
+        ub, xb, _ = O.bubble_ode(P, nu, dt, chunk, d, z3, z3, z3, ub, xb)
+        if abs(ub[2] - prev) < tol:
+            return ub
+    raise AssertionError("no terminal velocity")
+
+
+def _table4():
+    rows = np.loadtxt(GOLDEN, comments="#")
+    return rows[:, 0] * 1e-3, rows[:, 1], rows[:, 2]
+
+
+def test_terminal_velocity_matches_table4_force_balance_column():
+    """Table 4, column "Force balance eq." (eq. (23)-(24)): the ODE's fixed point with the paper's
+    drag closure. Holds only with Eo = (rho_l - rho_b) g d^2 / sigma (d squared) and with rho_l in
+    the drag; the printed values have four decimals."""
+    P = O.bubble_params(g=G, rho_l=RHO_L, rho_b=RHO_B, sigma=SIGMA, c_a=0.5)
+    d_all, fb, _ = _table4()
+    for d, v in zip(d_all, fb):
+        ub = _terminal(P, MU_L / RHO_L, d)
+        assert abs(ub[2] - v) < 1e-4, (d, ub[2], v)
+        assert abs(ub[0]) == 0 and abs(ub[1]) == 0
+
+
+def test_massless_bubble_reaches_mendelson_velocity():
+    """Table 4, column "Mendelson eq." (eq. (25)): the force balance with rho_b -> 0."""
+    P = O.bubble_params(g=G, rho_l=RHO_L, rho_b=0.0, sigma=SIGMA, c_a=0.5)
+    d_all, _, mend = _table4()
+    for d, v in zip(d_all, mend):
+        ub = _terminal(P, MU_L / RHO_L, d)
+        assert abs(ub[2] - v) < 1e-4, (d, ub[2], v)
+
+
+def test_hadamard_rybczynski_branch():
+    """Small bubble in the 48/Re branch of C_D (clean bubble): terminal velocity
+    v = (rho_l - rho_b) g d^2 / (36 mu)."""
+    P = O.bubble_params(g=G, rho_l=RHO_L, rho_b=RHO_B, sigma=SIGMA, c_a=0.5)
+    d = 0.5e-3
+    ub = _terminal(P, MU_L / RHO_L, d, dt=1e-6)
+    v = (RHO_L - RHO_B) * G * d * d / (36 * MU_L)
+    re = v * d * RHO_L / MU_L
+    assert 16 < re < 18 * 4 / 0.03  # inside the 48/Re branch
+    assert ub[2] == pytest.approx(v, rel=1e-10)
+
+
+def test_stokes_limit_discrete_recursion_is_exact():
+    """With k = 0 and a tiny Reynolds number the drag is Stokes drag 3 pi mu d u_r, and explicit
+    Euler with the added-mass-corrected inertia gives v_k = v_T [1 - (1 - dt/tau_p)^k] exactly,
+    v_T = F_B / (3 pi mu d), tau_p = (rho_b + C_A rho_l) V / (3 pi mu d) (lattice units)."""
+    omega, d, g = 1.0, 3.0, 1e-5
+    nu = (1 / omega - 0.5) / 3
+    P = O.bubble_params(g=g, rho_l=1.0, rho_b=1e-3, sigma=4.19e-5, c_a=0.5, cd_k=0.0)
+    V = np.pi * d ** 3 / 6
+    FB = (1.0 - 1e-3) * V * g
+    zeta = 3 * np.pi * nu * d
+    vT = FB / zeta
+    tau_p = (1e-3 + 0.5) * V / zeta
+    dt = 0.1
+    ub = np.zeros(3)
+    xb = np.zeros(3)
+    z3 = np.zeros(3)
+    zpos = 0.0
+    for k in range(1, 301):
+        ub, xb, psi = O.bubble_ode(P, nu, dt, 1, d, z3, z3, z3, ub, xb)
+        vk = vT * (1 - (1 - dt / tau_p) ** k)
+        zpos += dt * vk
+        assert ub[2] == pytest.approx(vk, rel=1e-12, abs=1e-22)
+        assert xb[2] == pytest.approx(zpos, rel=1e-12)
+        assert psi[2] == pytest.approx(zeta * vk, rel=1e-12)  # reaction = -F_D
+    assert dt / tau_p < 1  # stable explicit step with the effective mass
+
+
+def test_drag_is_finite_at_zero_relative_velocity():
+    P = O.bubble_params()
+    FD, FL = O.drag_lift(P, 1 / 6, 3.0, [0, 0, 0], [0, 0, 0], [1e-3, 0, 0])
+    assert np.all(FD == 0) and np.all(FL == 0)
+    cdu, cl, re = O.closures(P, 1 / 6, 3.0, 0.0)
+    assert np.isfinite(cdu) and re == 0.0
+
+
+def test_lift_coefficient_branches_and_reading():
+    """Table 1 lift coefficient. Three Eo_d branches; with the constant term 0.474 of the
+    polynomial the coefficient is continuous at Eo_d = 4 and nearly continuous at Eo_d = 10
+    (-0.270 against -0.29), while without it f(Eo_d) < 0 on the whole branch."""
+    nu, d = 1e-6, 4e-3
+    E_of = lambda Eo: 1 / (1 + 0.163 * Eo ** 0.757)
+    def sigma_for_eod(eod, g=9.81, drho=999.0):
+        lo, hi = 1e-6, 1e3  # bisection on Eo so that Eo / E^(2/3) = eod
+        for _ in range(200):
+            mid = np.sqrt(lo * hi)
+            if mid / E_of(mid) ** (2 / 3) < eod:
+                lo = mid
+            else:
+                hi = mid
+        return drho * g * d * d / lo
+    cls = {}
+    for eod in (3.999999, 4.0, 4.000001, 9.999999, 10.000001):
+        P = O.bubble_params(g=9.81, rho_l=1000.0, rho_b=1.0, sigma=sigma_for_eod(eod))
+        _, cl, _ = O.closures(P, nu, d, 10.0)  # large Re: tanh term saturates at 0.288
+        cls[eod] = cl
+    assert abs(cls[3.999999] - cls[4.000001]) < 1e-5
+    assert abs(cls[9.999999] - (-0.270)) < 2e-3
+    assert cls[10.000001] == -0.29
+    # low Re: the tanh branch wins below Eo_d = 4
+    P = O.bubble_params(g=9.81, rho_l=1000.0, rho_b=1.0, sigma=sigma_for_eod(2.0))
+    _, cl, re = O.closures(P, nu, d, 1e-4)
+    assert cl == pytest.approx(0.288 * np.tanh(0.121 * re), rel=1e-14)
+
+
+def test_lift_and_drag_directions():
+    """F_D opposes the relative velocity; F_L = -C_L rho_l V u_r x curl(u_l)."""
+    P = O.bubble_params(lift_f0=0.474)
+    nu, d = 1 / 6, 3.0
+    ub, ul, wl = np.array([0, 0, 1e-3]), np.zeros(3), np.array([0, 1e-4, 0])
+    FD, FL = O.drag_lift(P, nu, d, ub, ul, wl)
+    assert FD[2] < 0 and FD[0] == 0 and FD[1] == 0
+    _, cl, _ = O.closures(P, nu, d, 1e-3)
+    V = np.pi * d ** 3 / 6
+    assert np.allclose(FL, -cl * V * np.cross(ub - ul, wl), rtol=1e-14)
+    # scales multiply the forces
+    P2 = O.bubble_params(drag_scale=1.15, lift_scale=0.8)
+    FD2, FL2 = O.drag_lift(P2, nu, d, ub, ul, wl)
+    assert np.allclose(FD2, 1.15 * FD, rtol=1e-15) and np.allclose(FL2, 0.8 * FL, rtol=1e-15)
+
+
+def test_fluid_acceleration_term():
+    """Stress-gradient + fluid part of virtual mass: a bubble in a uniformly accelerating liquid
+    with no relative velocity gains (1 + C_A) rho_l V a / m_eff per unit time."""
+    P = O.bubble_params(g=0.0, cd_k=0.15)
+    nu, d, a = 1 / 6, 3.0, np.array([1e-6, -2e-6, 3e-6])
+    V = np.pi * d ** 3 / 6
+    m_eff = (1e-3 + 0.5) * V
+    ub, xb, _ = O.bubble_ode(P, nu, 0.1, 1, d, np.zeros(3), np.zeros(3), a, np.zeros(3), np.zeros(3))
+    # after one sub-step the relative velocity is still zero at the start of the step: exact
+    assert np.allclose(ub, 0.1 * (1.5 * V * a) / m_eff, rtol=1e-14)
+
+
+def test_schiller_naumann_branch_uses_particle_reynolds_number():
+    """Below Re ~ 15.8 the drag is the Schiller-Naumann law 3 pi mu d v (1 + 0.15 Re^0.687) with
+    Re = rho_l v d / mu_l; its terminal velocity is found here by bisection on that textbook law.
+    A Reynolds number without the diameter (as eq. (3) prints it) would give another value."""
+    P = O.bubble_params(g=G, rho_l=RHO_L, rho_b=RHO_B, sigma=SIGMA, c_a=0.5, cd_k=0.15)
+    d = 0.2e-3
+    FB = (RHO_L - RHO_B) * np.pi * d ** 3 / 6 * G
+    lo, hi = 0.0, 1.0
+    for _ in range(200):
+        v = 0.5 * (lo + hi)
+        re = RHO_L * v * d / MU_L
+        if 3 * np.pi * MU_L * d * v * (1 + 0.15 * re ** 0.687) < FB:
+            lo = v
+        else:
+            hi = v
+    assert 1 < RHO_L * lo * d / MU_L < 15
+    ub = _terminal(P, MU_L / RHO_L, d, dt=1e-6)
+    assert ub[2] == pytest.approx(lo, rel=1e-9)

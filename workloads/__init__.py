@@ -1,0 +1,139 @@
+"""Seeded synthetic inputs for the bubble-column workloads.
+
+This module only draws and lays out inputs (lattice shapes, relaxation rates, bubble positions
+and diameters, property constants). It holds none of the method's arithmetic, and both the CPU
+oracle tests and the GPU library's tests/benchmark read their inputs from here.
+
+The columns stand in for the paper's rectangular bubble columns (Table 2: 30 x 30 x 90; Table 5
+and Table 6: up to 120 x 120 x 360) at larger sizes; all values are in lattice units
+(dx = dt_l = 1, rho_l = 1), gravity along -z, bubble sub-step dt_b = dt_l / 10 (Table 2).
+Surface tension is chosen so that the Eotvos number at the workload's median diameter is 2.148,
+the value of the paper's 4 mm air bubble in water (Table 3).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+SEED = 1710
+BB, FS, PER = 0, 1, 2
+EO_4MM = 2.148  # (rho_l - rho_b) g d^2 / sigma of a 4 mm air bubble in water (Table 3)
+
+
+def sigma_for(g, d_median, rho_ratio=1e-3):
+    """Surface tension giving Eo = 2.148 at the median diameter."""
+    return (1.0 - rho_ratio) * g * d_median ** 2 / EO_4MM
+
+
+@dataclass
+class Workload:
+    name: str
+    shape: tuple            # (nx, ny, nz)
+    omega: float
+    bc: tuple               # (-x, +x, -y, +y, -z, +z)
+    pos: np.ndarray         # (3, nb) bubble centres, cell centres at integer coordinates
+    d: np.ndarray           # (nb,) diameters
+    params: dict            # bubble-phase constants
+    steps: int
+    dtype: str              # "f64" or "f32" population storage
+    vel: np.ndarray = None  # (3, nb) initial bubble velocities (zero if None)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nb(self):
+        return int(self.pos.shape[1])
+
+    @property
+    def cells(self):
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+
+def params(g=1e-5, rho_b=1e-3, sigma=4.19e-5, drag_scale=1.0, lift_scale=1.0, c_a=0.5,
+           kernel_factor=1.5, cd_k=0.15, lift_f0=0.474, n_sub=10):
+    return dict(g=g, rho_l=1.0, rho_b=rho_b, sigma=sigma, c_a=c_a, drag_scale=drag_scale,
+                lift_scale=lift_scale, kernel_factor=kernel_factor, cd_k=cd_k, lift_f0=lift_f0,
+                n_sub=n_sub)
+
+
+def plain_fp64(steps=500):
+    """32 x 32 x 64 column of liquid at rest, omega = 1, bounce-back walls, one bubble of
+    diameter 3 at (16, 16, 8), g = 1e-5, density ratio 1e-3."""
+    return Workload("plain_fp64_32x32x64", (32, 32, 64), 1.0, (BB,) * 6,
+                    np.array([[16.0], [16.0], [8.0]]), np.array([3.0]),
+                    params(g=1e-5, sigma=sigma_for(1e-5, 3.0)), steps, "f64")
+
+
+def single_fp32(steps=5000):
+    """128 x 128 x 512 column (8.4 M sites), omega = 1.6, bounce-back walls, one bubble of
+    diameter 4 released at the bottom centre."""
+    return Workload("single_fp32_128x128x512", (128, 128, 512), 1.6, (BB,) * 6,
+                    np.array([[63.5], [63.5], [8.0]]), np.array([4.0]),
+                    params(g=1e-5, sigma=sigma_for(1e-5, 4.0)), steps, "f32")
+
+
+def dense(steps=2000, shape=(256, 256, 768), nb=20000, seed=SEED):
+    """Dense dispersed flow: omega drawn in [1.2, 1.8]; nb bubbles uniformly in the bottom 20 %,
+    ln d ~ N(ln 3, 0.25^2), kept a window half-width away from the side and bottom walls."""
+    rng = np.random.default_rng(seed)
+    omega = float(rng.uniform(1.2, 1.8))
+    nx, ny, nz = shape
+    d = np.exp(rng.normal(np.log(3.0), 0.25, nb))
+    n = 1.5 * d
+    x = rng.uniform(n, nx - 1 - n)
+    y = rng.uniform(n, ny - 1 - n)
+    z = rng.uniform(n, 0.2 * nz)
+    return Workload(f"dense_{nx}x{ny}x{nz}_{nb}b", shape, omega, (BB,) * 6, np.stack([x, y, z]), d,
+                    params(g=1e-5, sigma=sigma_for(1e-5, 3.0)), steps, "f32")
+
+
+def batched(ncol=64, steps=3000, seed=SEED, lo=24, hi=96):
+    """Uneven columns for the batched sweep: cross-section n_x, n_y uniform in {lo..hi}, height
+    2-4 times n_x, omega_k = 0.6 + 1.3 k / (ncol - 1), 1-8 bubbles of diameter 2-5 in the bottom
+    20 % away from the walls. Returns a list of Workloads."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(ncol):
+        nx = int(rng.integers(lo, hi + 1))
+        ny = int(rng.integers(lo, hi + 1))
+        h = rng.uniform(2.0, 4.0)
+        nz = int(round(h * nx))
+        omega = 0.6 + 1.3 * k / max(ncol - 1, 1)
+        nb = int(rng.integers(1, 9))
+        d = rng.uniform(2.0, 5.0, nb)
+        n = 1.5 * d
+        x = rng.uniform(n, nx - 1 - n)
+        y = rng.uniform(n, ny - 1 - n)
+        z = rng.uniform(n, np.maximum(n + 1.0, 0.2 * nz))
+        out.append(Workload(f"column{k}_{nx}x{ny}x{nz}", (nx, ny, nz), float(omega), (BB,) * 6,
+                            np.stack([x, y, z]), d, params(g=1e-5, sigma=sigma_for(1e-5, 3.5)),
+                            steps, "f32"))
+    return out
+
+
+def adjoint(steps=2000, drag_scale=1.0, lift_scale=1.0, omega=1.4):
+    """64 x 64 x 192 column with 4 bubbles of diameter 3; g = 1e-4, sigma = 1e-4."""
+    pos = np.array([[26.0, 38.0, 26.0, 38.0], [26.0, 26.0, 38.0, 38.0], [20.0, 24.0, 28.0, 32.0]])
+    return Workload("adjoint_64x64x192_4b", (64, 64, 192), float(omega), (BB,) * 6, pos,
+                    np.full(4, 3.0), params(g=1e-4, sigma=1e-4, drag_scale=drag_scale,
+                                            lift_scale=lift_scale), steps, "f32",
+                    meta=dict(target=(1.15, 0.8, 1.5), theta0=(1.0, 1.0, 1.4), checkpoint=100))
+
+
+def with_steps(w: Workload, steps: int) -> Workload:
+    return replace(w, steps=steps)
+
+
+def random_populations(shape, amp, seed=SEED, dtype=np.float64):
+    """Random shifted populations g = f - w of amplitude amp, layout (19, nz, ny, nx)."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-amp, amp, (19, nz, ny, nx)).astype(dtype)
+
+
+def random_field(shape, amp, seed=SEED, dtype=np.float64):
+    """Random vector field, layout (3, nz, ny, nx)."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-amp, amp, (3, nz, ny, nx)).astype(dtype)
