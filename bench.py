@@ -1,0 +1,182 @@
+"""Benchmark of the coupled bubble-column step on one MI355X.
+
+A step is one pass of the whole hot path of Algorithm 1 over the lattice: the bubble kernel
+(forward coupling, bubble ODE, backward coupling) followed by the fused liquid step. The
+default workload is the single-bubble FP32 column, 128 x 128 x 512 (8.4 M sites), omega = 1.6,
+bounce-back walls, one bubble of diameter 4 at the bottom centre.
+
+Prints one JSON line: whole-job throughput in MLUPS (lattice-site updates per second), the
+roofline of the dominant kernel (the fused liquid step, HBM-bound; its per-launch duration comes
+from HIP events recorded around each launch on the library's stream in the timed region), and the
+CPU oracle timed on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("MLUPS and % HBM peak of fused step; batched and adjoint vs plain FP64 at stated error")
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_1710_07073_amd/csrc/step.hip", "paper_1710_07073_amd/csrc/lattice.hpp",
+                  "paper_1710_07073_amd/csrc/internal.hpp"]
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload, elem_bytes):
+    """HBM bytes per launch of the liquid step from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(PROFILES, f"k_step_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The oracle (plain FP64 C++, OpenMP over cells) on the same lattice and bubble, timed for
+    whole method steps until about budget_s of wall time has passed."""
+    import oracle as O
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    lat = O.Lattice(*w.shape, w.omega, w.bc)
+    bub = O.Bubbles(pos=w.pos.copy(), d=w.d.copy())
+    P = O.bubble_params(**w.params)
+    O.method_step(lat, P, bub, threads)  # warm-up (first touch of the arrays)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        O.method_step(lat, P, bub, threads)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 1000:
+            break
+    return {"value": round(w.cells * n / el / 1e6, 2), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n} full method steps of the same {w.shape[0]}x{w.shape[1]}x{w.shape[2]} "
+                      f"lattice and bubble, FP64, {threads} OpenMP threads, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="single_fp32", choices=["single_fp32", "plain_fp64"])
+    ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of known size (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the method runs on a single MI355X here; "
+              "multi-GPU runs (slab decomposition with halo exchange) are not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_1710_07073_amd import lbm as L
+    from paper_1710_07073_amd import sim as S
+
+    w = W.single_fp32() if args.workload == "single_fp32" else W.plain_fp64()
+    if args.precision:
+        w = W.Workload(w.name.replace("fp32", args.precision).replace("fp64", args.precision),
+                       w.shape, w.omega, w.bc, w.pos, w.d, w.params, w.steps, args.precision)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    sim = S.Simulation(w.shape, w.omega, precision=w.dtype, bc=w.bc, device=dev, stream=stream)
+    sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+    print(f"[bench] {w.name}: {w.cells} cells, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        sim.step(1)
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)  # 1 GiB read + 1 GiB write
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    bub = sim.bubbles
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        L.bubbles_step(sim.ctx, sim.params, bub.soa, bub.nb)
+        ev0[k].record(stream)
+        L.lbm_step(sim.ctx, 1)
+        ev1[k].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
+    kern_s = float(np.mean(step_ms)) * 1e-3
+
+    # the run stayed finite and conserved mass
+    _, _, sums = sim.moments(fields=False)
+    sim.check()
+    elem = 4 if w.dtype == "f32" else 8
+    mlups = w.cells * K / elapsed / 1e6
+    alg_bytes = 38 * elem * w.cells  # 19 loads + 19 stores per site
+    achieved = alg_bytes / kern_s / 1e9
+    traffic = read_traffic(w.name, elem)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / K * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w.dtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": list(w.shape), "cells": w.cells,
+                   "omega": w.omega, "bubbles": w.nb, "bubble_diameter": float(w.d[0]),
+                   "populations": f"D3Q19 shifted f-w, {w.dtype}", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_step (fused collide-stream)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
+                     "avg_launch_ms": round(kern_s * 1e3, 5),
+                     "kernel_mlups": round(w.cells / kern_s / 1e6, 1)},
+        "mass_drift": sums[0] - w.cells,
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

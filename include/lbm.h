@@ -1,0 +1,168 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the Euler-Lagrange bubble-column method of
+ * Agarwal, Ravindra & Prakash, "Development of algorithm to model dispersed gas-liquid flow
+ * using lattice Boltzmann method" (arXiv 1710.07073).
+ *
+ * The liquid is a D3Q19 BGK lattice-Boltzmann fluid with a per-cell body force (Sec. 2.2,
+ * eq. (5)-(16)); bubbles are Lagrangian point particles (Sec. 2.1, eq. (1)-(4), Table 1) coupled
+ * both ways through the clipped fourth-order polynomial mapping kernel (Sec. 3.2, eq. (18)-(21)).
+ * One method step of Algorithm 1 is bubbles_step() followed by lbm_step(ctx, 1).
+ *
+ * Conventions
+ *   - Lattice units: dx = dt_l = 1, liquid reference density 1. Cell (i, j, k) has its centre at
+ *     (i, j, k); a non-periodic wall lies half a cell outside the outermost cells. Gravity acts
+ *     along -z. Bubble sub-step dt_b = 1 / n_sub.
+ *   - Populations are stored shifted by their weights, g_q = f_q - w_q, structure of arrays
+ *     pop[q][z][y][x] (x fastest), q in the paper's velocity order of eq. (7): the six axis
+ *     directions (+x, -x, +y, -y, +z, -z), the twelve face diagonals (+x+y, -x+y, +x-y, -x-y,
+ *     +x+z, -x+z, +x-z, -x-z, +y+z, -y+z, +y-z, -y-z) and the rest particle.
+ *     Vector fields are vec[a][z][y][x], a = x, y, z. Field element type is float for
+ *     LBM_FP32_SHIFTED and double for LBM_FP64_SHIFTED.
+ *   - Memory: every buffer is caller-owned device memory (hipMalloc / torch allocations). The
+ *     library never allocates or frees device memory; the context itself is host memory owned by
+ *     the library and released by lbm_destroy().
+ *   - Streams: every call enqueues its kernels on the stream given to lbm_init() (or
+ *     lbm_set_stream()) and returns without waiting, except where stated. NULL = default stream.
+ *   - Errors: argument errors are detected on the host and returned at once as LBM_EINVAL,
+ *     without enqueuing anything. Launch failures return LBM_EDEVICE. Errors raised inside
+ *     kernels (a bubble too large for the stencil limit) are recorded in device memory and
+ *     reported by the next synchronising call (moments() with sums, lbm_check()).
+ *   - Threading: a context is not thread-safe; calls on one context must be serialised.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,       /* bad argument */
+  LBM_EUNSUPPORTED = -2, /* valid request outside what this build supports */
+  LBM_EDEVICE = -3,      /* HIP runtime or launch error */
+  LBM_EDIVERGED = -4     /* non-finite global sums: the BGK step went unstable */
+} lbm_status;
+
+typedef enum { LBM_FP32_SHIFTED = 1, LBM_FP64_SHIFTED = 2 } lbm_precision;
+
+/* Face conditions (Sec. 3.3): half-way bounce-back no-slip wall, free-slip (specular) wall,
+ * periodic (both faces of an axis must then be periodic). */
+typedef enum { LBM_BC_BOUNCE_BACK = 0, LBM_BC_FREE_SLIP = 1, LBM_BC_PERIODIC = 2 } lbm_bc;
+
+/* Behaviour flags of lbm_desc.flags. */
+enum {
+  /* Read the force field in every cell on every step and never clear it (a user-supplied
+   * steady body force, e.g. a driven channel). Not allowed together with bubbles_step(). */
+  LBM_FLAG_STATIC_FORCE = 1,
+  /* Write the collision velocity U in every cell, not only near bubbles. */
+  LBM_FLAG_WRITE_U_ALL = 2
+};
+
+typedef struct {
+  int32_t nx, ny, nz;  /* lattice extent, each >= 1 */
+  int32_t precision;   /* lbm_precision */
+  double omega;        /* BGK relaxation frequency 1/tau, 0 < omega < 2 (eq. (5), (9)) */
+  int32_t bc[6];       /* faces -x, +x, -y, +y, -z, +z (lbm_bc) */
+  int32_t flags;       /* LBM_FLAG_* */
+  int32_t reserved;    /* must be 0 */
+} lbm_desc;
+
+/* Bubble-phase constants (Table 1, Table 3), all in lattice units. */
+typedef struct {
+  double g;             /* gravity magnitude (acts along -z) */
+  double rho_l;         /* liquid density used by the force closures */
+  double rho_b;         /* bubble density */
+  double sigma;         /* surface tension (Eotvos number) */
+  double c_a;           /* added-mass coefficient C_A (Table 1: 0.5) */
+  double drag_scale;    /* multiplier of the drag force */
+  double lift_scale;    /* multiplier of the lift force */
+  double kernel_factor; /* half-width of the mapping window in diameters (Sec. 3.2: 1.5) */
+  double cd_k;          /* k in C_D = 24/Re (1 + k Re^0.687) */
+  double lift_f0;       /* constant term of the lift polynomial f(Eo_d) */
+  int32_t n_sub;        /* bubble sub-steps per liquid step, dt_b = 1/n_sub (Table 2: 10) */
+  int32_t reserved;     /* must be 0 */
+} bubble_params;
+
+/* Bubble state, structure of arrays of length nb in device memory (double precision).
+ * state: 0 = inactive (reached the top layer, Algorithm 1 stop test), 1 = active without a
+ * previous interpolated liquid velocity (first step), 2 = active. ul* hold the liquid velocity
+ * interpolated at the previous step (for the material derivative of u_l). psi* (optional) receive
+ * the reaction -(F_D + F_L) spread into the liquid (0 for an inactive bubble). */
+typedef struct {
+  double *x, *y, *z;
+  double *ux, *uy, *uz;
+  double *d;
+  double *ulx, *uly, *ulz;
+  int32_t *state;
+  double *psix, *psiy, *psiz; /* nullable: receives the reaction spread in the last step */
+} bubble_soa;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Largest bubble the stencil kernels accept: the mapping window may span at most this many
+ * cells per axis (window half-width n = kernel_factor * d, so d <= about 20 at factor 1.5). */
+#define LBM_MAX_STENCIL 64
+
+/* Sizes, in bytes, of one population buffer (19 x cells), of one vector field (3 x cells:
+ * force or velocity) and of the scratch buffer (tile masks and reduction partials). */
+lbm_status lbm_bytes_required(const lbm_desc* desc, size_t* pop_buffer_bytes,
+                              size_t* field_bytes, size_t* scratch_bytes);
+
+/* Create a context over caller-owned device buffers and initialise them on the stream:
+ * both population buffers to g = 0 (f = w, liquid at rest, rho = 1: Algorithm 1
+ * initialisation), force and velocity to 0, scratch to its initial state. The buffers must stay
+ * valid and unaliased until lbm_destroy(). stream is a hipStream_t or NULL. */
+lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* force, void* vel,
+                    void* scratch, void* stream, lbm_ctx** out);
+
+/* Change the stream later calls enqueue on. */
+lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
+
+/* nsteps liquid steps (Sec. 2.2, eq. (13)-(16) with the face conditions of Sec. 3.3): first
+ * forcing (13), BGK collision (14), Guo forcing (12), (15), streaming (16). Each step reads the
+ * force field where bubbles have spread force (or everywhere with LBM_FLAG_STATIC_FORCE),
+ * writes the collision velocity U of eq. (13) there (or everywhere with LBM_FLAG_WRITE_U_ALL)
+ * and clears the force it used. */
+lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
+
+/* Bubble half of one step of Algorithm 1 for nb bubbles (forward coupling eq. (20) of the
+ * liquid velocity and its curl with the weights of eq. (19); force closures of Table 1 and
+ * eq. (3); n_sub explicit sub-steps of eq. (4); backward coupling eq. (21) of the reaction
+ * -(F_D + F_L) into the force field). Uses the velocity field of the previous lbm_step(). Call
+ * exactly once before each lbm_step(ctx, 1). soa: host struct of device pointers. */
+lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* params, const bubble_soa* soa,
+                        int32_t nb);
+
+/* Macroscopic fields of the current state (eq. (10)): rho = sum_q f_q and u = sum_q c_q f_q / rho
+ * per cell (device buffers of N and 3 x N elements of the lattice type, each nullable), and
+ * sums_out (host, 4 doubles, nullable) = (sum rho, sum rho u_x, sum rho u_y, sum rho u_z)
+ * accumulated in double precision. With sums_out the call synchronises the stream and returns
+ * LBM_EDIVERGED if a sum is not finite, or a pending kernel error. */
+lbm_status moments(lbm_ctx* ctx, void* rho_out, void* u_out, double* sums_out);
+
+/* Write the current pre-collision populations g = f - w (19 x N, lattice type, the layout above)
+ * into the device buffer out. */
+lbm_status lbm_populations(lbm_ctx* ctx, void* out);
+
+/* Pointer of the buffer holding the current state (post-collision, awaiting streaming). */
+lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out);
+
+/* Synchronise the stream and report a pending kernel error (LBM_EINVAL for a bubble beyond the
+ * stencil limit), then clear it. */
+lbm_status lbm_check(lbm_ctx* ctx);
+
+/* Release the context (not the caller's buffers). NULL is accepted. */
+lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* Static description of a status code. */
+const char* lbm_status_string(lbm_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

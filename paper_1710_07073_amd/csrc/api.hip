@@ -1,0 +1,209 @@
+// C ABI (include/lbm.h): argument checking, the context, the scratch layout and the launches.
+#include <math.h>
+#include <new>
+#include <string.h>
+
+#include "internal.hpp"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t tiles, partials, result, status, total;
+  uint32_t ntiles, nred, tnx, tny, tnz;
+};
+
+bool desc_ok(const lbm_desc* d) {
+  if (!d) return false;
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return false;
+  if (d->precision != LBM_FP32_SHIFTED && d->precision != LBM_FP64_SHIFTED) return false;
+  if (!(d->omega > 0.0 && d->omega < 2.0)) return false;
+  if (d->flags & ~(LBM_FLAG_STATIC_FORCE | LBM_FLAG_WRITE_U_ALL)) return false;
+  if (d->reserved != 0) return false;
+  for (int a = 0; a < 3; ++a) {
+    const int lo = d->bc[2 * a], hi = d->bc[2 * a + 1];
+    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return false;
+    if ((lo == LBM_BC_PERIODIC) != (hi == LBM_BC_PERIODIC)) return false;
+  }
+  // cell indices are 32-bit and every population offset q * N + cell must fit in 31 bits
+  const double cells = (double)d->nx * d->ny * d->nz;
+  if (cells * 19.0 >= 2147483648.0) return false;
+  return true;
+}
+
+Layout layout_of(const lbm_desc* d) {
+  Layout L;
+  L.tnx = lbm::div_up(d->nx, lbm::kTile);
+  L.tny = lbm::div_up(d->ny, lbm::kTile);
+  L.tnz = lbm::div_up(d->nz, lbm::kTile);
+  L.ntiles = L.tnx * L.tny * L.tnz;
+  const uint32_t cells = (uint32_t)d->nx * d->ny * d->nz;
+  L.nred = lbm::div_up(cells, 256);
+  if (L.nred > lbm::kRedBlocks) L.nred = lbm::kRedBlocks;
+  L.tiles = 0;
+  L.partials = align_up(L.tiles + L.ntiles);
+  L.result = align_up(L.partials + (size_t)L.nred * 4 * sizeof(double));
+  L.status = align_up(L.result + 4 * sizeof(double));
+  L.total = align_up(L.status + sizeof(int32_t));
+  return L;
+}
+
+lbm_status from_hip(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_bytes_required(const lbm_desc* desc, size_t* pop_buffer_bytes, size_t* field_bytes,
+                              size_t* scratch_bytes) {
+  if (!desc_ok(desc)) return LBM_EINVAL;
+  const size_t cells = (size_t)desc->nx * desc->ny * desc->nz;
+  const size_t elem = desc->precision == LBM_FP32_SHIFTED ? 4 : 8;
+  if (pop_buffer_bytes) *pop_buffer_bytes = 19 * cells * elem;
+  if (field_bytes) *field_bytes = 3 * cells * elem;
+  if (scratch_bytes) *scratch_bytes = layout_of(desc).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* force, void* vel,
+                    void* scratch, void* stream, lbm_ctx** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  if (!desc_ok(desc) || !pops_a || !pops_b || !force || !vel || !scratch) return LBM_EINVAL;
+  if (pops_a == pops_b) return LBM_EINVAL;
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_EDEVICE;
+  c->desc = *desc;
+  const Layout L = layout_of(desc);
+  lbm::Geom& G = c->geom;
+  G.nx = desc->nx;
+  G.ny = desc->ny;
+  G.nz = desc->nz;
+  G.N = (uint32_t)desc->nx * desc->ny * desc->nz;
+  G.plane = (uint32_t)desc->nx * desc->ny;
+  for (int f = 0; f < 6; ++f) G.bc[f] = desc->bc[f];
+  G.tnx = (int)L.tnx;
+  G.tny = (int)L.tny;
+  c->general = false;
+  for (int f = 0; f < 6; ++f)
+    if (desc->bc[f] != LBM_BC_BOUNCE_BACK) c->general = true;
+  c->elem = desc->precision == LBM_FP32_SHIFTED ? 4 : 8;
+  c->pops[0] = pops_a;
+  c->pops[1] = pops_b;
+  c->cur = 0;
+  c->force = force;
+  c->vel = vel;
+  uint8_t* s = static_cast<uint8_t*>(scratch);
+  c->tiles = s + L.tiles;
+  c->ntiles = L.ntiles;
+  c->partials = reinterpret_cast<double*>(s + L.partials);
+  c->result = reinterpret_cast<double*>(s + L.result);
+  c->status = reinterpret_cast<int32_t*>(s + L.status);
+  c->nred = L.nred;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->steps = 0;
+  const size_t cells = G.N;
+  hipError_t e = lbm::launch_fill(pops_a, 19 * cells * c->elem, c->stream);
+  if (e == hipSuccess) e = lbm::launch_fill(pops_b, 19 * cells * c->elem, c->stream);
+  if (e == hipSuccess) e = lbm::launch_fill(force, 3 * cells * c->elem, c->stream);
+  if (e == hipSuccess) e = lbm::launch_fill(vel, 3 * cells * c->elem, c->stream);
+  if (e == hipSuccess) e = lbm::launch_fill(scratch, L.total, c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return LBM_EDEVICE;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream) {
+  if (!ctx) return LBM_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps) {
+  if (!ctx || nsteps < 0) return LBM_EINVAL;
+  for (int32_t i = 0; i < nsteps; ++i) {
+    const hipError_t e = lbm::launch_step(ctx);
+    if (e != hipSuccess) return LBM_EDEVICE;
+  }
+  return LBM_OK;
+}
+
+lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, int32_t nb) {
+  if (!ctx || !p || !s || nb < 0) return LBM_EINVAL;
+  if (ctx->desc.flags & LBM_FLAG_STATIC_FORCE) return LBM_EINVAL;
+  if (p->n_sub < 1 || p->reserved != 0) return LBM_EINVAL;
+  if (!(p->kernel_factor > 0.0) || !(p->sigma > 0.0) || !(p->rho_l > 0.0)) return LBM_EINVAL;
+  if (nb > 0) {
+    if (!s->x || !s->y || !s->z || !s->ux || !s->uy || !s->uz || !s->d || !s->ulx || !s->uly ||
+        !s->ulz || !s->state)
+      return LBM_EINVAL;
+    const bool any_psi = s->psix || s->psiy || s->psiz;
+    const bool all_psi = s->psix && s->psiy && s->psiz;
+    if (any_psi && !all_psi) return LBM_EINVAL;
+  }
+  return from_hip(lbm::launch_bubbles(ctx, p, s, nb));
+}
+
+lbm_status lbm_check(lbm_ctx* ctx) {
+  if (!ctx) return LBM_EINVAL;
+  int32_t st = 0;
+  if (hipMemcpyAsync(&st, ctx->status, sizeof(st), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+    return LBM_EDEVICE;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return LBM_EDEVICE;
+  if (st != 0) {
+    if (lbm::launch_fill(ctx->status, sizeof(int32_t) * 64, ctx->stream) != hipSuccess)
+      return LBM_EDEVICE;
+    return LBM_EINVAL;
+  }
+  return LBM_OK;
+}
+
+lbm_status moments(lbm_ctx* ctx, void* rho_out, void* u_out, double* sums_out) {
+  if (!ctx) return LBM_EINVAL;
+  if (lbm::launch_moments(ctx, rho_out, u_out, sums_out != nullptr) != hipSuccess) return LBM_EDEVICE;
+  if (!sums_out) return LBM_OK;
+  double r[4];
+  if (hipMemcpyAsync(r, ctx->result, sizeof(r), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+    return LBM_EDEVICE;
+  const lbm_status st = lbm_check(ctx);
+  if (st != LBM_OK) return st;
+  for (int k = 0; k < 4; ++k) sums_out[k] = r[k];
+  for (int k = 0; k < 4; ++k)
+    if (!isfinite(r[k])) return LBM_EDIVERGED;
+  return LBM_OK;
+}
+
+lbm_status lbm_populations(lbm_ctx* ctx, void* out) {
+  if (!ctx || !out) return LBM_EINVAL;
+  return from_hip(lbm::launch_populations(ctx, out));
+}
+
+lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out) {
+  if (!ctx || !out) return LBM_EINVAL;
+  *out = ctx->pops[ctx->cur];
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx* ctx) {
+  delete ctx;
+  return LBM_OK;
+}
+
+const char* lbm_status_string(lbm_status status) {
+  switch (status) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_EUNSUPPORTED: return "unsupported";
+    case LBM_EDEVICE: return "device error";
+    case LBM_EDIVERGED: return "diverged (non-finite sums)";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

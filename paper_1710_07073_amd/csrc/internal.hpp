@@ -1,0 +1,59 @@
+// Host-side context and kernel launch entry points shared by the translation units of the
+// library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/lbm.h"
+#include "lattice.hpp"
+
+struct lbm_ctx {
+  lbm_desc desc;
+  lbm::Geom geom;
+  bool general;     // any free-slip or periodic face
+  size_t elem;      // 4 or 8
+  void* pops[2];    // population buffers; pops[cur] holds the current post-collision state
+  int cur;
+  void* force;
+  void* vel;
+  uint8_t* tiles;   // one byte per 8^3 tile: force present / velocity needed
+  uint32_t ntiles;
+  double* partials; // moments reduction partials (4 doubles per block)
+  double* result;   // 4 doubles
+  int32_t* status;  // kernel error word
+  uint32_t nred;    // number of reduction partial slots
+  hipStream_t stream;
+  int64_t steps;
+};
+
+namespace lbm {
+
+constexpr uint32_t kTile = 8;
+constexpr uint32_t kRedBlocks = 1024;  // upper bound of moments reduction blocks
+
+enum : int32_t { STATUS_STENCIL_TOO_LARGE = 1 };
+
+// step.hip
+hipError_t launch_step(lbm_ctx* c);
+// bubbles.hip
+hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb);
+// moments.hip
+hipError_t launch_moments(lbm_ctx* c, void* rho, void* u, bool sums);
+hipError_t launch_populations(lbm_ctx* c, void* out);
+hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t s);
+
+inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+// Map a hardware workgroup index to a logical one so that the workgroups the dispatcher sends to
+// one XCD (index modulo 8) form a contiguous range of the domain: neighbouring rows then share
+// that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t i, uint32_t n) {
+  constexpr uint32_t X = 8;
+  const uint32_t q = n / X, r = n % X;
+  const uint32_t k = i % X, j = i / X;
+  return k * q + (k < r ? k : r) + j;
+}
+
+}  // namespace lbm

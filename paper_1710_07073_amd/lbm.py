@@ -1,0 +1,147 @@
+"""ctypes binding of the C ABI in ``include/lbm.h`` (same names, argument marshalling only).
+
+Every step of the method runs in the HIP kernels of ``_lib/liblbm.so``; this module converts
+Python arguments to C structs and pointers and raises on error codes. Loading fails loudly when
+the library has not been built. PyTorch is used only by :mod:`.sim` for device memory and
+streams.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_EDEVICE, LBM_EDIVERGED = 0, -1, -2, -3, -4
+LBM_FP32_SHIFTED, LBM_FP64_SHIFTED = 1, 2
+LBM_BC_BOUNCE_BACK, LBM_BC_FREE_SLIP, LBM_BC_PERIODIC = 0, 1, 2
+LBM_FLAG_STATIC_FORCE, LBM_FLAG_WRITE_U_ALL = 1, 2
+LBM_MAX_STENCIL = 64
+
+# every symbol include/lbm.h declares
+EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_step", "bubbles_step",
+           "moments", "lbm_populations", "lbm_state_buffer", "lbm_check", "lbm_destroy",
+           "lbm_status_string")
+
+
+class LbmDesc(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32),
+                ("precision", ct.c_int32), ("omega", ct.c_double), ("bc", ct.c_int32 * 6),
+                ("flags", ct.c_int32), ("reserved", ct.c_int32)]
+
+
+class BubbleParams(ct.Structure):
+    _fields_ = [("g", ct.c_double), ("rho_l", ct.c_double), ("rho_b", ct.c_double),
+                ("sigma", ct.c_double), ("c_a", ct.c_double), ("drag_scale", ct.c_double),
+                ("lift_scale", ct.c_double), ("kernel_factor", ct.c_double), ("cd_k", ct.c_double),
+                ("lift_f0", ct.c_double), ("n_sub", ct.c_int32), ("reserved", ct.c_int32)]
+
+
+class BubbleSoA(ct.Structure):
+    _fields_ = [(n, ct.c_void_p) for n in ("x", "y", "z", "ux", "uy", "uz", "d", "ulx", "uly", "ulz",
+                                          "state", "psix", "psiy", "psiz")]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {lbm_status_string(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library not built: {LIB_PATH} missing "
+                              "(run __graft_entry__.build() or paper_1710_07073_amd/build.py)")
+        L = ct.CDLL(LIB_PATH)
+        P = ct.c_void_p
+        L.lbm_bytes_required.argtypes = [ct.POINTER(LbmDesc), ct.POINTER(ct.c_size_t),
+                                         ct.POINTER(ct.c_size_t), ct.POINTER(ct.c_size_t)]
+        L.lbm_init.argtypes = [ct.POINTER(LbmDesc), P, P, P, P, P, P, ct.POINTER(P)]
+        L.lbm_set_stream.argtypes = [P, P]
+        L.lbm_step.argtypes = [P, ct.c_int32]
+        L.bubbles_step.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32]
+        L.moments.argtypes = [P, P, P, ct.POINTER(ct.c_double)]
+        L.lbm_populations.argtypes = [P, P]
+        L.lbm_state_buffer.argtypes = [P, ct.POINTER(P)]
+        L.lbm_check.argtypes = [P]
+        L.lbm_destroy.argtypes = [P]
+        L.lbm_status_string.argtypes = [ct.c_int]
+        L.lbm_status_string.restype = ct.c_char_p
+        for name in EXPORTS:
+            if name != "lbm_status_string":
+                getattr(L, name).restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def lbm_status_string(code):
+    return lib().lbm_status_string(int(code)).decode()
+
+
+def _ok(code, what):
+    if code != LBM_OK:
+        raise LbmError(code, what)
+
+
+def make_desc(shape, omega, precision, bc=(0,) * 6, flags=0):
+    nx, ny, nz = shape
+    return LbmDesc(int(nx), int(ny), int(nz), int(precision), float(omega),
+                   (ct.c_int32 * 6)(*[int(b) for b in bc]), int(flags), 0)
+
+
+def lbm_bytes_required(desc):
+    a, b, c = ct.c_size_t(), ct.c_size_t(), ct.c_size_t()
+    _ok(lib().lbm_bytes_required(ct.byref(desc), ct.byref(a), ct.byref(b), ct.byref(c)),
+        "lbm_bytes_required")
+    return a.value, b.value, c.value
+
+
+def lbm_init(desc, pops_a, pops_b, force, vel, scratch, stream):
+    ctx = ct.c_void_p()
+    _ok(lib().lbm_init(ct.byref(desc), pops_a, pops_b, force, vel, scratch, stream,
+                       ct.byref(ctx)), "lbm_init")
+    return ctx
+
+
+def lbm_set_stream(ctx, stream):
+    _ok(lib().lbm_set_stream(ctx, stream), "lbm_set_stream")
+
+
+def lbm_step(ctx, nsteps=1):
+    _ok(lib().lbm_step(ctx, int(nsteps)), "lbm_step")
+
+
+def bubbles_step(ctx, params, soa, nb):
+    _ok(lib().bubbles_step(ctx, ct.byref(params), ct.byref(soa), int(nb)), "bubbles_step")
+
+
+def moments(ctx, rho_ptr=None, u_ptr=None, want_sums=True):
+    sums = (ct.c_double * 4)() if want_sums else None
+    _ok(lib().moments(ctx, rho_ptr, u_ptr, sums), "moments")
+    return list(sums) if want_sums else None
+
+
+def lbm_populations(ctx, out_ptr):
+    _ok(lib().lbm_populations(ctx, out_ptr), "lbm_populations")
+
+
+def lbm_state_buffer(ctx):
+    p = ct.c_void_p()
+    _ok(lib().lbm_state_buffer(ctx, ct.byref(p)), "lbm_state_buffer")
+    return p.value
+
+
+def lbm_check(ctx):
+    _ok(lib().lbm_check(ctx), "lbm_check")
+
+
+def lbm_destroy(ctx):
+    if ctx:
+        lib().lbm_destroy(ctx)

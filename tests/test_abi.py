@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every function that
+include/lbm.h declares, and rejects bad arguments before touching the device."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_1710_07073_amd import lbm as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lbm.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"^\s*(?:lbm_status|const char\*)\s+(\w+)\s*\(", src, flags=re.M))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert names == set(L.EXPORTS)
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4):
+        assert L.lbm_status_string(code)
+    assert L.lbm_status_string(-99) == "unknown status"
+
+
+def test_bytes_required():
+    d = L.make_desc((32, 32, 64), 1.0, L.LBM_FP64_SHIFTED)
+    pop, field, scratch = L.lbm_bytes_required(d)
+    n = 32 * 32 * 64
+    assert pop == 19 * n * 8 and field == 3 * n * 8
+    assert scratch >= 4 * 4 * 8 * 1 + (32 // 8) * (32 // 8) * (64 // 8)
+    d = L.make_desc((37, 23, 19), 1.2, L.LBM_FP32_SHIFTED)
+    pop, field, _ = L.lbm_bytes_required(d)
+    assert pop == 19 * 37 * 23 * 19 * 4 and field == 3 * 37 * 23 * 19 * 4
+
+
+@pytest.mark.parametrize("kw", [
+    dict(shape=(0, 4, 4)), dict(omega=0.0), dict(omega=2.0), dict(omega=float("nan")),
+    dict(precision=3), dict(bc=(2, 0, 0, 0, 0, 0)), dict(bc=(0, 0, 0, 0, 0, 5)), dict(flags=8),
+    dict(shape=(2048, 2048, 32)),
+])
+def test_bad_descriptions_are_rejected(kw):
+    args = dict(shape=(8, 8, 8), omega=1.0, precision=L.LBM_FP32_SHIFTED, bc=(0,) * 6, flags=0)
+    args.update(kw)
+    d = L.make_desc(args["shape"], args["omega"], args["precision"], args["bc"], args["flags"])
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_bytes_required(d)
+    assert e.value.code == L.LBM_EINVAL
+
+
+def test_init_rejects_missing_buffers_without_device_work():
+    d = L.make_desc((8, 8, 8), 1.0, L.LBM_FP32_SHIFTED)
+    fake = ct.c_void_p(0x1000)
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_init(d, fake, None, fake, fake, fake, None)
+    assert e.value.code == L.LBM_EINVAL
+    with pytest.raises(L.LbmError) as e:  # aliased population buffers
+        L.lbm_init(d, fake, fake, fake, fake, fake, None)
+    assert e.value.code == L.LBM_EINVAL
+
+
+def test_null_context_calls_are_rejected():
+    lib = L.lib()
+    assert lib.lbm_step(None, 1) == L.LBM_EINVAL
+    assert lib.moments(None, None, None, None) == L.LBM_EINVAL
+    assert lib.lbm_check(None) == L.LBM_EINVAL
+    assert lib.lbm_destroy(None) == L.LBM_OK

@@ -1,0 +1,113 @@
+"""GPU parity of the fused liquid step (Sec. 2.2, eq. (13)-(16); Sec. 3.3 face conditions) against
+the CPU oracle, through the C ABI: random non-equilibrium states under a fixed force field, ragged
+shapes that do not fill the launch tiles, every face condition, both precisions."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from paper_1710_07073_amd import lbm as L
+from gpu_common import rel_l2, set_post_collision_state, gpu_u
+from paper_1710_07073_amd import sim as S
+
+BB, FS, PER = O.BC_BOUNCE_BACK, O.BC_FREE_SLIP, O.BC_PERIODIC
+FLAGS = L.LBM_FLAG_STATIC_FORCE | L.LBM_FLAG_WRITE_U_ALL
+
+# FP64 path: rounding-order differences only. FP32 path: storage and collision in float, the
+# tolerance of the method's stated FP32 target.
+TOL = {"f64": 1e-12, "f32": 2e-5}
+
+CASES = [
+    ((37, 23, 19), (BB,) * 6),
+    ((64, 8, 9), (BB, BB, BB, BB, BB, FS)),
+    ((33, 20, 17), (PER, PER, BB, BB, FS, FS)),
+    ((16, 16, 16), (PER,) * 6),
+    ((1, 12, 10), (PER, PER, BB, FS, BB, BB)),
+    ((130, 3, 5), (FS,) * 6),
+    ((256, 4, 3), (BB, BB, PER, PER, BB, FS)),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape,bc", CASES)
+def test_liquid_steps_match_oracle(prec, shape, bc):
+    print(f"[case] liquid {prec} {shape} bc={bc}", flush=True)
+    R = W.random_populations(shape, 1e-3, seed=3)
+    F = W.random_field(shape, 2e-5, seed=4)
+    if prec == "f32":
+        R = R.astype(np.float32).astype(np.float64)
+        F = F.astype(np.float32).astype(np.float64)
+    omega = 1.3
+    sim = S.Simulation(shape, omega, precision=prec, bc=bc, flags=FLAGS)
+    set_post_collision_state(sim, R)
+    sim.force.copy_(torch.from_numpy(F).to(sim.dtype))
+    lat = O.Lattice(*shape, omega, bc, g=O.stream(R, bc))
+    steps = 12
+    for _ in range(steps):
+        sim.liquid_steps(1)
+        lat.step(F)
+    gpu = sim.populations().double().cpu().numpy()
+    assert rel_l2(gpu, lat.g) <= TOL[prec]
+    U = sim.vel.double().cpu().numpy()
+    assert rel_l2(U, lat.U) <= TOL[prec]
+    u, sums = gpu_u(sim)
+    _, u_o, sums_o = lat.moments()
+    assert rel_l2(u, u_o) <= TOL[prec]
+    assert abs(sums[0] - sums_o[0]) <= 1e-9 * sums_o[0]
+    # the fixed force field is still there (static force is never cleared)
+    assert np.array_equal(sim.force.double().cpu().numpy(), F)
+    sim.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_rest_state_stays_at_rest(prec):
+    sim = S.Simulation((40, 24, 18), 1.7, precision=prec)
+    sim.liquid_steps(25)
+    g = sim.populations()
+    assert torch.count_nonzero(g).item() == 0
+    _, _, sums = sim.moments()
+    assert sums == [40 * 24 * 18, 0.0, 0.0, 0.0]
+    sim.close()
+
+
+@pytest.mark.gpu
+def test_periodic_momentum_balance_on_gpu():
+    """Fully periodic FP64 box: total momentum grows by exactly the total force per step."""
+    shape = (24, 20, 18)
+    R = W.random_populations(shape, 1e-3, seed=5)
+    F = W.random_field(shape, 1e-5, seed=6)
+    sim = S.Simulation(shape, 1.1, precision="f64", bc=(PER,) * 6, flags=FLAGS)
+    set_post_collision_state(sim, R)
+    sim.force.copy_(torch.from_numpy(F))
+    _, _, s0 = sim.moments(fields=False)
+    for k in range(1, 6):
+        sim.liquid_steps(1)
+        _, _, s1 = sim.moments(fields=False)
+        assert np.allclose(np.array(s1[1:]) - np.array(s0[1:]), F.sum(axis=(1, 2, 3)), rtol=0,
+                           atol=1e-15)
+        assert abs(s1[0] - s0[0]) < 1e-10
+        s0 = s1
+    sim.close()
+
+
+@pytest.mark.gpu
+def test_poiseuille_on_gpu():
+    """Body-force channel between bounce-back walls, FP64: the closed form with the half-way
+    bounce-back slip (the same closed form that pins the oracle)."""
+    N, Fz, omega = 12, 1e-6, 1.0
+    shape = (N, 2, 2)
+    sim = S.Simulation(shape, omega, precision="f64", bc=(BB, BB, PER, PER, PER, PER), flags=FLAGS)
+    F = np.zeros((3, 2, 2, N))
+    F[2] = Fz
+    sim.force.copy_(torch.from_numpy(F))
+    sim.liquid_steps(8000)
+    tau = 1 / omega
+    nu = (2 * tau - 1) / 6
+    x = np.arange(N)
+    ex = Fz / (2 * nu) * (x + 0.5) * (N - 0.5 - x) + Fz * ((2 * tau - 1) ** 2 - 0.75) / (2 * tau - 1)
+    U = sim.vel.cpu().numpy()
+    assert np.max(np.abs(U[2, 1, 1] - ex)) / ex.max() < 1e-12
+    sim.close()

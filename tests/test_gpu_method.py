@@ -1,0 +1,158 @@
+"""GPU parity of the coupled method (Algorithm 1: forward coupling, bubble ODE, backward
+coupling, fused liquid step) against the CPU oracle through the C ABI, with the tolerances the
+method targets: FP64 <= 1e-12 relative L2 on u after 1000 steps, FP32 <= 2e-5, bubble position
+<= 1e-4 lattice units."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_common import gpu_sim, gpu_u, oracle_state, rel_l2
+from paper_1710_07073_amd import lbm as L
+from paper_1710_07073_amd import sim as S
+
+BB, FS, PER = O.BC_BOUNCE_BACK, O.BC_FREE_SLIP, O.BC_PERIODIC
+U_TOL = {"f64": 1e-12, "f32": 2e-5}
+POS_TOL = 1e-4
+
+
+def _run_both(w, steps, check_every=None, nthreads=0):
+    sim = gpu_sim(w)
+    lat, bub, P = oracle_state(w)
+    worst_pos = 0.0
+    for n in range(steps):
+        sim.step(1)
+        O.method_step(lat, P, bub, nthreads)
+        if check_every and (n + 1) % check_every == 0:
+            worst_pos = max(worst_pos, np.abs(sim.bubbles.positions() - bub.pos).max())
+    return sim, lat, bub, worst_pos
+
+
+@pytest.mark.gpu
+def test_plain_fp64_column_1000_steps():
+    """32 x 32 x 64, omega = 1, bounce-back walls, one bubble d = 3 at (16, 16, 8)."""
+    w = W.plain_fp64(steps=1000)
+    print(f"[case] {w.name} {w.steps} steps", flush=True)
+    sim, lat, bub, worst = _run_both(w, w.steps, check_every=100)
+    u, sums = gpu_u(sim)
+    _, u_o, sums_o = lat.moments()
+    err = rel_l2(u, u_o)
+    print(f"rel-L2(u) = {err:.3e}, max |dx_b| = {worst:.3e}", flush=True)
+    assert err <= U_TOL["f64"]
+    assert np.abs(sim.bubbles.positions() - bub.pos).max() <= POS_TOL
+    assert np.abs(sim.bubbles.velocities() - bub.vel).max() <= 1e-12 * np.abs(bub.vel).max()
+    assert worst <= POS_TOL
+    g = sim.populations().cpu().numpy()
+    assert rel_l2(g, lat.g) <= U_TOL["f64"]
+    assert abs(sums[0] - sums_o[0]) < 1e-9
+    # the bubble rose
+    assert bub.pos[2, 0] > 8.0
+    sim.close()
+
+
+@pytest.mark.gpu
+def test_single_bubble_fp32_reduced_column():
+    """FP32 shifted populations (omega = 1.6, d = 4 released at the bottom centre) on a column
+    narrow enough for the oracle to follow 400 steps."""
+    w = W.single_fp32()
+    w = W.Workload("single_fp32_48x48x128", (48, 48, 128), w.omega, w.bc,
+                   np.array([[23.5], [23.5], [8.0]]), w.d, w.params, 400, "f32")
+    sim, lat, bub, worst = _run_both(w, w.steps, check_every=50)
+    u, _ = gpu_u(sim)
+    _, u_o, _ = lat.moments()
+    err = rel_l2(u, u_o)
+    print(f"rel-L2(u) = {err:.3e}, max |dx_b| = {worst:.3e}", flush=True)
+    assert err <= U_TOL["f32"]
+    assert worst <= POS_TOL
+    sim.close()
+
+
+def _many_bubbles(shape, bc, nb, seed, dtype, omega=1.4, steps=60, g=1e-4, dmin=1.5, dmax=4.0):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    d = rng.uniform(dmin, dmax, nb)
+    pos = np.stack([rng.uniform(0, nx - 1, nb), rng.uniform(0, ny - 1, nb), rng.uniform(0, nz - 1, nb)])
+    return W.Workload(f"many_{shape}_{bc}", shape, omega, bc, pos, d,
+                      W.params(g=g, sigma=W.sigma_for(g, 3.0)), steps, dtype)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape,bc", [
+    ((40, 36, 48), (BB,) * 6),
+    ((37, 29, 41), (BB, BB, BB, BB, BB, FS)),
+    ((32, 32, 40), (PER, PER, PER, PER, BB, BB)),
+    ((24, 26, 30), (PER,) * 6),
+])
+def test_many_bubbles_near_walls(prec, shape, bc):
+    """Overlapping windows, windows clipped by walls or wrapped by periodic faces, bubbles that
+    reach the top and stop."""
+    w = _many_bubbles(shape, bc, 24, seed=11, dtype=prec)
+    print(f"[case] {w.name} {prec}", flush=True)
+    sim, lat, bub, worst = _run_both(w, w.steps, check_every=10)
+    u, _ = gpu_u(sim)
+    _, u_o, _ = lat.moments()
+    assert rel_l2(u, u_o) <= U_TOL[prec]
+    assert worst <= POS_TOL
+    assert np.array_equal(sim.bubbles.state(), bub.state)
+    sim.close()
+
+
+@pytest.mark.gpu
+def test_periodic_box_momentum_equals_reactions_on_gpu():
+    """Fully periodic FP64 box with bubbles: the liquid gains exactly the spread reactions."""
+    w = _many_bubbles((28, 24, 32), (PER,) * 6, 6, seed=12, dtype="f64")
+    sim = gpu_sim(w)
+    _, _, s0 = sim.moments(fields=False)
+    for _ in range(15):
+        sim.step(1)
+        _, _, s1 = sim.moments(fields=False)
+        psi = sim.bubbles.reactions().sum(axis=1)
+        scale = np.abs(sim.bubbles.reactions()).sum()
+        assert np.allclose(np.array(s1[1:]) - np.array(s0[1:]), psi, rtol=0, atol=1e-12 * scale)
+        s0 = s1
+    sim.close()
+
+
+@pytest.mark.gpu
+def test_single_bubble_run_is_bitwise_deterministic():
+    w = W.Workload("det", (48, 40, 64), 1.5, (BB,) * 6, np.array([[20.3], [17.9], [9.1]]),
+                   np.array([3.3]), W.params(g=1e-4, sigma=1e-4), 50, "f32")
+    outs = []
+    for _ in range(2):
+        sim = gpu_sim(w)
+        sim.step(w.steps)
+        outs.append((sim.populations().cpu().numpy(), sim.bubbles.positions()))
+        sim.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.gpu
+def test_no_bubbles_and_inactive_bubbles():
+    w = W.Workload("inactive", (20, 20, 24), 1.0, (BB,) * 6, np.array([[10.0], [10.0], [22.95]]),
+                   np.array([2.0]), W.params(g=1e-4, sigma=1e-4), 3, "f64",
+                   vel=np.array([[0.0], [0.0], [0.2]]))
+    sim, lat, bub, _ = _run_both(w, 3)
+    assert sim.bubbles.state()[0] == 0 and bub.state[0] == 0
+    assert np.allclose(sim.bubbles.positions(), bub.pos, rtol=0, atol=1e-13)
+    assert np.all(sim.bubbles.reactions() == 0)
+    sim.close()
+    sim = S.Simulation((20, 20, 24), 1.0, precision="f64")
+    sim.add_bubbles(np.zeros((3, 0)), np.zeros(0), S.bubble_params())
+    sim.step(2)
+    assert torch.count_nonzero(sim.populations()).item() == 0
+    sim.close()
+
+
+@pytest.mark.gpu
+def test_bubble_beyond_stencil_limit_is_reported():
+    sim = S.Simulation((96, 96, 96), 1.0, precision="f32")
+    sim.add_bubbles([[48.0], [48.0], [48.0]], [30.0], S.bubble_params())  # window 91 cells wide
+    sim.step(1)
+    with pytest.raises(L.LbmError) as e:
+        sim.check()
+    assert e.value.code == L.LBM_EINVAL
+    sim.check()  # the error was cleared
+    assert torch.count_nonzero(sim.force).item() == 0
+    sim.close()
