@@ -87,10 +87,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="single_fp32", choices=["single_fp32", "plain_fp64"])
+    ap.add_argument("--workload", default="single_fp32", choices=["single_fp32", "plain_fp64", "dense"])
     ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch", default=None, help="vec,block_x of the liquid step (skips tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()
@@ -104,7 +106,7 @@ def main():
     from paper_1710_07073_amd import lbm as L
     from paper_1710_07073_amd import sim as S
 
-    w = W.single_fp32() if args.workload == "single_fp32" else W.plain_fp64()
+    w = {"single_fp32": W.single_fp32, "plain_fp64": W.plain_fp64, "dense": W.dense}[args.workload]()
     if args.precision:
         w = W.Workload(w.name.replace("fp32", args.precision).replace("fp64", args.precision),
                        w.shape, w.omega, w.bc, w.pos, w.d, w.params, w.steps, args.precision)
@@ -112,6 +114,21 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     sim = S.Simulation(w.shape, w.omega, precision=w.dtype, bc=w.bc, device=dev, stream=stream)
+    launch = {"vec": None, "bx": None, "tuned": False}
+    if args.launch:
+        vec, bx = (int(v) for v in args.launch.split(","))
+        L.lbm_set_launch(sim.ctx, vec, bx)
+        launch.update(vec=vec, bx=bx)
+    elif not args.no_autotune:
+        # the liquid is at rest before the bubbles are added: tuning steps leave it unchanged
+        from paper_1710_07073_amd import autotune
+        vec, bx, entry = autotune.tune(sim, use_cache=False)
+        launch.update(vec=vec, bx=bx, tuned=True)
+        for v, b, us in entry["sweep"]:
+            print(f"[autotune] vec={v} bx={b}: {us:.1f} us", file=sys.stderr, flush=True)
+    else:
+        vec, bx = L.lbm_get_launch(sim.ctx)
+        launch.update(vec=vec, bx=bx)
     sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
     print(f"[bench] {w.name}: {w.cells} cells, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
@@ -162,14 +179,15 @@ def main():
         "dtype": w.dtype,
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.shape), "cells": w.cells,
-                   "omega": w.omega, "bubbles": w.nb, "bubble_diameter": float(w.d[0]),
+                   "omega": w.omega, "bubbles": w.nb, "bubble_diameter": float(np.median(w.d)),
                    "populations": f"D3Q19 shifted f-w, {w.dtype}", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_step (fused collide-stream)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": round(kern_s * 1e3, 5),
-                     "kernel_mlups": round(w.cells / kern_s / 1e6, 1)},
+                     "kernel_mlups": round(w.cells / kern_s / 1e6, 1),
+                     "launch": launch},
         "mass_drift": sums[0] - w.cells,
     }
     sim.close()

@@ -99,7 +99,13 @@ typedef struct {
   double *ulx, *uly, *ulz;
   int32_t *state;
   double *psix, *psiy, *psiz; /* nullable: receives the reaction spread in the last step */
+  double *work;               /* device scratch of nb * LBM_BUBBLE_WORK doubles */
 } bubble_soa;
+
+/* Doubles of per-bubble device scratch that bubbles_step() needs in bubble_soa.work (the
+ * interpolated liquid velocity and vorticity, the start position and the reaction of the step,
+ * passed between its kernels). Its contents need no initialisation. */
+#define LBM_BUBBLE_WORK 16
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -121,6 +127,12 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
 
 /* Change the stream later calls enqueue on. */
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
+
+/* Launch shape of the liquid step (the tuning knob of the autotuner; results do not depend on
+ * it): vec = cells per thread along x (1, 2 or 4, must divide nx), block_x = threads per 256-thread
+ * workgroup along x (16, 32, 64, 128 or 256). lbm_init() picks a default. */
+lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t vec, int32_t block_x);
+lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* vec, int32_t* block_x);
 
 /* nsteps liquid steps (Sec. 2.2, eq. (13)-(16) with the face conditions of Sec. 3.3): first
  * forcing (13), BGK collision (14), Guo forcing (12), (15), streaming (16). Each step reads the

@@ -1,0 +1,97 @@
+"""Launch-shape autotuner of the fused liquid step.
+
+The step kernel has two shape parameters (see lbm_set_launch in include/lbm.h): cells per thread
+along x (1, 2, 4) and threads per workgroup along x. Results do not depend on them; speed does,
+and the best choice depends on the row length nx, the precision and the machine. The tuner times
+every valid candidate with HIP events on the simulation's stream, keeps the fastest, and caches
+the winner per size class (precision, nx, bucketed ny*nz) in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import torch
+
+from . import lbm as L
+
+CACHE = os.environ.get("LBM_AUTOTUNE_CACHE",
+                       os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib",
+                                    "autotune_cache.json"))
+
+
+def candidates(nx):
+    out = []
+    for vec in (1, 2, 4):
+        if nx % vec:
+            continue
+        per_row = nx // vec
+        for bx in (16, 32, 64, 128, 256):
+            if bx > 2 * per_row and bx > 64:
+                continue  # mostly idle lanes
+            out.append((vec, bx))
+    return out
+
+
+def size_class(shape, precision):
+    nx, ny, nz = shape
+    plane = ny * nz
+    bucket = 1 << max(0, int(plane - 1).bit_length())  # next power of two of ny*nz
+    return f"p{precision}_nx{nx}_yz{bucket}"
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(db):
+    os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def time_launch(sim, vec, bx, steps=20, warmup=3):
+    """Average duration (s) of one liquid-step launch with the given shape."""
+    L.lbm_set_launch(sim.ctx, vec, bx)
+    stream = sim.stream
+    L.lbm_step(sim.ctx, warmup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    L.lbm_step(sim.ctx, steps)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / steps
+
+
+def tune(sim, steps=20, use_cache=True, verbose=False):
+    """Pick the fastest launch shape for this simulation's lattice and apply it. The lattice state
+    advances by the timing steps (callers tune before loading their initial state, or on a
+    scratch simulation of the same shape)."""
+    key = size_class(sim.shape, sim.precision)
+    db = _load() if use_cache else {}
+    if key in db:
+        vec, bx = db[key]["vec"], db[key]["bx"]
+        L.lbm_set_launch(sim.ctx, vec, bx)
+        return vec, bx, db[key]
+    results = []
+    for vec, bx in candidates(sim.shape[0]):
+        t = time_launch(sim, vec, bx, steps)
+        results.append((t, vec, bx))
+        if verbose:
+            print(f"  vec={vec} bx={bx}: {t * 1e6:.1f} us/step", flush=True)
+    results.sort()
+    t, vec, bx = results[0]
+    L.lbm_set_launch(sim.ctx, vec, bx)
+    entry = {"vec": vec, "bx": bx, "us_per_step": t * 1e6,
+             "sweep": [[v, b, r * 1e6] for r, v, b in results], "time": time.time()}
+    db[key] = entry
+    _save(db)
+    return vec, bx, entry

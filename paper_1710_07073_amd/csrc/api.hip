@@ -12,7 +12,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t tiles, partials, result, status, total;
+  size_t tiles[2], partials, result, status, total;
   uint32_t ntiles, nred, tnx, tny, tnz;
 };
 
@@ -43,8 +43,9 @@ Layout layout_of(const lbm_desc* d) {
   const uint32_t cells = (uint32_t)d->nx * d->ny * d->nz;
   L.nred = lbm::div_up(cells, 256);
   if (L.nred > lbm::kRedBlocks) L.nred = lbm::kRedBlocks;
-  L.tiles = 0;
-  L.partials = align_up(L.tiles + L.ntiles);
+  L.tiles[0] = 0;
+  L.tiles[1] = align_up(L.ntiles);
+  L.partials = align_up(L.tiles[1] + L.ntiles);
   L.result = align_up(L.partials + (size_t)L.nred * 4 * sizeof(double));
   L.status = align_up(L.result + 4 * sizeof(double));
   L.total = align_up(L.status + sizeof(int32_t));
@@ -97,7 +98,10 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->force = force;
   c->vel = vel;
   uint8_t* s = static_cast<uint8_t*>(scratch);
-  c->tiles = s + L.tiles;
+  c->tiles[0] = s + L.tiles[0];
+  c->tiles[1] = s + L.tiles[1];
+  c->flag_cur = 0;
+  c->flag_clean[0] = c->flag_clean[1] = true;
   c->ntiles = L.ntiles;
   c->partials = reinterpret_cast<double*>(s + L.partials);
   c->result = reinterpret_cast<double*>(s + L.result);
@@ -105,6 +109,7 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->nred = L.nred;
   c->stream = static_cast<hipStream_t>(stream);
   c->steps = 0;
+  lbm::default_launch(G.nx, c->elem, &c->step_vec, &c->step_bx);
   const size_t cells = G.N;
   hipError_t e = lbm::launch_fill(pops_a, 19 * cells * c->elem, c->stream);
   if (e == hipSuccess) e = lbm::launch_fill(pops_b, 19 * cells * c->elem, c->stream);
@@ -125,6 +130,24 @@ lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream) {
   return LBM_OK;
 }
 
+lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t vec, int32_t block_x) {
+  if (!ctx) return LBM_EINVAL;
+  if (vec != 1 && vec != 2 && vec != 4) return LBM_EINVAL;
+  if (block_x != 16 && block_x != 32 && block_x != 64 && block_x != 128 && block_x != 256)
+    return LBM_EINVAL;
+  if (ctx->desc.nx % vec != 0) return LBM_EINVAL;
+  ctx->step_vec = vec;
+  ctx->step_bx = (uint32_t)block_x;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* vec, int32_t* block_x) {
+  if (!ctx || !vec || !block_x) return LBM_EINVAL;
+  *vec = ctx->step_vec;
+  *block_x = (int32_t)ctx->step_bx;
+  return LBM_OK;
+}
+
 lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps) {
   if (!ctx || nsteps < 0) return LBM_EINVAL;
   for (int32_t i = 0; i < nsteps; ++i) {
@@ -141,7 +164,7 @@ lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* 
   if (!(p->kernel_factor > 0.0) || !(p->sigma > 0.0) || !(p->rho_l > 0.0)) return LBM_EINVAL;
   if (nb > 0) {
     if (!s->x || !s->y || !s->z || !s->ux || !s->uy || !s->uz || !s->d || !s->ulx || !s->uly ||
-        !s->ulz || !s->state)
+        !s->ulz || !s->state || !s->work)
       return LBM_EINVAL;
     const bool any_psi = s->psix || s->psiy || s->psiz;
     const bool all_psi = s->psix && s->psiy && s->psiz;

@@ -1,14 +1,20 @@
-// Bubble half of one step of Algorithm 1, fused into one kernel with one workgroup per bubble:
-//   1. cell-integral weights of the clipped fourth-order polynomial kernel along each axis
-//      (eq. (18)-(19)), clipped at walls and renormalised, wrapped on periodic axes;
-//   2. forward coupling (eq. (20)): the liquid velocity of the previous collision and its curl
-//      (central differences, wall ghosts) are staged chunk by chunk in LDS and summed with the
-//      weights, wavefront reductions in double precision;
-//   3. the bubble ODE (eq. (1)-(4), Table 1) on one lane: n_sub explicit sub-steps with the
-//      added-mass term on the left-hand side, in double precision;
-//   4. backward coupling (eq. (21)): the reaction -(F_D + F_L) at the updated velocity is spread
-//      into the force field with the same weights (atomic adds), and the 8^3 tiles the liquid step
-//      must force, or must write the velocity in for the next interpolation, are flagged.
+// Bubble half of one step of Algorithm 1 as three kernels:
+//   k_interp  (one workgroup per bubble) cell-integral weights of the clipped fourth-order
+//             polynomial kernel (eq. (18)-(19)) and the forward coupling (eq. (20)) of the
+//             liquid velocity and of its curl, reduced across the workgroup in double precision;
+//   k_ode     (one lane per bubble) the force closures of Table 1 and n_sub explicit sub-steps
+//             of eq. (4), in double precision;
+//   k_spread  (one workgroup per bubble) the backward coupling (eq. (21)) of the reaction
+//             -(F_D + F_L) into the force field with the same weights (atomic adds), and the
+//             tiles the liquid step must force, or must write the velocity in, are flagged.
+//
+// The curl is the central-difference curl of the velocity with wall ghosts (bounce-back ghost =
+// -U of the mirror cell, free-slip ghost = mirror cell with the normal component negated). Its
+// kernel-weighted sum is evaluated by summation by parts: since the weights are separable,
+//   sum_j w(j) (U(j+1) - U(j-1)) / 2 = sum_j U(j) dw(j),  dw(j) = (w(j-1) - w(j+1)) / 2,
+// plus the folded ghost terms at a wall, so every cell of the window widened by one is read once
+// and no neighbour values are needed. A component is never differentiated along its own axis,
+// so the ghost sign along an axis is -1 at a bounce-back face and +1 at a free-slip face.
 #include <math.h>
 
 #include "internal.hpp"
@@ -16,9 +22,13 @@
 namespace lbm {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kMax = LBM_MAX_STENCIL;
-constexpr int kLdsBytes = 48 * 1024;
+constexpr int kMax = LBM_MAX_STENCIL;  // window cells per axis
+constexpr int kSpan = kMax + 2;        // window widened by one cell on each side
+constexpr int kWork = LBM_BUBBLE_WORK; // doubles of per-bubble workspace
+constexpr int kBlock = 256;            // threads per bubble in the stencil kernels
+constexpr int kBlockWaves = kBlock / 64;
+// workspace slots
+constexpr int W_UL = 0, W_WL = 3, W_X0 = 6, W_PSI = 9, W_VALID = 12;
 
 struct BubbleArgs {
   Geom G;
@@ -38,73 +48,8 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 __device__ __forceinline__ double kernel_P(double s) {
   if (s <= -1.0) return 0.0;
   if (s >= 1.0) return 1.0;
-  return 0.5 + 15.0 / 16.0 * (s - 2.0 / 3.0 * s * s * s + 0.2 * pow(s, 5.0));
-}
-
-// Velocity at an integer position at most one cell outside the domain, with the wall ghosts:
-// bounce-back negates the mirror cell's velocity, free slip negates its normal component.
-template <typename T>
-__device__ __forceinline__ void ghost_velocity(const T* __restrict__ U, const Geom& G, int x, int y,
-                                               int z, double out[3]) {
-  int p[3] = {x, y, z};
-  const int ext[3] = {G.nx, G.ny, G.nz};
-  double sign[3] = {1.0, 1.0, 1.0};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (G.bc[2 * a] == BC_PER) {
-      p[a] = wrapi(p[a], ext[a]);
-    } else if (p[a] < 0 || p[a] >= ext[a]) {
-      const int side = p[a] < 0 ? 0 : 1;
-      p[a] = side == 0 ? -1 - p[a] : 2 * ext[a] - 1 - p[a];
-      if (G.bc[2 * a + side] == BC_FS) {
-        sign[a] = -sign[a];
-      } else {
-        sign[0] = -sign[0];
-        sign[1] = -sign[1];
-        sign[2] = -sign[2];
-      }
-    }
-  }
-  const uint32_t c = ((uint32_t)p[2] * G.ny + p[1]) * G.nx + p[0];
-  out[0] = sign[0] * (double)U[c];
-  out[1] = sign[1] * (double)U[G.N + c];
-  out[2] = sign[2] * (double)U[2 * (size_t)G.N + c];
-}
-
-struct Closure {
-  double cdu, cl;
-};
-
-// Table 1 drag and lift coefficients with Re = |u_r| d / nu; C_D is returned multiplied by |u_r|.
-__device__ __forceinline__ Closure closures(const bubble_params& P, double nu, double d,
-                                            double urm, double Eo, double Eod) {
-  const double Re = urm * d / nu;
-  const double visc = fmin(24.0 * nu / d * (1.0 + P.cd_k * pow(Re, 0.687)), 48.0 * nu / d);
-  const double shape = 8.0 / 3.0 * Eo / (Eo + 4.0) * urm;
-  const double f = 0.00105 * Eod * Eod * Eod - 0.0159 * Eod * Eod - 0.0204 * Eod + P.lift_f0;
-  double cl;
-  if (Eod < 4.0)
-    cl = fmin(0.288 * tanh(0.121 * Re), f);
-  else if (Eod <= 10.0)
-    cl = f;
-  else
-    cl = -0.29;
-  return {fmax(visc, shape), cl};
-}
-
-__device__ __forceinline__ void drag_lift(const bubble_params& P, double nu, double d, double Eo,
-                                          double Eod, const double ub[3], const double ul[3],
-                                          const double wl[3], double FD[3], double FL[3]) {
-  const double pi = 3.14159265358979323846;
-  const double ur[3] = {ub[0] - ul[0], ub[1] - ul[1], ub[2] - ul[2]};
-  const double mag = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
-  const Closure c = closures(P, nu, d, mag, Eo, Eod);
-  const double V = pi * d * d * d / 6.0;
-  const double r = 0.5 * d;
-  for (int a = 0; a < 3; ++a) FD[a] = -0.5 * P.drag_scale * c.cdu * P.rho_l * pi * r * r * ur[a];
-  const double cr[3] = {ur[1] * wl[2] - ur[2] * wl[1], ur[2] * wl[0] - ur[0] * wl[2],
-                        ur[0] * wl[1] - ur[1] * wl[0]};
-  for (int a = 0; a < 3; ++a) FL[a] = -P.lift_scale * c.cl * P.rho_l * V * cr[a];
+  const double s2 = s * s;
+  return 0.5 + 15.0 / 16.0 * (s - 2.0 / 3.0 * s2 * s + 0.2 * s2 * s2 * s);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -113,291 +58,398 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Tile ranges touched along one axis by the cell range [vlo, vhi] (virtual, may wrap when
-// periodic): up to two ranges of 8-cell tiles.
-struct TileRanges {
-  int n;
-  int lo[2], hi[2];
+// The window of one bubble along one axis: cells [lo, hi] overlap the kernel support
+// [x - n, x + n]; [clo, chi] is the part inside the domain (all of it on a periodic axis, in
+// unwrapped coordinates); [dlo, dhi] widens that by one cell, clipped to the domain unless
+// periodic.
+struct Axis {
+  int lo, hi, clo, chi, dlo, dhi;
 };
 
-__device__ TileRanges tile_ranges(int vlo, int vhi, int ext, bool periodic) {
-  TileRanges t;
-  if (!periodic) {
-    vlo = vlo < 0 ? 0 : vlo;
-    vhi = vhi > ext - 1 ? ext - 1 : vhi;
-    t.n = vlo <= vhi ? 1 : 0;
-    t.lo[0] = vlo / (int)kTile;
-    t.hi[0] = vhi / (int)kTile;
-    return t;
+__device__ __forceinline__ bool axis_window(double x, double n, int ext, bool per, Axis& w) {
+  const double lo = floor(x - n - 0.5) + 1.0;
+  const double hi = ceil(x + n + 0.5) - 1.0;
+  if (!(hi - lo + 1.0 <= (double)kMax) || !(lo > -1e9) || !(hi < 1e9)) return false;
+  w.lo = (int)lo;
+  w.hi = (int)hi;
+  w.clo = per ? w.lo : max(w.lo, 0);
+  w.chi = per ? w.hi : min(w.hi, ext - 1);
+  if (w.clo > w.chi) return false;
+  w.dlo = per ? w.clo - 1 : max(w.clo - 1, 0);
+  w.dhi = per ? w.chi + 1 : min(w.chi + 1, ext - 1);
+  return true;
+}
+
+// Weights w and derivative weights dw of the bubble at xb along the three axes, into LDS,
+// indexed by (cell - lo + 1). Called by the whole workgroup; the first wavefront computes.
+__device__ bool build_weights(const Geom& G, const double xb[3], double n, int tid,
+                              double (*s_w)[kSpan], double (*s_dw)[kSpan], Axis win[3]) {
+  const int ext[3] = {G.nx, G.ny, G.nz};
+  for (int a = 0; a < 3; ++a) {
+    const bool per = G.bc[2 * a] == BC_PER;
+    if (!axis_window(xb[a], n, ext[a], per, win[a])) return false;
   }
-  if (vhi - vlo + 1 >= ext) {
-    t.n = 1;
-    t.lo[0] = 0;
-    t.hi[0] = (ext - 1) / (int)kTile;
-    return t;
+  const int lane = tid;
+  if (tid < 64) {
+  for (int a = 0; a < 3; ++a) {
+    const bool per = G.bc[2 * a] == BC_PER;
+    const Axis& A = win[a];
+    // raw cell integrals on [clo, chi], zero elsewhere
+    double part = 0.0;
+    for (int i = lane; i < kSpan; i += 64) {
+      const int v = A.lo - 1 + i;
+      double w = 0.0;
+      if (v >= A.clo && v <= A.chi)
+        w = kernel_P((v + 0.5 - xb[a]) / n) - kernel_P((v - 0.5 - xb[a]) / n);
+      s_w[a][i] = w;
+      part += w;
+    }
+    // clipped at a wall: renormalise the axis to a sum of one
+    if (!per) {
+      const double sum = wave_sum(part);
+      if (sum > 0.0)
+        for (int i = lane; i < kSpan; i += 64) s_w[a][i] /= sum;
+    }
   }
-  const int a = wrapi(vlo, ext), b = wrapi(vhi, ext);
-  if (a <= b) {
-    t.n = 1;
-    t.lo[0] = a / (int)kTile;
-    t.hi[0] = b / (int)kTile;
-  } else {
-    t.n = 2;
-    t.lo[0] = a / (int)kTile;
-    t.hi[0] = (ext - 1) / (int)kTile;
-    t.lo[1] = 0;
-    t.hi[1] = b / (int)kTile;
   }
+  __syncthreads();
+  if (tid < 64) {
+  for (int a = 0; a < 3; ++a) {
+    const bool per = G.bc[2 * a] == BC_PER;
+    const Axis& A = win[a];
+    const double s_lo = G.bc[2 * a] == BC_FS ? 1.0 : -1.0;
+    const double s_hi = G.bc[2 * a + 1] == BC_FS ? 1.0 : -1.0;
+    for (int i = lane; i < kSpan; i += 64) {
+      const int v = A.lo - 1 + i;
+      const double wm = i > 0 ? s_w[a][i - 1] : 0.0;
+      const double wp = i + 1 < kSpan ? s_w[a][i + 1] : 0.0;
+      double dw = 0.5 * (wm - wp);
+      if (!per) {
+        if (v == 0) dw -= 0.5 * s_lo * s_w[a][i];           // ghost below cell 0
+        if (v == ext[a] - 1) dw += 0.5 * s_hi * s_w[a][i];  // ghost above the last cell
+      }
+      s_dw[a][i] = dw;
+    }
+  }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Bubble handled by a workgroup: consecutive workgroups on one XCD take consecutive bubbles, so
+// a caller that orders its bubbles in space keeps each XCD's share of the force field in its L2.
+__device__ __forceinline__ int bubble_of_block(int nb) { return (int)xcd_remap(blockIdx.x, nb); }
+
+__device__ __forceinline__ double block_sum(double v, double* s_red, int tid) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((tid & 63) == 0) s_red[tid >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kBlockWaves; ++w) t += s_red[w];
   return t;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Forward coupling: u_l = sum W U and w_l = sum W curl U over the window.
+// ---------------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bubbles(const T* __restrict__ U, T* __restrict__ F,
-                                                      uint8_t* __restrict__ tiles, BubbleArgs A) {
-  constexpr int CAP = kLdsBytes / (3 * (int)sizeof(T));
-  __shared__ T s_u[3][CAP];
-  __shared__ double s_w[3][kMax];
-  __shared__ int s_i[3][kMax];  // wrapped cell index, -1 outside a wall
-  __shared__ double s_red[6][kThreads / 64];
-  __shared__ double s_psi[3];
-  __shared__ int s_box[3][2];   // clipped window, virtual coordinates
-  __shared__ int s_lo[3];       // unclipped window start
-  __shared__ int s_next[3][2];  // window at the new position
-  __shared__ int s_ok;
-
-  const Geom& G = A.G;
-  const int b = blockIdx.x;
+__global__ __launch_bounds__(kBlock) void k_interp(const T* __restrict__ U, BubbleArgs A) {
+  __shared__ double s_w[3][kSpan];
+  __shared__ double s_dw[3][kSpan];
+  __shared__ double s_red[kBlockWaves];
+  const int b = bubble_of_block(A.nb);
   const int tid = threadIdx.x;
-  const int ext[3] = {G.nx, G.ny, G.nz};
+  const Geom& G = A.G;
+  double* work = A.S.work + (size_t)b * kWork;
   if (A.S.state[b] == 0) {
-    if (tid == 0 && A.S.psix) {
+    if (tid == 0) work[W_VALID] = 0.0;
+    return;
+  }
+  const double xb[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
+  const double d = A.S.d[b];
+  const double n = A.P.kernel_factor * d;
+  Axis win[3];
+  const bool finite = isfinite(xb[0]) && isfinite(xb[1]) && isfinite(xb[2]) && d > 0.0;
+  if (!finite || !build_weights(G, xb, n, tid, s_w, s_dw, win)) {
+    if (tid == 0) {
+      work[W_VALID] = 0.0;
+      atomicOr(A.status, (int32_t)STATUS_STENCIL_TOO_LARGE);
+    }
+    return;
+  }
+  const int Dx = win[0].dhi - win[0].dlo + 1;
+  const int Dy = win[1].dhi - win[1].dlo + 1;
+  const int Dz = win[2].dhi - win[2].dlo + 1;
+  const int total = Dx * Dy * Dz;
+  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int f = tid; f < total; f += kBlock) {
+    const int i = f % Dx, r = f / Dx;
+    const int j = r % Dy, k = r / Dy;
+    const int vx = win[0].dlo + i, vy = win[1].dlo + j, vz = win[2].dlo + k;
+    const int ix = vx - win[0].lo + 1, iy = vy - win[1].lo + 1, iz = vz - win[2].lo + 1;
+    const int x = px ? wrapi(vx, G.nx) : vx;
+    const int y = py ? wrapi(vy, G.ny) : vy;
+    const int z = pz ? wrapi(vz, G.nz) : vz;
+    const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
+    const double ux = (double)U[c], uy = (double)U[G.N + c], uz = (double)U[2 * (size_t)G.N + c];
+    const double wa = s_w[0][ix], da = s_dw[0][ix];
+    const double wb = s_w[1][iy], db = s_dw[1][iy];
+    const double wc = s_w[2][iz], dc = s_dw[2][iz];
+    const double W = wa * wb * wc;
+    const double a_dbc = wa * db * wc;  // weight of d/dy
+    const double a_bdc = wa * wb * dc;  // weight of d/dz
+    const double da_bc = da * wb * wc;  // weight of d/dx
+    acc[0] += W * ux;
+    acc[1] += W * uy;
+    acc[2] += W * uz;
+    acc[3] += uz * a_dbc - uy * a_bdc;  // dUz/dy - dUy/dz
+    acc[4] += ux * a_bdc - uz * da_bc;  // dUx/dz - dUz/dx
+    acc[5] += uy * da_bc - ux * a_dbc;  // dUy/dx - dUx/dy
+  }
+  for (int m = 0; m < 6; ++m) acc[m] = block_sum(acc[m], s_red, tid);
+  if (tid == 0) {
+    for (int m = 0; m < 6; ++m) work[W_UL + m] = acc[m];
+    work[W_X0 + 0] = xb[0];
+    work[W_X0 + 1] = xb[1];
+    work[W_X0 + 2] = xb[2];
+    work[W_VALID] = 1.0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Bubble dynamics, one lane per bubble.
+// ---------------------------------------------------------------------------------------------
+// Per-bubble constants of the Table 1 closures (they depend on the diameter only).
+struct BubbleConst {
+  double V, r2pi, fb, inv_meff, va;  // volume, pi r^2, buoyancy, 1/m_eff, (1 + C_A) rho_l V
+  double visc24, visc48, re_sat;     // 24 nu/d, 48 nu/d, Re beyond which 48/Re wins
+  double shape;                      // 8/3 Eo/(Eo + 4)
+  double f_lift;                     // f(Eo_d)
+  double Eod;
+};
+
+__device__ BubbleConst bubble_constants(const bubble_params& P, double nu, double d) {
+  const double pi = 3.14159265358979323846;
+  BubbleConst k;
+  k.V = pi * d * d * d / 6.0;
+  const double r = 0.5 * d;
+  k.r2pi = pi * r * r;
+  k.fb = (P.rho_l - P.rho_b) * k.V * P.g;
+  k.inv_meff = 1.0 / (P.rho_b * k.V + P.c_a * P.rho_l * k.V);
+  k.va = (1.0 + P.c_a) * P.rho_l * k.V;
+  k.visc24 = 24.0 * nu / d;
+  k.visc48 = 48.0 * nu / d;
+  // 1 + k Re^0.687 >= 2 for Re >= (1/k)^(1/0.687): there the min{} of C_D is 48/Re
+  k.re_sat = P.cd_k > 0.0 ? exp(log(1.0 / P.cd_k) / 0.687) : INFINITY;
+  const double Eo = (P.rho_l - P.rho_b) * P.g * d * d / P.sigma;
+  k.shape = 8.0 / 3.0 * Eo / (Eo + 4.0);
+  const double E = 1.0 / (1.0 + 0.163 * exp(0.757 * log(Eo)));
+  k.Eod = Eo / exp(2.0 / 3.0 * log(E));
+  k.f_lift = 0.00105 * k.Eod * k.Eod * k.Eod - 0.0159 * k.Eod * k.Eod - 0.0204 * k.Eod + P.lift_f0;
+  return k;
+}
+
+// Drag and lift of Table 1 on a bubble moving at ub in liquid of velocity ul and vorticity wl,
+// with Re = |u_r| d / nu (eq. (3)). C_D is used multiplied by |u_r| so that the viscous
+// branches stay finite at u_r = 0: 24/Re |u_r| = 24 nu / d.
+__device__ __forceinline__ void drag_lift(const bubble_params& P, const BubbleConst& k, double d,
+                                          double nu, const double ub[3], const double ul[3],
+                                          const double wl[3], double FD[3], double FL[3]) {
+  const double ur[3] = {ub[0] - ul[0], ub[1] - ul[1], ub[2] - ul[2]};
+  const double mag = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
+  const double Re = mag * d / nu;
+  double visc = k.visc48;
+  if (Re < k.re_sat && Re > 0.0)
+    visc = fmin(k.visc24 * (1.0 + P.cd_k * exp(0.687 * log(Re))), k.visc48);
+  else if (Re == 0.0)
+    visc = fmin(k.visc24, k.visc48);
+  const double cdu = fmax(visc, k.shape * mag);
+  double cl;
+  if (k.Eod < 4.0)
+    cl = fmin(0.288 * tanh(0.121 * Re), k.f_lift);
+  else if (k.Eod <= 10.0)
+    cl = k.f_lift;
+  else
+    cl = -0.29;
+  const double dpre = -0.5 * P.drag_scale * cdu * P.rho_l * k.r2pi;
+  for (int a = 0; a < 3; ++a) FD[a] = dpre * ur[a];
+  const double cr[3] = {ur[1] * wl[2] - ur[2] * wl[1], ur[2] * wl[0] - ur[0] * wl[2],
+                        ur[0] * wl[1] - ur[1] * wl[0]};
+  const double lpre = -P.lift_scale * cl * P.rho_l * k.V;
+  for (int a = 0; a < 3; ++a) FL[a] = lpre * cr[a];
+}
+
+__global__ __launch_bounds__(64) void k_ode(BubbleArgs A) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (b >= A.nb) return;
+  const Geom& G = A.G;
+  const bubble_params& P = A.P;
+  double* work = A.S.work + (size_t)b * kWork;
+  const int st = A.S.state[b];
+  if (st == 0 || work[W_VALID] == 0.0) {
+    if (A.S.psix) {
       A.S.psix[b] = 0.0;
       A.S.psiy[b] = 0.0;
       A.S.psiz[b] = 0.0;
     }
     return;
   }
-  const double xb[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
+  const int ext[3] = {G.nx, G.ny, G.nz};
   const double d = A.S.d[b];
-  const double n = A.P.kernel_factor * d;
-
-  if (tid == 0) {
-    int ok = isfinite(xb[0]) && isfinite(xb[1]) && isfinite(xb[2]) && d > 0.0 && isfinite(n);
-    for (int a = 0; a < 3 && ok; ++a) {
-      const double lo = floor(xb[a] - n - 0.5) + 1.0;
-      const double hi = ceil(xb[a] + n + 0.5) - 1.0;
-      if (!(hi - lo + 1.0 <= (double)kMax) || lo < -1e9 || hi > 1e9) {
-        ok = 0;
-        break;
-      }
-      s_lo[a] = (int)lo;
-      const bool per = G.bc[2 * a] == BC_PER;
-      int clo = (int)lo, chi = (int)hi;
-      if (!per) {
-        clo = clo < 0 ? 0 : clo;
-        chi = chi > ext[a] - 1 ? ext[a] - 1 : chi;
-      }
-      if (clo > chi) ok = 0;  // window entirely outside the domain
-      s_box[a][0] = clo;
-      s_box[a][1] = chi;
-    }
-    if (!ok) atomicOr(A.status, (int32_t)STATUS_STENCIL_TOO_LARGE);
-    s_ok = ok;
+  const double ul[3] = {work[W_UL], work[W_UL + 1], work[W_UL + 2]};
+  const double wl[3] = {work[W_WL], work[W_WL + 1], work[W_WL + 2]};
+  double dul[3] = {0.0, 0.0, 0.0};
+  if (st == 2) {  // material derivative of u_l along the path, dt_l = 1
+    dul[0] = ul[0] - A.S.ulx[b];
+    dul[1] = ul[1] - A.S.uly[b];
+    dul[2] = ul[2] - A.S.ulz[b];
   }
-  __syncthreads();
-  if (!s_ok) return;
-
-  // 1. axis weights
-  for (int k = tid; k < 3 * kMax; k += kThreads) {
-    const int a = k / kMax, i = k % kMax;
-    const int v = s_lo[a] + i;
-    const bool per = G.bc[2 * a] == BC_PER;
-    double w = kernel_P((v + 0.5 - xb[a]) / n) - kernel_P((v - 0.5 - xb[a]) / n);
-    int idx = per ? wrapi(v, ext[a]) : v;
-    if (!per && (v < 0 || v >= ext[a])) {
-      idx = -1;
-      w = 0.0;
+  const BubbleConst kc = bubble_constants(P, A.nu, d);
+  const double dt = 1.0 / P.n_sub;
+  double ub[3] = {A.S.ux[b], A.S.uy[b], A.S.uz[b]};
+  double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
+  for (int k = 0; k < P.n_sub; ++k) {
+    // (m_b + C_A rho_l V) du_b/dt = F_B + F_D + F_L + (1 + C_A) rho_l V D_t u_l
+    double FD[3], FL[3];
+    drag_lift(P, kc, d, A.nu, ub, ul, wl, FD, FL);
+    for (int a = 0; a < 3; ++a) {
+      double f = FD[a] + FL[a] + kc.va * dul[a];
+      if (a == 2) f += kc.fb;
+      ub[a] += dt * f * kc.inv_meff;
     }
-    s_w[a][i] = w;
-    s_i[a][i] = idx;
-  }
-  __syncthreads();
-  if (tid < 3) {
-    const int a = tid;
-    if (G.bc[2 * a] != BC_PER) {
-      double sum = 0.0;
-      for (int v = s_box[a][0]; v <= s_box[a][1]; ++v) sum += s_w[a][v - s_lo[a]];
-      if (sum > 0.0)
-        for (int v = s_box[a][0]; v <= s_box[a][1]; ++v) s_w[a][v - s_lo[a]] /= sum;
-    }
-  }
-  __syncthreads();
-
-  // 2. forward coupling, staged in LDS chunk by chunk (whole x extent, chunks of y and z)
-  const int kx = s_box[0][1] - s_box[0][0] + 1;
-  const int ky = s_box[1][1] - s_box[1][0] + 1;
-  const int kz = s_box[2][1] - s_box[2][0] + 1;
-  const int ex = kx + 2;
-  int sy = ky, sz = kz;
-  // the window is at most kMax + 2 cells wide in x, so one 3 x 3 chunk column always fits
-  static_assert((kMax + 2) * 9 <= CAP, "LDS staging buffer too small");
-  while (ex * (sy + 2) * (sz + 2) > CAP) {
-    if (sz >= sy && sz > 1)
-      --sz;
-    else if (sy > 1)
-      --sy;
-    else
-      break;
-  }
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int z0 = 0; z0 < kz; z0 += sz) {
-    const int cz = kz - z0 < sz ? kz - z0 : sz;
-    for (int y0 = 0; y0 < ky; y0 += sy) {
-      const int cy = ky - y0 < sy ? ky - y0 : sy;
-      const int ey = cy + 2, ez = cz + 2;
-      const int tot = ex * ey * ez;
-      for (int k = tid; k < tot; k += kThreads) {
-        const int lx = k % ex, ly = (k / ex) % ey, lz = k / (ex * ey);
-        double v[3];
-        ghost_velocity(U, G, s_box[0][0] - 1 + lx, s_box[1][0] + y0 - 1 + ly,
-                       s_box[2][0] + z0 - 1 + lz, v);
-        s_u[0][k] = (T)v[0];
-        s_u[1][k] = (T)v[1];
-        s_u[2][k] = (T)v[2];
-      }
-      __syncthreads();
-      const int cells = kx * cy * cz;
-      for (int k = tid; k < cells; k += kThreads) {
-        const int i = k % kx, j = (k / kx) % cy, l = k / (kx * cy);
-        const double W = s_w[0][s_box[0][0] + i - s_lo[0]] * s_w[1][s_box[1][0] + y0 + j - s_lo[1]] *
-                         s_w[2][s_box[2][0] + z0 + l - s_lo[2]];
-        const int c0 = ((l + 1) * ey + (j + 1)) * ex + (i + 1);
-        const int xp = c0 + 1, xm = c0 - 1, yp = c0 + ex, ym = c0 - ex, zp = c0 + ex * ey,
-                  zm = c0 - ex * ey;
-        const double dUz_dy = 0.5 * ((double)s_u[2][yp] - (double)s_u[2][ym]);
-        const double dUy_dz = 0.5 * ((double)s_u[1][zp] - (double)s_u[1][zm]);
-        const double dUx_dz = 0.5 * ((double)s_u[0][zp] - (double)s_u[0][zm]);
-        const double dUz_dx = 0.5 * ((double)s_u[2][xp] - (double)s_u[2][xm]);
-        const double dUy_dx = 0.5 * ((double)s_u[1][xp] - (double)s_u[1][xm]);
-        const double dUx_dy = 0.5 * ((double)s_u[0][yp] - (double)s_u[0][ym]);
-        acc[0] += W * (double)s_u[0][c0];
-        acc[1] += W * (double)s_u[1][c0];
-        acc[2] += W * (double)s_u[2][c0];
-        acc[3] += W * (dUz_dy - dUy_dz);
-        acc[4] += W * (dUx_dz - dUz_dx);
-        acc[5] += W * (dUy_dx - dUx_dy);
-      }
-      __syncthreads();
-    }
-  }
-#pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    const double s = wave_sum(acc[m]);
-    if ((tid & 63) == 0) s_red[m][tid >> 6] = s;
-  }
-  __syncthreads();
-
-  // 3. the bubble ODE on one lane
-  if (tid == 0) {
-    double ul[3], wl[3];
-    for (int m = 0; m < 3; ++m) {
-      ul[m] = s_red[m][0] + s_red[m][1] + s_red[m][2] + s_red[m][3];
-      wl[m] = s_red[3 + m][0] + s_red[3 + m][1] + s_red[3 + m][2] + s_red[3 + m][3];
-    }
-    const bubble_params& P = A.P;
-    double dul[3] = {0.0, 0.0, 0.0};
-    const int st = A.S.state[b];
-    if (st == 2) {
-      dul[0] = ul[0] - A.S.ulx[b];
-      dul[1] = ul[1] - A.S.uly[b];
-      dul[2] = ul[2] - A.S.ulz[b];
-    }
-    const double pi = 3.14159265358979323846;
-    const double V = pi * d * d * d / 6.0;
-    const double m_eff = P.rho_b * V + P.c_a * P.rho_l * V;
-    const double FB = (P.rho_l - P.rho_b) * V * P.g;
-    const double Eo = (P.rho_l - P.rho_b) * P.g * d * d / P.sigma;
-    const double E = 1.0 / (1.0 + 0.163 * pow(Eo, 0.757));
-    const double Eod = Eo / pow(E, 2.0 / 3.0);
-    const double dt = 1.0 / P.n_sub;
-    double ub[3] = {A.S.ux[b], A.S.uy[b], A.S.uz[b]};
-    double xn[3] = {xb[0], xb[1], xb[2]};
-    for (int k = 0; k < P.n_sub; ++k) {
-      double FD[3], FL[3];
-      drag_lift(P, A.nu, d, Eo, Eod, ub, ul, wl, FD, FL);
-      for (int a = 0; a < 3; ++a) {
-        double f = FD[a] + FL[a] + (1.0 + P.c_a) * P.rho_l * V * dul[a];
-        if (a == 2) f += FB;
-        ub[a] += dt * f / m_eff;
-      }
-      for (int a = 0; a < 3; ++a) {
-        xn[a] += dt * ub[a];
-        if (G.bc[2 * a] == BC_PER) {
-          const double L = (double)ext[a];
-          xn[a] = fmod(xn[a], L);
-          if (xn[a] < 0.0) xn[a] += L;
-        } else {
-          if (xn[a] < 0.0) {
-            xn[a] = 0.0;
-            ub[a] = 0.0;
-          }
-          if (a != 2 && xn[a] > ext[a] - 1.0) {
-            xn[a] = ext[a] - 1.0;
-            ub[a] = 0.0;
-          }
+    for (int a = 0; a < 3; ++a) {
+      xn[a] += dt * ub[a];
+      if (G.bc[2 * a] == BC_PER) {
+        const double L = (double)ext[a];
+        xn[a] = fmod(xn[a], L);
+        if (xn[a] < 0.0) xn[a] += L;
+      } else {
+        if (xn[a] < 0.0) {
+          xn[a] = 0.0;
+          ub[a] = 0.0;
+        }
+        if (a != 2 && xn[a] > ext[a] - 1.0) {
+          xn[a] = ext[a] - 1.0;
+          ub[a] = 0.0;
         }
       }
     }
-    double FD[3], FL[3];
-    drag_lift(P, A.nu, d, Eo, Eod, ub, ul, wl, FD, FL);
-    for (int a = 0; a < 3; ++a) s_psi[a] = -(FD[a] + FL[a]);
-    A.S.x[b] = xn[0];
-    A.S.y[b] = xn[1];
-    A.S.z[b] = xn[2];
-    A.S.ux[b] = ub[0];
-    A.S.uy[b] = ub[1];
-    A.S.uz[b] = ub[2];
-    A.S.ulx[b] = ul[0];
-    A.S.uly[b] = ul[1];
-    A.S.ulz[b] = ul[2];
-    int nst = 2;
-    if (G.bc[4] != BC_PER && xn[2] >= ext[2] - 1.0) nst = 0;  // reached the top layer
-    A.S.state[b] = nst;
-    if (A.S.psix) {
-      A.S.psix[b] = s_psi[0];
-      A.S.psiy[b] = s_psi[1];
-      A.S.psiz[b] = s_psi[2];
-    }
-    for (int a = 0; a < 3; ++a) {
-      // window at the new position, widened by the curl halo of the next interpolation
-      const double nlo = floor(xn[a] - n - 0.5) + 1.0;
-      const double nhi = ceil(xn[a] + n + 0.5) - 1.0;
-      s_next[a][0] = (int)fmax(nlo, -1e9) - 1;
-      s_next[a][1] = (int)fmin(nhi, 1e9) + 1;
-    }
   }
-  __syncthreads();
+  double FD[3], FL[3];
+  drag_lift(P, kc, d, A.nu, ub, ul, wl, FD, FL);
+  double psi[3];
+  for (int a = 0; a < 3; ++a) psi[a] = -(FD[a] + FL[a]);
+  A.S.x[b] = xn[0];
+  A.S.y[b] = xn[1];
+  A.S.z[b] = xn[2];
+  A.S.ux[b] = ub[0];
+  A.S.uy[b] = ub[1];
+  A.S.uz[b] = ub[2];
+  A.S.ulx[b] = ul[0];
+  A.S.uly[b] = ul[1];
+  A.S.ulz[b] = ul[2];
+  int nst = 2;
+  if (G.bc[4] != BC_PER && xn[2] >= ext[2] - 1.0) nst = 0;  // reached the top layer
+  A.S.state[b] = nst;
+  for (int a = 0; a < 3; ++a) work[W_PSI + a] = psi[a];
+  if (A.S.psix) {
+    A.S.psix[b] = psi[0];
+    A.S.psiy[b] = psi[1];
+    A.S.psiz[b] = psi[2];
+  }
+}
 
-  // 4. backward coupling: spread psi W into the force field
-  const double psi0 = s_psi[0], psi1 = s_psi[1], psi2 = s_psi[2];
-  const int cells = kx * ky * kz;
-  for (int k = tid; k < cells; k += kThreads) {
-    const int i = k % kx, j = (k / kx) % ky, l = k / (kx * ky);
-    const int vi = s_box[0][0] + i - s_lo[0], vj = s_box[1][0] + j - s_lo[1],
-              vl = s_box[2][0] + l - s_lo[2];
-    const double W = s_w[0][vi] * s_w[1][vj] * s_w[2][vl];
-    const uint32_t c = ((uint32_t)s_i[2][vl] * G.ny + s_i[1][vj]) * G.nx + s_i[0][vi];
+// ---------------------------------------------------------------------------------------------
+// Backward coupling and tile flags.
+// ---------------------------------------------------------------------------------------------
+// Tile ranges touched along one axis by the cell range [vlo, vhi] (unwrapped on a periodic axis):
+// up to two ranges of tiles.
+struct TileRanges {
+  int n;
+  int lo[2], hi[2];
+};
+
+__device__ TileRanges tile_ranges(int vlo, int vhi, int ext, int tile, bool periodic) {
+  TileRanges t;
+  if (!periodic) {
+    vlo = vlo < 0 ? 0 : vlo;
+    vhi = vhi > ext - 1 ? ext - 1 : vhi;
+    t.n = vlo <= vhi ? 1 : 0;
+    t.lo[0] = vlo / tile;
+    t.hi[0] = vhi / tile;
+    return t;
+  }
+  if (vhi - vlo + 1 >= ext) {
+    t.n = 1;
+    t.lo[0] = 0;
+    t.hi[0] = (ext - 1) / tile;
+    return t;
+  }
+  const int a = wrapi(vlo, ext), b = wrapi(vhi, ext);
+  if (a <= b) {
+    t.n = 1;
+    t.lo[0] = a / tile;
+    t.hi[0] = b / tile;
+  } else {
+    t.n = 2;
+    t.lo[0] = a / tile;
+    t.hi[0] = (ext - 1) / tile;
+    t.lo[1] = 0;
+    t.hi[1] = b / tile;
+  }
+  return t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spread(T* __restrict__ F, uint8_t* __restrict__ tiles,
+                                                   BubbleArgs A) {
+  __shared__ double s_w[3][kSpan];
+  __shared__ double s_dw[3][kSpan];
+  const int b = bubble_of_block(A.nb);
+  const int tid = threadIdx.x;
+  const Geom& G = A.G;
+  const double* work = A.S.work + (size_t)b * kWork;
+  if (work[W_VALID] == 0.0) return;
+  const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+  const double n = A.P.kernel_factor * A.S.d[b];
+  Axis win[3];
+  if (!build_weights(G, x0, n, tid, s_w, s_dw, win)) return;  // validated by k_interp
+  const double psi0 = work[W_PSI], psi1 = work[W_PSI + 1], psi2 = work[W_PSI + 2];
+  const int Kx = win[0].chi - win[0].clo + 1;
+  const int Ky = win[1].chi - win[1].clo + 1;
+  const int Kz = win[2].chi - win[2].clo + 1;
+  const int total = Kx * Ky * Kz;
+  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+  for (int f = tid; f < total; f += kBlock) {
+    const int i = f % Kx, r = f / Kx;
+    const int j = r % Ky, k = r / Ky;
+    const int vx = win[0].clo + i, vy = win[1].clo + j, vz = win[2].clo + k;
+    const double W = s_w[0][vx - win[0].lo + 1] * s_w[1][vy - win[1].lo + 1] *
+                     s_w[2][vz - win[2].lo + 1];
+    const int x = px ? wrapi(vx, G.nx) : vx;
+    const int y = py ? wrapi(vy, G.ny) : vy;
+    const int z = pz ? wrapi(vz, G.nz) : vz;
+    const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
     atomicAdd(&F[c], (T)(psi0 * W));
     atomicAdd(&F[G.N + c], (T)(psi1 * W));
     atomicAdd(&F[2 * (size_t)G.N + c], (T)(psi2 * W));
   }
-  // flag the tiles: the force window now, and the velocity window of the next step
+  // flag the tiles: the force window now, and the velocity window (with the curl ring) that the
+  // next interpolation reads at the new position
+  const double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
+  const int ext[3] = {G.nx, G.ny, G.nz};
   TileRanges tr[3];
   for (int a = 0; a < 3; ++a) {
     const bool per = G.bc[2 * a] == BC_PER;
-    const int lo = min(s_box[a][0], s_next[a][0]);
-    const int hi = max(s_box[a][1], s_next[a][1]);
-    tr[a] = tile_ranges(lo, hi, ext[a], per);
+    int lo = win[a].clo, hi = win[a].chi;
+    Axis nw;
+    if (axis_window(xn[a], n, ext[a], per, nw)) {
+      lo = min(lo, nw.dlo);
+      hi = max(hi, nw.dhi);
+    }
+    tr[a] = tile_ranges(lo, hi, ext[a], (int)kTile, per);
   }
   for (int rz = 0; rz < tr[2].n; ++rz)
     for (int ry = 0; ry < tr[1].n; ++ry)
@@ -405,7 +457,7 @@ __global__ __launch_bounds__(kThreads) void k_bubbles(const T* __restrict__ U, T
         const int nx_ = tr[0].hi[rx] - tr[0].lo[rx] + 1;
         const int ny_ = tr[1].hi[ry] - tr[1].lo[ry] + 1;
         const int nz_ = tr[2].hi[rz] - tr[2].lo[rz] + 1;
-        for (int k = tid; k < nx_ * ny_ * nz_; k += kThreads) {
+        for (int k = tid; k < nx_ * ny_ * nz_; k += kBlock) {
           const int tx = tr[0].lo[rx] + k % nx_;
           const int ty = tr[1].lo[ry] + (k / nx_) % ny_;
           const int tz = tr[2].lo[rz] + k / (nx_ * ny_);
@@ -424,15 +476,32 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
   A.nb = nb;
   A.nu = (1.0 / c->desc.omega - 0.5) / 3.0;  // eq. (9), dx = dt_l = 1
   A.status = c->status;
-  hipError_t e = launch_fill(c->tiles, c->ntiles, c->stream);
-  if (e != hipSuccess || nb == 0) return e;
+  // this step's mask: the one the last liquid step cleared (cleared here if no liquid step ran)
+  const int m = c->flag_cur ^ 1;
+  if (!c->flag_clean[m]) {
+    const hipError_t e = launch_fill(c->tiles[m], c->ntiles, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  c->flag_clean[m] = false;
+  c->flag_cur = m;
+  if (nb == 0) return hipSuccess;
   if (c->elem == 4)
-    hipLaunchKernelGGL(k_bubbles<float>, dim3(nb), dim3(kThreads), 0, c->stream,
-                       static_cast<const float*>(c->vel), static_cast<float*>(c->force), c->tiles, A);
+    hipLaunchKernelGGL(k_interp<float>, dim3(nb), dim3(kBlock), 0, c->stream,
+                       static_cast<const float*>(c->vel), A);
   else
-    hipLaunchKernelGGL(k_bubbles<double>, dim3(nb), dim3(kThreads), 0, c->stream,
-                       static_cast<const double*>(c->vel), static_cast<double*>(c->force), c->tiles,
-                       A);
+    hipLaunchKernelGGL(k_interp<double>, dim3(nb), dim3(kBlock), 0, c->stream,
+                       static_cast<const double*>(c->vel), A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ode, dim3(div_up(nb, 64)), dim3(64), 0, c->stream, A);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (c->elem == 4)
+    hipLaunchKernelGGL(k_spread<float>, dim3(nb), dim3(kBlock), 0, c->stream,
+                       static_cast<float*>(c->force), c->tiles[m], A);
+  else
+    hipLaunchKernelGGL(k_spread<double>, dim3(nb), dim3(kBlock), 0, c->stream,
+                       static_cast<double*>(c->force), c->tiles[m], A);
   return hipGetLastError();
 }
 

@@ -18,7 +18,12 @@ struct lbm_ctx {
   int cur;
   void* force;
   void* vel;
-  uint8_t* tiles;   // one byte per 8^3 tile: force present / velocity needed
+  // Two tile masks, one byte per 8^3 tile (force present / velocity needed). bubbles_step()
+  // writes mask[flag_cur ^ 1] and makes it current; each liquid step reads mask[flag_cur] and
+  // clears the other one for the next bubble step.
+  uint8_t* tiles[2];
+  int flag_cur;
+  bool flag_clean[2];
   uint32_t ntiles;
   double* partials; // moments reduction partials (4 doubles per block)
   double* result;   // 4 doubles
@@ -26,6 +31,8 @@ struct lbm_ctx {
   uint32_t nred;    // number of reduction partial slots
   hipStream_t stream;
   int64_t steps;
+  int step_vec;      // cells per thread along x in the liquid step (1, 2, 4)
+  uint32_t step_bx;  // threads per workgroup along x (the workgroup has 256 threads)
 };
 
 namespace lbm {
@@ -45,6 +52,19 @@ hipError_t launch_populations(lbm_ctx* c, void* out);
 hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t s);
 
 inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+// Default launch shape of the liquid step: whole rows per workgroup where they fit.
+inline void default_launch(int nx, size_t elem, int* vec, uint32_t* bx) {
+  (void)elem;
+  *vec = 1;
+  *bx = 64;
+  for (uint32_t b : {256u, 128u}) {
+    if ((uint32_t)nx >= b && nx % b == 0) {
+      *bx = b;
+      break;
+    }
+  }
+}
 
 // Map a hardware workgroup index to a logical one so that the workgroups the dispatcher sends to
 // one XCD (index modulo 8) form a contiguous range of the domain: neighbouring rows then share

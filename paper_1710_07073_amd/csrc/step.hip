@@ -91,10 +91,93 @@ __device__ __forceinline__ void collide(T* g, T Fx, T Fy, T Fz, T omega, T& ux, 
   }
 }
 
-template <typename T, bool GENERAL>
+// VEC consecutive cells along x per thread (VEC = 1, 2 or 4; nx % VEC == 0). Interior threads
+// gather each population as one VEC-wide load: the source run is contiguous in x (shifted by
+// -c_x, so not VEC-aligned when c_x != 0) and lies in one row (y - c_y, z - c_z), so a wall in y
+// or z replaces the whole run. Threads whose run touches x = 0 or x = nx - 1 gather element by
+// element with the full face logic.
+template <typename T, int VEC>
+struct VecT {
+  typedef T type __attribute__((ext_vector_type(VEC)));
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_run(T* out, const T* p) {
+  if constexpr (VEC == 1) {
+    out[0] = *p;
+  } else {
+    typename VecT<T, VEC>::type v;
+    __builtin_memcpy(&v, p, sizeof(v));
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) out[e] = v[e];
+  }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_run(T* p, const T* in, bool nontemporal) {
+  if constexpr (VEC == 1) {
+    if (nontemporal)
+      __builtin_nontemporal_store(in[0], p);
+    else
+      *p = in[0];
+  } else {
+    typename VecT<T, VEC>::type v;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v[e] = in[e];
+    typedef typename VecT<T, VEC>::type vt;
+    if (nontemporal)
+      __builtin_nontemporal_store(v, reinterpret_cast<vt*>(p));
+    else
+      *reinterpret_cast<vt*>(p) = v;
+  }
+}
+
+template <int Q, bool GENERAL, int VEC, typename T>
+__device__ __forceinline__ void pull_run(T (*g)[19], const T* __restrict__ src, const Geom& G,
+                                         uint32_t cell, const CellNbr& nb) {
+  constexpr int cx = CX[Q], cy = CY[Q], cz = CZ[Q];
+  int32_t off = -cx;
+  bool oy = false, oz = false;
+  int32_t dy = 0, dz = 0;
+  if (cy > 0) { dy = nb.dm[1]; oy = nb.om[1]; }
+  if (cy < 0) { dy = nb.dp[1]; oy = nb.op[1]; }
+  if (cz > 0) { dz = nb.dm[2]; oz = nb.om[2]; }
+  if (cz < 0) { dz = nb.dp[2]; oz = nb.op[2]; }
+  off += dy + dz;
+  T v[VEC];
+  if (!(oy || oz)) {
+    load_run<T, VEC>(v, src + (size_t)Q * G.N + (uint32_t)((int32_t)cell + off));
+  } else {
+    bool done = false;
+    if constexpr (GENERAL) {
+      if (oy != oz) {
+        const int a = oy ? 1 : 2;
+        const int c = a == 1 ? cy : cz;
+        if (G.bc[2 * a + (c > 0 ? 0 : 1)] == BC_FS) {
+          const int qm = a == 1 ? mirrored(Q, 1) : mirrored(Q, 2);
+          load_run<T, VEC>(v, src + (size_t)qm * G.N + (uint32_t)((int32_t)cell + off - (a == 1 ? dy : dz)));
+          done = true;
+        }
+      }
+    }
+    if (!done) load_run<T, VEC>(v, src + (size_t)opposite(Q) * G.N + cell);
+  }
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) g[e][Q] = v[e];
+}
+
+template <bool GENERAL, int VEC, typename T, int... Qs>
+__device__ __forceinline__ void pull_runs(T (*g)[19], const T* __restrict__ src, const Geom& G,
+                                          uint32_t cell, const CellNbr& nb,
+                                          std::integer_sequence<int, Qs...>) {
+  (pull_run<Qs, GENERAL, VEC>(g, src, G, cell, nb), ...);
+}
+
+template <typename T, int VEC, bool GENERAL>
 __global__ __launch_bounds__(256) void k_step(const T* __restrict__ src, T* __restrict__ dst,
                                               T* __restrict__ F, T* __restrict__ U,
-                                              const uint8_t* __restrict__ tiles, Geom G, T omega,
+                                              const uint8_t* __restrict__ tiles,
+                                              uint8_t* __restrict__ tiles_next, Geom G, T omega,
                                               int flags, uint32_t bx_blocks, uint32_t by_blocks,
                                               uint32_t nblocks) {
   const uint32_t L = xcd_remap(blockIdx.x, nblocks);
@@ -102,57 +185,89 @@ __global__ __launch_bounds__(256) void k_step(const T* __restrict__ src, T* __re
   const uint32_t rest = L / bx_blocks;
   const uint32_t byi = rest % by_blocks;
   const uint32_t z = rest / by_blocks;
-  const int x = (int)(bxi * blockDim.x + threadIdx.x);
+  const int x0 = (int)(bxi * blockDim.x + threadIdx.x) * VEC;
   const int y = (int)(byi * blockDim.y + threadIdx.y);
-  if (x >= G.nx || y >= G.ny) return;
-  const uint32_t cell = ((uint32_t)z * G.ny + y) * G.nx + x;
-  const CellNbr nb = cell_neighbours(G, x, y, (int)z);
-  T g[19];
-  pull_all<GENERAL>(g, src, G, cell, nb, std::make_integer_sequence<int, 19>{});
+  if (x0 >= G.nx || y >= G.ny) return;
+  const uint32_t cell = ((uint32_t)z * G.ny + y) * G.nx + x0;
+  T g[VEC][19];
+  const bool xedge = VEC > 1 && (x0 == 0 || x0 + VEC == G.nx);
+  if (VEC == 1 || xedge) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const CellNbr nb = cell_neighbours(G, x0 + e, y, (int)z);
+      pull_all<GENERAL>(g[e], src, G, cell + e, nb, std::make_integer_sequence<int, 19>{});
+    }
+  } else {
+    const CellNbr nb = cell_neighbours(G, x0, y, (int)z);
+    pull_runs<GENERAL, VEC>(g, src, G, cell, nb, std::make_integer_sequence<int, 19>{});
+  }
 
   const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
+  const uint32_t tile = ((z >> 3) * G.tny + ((uint32_t)y >> 3)) * G.tnx + ((uint32_t)x0 >> 3);
   bool forced = static_force;
-  if (!static_force) forced = tiles[((z >> 3) * G.tny + ((uint32_t)y >> 3)) * G.tnx + ((uint32_t)x >> 3)] != 0;
-  T ux, uy, uz;
+  if (!static_force) forced = tiles[tile] != 0;
+  // the corner cell of each tile clears that tile in the mask of the next bubble step
+  if (((x0 | y | (int)z) & 7) == 0) tiles_next[tile] = 0;
+  T ux[VEC], uy[VEC], uz[VEC];
   if (__any(forced)) {
-    T Fx = 0, Fy = 0, Fz = 0;
+    T Fx[VEC], Fy[VEC], Fz[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) Fx[e] = Fy[e] = Fz[e] = T(0);
     if (forced) {
-      Fx = F[cell];
-      Fy = F[G.N + cell];
-      Fz = F[2 * (size_t)G.N + cell];
+      load_run<T, VEC>(Fx, F + cell);
+      load_run<T, VEC>(Fy, F + G.N + cell);
+      load_run<T, VEC>(Fz, F + 2 * (size_t)G.N + cell);
     }
-    collide<T, true>(g, Fx, Fy, Fz, omega, ux, uy, uz);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) collide<T, true>(g[e], Fx[e], Fy[e], Fz[e], omega, ux[e], uy[e], uz[e]);
   } else {
-    collide<T, false>(g, T(0), T(0), T(0), omega, ux, uy, uz);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) collide<T, false>(g[e], T(0), T(0), T(0), omega, ux[e], uy[e], uz[e]);
   }
 #pragma unroll
-  for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(g[q], &dst[(size_t)q * G.N + cell]);
+  for (int q = 0; q < 19; ++q) {
+    T v[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v[e] = g[e][q];
+    store_run<T, VEC>(dst + (size_t)q * G.N + cell, v, true);
+  }
   if (forced || (flags & LBM_FLAG_WRITE_U_ALL)) {
-    U[cell] = ux;
-    U[G.N + cell] = uy;
-    U[2 * (size_t)G.N + cell] = uz;
+    store_run<T, VEC>(U + cell, ux, false);
+    store_run<T, VEC>(U + G.N + cell, uy, false);
+    store_run<T, VEC>(U + 2 * (size_t)G.N + cell, uz, false);
   }
   if (forced && !static_force) {
-    F[cell] = T(0);
-    F[G.N + cell] = T(0);
-    F[2 * (size_t)G.N + cell] = T(0);
+    T zero[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) zero[e] = T(0);
+    store_run<T, VEC>(F + cell, zero, false);
+    store_run<T, VEC>(F + G.N + cell, zero, false);
+    store_run<T, VEC>(F + 2 * (size_t)G.N + cell, zero, false);
   }
 }
 
-template <typename T, bool GENERAL>
-hipError_t launch_typed(lbm_ctx* c) {
+template <typename T, int VEC, bool GENERAL>
+hipError_t launch_typed(lbm_ctx* c, uint32_t bx) {
   const Geom& G = c->geom;
-  uint32_t bx = G.nx >= 256 ? 256 : (G.nx >= 128 ? 128 : 64);
-  if (bx > 64 && (G.nx % bx) != 0) bx = 64;
   const uint32_t by = 256 / bx;
-  const uint32_t nbx = div_up(G.nx, bx), nby = div_up(G.ny, by);
+  const uint32_t nbx = div_up(G.nx / VEC, bx), nby = div_up(G.ny, by);
   const uint32_t nblocks = nbx * nby * (uint32_t)G.nz;
   const T* src = static_cast<const T*>(c->pops[c->cur]);
   T* dst = static_cast<T*>(c->pops[c->cur ^ 1]);
-  hipLaunchKernelGGL((k_step<T, GENERAL>), dim3(nblocks), dim3(bx, by), 0, c->stream, src, dst,
-                     static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles, G,
-                     (T)c->desc.omega, c->desc.flags, nbx, nby, nblocks);
+  hipLaunchKernelGGL((k_step<T, VEC, GENERAL>), dim3(nblocks), dim3(bx, by), 0, c->stream, src, dst,
+                     static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->flag_cur],
+                     c->tiles[c->flag_cur ^ 1], G, (T)c->desc.omega, c->desc.flags, nbx, nby,
+                     nblocks);
   return hipGetLastError();
+}
+
+template <typename T, bool GENERAL>
+hipError_t launch_vec(lbm_ctx* c) {
+  switch (c->step_vec) {
+    case 4: return launch_typed<T, 4, GENERAL>(c, c->step_bx);
+    case 2: return launch_typed<T, 2, GENERAL>(c, c->step_bx);
+    default: return launch_typed<T, 1, GENERAL>(c, c->step_bx);
+  }
 }
 
 }  // namespace
@@ -160,11 +275,12 @@ hipError_t launch_typed(lbm_ctx* c) {
 hipError_t launch_step(lbm_ctx* c) {
   hipError_t e;
   if (c->elem == 4)
-    e = c->general ? launch_typed<float, true>(c) : launch_typed<float, false>(c);
+    e = c->general ? launch_vec<float, true>(c) : launch_vec<float, false>(c);
   else
-    e = c->general ? launch_typed<double, true>(c) : launch_typed<double, false>(c);
+    e = c->general ? launch_vec<double, true>(c) : launch_vec<double, false>(c);
   if (e == hipSuccess) {
     c->cur ^= 1;
+    c->flag_clean[c->flag_cur ^ 1] = true;
     ++c->steps;
   }
   return e;

@@ -18,9 +18,11 @@ LBM_FP32_SHIFTED, LBM_FP64_SHIFTED = 1, 2
 LBM_BC_BOUNCE_BACK, LBM_BC_FREE_SLIP, LBM_BC_PERIODIC = 0, 1, 2
 LBM_FLAG_STATIC_FORCE, LBM_FLAG_WRITE_U_ALL = 1, 2
 LBM_MAX_STENCIL = 64
+LBM_BUBBLE_WORK = 16
 
 # every symbol include/lbm.h declares
-EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_step", "bubbles_step",
+EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch", "lbm_get_launch",
+           "lbm_step", "bubbles_step",
            "moments", "lbm_populations", "lbm_state_buffer", "lbm_check", "lbm_destroy",
            "lbm_status_string")
 
@@ -40,7 +42,7 @@ class BubbleParams(ct.Structure):
 
 class BubbleSoA(ct.Structure):
     _fields_ = [(n, ct.c_void_p) for n in ("x", "y", "z", "ux", "uy", "uz", "d", "ulx", "uly", "ulz",
-                                          "state", "psix", "psiy", "psiz")]
+                                          "state", "psix", "psiy", "psiz", "work")]
 
 
 class LbmError(RuntimeError):
@@ -65,6 +67,8 @@ def lib():
                                          ct.POINTER(ct.c_size_t), ct.POINTER(ct.c_size_t)]
         L.lbm_init.argtypes = [ct.POINTER(LbmDesc), P, P, P, P, P, P, ct.POINTER(P)]
         L.lbm_set_stream.argtypes = [P, P]
+        L.lbm_set_launch.argtypes = [P, ct.c_int32, ct.c_int32]
+        L.lbm_get_launch.argtypes = [P, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]
         L.lbm_step.argtypes = [P, ct.c_int32]
         L.bubbles_step.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32]
         L.moments.argtypes = [P, P, P, ct.POINTER(ct.c_double)]
@@ -112,6 +116,16 @@ def lbm_init(desc, pops_a, pops_b, force, vel, scratch, stream):
 
 def lbm_set_stream(ctx, stream):
     _ok(lib().lbm_set_stream(ctx, stream), "lbm_set_stream")
+
+
+def lbm_set_launch(ctx, vec, block_x):
+    _ok(lib().lbm_set_launch(ctx, int(vec), int(block_x)), "lbm_set_launch")
+
+
+def lbm_get_launch(ctx):
+    v, b = ct.c_int32(), ct.c_int32()
+    _ok(lib().lbm_get_launch(ctx, ct.byref(v), ct.byref(b)), "lbm_get_launch")
+    return v.value, b.value
 
 
 def lbm_step(ctx, nsteps=1):

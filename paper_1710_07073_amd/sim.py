@@ -33,8 +33,10 @@ class Bubbles:
         self.t["state"] = torch.ones(max(nb, 1), dtype=torch.int32, device=device)[:nb]
         for k in ("psix", "psiy", "psiz"):
             self.t[k] = torch.zeros(max(nb, 1), dtype=torch.float64, device=device)[:nb]
+        self.t["work"] = torch.empty(max(nb, 1) * L.LBM_BUBBLE_WORK, dtype=torch.float64,
+                                     device=device)
         self.soa = L.BubbleSoA(*[ct.c_void_p(self.t[k].data_ptr()) for k in
-                                 _BUBBLE_FIELDS + ("state", "psix", "psiy", "psiz")])
+                                 _BUBBLE_FIELDS + ("state", "psix", "psiy", "psiz", "work")])
 
     def positions(self):
         return torch.stack([self.t["x"], self.t["y"], self.t["z"]]).cpu().numpy()

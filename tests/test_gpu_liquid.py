@@ -111,3 +111,40 @@ def test_poiseuille_on_gpu():
     U = sim.vel.cpu().numpy()
     assert np.max(np.abs(U[2, 1, 1] - ex)) / ex.max() < 1e-12
     sim.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("shape,bc", [
+    ((128, 12, 10), (BB,) * 6),
+    ((36, 10, 9), (BB, BB, BB, BB, BB, FS)),
+    ((40, 9, 11), (PER, PER, PER, PER, FS, FS)),
+    ((64, 8, 8), (PER,) * 6),
+    ((8, 6, 7), (BB, BB, PER, PER, BB, BB)),
+])
+def test_every_launch_shape_gives_identical_results(prec, shape, bc):
+    """The launch shape (cells per thread, workgroup width) is a tuning knob only: every shape
+    the autotuner may pick reproduces the reference launch bit for bit."""
+    from paper_1710_07073_amd import autotune
+    R = W.random_populations(shape, 1e-3, seed=8)
+    F = W.random_field(shape, 2e-5, seed=9)
+    ref = None
+    for vec, bx in autotune.candidates(shape[0]):
+        sim = S.Simulation(shape, 1.45, precision=prec, bc=bc, flags=FLAGS)
+        L.lbm_set_launch(sim.ctx, vec, bx)
+        set_post_collision_state(sim, R)
+        sim.force.copy_(torch.from_numpy(F).to(sim.dtype))
+        sim.liquid_steps(7)
+        out = (sim.populations().cpu().numpy(), sim.vel.cpu().numpy())
+        sim.close()
+        if ref is None:
+            ref = out
+            lat = O.Lattice(*shape, 1.45, bc, g=O.stream(R.astype(np.float32).astype(np.float64)
+                                                         if prec == "f32" else R, bc))
+            Fo = F.astype(np.float32).astype(np.float64) if prec == "f32" else F
+            for _ in range(7):
+                lat.step(Fo)
+            assert rel_l2(out[0], lat.g) <= TOL[prec]
+        else:
+            assert np.array_equal(out[0], ref[0]), (vec, bx)
+            assert np.array_equal(out[1], ref[1]), (vec, bx)
