@@ -82,12 +82,81 @@ def cpu_baseline(w, budget_s=12.0):
                       f"lattice and bubble, FP64, {threads} OpenMP threads, {el:.1f} s"}
 
 
+def bench_batched(args):
+    """64 uneven columns stepped together (FP32, graph replays), against the same columns run one
+    at a time as plain single-lattice FP64 simulations."""
+    import torch
+    import workloads as W
+    from paper_1710_07073_amd import autotune
+    from paper_1710_07073_amd import lbm as L
+    from paper_1710_07073_amd import sim as S
+
+    ws = W.batched()
+    cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d) for w in ws]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(dev)
+    cells = sum(w.cells for w in ws)
+    gsteps = args.graph_steps or 20
+    with torch.cuda.stream(stream):
+        batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
+        items, sweep = (None, None)
+        if not args.no_autotune:
+            items, sweep = autotune.tune_batch(batch, steps=3)
+            for k, cand, ms in sweep:
+                print(f"[autotune] class {k} item {cand}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+        batch.run(args.warmup + (-args.warmup) % gsteps, graph_steps=gsteps)
+        stream.synchronize()
+        K = max(gsteps, args.steps - args.steps % gsteps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        batch.run(K, graph_steps=gsteps)
+        e1.record(stream)
+        stream.synchronize()
+        elapsed = time.perf_counter() - t0
+        ev_s = e0.elapsed_time(e1) * 1e-3
+        batch.check()
+        batch.close()
+        # plain single-lattice FP64 form: every column on its own, eager launches, a few steps
+        ks = 4
+        t_single = 0.0
+        for w in ws:
+            sim = S.Simulation(w.shape, w.omega, precision="f64", bc=w.bc, stream=stream)
+            sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+            sim.step(1)
+            stream.synchronize()
+            a = time.perf_counter()
+            sim.step(ks)
+            stream.synchronize()
+            t_single += time.perf_counter() - a
+            sim.close()
+    mlups = cells * K / elapsed / 1e6
+    fp64 = cells * ks / t_single / 1e6
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / K * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched_64_columns", "columns": len(ws), "cells": cells,
+                   "bubbles": int(sum(w.nb for w in ws)), "graph_steps": gsteps,
+                   "item_cells": items, "parallelism": "single GPU"},
+        "batched_vs_plain_fp64": {"batched_f32_mlups": round(mlups, 1),
+                                  "plain_fp64_single_mlups": round(fp64, 1),
+                                  "ratio": round(mlups / fp64, 3),
+                                  "event_ms_per_step": round(ev_s / K * 1e3, 5)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="single_fp32", choices=["single_fp32", "plain_fp64", "dense"])
+    ap.add_argument("--workload", default="single_fp32",
+                    choices=["single_fp32", "plain_fp64", "dense", "batched"])
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="replay the step loop from a HIP graph of this many steps (even)")
     ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -106,6 +175,8 @@ def main():
     from paper_1710_07073_amd import lbm as L
     from paper_1710_07073_amd import sim as S
 
+    if args.workload == "batched":
+        return bench_batched(args)
     w = {"single_fp32": W.single_fp32, "plain_fp64": W.plain_fp64, "dense": W.dense}[args.workload]()
     if args.precision:
         w = W.Workload(w.name.replace("fp32", args.precision).replace("fp64", args.precision),

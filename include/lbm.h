@@ -167,8 +167,56 @@ lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out);
  * stencil limit), then clear it. */
 lbm_status lbm_check(lbm_ctx* ctx);
 
+/* nsteps method steps (bubbles_step then lbm_step(ctx, 1), Algorithm 1) with the launches of
+ * graph_steps consecutive steps captured once into a HIP graph and replayed; the graph is kept
+ * while params, soa and nb stay the same. graph_steps must be even (the step alternates two
+ * population buffers), 0 runs every step eagerly. Graph capture needs a non-NULL stream. */
+lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* params, const bubble_soa* soa, int32_t nb,
+                   int32_t nsteps, int32_t graph_steps);
+
 /* Release the context (not the caller's buffers). NULL is accepted. */
 lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batched columns: many independent lattices (uneven extents, each with its own omega and faces)
+ * stepped together, as in the paper's grid-independence and stability sweeps (Sec. 4.2, 4.3).
+ * All columns share the precision and the bubble constants; column c owns bubbles
+ * [bubble_begin, bubble_begin + nb) of one shared bubble_soa, ranges consecutive in column order.
+ * Every buffer lives in one caller-owned pool and one caller-owned scratch block.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t bubble_begin, nb;
+  int32_t bc[6];
+  int32_t reserved;
+  double omega;
+} lbm_column;
+
+typedef struct lbm_batch lbm_batch;
+
+lbm_status lbm_batch_bytes_required(const lbm_column* cols, int32_t ncols, int32_t precision,
+                                    size_t* pool_bytes, size_t* scratch_bytes);
+/* Lay the columns out in pool, initialise every population to g = 0 and the fields to 0. The call
+ * synchronises the stream once (it uploads the column table). */
+lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precision, int32_t flags,
+                          void* pool, void* scratch, void* stream, lbm_batch** out);
+/* Cells per work item of each column in the batched liquid step (multiple of 256, at most 65536):
+ * the tuning knob of the batch autotuner; results do not depend on it. */
+lbm_status lbm_batch_set_items(lbm_batch* batch, const int32_t* item_cells);
+lbm_status lbm_batch_get_items(lbm_batch* batch, int32_t* item_cells);
+/* nsteps method steps of every column (eager launches). nb must equal the total bubble count. */
+lbm_status lbm_batch_step(lbm_batch* batch, const bubble_params* params, const bubble_soa* soa,
+                          int32_t nb, int32_t nsteps);
+/* As lbm_batch_step, with graph_steps steps captured into a HIP graph and replayed (see lbm_run). */
+lbm_status lbm_batch_run(lbm_batch* batch, const bubble_params* params, const bubble_soa* soa,
+                         int32_t nb, int32_t nsteps, int32_t graph_steps);
+/* Pre-collision populations g = f - w of column col (19 x N, lattice type) into device buffer out. */
+lbm_status lbm_batch_populations(lbm_batch* batch, int32_t col, void* out);
+/* Device pointers of column col: current state buffer, force field, velocity field. */
+lbm_status lbm_batch_column(lbm_batch* batch, int32_t col, void** state, void** force, void** vel);
+/* Synchronise and report a pending kernel error (as lbm_check). */
+lbm_status lbm_batch_check(lbm_batch* batch);
+lbm_status lbm_batch_destroy(lbm_batch* batch);
 
 /* Static description of a status code. */
 const char* lbm_status_string(lbm_status status);

@@ -12,6 +12,7 @@ import json
 import os
 import time
 
+import numpy as np
 import torch
 
 from . import lbm as L
@@ -95,3 +96,55 @@ def tune(sim, steps=20, use_cache=True, verbose=False):
     db[key] = entry
     _save(db)
     return vec, bx, entry
+
+
+# ---------------------------------------------------------------------------------------------
+# Batched columns: cells per work item, per column size class
+# ---------------------------------------------------------------------------------------------
+ITEM_CANDIDATES = (256, 512, 1024, 2048, 4096)
+
+
+def column_class(shape):
+    """Size class of a column for the batch tuner: by cells, in factors of 4."""
+    cells = int(np.prod(shape))
+    k = 0
+    while cells > 65536 and k < 4:
+        cells //= 4
+        k += 1
+    return k
+
+
+def time_batch(batch, steps=4, warmup=1):
+    """Average seconds per liquid+bubble step of the whole batch (eager launches)."""
+    batch.step(warmup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(batch.stream)
+    batch.step(steps)
+    e1.record(batch.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / steps
+
+
+def tune_batch(batch, steps=4, verbose=False):
+    """Coordinate descent over the size classes: for each class in turn, try every candidate item
+    size with the other classes fixed, keep the fastest. Applies and returns the per-column item
+    sizes and the sweep. The batch state advances by the timing steps."""
+    ncols = batch.ncols
+    classes = [column_class(c["shape"]) for c in batch.columns]
+    items = L.lbm_batch_get_items(batch.handle, ncols)
+    sweep = []
+    for k in sorted(set(classes)):
+        best = None
+        for cand in ITEM_CANDIDATES:
+            trial = [cand if classes[i] == k else items[i] for i in range(ncols)]
+            L.lbm_batch_set_items(batch.handle, trial)
+            t = time_batch(batch, steps)
+            sweep.append((k, cand, t * 1e3))
+            if verbose:
+                print(f"  class {k} item {cand}: {t * 1e3:.3f} ms/step", flush=True)
+            if best is None or t < best[0]:
+                best = (t, cand)
+        items = [best[1] if classes[i] == k else items[i] for i in range(ncols)]
+    L.lbm_batch_set_items(batch.handle, items)
+    return items, sweep

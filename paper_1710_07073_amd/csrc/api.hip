@@ -213,6 +213,65 @@ lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out) {
   return LBM_OK;
 }
 
+lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, int32_t nb,
+                   int32_t nsteps, int32_t graph_steps) {
+  if (!ctx || !p || !s || nb < 0 || nsteps < 0) return LBM_EINVAL;
+  if (graph_steps < 0 || graph_steps % 2) return LBM_EINVAL;
+  auto one = [&]() -> lbm_status {
+    lbm_status st = bubbles_step(ctx, p, s, nb);
+    if (st != LBM_OK) return st;
+    return lbm_step(ctx, 1);
+  };
+  if (graph_steps == 0 || nsteps < graph_steps || !ctx->stream) {
+    for (int32_t i = 0; i < nsteps; ++i) {
+      const lbm_status st = one();
+      if (st != LBM_OK) return st;
+    }
+    return LBM_OK;
+  }
+  const lbm::GraphKey key = lbm::GraphKey::of(p, s, nb, ctx->cur, ctx->flag_cur, graph_steps);
+  int32_t done = 0;
+  while (nsteps - done >= graph_steps) {
+    const int cur0 = ctx->cur, flag0 = ctx->flag_cur;
+    const bool clean0[2] = {ctx->flag_clean[0], ctx->flag_clean[1]};
+    const int64_t steps0 = ctx->steps;
+    lbm_status st_cap = LBM_OK;
+    bool captured = false;
+    hipError_t e = ctx->graph.ensure(key, ctx->stream,
+                                     [&]() -> hipError_t {
+                                       for (int i = 0; i < graph_steps; ++i) {
+                                         st_cap = one();
+                                         if (st_cap != LBM_OK) return hipErrorInvalidValue;
+                                       }
+                                       return hipSuccess;
+                                     },
+                                     &captured);
+    if (st_cap != LBM_OK) return st_cap;
+    if (e != hipSuccess) return LBM_EDEVICE;
+    // the capture only recorded the launches: rewind the host-side step state, then replay
+    ctx->cur = cur0;
+    ctx->flag_cur = flag0;
+    ctx->flag_clean[0] = clean0[0];
+    ctx->flag_clean[1] = clean0[1];
+    ctx->steps = steps0;
+    if (ctx->graph.launch(ctx->stream) != hipSuccess) return LBM_EDEVICE;
+    for (int i = 0; i < graph_steps; ++i) {  // advance the host state as the steps did
+      const int m = ctx->flag_cur ^ 1;
+      ctx->flag_clean[m] = false;
+      ctx->flag_cur = m;
+      ctx->cur ^= 1;
+      ctx->flag_clean[ctx->flag_cur ^ 1] = true;
+      ++ctx->steps;
+    }
+    done += graph_steps;
+  }
+  for (int32_t i = done; i < nsteps; ++i) {
+    const lbm_status st = one();
+    if (st != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_destroy(lbm_ctx* ctx) {
   delete ctx;
   return LBM_OK;

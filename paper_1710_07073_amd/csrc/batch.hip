@@ -1,0 +1,473 @@
+// Batched columns: many independent lattices of uneven size and relaxation rate (the paper's
+// grid-independence and stability sweeps, Sec. 4.2-4.3) advanced together. One liquid-step launch
+// covers every column through a table of work items (contiguous cell ranges of one column); the
+// bubbles of all columns go through the same three bubble kernels as a single lattice. Repeated
+// steps are captured once into a HIP graph and replayed (graph.hpp).
+#include <math.h>
+#include <new>
+#include <string.h>
+#include <vector>
+
+#include "collide.hpp"
+#include "graph.hpp"
+
+struct lbm_batch {
+  int ncols;
+  int32_t precision;
+  size_t elem;
+  bool general;
+  int flags;
+  std::vector<lbm_column> cols;       // as given
+  std::vector<lbm::ColumnDev> host;   // device-side table, host copy
+  lbm::ColumnDev* dev;                // device table (scratch)
+  int32_t* bubble_col;                // bubble -> column (scratch)
+  int32_t nb_total;
+  uint32_t nitems;
+  int cur;          // population buffer holding the current state, same for all columns
+  int flag_cur;     // current tile mask, same for all columns
+  bool flag_clean[2];
+  int32_t* status;
+  double* partials;
+  double* result;
+  uint32_t nred;
+  hipStream_t stream;
+  int64_t steps;
+  lbm::StepGraph graph;
+};
+
+namespace lbm {
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Exact x = cell % nx, y = (cell / nx) % ny, z = cell / (nx ny) for cell < 2^31, through a
+// double-precision reciprocal and one correction step each.
+__device__ __forceinline__ uint32_t div_exact(uint32_t a, uint32_t d, double inv) {
+  uint32_t q = (uint32_t)((double)a * inv);
+  if (q * d > a) --q;
+  if ((q + 1) * d <= a) ++q;
+  return q;
+}
+
+template <typename T, bool GENERAL>
+__global__ __launch_bounds__(256) void k_batch_step(const ColumnDev* __restrict__ cols, int ncols,
+                                                    uint32_t nitems, int cur, int flag, int flags) {
+  const uint32_t item = xcd_remap(blockIdx.x, nitems);
+  int lo = 0, hi = ncols - 1;
+  while (lo < hi) {  // last column whose first item is <= item
+    const int mid = (lo + hi + 1) >> 1;
+    if (cols[mid].item_begin <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const ColumnDev& C = cols[lo];
+  const Geom G = C.G;
+  const T* __restrict__ src = static_cast<const T*>(C.pops[cur]);
+  T* __restrict__ dst = static_cast<T*>(C.pops[cur ^ 1]);
+  T* __restrict__ F = static_cast<T*>(C.F);
+  T* __restrict__ U = static_cast<T*>(C.U);
+  const uint8_t* __restrict__ tiles = C.tiles[flag];
+  uint8_t* __restrict__ tiles_next = C.tiles[flag ^ 1];
+  const T omega = (T)C.omega;
+  const double inv_nx = 1.0 / G.nx, inv_plane = 1.0 / G.plane;
+  const uint32_t first = (item - C.item_begin) * C.item_cells;
+  const uint32_t last = min(first + C.item_cells, G.N);
+  for (uint32_t cell = first + threadIdx.x; cell < last; cell += 256) {
+    const uint32_t z = div_exact(cell, G.plane, inv_plane);
+    const uint32_t rem = cell - z * G.plane;
+    const uint32_t y = div_exact(rem, (uint32_t)G.nx, inv_nx);
+    const uint32_t x = rem - y * G.nx;
+    const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
+    T g[19];
+    pull_all<GENERAL>(g, src, G, cell, nb, std::make_integer_sequence<int, 19>{});
+    const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
+    const uint32_t tile = ((z >> 3) * G.tny + (y >> 3)) * G.tnx + (x >> 3);
+    bool forced = static_force;
+    if (!static_force) forced = tiles[tile] != 0;
+    if (((x | y | z) & 7) == 0) tiles_next[tile] = 0;
+    T ux, uy, uz;
+    if (__any(forced)) {
+      T Fx = 0, Fy = 0, Fz = 0;
+      if (forced) {
+        Fx = F[cell];
+        Fy = F[G.N + cell];
+        Fz = F[2 * (size_t)G.N + cell];
+      }
+      collide<T, true>(g, Fx, Fy, Fz, omega, ux, uy, uz);
+    } else {
+      collide<T, false>(g, T(0), T(0), T(0), omega, ux, uy, uz);
+    }
+#pragma unroll
+    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(g[q], &dst[(size_t)q * G.N + cell]);
+    if (forced || (flags & LBM_FLAG_WRITE_U_ALL)) {
+      U[cell] = ux;
+      U[G.N + cell] = uy;
+      U[2 * (size_t)G.N + cell] = uz;
+    }
+    if (forced && !static_force) {
+      F[cell] = T(0);
+      F[G.N + cell] = T(0);
+      F[2 * (size_t)G.N + cell] = T(0);
+    }
+  }
+}
+
+template <typename T, bool GENERAL>
+__global__ __launch_bounds__(256) void k_batch_populations(const ColumnDev* __restrict__ col, int cur,
+                                                           T* __restrict__ out) {
+  const Geom G = col->G;
+  const uint32_t cell = blockIdx.x * 256 + threadIdx.x;
+  if (cell >= G.N) return;
+  const T* __restrict__ src = static_cast<const T*>(col->pops[cur]);
+  const uint32_t x = cell % G.nx, y = (cell / G.nx) % G.ny, z = cell / G.plane;
+  const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
+  T g[19];
+  pull_all<GENERAL>(g, src, G, cell, nb, std::make_integer_sequence<int, 19>{});
+#pragma unroll
+  for (int q = 0; q < 19; ++q) out[(size_t)q * G.N + cell] = g[q];
+}
+
+bool column_ok(const lbm_column& c) {
+  if (c.nx < 1 || c.ny < 1 || c.nz < 1 || c.reserved != 0) return false;
+  if (!(c.omega > 0.0 && c.omega < 2.0)) return false;
+  if (c.nb < 0 || c.bubble_begin < 0) return false;
+  for (int a = 0; a < 3; ++a) {
+    const int lo = c.bc[2 * a], hi = c.bc[2 * a + 1];
+    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return false;
+    if ((lo == LBM_BC_PERIODIC) != (hi == LBM_BC_PERIODIC)) return false;
+  }
+  const double cells = (double)c.nx * c.ny * c.nz;
+  return cells * 19.0 < 2147483648.0;
+}
+
+struct BatchLayout {
+  std::vector<size_t> pops0, pops1, force, vel, tiles0, tiles1;
+  std::vector<uint32_t> ntiles;
+  size_t pool, table, bcol, partials, result, status, scratch;
+  int32_t nb_total;
+};
+
+bool layout_batch(const lbm_column* cols, int ncols, size_t elem, BatchLayout& L) {
+  L.pool = 0;
+  size_t tiles = 0;
+  L.nb_total = 0;
+  for (int c = 0; c < ncols; ++c) {
+    const lbm_column& k = cols[c];
+    if (!column_ok(k)) return false;
+    // columns own consecutive, non-overlapping bubble ranges in column order
+    if (k.bubble_begin != L.nb_total) return false;
+    L.nb_total += k.nb;
+    const size_t n = (size_t)k.nx * k.ny * k.nz;
+    L.pops0.push_back(L.pool);
+    L.pool = align_up(L.pool + 19 * n * elem);
+    L.pops1.push_back(L.pool);
+    L.pool = align_up(L.pool + 19 * n * elem);
+    L.force.push_back(L.pool);
+    L.pool = align_up(L.pool + 3 * n * elem);
+    L.vel.push_back(L.pool);
+    L.pool = align_up(L.pool + 3 * n * elem);
+    const uint32_t nt = div_up(k.nx, kTile) * div_up(k.ny, kTile) * div_up(k.nz, kTile);
+    L.ntiles.push_back(nt);
+    L.tiles0.push_back(tiles);
+    tiles = align_up(tiles + nt);
+    L.tiles1.push_back(tiles);
+    tiles = align_up(tiles + nt);
+  }
+  L.table = tiles;
+  L.bcol = align_up(L.table + (size_t)ncols * sizeof(ColumnDev));
+  L.partials = align_up(L.bcol + (size_t)(L.nb_total > 0 ? L.nb_total : 1) * sizeof(int32_t));
+  L.result = align_up(L.partials + (size_t)kRedBlocks * 4 * sizeof(double));
+  L.status = align_up(L.result + 4 * sizeof(double));
+  L.scratch = align_up(L.status + sizeof(int32_t));
+  return true;
+}
+
+uint32_t default_item_cells(const lbm_column& c) {
+  (void)c;
+  return 1024;
+}
+
+void assign_items(lbm_batch* b) {
+  uint32_t item = 0;
+  for (int c = 0; c < b->ncols; ++c) {
+    ColumnDev& D = b->host[c];
+    D.item_begin = item;
+    D.items = div_up(D.G.N, D.item_cells);
+    item += D.items;
+  }
+  b->nitems = item;
+}
+
+hipError_t upload_table(lbm_batch* b) {
+  hipError_t e = hipMemcpyAsync(b->dev, b->host.data(), b->host.size() * sizeof(ColumnDev),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(b->stream);
+}
+
+template <typename T, bool GENERAL>
+hipError_t batch_step_typed(lbm_batch* b) {
+  hipLaunchKernelGGL((k_batch_step<T, GENERAL>), dim3(b->nitems), dim3(256), 0, b->stream, b->dev,
+                     b->ncols, b->nitems, b->cur, b->flag_cur, b->flags);
+  return hipGetLastError();
+}
+
+// One method step of every column: bubble half, then the liquid step.
+hipError_t batch_method_step(lbm_batch* b, const bubble_params* p, const bubble_soa* s, int32_t nb) {
+  const int m = b->flag_cur ^ 1;
+  if (!b->flag_clean[m]) {
+    for (int c = 0; c < b->ncols; ++c) {
+      const hipError_t e = launch_fill(b->host[c].tiles[m],
+                                       (size_t)b->host[c].G.tnx * b->host[c].G.tny *
+                                           div_up(b->host[c].G.nz, kTile),
+                                       b->stream);
+      if (e != hipSuccess) return e;
+    }
+  }
+  b->flag_clean[m] = false;
+  b->flag_cur = m;
+  hipError_t e = launch_bubbles_batch(b->dev, b->bubble_col, m, b->elem, p, s, nb, b->status,
+                                      b->stream);
+  if (e != hipSuccess) return e;
+  if (b->elem == 4)
+    e = b->general ? batch_step_typed<float, true>(b) : batch_step_typed<float, false>(b);
+  else
+    e = b->general ? batch_step_typed<double, true>(b) : batch_step_typed<double, false>(b);
+  if (e != hipSuccess) return e;
+  b->cur ^= 1;
+  b->flag_clean[b->flag_cur ^ 1] = true;
+  ++b->steps;
+  return hipSuccess;
+}
+
+lbm_status to_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+lbm_status lbm_batch_bytes_required(const lbm_column* cols, int32_t ncols, int32_t precision,
+                                    size_t* pool_bytes, size_t* scratch_bytes) {
+  if (!cols || ncols < 1) return LBM_EINVAL;
+  if (precision != LBM_FP32_SHIFTED && precision != LBM_FP64_SHIFTED) return LBM_EINVAL;
+  BatchLayout L;
+  if (!layout_batch(cols, ncols, precision == LBM_FP32_SHIFTED ? 4 : 8, L)) return LBM_EINVAL;
+  if (pool_bytes) *pool_bytes = L.pool;
+  if (scratch_bytes) *scratch_bytes = L.scratch;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precision, int32_t flags,
+                          void* pool, void* scratch, void* stream, lbm_batch** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  if (!cols || ncols < 1 || !pool || !scratch) return LBM_EINVAL;
+  if (precision != LBM_FP32_SHIFTED && precision != LBM_FP64_SHIFTED) return LBM_EINVAL;
+  if (flags & ~(LBM_FLAG_STATIC_FORCE | LBM_FLAG_WRITE_U_ALL)) return LBM_EINVAL;
+  const size_t elem = precision == LBM_FP32_SHIFTED ? 4 : 8;
+  BatchLayout L;
+  if (!layout_batch(cols, ncols, elem, L)) return LBM_EINVAL;
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return LBM_EDEVICE;
+  b->ncols = ncols;
+  b->precision = precision;
+  b->elem = elem;
+  b->flags = flags;
+  b->general = false;
+  b->cols.assign(cols, cols + ncols);
+  b->nb_total = L.nb_total;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->cur = 0;
+  b->flag_cur = 0;
+  b->flag_clean[0] = b->flag_clean[1] = true;
+  b->steps = 0;
+  uint8_t* P = static_cast<uint8_t*>(pool);
+  uint8_t* S = static_cast<uint8_t*>(scratch);
+  b->dev = reinterpret_cast<ColumnDev*>(S + L.table);
+  b->bubble_col = reinterpret_cast<int32_t*>(S + L.bcol);
+  b->partials = reinterpret_cast<double*>(S + L.partials);
+  b->result = reinterpret_cast<double*>(S + L.result);
+  b->status = reinterpret_cast<int32_t*>(S + L.status);
+  b->nred = kRedBlocks;
+  b->host.resize(ncols);
+  std::vector<int32_t> bcol(L.nb_total > 0 ? L.nb_total : 1, 0);
+  hipError_t e = launch_fill(pool, L.pool, b->stream);
+  if (e == hipSuccess) e = launch_fill(scratch, L.scratch, b->stream);
+  for (int c = 0; c < ncols && e == hipSuccess; ++c) {
+    const lbm_column& k = cols[c];
+    ColumnDev& D = b->host[c];
+    memset(&D, 0, sizeof(D));
+    D.G.nx = k.nx;
+    D.G.ny = k.ny;
+    D.G.nz = k.nz;
+    D.G.N = (uint32_t)k.nx * k.ny * k.nz;
+    D.G.plane = (uint32_t)k.nx * k.ny;
+    for (int f = 0; f < 6; ++f) {
+      D.G.bc[f] = k.bc[f];
+      if (k.bc[f] != LBM_BC_BOUNCE_BACK) b->general = true;
+    }
+    D.G.tnx = (int)div_up(k.nx, kTile);
+    D.G.tny = (int)div_up(k.ny, kTile);
+    D.omega = k.omega;
+    D.nu = (1.0 / k.omega - 0.5) / 3.0;  // eq. (9), dx = dt_l = 1
+    D.pops[0] = P + L.pops0[c];
+    D.pops[1] = P + L.pops1[c];
+    D.F = P + L.force[c];
+    D.U = P + L.vel[c];
+    D.tiles[0] = S + L.tiles0[c];
+    D.tiles[1] = S + L.tiles1[c];
+    D.item_cells = default_item_cells(k);
+    D.bubble_begin = k.bubble_begin;
+    D.nb = k.nb;
+    for (int i = 0; i < k.nb; ++i) bcol[k.bubble_begin + i] = c;
+  }
+  if (e == hipSuccess) {
+    assign_items(b);
+    e = upload_table(b);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->bubble_col, bcol.data(), bcol.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    delete b;
+    return LBM_EDEVICE;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_items(lbm_batch* b, const int32_t* item_cells) {
+  if (!b || !item_cells) return LBM_EINVAL;
+  for (int c = 0; c < b->ncols; ++c)
+    if (item_cells[c] < 256 || item_cells[c] > (1 << 16) || item_cells[c] % 256) return LBM_EINVAL;
+  for (int c = 0; c < b->ncols; ++c) b->host[c].item_cells = (uint32_t)item_cells[c];
+  assign_items(b);
+  b->graph.reset();
+  return to_status(upload_table(b));
+}
+
+lbm_status lbm_batch_get_items(lbm_batch* b, int32_t* item_cells) {
+  if (!b || !item_cells) return LBM_EINVAL;
+  for (int c = 0; c < b->ncols; ++c) item_cells[c] = (int32_t)b->host[c].item_cells;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, const bubble_params* p, const bubble_soa* s, int32_t nb,
+                          int32_t nsteps) {
+  if (!b || !p || !s || nb != b->nb_total || nsteps < 0) return LBM_EINVAL;
+  if (nb > 0 && (b->flags & LBM_FLAG_STATIC_FORCE)) return LBM_EINVAL;
+  if (p->n_sub < 1 || p->reserved != 0 || !(p->kernel_factor > 0.0) || !(p->sigma > 0.0))
+    return LBM_EINVAL;
+  if (nb > 0 && (!s->x || !s->y || !s->z || !s->ux || !s->uy || !s->uz || !s->d || !s->ulx ||
+                 !s->uly || !s->ulz || !s->state || !s->work))
+    return LBM_EINVAL;
+  for (int32_t i = 0; i < nsteps; ++i) {
+    const hipError_t e = batch_method_step(b, p, s, nb);
+    if (e != hipSuccess) return LBM_EDEVICE;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_run(lbm_batch* b, const bubble_params* p, const bubble_soa* s, int32_t nb,
+                         int32_t nsteps, int32_t graph_steps) {
+  if (!b || !p || !s || nb != b->nb_total || nsteps < 0) return LBM_EINVAL;
+  if (graph_steps < 0 || graph_steps % 2) return LBM_EINVAL;
+  if (graph_steps == 0 || nsteps < graph_steps || !b->stream)
+    return lbm_batch_step(b, p, s, nb, nsteps);
+  // validate once through the eager entry point's checks
+  const lbm_status st = lbm_batch_step(b, p, s, nb, 0);
+  if (st != LBM_OK) return st;
+  auto enqueue = [&](int n) -> hipError_t {
+    for (int i = 0; i < n; ++i) {
+      const hipError_t e = batch_method_step(b, p, s, nb);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  const GraphKey key = GraphKey::of(p, s, nb, b->cur, b->flag_cur, graph_steps);
+  int32_t done = 0;
+  while (nsteps - done >= graph_steps) {
+    const int cur0 = b->cur, flag0 = b->flag_cur;
+    const bool clean0[2] = {b->flag_clean[0], b->flag_clean[1]};
+    const int64_t steps0 = b->steps;
+    bool captured = false;
+    hipError_t e = b->graph.ensure(key, b->stream, [&]() { return enqueue(graph_steps); }, &captured);
+    if (e != hipSuccess) return LBM_EDEVICE;
+    // capture only recorded the launches: rewind the host-side step state and replay
+    b->cur = cur0;
+    b->flag_cur = flag0;
+    b->flag_clean[0] = clean0[0];
+    b->flag_clean[1] = clean0[1];
+    b->steps = steps0;
+    e = b->graph.launch(b->stream);
+    if (e != hipSuccess) return LBM_EDEVICE;
+    for (int i = 0; i < graph_steps; ++i) {  // advance the host state as the steps did
+      const int m = b->flag_cur ^ 1;
+      b->flag_clean[m] = false;
+      b->flag_cur = m;
+      b->cur ^= 1;
+      b->flag_clean[b->flag_cur ^ 1] = true;
+      ++b->steps;
+    }
+    (void)captured;
+    done += graph_steps;
+  }
+  if (nsteps > done) return lbm_batch_step(b, p, s, nb, nsteps - done);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_populations(lbm_batch* b, int32_t col, void* out) {
+  if (!b || col < 0 || col >= b->ncols || !out) return LBM_EINVAL;
+  const ColumnDev* dc = b->dev + col;
+  const uint32_t N = b->host[col].G.N;
+  if (b->elem == 4) {
+    if (b->general)
+      hipLaunchKernelGGL((k_batch_populations<float, true>), dim3(div_up(N, 256)), dim3(256), 0,
+                         b->stream, dc, b->cur, static_cast<float*>(out));
+    else
+      hipLaunchKernelGGL((k_batch_populations<float, false>), dim3(div_up(N, 256)), dim3(256), 0,
+                         b->stream, dc, b->cur, static_cast<float*>(out));
+  } else {
+    if (b->general)
+      hipLaunchKernelGGL((k_batch_populations<double, true>), dim3(div_up(N, 256)), dim3(256), 0,
+                         b->stream, dc, b->cur, static_cast<double*>(out));
+    else
+      hipLaunchKernelGGL((k_batch_populations<double, false>), dim3(div_up(N, 256)), dim3(256), 0,
+                         b->stream, dc, b->cur, static_cast<double*>(out));
+  }
+  return to_status(hipGetLastError());
+}
+
+lbm_status lbm_batch_column(lbm_batch* b, int32_t col, void** state, void** force, void** vel) {
+  if (!b || col < 0 || col >= b->ncols) return LBM_EINVAL;
+  if (state) *state = b->host[col].pops[b->cur];
+  if (force) *force = b->host[col].F;
+  if (vel) *vel = b->host[col].U;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_check(lbm_batch* b) {
+  if (!b) return LBM_EINVAL;
+  int32_t st = 0;
+  if (hipMemcpyAsync(&st, b->status, sizeof(st), hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+    return LBM_EDEVICE;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EDEVICE;
+  if (st != 0) {
+    if (launch_fill(b->status, 256, b->stream) != hipSuccess) return LBM_EDEVICE;
+    return LBM_EINVAL;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_destroy(lbm_batch* b) {
+  delete b;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -31,11 +31,9 @@ constexpr int kBlockWaves = kBlock / 64;
 constexpr int W_UL = 0, W_WL = 3, W_X0 = 6, W_PSI = 9, W_VALID = 12;
 
 struct BubbleArgs {
-  Geom G;
   bubble_params P;
   bubble_soa S;
   int nb;
-  double nu;
   int32_t* status;
 };
 
@@ -153,14 +151,16 @@ __device__ __forceinline__ double block_sum(double v, double* s_red, int tid) {
 // ---------------------------------------------------------------------------------------------
 // Forward coupling: u_l = sum W U and w_l = sum W curl U over the window.
 // ---------------------------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_interp(const T* __restrict__ U, BubbleArgs A) {
+template <typename T, typename Geo>
+__global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   __shared__ double s_w[3][kSpan];
   __shared__ double s_dw[3][kSpan];
   __shared__ double s_red[kBlockWaves];
   const int b = bubble_of_block(A.nb);
   const int tid = threadIdx.x;
-  const Geom& G = A.G;
+  const ColumnView<T> col = geo.template view<T>(b);
+  const Geom& G = col.G;
+  const T* __restrict__ U = col.U;
   double* work = A.S.work + (size_t)b * kWork;
   if (A.S.state[b] == 0) {
     if (tid == 0) work[W_VALID] = 0.0;
@@ -281,10 +281,13 @@ __device__ __forceinline__ void drag_lift(const bubble_params& P, const BubbleCo
   for (int a = 0; a < 3; ++a) FL[a] = lpre * cr[a];
 }
 
-__global__ __launch_bounds__(64) void k_ode(BubbleArgs A) {
+template <typename Geo>
+__global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
   const int b = blockIdx.x * 64 + threadIdx.x;
   if (b >= A.nb) return;
-  const Geom& G = A.G;
+  const ColumnView<float> col = geo.template view<float>(b);
+  const Geom& G = col.G;
+  const double nu = col.nu;
   const bubble_params& P = A.P;
   double* work = A.S.work + (size_t)b * kWork;
   const int st = A.S.state[b];
@@ -306,14 +309,14 @@ __global__ __launch_bounds__(64) void k_ode(BubbleArgs A) {
     dul[1] = ul[1] - A.S.uly[b];
     dul[2] = ul[2] - A.S.ulz[b];
   }
-  const BubbleConst kc = bubble_constants(P, A.nu, d);
+  const BubbleConst kc = bubble_constants(P, nu, d);
   const double dt = 1.0 / P.n_sub;
   double ub[3] = {A.S.ux[b], A.S.uy[b], A.S.uz[b]};
   double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
   for (int k = 0; k < P.n_sub; ++k) {
     // (m_b + C_A rho_l V) du_b/dt = F_B + F_D + F_L + (1 + C_A) rho_l V D_t u_l
     double FD[3], FL[3];
-    drag_lift(P, kc, d, A.nu, ub, ul, wl, FD, FL);
+    drag_lift(P, kc, d, nu, ub, ul, wl, FD, FL);
     for (int a = 0; a < 3; ++a) {
       double f = FD[a] + FL[a] + kc.va * dul[a];
       if (a == 2) f += kc.fb;
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(64) void k_ode(BubbleArgs A) {
     }
   }
   double FD[3], FL[3];
-  drag_lift(P, kc, d, A.nu, ub, ul, wl, FD, FL);
+  drag_lift(P, kc, d, nu, ub, ul, wl, FD, FL);
   double psi[3];
   for (int a = 0; a < 3; ++a) psi[a] = -(FD[a] + FL[a]);
   A.S.x[b] = xn[0];
@@ -402,14 +405,16 @@ __device__ TileRanges tile_ranges(int vlo, int vhi, int ext, int tile, bool peri
   return t;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spread(T* __restrict__ F, uint8_t* __restrict__ tiles,
-                                                   BubbleArgs A) {
+template <typename T, typename Geo>
+__global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
   __shared__ double s_w[3][kSpan];
   __shared__ double s_dw[3][kSpan];
   const int b = bubble_of_block(A.nb);
   const int tid = threadIdx.x;
-  const Geom& G = A.G;
+  const ColumnView<T> col = geo.template view<T>(b);
+  const Geom& G = col.G;
+  T* __restrict__ F = col.F;
+  uint8_t* __restrict__ tiles = col.tiles;
   const double* work = A.S.work + (size_t)b * kWork;
   if (work[W_VALID] == 0.0) return;
   const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
@@ -466,15 +471,26 @@ __global__ __launch_bounds__(kBlock) void k_spread(T* __restrict__ F, uint8_t* _
       }
 }
 
+template <typename T, typename Geo>
+hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_t stream) {
+  const int nb = A.nb;
+  hipLaunchKernelGGL((k_interp<T, Geo>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_ode<Geo>), dim3(div_up(nb, 64)), dim3(64), 0, stream, geo, A);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_spread<T, Geo>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb) {
   BubbleArgs A;
-  A.G = c->geom;
   A.P = *p;
   A.S = *s;
   A.nb = nb;
-  A.nu = (1.0 / c->desc.omega - 0.5) / 3.0;  // eq. (9), dx = dt_l = 1
   A.status = c->status;
   // this step's mask: the one the last liquid step cleared (cleared here if no liquid step ran)
   const int m = c->flag_cur ^ 1;
@@ -485,24 +501,31 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
   c->flag_clean[m] = false;
   c->flag_cur = m;
   if (nb == 0) return hipSuccess;
-  if (c->elem == 4)
-    hipLaunchKernelGGL(k_interp<float>, dim3(nb), dim3(kBlock), 0, c->stream,
-                       static_cast<const float*>(c->vel), A);
-  else
-    hipLaunchKernelGGL(k_interp<double>, dim3(nb), dim3(kBlock), 0, c->stream,
-                       static_cast<const double*>(c->vel), A);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ode, dim3(div_up(nb, 64)), dim3(64), 0, c->stream, A);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (c->elem == 4)
-    hipLaunchKernelGGL(k_spread<float>, dim3(nb), dim3(kBlock), 0, c->stream,
-                       static_cast<float*>(c->force), c->tiles[m], A);
-  else
-    hipLaunchKernelGGL(k_spread<double>, dim3(nb), dim3(kBlock), 0, c->stream,
-                       static_cast<double*>(c->force), c->tiles[m], A);
-  return hipGetLastError();
+  OneColumn geo;
+  geo.G = c->geom;
+  geo.U = c->vel;
+  geo.F = c->force;
+  geo.tiles = c->tiles[m];
+  geo.nu = (1.0 / c->desc.omega - 0.5) / 3.0;  // eq. (9), dx = dt_l = 1
+  if (c->elem == 4) return launch_bubble_kernels<float>(geo, A, c->stream);
+  return launch_bubble_kernels<double>(geo, A, c->stream);
+}
+
+hipError_t launch_bubbles_batch(const ColumnDev* cols, const int32_t* bubble_col, int flag,
+                                size_t elem, const bubble_params* p, const bubble_soa* s,
+                                int32_t nb, int32_t* status, hipStream_t stream) {
+  if (nb == 0) return hipSuccess;
+  BubbleArgs A;
+  A.P = *p;
+  A.S = *s;
+  A.nb = nb;
+  A.status = status;
+  ManyColumns geo;
+  geo.cols = cols;
+  geo.bubble_col = bubble_col;
+  geo.flag = flag;
+  if (elem == 4) return launch_bubble_kernels<float>(geo, A, stream);
+  return launch_bubble_kernels<double>(geo, A, stream);
 }
 
 }  // namespace lbm

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "../../include/lbm.h"
+#include "graph.hpp"
 #include "lattice.hpp"
 
 struct lbm_ctx {
@@ -33,9 +34,61 @@ struct lbm_ctx {
   int64_t steps;
   int step_vec;      // cells per thread along x in the liquid step (1, 2, 4)
   uint32_t step_bx;  // threads per workgroup along x (the workgroup has 256 threads)
+  lbm::StepGraph graph;  // captured method steps (lbm_run)
 };
 
 namespace lbm {
+
+// Geometry and fields of the lattice a bubble lives in, as seen by the bubble kernels.
+template <typename T>
+struct ColumnView {
+  Geom G;
+  const T* U;
+  T* F;
+  uint8_t* tiles;
+  double nu;
+};
+
+// A single lattice (lbm_ctx).
+struct OneColumn {
+  Geom G;
+  void* U;
+  void* F;
+  uint8_t* tiles;
+  double nu;
+  template <typename T>
+  __device__ ColumnView<T> view(int) const {
+    return {G, static_cast<const T*>(U), static_cast<T*>(F), tiles, nu};
+  }
+};
+
+// One column of a batch, in device memory: geometry, relaxation rate, buffers, and its share of
+// the work items of the batched liquid step and of the bubble arrays.
+struct ColumnDev {
+  Geom G;
+  double omega, nu;
+  void* pops[2];
+  void* F;
+  void* U;
+  uint8_t* tiles[2];
+  uint32_t item_begin;  // first work item of this column
+  uint32_t items;       // work items of this column
+  uint32_t item_cells;  // cells per work item
+  int32_t bubble_begin, nb;
+  int32_t pad;
+};
+
+// Many columns: each bubble's column comes from a per-bubble index.
+struct ManyColumns {
+  const ColumnDev* cols;
+  const int32_t* bubble_col;
+  int flag;
+  template <typename T>
+  __device__ ColumnView<T> view(int b) const {
+    const ColumnDev& c = cols[bubble_col[b]];
+    return {c.G, static_cast<const T*>(c.U), static_cast<T*>(c.F), c.tiles[flag], c.nu};
+  }
+};
 
 constexpr uint32_t kTile = 8;
 constexpr uint32_t kRedBlocks = 1024;  // upper bound of moments reduction blocks
@@ -46,6 +99,9 @@ enum : int32_t { STATUS_STENCIL_TOO_LARGE = 1 };
 hipError_t launch_step(lbm_ctx* c);
 // bubbles.hip
 hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb);
+hipError_t launch_bubbles_batch(const ColumnDev* cols, const int32_t* bubble_col, int flag,
+                                size_t elem, const bubble_params* p, const bubble_soa* s,
+                                int32_t nb, int32_t* status, hipStream_t stream);
 // moments.hip
 hipError_t launch_moments(lbm_ctx* c, void* rho, void* u, bool sums);
 hipError_t launch_populations(lbm_ctx* c, void* out);

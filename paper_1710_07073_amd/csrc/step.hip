@@ -9,87 +9,10 @@
 // 8^3 tiles flagged by the bubble kernel, whose mask is a byte per tile.
 #include <utility>
 
-#include "internal.hpp"
+#include "collide.hpp"
 
 namespace lbm {
 namespace {
-
-template <bool GENERAL, typename T, int... Qs>
-__device__ __forceinline__ void pull_all(T* g, const T* __restrict__ src, const Geom& G,
-                                         uint32_t cell, const CellNbr& nb,
-                                         std::integer_sequence<int, Qs...>) {
-  ((g[Qs] = pull<Qs, GENERAL>(src, G, cell, nb)), ...);
-}
-
-template <typename T>
-__device__ __forceinline__ T recip(T v) {
-  return T(1) / v;
-}
-template <>
-__device__ __forceinline__ float recip<float>(float v) {
-  return __builtin_amdgcn_rcpf(v);
-}
-
-// BGK collision with the Guo force term, in place on the 19 shifted populations. Opposite
-// directions are handled as pairs: the equilibrium (6) and the force term (12) split into a part
-// even in c and a part odd in c. Returns the velocity of eq. (13).
-template <typename T, bool FORCED>
-__device__ __forceinline__ void collide(T* g, T Fx, T Fy, T Fz, T omega, T& ux, T& uy, T& uz) {
-  T drho = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-  for (int q = 0; q < 19; ++q) {
-    drho += g[q];
-    if (CX[q] > 0) jx += g[q];
-    if (CX[q] < 0) jx -= g[q];
-    if (CY[q] > 0) jy += g[q];
-    if (CY[q] < 0) jy -= g[q];
-    if (CZ[q] > 0) jz += g[q];
-    if (CZ[q] < 0) jz -= g[q];
-  }
-  const T rho = T(1) + drho;
-  const T inv = recip(rho);
-  if (FORCED) {
-    ux = (jx + T(0.5) * Fx) * inv;
-    uy = (jy + T(0.5) * Fy) * inv;
-    uz = (jz + T(0.5) * Fz) * inv;
-  } else {
-    ux = jx * inv;
-    uy = jy * inv;
-    uz = jz * inv;
-  }
-  const T usq = ux * ux + uy * uy + uz * uz;
-  const T om1 = T(1) - omega;
-  const T pre = T(1) - T(0.5) * omega;
-  const T uF = FORCED ? (ux * Fx + uy * Fy + uz * Fz) : T(0);
-  // rest particle
-  {
-    constexpr int q = 18;
-    const T geq = weight<T>(q) * (drho - rho * T(1.5) * usq);
-    T v = om1 * g[q] + omega * geq;
-    if (FORCED) v += pre * weight<T>(q) * (T(-3) * uF);
-    g[q] = v;
-  }
-#pragma unroll
-  for (int q = 0; q < 18; ++q) {
-    const int qb = opposite(q);
-    if (qb < q) continue;  // each pair once, from its lower index
-    const T cu = T(CX[q]) * ux + T(CY[q]) * uy + T(CZ[q]) * uz;
-    const T w = weight<T>(q);
-    const T sym = w * (drho + rho * (T(4.5) * cu * cu - T(1.5) * usq));
-    const T asym = w * rho * T(3) * cu;
-    T vp = om1 * g[q] + omega * (sym + asym);
-    T vm = om1 * g[qb] + omega * (sym - asym);
-    if (FORCED) {
-      const T cF = T(CX[q]) * Fx + T(CY[q]) * Fy + T(CZ[q]) * Fz;
-      const T ssym = pre * w * (T(9) * cu * cF - T(3) * uF);
-      const T sasym = pre * w * T(3) * cF;
-      vp += ssym + sasym;
-      vm += ssym - sasym;
-    }
-    g[q] = vp;
-    g[qb] = vm;
-  }
-}
 
 // VEC consecutive cells along x per thread (VEC = 1, 2 or 4; nx % VEC == 0). Interior threads
 // gather each population as one VEC-wide load: the source run is contiguous in x (shifted by

@@ -23,8 +23,11 @@ LBM_BUBBLE_WORK = 16
 # every symbol include/lbm.h declares
 EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch", "lbm_get_launch",
            "lbm_step", "bubbles_step",
-           "moments", "lbm_populations", "lbm_state_buffer", "lbm_check", "lbm_destroy",
-           "lbm_status_string")
+           "moments", "lbm_populations", "lbm_state_buffer", "lbm_check", "lbm_run", "lbm_destroy",
+           "lbm_status_string",
+           "lbm_batch_bytes_required", "lbm_batch_init", "lbm_batch_set_items", "lbm_batch_get_items",
+           "lbm_batch_step", "lbm_batch_run", "lbm_batch_populations", "lbm_batch_column",
+           "lbm_batch_check", "lbm_batch_destroy")
 
 
 class LbmDesc(ct.Structure):
@@ -43,6 +46,12 @@ class BubbleParams(ct.Structure):
 class BubbleSoA(ct.Structure):
     _fields_ = [(n, ct.c_void_p) for n in ("x", "y", "z", "ux", "uy", "uz", "d", "ulx", "uly", "ulz",
                                           "state", "psix", "psiy", "psiz", "work")]
+
+
+class LbmColumn(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32),
+                ("bubble_begin", ct.c_int32), ("nb", ct.c_int32), ("bc", ct.c_int32 * 6),
+                ("reserved", ct.c_int32), ("omega", ct.c_double)]
 
 
 class LbmError(RuntimeError):
@@ -75,7 +84,24 @@ def lib():
         L.lbm_populations.argtypes = [P, P]
         L.lbm_state_buffer.argtypes = [P, ct.POINTER(P)]
         L.lbm_check.argtypes = [P]
+        L.lbm_run.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32,
+                              ct.c_int32, ct.c_int32]
         L.lbm_destroy.argtypes = [P]
+        CP = ct.POINTER(LbmColumn)
+        L.lbm_batch_bytes_required.argtypes = [CP, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_size_t),
+                                               ct.POINTER(ct.c_size_t)]
+        L.lbm_batch_init.argtypes = [CP, ct.c_int32, ct.c_int32, ct.c_int32, P, P, P,
+                                     ct.POINTER(P)]
+        L.lbm_batch_set_items.argtypes = [P, ct.POINTER(ct.c_int32)]
+        L.lbm_batch_get_items.argtypes = [P, ct.POINTER(ct.c_int32)]
+        L.lbm_batch_step.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32,
+                                     ct.c_int32]
+        L.lbm_batch_run.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32,
+                                    ct.c_int32, ct.c_int32]
+        L.lbm_batch_populations.argtypes = [P, ct.c_int32, P]
+        L.lbm_batch_column.argtypes = [P, ct.c_int32, ct.POINTER(P), ct.POINTER(P), ct.POINTER(P)]
+        L.lbm_batch_check.argtypes = [P]
+        L.lbm_batch_destroy.argtypes = [P]
         L.lbm_status_string.argtypes = [ct.c_int]
         L.lbm_status_string.restype = ct.c_char_p
         for name in EXPORTS:
@@ -159,3 +185,77 @@ def lbm_check(ctx):
 def lbm_destroy(ctx):
     if ctx:
         lib().lbm_destroy(ctx)
+
+
+def lbm_run(ctx, params, soa, nb, nsteps, graph_steps=0):
+    _ok(lib().lbm_run(ctx, ct.byref(params), ct.byref(soa), int(nb), int(nsteps), int(graph_steps)),
+        "lbm_run")
+
+
+# ---- batched columns ----
+def make_columns(specs):
+    """specs: iterable of (shape, omega, bc, nb); bubble ranges are assigned consecutively."""
+    specs = list(specs)
+    arr = (LbmColumn * len(specs))()
+    begin = 0
+    for i, (shape, omega, bc, nb) in enumerate(specs):
+        nx, ny, nz = shape
+        arr[i] = LbmColumn(int(nx), int(ny), int(nz), begin, int(nb),
+                           (ct.c_int32 * 6)(*[int(b) for b in bc]), 0, float(omega))
+        begin += int(nb)
+    return arr
+
+
+def lbm_batch_bytes_required(cols, precision):
+    a, b = ct.c_size_t(), ct.c_size_t()
+    _ok(lib().lbm_batch_bytes_required(cols, len(cols), int(precision), ct.byref(a), ct.byref(b)),
+        "lbm_batch_bytes_required")
+    return a.value, b.value
+
+
+def lbm_batch_init(cols, precision, flags, pool, scratch, stream):
+    h = ct.c_void_p()
+    _ok(lib().lbm_batch_init(cols, len(cols), int(precision), int(flags), pool, scratch, stream,
+                             ct.byref(h)), "lbm_batch_init")
+    return h
+
+
+def lbm_batch_set_items(batch, item_cells):
+    arr = (ct.c_int32 * len(item_cells))(*[int(v) for v in item_cells])
+    _ok(lib().lbm_batch_set_items(batch, arr), "lbm_batch_set_items")
+
+
+def lbm_batch_get_items(batch, ncols):
+    arr = (ct.c_int32 * ncols)()
+    _ok(lib().lbm_batch_get_items(batch, arr), "lbm_batch_get_items")
+    return list(arr)
+
+
+def lbm_batch_step(batch, params, soa, nb, nsteps=1):
+    _ok(lib().lbm_batch_step(batch, ct.byref(params), ct.byref(soa), int(nb), int(nsteps)),
+        "lbm_batch_step")
+
+
+def lbm_batch_run(batch, params, soa, nb, nsteps, graph_steps=0):
+    _ok(lib().lbm_batch_run(batch, ct.byref(params), ct.byref(soa), int(nb), int(nsteps),
+                            int(graph_steps)), "lbm_batch_run")
+
+
+def lbm_batch_populations(batch, col, out_ptr):
+    _ok(lib().lbm_batch_populations(batch, int(col), out_ptr), "lbm_batch_populations")
+
+
+def lbm_batch_column(batch, col):
+    a, b, c = ct.c_void_p(), ct.c_void_p(), ct.c_void_p()
+    _ok(lib().lbm_batch_column(batch, int(col), ct.byref(a), ct.byref(b), ct.byref(c)),
+        "lbm_batch_column")
+    return a.value, b.value, c.value
+
+
+def lbm_batch_check(batch):
+    _ok(lib().lbm_batch_check(batch), "lbm_batch_check")
+
+
+def lbm_batch_destroy(batch):
+    if batch:
+        lib().lbm_batch_destroy(batch)

@@ -113,6 +113,14 @@ class Simulation:
                 L.bubbles_step(self.ctx, self.params, self.bubbles.soa, self.bubbles.nb)
             L.lbm_step(self.ctx, 1)
 
+    def run(self, nsteps, graph_steps=0):
+        """nsteps method steps through lbm_run (graph replay when graph_steps > 0)."""
+        if self.bubbles is not None and self.bubbles.nb > 0:
+            L.lbm_run(self.ctx, self.params, self.bubbles.soa, self.bubbles.nb, nsteps, graph_steps)
+        else:
+            empty = Bubbles(np.zeros((3, 0)), np.zeros(0), device=self.device)
+            L.lbm_run(self.ctx, self.params or bubble_params(), empty.soa, 0, nsteps, graph_steps)
+
     def liquid_steps(self, nsteps=1):
         L.lbm_step(self.ctx, nsteps)
 
@@ -133,3 +141,59 @@ class Simulation:
 
     def check(self):
         L.lbm_check(self.ctx)
+
+
+class Batch:
+    """Many columns (each a Workload-like spec) stepped together through the batched C ABI."""
+
+    def __init__(self, columns, params, precision="f32", flags=0, device="cuda", stream=None):
+        """columns: list of dicts with shape, omega, bc, pos (3, nb), d (nb)."""
+        self.columns = columns
+        self.precision = L.LBM_FP64_SHIFTED if precision in ("f64", "fp64") else L.LBM_FP32_SHIFTED
+        self.dtype = torch.float64 if self.precision == L.LBM_FP64_SHIFTED else torch.float32
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.cols = L.make_columns([(c["shape"], c["omega"], c["bc"], np.asarray(c["d"]).size)
+                                    for c in columns])
+        pool_b, scratch_b = L.lbm_batch_bytes_required(self.cols, self.precision)
+        self.pool = torch.empty(pool_b, dtype=torch.uint8, device=self.device)
+        self.scratch = torch.empty(scratch_b, dtype=torch.uint8, device=self.device)
+        self.handle = L.lbm_batch_init(self.cols, self.precision, flags, _ptr(self.pool),
+                                       _ptr(self.scratch), ct.c_void_p(self.stream.cuda_stream))
+        pos = np.concatenate([np.asarray(c["pos"], np.float64).reshape(3, -1) for c in columns], axis=1)
+        d = np.concatenate([np.asarray(c["d"], np.float64).reshape(-1) for c in columns])
+        self.bubbles = Bubbles(pos, d, device=self.device)
+        self.params = params
+        self.ncols = len(columns)
+        self.cells = sum(int(np.prod(c["shape"])) for c in columns)
+
+    def close(self):
+        if self.handle:
+            L.lbm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, nsteps=1):
+        L.lbm_batch_step(self.handle, self.params, self.bubbles.soa, self.bubbles.nb, nsteps)
+
+    def run(self, nsteps, graph_steps=0):
+        L.lbm_batch_run(self.handle, self.params, self.bubbles.soa, self.bubbles.nb, nsteps,
+                        graph_steps)
+
+    def populations(self, col):
+        nx, ny, nz = self.columns[col]["shape"]
+        out = torch.empty((19, nz, ny, nx), dtype=self.dtype, device=self.device)
+        L.lbm_batch_populations(self.handle, col, _ptr(out))
+        return out
+
+    def bubble_range(self, col):
+        c = self.cols[col]
+        return c.bubble_begin, c.bubble_begin + c.nb
+
+    def check(self):
+        L.lbm_batch_check(self.handle)

@@ -1,0 +1,174 @@
+"""Batched columns (many independent lattices of uneven size and relaxation rate stepped by one
+launch per kernel, repeated steps replayed from a HIP graph): every column must reproduce its own
+single-lattice run, the oracle, and graph replays must reproduce eager launches."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_common import rel_l2
+from paper_1710_07073_amd import lbm as L
+from paper_1710_07073_amd import sim as S
+
+BB, FS, PER = O.BC_BOUNCE_BACK, O.BC_FREE_SLIP, O.BC_PERIODIC
+TOL = {"f64": 1e-12, "f32": 2e-5}
+
+
+def _columns(seed=21, nb_max=4):
+    rng = np.random.default_rng(seed)
+    specs = [((24, 30, 50), 0.7, (BB,) * 6), ((37, 25, 61), 1.9, (BB,) * 6),
+             ((64, 40, 90), 1.3, (BB,) * 6), ((33, 33, 70), 1.1, (BB, BB, BB, BB, BB, FS)),
+             ((20, 28, 44), 1.6, (PER, PER, PER, PER, BB, BB))]
+    cols = []
+    for shape, omega, bc in specs:
+        nb = int(rng.integers(1, nb_max + 1))
+        d = rng.uniform(2.0, 4.0, nb)
+        n = 1.5 * d
+        nx, ny, nz = shape
+        pos = np.stack([rng.uniform(n, nx - 1 - n), rng.uniform(n, ny - 1 - n),
+                        rng.uniform(n, 0.4 * nz)])
+        cols.append(dict(shape=shape, omega=omega, bc=bc, pos=pos, d=d))
+    return cols
+
+
+def _params():
+    return W.params(g=1e-4, sigma=W.sigma_for(1e-4, 3.0))
+
+
+def _single(col, prec, steps):
+    sim = S.Simulation(col["shape"], col["omega"], precision=prec, bc=col["bc"])
+    sim.add_bubbles(col["pos"], col["d"], S.bubble_params(**_params()))
+    sim.step(steps)
+    out = sim.populations().double().cpu().numpy(), sim.bubbles.positions()
+    sim.close()
+    return out
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_columns_match_single_lattice_runs(prec):
+    cols = _columns()
+    batch = S.Batch(cols, S.bubble_params(**_params()), precision=prec)
+    steps = 40
+    batch.step(steps)
+    pos = batch.bubbles.positions()
+    for c, col in enumerate(cols):
+        g_ref, pos_ref = _single(col, prec, steps)
+        g = batch.populations(c).double().cpu().numpy()
+        assert rel_l2(g, g_ref) <= TOL[prec], c
+        b0, b1 = batch.bubble_range(c)
+        assert np.abs(pos[:, b0:b1] - pos_ref).max() <= 1e-4
+    batch.check()
+    batch.close()
+
+
+@pytest.mark.gpu
+def test_batch_columns_match_oracle():
+    cols = _columns(seed=22, nb_max=2)[:3]
+    batch = S.Batch(cols, S.bubble_params(**_params()), precision="f64")
+    steps = 30
+    batch.step(steps)
+    pos = batch.bubbles.positions()
+    P = O.bubble_params(**_params())
+    for c, col in enumerate(cols):
+        lat = O.Lattice(*col["shape"], col["omega"], col["bc"])
+        bub = O.Bubbles(pos=col["pos"].copy(), d=col["d"].copy())
+        O.run(lat, P, bub, steps)
+        assert rel_l2(batch.populations(c).cpu().numpy(), lat.g) <= 1e-12
+        b0, b1 = batch.bubble_range(c)
+        assert np.abs(pos[:, b0:b1] - bub.pos).max() <= 1e-10
+    batch.close()
+
+
+@pytest.mark.gpu
+def test_batch_item_sizes_are_bit_identical():
+    cols = [dict(c, pos=c["pos"][:, :1], d=c["d"][:1]) for c in _columns(seed=23)]
+    ref = None
+    for items in (256, 1024, 4096):
+        batch = S.Batch(cols, S.bubble_params(**_params()), precision="f32")
+        L.lbm_batch_set_items(batch.handle, [items] * len(cols))
+        batch.step(12)
+        out = [batch.populations(c).cpu().numpy() for c in range(len(cols))]
+        batch.close()
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(out, ref):
+                assert np.array_equal(a, b)
+
+
+@pytest.mark.gpu
+def test_batch_graph_replays_match_eager_launches():
+    """Each graph replay is checked against eager launches, with eager work and synchronisation
+    between the replays."""
+    cols = [dict(c, pos=c["pos"][:, :1], d=c["d"][:1]) for c in _columns(seed=24)]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        eager = S.Batch(cols, S.bubble_params(**_params()), precision="f64", stream=stream)
+        graph = S.Batch(cols, S.bubble_params(**_params()), precision="f64", stream=stream)
+        for rep in range(4):
+            eager.step(6)
+            graph.run(6, graph_steps=6)
+            stream.synchronize()
+            for c in range(len(cols)):
+                a = graph.populations(c).cpu().numpy()
+                b = eager.populations(c).cpu().numpy()
+                assert np.array_equal(a, b), (rep, c)
+            assert np.array_equal(graph.bubbles.positions(), eager.bubbles.positions())
+            _ = torch.ones(1000, device="cuda", dtype=torch.float64).sum().item()  # eager work
+        eager.close()
+        graph.close()
+
+
+@pytest.mark.gpu
+def test_single_lattice_graph_run_matches_eager():
+    w = W.Workload("graph", (40, 36, 64), 1.3, (BB,) * 6, np.array([[19.2], [17.7], [9.0]]),
+                   np.array([3.0]), _params(), 0, "f64")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sims = []
+        for _ in range(2):
+            sim = S.Simulation(w.shape, w.omega, precision="f64", stream=stream)
+            sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+            sims.append(sim)
+        for rep in range(3):
+            sims[0].step(10)
+            sims[1].run(10, graph_steps=4)  # two replays and two eager steps
+            stream.synchronize()
+            assert np.array_equal(sims[0].populations().cpu().numpy(),
+                                  sims[1].populations().cpu().numpy()), rep
+            assert np.array_equal(sims[0].bubbles.positions(), sims[1].bubbles.positions())
+        for s in sims:
+            s.close()
+
+
+@pytest.mark.gpu
+def test_batched_sweep_full_size():
+    """The 64-column sweep (cross-sections 24-96, heights 2-4 times the width, omega from 0.6 to
+    1.9, 1-8 bubbles each) in the benchmark's launch configuration (graph replays): a sample of
+    columns against their single-lattice runs, and mass conservation of every column."""
+    ws = W.batched(steps=4)
+    cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d) for w in ws]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
+        batch.run(4, graph_steps=2)
+        stream.synchronize()
+        batch.check()
+        sizes = [np.prod(w.shape) for w in ws]
+        sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17})
+        pos = batch.bubbles.positions()
+        for c in sample:
+            sim = S.Simulation(ws[c].shape, ws[c].omega, precision="f32", bc=ws[c].bc, stream=stream)
+            sim.add_bubbles(ws[c].pos, ws[c].d, S.bubble_params(**ws[c].params))
+            sim.step(4)
+            g_ref = sim.populations().double().cpu().numpy()
+            b0, b1 = batch.bubble_range(c)
+            assert np.abs(pos[:, b0:b1] - sim.bubbles.positions()).max() <= 1e-4
+            sim.close()
+            assert rel_l2(batch.populations(c).double().cpu().numpy(), g_ref) <= 2e-5
+        for c, w in enumerate(ws):
+            mass = batch.populations(c).double().sum().item()  # sum of g = sum rho - N
+            assert abs(mass) < 1e-6 * w.cells
+        batch.close()
