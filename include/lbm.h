@@ -178,6 +178,62 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* params, const bubble_soa* 
 lbm_status lbm_destroy(lbm_ctx* ctx);
 
 /* ---------------------------------------------------------------------------------------------
+ * Adjoint (reverse-mode derivative) of one method step, for gradients of a loss on bubble
+ * trajectories with respect to drag_scale, lift_scale and omega. The caller keeps the forward
+ * data of the step (a checkpoint-and-recompute schedule) and walks the steps backwards.
+ * grad (device, 4 doubles, accumulated): [0] dL/domega through the collision, [1] dL/d drag_scale,
+ * [2] dL/d lift_scale, [3] dL/dnu through the bubble closures (nu = (1/omega - 1/2)/3, eq. (9)).
+ * ------------------------------------------------------------------------------------------- */
+
+/* Doubles per bubble in a step record: x[3] u_b[3] u_l,prev[3] state u_l[3] w_l[3] psi[3] valid d,
+ * taken before the step (x, u_b, u_l,prev, state, d) and after its bubble half (u_l, w_l, psi,
+ * valid = the first LBM_BUBBLE_WORK slots 0-5, 9-12 of bubble_soa.work). */
+#define LBM_BUBBLE_RECORD 24
+/* Doubles per bubble of adjoint state: dL/dx[3], dL/du_b[3], dL/du_l,prev[3], unused[3]. */
+#define LBM_BUBBLE_ADJ 12
+
+/* Adjoint of the liquid step (eq. (12)-(16), Sec. 3.3). state: the post-collision buffer before the
+ * step (19 x N); force: the force field of the step (3 x N); lam_next: dL/d(state after the step);
+ * lam_prev (out, every element written): dL/d(state before); lam_u (in/out): dL/dU of the step's
+ * velocity field, read and cleared; lam_f (out): dL/dF. Device buffers of the lattice type. */
+lbm_status lbm_adjoint_liquid(lbm_ctx* ctx, const void* state, const void* force,
+                              const void* lam_next, void* lam_prev, void* lam_u, void* lam_f,
+                              double* grad);
+
+/* Adjoint of the bubble half (eq. (18)-(21), Table 1, eq. (1)-(4)). record: nb x
+ * LBM_BUBBLE_RECORD doubles of the step; vel_prev: velocity field the step interpolated;
+ * lam_f: dL/dF from lbm_adjoint_liquid; lam_u (out, accumulated): dL/d(vel_prev); lam: nb x
+ * LBM_BUBBLE_ADJ adjoint bubble state, dL/d(state after the step) in, dL/d(state before) out;
+ * scratch: nb x LBM_BUBBLE_WORK doubles. n_sub may be at most 32. */
+lbm_status lbm_adjoint_bubbles(lbm_ctx* ctx, const bubble_params* params, const double* record,
+                               const void* vel_prev, const void* lam_f, void* lam_u, double* lam,
+                               double* scratch, int32_t nb, double* grad);
+
+/* Host evaluation of the arithmetic the adjoint kernels run (double precision), for checks:
+ * one cell's collision (eq. (13)-(15)) and, if lam/lam_u/mu/lam_f/domega are given, its
+ * transposed Jacobian; */
+lbm_status lbm_host_collide(const double* p, const double* F, double omega, const double* lam,
+                            const double* lam_u, double* out, double* u, double* mu, double* lam_f,
+                            double* domega);
+/* the weights of one axis (LBM_MAX_STENCIL + 2 entries from cell lo - 1), their curl
+ * counterparts and both derivatives in the bubble coordinate; s_lo, s_hi: -1 bounce-back, +1
+ * free slip; */
+lbm_status lbm_host_axis_weights(double x, double n, int32_t ext, int32_t periodic, double s_lo,
+                                 double s_hi, int32_t* lo, double* w, double* dw, double* wx,
+                                 double* dwx);
+/* one step of the bubble ODE, and its reverse sweep: out = dL/d(x[3], u_b[3], u_l[3], w_l[3],
+ * D_t u_l[3]), dL/d drag_scale, dL/d lift_scale, dL/dnu. */
+lbm_status lbm_host_bubble_ode(const bubble_params* params, double nu, double d, const double* x0,
+                               const double* ub0, const double* ul, const double* wl,
+                               const double* dul, const int32_t* ext, const int32_t* periodic,
+                               double* x, double* ub, double* psi);
+lbm_status lbm_host_bubble_ode_adjoint(const bubble_params* params, double nu, double d,
+                                       const double* x0, const double* ub0, const double* ul,
+                                       const double* wl, const double* dul, const int32_t* ext,
+                                       const int32_t* periodic, const double* lx,
+                                       const double* lub, const double* lpsi, double* out);
+
+/* ---------------------------------------------------------------------------------------------
  * Batched columns: many independent lattices (uneven extents, each with its own omega and faces)
  * stepped together, as in the paper's grid-independence and stability sweeps (Sec. 4.2, 4.3).
  * All columns share the precision and the bubble constants; column c owns bubbles

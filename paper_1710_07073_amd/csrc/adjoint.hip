@@ -1,0 +1,432 @@
+// Adjoint (reverse-mode derivative) of one method step of Algorithm 1, for gradients of a loss on
+// bubble trajectories with respect to the drag scale, the lift scale and omega.
+//
+// Liquid step, k_adj_liquid: with lam = dL/d(post-collision buffer after the step), each cell
+// rebuilds its pre-collision populations p = pull(h) and force, applies the transposed Jacobian
+// of the collision (collide_cell_adjoint) and scatters the result to the sources of its pull.
+// Streaming with the face rules is a permutation of (cell, population), so the scatter writes
+// every element of the output exactly once.
+//
+// Bubble half, three kernels mirroring the forward ones:
+//   k_adj_gather   dL/dpsi = sum_j W_j dL/dF(j), and the position term of the spreading weights;
+//   k_adj_ode      reverse sweep of the sub-stepped ODE (ode_adjoint), one lane per bubble;
+//   k_adj_scatter  transpose of the interpolation: dL/dU(j) += W_j dL/du_l + curl weights . dL/dw_l
+//                  (atomic adds), and the position term of the interpolation weights.
+#include <utility>
+
+#include "adjoint_math.hpp"
+#include "collide.hpp"
+
+namespace lbm {
+namespace {
+
+constexpr int kB = 256;  // threads per bubble workgroup
+constexpr int kBW = kB / 64;
+// record of one bubble at the start of a step (doubles)
+constexpr int R_X = 0, R_UB = 3, R_ULP = 6, R_STATE = 9, R_UL = 10, R_WL = 13, R_PSI = 16,
+              R_VALID = 19, R_D = 20, R_SIZE = LBM_BUBBLE_RECORD;
+// adjoint bubble state (doubles)
+constexpr int A_X = 0, A_UB = 3, A_ULP = 6, A_SIZE = LBM_BUBBLE_ADJ;
+// adjoint scratch between the bubble kernels (doubles)
+constexpr int S_LPSI = 0, S_GX = 3, S_LUL = 6, S_LWL = 9, S_GXODE = 12, S_FLAG = 15;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double bsum(double v, double* s_red) {
+  v = wsum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kBW; ++w) t += s_red[w];
+  return t;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+template <bool GENERAL, typename T, int... Qs>
+__device__ __forceinline__ void push_all(T* __restrict__ dst, const T* mu, const Geom& G,
+                                         uint32_t cell, const CellNbr& nb,
+                                         std::integer_sequence<int, Qs...>) {
+  ((dst[pull_index<Qs, GENERAL>(G, cell, nb)] = mu[Qs]), ...);
+}
+
+template <typename T, bool GENERAL>
+__global__ __launch_bounds__(256) void k_adj_liquid(const T* __restrict__ h, const T* __restrict__ F,
+                                                    const T* __restrict__ lam_next,
+                                                    T* __restrict__ lam_prev, T* __restrict__ lam_u,
+                                                    T* __restrict__ lam_f, Geom G, T omega,
+                                                    double* __restrict__ grad) {
+  __shared__ double s_red[4];
+  const uint32_t cell = blockIdx.x * 256 + threadIdx.x;
+  double dom = 0.0;
+  if (cell < G.N) {
+    const uint32_t x = cell % G.nx, y = (cell / G.nx) % G.ny, z = cell / G.plane;
+    const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
+    T p[19], lam[19], mu[19];
+    pull_all<GENERAL>(p, h, G, cell, nb, std::make_integer_sequence<int, 19>{});
+#pragma unroll
+    for (int q = 0; q < 19; ++q) lam[q] = lam_next[(size_t)q * G.N + cell];
+    const T f[3] = {F[cell], F[G.N + cell], F[2 * (size_t)G.N + cell]};
+    const T lu[3] = {lam_u[cell], lam_u[G.N + cell], lam_u[2 * (size_t)G.N + cell]};
+    T lf[3];
+    collide_cell_adjoint<T>(p, f, omega, lam, lu, mu, lf, &dom);
+    push_all<GENERAL>(lam_prev, mu, G, cell, nb, std::make_integer_sequence<int, 19>{});
+    lam_f[cell] = lf[0];
+    lam_f[G.N + cell] = lf[1];
+    lam_f[2 * (size_t)G.N + cell] = lf[2];
+    // consumed: the next (earlier) step accumulates its own velocity adjoint here
+    lam_u[cell] = T(0);
+    lam_u[G.N + cell] = T(0);
+    lam_u[2 * (size_t)G.N + cell] = T(0);
+  }
+  dom = wsum(dom);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = dom;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&grad[0], s_red[0] + s_red[1] + s_red[2] + s_red[3]);
+}
+
+// Weights and derivatives of the three axes into LDS (one thread per axis).
+__device__ bool adj_weights(const Geom& G, const double* xb, double n, double (*w)[kAdjSpan],
+                            double (*dw)[kAdjSpan], double (*wx)[kAdjSpan], double (*dwx)[kAdjSpan],
+                            AxisW* win, int* s_ok) {
+  const int ext[3] = {G.nx, G.ny, G.nz};
+  if (threadIdx.x == 0) *s_ok = 1;
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int a = threadIdx.x;
+    const bool per = G.bc[2 * a] == BC_PER;
+    const double s_lo = G.bc[2 * a] == BC_FS ? 1.0 : -1.0;
+    const double s_hi = G.bc[2 * a + 1] == BC_FS ? 1.0 : -1.0;
+    if (!axis_weights_dx(xb[a], n, ext[a], per, s_lo, s_hi, win[a], w[a], dw[a], wx[a], dwx[a]))
+      *s_ok = 0;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kB) void k_adj_gather(const T* __restrict__ lam_f,
+                                                   const double* __restrict__ rec,
+                                                   double* __restrict__ scr, bubble_params P,
+                                                   Geom G, int nb) {
+  __shared__ double w[3][kAdjSpan], dw[3][kAdjSpan], wx[3][kAdjSpan], dwx[3][kAdjSpan];
+  __shared__ AxisW win[3];
+  __shared__ double s_red[kBW];
+  __shared__ int s_ok;
+  const int b = (int)xcd_remap(blockIdx.x, nb);
+  const double* r = rec + (size_t)b * R_SIZE;
+  double* s = scr + (size_t)b * LBM_BUBBLE_WORK;
+  if (r[R_VALID] == 0.0) {
+    if (threadIdx.x < 6) s[S_LPSI + threadIdx.x] = 0.0;
+    return;
+  }
+  const double xb[3] = {r[R_X], r[R_X + 1], r[R_X + 2]};
+  const double psi[3] = {r[R_PSI], r[R_PSI + 1], r[R_PSI + 2]};
+  if (!adj_weights(G, xb, P.kernel_factor * r[R_D], w, dw, wx, dwx, win, &s_ok)) {
+    if (threadIdx.x < 6) s[S_LPSI + threadIdx.x] = 0.0;
+    return;
+  }
+  const int Kx = win[0].chi - win[0].clo + 1, Ky = win[1].chi - win[1].clo + 1,
+            Kz = win[2].chi - win[2].clo + 1;
+  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int f = threadIdx.x; f < Kx * Ky * Kz; f += kB) {
+    const int i = f % Kx, rr = f / Kx, j = rr % Ky, k = rr / Ky;
+    const int vx = win[0].clo + i, vy = win[1].clo + j, vz = win[2].clo + k;
+    const int ix = vx - win[0].lo + 1, iy = vy - win[1].lo + 1, iz = vz - win[2].lo + 1;
+    const int x = px ? wrapi(vx, G.nx) : vx, y = py ? wrapi(vy, G.ny) : vy,
+              z = pz ? wrapi(vz, G.nz) : vz;
+    const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
+    const double l0 = (double)lam_f[c], l1 = (double)lam_f[G.N + c],
+                 l2 = (double)lam_f[2 * (size_t)G.N + c];
+    const double a = w[0][ix], bb = w[1][iy], cc = w[2][iz];
+    const double W = a * bb * cc;
+    const double pl = psi[0] * l0 + psi[1] * l1 + psi[2] * l2;
+    acc[0] += W * l0;
+    acc[1] += W * l1;
+    acc[2] += W * l2;
+    acc[3] += wx[0][ix] * bb * cc * pl;
+    acc[4] += a * wx[1][iy] * cc * pl;
+    acc[5] += a * bb * wx[2][iz] * pl;
+  }
+  for (int m = 0; m < 6; ++m) acc[m] = bsum(acc[m], s_red);
+  if (threadIdx.x == 0)
+    for (int m = 0; m < 6; ++m) s[S_LPSI + m] = acc[m];
+}
+
+__global__ __launch_bounds__(64) void k_adj_ode(const double* __restrict__ rec,
+                                                double* __restrict__ lam, double* __restrict__ scr,
+                                                bubble_params P, Geom G, double nu, int nb,
+                                                double* __restrict__ grad) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  double dsD = 0.0, dsL = 0.0, dnu = 0.0;
+  if (b < nb) {
+    const double* r = rec + (size_t)b * R_SIZE;
+    double* l = lam + (size_t)b * A_SIZE;
+    double* s = scr + (size_t)b * LBM_BUBBLE_WORK;
+    const int st = (int)r[R_STATE];
+    if (st == 0 || r[R_VALID] == 0.0) {
+      s[S_FLAG] = 0.0;  // frozen bubble: its adjoint state passes through unchanged
+    } else {
+      const double d = r[R_D];
+      OdeBounds Bd;
+      const int ext[3] = {G.nx, G.ny, G.nz};
+      for (int a = 0; a < 3; ++a) {
+        Bd.hi[a] = ext[a] - 1.0;
+        Bd.len[a] = G.bc[2 * a] == BC_PER ? (double)ext[a] : 0.0;
+      }
+      Bd.top = G.bc[4] != BC_PER;
+      const double* ul = r + R_UL;
+      const double* ulp = r + R_ULP;
+      double dul[3] = {0.0, 0.0, 0.0};
+      if (st == 2)
+        for (int a = 0; a < 3; ++a) dul[a] = ul[a] - ulp[a];
+      OdeAdj g;
+      ode_adjoint(P, nu, d, r + R_X, r + R_UB, ul, r + R_WL, dul, Bd, l + A_X, l + A_UB, s + S_LPSI, g);
+      for (int a = 0; a < 3; ++a) {
+        // u_l enters the drag/lift, D_t u_l = u_l - u_l,prev (state 2) and u_l,prev of the next step
+        s[S_LUL + a] = g.ul[a] + (st == 2 ? g.dul[a] : 0.0) + l[A_ULP + a];
+        s[S_LWL + a] = g.wl[a];
+        s[S_GXODE + a] = g.x[a];
+        l[A_UB + a] = g.ub[a];
+        l[A_ULP + a] = st == 2 ? -g.dul[a] : 0.0;
+      }
+      s[S_FLAG] = 1.0;
+      dsD = g.dsD;
+      dsL = g.dsL;
+      dnu = g.dnu;
+    }
+  }
+  dsD = wsum(dsD);
+  dsL = wsum(dsL);
+  dnu = wsum(dnu);
+  if (threadIdx.x == 0) {
+    atomicAdd(&grad[1], dsD);
+    atomicAdd(&grad[2], dsL);
+    atomicAdd(&grad[3], dnu);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kB) void k_adj_scatter(const T* __restrict__ U, T* __restrict__ lam_u,
+                                                    const double* __restrict__ rec,
+                                                    double* __restrict__ lam,
+                                                    const double* __restrict__ scr, bubble_params P,
+                                                    Geom G, int nb) {
+  __shared__ double w[3][kAdjSpan], dw[3][kAdjSpan], wx[3][kAdjSpan], dwx[3][kAdjSpan];
+  __shared__ AxisW win[3];
+  __shared__ double s_red[kBW];
+  __shared__ int s_ok;
+  const int b = (int)xcd_remap(blockIdx.x, nb);
+  const double* r = rec + (size_t)b * R_SIZE;
+  const double* s = scr + (size_t)b * LBM_BUBBLE_WORK;
+  double* l = lam + (size_t)b * A_SIZE;
+  if (s[S_FLAG] == 0.0) return;
+  const double xb[3] = {r[R_X], r[R_X + 1], r[R_X + 2]};
+  if (!adj_weights(G, xb, P.kernel_factor * r[R_D], w, dw, wx, dwx, win, &s_ok)) return;
+  const double lu[3] = {s[S_LUL], s[S_LUL + 1], s[S_LUL + 2]};
+  const double lw[3] = {s[S_LWL], s[S_LWL + 1], s[S_LWL + 2]};
+  const int Dx = win[0].dhi - win[0].dlo + 1, Dy = win[1].dhi - win[1].dlo + 1,
+            Dz = win[2].dhi - win[2].dlo + 1;
+  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+  double gx[3] = {0, 0, 0};
+  for (int f = threadIdx.x; f < Dx * Dy * Dz; f += kB) {
+    const int i = f % Dx, rr = f / Dx, j = rr % Dy, k = rr / Dy;
+    const int vx = win[0].dlo + i, vy = win[1].dlo + j, vz = win[2].dlo + k;
+    const int ix = vx - win[0].lo + 1, iy = vy - win[1].lo + 1, iz = vz - win[2].lo + 1;
+    const int x = px ? wrapi(vx, G.nx) : vx, y = py ? wrapi(vy, G.ny) : vy,
+              z = pz ? wrapi(vz, G.nz) : vz;
+    const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
+    const double a = w[0][ix], da = dw[0][ix], bb = w[1][iy], db = dw[1][iy], cc = w[2][iz],
+                 dc = dw[2][iz];
+    // forward: ul += W U; wx += Uz a db c - Uy a b dc; wy += Ux a b dc - Uz da b c;
+    //          wz += Uy da b c - Ux a db c
+    const double W = a * bb * cc, adbc = a * db * cc, abdc = a * bb * dc, dabc = da * bb * cc;
+    const double gUx = W * lu[0] + abdc * lw[1] - adbc * lw[2];
+    const double gUy = W * lu[1] - abdc * lw[0] + dabc * lw[2];
+    const double gUz = W * lu[2] + adbc * lw[0] - dabc * lw[1];
+    if (gUx != 0.0) atomicAdd(&lam_u[c], (T)gUx);
+    if (gUy != 0.0) atomicAdd(&lam_u[G.N + c], (T)gUy);
+    if (gUz != 0.0) atomicAdd(&lam_u[2 * (size_t)G.N + c], (T)gUz);
+    const double ux = (double)U[c], uy = (double)U[G.N + c], uz = (double)U[2 * (size_t)G.N + c];
+    // derivative of the same sums in the bubble coordinate along each axis
+    const double ax = wx[0][ix], dax = dwx[0][ix], by = wx[1][iy], dby = dwx[1][iy],
+                 cz = wx[2][iz], dcz = dwx[2][iz];
+    {  // x: a -> ax, da -> dax
+      const double Wd = ax * bb * cc, adbc_d = ax * db * cc, abdc_d = ax * bb * dc, dabc_d = dax * bb * cc;
+      gx[0] += lu[0] * Wd * ux + lu[1] * Wd * uy + lu[2] * Wd * uz +
+               lw[0] * (uz * adbc_d - uy * abdc_d) + lw[1] * (ux * abdc_d - uz * dabc_d) +
+               lw[2] * (uy * dabc_d - ux * adbc_d);
+    }
+    {  // y: b -> by, db -> dby
+      const double Wd = a * by * cc, adbc_d = a * dby * cc, abdc_d = a * by * dc, dabc_d = da * by * cc;
+      gx[1] += lu[0] * Wd * ux + lu[1] * Wd * uy + lu[2] * Wd * uz +
+               lw[0] * (uz * adbc_d - uy * abdc_d) + lw[1] * (ux * abdc_d - uz * dabc_d) +
+               lw[2] * (uy * dabc_d - ux * adbc_d);
+    }
+    {  // z: c -> cz, dc -> dcz
+      const double Wd = a * bb * cz, adbc_d = a * db * cz, abdc_d = a * bb * dcz, dabc_d = da * bb * cz;
+      gx[2] += lu[0] * Wd * ux + lu[1] * Wd * uy + lu[2] * Wd * uz +
+               lw[0] * (uz * adbc_d - uy * abdc_d) + lw[1] * (ux * abdc_d - uz * dabc_d) +
+               lw[2] * (uy * dabc_d - ux * adbc_d);
+    }
+  }
+  for (int m = 0; m < 3; ++m) gx[m] = bsum(gx[m], s_red);
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 3; ++a) l[A_X + a] = s[S_GXODE + a] + s[S_GX + a] + gx[a];
+}
+
+template <typename T, bool GENERAL>
+hipError_t liquid_typed(lbm_ctx* c, const void* state, const void* force, const void* lam_next,
+                        void* lam_prev, void* lam_u, void* lam_f, double* grad) {
+  hipLaunchKernelGGL((k_adj_liquid<T, GENERAL>), dim3(div_up(c->geom.N, 256)), dim3(256), 0,
+                     c->stream, static_cast<const T*>(state), static_cast<const T*>(force),
+                     static_cast<const T*>(lam_next), static_cast<T*>(lam_prev),
+                     static_cast<T*>(lam_u), static_cast<T*>(lam_f), c->geom, (T)c->desc.omega,
+                     grad);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t bubbles_typed(lbm_ctx* c, const bubble_params* p, const double* rec, const void* vel_prev,
+                         const void* lam_f, void* lam_u, double* lam, double* scr, int32_t nb,
+                         double* grad) {
+  const double nu = (1.0 / c->desc.omega - 0.5) / 3.0;
+  hipLaunchKernelGGL((k_adj_gather<T>), dim3(nb), dim3(kB), 0, c->stream,
+                     static_cast<const T*>(lam_f), rec, scr, *p, c->geom, nb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adj_ode, dim3(div_up(nb, 64)), dim3(64), 0, c->stream, rec, lam, scr, *p,
+                     c->geom, nu, nb, grad);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_adj_scatter<T>), dim3(nb), dim3(kB), 0, c->stream,
+                     static_cast<const T*>(vel_prev), static_cast<T*>(lam_u), rec, lam, scr, *p,
+                     c->geom, nb);
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+lbm_status lbm_adjoint_liquid(lbm_ctx* ctx, const void* state, const void* force,
+                              const void* lam_next, void* lam_prev, void* lam_u, void* lam_f,
+                              double* grad) {
+  if (!ctx || !state || !force || !lam_next || !lam_prev || !lam_u || !lam_f || !grad)
+    return LBM_EINVAL;
+  if (lam_next == lam_prev) return LBM_EINVAL;
+  hipError_t e;
+  if (ctx->elem == 4)
+    e = ctx->general ? liquid_typed<float, true>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad)
+                     : liquid_typed<float, false>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad);
+  else
+    e = ctx->general ? liquid_typed<double, true>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad)
+                     : liquid_typed<double, false>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad);
+  return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+lbm_status lbm_adjoint_bubbles(lbm_ctx* ctx, const bubble_params* p, const double* record,
+                               const void* vel_prev, const void* lam_f, void* lam_u, double* lam,
+                               double* scratch, int32_t nb, double* grad) {
+  if (!ctx || !p || nb < 0 || !grad) return LBM_EINVAL;
+  if (nb == 0) return LBM_OK;
+  if (!record || !vel_prev || !lam_f || !lam_u || !lam || !scratch) return LBM_EINVAL;
+  if (p->n_sub < 1 || p->n_sub > kMaxSub || p->reserved != 0) return LBM_EINVAL;
+  const hipError_t e =
+      ctx->elem == 4 ? bubbles_typed<float>(ctx, p, record, vel_prev, lam_f, lam_u, lam, scratch, nb, grad)
+                     : bubbles_typed<double>(ctx, p, record, vel_prev, lam_f, lam_u, lam, scratch, nb, grad);
+  return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+// ---- host evaluation of the same arithmetic (for checks on a CPU) ----
+
+lbm_status lbm_host_collide(const double* p, const double* F, double omega, const double* lam,
+                            const double* lam_u, double* out, double* u, double* mu, double* lam_f,
+                            double* domega) {
+  if (!p || !F) return LBM_EINVAL;
+  double o[19], uu[3];
+  collide_cell<double>(p, F, omega, o, uu);
+  if (out)
+    for (int q = 0; q < 19; ++q) out[q] = o[q];
+  if (u)
+    for (int a = 0; a < 3; ++a) u[a] = uu[a];
+  if (lam && lam_u && mu && lam_f && domega)
+    collide_cell_adjoint<double>(p, F, omega, lam, lam_u, mu, lam_f, domega);
+  return LBM_OK;
+}
+
+lbm_status lbm_host_axis_weights(double x, double n, int32_t ext, int32_t periodic, double s_lo,
+                                 double s_hi, int32_t* lo, double* w, double* dw, double* wx,
+                                 double* dwx) {
+  if (!lo || !w || !dw || !wx || !dwx || ext < 1 || !(n > 0.0)) return LBM_EINVAL;
+  AxisW A;
+  if (!axis_weights_dx(x, n, ext, periodic != 0, s_lo, s_hi, A, w, dw, wx, dwx)) return LBM_EINVAL;
+  *lo = A.lo;
+  return LBM_OK;
+}
+
+lbm_status lbm_host_bubble_ode(const bubble_params* p, double nu, double d, const double* x0,
+                               const double* ub0, const double* ul, const double* wl,
+                               const double* dul, const int32_t* ext, const int32_t* periodic,
+                               double* x, double* ub, double* psi) {
+  if (!p || !x0 || !ub0 || !ul || !wl || !dul || !ext || !periodic || !x || !ub || !psi)
+    return LBM_EINVAL;
+  if (p->n_sub < 1 || p->n_sub > kMaxSub) return LBM_EINVAL;
+  OdeBounds Bd;
+  for (int a = 0; a < 3; ++a) {
+    Bd.hi[a] = ext[a] - 1.0;
+    Bd.len[a] = periodic[a] ? (double)ext[a] : 0.0;
+  }
+  Bd.top = !periodic[2];
+  OdeOut o;
+  ode_forward(*p, nu, d, x0, ub0, ul, wl, dul, Bd, o, nullptr, nullptr);
+  for (int a = 0; a < 3; ++a) {
+    x[a] = o.x[a];
+    ub[a] = o.ub[a];
+    psi[a] = o.psi[a];
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_host_bubble_ode_adjoint(const bubble_params* p, double nu, double d,
+                                       const double* x0, const double* ub0, const double* ul,
+                                       const double* wl, const double* dul, const int32_t* ext,
+                                       const int32_t* periodic, const double* lx,
+                                       const double* lub, const double* lpsi, double* out) {
+  if (!p || !x0 || !ub0 || !ul || !wl || !dul || !ext || !periodic || !lx || !lub || !lpsi || !out)
+    return LBM_EINVAL;
+  if (p->n_sub < 1 || p->n_sub > kMaxSub) return LBM_EINVAL;
+  OdeBounds Bd;
+  for (int a = 0; a < 3; ++a) {
+    Bd.hi[a] = ext[a] - 1.0;
+    Bd.len[a] = periodic[a] ? (double)ext[a] : 0.0;
+  }
+  Bd.top = !periodic[2];
+  OdeAdj g;
+  ode_adjoint(*p, nu, d, x0, ub0, ul, wl, dul, Bd, lx, lub, lpsi, g);
+  for (int a = 0; a < 3; ++a) {
+    out[a] = g.x[a];
+    out[3 + a] = g.ub[a];
+    out[6 + a] = g.ul[a];
+    out[9 + a] = g.wl[a];
+    out[12 + a] = g.dul[a];
+  }
+  out[15] = g.dsD;
+  out[16] = g.dsL;
+  out[17] = g.dnu;
+  return LBM_OK;
+}
+
+}  // extern "C"

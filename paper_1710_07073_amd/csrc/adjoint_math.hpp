@@ -1,0 +1,423 @@
+// Host/device arithmetic of the method's adjoint: the transposed Jacobian of one cell's collision
+// (BGK with Guo forcing, Sec. 2.2 eq. (6), (12)-(15)), the kernel weights with their derivative in
+// the bubble position (eq. (18)-(19)), and the bubble ODE (eq. (1)-(4), Table 1) forward with
+// recorded sub-steps and its reverse sweep. The kernels of adjoint.hip call these; the library
+// also exports host wrappers so the same code can be checked against finite differences on a CPU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "../../include/lbm.h"
+#include "lattice.hpp"
+
+namespace lbm {
+
+#define LBM_HD __host__ __device__ inline
+
+// ---------------------------------------------------------------------------------------------
+// Collision of one cell, forward (generic arithmetic, any precision) and transposed Jacobian.
+// p: pre-collision shifted populations, F: force density, out: post-collision populations,
+// u: velocity of eq. (13).
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+LBM_HD void collide_cell(const T* p, const T* F, T omega, T* out, T* u) {
+  T drho = 0, j[3] = {0, 0, 0};
+  for (int q = 0; q < 19; ++q) {
+    drho += p[q];
+    j[0] += T(CX[q]) * p[q];
+    j[1] += T(CY[q]) * p[q];
+    j[2] += T(CZ[q]) * p[q];
+  }
+  const T rho = T(1) + drho;
+  for (int a = 0; a < 3; ++a) u[a] = (j[a] + T(0.5) * F[a]) / rho;
+  const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const T pre = T(1) - T(0.5) * omega;
+  const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+  for (int q = 0; q < 19; ++q) {
+    const T w = weight<T>(q);
+    const T cu = T(CX[q]) * u[0] + T(CY[q]) * u[1] + T(CZ[q]) * u[2];
+    const T cF = T(CX[q]) * F[0] + T(CY[q]) * F[1] + T(CZ[q]) * F[2];
+    const T geq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
+    const T X = T(3) * (cF - uF) + T(9) * cu * cF;
+    out[q] = (T(1) - omega) * p[q] + omega * geq + pre * w * X;
+  }
+}
+
+// Given lam = dL/d(out) and lamU = dL/du of one cell, returns mu = dL/dp, lamF = dL/dF and the
+// cell's share of dL/domega. With rho = 1 + sum p and u = (sum c p + F/2)/rho:
+//   mu_k = (1 - omega) lam_k + A + sum_a B_a (c_ka - u_a) / rho,
+//   A    = omega sum_q lam_q dgeq_q/drho,
+//   B_a  = sum_q lam_q (omega dgeq_q/du_a + dS_q/du_a) + lamU_a,
+//   lamF_a = sum_q lam_q dS_q/dF_a + B_a / (2 rho),
+//   dL/domega = sum_q lam_q (geq_q - p_q - X_q w_q / 2), S_q = (1 - omega/2) w_q X_q.
+template <typename T>
+LBM_HD void collide_cell_adjoint(const T* p, const T* F, T omega, const T* lam, const T* lamU, T* mu,
+                                 T* lamF, double* domega) {
+  T drho = 0, j[3] = {0, 0, 0};
+  for (int q = 0; q < 19; ++q) {
+    drho += p[q];
+    j[0] += T(CX[q]) * p[q];
+    j[1] += T(CY[q]) * p[q];
+    j[2] += T(CZ[q]) * p[q];
+  }
+  const T rho = T(1) + drho;
+  const T inv = T(1) / rho;
+  T u[3];
+  for (int a = 0; a < 3; ++a) u[a] = (j[a] + T(0.5) * F[a]) * inv;
+  const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const T pre = T(1) - T(0.5) * omega;
+  const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+  T A = 0, B[3] = {lamU[0], lamU[1], lamU[2]}, lf[3] = {0, 0, 0};
+  double dom = 0.0;
+  for (int q = 0; q < 19; ++q) {
+    const T w = weight<T>(q);
+    const T c[3] = {T(CX[q]), T(CY[q]), T(CZ[q])};
+    const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+    const T cF = c[0] * F[0] + c[1] * F[1] + c[2] * F[2];
+    const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+    const T geq = w * (drho + rho * base);
+    const T X = T(3) * (cF - uF) + T(9) * cu * cF;
+    const T l = lam[q];
+    A += l * w * (T(1) + base);
+    for (int a = 0; a < 3; ++a) {
+      const T dgeq = w * rho * (T(3) * c[a] + T(9) * cu * c[a] - T(3) * u[a]);
+      const T dS = pre * w * (T(-3) * F[a] + T(9) * c[a] * cF);
+      B[a] += l * (omega * dgeq + dS);
+      lf[a] += l * pre * w * (T(3) * (c[a] - u[a]) + T(9) * cu * c[a]);
+    }
+    dom += (double)l * ((double)geq - (double)p[q] - 0.5 * (double)(w * X));
+  }
+  A *= omega;
+  for (int k = 0; k < 19; ++k) {
+    mu[k] = (T(1) - omega) * lam[k] + A +
+            (B[0] * (T(CX[k]) - u[0]) + B[1] * (T(CY[k]) - u[1]) + B[2] * (T(CZ[k]) - u[2])) * inv;
+  }
+  for (int a = 0; a < 3; ++a) lamF[a] = lf[a] + B[a] * T(0.5) * inv;
+  *domega = dom;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Kernel weights along one axis with their derivative in the bubble coordinate.
+// ---------------------------------------------------------------------------------------------
+constexpr int kAdjSpan = LBM_MAX_STENCIL + 2;
+
+LBM_HD double kernel_P(double s) {
+  if (s <= -1.0) return 0.0;
+  if (s >= 1.0) return 1.0;
+  const double s2 = s * s;
+  return 0.5 + 15.0 / 16.0 * (s - 2.0 / 3.0 * s2 * s + 0.2 * s2 * s2 * s);
+}
+// dP/ds = Z in units of the half-width: 15/16 (1 - s^2)^2 inside the support
+LBM_HD double kernel_dP(double s) {
+  if (s <= -1.0 || s >= 1.0) return 0.0;
+  const double t = 1.0 - s * s;
+  return 15.0 / 16.0 * t * t;
+}
+
+struct AxisW {
+  int lo, hi, clo, chi, dlo, dhi;
+};
+
+LBM_HD bool axis_window_hd(double x, double n, int ext, bool per, AxisW& w) {
+  const double lo = floor(x - n - 0.5) + 1.0;
+  const double hi = ceil(x + n + 0.5) - 1.0;
+  if (!(hi - lo + 1.0 <= (double)LBM_MAX_STENCIL) || !(lo > -1e9) || !(hi < 1e9)) return false;
+  w.lo = (int)lo;
+  w.hi = (int)hi;
+  w.clo = per ? w.lo : (w.lo > 0 ? w.lo : 0);
+  w.chi = per ? w.hi : (w.hi < ext - 1 ? w.hi : ext - 1);
+  if (w.clo > w.chi) return false;
+  w.dlo = per ? w.clo - 1 : (w.clo - 1 > 0 ? w.clo - 1 : 0);
+  w.dhi = per ? w.chi + 1 : (w.chi + 1 < ext - 1 ? w.chi + 1 : ext - 1);
+  return true;
+}
+
+// Sequential evaluation of one axis: w, dw (curl weights with wall ghosts folded in) and their
+// derivatives wx = dw/dx_b, dwx = d(dw)/dx_b, indexed by cell - lo + 1. s_lo, s_hi: ghost signs of
+// the two faces (-1 bounce-back, +1 free slip); per: periodic axis.
+LBM_HD bool axis_weights_dx(double x, double n, int ext, bool per, double s_lo, double s_hi,
+                            AxisW& A, double* w, double* dw, double* wx, double* dwx) {
+  if (!axis_window_hd(x, n, ext, per, A)) return false;
+  double sum = 0.0, dsum = 0.0;
+  for (int i = 0; i < kAdjSpan; ++i) {
+    const int v = A.lo - 1 + i;
+    double wi = 0.0, di = 0.0;
+    if (v >= A.clo && v <= A.chi) {
+      const double sp = (v + 0.5 - x) / n, sm = (v - 0.5 - x) / n;
+      wi = kernel_P(sp) - kernel_P(sm);
+      di = -(kernel_dP(sp) - kernel_dP(sm)) / n;
+    }
+    w[i] = wi;
+    wx[i] = di;
+    sum += wi;
+    dsum += di;
+  }
+  if (!per && sum > 0.0) {  // clipped at a wall: renormalise, d(w/S) = (dw - (w/S) dS) / S
+    for (int i = 0; i < kAdjSpan; ++i) {
+      const double wn = w[i] / sum;
+      wx[i] = (wx[i] - wn * dsum) / sum;
+      w[i] = wn;
+    }
+  }
+  for (int i = 0; i < kAdjSpan; ++i) {
+    const int v = A.lo - 1 + i;
+    const double wm = i > 0 ? w[i - 1] : 0.0, wp = i + 1 < kAdjSpan ? w[i + 1] : 0.0;
+    const double xm = i > 0 ? wx[i - 1] : 0.0, xp = i + 1 < kAdjSpan ? wx[i + 1] : 0.0;
+    double d = 0.5 * (wm - wp), dx = 0.5 * (xm - xp);
+    if (!per) {
+      if (v == 0) {
+        d -= 0.5 * s_lo * w[i];
+        dx -= 0.5 * s_lo * wx[i];
+      }
+      if (v == ext - 1) {
+        d += 0.5 * s_hi * w[i];
+        dx += 0.5 * s_hi * wx[i];
+      }
+    }
+    dw[i] = d;
+    dwx[i] = dx;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Bubble ODE with recorded sub-steps, and its reverse sweep.
+// ---------------------------------------------------------------------------------------------
+constexpr int kMaxSub = 32;
+
+struct OdeBounds {
+  double hi[3];   // upper bound of the clamp on the lateral axes (ext - 1)
+  double len[3];  // period of a periodic axis, 0 otherwise
+  int top;        // z has a top (non-periodic): no clamp there, the bubble stops instead
+};
+
+struct ForceJac {
+  double F[3];      // F_D + F_L
+  double FD1[3];    // F_D / drag_scale
+  double FL1[3];    // F_L / lift_scale
+  double J[3][3];   // d(F_D + F_L)/du_r
+  double Jw[3][3];  // dF_L/d(curl u_l)
+  double dnu[3];    // d(F_D + F_L)/dnu
+};
+
+// Drag and lift of Table 1 at relative velocity u_r = ub - ul, with their derivatives.
+LBM_HD void force_jac(const bubble_params& P, double nu, double d, const double* ub,
+                      const double* ul, const double* wl, ForceJac& f) {
+  const double pi = 3.14159265358979323846;
+  const double V = pi * d * d * d / 6.0;
+  const double r = 0.5 * d;
+  const double KD = 0.5 * P.rho_l * pi * r * r;
+  const double KL = P.rho_l * V;
+  const double ur[3] = {ub[0] - ul[0], ub[1] - ul[1], ub[2] - ul[2]};
+  const double m = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
+  const double Re = m * d / nu;
+  const double Eo = (P.rho_l - P.rho_b) * P.g * d * d / P.sigma;
+  const double shape = 8.0 / 3.0 * Eo / (Eo + 4.0);
+  const double v24 = 24.0 * nu / d, v48 = 48.0 * nu / d;
+  // viscous branch min{24/Re (1 + k Re^0.687), 48/Re} |u_r|, its m d/dm and d/dnu
+  double visc = v48, visc_m = 0.0, visc_nu = 48.0 / d;
+  if (Re > 0.0) {
+    const double t = P.cd_k * exp(0.687 * log(Re));
+    const double a = v24 * (1.0 + t);
+    if (a < v48) {
+      visc = a;
+      visc_m = v24 * 0.687 * t;
+      visc_nu = 24.0 / d * (1.0 + 0.313 * t);
+    }
+  } else if (v24 < v48) {
+    visc = v24;
+    visc_nu = 24.0 / d;
+  }
+  double cdu, cdu_m, cdu_nu;
+  if (shape * m > visc) {
+    cdu = shape * m;
+    cdu_m = shape * m;
+    cdu_nu = 0.0;
+  } else {
+    cdu = visc;
+    cdu_m = visc_m;
+    cdu_nu = visc_nu;
+  }
+  // lift coefficient and dC_L/dRe
+  const double E = 1.0 / (1.0 + 0.163 * exp(0.757 * log(Eo)));
+  const double Eod = Eo / exp(2.0 / 3.0 * log(E));
+  const double fl = 0.00105 * Eod * Eod * Eod - 0.0159 * Eod * Eod - 0.0204 * Eod + P.lift_f0;
+  double cl, cl_re = 0.0;
+  if (Eod < 4.0) {
+    const double th = tanh(0.121 * Re);
+    if (0.288 * th < fl) {
+      cl = 0.288 * th;
+      cl_re = 0.288 * 0.121 * (1.0 - th * th);
+    } else {
+      cl = fl;
+    }
+  } else if (Eod <= 10.0) {
+    cl = fl;
+  } else {
+    cl = -0.29;
+  }
+  const double cr[3] = {ur[1] * wl[2] - ur[2] * wl[1], ur[2] * wl[0] - ur[0] * wl[2],
+                        ur[0] * wl[1] - ur[1] * wl[0]};
+  const double sD = P.drag_scale, sL = P.lift_scale;
+  const double uh[3] = {m > 0.0 ? ur[0] / m : 0.0, m > 0.0 ? ur[1] / m : 0.0, m > 0.0 ? ur[2] / m : 0.0};
+  // d(u_r x w)/du_r and d(u_r x w)/dw
+  const double dcr_du[3][3] = {{0.0, wl[2], -wl[1]}, {-wl[2], 0.0, wl[0]}, {wl[1], -wl[0], 0.0}};
+  const double dcr_dw[3][3] = {{0.0, -ur[2], ur[1]}, {ur[2], 0.0, -ur[0]}, {-ur[1], ur[0], 0.0}};
+  const double dcl_dm = cl_re * d / nu;  // dC_L/d|u_r|
+  for (int a = 0; a < 3; ++a) {
+    f.FD1[a] = -KD * cdu * ur[a];
+    f.FL1[a] = -KL * cl * cr[a];
+    f.F[a] = sD * f.FD1[a] + sL * f.FL1[a];
+    for (int b = 0; b < 3; ++b) {
+      const double dd = -sD * KD * ((a == b ? cdu : 0.0) + cdu_m * uh[a] * uh[b]);
+      const double dl = -sL * KL * (cl * dcr_du[a][b] + cr[a] * dcl_dm * uh[b]);
+      f.J[a][b] = dd + dl;
+      f.Jw[a][b] = -sL * KL * cl * dcr_dw[a][b];
+    }
+    f.dnu[a] = -sD * KD * cdu_nu * ur[a] - sL * KL * cr[a] * cl_re * (-Re / nu);
+  }
+}
+
+struct OdeOut {
+  double x[3], ub[3], psi[3];
+};
+
+// The ODE of one liquid step (n_sub explicit sub-steps with the added mass on the left), as the
+// forward kernel computes it; ubs/clamped record the sub-step velocities and clamp events.
+LBM_HD void ode_forward(const bubble_params& P, double nu, double d, const double* x0,
+                        const double* ub0, const double* ul, const double* wl, const double* dul,
+                        const OdeBounds& Bd, OdeOut& o, double (*ubs)[3], unsigned char (*clamped)[3]) {
+  const double pi = 3.14159265358979323846;
+  const double V = pi * d * d * d / 6.0;
+  const double inv_meff = 1.0 / (P.rho_b * V + P.c_a * P.rho_l * V);
+  const double va = (1.0 + P.c_a) * P.rho_l * V;
+  const double fb = (P.rho_l - P.rho_b) * V * P.g;
+  const double dt = 1.0 / P.n_sub;
+  double ub[3] = {ub0[0], ub0[1], ub0[2]}, x[3] = {x0[0], x0[1], x0[2]};
+  for (int k = 0; k < P.n_sub; ++k) {
+    if (ubs)
+      for (int a = 0; a < 3; ++a) ubs[k][a] = ub[a];
+    ForceJac f;
+    force_jac(P, nu, d, ub, ul, wl, f);
+    for (int a = 0; a < 3; ++a) {
+      double fa = f.F[a] + va * dul[a];
+      if (a == 2) fa += fb;
+      ub[a] += dt * fa * inv_meff;
+    }
+    for (int a = 0; a < 3; ++a) {
+      unsigned char c = 0;
+      x[a] += dt * ub[a];
+      if (Bd.len[a] > 0.0) {
+        x[a] = fmod(x[a], Bd.len[a]);
+        if (x[a] < 0.0) x[a] += Bd.len[a];
+      } else {
+        if (x[a] < 0.0) {
+          x[a] = 0.0;
+          ub[a] = 0.0;
+          c = 1;
+        }
+        if (!(a == 2 && Bd.top) && x[a] > Bd.hi[a]) {
+          x[a] = Bd.hi[a];
+          ub[a] = 0.0;
+          c = 1;
+        }
+      }
+      if (clamped) clamped[k][a] = c;
+    }
+  }
+  if (ubs)
+    for (int a = 0; a < 3; ++a) ubs[P.n_sub][a] = ub[a];
+  ForceJac f;
+  force_jac(P, nu, d, ub, ul, wl, f);
+  for (int a = 0; a < 3; ++a) {
+    o.x[a] = x[a];
+    o.ub[a] = ub[a];
+    o.psi[a] = -f.F[a];
+  }
+}
+
+struct OdeAdj {
+  double x[3], ub[3], ul[3], wl[3], dul[3];
+  double dsD, dsL, dnu;
+};
+
+// Reverse sweep of ode_forward: given dL/dx_new, dL/dub_new, dL/dpsi, returns the derivatives in
+// the step's inputs and in drag_scale, lift_scale and nu.
+LBM_HD void ode_adjoint(const bubble_params& P, double nu, double d, const double* x0,
+                        const double* ub0, const double* ul, const double* wl, const double* dul,
+                        const OdeBounds& Bd, const double* lx_new, const double* lub_new,
+                        const double* lpsi, OdeAdj& g) {
+  double ubs[kMaxSub + 1][3];
+  unsigned char clamped[kMaxSub][3];
+  OdeOut o;
+  ode_forward(P, nu, d, x0, ub0, ul, wl, dul, Bd, o, ubs, clamped);
+  const double pi = 3.14159265358979323846;
+  const double V = pi * d * d * d / 6.0;
+  const double inv_meff = 1.0 / (P.rho_b * V + P.c_a * P.rho_l * V);
+  const double va = (1.0 + P.c_a) * P.rho_l * V;
+  const double s = inv_meff / P.n_sub;
+  double lx[3], lub[3];
+  for (int a = 0; a < 3; ++a) {
+    lx[a] = lx_new[a];
+    lub[a] = lub_new[a];
+    g.ul[a] = g.wl[a] = g.dul[a] = 0.0;
+  }
+  g.dsD = g.dsL = g.dnu = 0.0;
+  {  // psi = -(F_D + F_L)(ub_n)
+    ForceJac f;
+    force_jac(P, nu, d, ubs[P.n_sub], ul, wl, f);
+    for (int b = 0; b < 3; ++b) {
+      double t = 0.0, tw = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        t += f.J[a][b] * lpsi[a];
+        tw += f.Jw[a][b] * lpsi[a];
+      }
+      lub[b] -= t;
+      g.ul[b] += t;
+      g.wl[b] -= tw;
+    }
+    for (int a = 0; a < 3; ++a) {
+      g.dsD -= f.FD1[a] * lpsi[a];
+      g.dsL -= f.FL1[a] * lpsi[a];
+      g.dnu -= f.dnu[a] * lpsi[a];
+    }
+  }
+  for (int k = P.n_sub - 1; k >= 0; --k) {
+    // x_{k+1} = x_k + dt ub'_{k+1} (then clamped), ub_{k+1} = ub' with clamped components zeroed
+    double lup[3];
+    for (int a = 0; a < 3; ++a) {
+      if (clamped[k][a]) {
+        lup[a] = 0.0;
+        lx[a] = 0.0;
+      } else {
+        lup[a] = lub[a] + lx[a] / P.n_sub;
+      }
+    }
+    // ub' = ub_k + dt/m_eff (F(ub_k) + va dul + fb e_z)
+    ForceJac f;
+    force_jac(P, nu, d, ubs[k], ul, wl, f);
+    for (int b = 0; b < 3; ++b) {
+      double t = 0.0, tw = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        t += f.J[a][b] * lup[a];
+        tw += f.Jw[a][b] * lup[a];
+      }
+      lub[b] = lup[b] + s * t;
+      g.ul[b] -= s * t;
+      g.wl[b] += s * tw;
+      g.dul[b] += s * va * lup[b];
+    }
+    for (int a = 0; a < 3; ++a) {
+      g.dsD += s * f.FD1[a] * lup[a];
+      g.dsL += s * f.FL1[a] * lup[a];
+      g.dnu += s * f.dnu[a] * lup[a];
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    g.x[a] = lx[a];
+    g.ub[a] = lub[a];
+  }
+}
+
+}  // namespace lbm

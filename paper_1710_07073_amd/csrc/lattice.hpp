@@ -66,16 +66,18 @@ __device__ __forceinline__ CellNbr cell_neighbours(const Geom& G, int x, int y, 
   return n;
 }
 
-// Gather (pull) of population Q arriving at cell `cell` from the post-collision buffer `src`:
-// the streaming step eq. (16) written per destination. A source beyond a wall is replaced by
+// Source of population Q arriving at cell `cell` in the post-collision buffer: the streaming step
+// eq. (16) written per destination, as a flat index q_src * N + cell_src. A source beyond a wall is
+// replaced by
 //   - half-way bounce-back: the opposite population of the same cell;
 //   - free slip, when exactly one coordinate of the source is outside: the population with the
 //     normal component mirrored, taken from the source position with the normal coordinate kept;
 //   - anything else (edges and corners): bounce-back.
+// Every (cell, q) of the buffer is the source of exactly one destination: the map is a
+// permutation, so its transpose (the adjoint of streaming) is a conflict-free scatter.
 // GENERAL = false compiles only the bounce-back/no-periodic case.
-template <int Q, bool GENERAL, typename T>
-__device__ __forceinline__ T pull(const T* __restrict__ src, const Geom& G, uint32_t cell,
-                                  const CellNbr& nb) {
+template <int Q, bool GENERAL>
+__device__ __forceinline__ size_t pull_index(const Geom& G, uint32_t cell, const CellNbr& nb) {
   constexpr int cx = CX[Q], cy = CY[Q], cz = CZ[Q];
   int32_t off = 0;
   bool out[3] = {false, false, false};
@@ -85,9 +87,8 @@ __device__ __forceinline__ T pull(const T* __restrict__ src, const Geom& G, uint
   if (cy < 0) { off += nb.dp[1]; out[1] = nb.op[1]; }
   if (cz > 0) { off += nb.dm[2]; out[2] = nb.om[2]; }
   if (cz < 0) { off += nb.dp[2]; out[2] = nb.op[2]; }
-  const size_t base = (size_t)Q * G.N;
   const bool any = out[0] || out[1] || out[2];
-  if (!any) return src[base + (uint32_t)((int32_t)cell + off)];
+  if (!any) return (size_t)Q * G.N + (uint32_t)((int32_t)cell + off);
   constexpr int qo = opposite(Q);
   if constexpr (GENERAL) {
     const int nout = (int)out[0] + (int)out[1] + (int)out[2];
@@ -101,11 +102,18 @@ __device__ __forceinline__ T pull(const T* __restrict__ src, const Geom& G, uint
                                   : (a == 1 ? (cy > 0 ? nb.dm[1] : nb.dp[1])
                                             : (cz > 0 ? nb.dm[2] : nb.dp[2]));
         const int qm = a == 0 ? mirrored(Q, 0) : (a == 1 ? mirrored(Q, 1) : mirrored(Q, 2));
-        return src[(size_t)qm * G.N + (uint32_t)((int32_t)cell + off - da)];
+        return (size_t)qm * G.N + (uint32_t)((int32_t)cell + off - da);
       }
     }
   }
-  return src[(size_t)qo * G.N + cell];
+  return (size_t)qo * G.N + cell;
+}
+
+// Gather (pull) of population Q arriving at cell `cell` from the post-collision buffer `src`.
+template <int Q, bool GENERAL, typename T>
+__device__ __forceinline__ T pull(const T* __restrict__ src, const Geom& G, uint32_t cell,
+                                  const CellNbr& nb) {
+  return src[pull_index<Q, GENERAL>(G, cell, nb)];
 }
 
 }  // namespace lbm

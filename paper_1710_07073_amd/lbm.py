@@ -19,6 +19,8 @@ LBM_BC_BOUNCE_BACK, LBM_BC_FREE_SLIP, LBM_BC_PERIODIC = 0, 1, 2
 LBM_FLAG_STATIC_FORCE, LBM_FLAG_WRITE_U_ALL = 1, 2
 LBM_MAX_STENCIL = 64
 LBM_BUBBLE_WORK = 16
+LBM_BUBBLE_RECORD = 24
+LBM_BUBBLE_ADJ = 12
 
 # every symbol include/lbm.h declares
 EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch", "lbm_get_launch",
@@ -27,7 +29,9 @@ EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch",
            "lbm_status_string",
            "lbm_batch_bytes_required", "lbm_batch_init", "lbm_batch_set_items", "lbm_batch_get_items",
            "lbm_batch_step", "lbm_batch_run", "lbm_batch_populations", "lbm_batch_column",
-           "lbm_batch_check", "lbm_batch_destroy")
+           "lbm_batch_check", "lbm_batch_destroy",
+           "lbm_adjoint_liquid", "lbm_adjoint_bubbles", "lbm_host_collide",
+           "lbm_host_axis_weights", "lbm_host_bubble_ode", "lbm_host_bubble_ode_adjoint")
 
 
 class LbmDesc(ct.Structure):
@@ -102,6 +106,17 @@ def lib():
         L.lbm_batch_column.argtypes = [P, ct.c_int32, ct.POINTER(P), ct.POINTER(P), ct.POINTER(P)]
         L.lbm_batch_check.argtypes = [P]
         L.lbm_batch_destroy.argtypes = [P]
+        D = ct.POINTER(ct.c_double)
+        I = ct.POINTER(ct.c_int32)
+        L.lbm_adjoint_liquid.argtypes = [P, P, P, P, P, P, P, P]
+        L.lbm_adjoint_bubbles.argtypes = [P, ct.POINTER(BubbleParams), P, P, P, P, P, P, ct.c_int32, P]
+        L.lbm_host_collide.argtypes = [D, D, ct.c_double, D, D, D, D, D, D, D]
+        L.lbm_host_axis_weights.argtypes = [ct.c_double, ct.c_double, ct.c_int32, ct.c_int32,
+                                            ct.c_double, ct.c_double, I, D, D, D, D]
+        L.lbm_host_bubble_ode.argtypes = [ct.POINTER(BubbleParams), ct.c_double, ct.c_double, D, D, D,
+                                          D, D, I, I, D, D, D]
+        L.lbm_host_bubble_ode_adjoint.argtypes = [ct.POINTER(BubbleParams), ct.c_double, ct.c_double,
+                                                  D, D, D, D, D, I, I, D, D, D, D]
         L.lbm_status_string.argtypes = [ct.c_int]
         L.lbm_status_string.restype = ct.c_char_p
         for name in EXPORTS:
@@ -259,3 +274,83 @@ def lbm_batch_check(batch):
 def lbm_batch_destroy(batch):
     if batch:
         lib().lbm_batch_destroy(batch)
+
+
+# ---- adjoint ----
+def lbm_adjoint_liquid(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad):
+    _ok(lib().lbm_adjoint_liquid(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad),
+        "lbm_adjoint_liquid")
+
+
+def lbm_adjoint_bubbles(ctx, params, record, vel_prev, lam_f, lam_u, lam, scratch, nb, grad):
+    _ok(lib().lbm_adjoint_bubbles(ctx, ct.byref(params), record, vel_prev, lam_f, lam_u, lam,
+                                  scratch, int(nb), grad), "lbm_adjoint_bubbles")
+
+
+def _dp(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def host_collide(p, F, omega, lam=None, lam_u=None):
+    """Host evaluation of one cell's collision (and its transposed Jacobian if lam is given)."""
+    import numpy as np
+    p, pp = _dp(p)
+    F, Fp = _dp(F)
+    out = np.zeros(19)
+    u = np.zeros(3)
+    mu = np.zeros(19)
+    lf = np.zeros(3)
+    dom = np.zeros(1)
+    if lam is None:
+        _ok(lib().lbm_host_collide(pp, Fp, float(omega), None, None, _dp(out)[1], _dp(u)[1], None,
+                                   None, None), "lbm_host_collide")
+        return out, u
+    lam, lp = _dp(lam)
+    lam_u, lup = _dp(lam_u)
+    _ok(lib().lbm_host_collide(pp, Fp, float(omega), lp, lup, out.ctypes.data_as(ct.POINTER(ct.c_double)),
+                               u.ctypes.data_as(ct.POINTER(ct.c_double)),
+                               mu.ctypes.data_as(ct.POINTER(ct.c_double)),
+                               lf.ctypes.data_as(ct.POINTER(ct.c_double)),
+                               dom.ctypes.data_as(ct.POINTER(ct.c_double))), "lbm_host_collide")
+    return out, u, mu, lf, float(dom[0])
+
+
+def host_axis_weights(x, n, ext, periodic=False, s_lo=-1.0, s_hi=-1.0):
+    """Host evaluation of one axis' weights: (lo, w, dw, dw/dx, d(dw)/dx), entries from lo - 1."""
+    import numpy as np
+    span = LBM_MAX_STENCIL + 2
+    arrs = [np.zeros(span) for _ in range(4)]
+    lo = ct.c_int32()
+    _ok(lib().lbm_host_axis_weights(float(x), float(n), int(ext), int(bool(periodic)), float(s_lo),
+                                    float(s_hi), ct.byref(lo),
+                                    *[a.ctypes.data_as(ct.POINTER(ct.c_double)) for a in arrs]),
+        "lbm_host_axis_weights")
+    return (lo.value,) + tuple(arrs)
+
+
+def host_bubble_ode(params, nu, d, x0, ub0, ul, wl, dul, ext, periodic=(0, 0, 0)):
+    import numpy as np
+    ins = [_dp(v) for v in (x0, ub0, ul, wl, dul)]
+    e = (ct.c_int32 * 3)(*[int(v) for v in ext])
+    pr = (ct.c_int32 * 3)(*[int(bool(v)) for v in periodic])
+    x, ub, psi = np.zeros(3), np.zeros(3), np.zeros(3)
+    _ok(lib().lbm_host_bubble_ode(ct.byref(params), float(nu), float(d), *[p for _, p in ins], e, pr,
+                                  *[a.ctypes.data_as(ct.POINTER(ct.c_double)) for a in (x, ub, psi)]),
+        "lbm_host_bubble_ode")
+    return x, ub, psi
+
+
+def host_bubble_ode_adjoint(params, nu, d, x0, ub0, ul, wl, dul, ext, periodic, lx, lub, lpsi):
+    import numpy as np
+    ins = [_dp(v) for v in (x0, ub0, ul, wl, dul)]
+    e = (ct.c_int32 * 3)(*[int(v) for v in ext])
+    pr = (ct.c_int32 * 3)(*[int(bool(v)) for v in periodic])
+    lams = [_dp(v) for v in (lx, lub, lpsi)]
+    out = np.zeros(18)
+    _ok(lib().lbm_host_bubble_ode_adjoint(ct.byref(params), float(nu), float(d), *[p for _, p in ins],
+                                          e, pr, *[p for _, p in lams],
+                                          out.ctypes.data_as(ct.POINTER(ct.c_double))),
+        "lbm_host_bubble_ode_adjoint")
+    return out

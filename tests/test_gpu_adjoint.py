@@ -1,0 +1,117 @@
+"""Gradient of the bubble-trajectory loss with respect to (drag_scale, lift_scale, omega) through
+the hand-written adjoint (checkpointed, torch.autograd.Function), against central finite
+differences of the GPU forward and of the FP64 oracle (h = 1e-3)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from paper_1710_07073_amd import adjoint as A
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_64x64x192_oracle_gradient.json")
+H = 1e-3
+
+
+def _small(steps=150):
+    pos = np.array([[10.0, 14.0], [11.0, 12.5], [9.0, 14.0]])
+    return W.Workload("adjoint_small_24x24x48_2b", (24, 24, 48), 1.4, (0,) * 6, pos,
+                      np.array([3.0, 2.5]), W.params(g=1e-4, sigma=1e-4), steps, "f64",
+                      meta=dict(target=(1.15, 0.8, 1.5), theta0=(1.0, 1.0, 1.4)))
+
+
+def _problem(w, precision, K):
+    return A.TrajectoryProblem(w.shape, w.bc, w.pos, w.d, w.params, w.steps, precision=precision,
+                               checkpoint=K)
+
+
+def _gpu_loss(problem, theta, target):
+    traj, sim, _ = problem.forward(theta, checkpoints=False)
+    sim.close()
+    return float(((traj - target) ** 2).sum())
+
+
+def _oracle_traj(w, theta):
+    sD, sL, om = theta
+    lat = O.Lattice(*w.shape, om, w.bc)
+    bub = O.Bubbles(pos=w.pos.copy(), d=w.d.copy())
+    p = dict(w.params)
+    p.update(drag_scale=sD, lift_scale=sL)
+    return O.run(lat, O.bubble_params(**p), bub, w.steps, record=True)
+
+
+def _adjoint_grad(problem, theta0, target):
+    theta = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    loss = A.trajectory_loss(problem, theta, target)
+    loss.backward()
+    return loss.item(), theta.grad.numpy()
+
+
+@pytest.mark.gpu
+def test_adjoint_matches_finite_differences_fp64():
+    w = _small()
+    prob = _problem(w, "f64", K=50)
+    target, sim, _ = prob.forward(w.meta["target"], checkpoints=False)
+    sim.close()
+    L0, g = _adjoint_grad(prob, w.meta["theta0"], target)
+    fd = np.zeros(3)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = H
+        th = np.array(w.meta["theta0"])
+        fd[i] = (_gpu_loss(prob, th + e, target) - _gpu_loss(prob, th - e, target)) / (2 * H)
+    print(f"L = {L0:.6e}, adjoint {g}, FD {fd}", flush=True)
+    scale = np.abs(fd).max()
+    assert np.allclose(g, fd, rtol=1e-4, atol=1e-5 * scale)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_adjoint_matches_oracle_gradient(precision):
+    w = _small()
+    th0 = np.array(w.meta["theta0"])
+    target_o = _oracle_traj(w, w.meta["target"])
+    lo = lambda th: float(np.sum((_oracle_traj(w, th) - target_o) ** 2))
+    fd = np.zeros(3)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = H
+        fd[i] = (lo(th0 + e) - lo(th0 - e)) / (2 * H)
+    prob = _problem(w, precision, K=40)
+    target = torch.tensor(target_o, device="cuda")
+    L0, g = _adjoint_grad(prob, w.meta["theta0"], target)
+    print(f"{precision}: L = {L0:.6e}, adjoint {g}, oracle FD {fd}", flush=True)
+    scale = np.abs(fd).max()
+    tol = 1e-4 if precision == "f64" else 2e-2
+    assert np.allclose(g, fd, rtol=tol, atol=tol * scale)
+
+
+@pytest.mark.gpu
+def test_adjoint_checkpoint_interval_does_not_change_the_gradient():
+    w = _small(steps=90)
+    target, sim, _ = _problem(w, "f64", 30).forward(w.meta["target"], checkpoints=False)
+    sim.close()
+    grads = [_adjoint_grad(_problem(w, "f64", K), w.meta["theta0"], target)[1] for K in (90, 30, 7)]
+    assert np.allclose(grads[0], grads[1], rtol=1e-11) and np.allclose(grads[0], grads[2], rtol=1e-11)
+
+
+@pytest.mark.gpu
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle gradient file not generated")
+def test_adjoint_full_column_against_oracle_gradient():
+    """64 x 64 x 192 FP32 column, 4 bubbles, 2000 steps, checkpoints every 100 steps."""
+    ref = json.load(open(GOLDEN))
+    w = W.adjoint(steps=ref["steps"])
+    prob = _problem(w, "f32", K=w.meta["checkpoint"])
+    target, sim, _ = prob.forward(w.meta["target"], checkpoints=False)
+    sim.close()
+    L0, g = _adjoint_grad(prob, w.meta["theta0"], target)
+    fd = np.array(ref["gradient"])
+    print(f"L = {L0:.6e} (oracle {ref['loss']:.6e}), adjoint {g}, oracle FD {fd}", flush=True)
+    assert L0 == pytest.approx(ref["loss"], rel=1e-2)
+    scale = np.abs(fd).max()
+    # drag and omega components to 2 %, the lift component (orders of magnitude smaller at these
+    # Reynolds numbers) to 2 % of the largest component
+    assert np.allclose(g, fd, rtol=2e-2, atol=2e-2 * scale)
