@@ -82,9 +82,10 @@ def cpu_baseline(w, budget_s=12.0):
                       f"lattice and bubble, FP64, {threads} OpenMP threads, {el:.1f} s"}
 
 
-def bench_batched(args):
+def leg_batched(args, steps):
     """64 uneven columns stepped together (FP32, graph replays), against the same columns run one
-    at a time as plain single-lattice FP64 simulations."""
+    at a time as plain single-lattice FP64 simulations; error of the FP32 batch against FP64
+    single-column runs of the same number of steps on four of the columns."""
     import torch
     import workloads as W
     from paper_1710_07073_amd import autotune
@@ -93,59 +94,210 @@ def bench_batched(args):
 
     ws = W.batched()
     cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d) for w in ws]
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    stream = torch.cuda.Stream(dev)
+    stream = torch.cuda.current_stream()
     cells = sum(w.cells for w in ws)
     gsteps = args.graph_steps or 20
-    with torch.cuda.stream(stream):
-        batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
-        items, sweep = (None, None)
-        if not args.no_autotune:
-            items, sweep = autotune.tune_batch(batch, steps=3)
-            for k, cand, ms in sweep:
-                print(f"[autotune] class {k} item {cand}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
-        batch.run(args.warmup + (-args.warmup) % gsteps, graph_steps=gsteps)
+    batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
+    items = None
+    if not args.no_autotune:
+        items, sweep = autotune.tune_batch(batch, steps=3)
+        for k, cand, ms in sweep:
+            print(f"[autotune] class {k} item {cand}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    batch.close()
+    # tuning stepped the columns; time a fresh batch with the tuned items
+    batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
+    if items is not None:
+        L.lbm_batch_set_items(batch.handle, items)
+    warm = args.warmup + (-args.warmup) % gsteps
+    batch.run(warm, graph_steps=gsteps)
+    stream.synchronize()
+    K = max(gsteps, steps - steps % gsteps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    batch.run(K, graph_steps=gsteps)
+    e1.record(stream)
+    stream.synchronize()
+    elapsed = time.perf_counter() - t0
+    ev_s = e0.elapsed_time(e1) * 1e-3
+    batch.check()
+    total = warm + K
+    # plain single-lattice FP64 form: every column on its own, eager launches, a few steps each
+    ks = 4
+    t_single = 0.0
+    for w in ws:
+        sim = S.Simulation(w.shape, w.omega, precision="f64", bc=w.bc, stream=stream)
+        sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+        sim.step(1)
         stream.synchronize()
-        K = max(gsteps, args.steps - args.steps % gsteps)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(stream)
-        batch.run(K, graph_steps=gsteps)
-        e1.record(stream)
+        a = time.perf_counter()
+        sim.step(ks)
         stream.synchronize()
-        elapsed = time.perf_counter() - t0
-        ev_s = e0.elapsed_time(e1) * 1e-3
-        batch.check()
-        batch.close()
-        # plain single-lattice FP64 form: every column on its own, eager launches, a few steps
-        ks = 4
-        t_single = 0.0
-        for w in ws:
-            sim = S.Simulation(w.shape, w.omega, precision="f64", bc=w.bc, stream=stream)
-            sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
-            sim.step(1)
-            stream.synchronize()
-            a = time.perf_counter()
-            sim.step(ks)
-            stream.synchronize()
-            t_single += time.perf_counter() - a
-            sim.close()
+        t_single += time.perf_counter() - a
+        sim.close()
+    # error of the FP32 batch against FP64 single-column runs over the same steps
+    err_g, err_x = 0.0, 0.0
+    for c in (0, 17, 40, 63):
+        w = ws[c]
+        sim = S.Simulation(w.shape, w.omega, precision="f64", bc=w.bc, stream=stream)
+        sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+        sim.run(total, graph_steps=gsteps)
+        g64 = sim.populations()
+        x64 = sim.bubbles.positions()
+        sim.close()
+        g32 = batch.populations(c)
+        b0, b1 = batch.bubble_range(c)
+        x32 = batch.bubbles.positions()[:, b0:b1]
+        err_g = max(err_g, float(((g32.double() - g64).norm() / g64.norm()).item()))
+        err_x = max(err_x, float(np.abs(x32 - x64).max()))
+    batch.close()
     mlups = cells * K / elapsed / 1e6
     fp64 = cells * ks / t_single / 1e6
+    return {"columns": len(ws), "cells": cells, "bubbles": int(sum(w.nb for w in ws)),
+            "steps": K, "graph_steps": gsteps, "item_cells": items,
+            "batched_f32_mlups": round(mlups, 1), "ms_per_step": round(elapsed / K * 1e3, 5),
+            "event_ms_per_step": round(ev_s / K * 1e3, 5),
+            "plain_fp64_single_mlups": round(fp64, 1), "ratio_vs_plain_fp64": round(mlups / fp64, 3),
+            "error_vs_fp64": {"after_steps": total, "columns_checked": [0, 17, 40, 63],
+                              "populations_rel_l2_max": err_g,
+                              "bubble_pos_max_abs": err_x}}
+
+
+def bench_batched(args):
+    leg = leg_batched(args, args.steps)
     out = {
-        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": K,
-        "warmup": args.warmup, "ms_per_step": round(elapsed / K * 1e3, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batched_64_columns", "columns": len(ws), "cells": cells,
-                   "bubbles": int(sum(w.nb for w in ws)), "graph_steps": gsteps,
-                   "item_cells": items, "parallelism": "single GPU"},
-        "batched_vs_plain_fp64": {"batched_f32_mlups": round(mlups, 1),
-                                  "plain_fp64_single_mlups": round(fp64, 1),
-                                  "ratio": round(mlups / fp64, 3),
-                                  "event_ms_per_step": round(ev_s / K * 1e3, 5)},
+        "metric": METRIC, "value": leg["batched_f32_mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": leg["steps"], "warmup": args.warmup, "ms_per_step": leg["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": {"workload": "batched_64_columns", "parallelism": "single GPU"},
+        "batched": leg,
     }
     print(json.dumps(out), flush=True)
+
+
+ADJOINT_GOLDEN = os.path.join(ROOT, "tests", "golden", "adjoint_64x64x192_oracle_gradient.json")
+
+
+def leg_adjoint(args):
+    """Gradient of the trajectory loss (drag scale, lift scale, omega) on the 64 x 64 x 192 FP32
+    column with 4 bubbles, 2000 steps, checkpoints every 100 steps: throughput of the whole gradient
+    pass (forward with checkpoints, segment recompute, reverse sweep) in lattice-site updates of
+    the simulated steps per second, against the plain FP64 forward of the same column; gradient
+    error against the oracle's central differences (h = 1e-3)."""
+    import torch
+    import workloads as W
+    from paper_1710_07073_amd import adjoint as A
+    from paper_1710_07073_amd import sim as S
+
+    w = W.adjoint()
+    stream = torch.cuda.current_stream()
+    prob = A.TrajectoryProblem(w.shape, w.bc, w.pos, w.d, w.params, w.steps, precision="f32",
+                               checkpoint=w.meta["checkpoint"], stream=stream)
+    target, sim, _ = prob.forward(w.meta["target"], checkpoints=False)
+    sim.close()
+    torch.cuda.synchronize()
+    prob.liquid_events = []
+    theta = torch.tensor(w.meta["theta0"], dtype=torch.float64, requires_grad=True)
+    t0 = time.perf_counter()
+    traj = A.BubbleTrajectory.apply(theta, prob)
+    loss = ((traj - target) ** 2).sum()
+    lv = loss.item()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = theta.grad.numpy()
+    kern_s = float(np.mean([a.elapsed_time(b) for a, b in prob.liquid_events])) * 1e-3
+    # plain single-instance FP64 form: the same column forward, graph replays
+    sim = S.Simulation(w.shape, w.omega, precision="f64", bc=w.bc, stream=stream)
+    sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+    sim.run(20, graph_steps=20)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    sim.run(w.steps, graph_steps=20)
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - a
+    sim.close()
+    cells = int(np.prod(w.shape))
+    mlups = cells * w.steps / (t2 - t0) / 1e6
+    fp64 = cells * w.steps / t_fp64 / 1e6
+    alg = 276 * cells  # FP32: pulled h 76 B, lambda in 76 B, lambda out 76 B, F 12 B, lambda_U 24 B, lambda_F 12 B
+    out = {"workload": "adjoint_64x64x192_4b_f32", "steps": w.steps, "checkpoint": w.meta["checkpoint"],
+           "gradient_pass_mlups": round(mlups, 1), "forward_s": round(t1 - t0, 4),
+           "backward_s": round(t2 - t1, 4), "plain_fp64_forward_mlups": round(fp64, 1),
+           "ratio_vs_plain_fp64": round(mlups / fp64, 3), "loss": lv, "gradient": g.tolist(),
+           "k_adj_liquid": {"avg_launch_ms": round(kern_s * 1e3, 5), "alg_bytes_per_launch": alg,
+                            "achieved_GBs": round(alg / kern_s / 1e9, 1),
+                            "frac_hbm": round(alg / kern_s / 1e9 / HBM_PEAK_GBS, 4)}}
+    if os.path.exists(ADJOINT_GOLDEN):
+        ref = json.load(open(ADJOINT_GOLDEN))
+        fd = np.array(ref["gradient"])
+        out["error_vs_oracle_fd"] = {"loss_rel": abs(lv - ref["loss"]) / abs(ref["loss"]),
+                                     "grad_rel_per_component": (np.abs(g - fd) / np.abs(fd)).tolist(),
+                                     "grad_rel_to_max": float(np.abs(g - fd).max() / np.abs(fd).max())}
+    return out
+
+
+def bench_adjoint(args):
+    leg = leg_adjoint(args)
+    out = {
+        "metric": METRIC, "value": leg["gradient_pass_mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": leg["steps"], "warmup": 0,
+        "ms_per_step": round((leg["forward_s"] + leg["backward_s"]) / leg["steps"] * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": {"workload": leg["workload"], "parallelism": "single GPU"},
+        "adjoint": leg,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def leg_precision(w, sim32, total_steps, gsteps=20):
+    """Error of the FP32 shifted path per result: on the 32 x 32 x 64 column (500 steps) against the
+    FP64 oracle itself, and on the timed workload against the FP64 GPU path (which matches the
+    oracle to 1e-12) after the same number of steps."""
+    import torch
+    import oracle as O
+    import workloads as W
+    from paper_1710_07073_amd import sim as S
+
+    def results(u, rho, x, v, sums):
+        return dict(u=u, rho=rho, x=x, v=v, sums=sums)
+
+    def compare(a, b):
+        return {"u_rel_l2": float(np.linalg.norm(a["u"] - b["u"]) / np.linalg.norm(b["u"])),
+                "rho_max_abs": float(np.abs(a["rho"] - b["rho"]).max()),
+                "bubble_pos_max_abs": float(np.abs(a["x"] - b["x"]).max()),
+                "bubble_vel_rel": float(np.abs(a["v"] - b["v"]).max() / np.abs(b["v"]).max()),
+                "mass_sum_abs": float(abs(a["sums"][0] - b["sums"][0])),
+                "momentum_sum_abs": float(np.abs(np.asarray(a["sums"][1:]) - np.asarray(b["sums"][1:])).max())}
+
+    def of_sim(sim):
+        rho, u, sums = sim.moments()
+        b = sim.bubbles
+        return results(u.double().cpu().numpy(), rho.double().cpu().numpy(),
+                       b.positions(), b.velocities(), list(sums))
+
+    small = W.plain_fp64()
+    s32 = S.Simulation(small.shape, small.omega, precision="f32", bc=small.bc)
+    s32.add_bubbles(small.pos, small.d, S.bubble_params(**small.params))
+    s32.step(small.steps)
+    r32 = of_sim(s32)
+    s32.close()
+    lat = O.Lattice(*small.shape, small.omega, small.bc)
+    bub = O.Bubbles(pos=small.pos.copy(), d=small.d.copy())
+    O.run(lat, O.bubble_params(**small.params), bub, small.steps)
+    rho, u, sums = lat.moments()
+    ro = results(u, rho, bub.pos, bub.vel, list(sums))
+    out = {"small_vs_oracle": dict(workload="32x32x64 column, one bubble d=3, 500 steps",
+                                   **compare(r32, ro))}
+    s64 = S.Simulation(w.shape, w.omega, precision="f64", bc=w.bc)
+    s64.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+    s64.run(total_steps - total_steps % gsteps, graph_steps=gsteps)
+    s64.step(total_steps % gsteps)
+    r64 = of_sim(s64)
+    s64.close()
+    out["timed_vs_fp64_gpu"] = dict(workload=f"{w.name}, {total_steps} steps", **compare(of_sim(sim32), r64))
+    return out
 
 
 def main():
@@ -154,7 +306,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="single_fp32",
-                    choices=["single_fp32", "plain_fp64", "dense", "batched"])
+                    choices=["single_fp32", "plain_fp64", "dense", "batched", "adjoint"])
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay the step loop from a HIP graph of this many steps (even)")
     ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
@@ -162,6 +314,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None, help="vec,block_x of the liquid step (skips tuning)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the batched, adjoint and precision legs of the default line")
+    ap.add_argument("--batched-steps", type=int, default=600)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()
@@ -177,6 +332,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
     w = {"single_fp32": W.single_fp32, "plain_fp64": W.plain_fp64, "dense": W.dense}[args.workload]()
     if args.precision:
         w = W.Workload(w.name.replace("fp32", args.precision).replace("fp64", args.precision),
@@ -261,7 +418,16 @@ def main():
                      "launch": launch},
         "mass_drift": sums[0] - w.cells,
     }
+    legs = args.workload == "single_fp32" and not args.no_legs and not args.precision
+    if legs:
+        print("[bench] precision leg", file=sys.stderr, flush=True)
+        out["precision"] = leg_precision(w, sim, args.warmup + K)
     sim.close()
+    if legs:
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        out["batched"] = leg_batched(args, args.batched_steps)
+        print("[bench] adjoint leg", file=sys.stderr, flush=True)
+        out["adjoint"] = leg_adjoint(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)

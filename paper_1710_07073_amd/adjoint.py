@@ -42,6 +42,8 @@ class TrajectoryProblem:
         self.K = int(checkpoint)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # when a list, backward appends a (start, end) event pair around every adjoint liquid step
+        self.liquid_events = None
 
     # ---- forward ----
     def make_sim(self, theta):
@@ -133,8 +135,15 @@ class TrajectoryProblem:
             for k in reversed(range(k0, k1)):
                 i = k - k0
                 lam_b[:, 0:3] += gt[k].t()
+                ev = None
+                if self.liquid_events is not None:
+                    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                    ev[0].record(self.stream)
                 L.lbm_adjoint_liquid(sim.ctx, _p(H[i]), _p(Fk[i]), _p(lam[cur]), _p(lam[1 - cur]),
                                      _p(lam_u), _p(lam_f), _p(grad))
+                if ev is not None:
+                    ev[1].record(self.stream)
+                    self.liquid_events.append(ev)
                 cur = 1 - cur
                 L.lbm_adjoint_bubbles(sim.ctx, sim.params, _p(rec[i]), _p(Up[i]), _p(lam_f),
                                       _p(lam_u), _p(lam_b), _p(scr), nb, _p(grad))
