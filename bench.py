@@ -314,6 +314,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None, help="vec,block_x of the liquid step (skips tuning)")
+    ap.add_argument("--layout", default="plane", choices=["plane", "soa"],
+                    help="population buffer layout: plane-blocked (default) or plain structure of arrays")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the batched, adjoint and precision legs of the default line")
     ap.add_argument("--batched-steps", type=int, default=600)
@@ -341,7 +343,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    sim = S.Simulation(w.shape, w.omega, precision=w.dtype, bc=w.bc, device=dev, stream=stream)
+    layout_flags = L.LBM_FLAG_PLAIN_SOA if args.layout == "soa" else 0
+    sim = S.Simulation(w.shape, w.omega, precision=w.dtype, bc=w.bc, flags=layout_flags, device=dev,
+                       stream=stream)
     launch = {"vec": None, "bx": None, "tuned": False}
     if args.launch:
         vec, bx = (int(v) for v in args.launch.split(","))
@@ -408,7 +412,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.shape), "cells": w.cells,
                    "omega": w.omega, "bubbles": w.nb, "bubble_diameter": float(np.median(w.d)),
-                   "populations": f"D3Q19 shifted f-w, {w.dtype}", "parallelism": "single GPU"},
+                   "populations": f"D3Q19 shifted f-w, {w.dtype}",
+                   "layout": "plane-blocked (nz,19,ny,nx)" if args.layout == "plane"
+                   else "structure of arrays (19,nz,ny,nx)", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_step (fused collide-stream)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -12,12 +12,14 @@
  *   - Lattice units: dx = dt_l = 1, liquid reference density 1. Cell (i, j, k) has its centre at
  *     (i, j, k); a non-periodic wall lies half a cell outside the outermost cells. Gravity acts
  *     along -z. Bubble sub-step dt_b = 1 / n_sub.
- *   - Populations are stored shifted by their weights, g_q = f_q - w_q, structure of arrays
- *     pop[q][z][y][x] (x fastest), q in the paper's velocity order of eq. (7): the six axis
- *     directions (+x, -x, +y, -y, +z, -z), the twelve face diagonals (+x+y, -x+y, +x-y, -x-y,
- *     +x+z, -x+z, +x-z, -x-z, +y+z, -y+z, +y-z, -y-z) and the rest particle.
- *     Vector fields are vec[a][z][y][x], a = x, y, z. Field element type is float for
- *     LBM_FP32_SHIFTED and double for LBM_FP64_SHIFTED.
+ *   - Populations are stored shifted by their weights, g_q = f_q - w_q, q in the paper's
+ *     velocity order of eq. (7): the six axis directions (+x, -x, +y, -y, +z, -z), the twelve
+ *     face diagonals (+x+y, -x+y, +x-y, -x-y, +x+z, -x+z, +x-z, -x-z, +y+z, -y+z, +y-z, -y-z) and
+ *     the rest particle. Population buffers are plane-blocked, pop[z][q][y][x] (x fastest: the
+ *     19 populations of a z-plane are 19 consecutive planes), or plain structure of arrays
+ *     pop[q][z][y][x] with LBM_FLAG_PLAIN_SOA. Exported populations (lbm_populations) are always
+ *     pop[q][z][y][x]. Vector fields are vec[a][z][y][x], a = x, y, z. Field element type is
+ *     float for LBM_FP32_SHIFTED and double for LBM_FP64_SHIFTED.
  *   - Memory: every buffer is caller-owned device memory (hipMalloc / torch allocations). The
  *     library never allocates or frees device memory; the context itself is host memory owned by
  *     the library and released by lbm_destroy().
@@ -59,7 +61,10 @@ enum {
    * steady body force, e.g. a driven channel). Not allowed together with bubbles_step(). */
   LBM_FLAG_STATIC_FORCE = 1,
   /* Write the collision velocity U in every cell, not only near bubbles. */
-  LBM_FLAG_WRITE_U_ALL = 2
+  LBM_FLAG_WRITE_U_ALL = 2,
+  /* population buffers in plain structure-of-arrays order (19, nz, ny, nx) instead of the
+   * default plane-blocked order (nz, 19, ny, nx) */
+  LBM_FLAG_PLAIN_SOA = 4
 };
 
 typedef struct {
@@ -156,11 +161,12 @@ lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* params, const bubble_
  * LBM_EDIVERGED if a sum is not finite, or a pending kernel error. */
 lbm_status moments(lbm_ctx* ctx, void* rho_out, void* u_out, double* sums_out);
 
-/* Write the current pre-collision populations g = f - w (19 x N, lattice type, the layout above)
- * into the device buffer out. */
+/* Write the current pre-collision populations g = f - w (19 x N, lattice type, plain order
+ * pop[q][z][y][x] whatever the buffer layout) into the device buffer out. */
 lbm_status lbm_populations(lbm_ctx* ctx, void* out);
 
-/* Pointer of the buffer holding the current state (post-collision, awaiting streaming). */
+/* Pointer of the buffer holding the current state (post-collision, awaiting streaming), in the
+ * context's population layout. */
 lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out);
 
 /* Synchronise the stream and report a pending kernel error (LBM_EINVAL for a bubble beyond the

@@ -53,9 +53,9 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 
 template <bool GENERAL, typename T, int... Qs>
 __device__ __forceinline__ void push_all(T* __restrict__ dst, const T* mu, const Geom& G,
-                                         uint32_t cell, const CellNbr& nb,
+                                         uint32_t lc, const CellNbr& nb,
                                          std::integer_sequence<int, Qs...>) {
-  ((dst[pull_index<Qs, GENERAL>(G, cell, nb)] = mu[Qs]), ...);
+  ((dst[pull_index<Qs, GENERAL>(G, lc, nb)] = mu[Qs]), ...);
 }
 
 template <typename T, bool GENERAL>
@@ -70,15 +70,16 @@ __global__ __launch_bounds__(256) void k_adj_liquid(const T* __restrict__ h, con
   if (cell < G.N) {
     const uint32_t x = cell % G.nx, y = (cell / G.nx) % G.ny, z = cell / G.plane;
     const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
+    const uint32_t lc = layout_cell(G, cell, z);
     T p[19], lam[19], mu[19];
-    pull_all<GENERAL>(p, h, G, cell, nb, std::make_integer_sequence<int, 19>{});
+    pull_all<GENERAL>(p, h, G, lc, nb, std::make_integer_sequence<int, 19>{});
 #pragma unroll
-    for (int q = 0; q < 19; ++q) lam[q] = lam_next[(size_t)q * G.N + cell];
+    for (int q = 0; q < 19; ++q) lam[q] = lam_next[(size_t)q * G.qs + lc];
     const T f[3] = {F[cell], F[G.N + cell], F[2 * (size_t)G.N + cell]};
     const T lu[3] = {lam_u[cell], lam_u[G.N + cell], lam_u[2 * (size_t)G.N + cell]};
     T lf[3];
     collide_cell_adjoint<T>(p, f, omega, lam, lu, mu, lf, &dom);
-    push_all<GENERAL>(lam_prev, mu, G, cell, nb, std::make_integer_sequence<int, 19>{});
+    push_all<GENERAL>(lam_prev, mu, G, lc, nb, std::make_integer_sequence<int, 19>{});
     lam_f[cell] = lf[0];
     lam_f[G.N + cell] = lf[1];
     lam_f[2 * (size_t)G.N + cell] = lf[2];

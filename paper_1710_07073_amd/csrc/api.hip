@@ -21,7 +21,7 @@ bool desc_ok(const lbm_desc* d) {
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) return false;
   if (d->precision != LBM_FP32_SHIFTED && d->precision != LBM_FP64_SHIFTED) return false;
   if (!(d->omega > 0.0 && d->omega < 2.0)) return false;
-  if (d->flags & ~(LBM_FLAG_STATIC_FORCE | LBM_FLAG_WRITE_U_ALL)) return false;
+  if (d->flags & ~(LBM_FLAG_STATIC_FORCE | LBM_FLAG_WRITE_U_ALL | LBM_FLAG_PLAIN_SOA)) return false;
   if (d->reserved != 0) return false;
   for (int a = 0; a < 3; ++a) {
     const int lo = d->bc[2 * a], hi = d->bc[2 * a + 1];
@@ -85,6 +85,7 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   G.nz = desc->nz;
   G.N = (uint32_t)desc->nx * desc->ny * desc->nz;
   G.plane = (uint32_t)desc->nx * desc->ny;
+  lbm::set_layout(G, (desc->flags & LBM_FLAG_PLAIN_SOA) != 0);
   for (int f = 0; f < 6; ++f) G.bc[f] = desc->bc[f];
   G.tnx = (int)L.tnx;
   G.tny = (int)L.tny;

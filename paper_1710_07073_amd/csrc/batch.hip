@@ -80,8 +80,9 @@ __global__ __launch_bounds__(256) void k_batch_step(const ColumnDev* __restrict_
     const uint32_t y = div_exact(rem, (uint32_t)G.nx, inv_nx);
     const uint32_t x = rem - y * G.nx;
     const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
+    const uint32_t lc = layout_cell(G, cell, z);
     T g[19];
-    pull_all<GENERAL>(g, src, G, cell, nb, std::make_integer_sequence<int, 19>{});
+    pull_all<GENERAL>(g, src, G, lc, nb, std::make_integer_sequence<int, 19>{});
     const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
     const uint32_t tile = ((z >> 3) * G.tny + (y >> 3)) * G.tnx + (x >> 3);
     bool forced = static_force;
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(256) void k_batch_step(const ColumnDev* __restrict_
       collide<T, false>(g, T(0), T(0), T(0), omega, ux, uy, uz);
     }
 #pragma unroll
-    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(g[q], &dst[(size_t)q * G.N + cell]);
+    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(g[q], &dst[(size_t)q * G.qs + lc]);
     if (forced || (flags & LBM_FLAG_WRITE_U_ALL)) {
       U[cell] = ux;
       U[G.N + cell] = uy;
@@ -124,7 +125,8 @@ __global__ __launch_bounds__(256) void k_batch_populations(const ColumnDev* __re
   const uint32_t x = cell % G.nx, y = (cell / G.nx) % G.ny, z = cell / G.plane;
   const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
   T g[19];
-  pull_all<GENERAL>(g, src, G, cell, nb, std::make_integer_sequence<int, 19>{});
+  pull_all<GENERAL>(g, src, G, layout_cell(G, cell, z), nb, std::make_integer_sequence<int, 19>{});
+  // exported in the plain (19, nz, ny, nx) order whatever the buffer layout
 #pragma unroll
   for (int q = 0; q < 19; ++q) out[(size_t)q * G.N + cell] = g[q];
 }
@@ -268,7 +270,7 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
   *out = nullptr;
   if (!cols || ncols < 1 || !pool || !scratch) return LBM_EINVAL;
   if (precision != LBM_FP32_SHIFTED && precision != LBM_FP64_SHIFTED) return LBM_EINVAL;
-  if (flags & ~(LBM_FLAG_STATIC_FORCE | LBM_FLAG_WRITE_U_ALL)) return LBM_EINVAL;
+  if (flags & ~(LBM_FLAG_STATIC_FORCE | LBM_FLAG_WRITE_U_ALL | LBM_FLAG_PLAIN_SOA)) return LBM_EINVAL;
   const size_t elem = precision == LBM_FP32_SHIFTED ? 4 : 8;
   BatchLayout L;
   if (!layout_batch(cols, ncols, elem, L)) return LBM_EINVAL;
@@ -307,6 +309,7 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
     D.G.nz = k.nz;
     D.G.N = (uint32_t)k.nx * k.ny * k.nz;
     D.G.plane = (uint32_t)k.nx * k.ny;
+    set_layout(D.G, (flags & LBM_FLAG_PLAIN_SOA) != 0);
     for (int f = 0; f < 6; ++f) {
       D.G.bc[f] = k.bc[f];
       if (k.bc[f] != LBM_BC_BOUNCE_BACK) b->general = true;

@@ -4,6 +4,9 @@
 // equilibrium (6) with BGK (14), adds the Guo force term (12), (15), and stores the 19
 // post-collision populations into the other buffer. All in shifted variables g = f - w.
 //
+// Populations are addressed through the buffer layout of Geom (layout index lc); the force and
+// velocity fields through the flat cell index.
+//
 // Memory traffic per cell: 19 loads + 19 stores of the lattice type (152 B in FP32, 304 B in
 // FP64); the force (3 loads, 3 stores to clear it) and the velocity (3 stores) are touched only in
 // 8^3 tiles flagged by the bubble kernel, whose mask is a byte per tile.
@@ -57,7 +60,7 @@ __device__ __forceinline__ void store_run(T* p, const T* in, bool nontemporal) {
 
 template <int Q, bool GENERAL, int VEC, typename T>
 __device__ __forceinline__ void pull_run(T (*g)[19], const T* __restrict__ src, const Geom& G,
-                                         uint32_t cell, const CellNbr& nb) {
+                                         uint32_t lc, const CellNbr& nb) {
   constexpr int cx = CX[Q], cy = CY[Q], cz = CZ[Q];
   int32_t off = -cx;
   bool oy = false, oz = false;
@@ -69,7 +72,7 @@ __device__ __forceinline__ void pull_run(T (*g)[19], const T* __restrict__ src, 
   off += dy + dz;
   T v[VEC];
   if (!(oy || oz)) {
-    load_run<T, VEC>(v, src + (size_t)Q * G.N + (uint32_t)((int32_t)cell + off));
+    load_run<T, VEC>(v, src + (size_t)Q * G.qs + (uint32_t)((int32_t)lc + off));
   } else {
     bool done = false;
     if constexpr (GENERAL) {
@@ -78,12 +81,12 @@ __device__ __forceinline__ void pull_run(T (*g)[19], const T* __restrict__ src, 
         const int c = a == 1 ? cy : cz;
         if (G.bc[2 * a + (c > 0 ? 0 : 1)] == BC_FS) {
           const int qm = a == 1 ? mirrored(Q, 1) : mirrored(Q, 2);
-          load_run<T, VEC>(v, src + (size_t)qm * G.N + (uint32_t)((int32_t)cell + off - (a == 1 ? dy : dz)));
+          load_run<T, VEC>(v, src + (size_t)qm * G.qs + (uint32_t)((int32_t)lc + off - (a == 1 ? dy : dz)));
           done = true;
         }
       }
     }
-    if (!done) load_run<T, VEC>(v, src + (size_t)opposite(Q) * G.N + cell);
+    if (!done) load_run<T, VEC>(v, src + (size_t)opposite(Q) * G.qs + lc);
   }
 #pragma unroll
   for (int e = 0; e < VEC; ++e) g[e][Q] = v[e];
@@ -91,9 +94,9 @@ __device__ __forceinline__ void pull_run(T (*g)[19], const T* __restrict__ src, 
 
 template <bool GENERAL, int VEC, typename T, int... Qs>
 __device__ __forceinline__ void pull_runs(T (*g)[19], const T* __restrict__ src, const Geom& G,
-                                          uint32_t cell, const CellNbr& nb,
+                                          uint32_t lc, const CellNbr& nb,
                                           std::integer_sequence<int, Qs...>) {
-  (pull_run<Qs, GENERAL, VEC>(g, src, G, cell, nb), ...);
+  (pull_run<Qs, GENERAL, VEC>(g, src, G, lc, nb), ...);
 }
 
 template <typename T, int VEC, bool GENERAL>
@@ -112,17 +115,18 @@ __global__ __launch_bounds__(256) void k_step(const T* __restrict__ src, T* __re
   const int y = (int)(byi * blockDim.y + threadIdx.y);
   if (x0 >= G.nx || y >= G.ny) return;
   const uint32_t cell = ((uint32_t)z * G.ny + y) * G.nx + x0;
+  const uint32_t lc = layout_cell(G, cell, z);
   T g[VEC][19];
   const bool xedge = VEC > 1 && (x0 == 0 || x0 + VEC == G.nx);
   if (VEC == 1 || xedge) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
       const CellNbr nb = cell_neighbours(G, x0 + e, y, (int)z);
-      pull_all<GENERAL>(g[e], src, G, cell + e, nb, std::make_integer_sequence<int, 19>{});
+      pull_all<GENERAL>(g[e], src, G, lc + e, nb, std::make_integer_sequence<int, 19>{});
     }
   } else {
     const CellNbr nb = cell_neighbours(G, x0, y, (int)z);
-    pull_runs<GENERAL, VEC>(g, src, G, cell, nb, std::make_integer_sequence<int, 19>{});
+    pull_runs<GENERAL, VEC>(g, src, G, lc, nb, std::make_integer_sequence<int, 19>{});
   }
 
   const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(256) void k_step(const T* __restrict__ src, T* __re
     T v[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) v[e] = g[e][q];
-    store_run<T, VEC>(dst + (size_t)q * G.N + cell, v, true);
+    store_run<T, VEC>(dst + (size_t)q * G.qs + lc, v, true);
   }
   if (forced || (flags & LBM_FLAG_WRITE_U_ALL)) {
     store_run<T, VEC>(U + cell, ux, false);

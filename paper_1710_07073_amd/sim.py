@@ -76,8 +76,10 @@ class Simulation:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         n = nx * ny * nz
         self.cells = n
-        self.pops = [torch.empty((19, nz, ny, nx), dtype=self.dtype, device=self.device)
-                     for _ in range(2)]
+        self.flags = int(flags)
+        # population buffers in the library's layout: plane-blocked (nz, 19, ny, nx) by default
+        pshape = (19, nz, ny, nx) if self.flags & L.LBM_FLAG_PLAIN_SOA else (nz, 19, ny, nx)
+        self.pops = [torch.empty(pshape, dtype=self.dtype, device=self.device) for _ in range(2)]
         self.force = torch.empty((3, nz, ny, nx), dtype=self.dtype, device=self.device)
         self.vel = torch.empty((3, nz, ny, nx), dtype=self.dtype, device=self.device)
         self.scratch = torch.empty(scratch_b, dtype=torch.uint8, device=self.device)
@@ -126,7 +128,8 @@ class Simulation:
 
     # ---- observables ----
     def populations(self):
-        out = torch.empty_like(self.pops[0])
+        nx, ny, nz = self.shape
+        out = torch.empty((19, nz, ny, nx), dtype=self.dtype, device=self.device)
         L.lbm_populations(self.ctx, _ptr(out))
         return out
 

@@ -34,10 +34,20 @@ def state_index(sim):
     return 0 if p == sim.pops[0].data_ptr() else 1
 
 
+def to_buffer_layout(sim, R):
+    """R (19, nz, ny, nx) in the context's population layout: plane-blocked (nz, 19, ny, nx)
+    unless the plain structure-of-arrays flag is set."""
+    R = np.asarray(R)
+    if not (sim.flags & L.LBM_FLAG_PLAIN_SOA):
+        R = R.transpose(1, 0, 2, 3)
+    return np.ascontiguousarray(R)
+
+
 def set_post_collision_state(sim, R):
     """Overwrite the GPU's current (post-collision) buffer with R (19, nz, ny, nx)."""
     k = state_index(sim)
-    sim.pops[k].copy_(torch.from_numpy(np.ascontiguousarray(R)).to(sim.dtype))
+    buf = torch.from_numpy(to_buffer_layout(sim, R)).to(sim.dtype)
+    sim.pops[k].view(-1).copy_(buf.view(-1))
     torch.cuda.synchronize()
 
 
