@@ -173,6 +173,105 @@ __global__ __launch_bounds__(256) void k_step(const T* __restrict__ src, T* __re
   }
 }
 
+// Specialisation for the case that dominates the method's columns: every face half-way
+// bounce-back, one cell per thread, population buffer below 4 GiB. The source of a population is
+// then at a fixed (uniform) offset from the destination except for lanes on a wall, so each
+// gather is a scalar base plus a 32-bit byte offset selected from two uniform values, and each
+// store (populations, velocity, force) is a scalar base plus the lane's own offset: almost no
+// per-lane address arithmetic is left beside the collision.
+// Byte offsets of every population (and field) element fit in 32 bits.
+inline bool bb_fast_ok(const Geom& G, size_t esz) {
+  return (size_t)19 * G.N * esz <= 0xffffffffull;
+}
+
+template <int Q, typename T>
+__device__ __forceinline__ T pull_bb(const char* __restrict__ sb, const Geom& G, uint32_t lc4,
+                                     uint32_t walls) {
+  constexpr int cx = CX[Q], cy = CY[Q], cz = CZ[Q];
+  // walls: bit 0 x = 0, 1 x = nx - 1, 2 y = 0, 3 y = ny - 1, 4 z = 0, 5 z = nz - 1; the source
+  // x - c lies beyond the wall at x = 0 when c_x > 0, and so on
+  constexpr uint32_t m = (cx > 0 ? 1u : 0u) | (cx < 0 ? 2u : 0u) | (cy > 0 ? 4u : 0u) |
+                         (cy < 0 ? 8u : 0u) | (cz > 0 ? 16u : 0u) | (cz < 0 ? 32u : 0u);
+  constexpr uint32_t esz = sizeof(T);
+  // byte offsets modulo 2^32; the sum with lc4 is the true offset, below 2^32
+  const uint32_t k = ((uint32_t)Q * G.qs - (uint32_t)(cx + cy * G.nx) - (uint32_t)cz * G.zs) * esz;
+  const uint32_t kb = (uint32_t)opposite(Q) * G.qs * esz;
+  const uint32_t off = lc4 + ((walls & m) ? kb : k);
+  return *reinterpret_cast<const T*>(sb + off);
+}
+
+template <typename T, int... Qs>
+__device__ __forceinline__ void pull_bb_all(T* g, const char* __restrict__ sb, const Geom& G,
+                                            uint32_t lc4, uint32_t walls,
+                                            std::integer_sequence<int, Qs...>) {
+  ((g[Qs] = pull_bb<Qs, T>(sb, G, lc4, walls)), ...);
+}
+
+template <typename T>
+__device__ __forceinline__ T* at_bytes(T* base, uint32_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* __restrict__ dst,
+                                                 T* __restrict__ F, T* __restrict__ U,
+                                                 const uint8_t* __restrict__ tiles,
+                                                 uint8_t* __restrict__ tiles_next, Geom G, T omega,
+                                                 int flags, uint32_t bx_blocks, uint32_t by_blocks,
+                                                 uint32_t nblocks) {
+  const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+  const uint32_t bxi = L % bx_blocks;
+  const uint32_t rest = L / bx_blocks;
+  const uint32_t byi = rest % by_blocks;
+  const uint32_t z = rest / by_blocks;
+  const int x = (int)(bxi * blockDim.x + threadIdx.x);
+  const int y = (int)(byi * blockDim.y + threadIdx.y);
+  if (x >= G.nx || y >= G.ny) return;
+  const uint32_t cell = ((uint32_t)z * G.ny + y) * G.nx + x;
+  constexpr uint32_t esz = sizeof(T);
+  const uint32_t lc4 = layout_cell(G, cell, z) * esz;
+  const uint32_t walls = (x == 0 ? 1u : 0u) | (x == G.nx - 1 ? 2u : 0u) | (y == 0 ? 4u : 0u) |
+                         (y == G.ny - 1 ? 8u : 0u) | (z == 0 ? 16u : 0u) |
+                         (z == (uint32_t)G.nz - 1 ? 32u : 0u);
+  T g[19];
+  pull_bb_all<T>(g, reinterpret_cast<const char*>(src), G, lc4, walls,
+                 std::make_integer_sequence<int, 19>{});
+
+  const uint32_t c4 = cell * esz;
+  const uint32_t n4 = G.N * esz;
+  const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
+  const uint32_t tile = ((z >> 3) * G.tny + ((uint32_t)y >> 3)) * G.tnx + ((uint32_t)x >> 3);
+  bool forced = static_force;
+  if (!static_force) forced = tiles[tile] != 0;
+  if (((x | y | (int)z) & 7) == 0) tiles_next[tile] = 0;
+  T ux, uy, uz;
+  if (__any(forced)) {
+    T Fx = T(0), Fy = T(0), Fz = T(0);
+    if (forced) {
+      Fx = *at_bytes(F, c4);
+      Fy = *at_bytes(F, c4 + n4);
+      Fz = *at_bytes(F, c4 + 2 * n4);
+    }
+    collide<T, true>(g, Fx, Fy, Fz, omega, ux, uy, uz);
+  } else {
+    collide<T, false>(g, T(0), T(0), T(0), omega, ux, uy, uz);
+  }
+  // one scalar base and a 32-bit offset per store (a 32-bit sum cannot be widened by the compiler)
+  const uint32_t qs4 = G.qs * esz;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(g[q], at_bytes(dst, lc4 + (uint32_t)q * qs4));
+  if (forced || (flags & LBM_FLAG_WRITE_U_ALL)) {
+    *at_bytes(U, c4) = ux;
+    *at_bytes(U, c4 + n4) = uy;
+    *at_bytes(U, c4 + 2 * n4) = uz;
+  }
+  if (forced && !static_force) {
+    *at_bytes(F, c4) = T(0);
+    *at_bytes(F, c4 + n4) = T(0);
+    *at_bytes(F, c4 + 2 * n4) = T(0);
+  }
+}
+
 template <typename T, int VEC, bool GENERAL>
 hipError_t launch_typed(lbm_ctx* c, uint32_t bx) {
   const Geom& G = c->geom;
@@ -181,6 +280,13 @@ hipError_t launch_typed(lbm_ctx* c, uint32_t bx) {
   const uint32_t nblocks = nbx * nby * (uint32_t)G.nz;
   const T* src = static_cast<const T*>(c->pops[c->cur]);
   T* dst = static_cast<T*>(c->pops[c->cur ^ 1]);
+  if (!GENERAL && VEC == 1 && bb_fast_ok(G, sizeof(T))) {
+    hipLaunchKernelGGL((k_step_bb<T>), dim3(nblocks), dim3(bx, by), 0, c->stream, src, dst,
+                       static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->flag_cur],
+                       c->tiles[c->flag_cur ^ 1], G, (T)c->desc.omega, c->desc.flags, nbx, nby,
+                       nblocks);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_step<T, VEC, GENERAL>), dim3(nblocks), dim3(bx, by), 0, c->stream, src, dst,
                      static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->flag_cur],
                      c->tiles[c->flag_cur ^ 1], G, (T)c->desc.omega, c->desc.flags, nbx, nby,
