@@ -28,7 +28,7 @@ METRIC = ("MLUPS and % HBM peak of fused step; batched and adjoint vs plain FP64
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_1710_07073_amd/csrc/step.hip", "paper_1710_07073_amd/csrc/lattice.hpp",
-                  "paper_1710_07073_amd/csrc/internal.hpp"]
+                  "paper_1710_07073_amd/csrc/internal.hpp", "paper_1710_07073_amd/csrc/collide.hpp"]
 
 
 def kernel_source_sha():
@@ -316,6 +316,8 @@ def main():
     ap.add_argument("--launch", default=None, help="vec,block_x of the liquid step (skips tuning)")
     ap.add_argument("--layout", default="plane", choices=["plane", "soa"],
                     help="population buffer layout: plane-blocked (default) or plain structure of arrays")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the bubble kernels and the liquid step one after the other")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the batched, adjoint and precision legs of the default line")
     ap.add_argument("--batched-steps", type=int, default=600)
@@ -362,6 +364,8 @@ def main():
         vec, bx = L.lbm_get_launch(sim.ctx)
         launch.update(vec=vec, bx=bx)
     sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+    if args.no_overlap:
+        L.lbm_set_overlap(sim.ctx, False)
     print(f"[bench] {w.name}: {w.cells} cells, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -374,27 +378,37 @@ def main():
     torch.cuda.synchronize()
 
     K = args.steps
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    # the library records these around the launch of the fused step that updates the lattice away
+    # from the bubbles, on the stream it runs on (the side stream when the step is overlapped)
+    # every EVERY-th launch is timed (an event record costs a queue marker of a few microseconds)
+    EVERY = 8
+    nt = (K + EVERY - 1) // EVERY
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]
+    for e in ev0 + ev1:
+        e.record(stream)  # creates the underlying HIP event
     bub = sim.bubbles
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
+        if k % EVERY == 0:
+            L.lbm_time_next_step(sim.ctx, ev0[k // EVERY], ev1[k // EVERY])
         L.bubbles_step(sim.ctx, sim.params, bub.soa, bub.nb)
-        ev0[k].record(stream)
         L.lbm_step(sim.ctx, 1)
-        ev1[k].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     step_ms = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
     kern_s = float(np.mean(step_ms)) * 1e-3
+    region_cells = L.lbm_region_cells(sim.ctx)
+    overlap_on, overlap_avail = L.lbm_get_overlap(sim.ctx)
 
     # the run stayed finite and conserved mass
     _, _, sums = sim.moments(fields=False)
     sim.check()
     elem = 4 if w.dtype == "f32" else 8
     mlups = w.cells * K / elapsed / 1e6
-    alg_bytes = 38 * elem * w.cells  # 19 loads + 19 stores per site
+    # 19 loads + 19 stores per site the launch updates (the bulk: every site outside the region)
+    alg_bytes = 38 * elem * (w.cells - region_cells)
     achieved = alg_bytes / kern_s / 1e9
     traffic = read_traffic(w.name, elem)
     out = {
@@ -415,13 +429,17 @@ def main():
                    "populations": f"D3Q19 shifted f-w, {w.dtype}",
                    "layout": "plane-blocked (nz,19,ny,nx)" if args.layout == "plane"
                    else "structure of arrays (19,nz,ny,nx)", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_step (fused collide-stream)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_step_bb (fused collide-stream, bulk launch of the overlapped step)"
+                     if region_cells else "k_step (fused collide-stream)",
+                     "sites_per_launch": w.cells - region_cells,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": round(kern_s * 1e3, 5),
-                     "kernel_mlups": round(w.cells / kern_s / 1e6, 1),
+                     "avg_launch_ms": round(kern_s * 1e3, 5), "launches_timed": nt,
+                     "kernel_mlups": round((w.cells - region_cells) / kern_s / 1e6, 1),
                      "launch": launch},
+        "overlap": {"enabled": overlap_on and overlap_avail, "region_sites_last_step": region_cells},
         "mass_drift": sums[0] - w.cells,
     }
     legs = args.workload == "single_fp32" and not args.no_legs and not args.precision

@@ -139,6 +139,32 @@ lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t vec, int32_t block_x);
 lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* vec, int32_t* block_x);
 
+/* Overlap of the bubble kernels with the liquid step, available when every face is bounce-back,
+ * the launch shape has one cell per thread and the population buffer is below 4 GiB; on by
+ * default for lattices of 2^22 cells or more, where the liquid step outlasts the bubble kernels
+ * (it costs a region launch and two cross-stream waits, about 35 us a step). With it,
+ * bubbles_step() marks the region of this step (the 8^3 tiles within the bubbles' stencil windows
+ * widened by the curl ring and two cells), runs the bubble kernels on a library-owned side stream
+ * while the liquid update of every other tile (the bulk) runs on the caller's stream, and makes the
+ * caller's stream wait for the bubble kernels; lbm_step() then updates the region. Work enqueued on
+ * the caller's stream after bubbles_step() sees the bubble results. Results are identical to the
+ * serial step bit for bit. A bubble that moves more than two cells in one step would leave the region; that
+ * is reported by lbm_check() / moments() with sums as LBM_EUNSUPPORTED. Not allowed while a
+ * bubble half awaits its lbm_step(). available (nullable) reports whether the current
+ * configuration can overlap. */
+lbm_status lbm_set_overlap(lbm_ctx* ctx, int32_t enable);
+lbm_status lbm_get_overlap(lbm_ctx* ctx, int32_t* enabled, int32_t* available);
+
+/* Timing hook for profiling: start and end (hipEvent_t, each nullable) are recorded on the
+ * caller's stream immediately before and after the next liquid launch that updates the lattice
+ * away from the bubbles (the bulk launch of an overlapped step, made by bubbles_step(), else the
+ * whole liquid step). One-shot: the events are forgotten after that launch. The caller owns the events. */
+lbm_status lbm_time_next_step(lbm_ctx* ctx, void* start, void* end);
+
+/* Cells in the region of the last overlapped step (0 if none since the last serial step); the bulk
+ * launch of that step updated the other N - cells. Synchronises the stream. */
+lbm_status lbm_region_cells(lbm_ctx* ctx, int64_t* cells);
+
 /* nsteps liquid steps (Sec. 2.2, eq. (13)-(16) with the face conditions of Sec. 3.3): first
  * forcing (13), BGK collision (14), Guo forcing (12), (15), streaming (16). Each step reads the
  * force field where bubbles have spread force (or everywhere with LBM_FLAG_STATIC_FORCE),
@@ -170,7 +196,8 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* out);
 lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out);
 
 /* Synchronise the stream and report a pending kernel error (LBM_EINVAL for a bubble beyond the
- * stencil limit), then clear it. */
+ * stencil limit, LBM_EUNSUPPORTED for a bubble that left the region of an overlapped step), then
+ * clear it. */
 lbm_status lbm_check(lbm_ctx* ctx);
 
 /* nsteps method steps (bubbles_step then lbm_step(ctx, 1), Algorithm 1) with the launches of

@@ -1,7 +1,9 @@
 // C ABI (include/lbm.h): argument checking, the context, the scratch layout and the launches.
 #include <math.h>
+#include <algorithm>
 #include <new>
 #include <string.h>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -12,7 +14,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t tiles[2], partials, result, status, total;
+  size_t tiles[2], region, region_list[2], region_count, partials, result, status, total;
   uint32_t ntiles, nred, tnx, tny, tnz;
 };
 
@@ -45,7 +47,11 @@ Layout layout_of(const lbm_desc* d) {
   if (L.nred > lbm::kRedBlocks) L.nred = lbm::kRedBlocks;
   L.tiles[0] = 0;
   L.tiles[1] = align_up(L.ntiles);
-  L.partials = align_up(L.tiles[1] + L.ntiles);
+  L.region = align_up(L.tiles[1] + L.ntiles);
+  L.region_list[0] = align_up(L.region + (size_t)L.ntiles * 4);
+  L.region_list[1] = align_up(L.region_list[0] + (size_t)L.ntiles * 4);
+  L.region_count = align_up(L.region_list[1] + (size_t)L.ntiles * 4);
+  L.partials = align_up(L.region_count + 2 * sizeof(uint32_t));
   L.result = align_up(L.partials + (size_t)L.nred * 4 * sizeof(double));
   L.status = align_up(L.result + 4 * sizeof(double));
   L.total = align_up(L.status + sizeof(int32_t));
@@ -95,22 +101,40 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->elem = desc->precision == LBM_FP32_SHIFTED ? 4 : 8;
   c->pops[0] = pops_a;
   c->pops[1] = pops_b;
-  c->cur = 0;
+  c->hs = lbm::HostState{};
+  c->hs.flag_clean[0] = c->hs.flag_clean[1] = true;
   c->force = force;
   c->vel = vel;
   uint8_t* s = static_cast<uint8_t*>(scratch);
   c->tiles[0] = s + L.tiles[0];
   c->tiles[1] = s + L.tiles[1];
-  c->flag_cur = 0;
-  c->flag_clean[0] = c->flag_clean[1] = true;
+  c->region = reinterpret_cast<uint32_t*>(s + L.region);
+  c->region_list[0] = reinterpret_cast<uint32_t*>(s + L.region_list[0]);
+  c->region_list[1] = reinterpret_cast<uint32_t*>(s + L.region_list[1]);
+  c->region_count = reinterpret_cast<uint32_t*>(s + L.region_count);
   c->ntiles = L.ntiles;
   c->partials = reinterpret_cast<double*>(s + L.partials);
   c->result = reinterpret_cast<double*>(s + L.result);
   c->status = reinterpret_cast<int32_t*>(s + L.status);
   c->nred = L.nred;
   c->stream = static_cast<hipStream_t>(stream);
-  c->steps = 0;
   lbm::default_launch(G.nx, c->elem, &c->step_vec, &c->step_bx);
+  // side stream and events of the overlapped step (default priority); without them the step
+  // runs on the caller's stream only. The events order kernels of this device only: every kernel
+  // dispatch already releases its writes and acquires at its start, so the events carry no
+  // system-scope fence of their own (a cache writeback costing about 10 us per event).
+  // on by default where the liquid step is long enough to hide the bubble kernels (its fixed cost,
+  // the region launch and the two cross-stream waits, is about 35 us per step)
+  c->overlap = G.N >= lbm::kOverlapMinCells;
+  c->side = nullptr;
+  c->t_start = c->t_end = nullptr;
+  const unsigned ev_flags = hipEventDisableTiming | hipEventDisableSystemFence;
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
+  if (c->side && (hipEventCreateWithFlags(&c->ev_fork, ev_flags) != hipSuccess ||
+                  hipEventCreateWithFlags(&c->ev_join, ev_flags) != hipSuccess)) {
+    (void)hipStreamDestroy(c->side);
+    c->side = nullptr;
+  }
   const size_t cells = G.N;
   hipError_t e = lbm::launch_fill(pops_a, 19 * cells * c->elem, c->stream);
   if (e == hipSuccess) e = lbm::launch_fill(pops_b, 19 * cells * c->elem, c->stream);
@@ -118,7 +142,7 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   if (e == hipSuccess) e = lbm::launch_fill(vel, 3 * cells * c->elem, c->stream);
   if (e == hipSuccess) e = lbm::launch_fill(scratch, L.total, c->stream);
   if (e != hipSuccess) {
-    delete c;
+    lbm_destroy(c);
     return LBM_EDEVICE;
   }
   *out = c;
@@ -126,13 +150,65 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
 }
 
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream) {
-  if (!ctx) return LBM_EINVAL;
+  if (!ctx || ctx->hs.pending) return LBM_EINVAL;
   ctx->stream = static_cast<hipStream_t>(stream);
   return LBM_OK;
 }
 
-lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t vec, int32_t block_x) {
+lbm_status lbm_set_overlap(lbm_ctx* ctx, int32_t enable) {
+  if (!ctx || ctx->hs.pending) return LBM_EINVAL;
+  ctx->overlap = enable != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_time_next_step(lbm_ctx* ctx, void* start, void* end) {
   if (!ctx) return LBM_EINVAL;
+  ctx->t_start = static_cast<hipEvent_t>(start);
+  ctx->t_end = static_cast<hipEvent_t>(end);
+  return LBM_OK;
+}
+
+lbm_status lbm_region_cells(lbm_ctx* ctx, int64_t* cells) {
+  if (!ctx || !cells) return LBM_EINVAL;
+  *cells = 0;
+  if (ctx->hs.pending) return LBM_EINVAL;
+  // the list of the last overlapped step stays until the next step of the same parity
+  const int r = ctx->hs.rpar ^ 1;
+  uint32_t count = 0;
+  if (hipMemcpyAsync(&count, ctx->region_count + r, sizeof(count), hipMemcpyDeviceToHost,
+                     ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return LBM_EDEVICE;
+  if (count > ctx->ntiles) return LBM_EDEVICE;
+  std::vector<uint32_t> list(count);
+  if (count && (hipMemcpyAsync(list.data(), ctx->region_list[r], count * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess))
+    return LBM_EDEVICE;
+  const lbm::Geom& G = ctx->geom;
+  const int kt = (int)lbm::kTile;
+  int64_t n = 0;
+  for (const uint32_t t : list) {
+    if (t >= ctx->ntiles) return LBM_EDEVICE;
+    const int tx = (int)(t % (uint32_t)G.tnx), ty = (int)((t / (uint32_t)G.tnx) % (uint32_t)G.tny);
+    const int tz = (int)(t / ((uint32_t)G.tnx * (uint32_t)G.tny));
+    const int64_t ex = std::min(kt, G.nx - tx * kt), ey = std::min(kt, G.ny - ty * kt),
+                  ez = std::min(kt, G.nz - tz * kt);
+    n += ex * ey * ez;
+  }
+  *cells = n;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_overlap(lbm_ctx* ctx, int32_t* enabled, int32_t* available) {
+  if (!ctx) return LBM_EINVAL;
+  if (enabled) *enabled = ctx->overlap ? 1 : 0;
+  if (available) *available = lbm::can_overlap(ctx) ? 1 : 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t vec, int32_t block_x) {
+  if (!ctx || ctx->hs.pending) return LBM_EINVAL;
   if (vec != 1 && vec != 2 && vec != 4) return LBM_EINVAL;
   if (block_x != 16 && block_x != 32 && block_x != 64 && block_x != 128 && block_x != 256)
     return LBM_EINVAL;
@@ -171,7 +247,9 @@ lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* 
     const bool all_psi = s->psix && s->psiy && s->psiz;
     if (any_psi && !all_psi) return LBM_EINVAL;
   }
-  return from_hip(lbm::launch_bubbles(ctx, p, s, nb));
+  if (ctx->hs.pending) return LBM_EINVAL;  // the previous bubble half still awaits its lbm_step
+  const bool overlap = ctx->overlap && nb > 0 && lbm::can_overlap(ctx);
+  return from_hip(lbm::launch_bubbles(ctx, p, s, nb, overlap));
 }
 
 lbm_status lbm_check(lbm_ctx* ctx) {
@@ -183,7 +261,7 @@ lbm_status lbm_check(lbm_ctx* ctx) {
   if (st != 0) {
     if (lbm::launch_fill(ctx->status, sizeof(int32_t) * 64, ctx->stream) != hipSuccess)
       return LBM_EDEVICE;
-    return LBM_EINVAL;
+    return (st & lbm::STATUS_STENCIL_TOO_LARGE) ? LBM_EINVAL : LBM_EUNSUPPORTED;
   }
   return LBM_OK;
 }
@@ -210,14 +288,14 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* out) {
 
 lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out) {
   if (!ctx || !out) return LBM_EINVAL;
-  *out = ctx->pops[ctx->cur];
+  *out = ctx->pops[ctx->hs.cur];
   return LBM_OK;
 }
 
 lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, int32_t nb,
                    int32_t nsteps, int32_t graph_steps) {
   if (!ctx || !p || !s || nb < 0 || nsteps < 0) return LBM_EINVAL;
-  if (graph_steps < 0 || graph_steps % 2) return LBM_EINVAL;
+  if (graph_steps < 0 || graph_steps % 2 || ctx->hs.pending) return LBM_EINVAL;
   auto one = [&]() -> lbm_status {
     lbm_status st = bubbles_step(ctx, p, s, nb);
     if (st != LBM_OK) return st;
@@ -230,12 +308,16 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, in
     }
     return LBM_OK;
   }
-  const lbm::GraphKey key = lbm::GraphKey::of(p, s, nb, ctx->cur, ctx->flag_cur, graph_steps);
   int32_t done = 0;
   while (nsteps - done >= graph_steps) {
-    const int cur0 = ctx->cur, flag0 = ctx->flag_cur;
-    const bool clean0[2] = {ctx->flag_clean[0], ctx->flag_clean[1]};
-    const int64_t steps0 = ctx->steps;
+    // the captured launches depend on the host step state (buffer and mask parities, which
+    // masks are clean, overlap): the key holds all of it, and the state after the captured
+    // steps is recorded with the graph
+    const lbm::HostState pre = ctx->hs;
+    const uint32_t mode = (pre.flag_clean[0] ? 1u : 0u) | (pre.flag_clean[1] ? 2u : 0u) |
+                          ((uint32_t)pre.rpar << 4) | (ctx->overlap ? 32u : 0u) |
+                          ((uint32_t)ctx->step_vec << 8) | (ctx->step_bx << 12);
+    const lbm::GraphKey key = lbm::GraphKey::of(p, s, nb, pre.cur, pre.flag_cur, graph_steps, mode);
     lbm_status st_cap = LBM_OK;
     bool captured = false;
     hipError_t e = ctx->graph.ensure(key, ctx->stream,
@@ -249,21 +331,10 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, in
                                      &captured);
     if (st_cap != LBM_OK) return st_cap;
     if (e != hipSuccess) return LBM_EDEVICE;
-    // the capture only recorded the launches: rewind the host-side step state, then replay
-    ctx->cur = cur0;
-    ctx->flag_cur = flag0;
-    ctx->flag_clean[0] = clean0[0];
-    ctx->flag_clean[1] = clean0[1];
-    ctx->steps = steps0;
+    if (captured) ctx->graph_post = ctx->hs;  // the capture only recorded the launches
     if (ctx->graph.launch(ctx->stream) != hipSuccess) return LBM_EDEVICE;
-    for (int i = 0; i < graph_steps; ++i) {  // advance the host state as the steps did
-      const int m = ctx->flag_cur ^ 1;
-      ctx->flag_clean[m] = false;
-      ctx->flag_cur = m;
-      ctx->cur ^= 1;
-      ctx->flag_clean[ctx->flag_cur ^ 1] = true;
-      ++ctx->steps;
-    }
+    ctx->hs = ctx->graph_post;
+    ctx->hs.steps = pre.steps + graph_steps;
     done += graph_steps;
   }
   for (int32_t i = done; i < nsteps; ++i) {
@@ -274,8 +345,17 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, in
 }
 
 lbm_status lbm_destroy(lbm_ctx* ctx) {
+  if (!ctx) return LBM_OK;
+  lbm_status st = LBM_OK;
+  if (ctx->side) {
+    // a bulk launch may still be running (bubbles_step without its lbm_step)
+    if (hipStreamSynchronize(ctx->side) != hipSuccess) st = LBM_EDEVICE;
+    (void)hipEventDestroy(ctx->ev_fork);
+    (void)hipEventDestroy(ctx->ev_join);
+    (void)hipStreamDestroy(ctx->side);
+  }
   delete ctx;
-  return LBM_OK;
+  return st;
 }
 
 const char* lbm_status_string(lbm_status status) {

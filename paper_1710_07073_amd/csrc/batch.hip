@@ -393,9 +393,10 @@ lbm_status lbm_batch_run(lbm_batch* b, const bubble_params* p, const bubble_soa*
     }
     return hipSuccess;
   };
-  const GraphKey key = GraphKey::of(p, s, nb, b->cur, b->flag_cur, graph_steps);
   int32_t done = 0;
   while (nsteps - done >= graph_steps) {
+    const uint32_t mode = (b->flag_clean[0] ? 1u : 0u) | (b->flag_clean[1] ? 2u : 0u);
+    const GraphKey key = GraphKey::of(p, s, nb, b->cur, b->flag_cur, graph_steps, mode);
     const int cur0 = b->cur, flag0 = b->flag_cur;
     const bool clean0[2] = {b->flag_clean[0], b->flag_clean[1]};
     const int64_t steps0 = b->steps;

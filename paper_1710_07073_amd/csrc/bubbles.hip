@@ -466,7 +466,52 @@ __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
           const int tx = tr[0].lo[rx] + k % nx_;
           const int ty = tr[1].lo[ry] + (k / nx_) % ny_;
           const int tz = tr[2].lo[rz] + k / (nx_ * ny_);
-          tiles[((uint32_t)tz * G.tny + ty) * G.tnx + tx] = 1;
+          const uint32_t t = ((uint32_t)tz * G.tny + ty) * G.tnx + tx;
+          tiles[t] = 1;
+          // in an overlapped step the bulk launch has updated the tiles outside the region
+          // concurrently: a tile forced or needing the velocity there is an error
+          if (col.region && !col.region[t]) atomicOr(A.status, (int32_t)STATUS_REGION_MISS);
+        }
+      }
+}
+
+// Region of an overlapped step (one wavefront per bubble): the tiles of the bubble's stencil
+// window at its current position widened by the curl ring and by kRegionMargin cells. They hold
+// every tile k_spread flags in this step (the force window at this position, the velocity window
+// at the position after the bubble update). A tile enters the list once (its flag is set by an
+// atomic exchange; the lane that finds it clear appends it).
+template <typename Geo>
+__global__ __launch_bounds__(64) void k_mark(Geo geo, BubbleArgs A, uint32_t* __restrict__ region,
+                                             uint32_t* __restrict__ list, uint32_t* __restrict__ count,
+                                             uint32_t ntiles) {
+  const int b = bubble_of_block(A.nb);
+  if (A.S.state[b] == 0) return;
+  const Geom G = geo.template view<float>(b).G;
+  const double xb[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
+  const double n = A.P.kernel_factor * A.S.d[b];
+  const int ext[3] = {G.nx, G.ny, G.nz};
+  TileRanges tr[3];
+  for (int a = 0; a < 3; ++a) {
+    const bool per = G.bc[2 * a] == BC_PER;
+    Axis w;
+    if (!axis_window(xb[a], n, ext[a], per, w)) return;  // reported by k_interp
+    tr[a] = tile_ranges(w.lo - 1 - kRegionMargin, w.hi + 1 + kRegionMargin, ext[a], (int)kTile, per);
+  }
+  for (int rz = 0; rz < tr[2].n; ++rz)
+    for (int ry = 0; ry < tr[1].n; ++ry)
+      for (int rx = 0; rx < tr[0].n; ++rx) {
+        const int nx_ = tr[0].hi[rx] - tr[0].lo[rx] + 1;
+        const int ny_ = tr[1].hi[ry] - tr[1].lo[ry] + 1;
+        const int nz_ = tr[2].hi[rz] - tr[2].lo[rz] + 1;
+        for (int k = threadIdx.x; k < nx_ * ny_ * nz_; k += 64) {
+          const int tx = tr[0].lo[rx] + k % nx_;
+          const int ty = tr[1].lo[ry] + (k / nx_) % ny_;
+          const int tz = tr[2].lo[rz] + k / (nx_ * ny_);
+          const uint32_t t = ((uint32_t)tz * G.tny + ty) * G.tnx + tx;
+          if (atomicExch(&region[t], 1u) == 0u) {
+            const uint32_t i = atomicAdd(count, 1u);
+            if (i < ntiles) list[i] = t;  // a tile is listed once per step: i < ntiles
+          }
         }
       }
 }
@@ -486,20 +531,21 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
 
 }  // namespace
 
-hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb) {
+hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb,
+                          bool overlap) {
   BubbleArgs A;
   A.P = *p;
   A.S = *s;
   A.nb = nb;
   A.status = c->status;
   // this step's mask: the one the last liquid step cleared (cleared here if no liquid step ran)
-  const int m = c->flag_cur ^ 1;
-  if (!c->flag_clean[m]) {
+  const int m = c->hs.flag_cur ^ 1;
+  if (!c->hs.flag_clean[m]) {
     const hipError_t e = launch_fill(c->tiles[m], c->ntiles, c->stream);
     if (e != hipSuccess) return e;
   }
-  c->flag_clean[m] = false;
-  c->flag_cur = m;
+  c->hs.flag_clean[m] = false;
+  c->hs.flag_cur = m;
   if (nb == 0) return hipSuccess;
   OneColumn geo;
   geo.G = c->geom;
@@ -507,6 +553,29 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
   geo.F = c->force;
   geo.tiles = c->tiles[m];
   geo.nu = (1.0 / c->desc.omega - 0.5) / 3.0;  // eq. (9), dx = dt_l = 1
+  geo.region = nullptr;
+  if (overlap) {
+    // Region of this step, then fork: the bubble kernels run on the side stream while the bulk of
+    // the liquid step runs on the caller's stream, which then waits for the bubble kernels (so
+    // that work the caller enqueues next sees their results); lbm_step() updates the region.
+    const int r = c->hs.rpar;
+    hipLaunchKernelGGL((k_mark<OneColumn>), dim3(nb), dim3(64), 0, c->stream, geo, A, c->region,
+                       c->region_list[r], c->region_count + r, c->ntiles);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    if (e != hipSuccess) return e;
+    geo.region = c->region;
+    e = c->elem == 4 ? launch_bubble_kernels<float>(geo, A, c->side)
+                     : launch_bubble_kernels<double>(geo, A, c->side);
+    if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side);
+    if (e == hipSuccess) e = launch_bulk(c);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_join, 0);
+    if (e != hipSuccess) return e;
+    c->hs.pending = true;
+    c->pending_nb = nb;
+    return hipSuccess;
+  }
   if (c->elem == 4) return launch_bubble_kernels<float>(geo, A, c->stream);
   return launch_bubble_kernels<double>(geo, A, c->stream);
 }

@@ -28,8 +28,14 @@ __device__ __forceinline__ float recip<float>(float v) {
 // BGK collision with the Guo force term, in place on the 19 shifted populations. Opposite
 // directions are handled as pairs: the equilibrium (6) and the force term (12) split into a part
 // even in c and a part odd in c. Returns the velocity of eq. (13).
+//
+// The arithmetic is written out operation by operation (contraction off, fused multiply-adds
+// explicit), so every kernel that inlines it computes the same bits whatever the surrounding code;
+// with a zero force the forced variant returns the unforced result exactly (every force term is an
+// exact zero added last), which lets kernels choose the variant per wavefront or per tile.
 template <typename T, bool FORCED>
 __device__ __forceinline__ void collide(T* g, T Fx, T Fy, T Fz, T omega, T& ux, T& uy, T& uz) {
+#pragma clang fp contract(off)
   T drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
@@ -44,24 +50,25 @@ __device__ __forceinline__ void collide(T* g, T Fx, T Fy, T Fz, T omega, T& ux, 
   const T rho = T(1) + drho;
   const T inv = recip(rho);
   if (FORCED) {
-    ux = (jx + T(0.5) * Fx) * inv;
-    uy = (jy + T(0.5) * Fy) * inv;
-    uz = (jz + T(0.5) * Fz) * inv;
+    ux = fma(T(0.5), Fx, jx) * inv;
+    uy = fma(T(0.5), Fy, jy) * inv;
+    uz = fma(T(0.5), Fz, jz) * inv;
   } else {
     ux = jx * inv;
     uy = jy * inv;
     uz = jz * inv;
   }
-  const T usq = ux * ux + uy * uy + uz * uz;
+  const T usq = fma(ux, ux, fma(uy, uy, uz * uz));
   const T om1 = T(1) - omega;
   const T pre = T(1) - T(0.5) * omega;
-  const T uF = FORCED ? (ux * Fx + uy * Fy + uz * Fz) : T(0);
+  const T uF = FORCED ? fma(ux, Fx, fma(uy, Fy, uz * Fz)) : T(0);
+  const T m15usq = T(-1.5) * usq;
   // rest particle
   {
     constexpr int q = 18;
-    const T geq = weight<T>(q) * (drho - rho * T(1.5) * usq);
-    T v = om1 * g[q] + omega * geq;
-    if (FORCED) v += pre * weight<T>(q) * (T(-3) * uF);
+    const T geq = fma(weight<T>(q) * rho, m15usq, weight<T>(q) * drho);
+    T v = fma(omega, geq, om1 * g[q]);
+    if (FORCED) v = v + pre * weight<T>(q) * (T(-3) * uF);
     g[q] = v;
   }
 #pragma unroll
@@ -70,16 +77,17 @@ __device__ __forceinline__ void collide(T* g, T Fx, T Fy, T Fz, T omega, T& ux, 
     if (qb < q) continue;  // each pair once, from its lower index
     const T cu = T(CX[q]) * ux + T(CY[q]) * uy + T(CZ[q]) * uz;
     const T w = weight<T>(q);
-    const T sym = w * (drho + rho * (T(4.5) * cu * cu - T(1.5) * usq));
-    const T asym = w * rho * T(3) * cu;
-    T vp = om1 * g[q] + omega * (sym + asym);
-    T vm = om1 * g[qb] + omega * (sym - asym);
+    // w rho and w drho are common to the pairs of one weight class
+    const T sym = fma(w * rho, fma(T(4.5) * cu, cu, m15usq), w * drho);
+    const T asym = (T(3) * w) * rho * cu;
+    T vp = fma(omega, sym + asym, om1 * g[q]);
+    T vm = fma(omega, sym - asym, om1 * g[qb]);
     if (FORCED) {
       const T cF = T(CX[q]) * Fx + T(CY[q]) * Fy + T(CZ[q]) * Fz;
-      const T ssym = pre * w * (T(9) * cu * cF - T(3) * uF);
-      const T sasym = pre * w * T(3) * cF;
-      vp += ssym + sasym;
-      vm += ssym - sasym;
+      const T ssym = pre * w * fma(T(9) * cu, cF, T(-3) * uF);
+      const T sasym = pre * (T(3) * w) * cF;
+      vp = vp + (ssym + sasym);
+      vm = vm + (ssym - sasym);
     }
     g[q] = vp;
     g[qb] = vm;

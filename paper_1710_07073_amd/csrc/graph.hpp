@@ -14,10 +14,11 @@ struct GraphKey {
   bubble_params p;
   bubble_soa s;
   int32_t nb, cur, flag, steps;
+  uint32_t mode;  // the rest of the host step state and the launch configuration
   bool valid;
 
   static GraphKey of(const bubble_params* p, const bubble_soa* s, int32_t nb, int cur, int flag,
-                     int steps) {
+                     int steps, uint32_t mode) {
     GraphKey k;
     memset(&k, 0, sizeof(k));
     if (p) memcpy(&k.p, p, sizeof(*p));
@@ -26,13 +27,14 @@ struct GraphKey {
     k.cur = cur;
     k.flag = flag;
     k.steps = steps;
+    k.mode = mode;
     k.valid = true;
     return k;
   }
   bool same(const GraphKey& o) const {
     return valid && o.valid && memcmp(&p, &o.p, sizeof(p)) == 0 &&
            memcmp(&s, &o.s, sizeof(s)) == 0 && nb == o.nb && cur == o.cur && flag == o.flag &&
-           steps == o.steps;
+           steps == o.steps && mode == o.mode;
   }
 };
 

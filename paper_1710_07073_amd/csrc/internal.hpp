@@ -10,28 +10,51 @@
 #include "graph.hpp"
 #include "lattice.hpp"
 
+namespace lbm {
+// Host-side step state of a context: which buffers and masks the next launches use.
+struct HostState {
+  int cur;                // pops[cur] holds the current post-collision state
+  int flag_cur;           // current force / velocity tile mask
+  bool flag_clean[2];     // tile mask known to be all zero
+  int rpar;               // parity of the next overlapped step (its region list and counter)
+  bool pending;           // bubbles_step() enqueued the bulk; lbm_step() must update the region
+  int64_t steps;
+};
+}  // namespace lbm
+
 struct lbm_ctx {
   lbm_desc desc;
   lbm::Geom geom;
   bool general;     // any free-slip or periodic face
   size_t elem;      // 4 or 8
-  void* pops[2];    // population buffers; pops[cur] holds the current post-collision state
-  int cur;
+  void* pops[2];    // population buffers; pops[hs.cur] holds the current post-collision state
   void* force;
   void* vel;
   // Two tile masks, one byte per 8^3 tile (force present / velocity needed). bubbles_step()
   // writes mask[flag_cur ^ 1] and makes it current; each liquid step reads mask[flag_cur] and
   // clears the other one for the next bubble step.
   uint8_t* tiles[2];
-  int flag_cur;
-  bool flag_clean[2];
+  // Region of an overlapped step: the tiles near bubbles, which the liquid step updates only after
+  // the bubble kernels; the rest of the lattice (the bulk) is updated while they run. A flag per
+  // tile (nonzero: in the region), and per step parity a compact list of the region's tiles and
+  // its length. The region launch clears the flags it used and the next parity's counter.
+  uint32_t* region;
+  uint32_t* region_list[2];
+  uint32_t* region_count;  // [2]
+  lbm::HostState hs;
+  lbm::HostState graph_post;  // host state after the captured steps of `graph`
+  bool overlap;               // overlap enabled (lbm_set_overlap)
+  hipStream_t side;           // null if it could not be created (overlap then unavailable)
+  hipEvent_t ev_fork, ev_join;
+  // caller's events recorded around the next bulk (or whole-lattice) liquid launch, one-shot
+  hipEvent_t t_start, t_end;
+  int32_t pending_nb;  // bubbles of the pending overlapped step
   uint32_t ntiles;
   double* partials; // moments reduction partials (4 doubles per block)
   double* result;   // 4 doubles
   int32_t* status;  // kernel error word
   uint32_t nred;    // number of reduction partial slots
   hipStream_t stream;
-  int64_t steps;
   int step_vec;      // cells per thread along x in the liquid step (1, 2, 4)
   uint32_t step_bx;  // threads per workgroup along x (the workgroup has 256 threads)
   lbm::StepGraph graph;  // captured method steps (lbm_run)
@@ -47,6 +70,7 @@ struct ColumnView {
   T* F;
   uint8_t* tiles;
   double nu;
+  const uint32_t* region;  // region flags of an overlapped step (tiles the spread may force), or null
 };
 
 // A single lattice (lbm_ctx).
@@ -56,9 +80,10 @@ struct OneColumn {
   void* F;
   uint8_t* tiles;
   double nu;
+  const uint32_t* region;
   template <typename T>
   __device__ ColumnView<T> view(int) const {
-    return {G, static_cast<const T*>(U), static_cast<T*>(F), tiles, nu};
+    return {G, static_cast<const T*>(U), static_cast<T*>(F), tiles, nu, region};
   }
 };
 
@@ -86,19 +111,35 @@ struct ManyColumns {
   template <typename T>
   __device__ ColumnView<T> view(int b) const {
     const ColumnDev& c = cols[bubble_col[b]];
-    return {c.G, static_cast<const T*>(c.U), static_cast<T*>(c.F), c.tiles[flag], c.nu};
+    return {c.G, static_cast<const T*>(c.U), static_cast<T*>(c.F), c.tiles[flag], c.nu, nullptr};
   }
 };
 
 constexpr uint32_t kTile = 8;
 constexpr uint32_t kRedBlocks = 1024;  // upper bound of moments reduction blocks
 
-enum : int32_t { STATUS_STENCIL_TOO_LARGE = 1 };
+enum : int32_t { STATUS_STENCIL_TOO_LARGE = 1, STATUS_REGION_MISS = 2 };
+
+// Cells the region of an overlapped step extends beyond a bubble's stencil window widened by the
+// curl ring: covers the bubble's displacement in one step.
+constexpr int kRegionMargin = 2;
+
+// Lattices from this size on overlap the bubble kernels with the liquid step by default.
+constexpr uint32_t kOverlapMinCells = 1u << 22;
+
+// Byte offsets of every population (and field) element fit in 32 bits.
+inline bool bb_fast_ok(const Geom& G, size_t esz) { return (size_t)19 * G.N * esz <= 0xffffffffull; }
 
 // step.hip
 hipError_t launch_step(lbm_ctx* c);
+// The liquid step can be split into bulk and region launches (all faces bounce-back, one cell
+// per thread, buffers below 4 GiB).
+bool can_overlap(const lbm_ctx* c);
+// Bulk part of the liquid step of an overlapped step (on the caller's stream).
+hipError_t launch_bulk(lbm_ctx* c);
 // bubbles.hip
-hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb);
+hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb,
+                          bool overlap);
 hipError_t launch_bubbles_batch(const ColumnDev* cols, const int32_t* bubble_col, int flag,
                                 size_t elem, const bubble_params* p, const bubble_soa* s,
                                 int32_t nb, int32_t* status, hipStream_t stream);

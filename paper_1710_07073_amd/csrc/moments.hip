@@ -116,7 +116,7 @@ template <typename T, bool GENERAL>
 hipError_t moments_typed(lbm_ctx* c, void* rho, void* u) {
   const uint32_t blocks = c->nred;
   hipLaunchKernelGGL((k_moments<T, GENERAL>), dim3(blocks), dim3(kThreads), 0, c->stream,
-                     static_cast<const T*>(c->pops[c->cur]), static_cast<T*>(rho),
+                     static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(rho),
                      static_cast<T*>(u), c->partials, c->geom);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -128,7 +128,7 @@ hipError_t moments_typed(lbm_ctx* c, void* rho, void* u) {
 template <typename T, bool GENERAL>
 hipError_t populations_typed(lbm_ctx* c, void* out) {
   hipLaunchKernelGGL((k_populations<T, GENERAL>), dim3(div_up(c->geom.N, kThreads)), dim3(kThreads),
-                     0, c->stream, static_cast<const T*>(c->pops[c->cur]), static_cast<T*>(out),
+                     0, c->stream, static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(out),
                      c->geom);
   return hipGetLastError();
 }

@@ -10,6 +10,7 @@
 // Memory traffic per cell: 19 loads + 19 stores of the lattice type (152 B in FP32, 304 B in
 // FP64); the force (3 loads, 3 stores to clear it) and the velocity (3 stores) are touched only in
 // 8^3 tiles flagged by the bubble kernel, whose mask is a byte per tile.
+#include <algorithm>
 #include <utility>
 
 #include "collide.hpp"
@@ -179,11 +180,6 @@ __global__ __launch_bounds__(256) void k_step(const T* __restrict__ src, T* __re
 // gather is a scalar base plus a 32-bit byte offset selected from two uniform values, and each
 // store (populations, velocity, force) is a scalar base plus the lane's own offset: almost no
 // per-lane address arithmetic is left beside the collision.
-// Byte offsets of every population (and field) element fit in 32 bits.
-inline bool bb_fast_ok(const Geom& G, size_t esz) {
-  return (size_t)19 * G.N * esz <= 0xffffffffull;
-}
-
 template <int Q, typename T>
 __device__ __forceinline__ T pull_bb(const char* __restrict__ sb, const Geom& G, uint32_t lc4,
                                      uint32_t walls) {
@@ -212,21 +208,13 @@ __device__ __forceinline__ T* at_bytes(T* base, uint32_t off) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
 }
 
+// One cell of the bounce-back fast path: gather, collision, stores. forced: the cell's tile
+// holds force (read F, write U, clear F).
 template <typename T>
-__global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* __restrict__ dst,
-                                                 T* __restrict__ F, T* __restrict__ U,
-                                                 const uint8_t* __restrict__ tiles,
-                                                 uint8_t* __restrict__ tiles_next, Geom G, T omega,
-                                                 int flags, uint32_t bx_blocks, uint32_t by_blocks,
-                                                 uint32_t nblocks) {
-  const uint32_t L = xcd_remap(blockIdx.x, nblocks);
-  const uint32_t bxi = L % bx_blocks;
-  const uint32_t rest = L / bx_blocks;
-  const uint32_t byi = rest % by_blocks;
-  const uint32_t z = rest / by_blocks;
-  const int x = (int)(bxi * blockDim.x + threadIdx.x);
-  const int y = (int)(byi * blockDim.y + threadIdx.y);
-  if (x >= G.nx || y >= G.ny) return;
+__device__ __forceinline__ void step_cell_bb(const T* __restrict__ src, T* __restrict__ dst,
+                                             T* __restrict__ F, T* __restrict__ U, const Geom& G,
+                                             T omega, int flags, int x, int y, uint32_t z,
+                                             bool forced, bool wave_forced) {
   const uint32_t cell = ((uint32_t)z * G.ny + y) * G.nx + x;
   constexpr uint32_t esz = sizeof(T);
   const uint32_t lc4 = layout_cell(G, cell, z) * esz;
@@ -236,16 +224,11 @@ __global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* _
   T g[19];
   pull_bb_all<T>(g, reinterpret_cast<const char*>(src), G, lc4, walls,
                  std::make_integer_sequence<int, 19>{});
-
   const uint32_t c4 = cell * esz;
   const uint32_t n4 = G.N * esz;
   const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
-  const uint32_t tile = ((z >> 3) * G.tny + ((uint32_t)y >> 3)) * G.tnx + ((uint32_t)x >> 3);
-  bool forced = static_force;
-  if (!static_force) forced = tiles[tile] != 0;
-  if (((x | y | (int)z) & 7) == 0) tiles_next[tile] = 0;
   T ux, uy, uz;
-  if (__any(forced)) {
+  if (wave_forced) {
     T Fx = T(0), Fy = T(0), Fz = T(0);
     if (forced) {
       Fx = *at_bytes(F, c4);
@@ -272,24 +255,89 @@ __global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* _
   }
 }
 
+// The whole lattice (region == nullptr), or the bulk of an overlapped step: every cell whose tile
+// is not in the region mask.
+template <typename T>
+__global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* __restrict__ dst,
+                                                 T* __restrict__ F, T* __restrict__ U,
+                                                 const uint8_t* __restrict__ tiles,
+                                                 uint8_t* __restrict__ tiles_next,
+                                                 const uint32_t* __restrict__ region, Geom G,
+                                                 T omega, int flags, uint32_t bx_blocks,
+                                                 uint32_t by_blocks, uint32_t nblocks) {
+  const uint32_t L = xcd_remap(blockIdx.x, nblocks);
+  const uint32_t bxi = L % bx_blocks;
+  const uint32_t rest = L / bx_blocks;
+  const uint32_t byi = rest % by_blocks;
+  const uint32_t z = rest / by_blocks;
+  const int x = (int)(bxi * blockDim.x + threadIdx.x);
+  const int y = (int)(byi * blockDim.y + threadIdx.y);
+  if (x >= G.nx || y >= G.ny) return;
+  const uint32_t tile = ((z >> 3) * G.tny + ((uint32_t)y >> 3)) * G.tnx + ((uint32_t)x >> 3);
+  if (region && region[tile]) return;  // updated by the region launch
+  const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
+  bool forced = static_force;
+  if (!static_force) forced = tiles[tile] != 0;
+  // the corner cell of each tile clears that tile in the mask of the next bubble step
+  if (((x | y | (int)z) & 7) == 0) tiles_next[tile] = 0;
+  step_cell_bb<T>(src, dst, F, U, G, omega, flags, x, y, z, forced, __any(forced));
+}
+
+// The region of an overlapped step: the tiles of its list, one workgroup per tile at a time. It
+// runs after the bulk launch and the bubble kernels; it clears the flags of its tiles and the
+// counter of the next step's list.
+template <typename T>
+__global__ __launch_bounds__(256) void k_region_bb(const T* __restrict__ src, T* __restrict__ dst,
+                                                   T* __restrict__ F, T* __restrict__ U,
+                                                   const uint8_t* __restrict__ tiles,
+                                                   uint8_t* __restrict__ tiles_next,
+                                                   uint32_t* __restrict__ region,
+                                                   const uint32_t* __restrict__ list,
+                                                   const uint32_t* __restrict__ count,
+                                                   uint32_t* __restrict__ count_next, Geom G,
+                                                   T omega, int flags, uint32_t ntiles) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *count_next = 0;
+  const uint32_t n = min(*count, ntiles);
+#pragma unroll 1
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const uint32_t tile = list[i];
+    const uint32_t tx = tile % (uint32_t)G.tnx, r = tile / (uint32_t)G.tnx;
+    const uint32_t ty = r % (uint32_t)G.tny, tz = r / (uint32_t)G.tny;
+    const bool forced = tiles[tile] != 0;  // uniform over the workgroup
+    // 512 cells, two per thread (z and z + 4)
+    const int x = (int)(tx * 8 + (threadIdx.x & 7));
+    const int y = (int)(ty * 8 + ((threadIdx.x >> 3) & 7));
+    const uint32_t z0 = tz * 8 + (threadIdx.x >> 6);
+    if (x < G.nx && y < G.ny) {
+#pragma unroll 1
+      for (uint32_t z = z0; z < tz * 8 + 8 && z < (uint32_t)G.nz; z += 4)
+        step_cell_bb<T>(src, dst, F, U, G, omega, flags, x, y, z, forced, forced);
+    }
+    if (threadIdx.x == 0) {
+      tiles_next[tile] = 0;
+      region[tile] = 0u;
+    }
+  }
+}
+
 template <typename T, int VEC, bool GENERAL>
 hipError_t launch_typed(lbm_ctx* c, uint32_t bx) {
   const Geom& G = c->geom;
   const uint32_t by = 256 / bx;
   const uint32_t nbx = div_up(G.nx / VEC, bx), nby = div_up(G.ny, by);
   const uint32_t nblocks = nbx * nby * (uint32_t)G.nz;
-  const T* src = static_cast<const T*>(c->pops[c->cur]);
-  T* dst = static_cast<T*>(c->pops[c->cur ^ 1]);
+  const T* src = static_cast<const T*>(c->pops[c->hs.cur]);
+  T* dst = static_cast<T*>(c->pops[c->hs.cur ^ 1]);
   if (!GENERAL && VEC == 1 && bb_fast_ok(G, sizeof(T))) {
     hipLaunchKernelGGL((k_step_bb<T>), dim3(nblocks), dim3(bx, by), 0, c->stream, src, dst,
-                       static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->flag_cur],
-                       c->tiles[c->flag_cur ^ 1], G, (T)c->desc.omega, c->desc.flags, nbx, nby,
-                       nblocks);
+                       static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
+                       c->tiles[c->hs.flag_cur ^ 1], nullptr, G, (T)c->desc.omega, c->desc.flags,
+                       nbx, nby, nblocks);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_step<T, VEC, GENERAL>), dim3(nblocks), dim3(bx, by), 0, c->stream, src, dst,
-                     static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->flag_cur],
-                     c->tiles[c->flag_cur ^ 1], G, (T)c->desc.omega, c->desc.flags, nbx, nby,
+                     static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
+                     c->tiles[c->hs.flag_cur ^ 1], G, (T)c->desc.omega, c->desc.flags, nbx, nby,
                      nblocks);
   return hipGetLastError();
 }
@@ -303,18 +351,77 @@ hipError_t launch_vec(lbm_ctx* c) {
   }
 }
 
+// Records the caller's timing events (if any) around one launch on stream s.
+template <class F>
+hipError_t timed(lbm_ctx* c, hipStream_t s, F&& launch) {
+  hipEvent_t a = c->t_start, b = c->t_end;
+  c->t_start = c->t_end = nullptr;
+  hipError_t e = a ? hipEventRecord(a, s) : hipSuccess;
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess && b) e = hipEventRecord(b, s);
+  return e;
+}
+
+template <typename T>
+hipError_t launch_bulk_typed(lbm_ctx* c) {
+  const Geom& G = c->geom;
+  const uint32_t bx = c->step_bx, by = 256 / bx;
+  const uint32_t nbx = div_up(G.nx, bx), nby = div_up(G.ny, by);
+  const uint32_t nblocks = nbx * nby * (uint32_t)G.nz;
+  hipLaunchKernelGGL((k_step_bb<T>), dim3(nblocks), dim3(bx, by), 0, c->stream,
+                     static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(c->pops[c->hs.cur ^ 1]),
+                     static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
+                     c->tiles[c->hs.flag_cur ^ 1], c->region, G, (T)c->desc.omega,
+                     c->desc.flags, nbx, nby, nblocks);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_region_typed(lbm_ctx* c, int32_t nb) {
+  // at most 64 tiles per bubble for the stencils this library accepts at kernel factor 1.5 and
+  // d <= 5; larger regions are strided over the grid
+  const uint32_t want = (uint32_t)std::min<int64_t>((int64_t)nb * 64, 8192);
+  const uint32_t blocks = std::max(1u, std::min(c->ntiles, want));
+  const int r = c->hs.rpar;
+  hipLaunchKernelGGL((k_region_bb<T>), dim3(blocks), dim3(256), 0, c->stream,
+                     static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(c->pops[c->hs.cur ^ 1]),
+                     static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
+                     c->tiles[c->hs.flag_cur ^ 1], c->region, c->region_list[r], c->region_count + r,
+                     c->region_count + (r ^ 1), c->geom, (T)c->desc.omega, c->desc.flags, c->ntiles);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+bool can_overlap(const lbm_ctx* c) {
+  return c->side && !c->general && c->step_vec == 1 && bb_fast_ok(c->geom, c->elem);
+}
+
+hipError_t launch_bulk(lbm_ctx* c) {
+  return timed(c, c->stream, [&] {
+    return c->elem == 4 ? launch_bulk_typed<float>(c) : launch_bulk_typed<double>(c);
+  });
+}
 
 hipError_t launch_step(lbm_ctx* c) {
   hipError_t e;
-  if (c->elem == 4)
-    e = c->general ? launch_vec<float, true>(c) : launch_vec<float, false>(c);
-  else
-    e = c->general ? launch_vec<double, true>(c) : launch_vec<double, false>(c);
+  if (c->hs.pending) {
+    // overlapped step: the bulk and the bubble kernels are enqueued; update the region
+    e = c->elem == 4 ? launch_region_typed<float>(c, c->pending_nb)
+                     : launch_region_typed<double>(c, c->pending_nb);
+    if (e != hipSuccess) return e;
+    c->hs.pending = false;
+    c->hs.rpar ^= 1;
+  } else {
+    e = timed(c, c->stream, [&] {
+      if (c->elem == 4) return c->general ? launch_vec<float, true>(c) : launch_vec<float, false>(c);
+      return c->general ? launch_vec<double, true>(c) : launch_vec<double, false>(c);
+    });
+  }
   if (e == hipSuccess) {
-    c->cur ^= 1;
-    c->flag_clean[c->flag_cur ^ 1] = true;
-    ++c->steps;
+    c->hs.cur ^= 1;
+    c->hs.flag_clean[c->hs.flag_cur ^ 1] = true;
+    ++c->hs.steps;
   }
   return e;
 }

@@ -24,6 +24,7 @@ LBM_BUBBLE_ADJ = 12
 
 # every symbol include/lbm.h declares
 EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch", "lbm_get_launch",
+           "lbm_set_overlap", "lbm_get_overlap", "lbm_time_next_step", "lbm_region_cells",
            "lbm_step", "bubbles_step",
            "moments", "lbm_populations", "lbm_state_buffer", "lbm_check", "lbm_run", "lbm_destroy",
            "lbm_status_string",
@@ -82,6 +83,10 @@ def lib():
         L.lbm_set_stream.argtypes = [P, P]
         L.lbm_set_launch.argtypes = [P, ct.c_int32, ct.c_int32]
         L.lbm_get_launch.argtypes = [P, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]
+        L.lbm_set_overlap.argtypes = [P, ct.c_int32]
+        L.lbm_time_next_step.argtypes = [P, P, P]
+        L.lbm_region_cells.argtypes = [P, ct.POINTER(ct.c_int64)]
+        L.lbm_get_overlap.argtypes = [P, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]
         L.lbm_step.argtypes = [P, ct.c_int32]
         L.bubbles_step.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32]
         L.moments.argtypes = [P, P, P, ct.POINTER(ct.c_double)]
@@ -167,6 +172,29 @@ def lbm_get_launch(ctx):
     v, b = ct.c_int32(), ct.c_int32()
     _ok(lib().lbm_get_launch(ctx, ct.byref(v), ct.byref(b)), "lbm_get_launch")
     return v.value, b.value
+
+
+def lbm_set_overlap(ctx, enable):
+    _ok(lib().lbm_set_overlap(ctx, 1 if enable else 0), "lbm_set_overlap")
+
+
+def lbm_get_overlap(ctx):
+    """(enabled, available)"""
+    e, a = ct.c_int32(), ct.c_int32()
+    _ok(lib().lbm_get_overlap(ctx, ct.byref(e), ct.byref(a)), "lbm_get_overlap")
+    return bool(e.value), bool(a.value)
+
+
+def lbm_time_next_step(ctx, start, end):
+    """start, end: torch.cuda.Event objects (already recorded once, so that they exist) or None."""
+    h = lambda e: None if e is None else ct.c_void_p(e.cuda_event)
+    _ok(lib().lbm_time_next_step(ctx, h(start), h(end)), "lbm_time_next_step")
+
+
+def lbm_region_cells(ctx):
+    n = ct.c_int64()
+    _ok(lib().lbm_region_cells(ctx, ct.byref(n)), "lbm_region_cells")
+    return n.value
 
 
 def lbm_step(ctx, nsteps=1):

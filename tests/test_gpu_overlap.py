@@ -1,0 +1,109 @@
+"""Overlapped method step (bubble kernels on the caller's stream while the liquid step updates the
+tiles away from the bubbles on a side stream): identical to the serial step bit for bit, eager and
+replayed from a HIP graph, and a bubble leaving the step's region is reported."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from paper_1710_07073_amd import lbm as L
+from paper_1710_07073_amd import sim as S
+
+BB, FS, PER = 0, 1, 2
+
+
+def _run(shape, prec, pos, d, overlap, steps, graph_steps=0, vel=None, **pkw):
+    sim = S.Simulation(shape, 1.35, precision=prec, bc=(BB,) * 6)
+    L.lbm_set_overlap(sim.ctx, overlap)
+    sim.add_bubbles(pos, d, S.bubble_params(**pkw), vel=vel)
+    if graph_steps:
+        sim.run(steps, graph_steps=graph_steps)
+    else:
+        sim.step(steps)
+    out = dict(g=sim.populations().cpu().numpy(), U=sim.vel.cpu().numpy(),
+               x=sim.bubbles.positions(), v=sim.bubbles.velocities(), st=sim.bubbles.state())
+    sim.check()
+    sim.close()
+    return out
+
+
+def _same(a, b):
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+CASES = [
+    # ragged shape (partial tiles), bubbles near the walls and close to each other
+    ((37, 29, 45), [[2.0, 18.5, 34.3], [27.2, 14.0, 3.1], [9.0, 30.5, 21.0]], [3.0, 2.5, 4.0]),
+    ((64, 64, 96), [[32.0, 31.5, 10.0, 40.0], [32.0, 33.0, 60.0, 12.0], [8.0, 8.0, 8.5, 30.0]],
+     [4.0, 4.0, 3.0, 5.0]),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("shape,pos,d", CASES)
+def test_overlapped_step_matches_serial_step(prec, shape, pos, d):
+    print(f"overlap vs serial {shape} {prec}", flush=True)
+    pos = np.array(pos, dtype=np.float64)
+    kw = dict(g=1e-4, sigma=1e-4)
+    sim = S.Simulation(shape, 1.35, precision=prec, bc=(BB,) * 6)
+    assert L.lbm_get_overlap(sim.ctx) == (False, True)  # available; off by default below 2^22 cells
+    sim.close()
+    a = _run(shape, prec, pos, d, False, 40, **kw)
+    b = _run(shape, prec, pos, d, True, 40, **kw)
+    _same(a, b)
+    assert np.abs(a["x"][2] - pos[2]).max() > 1e-3  # the bubbles moved
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_overlapped_steps_replayed_from_a_graph(prec):
+    shape, pos, d = CASES[1]
+    pos = np.array(pos, dtype=np.float64)
+    print(f"overlap graph {prec}", flush=True)
+    kw = dict(g=1e-4, sigma=1e-4)
+    eager = _run(shape, prec, pos, d, False, 26, **kw)
+    graph = _run(shape, prec, pos, d, True, 26, graph_steps=4, **kw)
+    _same(eager, graph)
+
+
+@pytest.mark.gpu
+def test_overlap_unavailable_is_the_serial_step():
+    """Periodic or free-slip faces take the general step: no overlap, and asking for it is a no-op."""
+    sim = S.Simulation((24, 24, 32), 1.2, precision="f32", bc=(PER, PER, PER, PER, BB, FS))
+    L.lbm_set_overlap(sim.ctx, True)
+    assert L.lbm_get_overlap(sim.ctx) == (True, False)
+    sim.add_bubbles(np.array([[12.0], [12.0], [8.0]]), [3.0], S.bubble_params(g=1e-4, sigma=1e-4))
+    sim.step(5)
+    sim.check()
+    sim.close()
+
+
+@pytest.mark.gpu
+def test_bubble_leaving_the_region_is_reported():
+    """A buoyancy kick moving the bubble by several cells in one step takes its next velocity
+    window out of the step's region: the step reports it (kernels run to completion). With the
+    bubble at z = 16 (d = 3) the region ends at z = 23, a tile boundary; the kick (g = 10) moves it
+    by about 3.6 cells, so its next velocity window reaches z = 25."""
+    print("region miss", flush=True)
+    P = S.bubble_params(g=10.0, sigma=1e-4)
+    nu = (1 / 1.2 - 0.5) / 3
+    x, _, _ = L.host_bubble_ode(P, nu, 3.0, np.array([12.0, 12.0, 16.0]), np.zeros(3), np.zeros(3),
+                                np.zeros(3), np.zeros(3), (24, 24, 96))
+    assert x[2] > 19.0
+    sim = S.Simulation((24, 24, 96), 1.2, precision="f32", bc=(BB,) * 6)
+    L.lbm_set_overlap(sim.ctx, True)
+    sim.add_bubbles(np.array([[12.0], [12.0], [16.0]]), [3.0], P)
+    sim.step(1)
+    with pytest.raises(L.LbmError) as e:
+        sim.check()
+    assert e.value.code == L.LBM_EUNSUPPORTED
+    sim.close()
+
+
+@pytest.mark.gpu
+def test_overlap_is_on_by_default_for_large_lattices():
+    sim = S.Simulation((128, 128, 256), 1.6, precision="f32", bc=(BB,) * 6)
+    assert L.lbm_get_overlap(sim.ctx) == (True, True)
+    sim.close()
