@@ -47,10 +47,11 @@ Layout layout_of(const lbm_desc* d) {
   if (L.nred > lbm::kRedBlocks) L.nred = lbm::kRedBlocks;
   L.tiles[0] = 0;
   L.tiles[1] = align_up(L.ntiles);
+  const size_t nrows = (size_t)L.tny * L.tnz;
   L.region = align_up(L.tiles[1] + L.ntiles);
-  L.region_list[0] = align_up(L.region + (size_t)L.ntiles * 4);
-  L.region_list[1] = align_up(L.region_list[0] + (size_t)L.ntiles * 4);
-  L.region_count = align_up(L.region_list[1] + (size_t)L.ntiles * 4);
+  L.region_list[0] = align_up(L.region + nrows * 4);
+  L.region_list[1] = align_up(L.region_list[0] + nrows * 4);
+  L.region_count = align_up(L.region_list[1] + nrows * 4);
   L.partials = align_up(L.region_count + 2 * sizeof(uint32_t));
   L.result = align_up(L.partials + (size_t)L.nred * 4 * sizeof(double));
   L.status = align_up(L.result + 4 * sizeof(double));
@@ -113,6 +114,7 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->region_list[1] = reinterpret_cast<uint32_t*>(s + L.region_list[1]);
   c->region_count = reinterpret_cast<uint32_t*>(s + L.region_count);
   c->ntiles = L.ntiles;
+  c->nrows = L.tny * L.tnz;
   c->partials = reinterpret_cast<double*>(s + L.partials);
   c->result = reinterpret_cast<double*>(s + L.result);
   c->status = reinterpret_cast<int32_t*>(s + L.status);
@@ -179,7 +181,7 @@ lbm_status lbm_region_cells(lbm_ctx* ctx, int64_t* cells) {
                      ctx->stream) != hipSuccess ||
       hipStreamSynchronize(ctx->stream) != hipSuccess)
     return LBM_EDEVICE;
-  if (count > ctx->ntiles) return LBM_EDEVICE;
+  if (count > ctx->nrows) return LBM_EDEVICE;
   std::vector<uint32_t> list(count);
   if (count && (hipMemcpyAsync(list.data(), ctx->region_list[r], count * sizeof(uint32_t),
                                hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
@@ -188,13 +190,11 @@ lbm_status lbm_region_cells(lbm_ctx* ctx, int64_t* cells) {
   const lbm::Geom& G = ctx->geom;
   const int kt = (int)lbm::kTile;
   int64_t n = 0;
-  for (const uint32_t t : list) {
-    if (t >= ctx->ntiles) return LBM_EDEVICE;
-    const int tx = (int)(t % (uint32_t)G.tnx), ty = (int)((t / (uint32_t)G.tnx) % (uint32_t)G.tny);
-    const int tz = (int)(t / ((uint32_t)G.tnx * (uint32_t)G.tny));
-    const int64_t ex = std::min(kt, G.nx - tx * kt), ey = std::min(kt, G.ny - ty * kt),
-                  ez = std::min(kt, G.nz - tz * kt);
-    n += ex * ey * ez;
+  for (const uint32_t u : list) {
+    if (u >= ctx->nrows) return LBM_EDEVICE;
+    const int ty = (int)(u % (uint32_t)G.tny), tz = (int)(u / (uint32_t)G.tny);
+    const int64_t ey = std::min(kt, G.ny - ty * kt), ez = std::min(kt, G.nz - tz * kt);
+    n += (int64_t)G.nx * ey * ez;
   }
   *cells = n;
   return LBM_OK;

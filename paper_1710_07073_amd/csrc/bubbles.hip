@@ -468,22 +468,23 @@ __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
           const int tz = tr[2].lo[rz] + k / (nx_ * ny_);
           const uint32_t t = ((uint32_t)tz * G.tny + ty) * G.tnx + tx;
           tiles[t] = 1;
-          // in an overlapped step the bulk launch has updated the tiles outside the region
+          // in an overlapped step the bulk launch has updated the rows outside the region
           // concurrently: a tile forced or needing the velocity there is an error
-          if (col.region && !col.region[t]) atomicOr(A.status, (int32_t)STATUS_REGION_MISS);
+          if (col.region && !col.region[t / (uint32_t)G.tnx])
+            atomicOr(A.status, (int32_t)STATUS_REGION_MISS);
         }
       }
 }
 
-// Region of an overlapped step (one wavefront per bubble): the tiles of the bubble's stencil
-// window at its current position widened by the curl ring and by kRegionMargin cells. They hold
-// every tile k_spread flags in this step (the force window at this position, the velocity window
-// at the position after the bubble update). A tile enters the list once (its flag is set by an
-// atomic exchange; the lane that finds it clear appends it).
+// Region of an overlapped step (one wavefront per bubble): the tile rows (y, z) of the bubble's
+// stencil window at its current position widened by the curl ring and by kRegionMargin cells.
+// They hold every tile k_spread flags in this step (the force window at this position, the
+// velocity window at the position after the bubble update). A row enters the list once (its flag
+// is set by an atomic exchange; the lane that finds it clear appends it).
 template <typename Geo>
 __global__ __launch_bounds__(64) void k_mark(Geo geo, BubbleArgs A, uint32_t* __restrict__ region,
                                              uint32_t* __restrict__ list, uint32_t* __restrict__ count,
-                                             uint32_t ntiles) {
+                                             uint32_t nrows) {
   const int b = bubble_of_block(A.nb);
   if (A.S.state[b] == 0) return;
   const Geom G = geo.template view<float>(b).G;
@@ -491,29 +492,26 @@ __global__ __launch_bounds__(64) void k_mark(Geo geo, BubbleArgs A, uint32_t* __
   const double n = A.P.kernel_factor * A.S.d[b];
   const int ext[3] = {G.nx, G.ny, G.nz};
   TileRanges tr[3];
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 1; a < 3; ++a) {
     const bool per = G.bc[2 * a] == BC_PER;
     Axis w;
     if (!axis_window(xb[a], n, ext[a], per, w)) return;  // reported by k_interp
     tr[a] = tile_ranges(w.lo - 1 - kRegionMargin, w.hi + 1 + kRegionMargin, ext[a], (int)kTile, per);
   }
   for (int rz = 0; rz < tr[2].n; ++rz)
-    for (int ry = 0; ry < tr[1].n; ++ry)
-      for (int rx = 0; rx < tr[0].n; ++rx) {
-        const int nx_ = tr[0].hi[rx] - tr[0].lo[rx] + 1;
-        const int ny_ = tr[1].hi[ry] - tr[1].lo[ry] + 1;
-        const int nz_ = tr[2].hi[rz] - tr[2].lo[rz] + 1;
-        for (int k = threadIdx.x; k < nx_ * ny_ * nz_; k += 64) {
-          const int tx = tr[0].lo[rx] + k % nx_;
-          const int ty = tr[1].lo[ry] + (k / nx_) % ny_;
-          const int tz = tr[2].lo[rz] + k / (nx_ * ny_);
-          const uint32_t t = ((uint32_t)tz * G.tny + ty) * G.tnx + tx;
-          if (atomicExch(&region[t], 1u) == 0u) {
-            const uint32_t i = atomicAdd(count, 1u);
-            if (i < ntiles) list[i] = t;  // a tile is listed once per step: i < ntiles
-          }
+    for (int ry = 0; ry < tr[1].n; ++ry) {
+      const int ny_ = tr[1].hi[ry] - tr[1].lo[ry] + 1;
+      const int nz_ = tr[2].hi[rz] - tr[2].lo[rz] + 1;
+      for (int k = threadIdx.x; k < ny_ * nz_; k += 64) {
+        const int ty = tr[1].lo[ry] + k % ny_;
+        const int tz = tr[2].lo[rz] + k / ny_;
+        const uint32_t u = (uint32_t)tz * G.tny + ty;
+        if (atomicExch(&region[u], 1u) == 0u) {
+          const uint32_t i = atomicAdd(count, 1u);
+          if (i < nrows) list[i] = u;  // a row is listed once per step: i < nrows
         }
       }
+    }
 }
 
 template <typename T, typename Geo>
@@ -560,7 +558,7 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
     // that work the caller enqueues next sees their results); lbm_step() updates the region.
     const int r = c->hs.rpar;
     hipLaunchKernelGGL((k_mark<OneColumn>), dim3(nb), dim3(64), 0, c->stream, geo, A, c->region,
-                       c->region_list[r], c->region_count + r, c->ntiles);
+                       c->region_list[r], c->region_count + r, c->nrows);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_fork, 0);

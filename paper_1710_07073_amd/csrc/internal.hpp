@@ -34,10 +34,12 @@ struct lbm_ctx {
   // writes mask[flag_cur ^ 1] and makes it current; each liquid step reads mask[flag_cur] and
   // clears the other one for the next bubble step.
   uint8_t* tiles[2];
-  // Region of an overlapped step: the tiles near bubbles, which the liquid step updates only after
-  // the bubble kernels; the rest of the lattice (the bulk) is updated while they run. A flag per
-  // tile (nonzero: in the region), and per step parity a compact list of the region's tiles and
-  // its length. The region launch clears the flags it used and the next parity's counter.
+  // Region of an overlapped step: the rows of tiles near bubbles (a row: 8 y by 8 z cells across
+  // the whole x extent, so that the region launch reads long coalesced runs like the bulk), which
+  // the liquid step updates only after the bubble kernels; the rest of the lattice (the bulk) is
+  // updated while they run. A flag per row (nonzero: in the region), and per step parity a compact
+  // list of the region's rows and its length. The region launch clears the flags it used and the
+  // next parity's counter.
   uint32_t* region;
   uint32_t* region_list[2];
   uint32_t* region_count;  // [2]
@@ -50,6 +52,7 @@ struct lbm_ctx {
   hipEvent_t t_start, t_end;
   int32_t pending_nb;  // bubbles of the pending overlapped step
   uint32_t ntiles;
+  uint32_t nrows;  // tile rows (y, z tile coordinates)
   double* partials; // moments reduction partials (4 doubles per block)
   double* result;   // 4 doubles
   int32_t* status;  // kernel error word

@@ -256,7 +256,7 @@ __device__ __forceinline__ void step_cell_bb(const T* __restrict__ src, T* __res
 }
 
 // The whole lattice (region == nullptr), or the bulk of an overlapped step: every cell whose tile
-// is not in the region mask.
+// row is not in the region.
 template <typename T>
 __global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* __restrict__ dst,
                                                  T* __restrict__ F, T* __restrict__ U,
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* _
   const int y = (int)(byi * blockDim.y + threadIdx.y);
   if (x >= G.nx || y >= G.ny) return;
   const uint32_t tile = ((z >> 3) * G.tny + ((uint32_t)y >> 3)) * G.tnx + ((uint32_t)x >> 3);
-  if (region && region[tile]) return;  // updated by the region launch
+  if (region && region[(z >> 3) * G.tny + ((uint32_t)y >> 3)]) return;  // the region launch's
   const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
   bool forced = static_force;
   if (!static_force) forced = tiles[tile] != 0;
@@ -283,9 +283,9 @@ __global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* _
   step_cell_bb<T>(src, dst, F, U, G, omega, flags, x, y, z, forced, __any(forced));
 }
 
-// The region of an overlapped step: the tiles of its list, one workgroup per tile at a time. It
-// runs after the bulk launch and the bubble kernels; it clears the flags of its tiles and the
-// counter of the next step's list.
+// The region of an overlapped step: the tile rows of its list, each cut into the same workgroups
+// as the bulk launch (bx by by cells of one z-plane). It runs after the bulk launch and the bubble
+// kernels; it clears the flags of its rows and the counter of the next step's list.
 template <typename T>
 __global__ __launch_bounds__(256) void k_region_bb(const T* __restrict__ src, T* __restrict__ dst,
                                                    T* __restrict__ F, T* __restrict__ U,
@@ -295,28 +295,28 @@ __global__ __launch_bounds__(256) void k_region_bb(const T* __restrict__ src, T*
                                                    const uint32_t* __restrict__ list,
                                                    const uint32_t* __restrict__ count,
                                                    uint32_t* __restrict__ count_next, Geom G,
-                                                   T omega, int flags, uint32_t ntiles) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *count_next = 0;
-  const uint32_t n = min(*count, ntiles);
+                                                   T omega, int flags, uint32_t nrows,
+                                                   uint32_t bx_blocks, uint32_t by_blocks) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) *count_next = 0;
+  const uint32_t n = min(*count, nrows);
+  const uint32_t per = bx_blocks * by_blocks * kTile;  // workgroups per row
 #pragma unroll 1
-  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-    const uint32_t tile = list[i];
-    const uint32_t tx = tile % (uint32_t)G.tnx, r = tile / (uint32_t)G.tnx;
-    const uint32_t ty = r % (uint32_t)G.tny, tz = r / (uint32_t)G.tny;
-    const bool forced = tiles[tile] != 0;  // uniform over the workgroup
-    // 512 cells, two per thread (z and z + 4)
-    const int x = (int)(tx * 8 + (threadIdx.x & 7));
-    const int y = (int)(ty * 8 + ((threadIdx.x >> 3) & 7));
-    const uint32_t z0 = tz * 8 + (threadIdx.x >> 6);
-    if (x < G.nx && y < G.ny) {
-#pragma unroll 1
-      for (uint32_t z = z0; z < tz * 8 + 8 && z < (uint32_t)G.nz; z += 4)
-        step_cell_bb<T>(src, dst, F, U, G, omega, flags, x, y, z, forced, forced);
+  for (uint32_t w = blockIdx.x; w < n * per; w += gridDim.x) {
+    const uint32_t u = list[w / per], sub = w % per;
+    const uint32_t bxi = sub % bx_blocks, rest = sub / bx_blocks;
+    const uint32_t byi = rest % by_blocks, zz = rest / by_blocks;
+    const uint32_t ty = u % (uint32_t)G.tny, tz = u / (uint32_t)G.tny;
+    const int x = (int)(bxi * blockDim.x + threadIdx.x);
+    const uint32_t yr = byi * blockDim.y + threadIdx.y;  // row within the tile row
+    const int y = (int)(ty * kTile + yr);
+    const uint32_t z = tz * kTile + zz;
+    if (x < G.nx && y < G.ny && yr < kTile && z < (uint32_t)G.nz) {
+      const uint32_t tile = ((z >> 3) * G.tny + ((uint32_t)y >> 3)) * G.tnx + ((uint32_t)x >> 3);
+      const bool forced = tiles[tile] != 0;
+      if (((x | y | (int)z) & 7) == 0) tiles_next[tile] = 0;
+      step_cell_bb<T>(src, dst, F, U, G, omega, flags, x, y, z, forced, __any(forced));
     }
-    if (threadIdx.x == 0) {
-      tiles_next[tile] = 0;
-      region[tile] = 0u;
-    }
+    if (sub == 0 && threadIdx.x == 0 && threadIdx.y == 0) region[u] = 0u;
   }
 }
 
@@ -378,16 +378,20 @@ hipError_t launch_bulk_typed(lbm_ctx* c) {
 
 template <typename T>
 hipError_t launch_region_typed(lbm_ctx* c, int32_t nb) {
-  // at most 64 tiles per bubble for the stencils this library accepts at kernel factor 1.5 and
-  // d <= 5; larger regions are strided over the grid
-  const uint32_t want = (uint32_t)std::min<int64_t>((int64_t)nb * 64, 8192);
-  const uint32_t blocks = std::max(1u, std::min(c->ntiles, want));
+  const Geom& G = c->geom;
+  const uint32_t bx = c->step_bx, by = 256 / bx;
+  const uint32_t bx_blocks = div_up(G.nx, bx), by_blocks = div_up(kTile, by);
+  const uint64_t per = (uint64_t)bx_blocks * by_blocks * kTile;
+  // about 16 rows per bubble for the stencils of d <= 5 at kernel factor 1.5; more are strided
+  const uint64_t rows = std::min<uint64_t>((uint64_t)nb * 16, c->nrows);
+  const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(rows * per, 16384));
   const int r = c->hs.rpar;
-  hipLaunchKernelGGL((k_region_bb<T>), dim3(blocks), dim3(256), 0, c->stream,
+  hipLaunchKernelGGL((k_region_bb<T>), dim3(blocks), dim3(bx, by), 0, c->stream,
                      static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(c->pops[c->hs.cur ^ 1]),
                      static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
                      c->tiles[c->hs.flag_cur ^ 1], c->region, c->region_list[r], c->region_count + r,
-                     c->region_count + (r ^ 1), c->geom, (T)c->desc.omega, c->desc.flags, c->ntiles);
+                     c->region_count + (r ^ 1), G, (T)c->desc.omega, c->desc.flags, c->nrows,
+                     bx_blocks, by_blocks);
   return hipGetLastError();
 }
 
