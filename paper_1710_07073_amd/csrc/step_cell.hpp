@@ -1,0 +1,92 @@
+// One cell of the fused liquid step on the bounce-back fast path, shared by the single-lattice
+// and the batched kernels (eq. (13)-(16) with half-way bounce-back on every face, Sec. 3.3).
+#pragma once
+
+#include <utility>
+
+#include "collide.hpp"
+
+namespace lbm {
+
+// Specialisation for the case that dominates the method's columns: every face half-way
+// bounce-back, one cell per thread, population buffer below 4 GiB. The source of a population is
+// then at a fixed (uniform) offset from the destination except for lanes on a wall, so each
+// gather is a scalar base plus a 32-bit byte offset selected from two uniform values, and each
+// store (populations, velocity, force) is a scalar base plus the lane's own offset: almost no
+// per-lane address arithmetic is left beside the collision.
+template <int Q, typename T>
+__device__ __forceinline__ T pull_bb(const char* __restrict__ sb, const Geom& G, uint32_t lc4,
+                                     uint32_t walls) {
+  constexpr int cx = CX[Q], cy = CY[Q], cz = CZ[Q];
+  // walls: bit 0 x = 0, 1 x = nx - 1, 2 y = 0, 3 y = ny - 1, 4 z = 0, 5 z = nz - 1; the source
+  // x - c lies beyond the wall at x = 0 when c_x > 0, and so on
+  constexpr uint32_t m = (cx > 0 ? 1u : 0u) | (cx < 0 ? 2u : 0u) | (cy > 0 ? 4u : 0u) |
+                         (cy < 0 ? 8u : 0u) | (cz > 0 ? 16u : 0u) | (cz < 0 ? 32u : 0u);
+  constexpr uint32_t esz = sizeof(T);
+  // byte offsets modulo 2^32; the sum with lc4 is the true offset, below 2^32
+  const uint32_t k = ((uint32_t)Q * G.qs - (uint32_t)(cx + cy * G.nx) - (uint32_t)cz * G.zs) * esz;
+  const uint32_t kb = (uint32_t)opposite(Q) * G.qs * esz;
+  const uint32_t off = lc4 + ((walls & m) ? kb : k);
+  return *reinterpret_cast<const T*>(sb + off);
+}
+
+template <typename T, int... Qs>
+__device__ __forceinline__ void pull_bb_all(T* g, const char* __restrict__ sb, const Geom& G,
+                                            uint32_t lc4, uint32_t walls,
+                                            std::integer_sequence<int, Qs...>) {
+  ((g[Qs] = pull_bb<Qs, T>(sb, G, lc4, walls)), ...);
+}
+
+template <typename T>
+__device__ __forceinline__ T* at_bytes(T* base, uint32_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+
+// One cell of the bounce-back fast path: gather, collision, stores. forced: the cell's tile
+// holds force (read F, write U, clear F).
+template <typename T>
+__device__ __forceinline__ void step_cell_bb(const T* __restrict__ src, T* __restrict__ dst,
+                                             T* __restrict__ F, T* __restrict__ U, const Geom& G,
+                                             T omega, int flags, int x, int y, uint32_t z,
+                                             bool forced, bool wave_forced) {
+  const uint32_t cell = ((uint32_t)z * G.ny + y) * G.nx + x;
+  constexpr uint32_t esz = sizeof(T);
+  const uint32_t lc4 = layout_cell(G, cell, z) * esz;
+  const uint32_t walls = (x == 0 ? 1u : 0u) | (x == G.nx - 1 ? 2u : 0u) | (y == 0 ? 4u : 0u) |
+                         (y == G.ny - 1 ? 8u : 0u) | (z == 0 ? 16u : 0u) |
+                         (z == (uint32_t)G.nz - 1 ? 32u : 0u);
+  T g[19];
+  pull_bb_all<T>(g, reinterpret_cast<const char*>(src), G, lc4, walls,
+                 std::make_integer_sequence<int, 19>{});
+  const uint32_t c4 = cell * esz;
+  const uint32_t n4 = G.N * esz;
+  const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
+  T ux, uy, uz;
+  if (wave_forced) {
+    T Fx = T(0), Fy = T(0), Fz = T(0);
+    if (forced) {
+      Fx = *at_bytes(F, c4);
+      Fy = *at_bytes(F, c4 + n4);
+      Fz = *at_bytes(F, c4 + 2 * n4);
+    }
+    collide<T, true>(g, Fx, Fy, Fz, omega, ux, uy, uz);
+  } else {
+    collide<T, false>(g, T(0), T(0), T(0), omega, ux, uy, uz);
+  }
+  // one scalar base and a 32-bit offset per store (a 32-bit sum cannot be widened by the compiler)
+  const uint32_t qs4 = G.qs * esz;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(g[q], at_bytes(dst, lc4 + (uint32_t)q * qs4));
+  if (forced || (flags & LBM_FLAG_WRITE_U_ALL)) {
+    *at_bytes(U, c4) = ux;
+    *at_bytes(U, c4 + n4) = uy;
+    *at_bytes(U, c4 + 2 * n4) = uz;
+  }
+  if (forced && !static_force) {
+    *at_bytes(F, c4) = T(0);
+    *at_bytes(F, c4 + n4) = T(0);
+    *at_bytes(F, c4 + 2 * n4) = T(0);
+  }
+}
+
+}  // namespace lbm
