@@ -28,7 +28,8 @@ METRIC = ("MLUPS and % HBM peak of fused step; batched and adjoint vs plain FP64
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_1710_07073_amd/csrc/step.hip", "paper_1710_07073_amd/csrc/lattice.hpp",
-                  "paper_1710_07073_amd/csrc/internal.hpp", "paper_1710_07073_amd/csrc/collide.hpp"]
+                  "paper_1710_07073_amd/csrc/internal.hpp", "paper_1710_07073_amd/csrc/collide.hpp",
+                  "paper_1710_07073_amd/csrc/step_cell.hpp"]
 
 
 def kernel_source_sha():

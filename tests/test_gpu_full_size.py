@@ -1,0 +1,47 @@
+"""The benchmark workload at its full size — 128 x 128 x 512 FP32 lattice (8.4 M sites), omega 1.6,
+bounce-back walls, one bubble of diameter 4 released at the bottom centre — in the launch
+configuration the benchmark times (one cell per thread, workgroup x-width 128, overlapped method
+step), eager and replayed from a HIP graph, against the oracle on the whole lattice."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_common import gpu_sim, oracle_state, rel_l2
+from paper_1710_07073_amd import lbm as L
+
+U_TOL = 2e-5   # FP32 shifted path, relative L2
+POS_TOL = 1e-4  # bubble position, lattice units
+
+
+@pytest.mark.gpu
+def test_single_fp32_full_size_matches_oracle():
+    w = W.single_fp32(steps=40)
+    print(f"[case] {w.name}: {w.cells} sites, 20 eager + 20 graph-replayed steps", flush=True)
+    sim = gpu_sim(w)
+    L.lbm_set_launch(sim.ctx, 1, 128)
+    assert L.lbm_get_overlap(sim.ctx) == (True, True)
+    sim.step(20)
+    sim.run(20, graph_steps=10)
+    assert L.lbm_region_cells(sim.ctx) > 0  # the last steps were overlapped
+    _, u, sums = sim.moments()
+    g = sim.populations().double().cpu().numpy()
+    u = u.double().cpu().numpy()
+    x, v = sim.bubbles.positions(), sim.bubbles.velocities()
+    sim.check()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    lat, bub, P = oracle_state(w)
+    for _ in range(w.steps):
+        O.method_step(lat, P, bub)
+    _, u_o, sums_o = lat.moments()
+    eg, eu = rel_l2(g, lat.g), rel_l2(u, u_o)
+    dx = np.abs(x - bub.pos).max()
+    print(f"rel-L2 g {eg:.2e}, u {eu:.2e}; |dx_b| {dx:.2e}; bubble z {x[2, 0]:.4f}", flush=True)
+    assert eg <= U_TOL and eu <= U_TOL
+    assert dx <= POS_TOL
+    assert np.abs(v - bub.vel).max() <= 1e-4 * np.abs(bub.vel).max()
+    assert abs(sums[0] - sums_o[0]) <= 1e-6 * w.cells
+    assert x[2, 0] > w.pos[2, 0]  # the bubble rose
