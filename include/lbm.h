@@ -195,6 +195,14 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* out);
  * context's population layout. */
 lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out);
 
+/* Rebind the context to other caller-owned buffers (each nullable: keep the current one). state:
+ * a population buffer (layout of the context) that already holds the current state; next_state:
+ * the buffer the next liquid step writes into (then the current state); vel: the velocity field
+ * the bubble half reads and the liquid step writes. Used by checkpointed recomputation to write
+ * each step's state straight into its own buffer. Not allowed while a bubble half awaits its
+ * lbm_step(); state and next_state must differ. Drops the captured lbm_run() graph. */
+lbm_status lbm_bind_buffers(lbm_ctx* ctx, void* state, void* next_state, void* vel);
+
 /* Synchronise the stream and report a pending kernel error (LBM_EINVAL for a bubble beyond the
  * stencil limit, LBM_EUNSUPPORTED for a bubble that left the region of an overlapped step), then
  * clear it. */
@@ -225,6 +233,12 @@ lbm_status lbm_destroy(lbm_ctx* ctx);
 /* Doubles per bubble of adjoint state: dL/dx[3], dL/du_b[3], dL/du_l,prev[3], unused[3]. */
 #define LBM_BUBBLE_ADJ 12
 
+/* Fill the step record (nb x LBM_BUBBLE_RECORD doubles, device) from the bubble arrays: stage 0,
+ * called before the step's bubble half, writes x, u_b, u_l,prev, state and d; stage 1, called
+ * after it, writes u_l, w_l, psi and valid from soa->work. */
+lbm_status lbm_bubble_record(lbm_ctx* ctx, const bubble_soa* soa, int32_t nb, int32_t stage,
+                             double* record);
+
 /* Adjoint of the liquid step (eq. (12)-(16), Sec. 3.3). state: the post-collision buffer before the
  * step (19 x N); force: the force field of the step (3 x N); lam_next: dL/d(state after the step);
  * lam_prev (out, every element written): dL/d(state before); lam_u (in/out): dL/dU of the step's
@@ -237,7 +251,8 @@ lbm_status lbm_adjoint_liquid(lbm_ctx* ctx, const void* state, const void* force
  * LBM_BUBBLE_RECORD doubles of the step; vel_prev: velocity field the step interpolated;
  * lam_f: dL/dF from lbm_adjoint_liquid; lam_u (out, accumulated): dL/d(vel_prev); lam: nb x
  * LBM_BUBBLE_ADJ adjoint bubble state, dL/d(state after the step) in, dL/d(state before) out;
- * scratch: nb x LBM_BUBBLE_WORK doubles. n_sub may be at most 32. */
+ * scratch: reserved (may be NULL). grad[1..3] accumulate dL/d(drag_scale), dL/d(lift_scale),
+ * dL/dnu. n_sub may be at most 32. */
 lbm_status lbm_adjoint_bubbles(lbm_ctx* ctx, const bubble_params* params, const double* record,
                                const void* vel_prev, const void* lam_f, void* lam_u, double* lam,
                                double* scratch, int32_t nb, double* grad);

@@ -64,13 +64,6 @@ class TrajectoryProblem:
         return dict(state=self.state_tensor(sim).clone(), vel=sim.vel.clone(),
                     bub={k: sim.bubbles.t[k].clone() for k in _PRE + ("state",)})
 
-    def _restore(self, sim, ck):
-        self.state_tensor(sim).copy_(ck["state"])
-        sim.vel.copy_(ck["vel"])
-        sim.force.zero_()
-        for k, v in ck["bub"].items():
-            sim.bubbles.t[k].copy_(v)
-
     def _positions(self, sim):
         t = sim.bubbles.t
         return torch.stack([t["x"], t["y"], t["z"]])
@@ -88,49 +81,46 @@ class TrajectoryProblem:
         return traj, sim, ckpts
 
     # ---- backward ----
-    def _record_pre(self, sim, rec):
-        t = sim.bubbles.t
-        for i, k in enumerate(_PRE):
-            rec[:, i] = t[k]
-        rec[:, 9] = t["state"].double()
-        rec[:, 20] = t["d"]
-
-    def _record_post(self, sim, rec):
-        w = sim.bubbles.t["work"][: self.nb * L.LBM_BUBBLE_WORK].view(self.nb, L.LBM_BUBBLE_WORK)
-        rec[:, 10:16] = w[:, 0:6]     # interpolated u_l and curl u_l
-        rec[:, 16:19] = w[:, 9:12]    # reaction psi
-        rec[:, 19] = w[:, 12]         # window valid
-
     def backward(self, theta, sim, ckpts, grad_traj):
         """dL/dtheta given dL/d(trajectory)."""
         omega = float(theta[2])
         nb, K = self.nb, self.K
-        pops = sim.pops[0]
+        pops = self.state_tensor(sim)
+        dev = self.device
         lam = [torch.zeros_like(pops), torch.zeros_like(pops)]
         lam_u = torch.zeros_like(sim.vel)
         lam_f = torch.empty_like(sim.vel)
-        lam_b = torch.zeros((nb, L.LBM_BUBBLE_ADJ), dtype=torch.float64, device=self.device)
-        scr = torch.empty((nb, L.LBM_BUBBLE_WORK), dtype=torch.float64, device=self.device)
-        grad = torch.zeros(4, dtype=torch.float64, device=self.device)
-        H = torch.empty((K,) + tuple(pops.shape), dtype=pops.dtype, device=self.device)
-        Up = torch.empty((K,) + tuple(sim.vel.shape), dtype=pops.dtype, device=self.device)
-        Fk = torch.empty_like(Up)
-        rec = torch.zeros((K, nb, L.LBM_BUBBLE_RECORD), dtype=torch.float64, device=self.device)
-        gt = grad_traj.to(self.device, torch.float64)
+        lam_b = torch.zeros((nb, L.LBM_BUBBLE_ADJ), dtype=torch.float64, device=dev)
+        grad = torch.zeros(4, dtype=torch.float64, device=dev)
+        # per step of a segment: the state entering it (H[i], the recompute writes H[i + 1]
+        # directly), the velocity field its bubble half reads (Up[i], its collision writes
+        # Up[i + 1]), its force field and its bubble record
+        H = torch.empty((K + 1,) + tuple(pops.shape), dtype=pops.dtype, device=dev)
+        Up = torch.empty((K + 1,) + tuple(sim.vel.shape), dtype=pops.dtype, device=dev)
+        Fk = torch.empty((K,) + tuple(sim.vel.shape), dtype=pops.dtype, device=dev)
+        rec = torch.zeros((K, nb, L.LBM_BUBBLE_RECORD), dtype=torch.float64, device=dev)
+        gt = grad_traj.to(dev, torch.float64)
+        # buffers are rebound between the bubble half and the liquid step: no overlapped steps
+        L.lbm_set_overlap(sim.ctx, False)
         cur = 0
         bub = sim.bubbles
         for s in reversed(range(len(ckpts))):
             k0 = s * K
             k1 = min(k0 + K, self.steps)
-            self._restore(sim, ckpts[s])
+            ck = ckpts[s]
+            H[0].copy_(ck["state"])
+            Up[0].copy_(ck["vel"])
+            sim.force.zero_()
+            for key, v in ck["bub"].items():
+                bub.t[key].copy_(v)
             for k in range(k0, k1):
                 i = k - k0
-                H[i].copy_(self.state_tensor(sim))
-                Up[i].copy_(sim.vel)
-                self._record_pre(sim, rec[i])
+                L.lbm_bind_buffers(sim.ctx, _p(H[i]), _p(H[i + 1]), _p(Up[i]))
+                L.lbm_bubble_record(sim.ctx, bub.soa, nb, 0, _p(rec[i]))
                 L.bubbles_step(sim.ctx, sim.params, bub.soa, nb)
-                self._record_post(sim, rec[i])
+                L.lbm_bubble_record(sim.ctx, bub.soa, nb, 1, _p(rec[i]))
                 Fk[i].copy_(sim.force)
+                L.lbm_bind_buffers(sim.ctx, None, None, _p(Up[i + 1]))
                 L.lbm_step(sim.ctx, 1)
             for k in reversed(range(k0, k1)):
                 i = k - k0
@@ -146,7 +136,9 @@ class TrajectoryProblem:
                     self.liquid_events.append(ev)
                 cur = 1 - cur
                 L.lbm_adjoint_bubbles(sim.ctx, sim.params, _p(rec[i]), _p(Up[i]), _p(lam_f),
-                                      _p(lam_u), _p(lam_b), _p(scr), nb, _p(grad))
+                                      _p(lam_u), _p(lam_b), None, nb, _p(grad))
+        # back to the simulation's own buffers before the segment buffers go away
+        L.lbm_bind_buffers(sim.ctx, _p(sim.pops[0]), _p(sim.pops[1]), _p(sim.vel))
         g = grad.cpu().numpy()
         # omega enters the collision directly and the bubble closures through nu = (1/omega - 1/2)/3
         return np.array([g[1], g[2], g[0] + g[3] * (-1.0 / (3.0 * omega * omega))])

@@ -7,11 +7,8 @@
 // Streaming with the face rules is a permutation of (cell, population), so the scatter writes
 // every element of the output exactly once.
 //
-// Bubble half, three kernels mirroring the forward ones:
-//   k_adj_gather   dL/dpsi = sum_j W_j dL/dF(j), and the position term of the spreading weights;
-//   k_adj_ode      reverse sweep of the sub-stepped ODE (ode_adjoint), one lane per bubble;
-//   k_adj_scatter  transpose of the interpolation: dL/dU(j) += W_j dL/du_l + curl weights . dL/dw_l
-//                  (atomic adds), and the position term of the interpolation weights.
+// Bubble half, k_adj_bubble: one workgroup per bubble runs the transposes of the three forward
+// bubble kernels in reverse order (spreading, sub-stepped ODE, interpolation).
 #include <utility>
 
 #include "adjoint_math.hpp"
@@ -27,8 +24,6 @@ constexpr int R_X = 0, R_UB = 3, R_ULP = 6, R_STATE = 9, R_UL = 10, R_WL = 13, R
               R_VALID = 19, R_D = 20, R_SIZE = LBM_BUBBLE_RECORD;
 // adjoint bubble state (doubles)
 constexpr int A_X = 0, A_UB = 3, A_ULP = 6, A_SIZE = LBM_BUBBLE_ADJ;
-// adjoint scratch between the bubble kernels (doubles)
-constexpr int S_LPSI = 0, S_GX = 3, S_LUL = 6, S_LWL = 9, S_GXODE = 12, S_FLAG = 15;
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -113,131 +108,103 @@ __device__ bool adj_weights(const Geom& G, const double* xb, double n, double (*
   return *s_ok != 0;
 }
 
+// The bubble half of the adjoint for one bubble per workgroup. Phases, separated by barriers:
+//   gather   dL/dpsi = sum_j W_j dL/dF(j), and the position term of the spreading weights;
+//   reverse  sweep of the sub-stepped ODE (ode_adjoint), one lane;
+//   scatter  transpose of the interpolation: dL/dU(j) += W_j dL/du_l + curl weights . dL/dw_l
+//            (atomic adds), and the position term of the interpolation weights.
+// The weights and their derivatives are computed once, in LDS, for both stencil phases.
 template <typename T>
-__global__ __launch_bounds__(kB) void k_adj_gather(const T* __restrict__ lam_f,
+__global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
+                                                   const T* __restrict__ U, T* __restrict__ lam_u,
                                                    const double* __restrict__ rec,
-                                                   double* __restrict__ scr, bubble_params P,
-                                                   Geom G, int nb) {
+                                                   double* __restrict__ lam, bubble_params P, Geom G,
+                                                   double nu, int nb, double* __restrict__ grad) {
   __shared__ double w[3][kAdjSpan], dw[3][kAdjSpan], wx[3][kAdjSpan], dwx[3][kAdjSpan];
   __shared__ AxisW win[3];
   __shared__ double s_red[kBW];
   __shared__ int s_ok;
+  __shared__ double s_lpsi[3], s_gx[3], s_lul[3], s_lwl[3], s_gxode[3];
   const int b = (int)xcd_remap(blockIdx.x, nb);
   const double* r = rec + (size_t)b * R_SIZE;
-  double* s = scr + (size_t)b * LBM_BUBBLE_WORK;
-  if (r[R_VALID] == 0.0) {
-    if (threadIdx.x < 6) s[S_LPSI + threadIdx.x] = 0.0;
-    return;
-  }
-  const double xb[3] = {r[R_X], r[R_X + 1], r[R_X + 2]};
-  const double psi[3] = {r[R_PSI], r[R_PSI + 1], r[R_PSI + 2]};
-  if (!adj_weights(G, xb, P.kernel_factor * r[R_D], w, dw, wx, dwx, win, &s_ok)) {
-    if (threadIdx.x < 6) s[S_LPSI + threadIdx.x] = 0.0;
-    return;
-  }
-  const int Kx = win[0].chi - win[0].clo + 1, Ky = win[1].chi - win[1].clo + 1,
-            Kz = win[2].chi - win[2].clo + 1;
-  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int f = threadIdx.x; f < Kx * Ky * Kz; f += kB) {
-    const int i = f % Kx, rr = f / Kx, j = rr % Ky, k = rr / Ky;
-    const int vx = win[0].clo + i, vy = win[1].clo + j, vz = win[2].clo + k;
-    const int ix = vx - win[0].lo + 1, iy = vy - win[1].lo + 1, iz = vz - win[2].lo + 1;
-    const int x = px ? wrapi(vx, G.nx) : vx, y = py ? wrapi(vy, G.ny) : vy,
-              z = pz ? wrapi(vz, G.nz) : vz;
-    const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
-    const double l0 = (double)lam_f[c], l1 = (double)lam_f[G.N + c],
-                 l2 = (double)lam_f[2 * (size_t)G.N + c];
-    const double a = w[0][ix], bb = w[1][iy], cc = w[2][iz];
-    const double W = a * bb * cc;
-    const double pl = psi[0] * l0 + psi[1] * l1 + psi[2] * l2;
-    acc[0] += W * l0;
-    acc[1] += W * l1;
-    acc[2] += W * l2;
-    acc[3] += wx[0][ix] * bb * cc * pl;
-    acc[4] += a * wx[1][iy] * cc * pl;
-    acc[5] += a * bb * wx[2][iz] * pl;
-  }
-  for (int m = 0; m < 6; ++m) acc[m] = bsum(acc[m], s_red);
-  if (threadIdx.x == 0)
-    for (int m = 0; m < 6; ++m) s[S_LPSI + m] = acc[m];
-}
-
-__global__ __launch_bounds__(64) void k_adj_ode(const double* __restrict__ rec,
-                                                double* __restrict__ lam, double* __restrict__ scr,
-                                                bubble_params P, Geom G, double nu, int nb,
-                                                double* __restrict__ grad) {
-  const int b = blockIdx.x * 64 + threadIdx.x;
-  double dsD = 0.0, dsL = 0.0, dnu = 0.0;
-  if (b < nb) {
-    const double* r = rec + (size_t)b * R_SIZE;
-    double* l = lam + (size_t)b * A_SIZE;
-    double* s = scr + (size_t)b * LBM_BUBBLE_WORK;
-    const int st = (int)r[R_STATE];
-    if (st == 0 || r[R_VALID] == 0.0) {
-      s[S_FLAG] = 0.0;  // frozen bubble: its adjoint state passes through unchanged
-    } else {
-      const double d = r[R_D];
-      OdeBounds Bd;
-      const int ext[3] = {G.nx, G.ny, G.nz};
-      for (int a = 0; a < 3; ++a) {
-        Bd.hi[a] = ext[a] - 1.0;
-        Bd.len[a] = G.bc[2 * a] == BC_PER ? (double)ext[a] : 0.0;
-      }
-      Bd.top = G.bc[4] != BC_PER;
-      const double* ul = r + R_UL;
-      const double* ulp = r + R_ULP;
-      double dul[3] = {0.0, 0.0, 0.0};
-      if (st == 2)
-        for (int a = 0; a < 3; ++a) dul[a] = ul[a] - ulp[a];
-      OdeAdj g;
-      ode_adjoint(P, nu, d, r + R_X, r + R_UB, ul, r + R_WL, dul, Bd, l + A_X, l + A_UB, s + S_LPSI, g);
-      for (int a = 0; a < 3; ++a) {
-        // u_l enters the drag/lift, D_t u_l = u_l - u_l,prev (state 2) and u_l,prev of the next step
-        s[S_LUL + a] = g.ul[a] + (st == 2 ? g.dul[a] : 0.0) + l[A_ULP + a];
-        s[S_LWL + a] = g.wl[a];
-        s[S_GXODE + a] = g.x[a];
-        l[A_UB + a] = g.ub[a];
-        l[A_ULP + a] = st == 2 ? -g.dul[a] : 0.0;
-      }
-      s[S_FLAG] = 1.0;
-      dsD = g.dsD;
-      dsL = g.dsL;
-      dnu = g.dnu;
-    }
-  }
-  dsD = wsum(dsD);
-  dsL = wsum(dsL);
-  dnu = wsum(dnu);
-  if (threadIdx.x == 0) {
-    atomicAdd(&grad[1], dsD);
-    atomicAdd(&grad[2], dsL);
-    atomicAdd(&grad[3], dnu);
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kB) void k_adj_scatter(const T* __restrict__ U, T* __restrict__ lam_u,
-                                                    const double* __restrict__ rec,
-                                                    double* __restrict__ lam,
-                                                    const double* __restrict__ scr, bubble_params P,
-                                                    Geom G, int nb) {
-  __shared__ double w[3][kAdjSpan], dw[3][kAdjSpan], wx[3][kAdjSpan], dwx[3][kAdjSpan];
-  __shared__ AxisW win[3];
-  __shared__ double s_red[kBW];
-  __shared__ int s_ok;
-  const int b = (int)xcd_remap(blockIdx.x, nb);
-  const double* r = rec + (size_t)b * R_SIZE;
-  const double* s = scr + (size_t)b * LBM_BUBBLE_WORK;
   double* l = lam + (size_t)b * A_SIZE;
-  if (s[S_FLAG] == 0.0) return;
+  const int st = (int)r[R_STATE];
+  // a frozen bubble (inactive, or no valid window in the step): its adjoint state passes through
+  if (st == 0 || r[R_VALID] == 0.0) return;
   const double xb[3] = {r[R_X], r[R_X + 1], r[R_X + 2]};
   if (!adj_weights(G, xb, P.kernel_factor * r[R_D], w, dw, wx, dwx, win, &s_ok)) return;
-  const double lu[3] = {s[S_LUL], s[S_LUL + 1], s[S_LUL + 2]};
-  const double lw[3] = {s[S_LWL], s[S_LWL + 1], s[S_LWL + 2]};
+  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+
+  // gather
+  {
+    const double psi[3] = {r[R_PSI], r[R_PSI + 1], r[R_PSI + 2]};
+    const int Kx = win[0].chi - win[0].clo + 1, Ky = win[1].chi - win[1].clo + 1,
+              Kz = win[2].chi - win[2].clo + 1;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int f = threadIdx.x; f < Kx * Ky * Kz; f += kB) {
+      const int i = f % Kx, rr = f / Kx, j = rr % Ky, k = rr / Ky;
+      const int vx = win[0].clo + i, vy = win[1].clo + j, vz = win[2].clo + k;
+      const int ix = vx - win[0].lo + 1, iy = vy - win[1].lo + 1, iz = vz - win[2].lo + 1;
+      const int x = px ? wrapi(vx, G.nx) : vx, y = py ? wrapi(vy, G.ny) : vy,
+                z = pz ? wrapi(vz, G.nz) : vz;
+      const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
+      const double l0 = (double)lam_f[c], l1 = (double)lam_f[G.N + c],
+                   l2 = (double)lam_f[2 * (size_t)G.N + c];
+      const double a = w[0][ix], bb = w[1][iy], cc = w[2][iz];
+      const double W = a * bb * cc;
+      const double pl = psi[0] * l0 + psi[1] * l1 + psi[2] * l2;
+      acc[0] += W * l0;
+      acc[1] += W * l1;
+      acc[2] += W * l2;
+      acc[3] += wx[0][ix] * bb * cc * pl;
+      acc[4] += a * wx[1][iy] * cc * pl;
+      acc[5] += a * bb * wx[2][iz] * pl;
+    }
+    for (int m = 0; m < 6; ++m) acc[m] = bsum(acc[m], s_red);
+    if (threadIdx.x == 0)
+      for (int m = 0; m < 3; ++m) {
+        s_lpsi[m] = acc[m];
+        s_gx[m] = acc[3 + m];
+      }
+  }
+  __syncthreads();
+
+  // reverse sweep of the sub-steps
+  if (threadIdx.x == 0) {
+    OdeBounds Bd;
+    const int ext[3] = {G.nx, G.ny, G.nz};
+    for (int a = 0; a < 3; ++a) {
+      Bd.hi[a] = ext[a] - 1.0;
+      Bd.len[a] = G.bc[2 * a] == BC_PER ? (double)ext[a] : 0.0;
+    }
+    Bd.top = G.bc[4] != BC_PER;
+    const double* ul = r + R_UL;
+    const double* ulp = r + R_ULP;
+    double dul[3] = {0.0, 0.0, 0.0};
+    if (st == 2)
+      for (int a = 0; a < 3; ++a) dul[a] = ul[a] - ulp[a];
+    OdeAdj g;
+    ode_adjoint(P, nu, r[R_D], r + R_X, r + R_UB, ul, r + R_WL, dul, Bd, l + A_X, l + A_UB, s_lpsi,
+                g);
+    for (int a = 0; a < 3; ++a) {
+      // u_l enters the drag/lift, D_t u_l = u_l - u_l,prev (state 2) and u_l,prev of the next step
+      s_lul[a] = g.ul[a] + (st == 2 ? g.dul[a] : 0.0) + l[A_ULP + a];
+      s_lwl[a] = g.wl[a];
+      s_gxode[a] = g.x[a];
+      l[A_UB + a] = g.ub[a];
+      l[A_ULP + a] = st == 2 ? -g.dul[a] : 0.0;
+    }
+    atomicAdd(&grad[1], g.dsD);
+    atomicAdd(&grad[2], g.dsL);
+    atomicAdd(&grad[3], g.dnu);
+  }
+  __syncthreads();
+
+  // scatter
+  const double lu[3] = {s_lul[0], s_lul[1], s_lul[2]};
+  const double lw[3] = {s_lwl[0], s_lwl[1], s_lwl[2]};
   const int Dx = win[0].dhi - win[0].dlo + 1, Dy = win[1].dhi - win[1].dlo + 1,
             Dz = win[2].dhi - win[2].dlo + 1;
-  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
   double gx[3] = {0, 0, 0};
   for (int f = threadIdx.x; f < Dx * Dy * Dz; f += kB) {
     const int i = f % Dx, rr = f / Dx, j = rr % Dy, k = rr / Dy;
@@ -282,7 +249,34 @@ __global__ __launch_bounds__(kB) void k_adj_scatter(const T* __restrict__ U, T* 
   }
   for (int m = 0; m < 3; ++m) gx[m] = bsum(gx[m], s_red);
   if (threadIdx.x == 0)
-    for (int a = 0; a < 3; ++a) l[A_X + a] = s[S_GXODE + a] + s[S_GX + a] + gx[a];
+    for (int a = 0; a < 3; ++a) l[A_X + a] = s_gxode[a] + s_gx[a] + gx[a];
+}
+
+// Step record of every bubble (one lane per bubble): stage 0, before the step's bubble half, takes
+// x, u_b, u_l,prev, state and d from the bubble arrays; stage 1, after it, takes u_l, w_l, psi and
+// the window flag from the bubble workspace.
+__global__ __launch_bounds__(64) void k_record(bubble_soa S, int nb, int stage, double* __restrict__ rec) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (b >= nb) return;
+  double* r = rec + (size_t)b * R_SIZE;
+  if (stage == 0) {
+    r[R_X] = S.x[b];
+    r[R_X + 1] = S.y[b];
+    r[R_X + 2] = S.z[b];
+    r[R_UB] = S.ux[b];
+    r[R_UB + 1] = S.uy[b];
+    r[R_UB + 2] = S.uz[b];
+    r[R_ULP] = S.ulx[b];
+    r[R_ULP + 1] = S.uly[b];
+    r[R_ULP + 2] = S.ulz[b];
+    r[R_STATE] = (double)S.state[b];
+    r[R_D] = S.d[b];
+  } else {
+    const double* wk = S.work + (size_t)b * LBM_BUBBLE_WORK;
+    for (int m = 0; m < 6; ++m) r[R_UL + m] = wk[W_UL + m];  // u_l then w_l
+    for (int m = 0; m < 3; ++m) r[R_PSI + m] = wk[W_PSI + m];
+    r[R_VALID] = wk[W_VALID];
+  }
 }
 
 template <typename T, bool GENERAL>
@@ -298,20 +292,11 @@ hipError_t liquid_typed(lbm_ctx* c, const void* state, const void* force, const 
 
 template <typename T>
 hipError_t bubbles_typed(lbm_ctx* c, const bubble_params* p, const double* rec, const void* vel_prev,
-                         const void* lam_f, void* lam_u, double* lam, double* scr, int32_t nb,
-                         double* grad) {
+                         const void* lam_f, void* lam_u, double* lam, int32_t nb, double* grad) {
   const double nu = (1.0 / c->desc.omega - 0.5) / 3.0;
-  hipLaunchKernelGGL((k_adj_gather<T>), dim3(nb), dim3(kB), 0, c->stream,
-                     static_cast<const T*>(lam_f), rec, scr, *p, c->geom, nb);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_ode, dim3(div_up(nb, 64)), dim3(64), 0, c->stream, rec, lam, scr, *p,
-                     c->geom, nu, nb, grad);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_adj_scatter<T>), dim3(nb), dim3(kB), 0, c->stream,
-                     static_cast<const T*>(vel_prev), static_cast<T*>(lam_u), rec, lam, scr, *p,
-                     c->geom, nb);
+  hipLaunchKernelGGL((k_adj_bubble<T>), dim3(nb), dim3(kB), 0, c->stream,
+                     static_cast<const T*>(lam_f), static_cast<const T*>(vel_prev),
+                     static_cast<T*>(lam_u), rec, lam, *p, c->geom, nu, nb, grad);
   return hipGetLastError();
 }
 
@@ -343,12 +328,27 @@ lbm_status lbm_adjoint_bubbles(lbm_ctx* ctx, const bubble_params* p, const doubl
                                double* scratch, int32_t nb, double* grad) {
   if (!ctx || !p || nb < 0 || !grad) return LBM_EINVAL;
   if (nb == 0) return LBM_OK;
-  if (!record || !vel_prev || !lam_f || !lam_u || !lam || !scratch) return LBM_EINVAL;
+  (void)scratch;  // reserved
+  if (!record || !vel_prev || !lam_f || !lam_u || !lam) return LBM_EINVAL;
   if (p->n_sub < 1 || p->n_sub > kMaxSub || p->reserved != 0) return LBM_EINVAL;
   const hipError_t e =
-      ctx->elem == 4 ? bubbles_typed<float>(ctx, p, record, vel_prev, lam_f, lam_u, lam, scratch, nb, grad)
-                     : bubbles_typed<double>(ctx, p, record, vel_prev, lam_f, lam_u, lam, scratch, nb, grad);
+      ctx->elem == 4 ? bubbles_typed<float>(ctx, p, record, vel_prev, lam_f, lam_u, lam, nb, grad)
+                     : bubbles_typed<double>(ctx, p, record, vel_prev, lam_f, lam_u, lam, nb, grad);
   return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+lbm_status lbm_bubble_record(lbm_ctx* ctx, const bubble_soa* soa, int32_t nb, int32_t stage,
+                             double* record) {
+  if (!ctx || !soa || nb < 0 || (stage != 0 && stage != 1)) return LBM_EINVAL;
+  if (nb == 0) return LBM_OK;
+  if (!record) return LBM_EINVAL;
+  if (stage == 0 && (!soa->x || !soa->y || !soa->z || !soa->ux || !soa->uy || !soa->uz ||
+                     !soa->ulx || !soa->uly || !soa->ulz || !soa->state || !soa->d))
+    return LBM_EINVAL;
+  if (stage == 1 && !soa->work) return LBM_EINVAL;
+  hipLaunchKernelGGL(k_record, dim3(div_up((uint32_t)nb, 64)), dim3(64), 0, ctx->stream, *soa, nb,
+                     stage, record);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }
 
 // ---- host evaluation of the same arithmetic (for checks on a CPU) ----

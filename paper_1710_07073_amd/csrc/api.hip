@@ -286,6 +286,18 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* out) {
   return from_hip(lbm::launch_populations(ctx, out));
 }
 
+lbm_status lbm_bind_buffers(lbm_ctx* ctx, void* state, void* next_state, void* vel) {
+  if (!ctx || ctx->hs.pending) return LBM_EINVAL;
+  void* cur = state ? state : ctx->pops[ctx->hs.cur];
+  void* nxt = next_state ? next_state : ctx->pops[ctx->hs.cur ^ 1];
+  if (cur == nxt) return LBM_EINVAL;
+  ctx->pops[ctx->hs.cur] = cur;
+  ctx->pops[ctx->hs.cur ^ 1] = nxt;
+  if (vel) ctx->vel = vel;
+  ctx->graph.reset();  // captured launches name the old buffers
+  return LBM_OK;
+}
+
 lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out) {
   if (!ctx || !out) return LBM_EINVAL;
   *out = ctx->pops[ctx->hs.cur];

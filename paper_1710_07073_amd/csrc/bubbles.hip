@@ -27,8 +27,6 @@ constexpr int kSpan = kMax + 2;        // window widened by one cell on each sid
 constexpr int kWork = LBM_BUBBLE_WORK; // doubles of per-bubble workspace
 constexpr int kBlock = 256;            // threads per bubble in the stencil kernels
 constexpr int kBlockWaves = kBlock / 64;
-// workspace slots
-constexpr int W_UL = 0, W_WL = 3, W_X0 = 6, W_PSI = 9, W_VALID = 12;
 
 struct BubbleArgs {
   bubble_params P;

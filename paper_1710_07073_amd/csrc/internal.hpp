@@ -119,6 +119,10 @@ struct ManyColumns {
 };
 
 constexpr uint32_t kTile = 8;
+
+// Slots of the per-bubble workspace (bubble_soa.work) the bubble kernels pass between them:
+// interpolated u_l and curl w_l, position at interpolation, reaction psi, window valid.
+constexpr int W_UL = 0, W_WL = 3, W_X0 = 6, W_PSI = 9, W_VALID = 12;
 constexpr uint32_t kRedBlocks = 1024;  // upper bound of moments reduction blocks
 
 enum : int32_t { STATUS_STENCIL_TOO_LARGE = 1, STATUS_REGION_MISS = 2 };

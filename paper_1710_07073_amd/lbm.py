@@ -31,7 +31,8 @@ EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch",
            "lbm_batch_bytes_required", "lbm_batch_init", "lbm_batch_set_items", "lbm_batch_get_items",
            "lbm_batch_step", "lbm_batch_run", "lbm_batch_populations", "lbm_batch_column",
            "lbm_batch_check", "lbm_batch_destroy",
-           "lbm_adjoint_liquid", "lbm_adjoint_bubbles", "lbm_host_collide",
+           "lbm_adjoint_liquid", "lbm_adjoint_bubbles", "lbm_bubble_record", "lbm_bind_buffers",
+           "lbm_host_collide",
            "lbm_host_axis_weights", "lbm_host_bubble_ode", "lbm_host_bubble_ode_adjoint")
 
 
@@ -115,6 +116,8 @@ def lib():
         I = ct.POINTER(ct.c_int32)
         L.lbm_adjoint_liquid.argtypes = [P, P, P, P, P, P, P, P]
         L.lbm_adjoint_bubbles.argtypes = [P, ct.POINTER(BubbleParams), P, P, P, P, P, P, ct.c_int32, P]
+        L.lbm_bubble_record.argtypes = [P, ct.POINTER(BubbleSoA), ct.c_int32, ct.c_int32, P]
+        L.lbm_bind_buffers.argtypes = [P, P, P, P]
         L.lbm_host_collide.argtypes = [D, D, ct.c_double, D, D, D, D, D, D, D]
         L.lbm_host_axis_weights.argtypes = [ct.c_double, ct.c_double, ct.c_int32, ct.c_int32,
                                             ct.c_double, ct.c_double, I, D, D, D, D]
@@ -313,6 +316,15 @@ def lbm_adjoint_liquid(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad
 def lbm_adjoint_bubbles(ctx, params, record, vel_prev, lam_f, lam_u, lam, scratch, nb, grad):
     _ok(lib().lbm_adjoint_bubbles(ctx, ct.byref(params), record, vel_prev, lam_f, lam_u, lam,
                                   scratch, int(nb), grad), "lbm_adjoint_bubbles")
+
+
+def lbm_bubble_record(ctx, soa, nb, stage, record):
+    _ok(lib().lbm_bubble_record(ctx, ct.byref(soa), int(nb), int(stage), record), "lbm_bubble_record")
+
+
+def lbm_bind_buffers(ctx, state=None, next_state=None, vel=None):
+    """Device pointers (ctypes c_void_p or None to keep the current buffer)."""
+    _ok(lib().lbm_bind_buffers(ctx, state, next_state, vel), "lbm_bind_buffers")
 
 
 def _dp(a):
