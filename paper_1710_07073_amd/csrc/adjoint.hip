@@ -9,10 +9,12 @@
 //
 // Bubble half, k_adj_bubble: one workgroup per bubble runs the transposes of the three forward
 // bubble kernels in reverse order (spreading, sub-stepped ODE, interpolation).
+#include <algorithm>
 #include <utility>
 
 #include "adjoint_math.hpp"
 #include "collide.hpp"
+#include "step_cell.hpp"
 
 namespace lbm {
 namespace {
@@ -87,6 +89,78 @@ __global__ __launch_bounds__(256) void k_adj_liquid(const T* __restrict__ h, con
   if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = dom;
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&grad[0], s_red[0] + s_red[1] + s_red[2] + s_red[3]);
+}
+
+template <typename T, int... Qs>
+__device__ __forceinline__ void pull_push_bb(T* p, const T* __restrict__ h, const Geom& G, uint32_t lc4,
+                                             uint32_t walls, std::integer_sequence<int, Qs...>) {
+  ((p[Qs] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(h) +
+                                         pull_off_bb<Qs, T>(G, lc4, walls))),
+   ...);
+}
+
+template <typename T, int... Qs>
+__device__ __forceinline__ void push_bb(T* __restrict__ dst, const T* mu, const Geom& G, uint32_t lc4,
+                                        uint32_t walls, std::integer_sequence<int, Qs...>) {
+  ((*at_bytes(dst, pull_off_bb<Qs, T>(G, lc4, walls)) = mu[Qs]), ...);
+}
+
+// The same on the bounce-back fast path (every face bounce-back, byte offsets below 4 GiB): every
+// access is a scalar base plus a 32-bit byte offset, and the push goes to the byte offsets the
+// pull read from. The dL/domega partial of each workgroup goes to one of nbins bins (atomic adds
+// spread over the bins instead of one address), summed by k_bins.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_liquid_bb(const T* __restrict__ h,
+                                                       const T* __restrict__ F,
+                                                       const T* __restrict__ lam_next,
+                                                       T* __restrict__ lam_prev,
+                                                       T* __restrict__ lam_u, T* __restrict__ lam_f,
+                                                       Geom G, T omega, double* __restrict__ bins,
+                                                       uint32_t nbins) {
+  __shared__ double s_red[4];
+  const uint32_t cell = blockIdx.x * 256 + threadIdx.x;
+  double dom = 0.0;
+  if (cell < G.N) {
+    const uint32_t z = cell / G.plane, rem = cell - z * G.plane;
+    const uint32_t y = rem / (uint32_t)G.nx, x = rem - y * (uint32_t)G.nx;
+    constexpr uint32_t esz = sizeof(T);
+    const uint32_t lc4 = layout_cell(G, cell, z) * esz;
+    const uint32_t walls = wall_bits(G, (int)x, (int)y, z);
+    const uint32_t c4 = cell * esz, n4 = G.N * esz, qs4 = G.qs * esz;
+    T p[19], lam[19], mu[19];
+    pull_push_bb<T>(p, h, G, lc4, walls, std::make_integer_sequence<int, 19>{});
+#pragma unroll
+    for (int q = 0; q < 19; ++q) lam[q] = *at_bytes(lam_next, lc4 + (uint32_t)q * qs4);
+    const T f[3] = {*at_bytes(F, c4), *at_bytes(F, c4 + n4), *at_bytes(F, c4 + 2 * n4)};
+    const T lu[3] = {*at_bytes(lam_u, c4), *at_bytes(lam_u, c4 + n4), *at_bytes(lam_u, c4 + 2 * n4)};
+    T lf[3];
+    collide_cell_adjoint<T>(p, f, omega, lam, lu, mu, lf, &dom);
+    push_bb<T>(lam_prev, mu, G, lc4, walls, std::make_integer_sequence<int, 19>{});
+    *at_bytes(lam_f, c4) = lf[0];
+    *at_bytes(lam_f, c4 + n4) = lf[1];
+    *at_bytes(lam_f, c4 + 2 * n4) = lf[2];
+    // consumed: the next (earlier) step accumulates its own velocity adjoint here
+    *at_bytes(lam_u, c4) = T(0);
+    *at_bytes(lam_u, c4 + n4) = T(0);
+    *at_bytes(lam_u, c4 + 2 * n4) = T(0);
+  }
+  dom = wsum(dom);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = dom;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicAdd(&bins[blockIdx.x % nbins], s_red[0] + s_red[1] + s_red[2] + s_red[3]);
+}
+
+// grad[0] += sum of the bins, in a fixed order; the bins are left at zero.
+__global__ __launch_bounds__(64) void k_bins(double* __restrict__ bins, uint32_t nbins,
+                                             double* __restrict__ grad) {
+  double v = 0.0;
+  if (threadIdx.x < nbins) {
+    v = bins[threadIdx.x];
+    bins[threadIdx.x] = 0.0;
+  }
+  v = wsum(v);
+  if (threadIdx.x == 0) grad[0] += v;
 }
 
 // Weights and derivatives of the three axes into LDS (one thread per axis).
@@ -282,6 +356,25 @@ __global__ __launch_bounds__(64) void k_record(bubble_soa S, int nb, int stage, 
 template <typename T, bool GENERAL>
 hipError_t liquid_typed(lbm_ctx* c, const void* state, const void* force, const void* lam_next,
                         void* lam_prev, void* lam_u, void* lam_f, double* grad) {
+  if (!GENERAL && bb_fast_ok(c->geom, sizeof(T))) {
+    // bins for the dL/domega partials: the moments reduction scratch (at least 64 doubles for
+    // lattices of 4096 cells or more)
+    const uint32_t nbins = std::min<uint32_t>(64, c->nred * 4);
+    hipError_t e = hipSuccess;
+    if (!c->bins_clean) e = launch_fill(c->partials, nbins * sizeof(double), c->stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_adj_liquid_bb<T>), dim3(div_up(c->geom.N, 256)), dim3(256), 0, c->stream,
+                       static_cast<const T*>(state), static_cast<const T*>(force),
+                       static_cast<const T*>(lam_next), static_cast<T*>(lam_prev),
+                       static_cast<T*>(lam_u), static_cast<T*>(lam_f), c->geom, (T)c->desc.omega,
+                       c->partials, nbins);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bins, dim3(1), dim3(64), 0, c->stream, c->partials, nbins, grad);
+    e = hipGetLastError();
+    c->bins_clean = e == hipSuccess;
+    return e;
+  }
   hipLaunchKernelGGL((k_adj_liquid<T, GENERAL>), dim3(div_up(c->geom.N, 256)), dim3(256), 0,
                      c->stream, static_cast<const T*>(state), static_cast<const T*>(force),
                      static_cast<const T*>(lam_next), static_cast<T*>(lam_prev),

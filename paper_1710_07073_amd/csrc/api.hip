@@ -119,6 +119,7 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->result = reinterpret_cast<double*>(s + L.result);
   c->status = reinterpret_cast<int32_t*>(s + L.status);
   c->nred = L.nred;
+  c->bins_clean = false;
   c->stream = static_cast<hipStream_t>(stream);
   lbm::default_launch(G.nx, c->elem, &c->step_vec, &c->step_bx);
   // side stream and events of the overlapped step (default priority); without them the step

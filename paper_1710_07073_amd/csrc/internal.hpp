@@ -53,7 +53,8 @@ struct lbm_ctx {
   int32_t pending_nb;  // bubbles of the pending overlapped step
   uint32_t ntiles;
   uint32_t nrows;  // tile rows (y, z tile coordinates)
-  double* partials; // moments reduction partials (4 doubles per block)
+  double* partials; // moments reduction partials (4 doubles per block); adjoint dL/domega bins
+  bool bins_clean;   // the first 64 partials are zero (the adjoint's bins)
   double* result;   // 4 doubles
   int32_t* status;  // kernel error word
   uint32_t nred;    // number of reduction partial slots

@@ -115,6 +115,7 @@ __global__ void k_fill_bytes(uint8_t* __restrict__ p, size_t n) {
 template <typename T, bool GENERAL>
 hipError_t moments_typed(lbm_ctx* c, void* rho, void* u) {
   const uint32_t blocks = c->nred;
+  c->bins_clean = false;
   hipLaunchKernelGGL((k_moments<T, GENERAL>), dim3(blocks), dim3(kThreads), 0, c->stream,
                      static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(rho),
                      static_cast<T*>(u), c->partials, c->geom);

@@ -2,6 +2,7 @@
 // and the batched kernels (eq. (13)-(16) with half-way bounce-back on every face, Sec. 3.3).
 #pragma once
 
+#include <type_traits>
 #include <utility>
 
 #include "collide.hpp"
@@ -14,20 +15,30 @@ namespace lbm {
 // gather is a scalar base plus a 32-bit byte offset selected from two uniform values, and each
 // store (populations, velocity, force) is a scalar base plus the lane's own offset: almost no
 // per-lane address arithmetic is left beside the collision.
+// Byte offset of the source of population Q of the cell at byte offset lc4 (layout index times the
+// element size). walls: bit 0 x = 0, 1 x = nx - 1, 2 y = 0, 3 y = ny - 1, 4 z = 0, 5 z = nz - 1; the
+// source x - c lies beyond the wall at x = 0 when c_x > 0, and so on.
 template <int Q, typename T>
-__device__ __forceinline__ T pull_bb(const char* __restrict__ sb, const Geom& G, uint32_t lc4,
-                                     uint32_t walls) {
+__device__ __forceinline__ uint32_t pull_off_bb(const Geom& G, uint32_t lc4, uint32_t walls) {
   constexpr int cx = CX[Q], cy = CY[Q], cz = CZ[Q];
-  // walls: bit 0 x = 0, 1 x = nx - 1, 2 y = 0, 3 y = ny - 1, 4 z = 0, 5 z = nz - 1; the source
-  // x - c lies beyond the wall at x = 0 when c_x > 0, and so on
   constexpr uint32_t m = (cx > 0 ? 1u : 0u) | (cx < 0 ? 2u : 0u) | (cy > 0 ? 4u : 0u) |
                          (cy < 0 ? 8u : 0u) | (cz > 0 ? 16u : 0u) | (cz < 0 ? 32u : 0u);
   constexpr uint32_t esz = sizeof(T);
   // byte offsets modulo 2^32; the sum with lc4 is the true offset, below 2^32
   const uint32_t k = ((uint32_t)Q * G.qs - (uint32_t)(cx + cy * G.nx) - (uint32_t)cz * G.zs) * esz;
   const uint32_t kb = (uint32_t)opposite(Q) * G.qs * esz;
-  const uint32_t off = lc4 + ((walls & m) ? kb : k);
-  return *reinterpret_cast<const T*>(sb + off);
+  return lc4 + ((walls & m) ? kb : k);
+}
+
+template <int Q, typename T>
+__device__ __forceinline__ T pull_bb(const char* __restrict__ sb, const Geom& G, uint32_t lc4,
+                                     uint32_t walls) {
+  return *reinterpret_cast<const T*>(sb + pull_off_bb<Q, T>(G, lc4, walls));
+}
+
+__device__ __forceinline__ uint32_t wall_bits(const Geom& G, int x, int y, uint32_t z) {
+  return (x == 0 ? 1u : 0u) | (x == G.nx - 1 ? 2u : 0u) | (y == 0 ? 4u : 0u) |
+         (y == G.ny - 1 ? 8u : 0u) | (z == 0 ? 16u : 0u) | (z == (uint32_t)G.nz - 1 ? 32u : 0u);
 }
 
 template <typename T, int... Qs>
@@ -39,7 +50,8 @@ __device__ __forceinline__ void pull_bb_all(T* g, const char* __restrict__ sb, c
 
 template <typename T>
 __device__ __forceinline__ T* at_bytes(T* base, uint32_t off) {
-  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+  using B = std::conditional_t<std::is_const_v<T>, const char, char>;
+  return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + off);
 }
 
 // One cell of the bounce-back fast path: gather, collision, stores. forced: the cell's tile
@@ -52,9 +64,7 @@ __device__ __forceinline__ void step_cell_bb(const T* __restrict__ src, T* __res
   const uint32_t cell = ((uint32_t)z * G.ny + y) * G.nx + x;
   constexpr uint32_t esz = sizeof(T);
   const uint32_t lc4 = layout_cell(G, cell, z) * esz;
-  const uint32_t walls = (x == 0 ? 1u : 0u) | (x == G.nx - 1 ? 2u : 0u) | (y == 0 ? 4u : 0u) |
-                         (y == G.ny - 1 ? 8u : 0u) | (z == 0 ? 16u : 0u) |
-                         (z == (uint32_t)G.nz - 1 ? 32u : 0u);
+  const uint32_t walls = wall_bits(G, x, y, z);
   T g[19];
   pull_bb_all<T>(g, reinterpret_cast<const char*>(src), G, lc4, walls,
                  std::make_integer_sequence<int, 19>{});
