@@ -110,7 +110,7 @@ typedef struct {
 /* Doubles of per-bubble device scratch that bubbles_step() needs in bubble_soa.work (the
  * interpolated liquid velocity and vorticity, the start position and the reaction of the step,
  * passed between its kernels). Its contents need no initialisation. */
-#define LBM_BUBBLE_WORK 16
+#define LBM_BUBBLE_WORK 216
 
 typedef struct lbm_ctx lbm_ctx;
 

@@ -17,6 +17,9 @@
 // so the ghost sign along an axis is -1 at a bounce-back face and +1 at a free-slip face.
 #include <math.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace lbm {
@@ -76,6 +79,26 @@ __device__ __forceinline__ bool axis_window(double x, double n, int ext, bool pe
   return true;
 }
 
+// Weights of one axis (eq. (19)): cell integrals of the kernel over the clipped window [clo, chi],
+// indexed by (cell - lo + 1), renormalised to a sum of one when a wall clips the window. One full
+// wavefront (lane = 0..63) computes; the renormalising sum is taken in a fixed order.
+__device__ void wave_axis_weights(const Axis& A, double xa, double n, bool per, int lane,
+                                  double* s_w_a) {
+  double part = 0.0;
+  for (int i = lane; i < kSpan; i += 64) {
+    const int v = A.lo - 1 + i;
+    double w = 0.0;
+    if (v >= A.clo && v <= A.chi) w = kernel_P((v + 0.5 - xa) / n) - kernel_P((v - 0.5 - xa) / n);
+    s_w_a[i] = w;
+    part += w;
+  }
+  if (!per) {
+    const double sum = wave_sum(part);
+    if (sum > 0.0)
+      for (int i = lane; i < kSpan; i += 64) s_w_a[i] /= sum;
+  }
+}
+
 // Weights w and derivative weights dw of the bubble at xb along the three axes, into LDS,
 // indexed by (cell - lo + 1). Called by the whole workgroup; the first wavefront computes.
 __device__ bool build_weights(const Geom& G, const double xb[3], double n, int tid,
@@ -86,28 +109,8 @@ __device__ bool build_weights(const Geom& G, const double xb[3], double n, int t
     if (!axis_window(xb[a], n, ext[a], per, win[a])) return false;
   }
   const int lane = tid;
-  if (tid < 64) {
-  for (int a = 0; a < 3; ++a) {
-    const bool per = G.bc[2 * a] == BC_PER;
-    const Axis& A = win[a];
-    // raw cell integrals on [clo, chi], zero elsewhere
-    double part = 0.0;
-    for (int i = lane; i < kSpan; i += 64) {
-      const int v = A.lo - 1 + i;
-      double w = 0.0;
-      if (v >= A.clo && v <= A.chi)
-        w = kernel_P((v + 0.5 - xb[a]) / n) - kernel_P((v - 0.5 - xb[a]) / n);
-      s_w[a][i] = w;
-      part += w;
-    }
-    // clipped at a wall: renormalise the axis to a sum of one
-    if (!per) {
-      const double sum = wave_sum(part);
-      if (sum > 0.0)
-        for (int i = lane; i < kSpan; i += 64) s_w[a][i] /= sum;
-    }
-  }
-  }
+  if (tid < 64)
+    for (int a = 0; a < 3; ++a) wave_axis_weights(win[a], xb[a], n, G.bc[2 * a] == BC_PER, lane, s_w[a]);
   __syncthreads();
   if (tid < 64) {
   for (int a = 0; a < 3; ++a) {
@@ -156,6 +159,10 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   __shared__ double s_red[kBlockWaves];
   const int b = bubble_of_block(A.nb);
   const int tid = threadIdx.x;
+  if constexpr (std::is_same_v<Geo, OneColumn>) {
+    // a new step of the deterministic spreading: no list has overflowed yet
+    if (blockIdx.x == 0 && tid == 0) *geo.ovf = 0u;
+  }
   const ColumnView<T> col = geo.template view<T>(b);
   const Geom& G = col.G;
   const T* __restrict__ U = col.U;
@@ -176,6 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
     }
     return;
   }
+  // the weights at x0 for the spreading of this step
+  for (int i = tid; i < 3 * kSpan; i += kBlock) work[W_WGT + i] = s_w[i / kSpan][i % kSpan];
   const int Dx = win[0].dhi - win[0].dlo + 1;
   const int Dy = win[1].dhi - win[1].dlo + 1;
   const int Dz = win[2].dhi - win[2].dlo + 1;
@@ -393,6 +402,10 @@ __device__ TileRanges tile_ranges(int vlo, int vhi, int ext, int tile, bool peri
     t.n = 1;
     t.lo[0] = a / tile;
     t.hi[0] = b / tile;
+  } else if (b / tile >= a / tile) {  // the two wrapped pieces share a tile: every tile once
+    t.n = 1;
+    t.lo[0] = 0;
+    t.hi[0] = (ext - 1) / tile;
   } else {
     t.n = 2;
     t.lo[0] = a / tile;
@@ -403,22 +416,43 @@ __device__ TileRanges tile_ranges(int vlo, int vhi, int ext, int tile, bool peri
   return t;
 }
 
-template <typename T, typename Geo>
-__global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
-  __shared__ double s_w[3][kSpan];
-  __shared__ double s_dw[3][kSpan];
-  const int b = bubble_of_block(A.nb);
-  const int tid = threadIdx.x;
-  const ColumnView<T> col = geo.template view<T>(b);
-  const Geom& G = col.G;
-  T* __restrict__ F = col.F;
-  uint8_t* __restrict__ tiles = col.tiles;
-  const double* work = A.S.work + (size_t)b * kWork;
-  if (work[W_VALID] == 0.0) return;
-  const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
-  const double n = A.P.kernel_factor * A.S.d[b];
-  Axis win[3];
-  if (!build_weights(G, x0, n, tid, s_w, s_dw, win)) return;  // validated by k_interp
+// Force window of a bubble at x0 (the clipped stencil window [clo, chi] of each axis).
+__device__ bool force_windows(const Geom& G, const double x0[3], double n, Axis win[3]) {
+  const int ext[3] = {G.nx, G.ny, G.nz};
+  for (int a = 0; a < 3; ++a)
+    if (!axis_window(x0[a], n, ext[a], G.bc[2 * a] == BC_PER, win[a])) return false;
+  return true;
+}
+
+// Calls f(tile) for every tile of the ranges tr, over the threads of the workgroup.
+template <class Fn>
+__device__ void for_tiles(const Geom& G, const TileRanges tr[3], int tid, int nthreads, Fn&& f) {
+  for (int rz = 0; rz < tr[2].n; ++rz)
+    for (int ry = 0; ry < tr[1].n; ++ry)
+      for (int rx = 0; rx < tr[0].n; ++rx) {
+        const int nx_ = tr[0].hi[rx] - tr[0].lo[rx] + 1;
+        const int ny_ = tr[1].hi[ry] - tr[1].lo[ry] + 1;
+        const int nz_ = tr[2].hi[rz] - tr[2].lo[rz] + 1;
+        for (int k = tid; k < nx_ * ny_ * nz_; k += nthreads) {
+          const int tx = tr[0].lo[rx] + k % nx_;
+          const int ty = tr[1].lo[ry] + (k / nx_) % ny_;
+          const int tz = tr[2].lo[rz] + k / (nx_ * ny_);
+          f(((uint32_t)tz * G.tny + ty) * G.tnx + tx);
+        }
+      }
+}
+
+// Tiles of the force window.
+__device__ void force_tiles(const Geom& G, const Axis win[3], TileRanges tr[3]) {
+  const int ext[3] = {G.nx, G.ny, G.nz};
+  for (int a = 0; a < 3; ++a)
+    tr[a] = tile_ranges(win[a].clo, win[a].chi, ext[a], (int)kTile, G.bc[2 * a] == BC_PER);
+}
+
+// Backward coupling by atomic adds: F(j) += psi W_j over the force window (eq. (21)).
+template <typename T>
+__device__ void spread_atomic(const Geom& G, T* __restrict__ F, const Axis win[3],
+                              double (*s_w)[kSpan], const double* work, int tid) {
   const double psi0 = work[W_PSI], psi1 = work[W_PSI + 1], psi2 = work[W_PSI + 2];
   const int Kx = win[0].chi - win[0].clo + 1;
   const int Ky = win[1].chi - win[1].clo + 1;
@@ -439,8 +473,15 @@ __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
     atomicAdd(&F[G.N + c], (T)(psi1 * W));
     atomicAdd(&F[2 * (size_t)G.N + c], (T)(psi2 * W));
   }
-  // flag the tiles: the force window now, and the velocity window (with the curl ring) that the
-  // next interpolation reads at the new position
+}
+
+// Flags the tiles the liquid step must force (the force window now) or write the velocity in (the
+// velocity window, with the curl ring, that the next interpolation reads at the new position).
+template <typename T>
+__device__ void mark_tiles(const ColumnView<T>& col, const BubbleArgs& A, int b, const Axis win[3],
+                           double n, int tid) {
+  const Geom& G = col.G;
+  uint8_t* __restrict__ tiles = col.tiles;
   const double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
   const int ext[3] = {G.nx, G.ny, G.nz};
   TileRanges tr[3];
@@ -454,24 +495,156 @@ __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
     }
     tr[a] = tile_ranges(lo, hi, ext[a], (int)kTile, per);
   }
-  for (int rz = 0; rz < tr[2].n; ++rz)
-    for (int ry = 0; ry < tr[1].n; ++ry)
-      for (int rx = 0; rx < tr[0].n; ++rx) {
-        const int nx_ = tr[0].hi[rx] - tr[0].lo[rx] + 1;
-        const int ny_ = tr[1].hi[ry] - tr[1].lo[ry] + 1;
-        const int nz_ = tr[2].hi[rz] - tr[2].lo[rz] + 1;
-        for (int k = tid; k < nx_ * ny_ * nz_; k += kBlock) {
-          const int tx = tr[0].lo[rx] + k % nx_;
-          const int ty = tr[1].lo[ry] + (k / nx_) % ny_;
-          const int tz = tr[2].lo[rz] + k / (nx_ * ny_);
-          const uint32_t t = ((uint32_t)tz * G.tny + ty) * G.tnx + tx;
-          tiles[t] = 1;
-          // in an overlapped step the bulk launch has updated the rows outside the region
-          // concurrently: a tile forced or needing the velocity there is an error
-          if (col.region && !col.region[t / (uint32_t)G.tnx])
-            atomicOr(A.status, (int32_t)STATUS_REGION_MISS);
-        }
-      }
+  for_tiles(G, tr, tid, kBlock, [&](uint32_t t) {
+    tiles[t] = 1;
+    // in an overlapped step the bulk launch has updated the rows outside the region
+    // concurrently: a tile forced or needing the velocity there is an error
+    if (col.region && !col.region[t / (uint32_t)G.tnx]) atomicOr(A.status, (int32_t)STATUS_REGION_MISS);
+  });
+}
+
+// Backward coupling of one bubble per workgroup by atomic adds, and the tile flags.
+template <typename T, typename Geo>
+__global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
+  __shared__ double s_w[3][kSpan];
+  __shared__ double s_dw[3][kSpan];
+  const int b = bubble_of_block(A.nb);
+  const int tid = threadIdx.x;
+  const ColumnView<T> col = geo.template view<T>(b);
+  const double* work = A.S.work + (size_t)b * kWork;
+  if (work[W_VALID] == 0.0) return;
+  const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+  const double n = A.P.kernel_factor * A.S.d[b];
+  Axis win[3];
+  if (!build_weights(col.G, x0, n, tid, s_w, s_dw, win)) return;  // validated by k_interp
+  spread_atomic<T>(col.G, col.F, win, s_w, work, tid);
+  mark_tiles<T>(col, A, b, win, n, tid);
+}
+
+// ---- deterministic backward coupling (gather per tile), for many bubbles on one lattice ----
+//
+// k_spread_fill     per bubble: enters the bubble in the list of each tile of its force window
+//                   (kTileCap entries per tile; a full list sets the overflow flag) and flags the
+//                   tiles for the liquid step;
+// k_spread_gather   per tile: sorts the tile's bubbles by index and sums psi_b W_b(j) in that order
+//                   in double precision, with the weights k_interp stored at x0: F(j) does not
+//                   depend on the order in which workgroups ran. With one bubble per cell the sum
+//                   is the atomic path's single addition, bit for bit;
+// k_spread_fallback per bubble, only after an overflow: atomic adds, as k_spread.
+__global__ __launch_bounds__(kBlock) void k_spread_fill(OneColumn geo, BubbleArgs A) {
+  const int b = bubble_of_block(A.nb);
+  const int tid = threadIdx.x;
+  const ColumnView<float> col = geo.view<float>(b);  // geometry, flags and region only
+  const double* work = A.S.work + (size_t)b * kWork;
+  if (work[W_VALID] == 0.0) return;
+  const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+  const double n = A.P.kernel_factor * A.S.d[b];
+  Axis win[3];
+  if (!force_windows(col.G, x0, n, win)) return;  // validated by k_interp
+  TileRanges tr[3];
+  force_tiles(col.G, win, tr);
+  for_tiles(col.G, tr, tid, kBlock, [&](uint32_t t) {
+    const uint32_t slot = atomicAdd(&geo.tcount[t], 1u);
+    if (slot < kTileCap)
+      geo.tlist[(size_t)t * kTileCap + slot] = (uint32_t)b;
+    else
+      atomicOr(geo.ovf, 1u);
+  });
+  mark_tiles<float>(col, A, b, win, n, tid);
+}
+
+// Sum of the weights of axis a (global copy, indexed cell - lo + 1) at the window cells congruent
+// to cell v (one cell unless a periodic window is wider than the lattice).
+__device__ __forceinline__ double axis_weight_at(const Axis& A, const double* w_a, int v, int ext,
+                                                 bool per) {
+  if (!per) return (v >= A.clo && v <= A.chi) ? w_a[v - A.lo + 1] : 0.0;
+  int u = A.clo + wrapi(v - A.clo, ext);  // first window cell congruent to v
+  if (u > A.chi) return 0.0;
+  double s = w_a[u - A.lo + 1];
+  for (u += ext; u <= A.chi; u += ext) s += w_a[u - A.lo + 1];
+  return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spread_gather(OneColumn geo, BubbleArgs A) {
+  __shared__ uint32_t s_list[kTileCap];
+  __shared__ uint32_t s_sorted[kTileCap];
+  __shared__ Axis s_win[kTileCap][3];
+  __shared__ double s_psi[kTileCap][3];
+  const uint32_t t = blockIdx.x;
+  const int tid = threadIdx.x;
+  const Geom& G = geo.G;
+  const uint32_t cnt = geo.tcount[t];
+  if (cnt == 0u) return;
+  if (*geo.ovf) {  // this step spreads by atomic adds: only reset the count
+    if (tid == 0) geo.tcount[t] = 0u;
+    return;
+  }
+  const uint32_t n = cnt;  // <= kTileCap: no list overflowed
+  if (tid < (int)n) s_list[tid] = geo.tlist[(size_t)t * kTileCap + tid];
+  __syncthreads();
+  if (tid < (int)n) {  // rank sort (ties, which the lists do not hold, would keep list order)
+    const uint32_t v = s_list[tid];
+    uint32_t r = 0;
+    for (uint32_t j = 0; j < n; ++j) r += (s_list[j] < v || (s_list[j] == v && j < (uint32_t)tid)) ? 1u : 0u;
+    s_sorted[r] = v;
+  }
+  __syncthreads();
+  if (tid < (int)n) {
+    const uint32_t b = s_sorted[tid];
+    const double* work = A.S.work + (size_t)b * kWork;
+    const double xb[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+    Axis win[3];
+    force_windows(G, xb, A.P.kernel_factor * A.S.d[b], win);  // valid: the bubble was listed
+    for (int a = 0; a < 3; ++a) {
+      s_win[tid][a] = win[a];
+      s_psi[tid][a] = work[W_PSI + a];
+    }
+  }
+  __syncthreads();
+  const uint32_t tx = t % (uint32_t)G.tnx, rr = t / (uint32_t)G.tnx;
+  const uint32_t ty = rr % (uint32_t)G.tny, tz = rr / (uint32_t)G.tny;
+  const int x = (int)(tx * kTile + (tid & 7)), y = (int)(ty * kTile + ((tid >> 3) & 7));
+  const int z0 = (int)(tz * kTile + (tid >> 6));
+  if (x >= G.nx || y >= G.ny) return;
+  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+  double acc[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  for (uint32_t k = 0; k < n; ++k) {
+    const double* wk = A.S.work + (size_t)s_sorted[k] * kWork + W_WGT;
+    const double wx = axis_weight_at(s_win[k][0], wk, x, G.nx, px);
+    const double wy = axis_weight_at(s_win[k][1], wk + kSpan, y, G.ny, py);
+    for (int h = 0; h < 2; ++h) {
+      const double wz = axis_weight_at(s_win[k][2], wk + 2 * kSpan, z0 + 4 * h, G.nz, pz);
+      const double W = wx * wy * wz;
+      for (int q = 0; q < 3; ++q) acc[h][q] += s_psi[k][q] * W;
+    }
+  }
+  T* __restrict__ F = static_cast<T*>(geo.F);
+  for (int h = 0; h < 2; ++h) {
+    const int z = z0 + 4 * h;
+    if (z >= G.nz) continue;
+    const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
+    F[c] = (T)acc[h][0];
+    F[G.N + c] = (T)acc[h][1];
+    F[2 * (size_t)G.N + c] = (T)acc[h][2];
+  }
+  if (tid == 0) geo.tcount[t] = 0u;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spread_fallback(OneColumn geo, BubbleArgs A) {
+  __shared__ double s_w[3][kSpan];
+  __shared__ double s_dw[3][kSpan];
+  if (*geo.ovf == 0u) return;
+  const int b = bubble_of_block(A.nb);
+  const int tid = threadIdx.x;
+  const ColumnView<T> col = geo.view<T>(b);
+  const double* work = A.S.work + (size_t)b * kWork;
+  if (work[W_VALID] == 0.0) return;
+  const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+  Axis win[3];
+  if (!build_weights(col.G, x0, A.P.kernel_factor * A.S.d[b], tid, s_w, s_dw, win)) return;
+  spread_atomic<T>(col.G, col.F, win, s_w, work, tid);
 }
 
 // Region of an overlapped step (one wavefront per bubble): the tile rows (y, z) of the bubble's
@@ -521,6 +694,22 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
   hipLaunchKernelGGL((k_ode<Geo>), dim3(div_up(nb, 64)), dim3(64), 0, stream, geo, A);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if constexpr (std::is_same_v<Geo, OneColumn>) {
+    if (nb > 1) {  // several bubbles: deterministic spreading through per-tile lists
+      const uint32_t ntiles = (uint32_t)geo.G.tnx * geo.G.tny * div_up(geo.G.nz, kTile);
+      hipLaunchKernelGGL(k_spread_fill, dim3(nb), dim3(kBlock), 0, stream, geo, A);
+      e = hipGetLastError();
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL((k_spread_gather<T>), dim3(ntiles), dim3(kBlock), 0, stream, geo, A);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL((k_spread_fallback<T>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+        e = hipGetLastError();
+      }
+      return e;
+    }
+  }
   hipLaunchKernelGGL((k_spread<T, Geo>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
   return hipGetLastError();
 }
@@ -550,6 +739,9 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
   geo.tiles = c->tiles[m];
   geo.nu = (1.0 / c->desc.omega - 0.5) / 3.0;  // eq. (9), dx = dt_l = 1
   geo.region = nullptr;
+  geo.tcount = c->tcount;
+  geo.tlist = c->tlist;
+  geo.ovf = c->ovf;
   if (overlap) {
     // Region of this step, then fork: the bubble kernels run on the side stream while the bulk of
     // the liquid step runs on the caller's stream, which then waits for the bubble kernels (so

@@ -43,6 +43,11 @@ struct lbm_ctx {
   uint32_t* region;
   uint32_t* region_list[2];
   uint32_t* region_count;  // [2]
+  // per-tile bubble lists of the deterministic force spreading: bubbles per tile (zero between
+  // steps), kTileCap list entries per tile, and the overflow flag
+  uint32_t* tcount;
+  uint32_t* tlist;
+  uint32_t* ovf;
   lbm::HostState hs;
   lbm::HostState graph_post;  // host state after the captured steps of `graph`
   bool overlap;               // overlap enabled (lbm_set_overlap)
@@ -77,7 +82,8 @@ struct ColumnView {
   const uint32_t* region;  // region flags of an overlapped step (tiles the spread may force), or null
 };
 
-// A single lattice (lbm_ctx).
+// A single lattice (lbm_ctx). tcount/tlist/ovf: the per-tile bubble lists of the deterministic
+// spreading (kTileCap entries per tile) and their overflow flag.
 struct OneColumn {
   Geom G;
   void* U;
@@ -85,6 +91,9 @@ struct OneColumn {
   uint8_t* tiles;
   double nu;
   const uint32_t* region;
+  uint32_t* tcount;
+  uint32_t* tlist;
+  uint32_t* ovf;
   template <typename T>
   __device__ ColumnView<T> view(int) const {
     return {G, static_cast<const T*>(U), static_cast<T*>(F), tiles, nu, region};
@@ -124,6 +133,12 @@ constexpr uint32_t kTile = 8;
 // Slots of the per-bubble workspace (bubble_soa.work) the bubble kernels pass between them:
 // interpolated u_l and curl w_l, position at interpolation, reaction psi, window valid.
 constexpr int W_UL = 0, W_WL = 3, W_X0 = 6, W_PSI = 9, W_VALID = 12;
+// From W_WGT: the three axes' stencil weights at x0, LBM_MAX_STENCIL + 2 doubles per axis, indexed
+// like the LDS copies of the bubble kernels (cell - lo + 1).
+constexpr int W_WGT = 16;
+static_assert(W_WGT + 3 * (LBM_MAX_STENCIL + 2) <= LBM_BUBBLE_WORK, "bubble workspace too small");
+// Bubbles a tile's list holds in the deterministic spreading.
+constexpr uint32_t kTileCap = 64;
 constexpr uint32_t kRedBlocks = 1024;  // upper bound of moments reduction blocks
 
 enum : int32_t { STATUS_STENCIL_TOO_LARGE = 1, STATUS_REGION_MISS = 2 };

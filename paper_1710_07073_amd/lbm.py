@@ -18,7 +18,7 @@ LBM_FP32_SHIFTED, LBM_FP64_SHIFTED = 1, 2
 LBM_BC_BOUNCE_BACK, LBM_BC_FREE_SLIP, LBM_BC_PERIODIC = 0, 1, 2
 LBM_FLAG_STATIC_FORCE, LBM_FLAG_WRITE_U_ALL, LBM_FLAG_PLAIN_SOA = 1, 2, 4
 LBM_MAX_STENCIL = 64
-LBM_BUBBLE_WORK = 16
+LBM_BUBBLE_WORK = 216
 LBM_BUBBLE_RECORD = 24
 LBM_BUBBLE_ADJ = 12
 

@@ -156,3 +156,39 @@ def test_bubble_beyond_stencil_limit_is_reported():
     sim.check()  # the error was cleared
     assert torch.count_nonzero(sim.force).item() == 0
     sim.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_many_overlapping_bubbles_are_bitwise_reproducible(prec):
+    """Force from many bubbles with overlapping windows is summed per cell in bubble order, so
+    two runs give the same bits whatever order the workgroups ran in."""
+    w = _many_bubbles((40, 40, 48), (BB,) * 6, 300, 21, prec, steps=25, dmin=2.0, dmax=5.0)
+    print(f"[case] {w.name} {prec}: {w.nb} bubbles", flush=True)
+    runs = []
+    for _ in range(2):
+        sim = gpu_sim(w)
+        sim.step(w.steps)
+        runs.append((sim.populations().cpu().numpy(), sim.bubbles.positions(), sim.bubbles.velocities()))
+        sim.check()
+        sim.close()
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.gpu
+def test_spreading_list_overflow_falls_back_and_matches_oracle():
+    """80 bubbles packed into one 8^3 block: the tiles around it are in more than 64 force
+    windows, more than a tile's list holds, so the step spreads by atomic adds; it still matches
+    the oracle."""
+    rng = np.random.default_rng(41)
+    pos = rng.uniform(20.0, 27.99, (3, 80))
+    w = W.Workload("clustered_80", (48, 48, 48), 1.3, (BB,) * 6, pos, rng.uniform(2.0, 3.0, 80),
+                   W.params(g=1e-5, sigma=W.sigma_for(1e-5, 2.5)), 6, "f64")
+    print(f"[case] {w.name}: {w.nb} bubbles in one 8^3 block", flush=True)
+    sim, lat, bub, worst = _run_both(w, w.steps, check_every=3)
+    u, _ = gpu_u(sim)
+    _, u_o, _ = lat.moments()
+    assert rel_l2(u, u_o) <= U_TOL["f64"]
+    assert worst <= POS_TOL
+    sim.close()
