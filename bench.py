@@ -176,6 +176,52 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_stability(args):
+    """Stability sweep (Sec. 4.4): the App. A column (30 x 30 x 90, 4 mm bubble, d = 0.8) at 16
+    values of omega from 1.90 to 1.9999 in one batch, FP32, graph replays of 500 steps; after each
+    chunk the per-column sums tell which columns went unstable."""
+    import torch
+    import workloads as W
+    from paper_1710_07073_amd import sim as S
+
+    ws = W.stability(steps=args.steps)
+    cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d) for w in ws]
+    stream = torch.cuda.current_stream()
+    batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
+    chunk = 500
+    first = [None] * len(ws)
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.steps:
+        n = min(chunk, args.steps - done)
+        batch.run(n, graph_steps=chunk if n == chunk else 0)
+        done += n
+        _, diverged = batch.sums()
+        for k, dv in enumerate(diverged):
+            if dv and first[k] is None:
+                first[k] = done
+        print(f"[stability] {done} steps, unstable: {[w.omega for w, f in zip(ws, first) if f]}",
+              file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    z = batch.bubbles.positions()[2]
+    batch.close()
+    cells = sum(w.cells for w in ws)
+    stable = [w.omega for w, f in zip(ws, first) if f is None]
+    out = {
+        "metric": METRIC, "value": round(cells * args.steps / elapsed / 1e6, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": 0,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "stability_sweep_30x30x90_x16", "columns": len(ws),
+                   "parallelism": "single GPU"},
+        "stability": {"omega": [w.omega for w in ws], "first_unstable_step": first,
+                      "bubble_z_end": [None if not np.isfinite(v) else round(float(v), 3) for v in z],
+                      "max_stable_omega": max(stable) if stable else None,
+                      "check_every_steps": chunk},
+    }
+    print(json.dumps(out), flush=True)
+
+
 ADJOINT_GOLDEN = os.path.join(ROOT, "tests", "golden", "adjoint_64x64x192_oracle_gradient.json")
 
 
@@ -307,7 +353,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="single_fp32",
-                    choices=["single_fp32", "plain_fp64", "dense", "batched", "adjoint"])
+                    choices=["single_fp32", "plain_fp64", "dense", "batched", "adjoint", "stability"])
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay the step loop from a HIP graph of this many steps (even)")
     ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
@@ -339,6 +385,8 @@ def main():
         return bench_batched(args)
     if args.workload == "adjoint":
         return bench_adjoint(args)
+    if args.workload == "stability":
+        return bench_stability(args)
     w = {"single_fp32": W.single_fp32, "plain_fp64": W.plain_fp64, "dense": W.dense}[args.workload]()
     if args.precision:
         w = W.Workload(w.name.replace("fp32", args.precision).replace("fp64", args.precision),

@@ -316,6 +316,11 @@ lbm_status lbm_batch_run(lbm_batch* batch, const bubble_params* params, const bu
                          int32_t nb, int32_t nsteps, int32_t graph_steps);
 /* Pre-collision populations g = f - w of column col (19 x N, lattice type) into device buffer out. */
 lbm_status lbm_batch_populations(lbm_batch* batch, int32_t col, void* out);
+/* Per-column global sums of the current state (eq. (10)): sums (host, ncols x 4 doubles) =
+ * (sum rho, sum rho u_x, sum rho u_y, sum rho u_z) of each column, accumulated in double
+ * precision in a fixed order. Synchronises the stream. Returns LBM_EDIVERGED when a sum is not
+ * finite (the BGK step of that column went unstable; the other columns' sums are valid). */
+lbm_status lbm_batch_sums(lbm_batch* batch, double* sums);
 /* Device pointers of column col: current state buffer, force field, velocity field. */
 lbm_status lbm_batch_column(lbm_batch* batch, int32_t col, void** state, void** force, void** vel);
 /* Synchronise and report a pending kernel error (as lbm_check). */

@@ -4,6 +4,8 @@
 // bubbles of all columns go through the same three bubble kernels as a single lattice. Repeated
 // steps are captured once into a HIP graph and replayed (graph.hpp).
 #include <math.h>
+
+#include <algorithm>
 #include <new>
 #include <string.h>
 #include <vector>
@@ -40,6 +42,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+constexpr uint32_t kSumBlocks = 16;  // workgroups per column of the per-column sums
 
 // Exact x = cell % nx, y = (cell / nx) % ny, z = cell / (nx ny) for cell < 2^31, through a
 // double-precision reciprocal and one correction step each.
@@ -115,6 +119,55 @@ __global__ __launch_bounds__(256) void k_batch_step(const ColumnDev* __restrict_
   }
 }
 
+// Per-column sums (eq. (10)) of the current state: kSumBlocks workgroups per column accumulate
+// (sum drho, sum rho u) of their share of the cells in double precision; k_batch_sums_reduce adds
+// the shares of each column in a fixed order.
+template <typename T, bool GENERAL>
+__global__ __launch_bounds__(256) void k_batch_sums(const ColumnDev* __restrict__ cols, int cur,
+                                                    double* __restrict__ partials) {
+  __shared__ double s_red[4][4];
+  const uint32_t col = blockIdx.x / kSumBlocks, part = blockIdx.x % kSumBlocks;
+  const ColumnDev& C = cols[col];
+  const Geom G = C.G;
+  const T* __restrict__ src = static_cast<const T*>(C.pops[cur]);
+  double acc[4] = {0, 0, 0, 0};
+  for (uint32_t cell = part * 256 + threadIdx.x; cell < G.N; cell += kSumBlocks * 256) {
+    const uint32_t x = cell % G.nx, y = (cell / G.nx) % G.ny, z = cell / G.plane;
+    const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
+    T g[19];
+    pull_all<GENERAL>(g, src, G, layout_cell(G, cell, z), nb, std::make_integer_sequence<int, 19>{});
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+      const double v = (double)g[q];
+      acc[0] += v;
+      acc[1] += CX[q] * v;
+      acc[2] += CY[q] * v;
+      acc[3] += CZ[q] * v;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double v = acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s_red[k][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4)
+    partials[(size_t)blockIdx.x * 4 + threadIdx.x] =
+        s_red[threadIdx.x][0] + s_red[threadIdx.x][1] + s_red[threadIdx.x][2] + s_red[threadIdx.x][3];
+}
+
+__global__ void k_batch_sums_reduce(const ColumnDev* __restrict__ cols, int ncols,
+                                    const double* __restrict__ partials, double* __restrict__ result) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncols) return;
+  double s[4] = {0, 0, 0, 0};
+  for (uint32_t p = 0; p < kSumBlocks; ++p)
+    for (int k = 0; k < 4; ++k) s[k] += partials[((size_t)col * kSumBlocks + p) * 4 + k];
+  result[(size_t)col * 4] = (double)cols[col].G.N + s[0];
+  for (int k = 1; k < 4; ++k) result[(size_t)col * 4 + k] = s[k];
+}
+
 template <typename T, bool GENERAL>
 __global__ __launch_bounds__(256) void k_batch_populations(const ColumnDev* __restrict__ col, int cur,
                                                            T* __restrict__ out) {
@@ -180,8 +233,9 @@ bool layout_batch(const lbm_column* cols, int ncols, size_t elem, BatchLayout& L
   L.table = tiles;
   L.bcol = align_up(L.table + (size_t)ncols * sizeof(ColumnDev));
   L.partials = align_up(L.bcol + (size_t)(L.nb_total > 0 ? L.nb_total : 1) * sizeof(int32_t));
-  L.result = align_up(L.partials + (size_t)kRedBlocks * 4 * sizeof(double));
-  L.status = align_up(L.result + 4 * sizeof(double));
+  const size_t nparts = std::max<size_t>(kRedBlocks, (size_t)ncols * kSumBlocks);
+  L.result = align_up(L.partials + nparts * 4 * sizeof(double));
+  L.status = align_up(L.result + (size_t)ncols * 4 * sizeof(double));
   L.scratch = align_up(L.status + sizeof(int32_t));
   return true;
 }
@@ -423,6 +477,37 @@ lbm_status lbm_batch_run(lbm_batch* b, const bubble_params* p, const bubble_soa*
     done += graph_steps;
   }
   if (nsteps > done) return lbm_batch_step(b, p, s, nb, nsteps - done);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_sums(lbm_batch* b, double* sums) {
+  if (!b || !sums) return LBM_EINVAL;
+  const uint32_t blocks = (uint32_t)b->ncols * kSumBlocks;
+  if (b->elem == 4) {
+    if (b->general)
+      hipLaunchKernelGGL((k_batch_sums<float, true>), dim3(blocks), dim3(256), 0, b->stream, b->dev,
+                         b->cur, b->partials);
+    else
+      hipLaunchKernelGGL((k_batch_sums<float, false>), dim3(blocks), dim3(256), 0, b->stream, b->dev,
+                         b->cur, b->partials);
+  } else {
+    if (b->general)
+      hipLaunchKernelGGL((k_batch_sums<double, true>), dim3(blocks), dim3(256), 0, b->stream, b->dev,
+                         b->cur, b->partials);
+    else
+      hipLaunchKernelGGL((k_batch_sums<double, false>), dim3(blocks), dim3(256), 0, b->stream, b->dev,
+                         b->cur, b->partials);
+  }
+  if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+  hipLaunchKernelGGL(k_batch_sums_reduce, dim3(div_up((uint32_t)b->ncols, 64)), dim3(64), 0, b->stream,
+                     b->dev, b->ncols, b->partials, b->result);
+  if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+  if (hipMemcpyAsync(sums, b->result, (size_t)b->ncols * 4 * sizeof(double), hipMemcpyDeviceToHost,
+                     b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return LBM_EDEVICE;
+  for (int i = 0; i < 4 * b->ncols; ++i)
+    if (!isfinite(sums[i])) return LBM_EDIVERGED;
   return LBM_OK;
 }
 

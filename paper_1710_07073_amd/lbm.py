@@ -29,7 +29,8 @@ EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch",
            "moments", "lbm_populations", "lbm_state_buffer", "lbm_check", "lbm_run", "lbm_destroy",
            "lbm_status_string",
            "lbm_batch_bytes_required", "lbm_batch_init", "lbm_batch_set_items", "lbm_batch_get_items",
-           "lbm_batch_step", "lbm_batch_run", "lbm_batch_populations", "lbm_batch_column",
+           "lbm_batch_step", "lbm_batch_run", "lbm_batch_populations", "lbm_batch_sums",
+           "lbm_batch_column",
            "lbm_batch_check", "lbm_batch_destroy",
            "lbm_adjoint_liquid", "lbm_adjoint_bubbles", "lbm_bubble_record", "lbm_bind_buffers",
            "lbm_host_collide",
@@ -109,6 +110,7 @@ def lib():
         L.lbm_batch_run.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32,
                                     ct.c_int32, ct.c_int32]
         L.lbm_batch_populations.argtypes = [P, ct.c_int32, P]
+        L.lbm_batch_sums.argtypes = [P, ct.POINTER(ct.c_double)]
         L.lbm_batch_column.argtypes = [P, ct.c_int32, ct.POINTER(P), ct.POINTER(P), ct.POINTER(P)]
         L.lbm_batch_check.argtypes = [P]
         L.lbm_batch_destroy.argtypes = [P]
@@ -289,6 +291,17 @@ def lbm_batch_run(batch, params, soa, nb, nsteps, graph_steps=0):
 
 def lbm_batch_populations(batch, col, out_ptr):
     _ok(lib().lbm_batch_populations(batch, int(col), out_ptr), "lbm_batch_populations")
+
+
+def lbm_batch_sums(batch, ncols):
+    """Per-column (sum rho, sum rho u) as a (ncols, 4) array and whether any column diverged
+    (non-finite sums, LBM_EDIVERGED); other errors raise."""
+    import numpy as np
+    out = (ct.c_double * (4 * ncols))()
+    rc = lib().lbm_batch_sums(batch, out)
+    if rc not in (LBM_OK, LBM_EDIVERGED):
+        _ok(rc, "lbm_batch_sums")
+    return np.array(out[:], dtype=np.float64).reshape(ncols, 4), rc == LBM_EDIVERGED
 
 
 def lbm_batch_column(batch, col):

@@ -165,7 +165,12 @@ class Batch:
                                        _ptr(self.scratch), ct.c_void_p(self.stream.cuda_stream))
         pos = np.concatenate([np.asarray(c["pos"], np.float64).reshape(3, -1) for c in columns], axis=1)
         d = np.concatenate([np.asarray(c["d"], np.float64).reshape(-1) for c in columns])
-        self.bubbles = Bubbles(pos, d, device=self.device)
+        vel = None
+        if any(c.get("vel") is not None for c in columns):
+            vel = np.concatenate([np.zeros((3, np.asarray(c["d"]).size)) if c.get("vel") is None
+                                  else np.asarray(c["vel"], np.float64).reshape(3, -1) for c in columns],
+                                 axis=1)
+        self.bubbles = Bubbles(pos, d, vel, device=self.device)
         self.params = params
         self.ncols = len(columns)
         self.cells = sum(int(np.prod(c["shape"])) for c in columns)
@@ -200,3 +205,9 @@ class Batch:
 
     def check(self):
         L.lbm_batch_check(self.handle)
+
+    def sums(self):
+        """(ncols, 4) per-column (sum rho, sum rho u) and a mask of the columns whose sums are not
+        finite (diverged)."""
+        sums, _ = L.lbm_batch_sums(self.handle, self.ncols)
+        return sums, ~np.isfinite(sums).all(axis=1)

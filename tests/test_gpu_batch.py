@@ -172,3 +172,31 @@ def test_batched_sweep_full_size():
             mass = batch.populations(c).double().sum().item()  # sum of g = sum rho - N
             assert abs(mass) < 1e-6 * w.cells
         batch.close()
+
+
+@pytest.mark.gpu
+def test_batch_sums_flag_only_the_diverged_column():
+    """Three columns stepped together; in the middle one the host sets a non-finite bubble
+    velocity, which makes that column's reaction force and then its populations non-finite (the
+    state of a column that went unstable). The per-column sums flag it, and the other two columns'
+    sums stay finite and equal those of their single-lattice runs."""
+    shape = (20, 20, 40)
+    cols = []
+    for om, v in ((1.5, 0.0), (1.9999, float("nan")), (1.2, 0.0)):
+        cols.append(dict(shape=shape, omega=om, bc=(0,) * 6, pos=np.array([[10.0], [10.0], [12.0]]),
+                         d=np.array([3.0]), vel=np.array([[0.0], [0.0], [v]])))
+    P = S.bubble_params(g=1e-4, sigma=1e-4)
+    b = S.Batch(cols, P, precision="f64")
+    b.step(60)
+    sums, diverged = b.sums()
+    print(f"sums {sums.tolist()}", flush=True)
+    b.close()
+    assert diverged.tolist() == [False, True, False]
+    for k in (0, 2):
+        c = cols[k]
+        sim = S.Simulation(shape, c["omega"], precision="f64", bc=c["bc"])
+        sim.add_bubbles(c["pos"], c["d"], P, vel=c["vel"])
+        sim.step(60)
+        _, _, s1 = sim.moments(fields=False)
+        sim.close()
+        assert np.allclose(sums[k], s1, rtol=1e-12, atol=1e-14)

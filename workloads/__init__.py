@@ -136,6 +136,26 @@ def adjoint(steps=2000, drag_scale=1.0, lift_scale=1.0, omega=1.4):
                     meta=dict(target=(1.15, 0.8, 1.5), theta0=(1.0, 1.0, 1.4), checkpoint=100))
 
 
+STABILITY_OMEGAS = (1.90, 1.92, 1.94, 1.95, 1.96, 1.965, 1.97, 1.975, 1.98, 1.985, 1.99, 1.995,
+                    1.998, 1.999, 1.9995, 1.9999)
+
+
+def stability(steps=20000, omegas=STABILITY_OMEGAS):
+    """The stability sweep (Sec. 4.4): the App. A column (0.15 x 0.15 x 0.45 m tank at aspect ratio
+    1.25 for a 4 mm bubble: 30 x 30 x 90 cells, d = 0.8) with g and sigma of air in water converted
+    to lattice units (g = 9.81 m/s^2, sigma = 0.0728 N/m, dt = 1e-4 s), bounce-back walls and bottom,
+    free-slip top, the bubble released at the bottom centre; one column per omega."""
+    from paper_1710_07073_amd import units as U
+    u = U.column_units(0.004, 1.25)
+    col = U.column(u, 0.004)
+    g = u.acceleration(9.81)
+    sigma = u.surface_tension(0.0728)
+    pos = np.array([[col.nx / 2 - 0.5], [col.ny / 2 - 0.5], [3.0]])
+    bc = (BB, BB, BB, BB, BB, FS)
+    return [Workload(f"stability_omega{om}", (col.nx, col.ny, col.nz), float(om), bc, pos.copy(),
+                     np.array([col.d_b]), params(g=g, sigma=sigma), steps, "f32") for om in omegas]
+
+
 def with_steps(w: Workload, steps: int) -> Workload:
     return replace(w, steps=steps)
 
