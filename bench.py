@@ -222,6 +222,82 @@ def bench_stability(args):
     print(json.dumps(out), flush=True)
 
 
+# Table 6: the paper's terminal velocity (m/s), identical at all three aspect ratios
+PAPER_VT = {4: 0.2383, 8: 0.2411, 10: 0.2538}
+
+
+def bench_grid(args):
+    """Grid-independence study (Sec. 4.3, Tables 5 and 6): the nine columns of Table 5 (4, 8 and
+    10 mm bubbles at aspect ratios 1.25, 0.625, 0.3125) in physical units, FP32, one simulation per
+    column replayed from graphs of 100 steps; the bubble's rise velocity is read every 100 steps
+    (0.01 s) and the terminal velocity is its mean over 0.5 to 0.9 s, converted to m/s; the slip
+    velocity is the same mean of u_b - u_l with u_l the liquid velocity interpolated at the bubble."""
+    import torch
+    import workloads as W
+    from paper_1710_07073_amd import sim as S
+    from paper_1710_07073_amd import units as U
+
+    chunk = 100
+    steps = max(args.steps - args.steps % chunk, 2 * chunk)
+    ws = W.grid_independence(steps=steps)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    rows, elapsed, cells = [], 0.0, 0
+    for w in ws:
+        u = U.column_units(w.meta["d_mm"] * 1e-3, w.meta["aspect"])
+        sim = S.Simulation(w.shape, w.omega, precision="f32", bc=w.bc, device=dev, stream=stream)
+        sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+        t_s, z_m, v_ms, ul_ms = [], [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps // chunk):
+            sim.run(chunk, graph_steps=chunk)
+            x, v, ul = sim.bubbles.positions(), sim.bubbles.velocities(), sim.bubbles.liquid_velocity()
+            t_s.append((k + 1) * chunk * u.dt)
+            z_m.append(float(x[2, 0]) * u.dx)
+            v_ms.append(u.velocity_pu(float(v[2, 0])))
+            ul_ms.append(u.velocity_pu(float(ul[2, 0])))
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        cells += w.cells
+        state = int(sim.bubbles.state()[0])
+        sim.check()
+        sim.close()
+        t_s, v_ms, ul_ms = np.array(t_s), np.array(v_ms), np.array(ul_ms)
+        window = (t_s >= 0.5 - 1e-9) & (t_s <= 0.9 + 1e-9)
+        if not window.any():
+            window = t_s >= t_s[-1] / 2
+        vt = float(v_ms[window].mean())
+        marks = {f"{t:.2f}": round(z_m[int(round(t / (chunk * u.dt))) - 1], 5)
+                 for t in (0.25, 0.5, 0.75, 1.0) if int(round(t / (chunk * u.dt))) <= len(z_m)}
+        rows.append(dict(case=w.name, d_mm=w.meta["d_mm"], aspect=w.meta["aspect"], grid=list(w.shape),
+                         d_lu=float(w.d[0]), omega=w.omega, vT_ms=round(vt, 5),
+                         vT_spread_ms=round(float(np.ptp(v_ms[window])), 6),
+                         ul_at_bubble_ms=round(float(ul_ms[window].mean()), 5),
+                         slip_ms=round(float((v_ms - ul_ms)[window].mean()), 5),
+                         re_end=round(v_ms[-1] * w.meta["d_mm"] * 1e-3 / W.WATER_NU, 1),
+                         z_m=marks, active=state, paper_vT_ms=PAPER_VT[int(w.meta["d_mm"])]))
+        print(f"[grid] {w.name} {w.shape} omega {w.omega:.6f}: v_T {vt:.4f} m/s "
+              f"(paper {PAPER_VT[int(w.meta['d_mm'])]})", file=sys.stderr, flush=True)
+    def spread(key):
+        by_d = {}
+        for r in rows:
+            by_d.setdefault(r["d_mm"], []).append(r[key])
+        return {f"{int(d)}mm": round((max(v) - min(v)) / np.mean(v), 6) for d, v in by_d.items()}
+    out = {
+        "metric": METRIC, "value": round(cells * steps / elapsed / 1e6, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": round(elapsed / steps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "grid_independence_table5_x9", "columns": len(ws),
+                   "parallelism": "single GPU"},
+        "grid": {"cases": rows, "vT_relative_spread_over_aspect": spread("vT_ms"),
+                 "slip_relative_spread_over_aspect": spread("slip_ms"),
+                 "vT_window_s": [0.5, 0.9], "sample_every_steps": chunk},
+    }
+    print(json.dumps(out), flush=True)
+
+
 ADJOINT_GOLDEN = os.path.join(ROOT, "tests", "golden", "adjoint_64x64x192_oracle_gradient.json")
 
 
@@ -353,7 +429,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="single_fp32",
-                    choices=["single_fp32", "plain_fp64", "dense", "batched", "adjoint", "stability"])
+                    choices=["single_fp32", "plain_fp64", "dense", "batched", "adjoint", "stability",
+                             "grid"])
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay the step loop from a HIP graph of this many steps (even)")
     ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
@@ -387,6 +464,8 @@ def main():
         return bench_adjoint(args)
     if args.workload == "stability":
         return bench_stability(args)
+    if args.workload == "grid":
+        return bench_grid(args)
     w = {"single_fp32": W.single_fp32, "plain_fp64": W.plain_fp64, "dense": W.dense}[args.workload]()
     if args.precision:
         w = W.Workload(w.name.replace("fp32", args.precision).replace("fp64", args.precision),
@@ -429,7 +508,8 @@ def main():
     K = args.steps
     # the library records these around the launch of the fused step that updates the lattice away
     # from the bubbles, on the stream it runs on (the side stream when the step is overlapped)
-    # every EVERY-th launch is timed (an event record costs a queue marker of a few microseconds)
+    # every EVERY-th launch is timed (an event record costs a queue marker of a few microseconds);
+    # the steps run through lbm_run in runs of EVERY, the first of which is timed
     EVERY = 8
     nt = (K + EVERY - 1) // EVERY
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]
@@ -439,11 +519,9 @@ def main():
     bub = sim.bubbles
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(K):
-        if k % EVERY == 0:
-            L.lbm_time_next_step(sim.ctx, ev0[k // EVERY], ev1[k // EVERY])
-        L.bubbles_step(sim.ctx, sim.params, bub.soa, bub.nb)
-        L.lbm_step(sim.ctx, 1)
+    for k in range(0, K, EVERY):
+        L.lbm_time_next_step(sim.ctx, ev0[k // EVERY], ev1[k // EVERY])
+        L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, min(EVERY, K - k), 0)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     step_ms = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]

@@ -1,0 +1,103 @@
+"""The paper's physical-unit columns (Sec. 4.3, Tables 3, 5 and 6; App. A): a 4 mm or 10 mm air
+bubble in water at omega up to 1.99999, where BGK is barely damped.
+
+* Parity with the oracle on two of the Table 5 columns, FP64 and FP32, graph-replayed.
+* Grid independence (Table 6): the 4 mm bubble on the three Table 5 grids. The slip velocity
+  u_b - u_l (bubble against the liquid interpolated at its centre) does not depend on the grid
+  and equals the oracle ODE's terminal velocity in a quiescent liquid (the force balance of
+  eq. (23)-(24)); the absolute rise velocity adds the liquid the bubble entrains, which grows
+  with resolution and converges: each refinement changes it by less than half the previous
+  change.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_common import gpu_sim, oracle_state, rel_l2
+
+U_TOL = {"f64": 1e-12, "f32": 2e-5}     # relative L2 of u after 300 steps
+POS_TOL = {"f64": 1e-12, "f32": 1e-6}   # bubble position, lattice units
+CASES = {w.name: w for w in W.grid_independence()}
+
+
+def _with(w, steps, dtype):
+    return W.Workload(w.name, w.shape, w.omega, w.bc, w.pos, w.d, w.params, steps, dtype, meta=w.meta)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["grid_4mm_ar1.25", "grid_10mm_ar0.625"])
+def test_physical_column_matches_oracle(name, dtype):
+    w = _with(CASES[name], 300, dtype)
+    print(f"[case] {name} {w.shape} omega {w.omega:.6f} {dtype}: 300 steps, graphs of 100",
+          flush=True)
+    sim = gpu_sim(w)
+    sim.run(w.steps, graph_steps=100)
+    _, u, _ = sim.moments()
+    u = u.double().cpu().numpy()
+    x, v = sim.bubbles.positions(), sim.bubbles.velocities()
+    sim.check()
+    sim.close()
+    lat, bub, P = oracle_state(w)
+    for _ in range(w.steps):
+        O.method_step(lat, P, bub)
+    _, u_o, _ = lat.moments()
+    eu, dx = rel_l2(u, u_o), np.abs(x - bub.pos).max()
+    print(f"rel-L2 u {eu:.2e}, |dx_b| {dx:.2e}, bubble w {v[2, 0]:.6e}", flush=True)
+    assert eu <= U_TOL[dtype]
+    assert dx <= POS_TOL[dtype]
+    assert np.abs(v - bub.vel).max() <= U_TOL[dtype] * np.abs(bub.vel).max()
+    assert v[2, 0] > 0
+
+
+def _ode_terminal(w):
+    """Terminal rise velocity (lattice units) of the oracle's bubble ODE in a quiescent liquid."""
+    P = O.bubble_params(**w.params)
+    nu = (1.0 / w.omega - 0.5) / 3.0
+    z3 = np.zeros(3)
+    ub, xb = np.zeros(3), np.zeros(3)
+    for _ in range(400):
+        prev = ub[2]
+        ub, xb, _ = O.bubble_ode(P, nu, 1.0 / P.n_sub, 20000, float(w.d[0]), z3, z3, z3, ub, xb)
+        if abs(ub[2] - prev) <= 1e-13:
+            return ub[2]
+    raise AssertionError("the ODE has no terminal velocity")
+
+
+@pytest.mark.gpu
+def test_slip_velocity_grid_independent_and_rise_velocity_converges():
+    steps, chunk = 6000, 100
+    rise, slip, vt_ode = [], [], []
+    for aspect in (1.25, 0.625, 0.3125):
+        w = CASES[f"grid_4mm_ar{aspect}"]
+        print(f"[case] {w.name} {w.shape} omega {w.omega:.6f}: {steps} steps (0.6 s)", flush=True)
+        sim = gpu_sim(_with(w, steps, "f32"))
+        ub, ul = [], []
+        for k in range(steps // chunk):
+            sim.run(chunk, graph_steps=chunk)
+            if (k + 1) * chunk >= 4000:   # 0.4 to 0.6 s
+                ub.append(sim.bubbles.velocities()[2, 0])
+                ul.append(sim.bubbles.liquid_velocity()[2, 0])
+        state = sim.bubbles.state()[0]
+        sim.check()
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        scale = w.meta["tcf"] / w.meta["lcf"]   # lattice -> m/s
+        rise.append(np.mean(ub) * scale)
+        slip.append((np.mean(ub) - np.mean(ul)) * scale)
+        vt_ode.append(_ode_terminal(w) * scale)
+        print(f"rise {rise[-1]:.5f} m/s, slip {slip[-1]:.5f} m/s, ODE terminal {vt_ode[-1]:.5f} m/s",
+              flush=True)
+        assert state == 2
+    slip, rise, vt_ode = map(np.array, (slip, rise, vt_ode))
+    # the force balance itself is unit-free: the ODE gives one velocity in m/s on every grid
+    assert np.ptp(vt_ode) <= 1e-6 * vt_ode.mean()
+    assert abs(vt_ode[0] - 0.2368) <= 1e-4   # Table 4, force balance, 4 mm
+    assert np.ptp(slip) <= 1e-3 * slip.mean()
+    assert np.all(np.abs(slip - vt_ode) <= 1e-3 * vt_ode)
+    d1, d2 = rise[1] - rise[0], rise[2] - rise[1]
+    assert d1 > 0 and d2 > 0 and d2 < 0.5 * d1
+    assert np.all(rise <= 1.05 * vt_ode)

@@ -140,20 +140,51 @@ STABILITY_OMEGAS = (1.90, 1.92, 1.94, 1.95, 1.96, 1.965, 1.97, 1.975, 1.98, 1.98
                     1.998, 1.999, 1.9995, 1.9999)
 
 
+# Air bubble in water (Table 3) and standard gravity, SI units
+WATER_NU, WATER_RHO, AIR_RHO, WATER_SIGMA, GRAVITY = 1e-6, 1000.0, 1.0, 0.073, 9.81
+
+
 def stability(steps=20000, omegas=STABILITY_OMEGAS):
     """The stability sweep (Sec. 4.4): the App. A column (0.15 x 0.15 x 0.45 m tank at aspect ratio
     1.25 for a 4 mm bubble: 30 x 30 x 90 cells, d = 0.8) with g and sigma of air in water converted
-    to lattice units (g = 9.81 m/s^2, sigma = 0.0728 N/m, dt = 1e-4 s), bounce-back walls and bottom,
+    to lattice units (g = 9.81 m/s^2, sigma = 0.073 N/m, dt = 1e-4 s), bounce-back walls and bottom,
     free-slip top, the bubble released at the bottom centre; one column per omega."""
     from paper_1710_07073_amd import units as U
     u = U.column_units(0.004, 1.25)
     col = U.column(u, 0.004)
-    g = u.acceleration(9.81)
-    sigma = u.surface_tension(0.0728)
+    g = u.acceleration(GRAVITY)
+    sigma = u.surface_tension(WATER_SIGMA)
     pos = np.array([[col.nx / 2 - 0.5], [col.ny / 2 - 0.5], [3.0]])
     bc = (BB, BB, BB, BB, BB, FS)
     return [Workload(f"stability_omega{om}", (col.nx, col.ny, col.nz), float(om), bc, pos.copy(),
                      np.array([col.d_b]), params(g=g, sigma=sigma), steps, "f32") for om in omegas]
+
+
+GRID_CASES = ((0.004, 1.25), (0.004, 0.625), (0.004, 0.3125),
+              (0.008, 1.25), (0.008, 0.625), (0.008, 0.3125),
+              (0.010, 1.25), (0.010, 0.625), (0.010, 0.3125))
+
+
+def grid_independence(steps=10000, cases=GRID_CASES, release=0.02):
+    """The grid-independence study (Sec. 4.3, Tables 5 and 6): the 0.15 x 0.15 x 0.45 m tank for
+    bubbles of 4, 8 and 10 mm at aspect ratios dx / d_b of 1.25, 0.625 and 0.3125, the Table 3
+    properties (water: nu = 1e-6 m^2/s, so omega is 1.9992 to 1.99999; air at 1 kg/m^3;
+    sigma = 0.073 N/m; g = 9.81 m/s^2) converted to lattice units per App. A with dt = 1e-4 s;
+    bounce-back walls and bottom, free-slip top; the bubble released at rest `release` metres
+    above the bottom on the axis. 10000 steps are 1 s of rise."""
+    from paper_1710_07073_amd import units as U
+    out = []
+    for d_b, aspect in cases:
+        u = U.column_units(d_b, aspect)
+        col = U.column(u, d_b)
+        om = U.omega_of(u.viscosity(WATER_NU))
+        pos = np.array([[col.nx / 2 - 0.5], [col.ny / 2 - 0.5], [u.length(release)]])
+        p = params(g=u.acceleration(GRAVITY), sigma=u.surface_tension(WATER_SIGMA),
+                   rho_b=AIR_RHO / WATER_RHO)
+        out.append(Workload(f"grid_{int(d_b * 1000)}mm_ar{aspect}", (col.nx, col.ny, col.nz), float(om),
+                            (BB, BB, BB, BB, BB, FS), pos, np.array([col.d_b]), p, steps, "f32",
+                            meta=dict(d_mm=d_b * 1000, aspect=aspect, lcf=u.lcf, tcf=u.tcf)))
+    return out
 
 
 def with_steps(w: Workload, steps: int) -> Workload:
