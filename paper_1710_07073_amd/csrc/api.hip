@@ -14,7 +14,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t tiles[2], region, region_list[2], region_count, tcount, tlist, ovf, partials, result,
+  size_t tiles[2], region[2], region_list[2], region_count, tcount, tlist, ovf, partials, result,
       status, total;
   uint32_t ntiles, nred, tnx, tny, tnz;
 };
@@ -49,8 +49,9 @@ Layout layout_of(const lbm_desc* d) {
   L.tiles[0] = 0;
   L.tiles[1] = align_up(L.ntiles);
   const size_t nrows = (size_t)L.tny * L.tnz;
-  L.region = align_up(L.tiles[1] + L.ntiles);
-  L.region_list[0] = align_up(L.region + nrows * 4);
+  L.region[0] = align_up(L.tiles[1] + L.ntiles);
+  L.region[1] = align_up(L.region[0] + nrows * 4);
+  L.region_list[0] = align_up(L.region[1] + nrows * 4);
   L.region_list[1] = align_up(L.region_list[0] + nrows * 4);
   L.region_count = align_up(L.region_list[1] + nrows * 4);
   L.tcount = align_up(L.region_count + 2 * sizeof(uint32_t));
@@ -113,7 +114,8 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   uint8_t* s = static_cast<uint8_t*>(scratch);
   c->tiles[0] = s + L.tiles[0];
   c->tiles[1] = s + L.tiles[1];
-  c->region = reinterpret_cast<uint32_t*>(s + L.region);
+  c->region[0] = reinterpret_cast<uint32_t*>(s + L.region[0]);
+  c->region[1] = reinterpret_cast<uint32_t*>(s + L.region[1]);
   c->region_list[0] = reinterpret_cast<uint32_t*>(s + L.region_list[0]);
   c->region_list[1] = reinterpret_cast<uint32_t*>(s + L.region_list[1]);
   c->region_count = reinterpret_cast<uint32_t*>(s + L.region_count);
@@ -137,11 +139,15 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   // the region launch and the two cross-stream waits, is about 35 us per step)
   c->overlap = G.N >= lbm::kOverlapMinCells;
   c->side = nullptr;
+  c->ev_fork = c->ev_join = c->ev_region = nullptr;
   c->t_start = c->t_end = nullptr;
   const unsigned ev_flags = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
   if (c->side && (hipEventCreateWithFlags(&c->ev_fork, ev_flags) != hipSuccess ||
-                  hipEventCreateWithFlags(&c->ev_join, ev_flags) != hipSuccess)) {
+                  hipEventCreateWithFlags(&c->ev_join, ev_flags) != hipSuccess ||
+                  hipEventCreateWithFlags(&c->ev_region, ev_flags) != hipSuccess)) {
+    for (hipEvent_t ev : {c->ev_fork, c->ev_join, c->ev_region})
+      if (ev) (void)hipEventDestroy(ev);
     (void)hipStreamDestroy(c->side);
     c->side = nullptr;
   }
@@ -242,7 +248,11 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps) {
   return LBM_OK;
 }
 
-lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, int32_t nb) {
+namespace {
+// in_run: a step of lbm_run, where no caller code runs between steps, so that an overlapped step
+// may mark the region of the next one while its bulk runs (from the bubble state it leaves).
+lbm_status bubble_half(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, int32_t nb,
+                       bool in_run) {
   if (!ctx || !p || !s || nb < 0) return LBM_EINVAL;
   if (ctx->desc.flags & LBM_FLAG_STATIC_FORCE) return LBM_EINVAL;
   if (p->n_sub < 1 || p->reserved != 0) return LBM_EINVAL;
@@ -256,8 +266,15 @@ lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* 
     if (any_psi && !all_psi) return LBM_EINVAL;
   }
   if (ctx->hs.pending) return LBM_EINVAL;  // the previous bubble half still awaits its lbm_step
+  // the caller may have moved bubbles since a previous run marked ahead: mark afresh
+  if (!in_run) ctx->hs.marked = false;
   const bool overlap = ctx->overlap && nb > 0 && lbm::can_overlap(ctx);
-  return from_hip(lbm::launch_bubbles(ctx, p, s, nb, overlap));
+  return from_hip(lbm::launch_bubbles(ctx, p, s, nb, overlap, in_run));
+}
+}  // namespace
+
+lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, int32_t nb) {
+  return bubble_half(ctx, p, s, nb, false);
 }
 
 lbm_status lbm_check(lbm_ctx* ctx) {
@@ -316,8 +333,9 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, in
                    int32_t nsteps, int32_t graph_steps) {
   if (!ctx || !p || !s || nb < 0 || nsteps < 0) return LBM_EINVAL;
   if (graph_steps < 0 || graph_steps % 2 || ctx->hs.pending) return LBM_EINVAL;
+  ctx->hs.marked = false;  // the bubble state may have changed since the last call
   auto one = [&]() -> lbm_status {
-    lbm_status st = bubbles_step(ctx, p, s, nb);
+    lbm_status st = bubble_half(ctx, p, s, nb, true);
     if (st != LBM_OK) return st;
     return lbm_step(ctx, 1);
   };
@@ -336,6 +354,7 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, in
     const lbm::HostState pre = ctx->hs;
     const uint32_t mode = (pre.flag_clean[0] ? 1u : 0u) | (pre.flag_clean[1] ? 2u : 0u) |
                           ((uint32_t)pre.rpar << 4) | (ctx->overlap ? 32u : 0u) |
+                          (pre.marked ? 64u : 0u) |
                           ((uint32_t)ctx->step_vec << 8) | (ctx->step_bx << 12);
     const lbm::GraphKey key = lbm::GraphKey::of(p, s, nb, pre.cur, pre.flag_cur, graph_steps, mode);
     lbm_status st_cap = LBM_OK;
@@ -351,9 +370,9 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, in
                                      &captured);
     if (st_cap != LBM_OK) return st_cap;
     if (e != hipSuccess) return LBM_EDEVICE;
-    if (captured) ctx->graph_post = ctx->hs;  // the capture only recorded the launches
+    if (captured) ctx->graph.post() = ctx->hs;  // the capture only recorded the launches
     if (ctx->graph.launch(ctx->stream) != hipSuccess) return LBM_EDEVICE;
-    ctx->hs = ctx->graph_post;
+    ctx->hs = ctx->graph.post();
     ctx->hs.steps = pre.steps + graph_steps;
     done += graph_steps;
   }
@@ -372,6 +391,7 @@ lbm_status lbm_destroy(lbm_ctx* ctx) {
     if (hipStreamSynchronize(ctx->side) != hipSuccess) st = LBM_EDEVICE;
     (void)hipEventDestroy(ctx->ev_fork);
     (void)hipEventDestroy(ctx->ev_join);
+    (void)hipEventDestroy(ctx->ev_region);
     (void)hipStreamDestroy(ctx->side);
   }
   delete ctx;

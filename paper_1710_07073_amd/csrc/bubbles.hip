@@ -160,8 +160,12 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   const int b = bubble_of_block(A.nb);
   const int tid = threadIdx.x;
   if constexpr (std::is_same_v<Geo, OneColumn>) {
-    // a new step of the deterministic spreading: no list has overflowed yet
-    if (blockIdx.x == 0 && tid == 0) *geo.ovf = 0u;
+    // a new step of the deterministic spreading: no list has overflowed yet; in an overlapped
+    // step, the other parity's region list (its region launch ran before) starts empty
+    if (blockIdx.x == 0 && tid == 0) {
+      *geo.ovf = 0u;
+      if (geo.clear_count) *geo.clear_count = 0u;
+    }
   }
   const ColumnView<T> col = geo.template view<T>(b);
   const Geom& G = col.G;
@@ -695,6 +699,13 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if constexpr (std::is_same_v<Geo, OneColumn>) {
+    if (geo.next_region) {
+      // the region of the next step, from the bubble state this update leaves
+      hipLaunchKernelGGL((k_mark<OneColumn>), dim3(nb), dim3(64), 0, stream, geo, A,
+                         geo.next_region, geo.next_list, geo.next_count, geo.nrows);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     if (nb > 1) {  // several bubbles: deterministic spreading through per-tile lists
       const uint32_t ntiles = (uint32_t)geo.G.tnx * geo.G.tny * div_up(geo.G.nz, kTile);
       hipLaunchKernelGGL(k_spread_fill, dim3(nb), dim3(kBlock), 0, stream, geo, A);
@@ -717,7 +728,7 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
 }  // namespace
 
 hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb,
-                          bool overlap) {
+                          bool overlap, bool mark_ahead) {
   BubbleArgs A;
   A.P = *p;
   A.S = *s;
@@ -742,18 +753,35 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
   geo.tcount = c->tcount;
   geo.tlist = c->tlist;
   geo.ovf = c->ovf;
+  geo.clear_count = nullptr;
+  geo.next_region = nullptr;
+  geo.next_list = nullptr;
+  geo.next_count = nullptr;
+  geo.nrows = c->nrows;
   if (overlap) {
-    // Region of this step, then fork: the bubble kernels run on the side stream while the bulk of
-    // the liquid step runs on the caller's stream, which then waits for the bubble kernels (so
-    // that work the caller enqueues next sees their results); lbm_step() updates the region.
+    // Region of this step (unless the previous step of this run marked it), then fork: the
+    // bubble kernels run on the side stream while the bulk of the liquid step runs on the
+    // caller's stream, which then waits for the bubble kernels (so that work the caller enqueues
+    // next sees their results); lbm_step() updates the region. Marks left by an earlier call
+    // only widen a region (the flags admit each row once), which stays correct.
     const int r = c->hs.rpar;
-    hipLaunchKernelGGL((k_mark<OneColumn>), dim3(nb), dim3(64), 0, c->stream, geo, A, c->region,
-                       c->region_list[r], c->region_count + r, c->nrows);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipSuccess;
+    if (!c->hs.marked) {
+      hipLaunchKernelGGL((k_mark<OneColumn>), dim3(nb), dim3(64), 0, c->stream, geo, A,
+                         c->region[r], c->region_list[r], c->region_count + r, c->nrows);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_fork, 0);
     if (e != hipSuccess) return e;
-    geo.region = c->region;
+    geo.region = c->region[r];
+    geo.clear_count = c->region_count + (r ^ 1);
+    if (mark_ahead) {
+      geo.next_region = c->region[r ^ 1];
+      geo.next_list = c->region_list[r ^ 1];
+      geo.next_count = c->region_count + (r ^ 1);
+    }
+    c->hs.marked = mark_ahead;
     e = c->elem == 4 ? launch_bubble_kernels<float>(geo, A, c->side)
                      : launch_bubble_kernels<double>(geo, A, c->side);
     if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side);

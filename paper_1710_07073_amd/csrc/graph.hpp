@@ -79,10 +79,48 @@ class StepGraph {
   }
 
   hipError_t launch(hipStream_t s) { return hipGraphLaunch(exec_, s); }
+  bool holds(const GraphKey& key) const { return exec_ && key_.same(key); }
 
  private:
   hipGraphExec_t exec_ = nullptr;
   GraphKey key_;
+};
+
+// A few captured graphs, each with the host step state its replay leaves behind (Post); a new
+// key replaces the least recently used one.
+template <class Post, int N = 2>
+class GraphCache {
+ public:
+  void reset() {
+    for (Slot& s : slot_) s.g.reset();
+  }
+  template <class F>
+  hipError_t ensure(const GraphKey& key, hipStream_t s, F&& enqueue, bool* captured) {
+    int k = -1;
+    for (int i = 0; i < N; ++i)
+      if (slot_[i].g.holds(key)) k = i;
+    if (k < 0) {
+      k = 0;
+      for (int i = 1; i < N; ++i)
+        if (slot_[i].used < slot_[k].used) k = i;
+    }
+    cur_ = k;
+    slot_[k].used = ++clock_;
+    return slot_[k].g.ensure(key, s, static_cast<F&&>(enqueue), captured);
+  }
+  // the graph of the last ensure()
+  hipError_t launch(hipStream_t s) { return slot_[cur_].g.launch(s); }
+  Post& post() { return slot_[cur_].post; }
+
+ private:
+  struct Slot {
+    StepGraph g;
+    Post post{};
+    unsigned long long used = 0;
+  };
+  Slot slot_[N];
+  int cur_ = 0;
+  unsigned long long clock_ = 0;
 };
 
 }  // namespace lbm

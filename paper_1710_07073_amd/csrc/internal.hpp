@@ -16,8 +16,9 @@ struct HostState {
   int cur;                // pops[cur] holds the current post-collision state
   int flag_cur;           // current force / velocity tile mask
   bool flag_clean[2];     // tile mask known to be all zero
-  int rpar;               // parity of the next overlapped step (its region list and counter)
+  int rpar;               // parity of the next overlapped step (its region flags, list, counter)
   bool pending;           // bubbles_step() enqueued the bulk; lbm_step() must update the region
+  bool marked;            // the region of the next overlapped step is marked (within lbm_run)
   int64_t steps;
 };
 }  // namespace lbm
@@ -37,10 +38,10 @@ struct lbm_ctx {
   // Region of an overlapped step: the rows of tiles near bubbles (a row: 8 y by 8 z cells across
   // the whole x extent, so that the region launch reads long coalesced runs like the bulk), which
   // the liquid step updates only after the bubble kernels; the rest of the lattice (the bulk) is
-  // updated while they run. A flag per row (nonzero: in the region), and per step parity a compact
-  // list of the region's rows and its length. The region launch clears the flags it used and the
-  // next parity's counter.
-  uint32_t* region;
+  // updated while they run. Per step parity, a flag per row (nonzero: in the region), a compact
+  // list of the region's rows and its length. The region launch clears the flags it used; the
+  // first bubble kernel of a step clears the other parity's counter (its region launch is done).
+  uint32_t* region[2];
   uint32_t* region_list[2];
   uint32_t* region_count;  // [2]
   // per-tile bubble lists of the deterministic force spreading: bubbles per tile (zero between
@@ -49,10 +50,9 @@ struct lbm_ctx {
   uint32_t* tlist;
   uint32_t* ovf;
   lbm::HostState hs;
-  lbm::HostState graph_post;  // host state after the captured steps of `graph`
   bool overlap;               // overlap enabled (lbm_set_overlap)
   hipStream_t side;           // null if it could not be created (overlap then unavailable)
-  hipEvent_t ev_fork, ev_join;
+  hipEvent_t ev_fork, ev_join, ev_region;
   // caller's events recorded around the next bulk (or whole-lattice) liquid launch, one-shot
   hipEvent_t t_start, t_end;
   int32_t pending_nb;  // bubbles of the pending overlapped step
@@ -66,7 +66,8 @@ struct lbm_ctx {
   hipStream_t stream;
   int step_vec;      // cells per thread along x in the liquid step (1, 2, 4)
   uint32_t step_bx;  // threads per workgroup along x (the workgroup has 256 threads)
-  lbm::StepGraph graph;  // captured method steps (lbm_run)
+  lbm::GraphCache<lbm::HostState> graph;  // captured method steps (lbm_run), with the host state
+                                          // their replay leaves
 };
 
 namespace lbm {
@@ -94,6 +95,13 @@ struct OneColumn {
   uint32_t* tcount;
   uint32_t* tlist;
   uint32_t* ovf;
+  // overlapped steps: the counter k_interp clears (null: none), and where the region of the next
+  // step is marked after the bubble update (next_region null: not here)
+  uint32_t* clear_count;
+  uint32_t* next_region;
+  uint32_t* next_list;
+  uint32_t* next_count;
+  uint32_t nrows;
   template <typename T>
   __device__ ColumnView<T> view(int) const {
     return {G, static_cast<const T*>(U), static_cast<T*>(F), tiles, nu, region};
@@ -150,6 +158,10 @@ constexpr int kRegionMargin = 2;
 // Lattices from this size on overlap the bubble kernels with the liquid step by default.
 constexpr uint32_t kOverlapMinCells = 1u << 22;
 
+// Overlapped steps with at most this many bubbles update their region on the side stream,
+// alongside the bulk; with more, on the caller's stream after the bulk.
+constexpr int32_t kRegionSideMaxBubbles = 64;
+
 // Byte offsets of every population (and field) element fit in 32 bits.
 inline bool bb_fast_ok(const Geom& G, size_t esz) { return (size_t)19 * G.N * esz <= 0xffffffffull; }
 
@@ -161,8 +173,10 @@ bool can_overlap(const lbm_ctx* c);
 // Bulk part of the liquid step of an overlapped step (on the caller's stream).
 hipError_t launch_bulk(lbm_ctx* c);
 // bubbles.hip
+// mark_ahead (overlapped steps of lbm_run only): also mark the region of the next step, after the
+// bubble update, on the side stream
 hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb,
-                          bool overlap);
+                          bool overlap, bool mark_ahead);
 hipError_t launch_bubbles_batch(const ColumnDev* cols, const int32_t* bubble_col, int flag,
                                 size_t elem, const bubble_params* p, const bubble_soa* s,
                                 int32_t nb, int32_t* status, hipStream_t stream);

@@ -204,8 +204,8 @@ __global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* _
 }
 
 // The region of an overlapped step: the tile rows of its list, each cut into the same workgroups
-// as the bulk launch (bx by by cells of one z-plane). It runs after the bulk launch and the bubble
-// kernels; it clears the flags of its rows and the counter of the next step's list.
+// as the bulk launch (bx by by cells of one z-plane). It runs after the bubble kernels, alongside
+// the bulk launch; it clears the flags of its rows.
 template <typename T>
 __global__ __launch_bounds__(256) void k_region_bb(const T* __restrict__ src, T* __restrict__ dst,
                                                    T* __restrict__ F, T* __restrict__ U,
@@ -213,11 +213,9 @@ __global__ __launch_bounds__(256) void k_region_bb(const T* __restrict__ src, T*
                                                    uint8_t* __restrict__ tiles_next,
                                                    uint32_t* __restrict__ region,
                                                    const uint32_t* __restrict__ list,
-                                                   const uint32_t* __restrict__ count,
-                                                   uint32_t* __restrict__ count_next, Geom G,
+                                                   const uint32_t* __restrict__ count, Geom G,
                                                    T omega, int flags, uint32_t nrows,
                                                    uint32_t bx_blocks, uint32_t by_blocks) {
-  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) *count_next = 0;
   const uint32_t n = min(*count, nrows);
   const uint32_t per = bx_blocks * by_blocks * kTile;  // workgroups per row
 #pragma unroll 1
@@ -291,13 +289,13 @@ hipError_t launch_bulk_typed(lbm_ctx* c) {
   hipLaunchKernelGGL((k_step_bb<T>), dim3(nblocks), dim3(bx, by), 0, c->stream,
                      static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(c->pops[c->hs.cur ^ 1]),
                      static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
-                     c->tiles[c->hs.flag_cur ^ 1], c->region, G, (T)c->desc.omega,
+                     c->tiles[c->hs.flag_cur ^ 1], c->region[c->hs.rpar], G, (T)c->desc.omega,
                      c->desc.flags, nbx, nby, nblocks);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_region_typed(lbm_ctx* c, int32_t nb) {
+hipError_t launch_region_typed(lbm_ctx* c, int32_t nb, hipStream_t stream) {
   const Geom& G = c->geom;
   const uint32_t bx = c->step_bx, by = 256 / bx;
   const uint32_t bx_blocks = div_up(G.nx, bx), by_blocks = div_up(kTile, by);
@@ -306,11 +304,11 @@ hipError_t launch_region_typed(lbm_ctx* c, int32_t nb) {
   const uint64_t rows = std::min<uint64_t>((uint64_t)nb * 16, c->nrows);
   const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(rows * per, 16384));
   const int r = c->hs.rpar;
-  hipLaunchKernelGGL((k_region_bb<T>), dim3(blocks), dim3(bx, by), 0, c->stream,
+  hipLaunchKernelGGL((k_region_bb<T>), dim3(blocks), dim3(bx, by), 0, stream,
                      static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(c->pops[c->hs.cur ^ 1]),
                      static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
-                     c->tiles[c->hs.flag_cur ^ 1], c->region, c->region_list[r], c->region_count + r,
-                     c->region_count + (r ^ 1), G, (T)c->desc.omega, c->desc.flags, c->nrows,
+                     c->tiles[c->hs.flag_cur ^ 1], c->region[r], c->region_list[r], c->region_count + r,
+                     G, (T)c->desc.omega, c->desc.flags, c->nrows,
                      bx_blocks, by_blocks);
   return hipGetLastError();
 }
@@ -330,9 +328,18 @@ hipError_t launch_bulk(lbm_ctx* c) {
 hipError_t launch_step(lbm_ctx* c) {
   hipError_t e;
   if (c->hs.pending) {
-    // overlapped step: the bulk and the bubble kernels are enqueued; update the region
-    e = c->elem == 4 ? launch_region_typed<float>(c, c->pending_nb)
-                     : launch_region_typed<double>(c, c->pending_nb);
+    // overlapped step: the bulk and the bubble kernels are enqueued. The region rows depend only
+    // on the bubble kernels (their force), not on the bulk (disjoint rows of one pull step). With
+    // few bubbles they are updated on the side stream right after the spread, alongside the bulk,
+    // and the caller's stream waits for them. With many, the bubble kernels take a good part of
+    // the bulk's time and the region is large: sharing the chip with the bulk it would end after
+    // it, so it runs on the caller's stream once the bulk is done.
+    const bool side = c->pending_nb <= kRegionSideMaxBubbles;
+    hipStream_t rs = side ? c->side : c->stream;
+    e = c->elem == 4 ? launch_region_typed<float>(c, c->pending_nb, rs)
+                     : launch_region_typed<double>(c, c->pending_nb, rs);
+    if (e == hipSuccess && side) e = hipEventRecord(c->ev_region, c->side);
+    if (e == hipSuccess && side) e = hipStreamWaitEvent(c->stream, c->ev_region, 0);
     if (e != hipSuccess) return e;
     c->hs.pending = false;
     c->hs.rpar ^= 1;

@@ -12,11 +12,13 @@ from paper_1710_07073_amd import sim as S
 BB, FS, PER = 0, 1, 2
 
 
-def _run(shape, prec, pos, d, overlap, steps, graph_steps=0, vel=None, **pkw):
+def _run(shape, prec, pos, d, overlap, steps, graph_steps=0, vel=None, run=False, **pkw):
+    """steps method steps: through lbm_run (graph replay if graph_steps) or, unless run is set and
+    graph_steps is 0, one bubbles_step + lbm_step pair at a time."""
     sim = S.Simulation(shape, 1.35, precision=prec, bc=(BB,) * 6)
     L.lbm_set_overlap(sim.ctx, overlap)
     sim.add_bubbles(pos, d, S.bubble_params(**pkw), vel=vel)
-    if graph_steps:
+    if graph_steps or run:
         sim.run(steps, graph_steps=graph_steps)
     else:
         sim.step(steps)
@@ -53,6 +55,8 @@ def test_overlapped_step_matches_serial_step(prec, shape, pos, d):
     a = _run(shape, prec, pos, d, False, 40, **kw)
     b = _run(shape, prec, pos, d, True, 40, **kw)
     _same(a, b)
+    c = _run(shape, prec, pos, d, True, 40, run=True, **kw)  # eager lbm_run: marks ahead
+    _same(a, c)
     assert np.abs(a["x"][2] - pos[2]).max() > 1e-3  # the bubbles moved
 
 
@@ -66,6 +70,22 @@ def test_overlapped_steps_replayed_from_a_graph(prec):
     eager = _run(shape, prec, pos, d, False, 26, **kw)
     graph = _run(shape, prec, pos, d, True, 26, graph_steps=4, **kw)
     _same(eager, graph)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("graph_steps", [0, 4])
+def test_many_bubbles_overlapped_match_serial(graph_steps):
+    """More than 64 bubbles: the region is updated on the caller's stream after the bulk."""
+    rng = np.random.default_rng(11)
+    nb = 96
+    shape = (64, 64, 96)
+    pos = np.stack([rng.uniform(6, 58, nb), rng.uniform(6, 58, nb), rng.uniform(6, 70, nb)])
+    d = rng.uniform(2.0, 3.5, nb)
+    print(f"overlap vs serial, {nb} bubbles, graph_steps {graph_steps}", flush=True)
+    kw = dict(g=1e-4, sigma=1e-4)
+    a = _run(shape, "f32", pos, d, False, 12, **kw)
+    b = _run(shape, "f32", pos, d, True, 12, graph_steps=graph_steps, run=True, **kw)
+    _same(a, b)
 
 
 @pytest.mark.gpu
@@ -107,3 +127,35 @@ def test_overlap_is_on_by_default_for_large_lattices():
     sim = S.Simulation((128, 128, 256), 1.6, precision="f32", bc=(BB,) * 6)
     assert L.lbm_get_overlap(sim.ctx) == (True, True)
     sim.close()
+
+
+def _run_with_moves(overlap, graph_steps, prec="f32"):
+    shape, pos, d = CASES[1]
+    sim = S.Simulation(shape, 1.35, precision=prec, bc=(BB,) * 6)
+    L.lbm_set_overlap(sim.ctx, overlap)
+    sim.add_bubbles(np.array(pos, dtype=np.float64), d, S.bubble_params(g=1e-4, sigma=1e-4))
+    sim.run(10, graph_steps=graph_steps)
+    # the caller moves the bubbles between calls, beyond the region the last step marked ahead
+    sim.bubbles.t["z"] += 20.0
+    sim.run(10, graph_steps=graph_steps)
+    sim.step(3)
+    sim.bubbles.t["x"] -= 6.0
+    sim.bubbles.t["y"] += 5.0
+    sim.run(6, graph_steps=graph_steps)
+    out = dict(g=sim.populations().cpu().numpy(), U=sim.vel.cpu().numpy(),
+               x=sim.bubbles.positions(), v=sim.bubbles.velocities(), st=sim.bubbles.state())
+    sim.check()  # no bubble left its step's region
+    sim.close()
+    return out
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("graph_steps", [0, 2])
+def test_bubbles_moved_between_runs_are_marked_afresh(graph_steps):
+    """Inside lbm_run each overlapped step marks the next step's region after its bubble update;
+    a new call (or a single bubbles_step) marks afresh from the caller's bubble state, and marks
+    left over from the previous call only widen the region: identical to the serial step."""
+    print(f"overlap with host moves between runs, graph_steps {graph_steps}", flush=True)
+    a = _run_with_moves(False, graph_steps)
+    b = _run_with_moves(True, graph_steps)
+    _same(a, b)
