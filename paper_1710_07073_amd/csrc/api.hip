@@ -14,7 +14,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t tiles[2], region[2], region_list[2], region_count, tcount, tlist, ovf, partials, result,
+  size_t tiles[2], region[2], region_list[2], region_count, tcount, tlist, partials, result,
       status, total;
   uint32_t ntiles, nred, tnx, tny, tnz;
 };
@@ -56,8 +56,7 @@ Layout layout_of(const lbm_desc* d) {
   L.region_count = align_up(L.region_list[1] + nrows * 4);
   L.tcount = align_up(L.region_count + 2 * sizeof(uint32_t));
   L.tlist = align_up(L.tcount + (size_t)L.ntiles * 4);
-  L.ovf = align_up(L.tlist + (size_t)L.ntiles * lbm::kTileCap * 4);
-  L.partials = align_up(L.ovf + sizeof(uint32_t));
+  L.partials = align_up(L.tlist + (size_t)L.ntiles * lbm::kTileCap * 4);
   L.result = align_up(L.partials + (size_t)L.nred * 4 * sizeof(double));
   L.status = align_up(L.result + 4 * sizeof(double));
   L.total = align_up(L.status + sizeof(int32_t));
@@ -121,7 +120,6 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->region_count = reinterpret_cast<uint32_t*>(s + L.region_count);
   c->tcount = reinterpret_cast<uint32_t*>(s + L.tcount);
   c->tlist = reinterpret_cast<uint32_t*>(s + L.tlist);
-  c->ovf = reinterpret_cast<uint32_t*>(s + L.ovf);
   c->ntiles = L.ntiles;
   c->nrows = L.tny * L.tnz;
   c->partials = reinterpret_cast<double*>(s + L.partials);

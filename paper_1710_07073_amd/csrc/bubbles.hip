@@ -150,6 +150,112 @@ __device__ __forceinline__ double block_sum(double v, double* s_red, int tid) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// Tiles of stencil windows.
+// ---------------------------------------------------------------------------------------------
+// Tile ranges touched along one axis by the cell range [vlo, vhi] (unwrapped on a periodic axis):
+// up to two ranges of tiles.
+struct TileRanges {
+  int n;
+  int lo[2], hi[2];
+};
+
+__device__ TileRanges tile_ranges(int vlo, int vhi, int ext, int tile, bool periodic) {
+  TileRanges t;
+  if (!periodic) {
+    vlo = vlo < 0 ? 0 : vlo;
+    vhi = vhi > ext - 1 ? ext - 1 : vhi;
+    t.n = vlo <= vhi ? 1 : 0;
+    t.lo[0] = vlo / tile;
+    t.hi[0] = vhi / tile;
+    return t;
+  }
+  if (vhi - vlo + 1 >= ext) {
+    t.n = 1;
+    t.lo[0] = 0;
+    t.hi[0] = (ext - 1) / tile;
+    return t;
+  }
+  const int a = wrapi(vlo, ext), b = wrapi(vhi, ext);
+  if (a <= b) {
+    t.n = 1;
+    t.lo[0] = a / tile;
+    t.hi[0] = b / tile;
+  } else if (b / tile >= a / tile) {  // the two wrapped pieces share a tile: every tile once
+    t.n = 1;
+    t.lo[0] = 0;
+    t.hi[0] = (ext - 1) / tile;
+  } else {
+    t.n = 2;
+    t.lo[0] = a / tile;
+    t.hi[0] = (ext - 1) / tile;
+    t.lo[1] = 0;
+    t.hi[1] = b / tile;
+  }
+  return t;
+}
+
+// Force window of a bubble at x0 (the clipped stencil window [clo, chi] of each axis).
+__device__ bool force_windows(const Geom& G, const double x0[3], double n, Axis win[3]) {
+  const int ext[3] = {G.nx, G.ny, G.nz};
+  for (int a = 0; a < 3; ++a)
+    if (!axis_window(x0[a], n, ext[a], G.bc[2 * a] == BC_PER, win[a])) return false;
+  return true;
+}
+
+// Calls f(tile) for every tile of the ranges tr, over the threads of the workgroup.
+template <class Fn>
+__device__ void for_tiles(const Geom& G, const TileRanges tr[3], int tid, int nthreads, Fn&& f) {
+  for (int rz = 0; rz < tr[2].n; ++rz)
+    for (int ry = 0; ry < tr[1].n; ++ry)
+      for (int rx = 0; rx < tr[0].n; ++rx) {
+        const int nx_ = tr[0].hi[rx] - tr[0].lo[rx] + 1;
+        const int ny_ = tr[1].hi[ry] - tr[1].lo[ry] + 1;
+        const int nz_ = tr[2].hi[rz] - tr[2].lo[rz] + 1;
+        for (int k = tid; k < nx_ * ny_ * nz_; k += nthreads) {
+          const int tx = tr[0].lo[rx] + k % nx_;
+          const int ty = tr[1].lo[ry] + (k / nx_) % ny_;
+          const int tz = tr[2].lo[rz] + k / (nx_ * ny_);
+          f(((uint32_t)tz * G.tny + ty) * G.tnx + tx);
+        }
+      }
+}
+
+// Tiles of the force window.
+__device__ void force_tiles(const Geom& G, const Axis win[3], TileRanges tr[3]) {
+  const int ext[3] = {G.nx, G.ny, G.nz};
+  for (int a = 0; a < 3; ++a)
+    tr[a] = tile_ranges(win[a].clo, win[a].chi, ext[a], (int)kTile, G.bc[2 * a] == BC_PER);
+}
+
+// Flags the tiles the liquid step must force (the force window now) or write the velocity in (the
+// velocity window, with the curl ring, that the next interpolation reads at the new position).
+template <typename T>
+__device__ void mark_tiles(const ColumnView<T>& col, const BubbleArgs& A, int b, const Axis win[3],
+                           double n, int tid, int nthreads) {
+  const Geom& G = col.G;
+  uint8_t* __restrict__ tiles = col.tiles;
+  const double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
+  const int ext[3] = {G.nx, G.ny, G.nz};
+  TileRanges tr[3];
+  for (int a = 0; a < 3; ++a) {
+    const bool per = G.bc[2 * a] == BC_PER;
+    int lo = win[a].clo, hi = win[a].chi;
+    Axis nw;
+    if (axis_window(xn[a], n, ext[a], per, nw)) {
+      lo = min(lo, nw.dlo);
+      hi = max(hi, nw.dhi);
+    }
+    tr[a] = tile_ranges(lo, hi, ext[a], (int)kTile, per);
+  }
+  for_tiles(G, tr, tid, nthreads, [&](uint32_t t) {
+    tiles[t] = 1;
+    // in an overlapped step the bulk launch has updated the rows outside the region
+    // concurrently: a tile forced or needing the velocity there is an error
+    if (col.region && !col.region[t / (uint32_t)G.tnx]) atomicOr(A.status, (int32_t)STATUS_REGION_MISS);
+  });
+}
+
+// ---------------------------------------------------------------------------------------------
 // Forward coupling: u_l = sum W U and w_l = sum W curl U over the window.
 // ---------------------------------------------------------------------------------------------
 template <typename T, typename Geo>
@@ -160,12 +266,9 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   const int b = bubble_of_block(A.nb);
   const int tid = threadIdx.x;
   if constexpr (std::is_same_v<Geo, OneColumn>) {
-    // a new step of the deterministic spreading: no list has overflowed yet; in an overlapped
-    // step, the other parity's region list (its region launch ran before) starts empty
-    if (blockIdx.x == 0 && tid == 0) {
-      *geo.ovf = 0u;
-      if (geo.clear_count) *geo.clear_count = 0u;
-    }
+    // in an overlapped step, the other parity's region list (its region launch ran before)
+    // starts empty
+    if (blockIdx.x == 0 && tid == 0 && geo.clear_count) *geo.clear_count = 0u;
   }
   const ColumnView<T> col = geo.template view<T>(b);
   const Geom& G = col.G;
@@ -189,6 +292,16 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   }
   // the weights at x0 for the spreading of this step
   for (int i = tid; i < 3 * kSpan; i += kBlock) work[W_WGT + i] = s_w[i / kSpan][i % kSpan];
+  if constexpr (std::is_same_v<Geo, OneColumn>) {
+    if (geo.lists) {  // enter the bubble in the list of every tile of its force window
+      TileRanges tr[3];
+      force_tiles(G, win, tr);
+      for_tiles(G, tr, tid, kBlock, [&](uint32_t t) {
+        const uint32_t slot = atomicAdd(&geo.tcount[t], 1u);
+        if (slot < kTileCap) geo.tlist[(size_t)t * kTileCap + slot] = (uint32_t)b;
+      });
+    }
+  }
   const int Dx = win[0].dhi - win[0].dlo + 1;
   const int Dy = win[1].dhi - win[1].dlo + 1;
   const int Dz = win[2].dhi - win[2].dlo + 1;
@@ -373,86 +486,19 @@ __global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
     A.S.psiy[b] = psi[1];
     A.S.psiz[b] = psi[2];
   }
+  if constexpr (std::is_same_v<Geo, OneColumn>) {
+    if (geo.lists) {  // the spreading gathers per tile: flag this bubble's tiles here, in one lane
+      const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+      const double n = P.kernel_factor * d;
+      Axis win[3];
+      if (force_windows(G, x0, n, win)) mark_tiles<float>(col, A, b, win, n, 0, 1);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Backward coupling and tile flags.
 // ---------------------------------------------------------------------------------------------
-// Tile ranges touched along one axis by the cell range [vlo, vhi] (unwrapped on a periodic axis):
-// up to two ranges of tiles.
-struct TileRanges {
-  int n;
-  int lo[2], hi[2];
-};
-
-__device__ TileRanges tile_ranges(int vlo, int vhi, int ext, int tile, bool periodic) {
-  TileRanges t;
-  if (!periodic) {
-    vlo = vlo < 0 ? 0 : vlo;
-    vhi = vhi > ext - 1 ? ext - 1 : vhi;
-    t.n = vlo <= vhi ? 1 : 0;
-    t.lo[0] = vlo / tile;
-    t.hi[0] = vhi / tile;
-    return t;
-  }
-  if (vhi - vlo + 1 >= ext) {
-    t.n = 1;
-    t.lo[0] = 0;
-    t.hi[0] = (ext - 1) / tile;
-    return t;
-  }
-  const int a = wrapi(vlo, ext), b = wrapi(vhi, ext);
-  if (a <= b) {
-    t.n = 1;
-    t.lo[0] = a / tile;
-    t.hi[0] = b / tile;
-  } else if (b / tile >= a / tile) {  // the two wrapped pieces share a tile: every tile once
-    t.n = 1;
-    t.lo[0] = 0;
-    t.hi[0] = (ext - 1) / tile;
-  } else {
-    t.n = 2;
-    t.lo[0] = a / tile;
-    t.hi[0] = (ext - 1) / tile;
-    t.lo[1] = 0;
-    t.hi[1] = b / tile;
-  }
-  return t;
-}
-
-// Force window of a bubble at x0 (the clipped stencil window [clo, chi] of each axis).
-__device__ bool force_windows(const Geom& G, const double x0[3], double n, Axis win[3]) {
-  const int ext[3] = {G.nx, G.ny, G.nz};
-  for (int a = 0; a < 3; ++a)
-    if (!axis_window(x0[a], n, ext[a], G.bc[2 * a] == BC_PER, win[a])) return false;
-  return true;
-}
-
-// Calls f(tile) for every tile of the ranges tr, over the threads of the workgroup.
-template <class Fn>
-__device__ void for_tiles(const Geom& G, const TileRanges tr[3], int tid, int nthreads, Fn&& f) {
-  for (int rz = 0; rz < tr[2].n; ++rz)
-    for (int ry = 0; ry < tr[1].n; ++ry)
-      for (int rx = 0; rx < tr[0].n; ++rx) {
-        const int nx_ = tr[0].hi[rx] - tr[0].lo[rx] + 1;
-        const int ny_ = tr[1].hi[ry] - tr[1].lo[ry] + 1;
-        const int nz_ = tr[2].hi[rz] - tr[2].lo[rz] + 1;
-        for (int k = tid; k < nx_ * ny_ * nz_; k += nthreads) {
-          const int tx = tr[0].lo[rx] + k % nx_;
-          const int ty = tr[1].lo[ry] + (k / nx_) % ny_;
-          const int tz = tr[2].lo[rz] + k / (nx_ * ny_);
-          f(((uint32_t)tz * G.tny + ty) * G.tnx + tx);
-        }
-      }
-}
-
-// Tiles of the force window.
-__device__ void force_tiles(const Geom& G, const Axis win[3], TileRanges tr[3]) {
-  const int ext[3] = {G.nx, G.ny, G.nz};
-  for (int a = 0; a < 3; ++a)
-    tr[a] = tile_ranges(win[a].clo, win[a].chi, ext[a], (int)kTile, G.bc[2 * a] == BC_PER);
-}
-
 // Backward coupling by atomic adds: F(j) += psi W_j over the force window (eq. (21)).
 template <typename T>
 __device__ void spread_atomic(const Geom& G, T* __restrict__ F, const Axis win[3],
@@ -479,34 +525,6 @@ __device__ void spread_atomic(const Geom& G, T* __restrict__ F, const Axis win[3
   }
 }
 
-// Flags the tiles the liquid step must force (the force window now) or write the velocity in (the
-// velocity window, with the curl ring, that the next interpolation reads at the new position).
-template <typename T>
-__device__ void mark_tiles(const ColumnView<T>& col, const BubbleArgs& A, int b, const Axis win[3],
-                           double n, int tid) {
-  const Geom& G = col.G;
-  uint8_t* __restrict__ tiles = col.tiles;
-  const double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
-  const int ext[3] = {G.nx, G.ny, G.nz};
-  TileRanges tr[3];
-  for (int a = 0; a < 3; ++a) {
-    const bool per = G.bc[2 * a] == BC_PER;
-    int lo = win[a].clo, hi = win[a].chi;
-    Axis nw;
-    if (axis_window(xn[a], n, ext[a], per, nw)) {
-      lo = min(lo, nw.dlo);
-      hi = max(hi, nw.dhi);
-    }
-    tr[a] = tile_ranges(lo, hi, ext[a], (int)kTile, per);
-  }
-  for_tiles(G, tr, tid, kBlock, [&](uint32_t t) {
-    tiles[t] = 1;
-    // in an overlapped step the bulk launch has updated the rows outside the region
-    // concurrently: a tile forced or needing the velocity there is an error
-    if (col.region && !col.region[t / (uint32_t)G.tnx]) atomicOr(A.status, (int32_t)STATUS_REGION_MISS);
-  });
-}
-
 // Backward coupling of one bubble per workgroup by atomic adds, and the tile flags.
 template <typename T, typename Geo>
 __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
@@ -522,41 +540,19 @@ __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
   Axis win[3];
   if (!build_weights(col.G, x0, n, tid, s_w, s_dw, win)) return;  // validated by k_interp
   spread_atomic<T>(col.G, col.F, win, s_w, work, tid);
-  mark_tiles<T>(col, A, b, win, n, tid);
+  mark_tiles<T>(col, A, b, win, n, tid, kBlock);
 }
 
-// ---- deterministic backward coupling (gather per tile), for many bubbles on one lattice ----
+// ---- deterministic backward coupling (gather per tile), for several bubbles on one lattice ----
 //
-// k_spread_fill     per bubble: enters the bubble in the list of each tile of its force window
-//                   (kTileCap entries per tile; a full list sets the overflow flag) and flags the
-//                   tiles for the liquid step;
-// k_spread_gather   per tile: sorts the tile's bubbles by index and sums psi_b W_b(j) in that order
-//                   in double precision, with the weights k_interp stored at x0: F(j) does not
-//                   depend on the order in which workgroups ran. With one bubble per cell the sum
-//                   is the atomic path's single addition, bit for bit;
-// k_spread_fallback per bubble, only after an overflow: atomic adds, as k_spread.
-__global__ __launch_bounds__(kBlock) void k_spread_fill(OneColumn geo, BubbleArgs A) {
-  const int b = bubble_of_block(A.nb);
-  const int tid = threadIdx.x;
-  const ColumnView<float> col = geo.view<float>(b);  // geometry, flags and region only
-  const double* work = A.S.work + (size_t)b * kWork;
-  if (work[W_VALID] == 0.0) return;
-  const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
-  const double n = A.P.kernel_factor * A.S.d[b];
-  Axis win[3];
-  if (!force_windows(col.G, x0, n, win)) return;  // validated by k_interp
-  TileRanges tr[3];
-  force_tiles(col.G, win, tr);
-  for_tiles(col.G, tr, tid, kBlock, [&](uint32_t t) {
-    const uint32_t slot = atomicAdd(&geo.tcount[t], 1u);
-    if (slot < kTileCap)
-      geo.tlist[(size_t)t * kTileCap + slot] = (uint32_t)b;
-    else
-      atomicOr(geo.ovf, 1u);
-  });
-  mark_tiles<float>(col, A, b, win, n, tid);
-}
-
+// k_interp enters each bubble in the list of every tile of its force window at x0 (kTileCap
+// entries per tile; the count keeps rising past a full list), k_ode flags the bubble's tiles for
+// the liquid step, and k_spread_gather, one workgroup per tile, sums psi_b W_b(j) over the tile's
+// bubbles in bubble order in double precision with the weights k_interp stored at x0. A tile
+// whose list overflowed finds its bubbles by a scan of all bubbles in index order instead, so the
+// sum has the same terms in the same order either way. F(j) does not depend on the order in
+// which workgroups ran; with one bubble per cell the sum is the atomic path's single addition,
+// bit for bit.
 // Sum of the weights of axis a (global copy, indexed cell - lo + 1) at the window cells congruent
 // to cell v (one cell unless a periodic window is wider than the lattice).
 __device__ __forceinline__ double axis_weight_at(const Axis& A, const double* w_a, int v, int ext,
@@ -569,86 +565,116 @@ __device__ __forceinline__ double axis_weight_at(const Axis& A, const double* w_
   return s;
 }
 
+__device__ __forceinline__ bool in_tile_ranges(const TileRanges& r, int t) {
+  for (int i = 0; i < r.n; ++i)
+    if (t >= r.lo[i] && t <= r.hi[i]) return true;
+  return false;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_spread_gather(OneColumn geo, BubbleArgs A) {
+  static_assert(kTileCap == 64, "one wavefront compacts a chunk of the overflow scan");
   __shared__ uint32_t s_list[kTileCap];
   __shared__ uint32_t s_sorted[kTileCap];
   __shared__ Axis s_win[kTileCap][3];
   __shared__ double s_psi[kTileCap][3];
+  __shared__ uint32_t s_n;
   const uint32_t t = blockIdx.x;
   const int tid = threadIdx.x;
   const Geom& G = geo.G;
   const uint32_t cnt = geo.tcount[t];
   if (cnt == 0u) return;
-  if (*geo.ovf) {  // this step spreads by atomic adds: only reset the count
-    if (tid == 0) geo.tcount[t] = 0u;
-    return;
-  }
-  const uint32_t n = cnt;  // <= kTileCap: no list overflowed
-  if (tid < (int)n) s_list[tid] = geo.tlist[(size_t)t * kTileCap + tid];
-  __syncthreads();
-  if (tid < (int)n) {  // rank sort (ties, which the lists do not hold, would keep list order)
-    const uint32_t v = s_list[tid];
-    uint32_t r = 0;
-    for (uint32_t j = 0; j < n; ++j) r += (s_list[j] < v || (s_list[j] == v && j < (uint32_t)tid)) ? 1u : 0u;
-    s_sorted[r] = v;
-  }
-  __syncthreads();
-  if (tid < (int)n) {
-    const uint32_t b = s_sorted[tid];
+  const uint32_t tx = t % (uint32_t)G.tnx, rr = t / (uint32_t)G.tnx;
+  const uint32_t ty = rr % (uint32_t)G.tny, tz = rr / (uint32_t)G.tny;
+  const int x = (int)(tx * kTile + (tid & 7)), y = (int)(ty * kTile + ((tid >> 3) & 7));
+  const int z0 = (int)(tz * kTile + (tid >> 6));
+  const bool inside = x < G.nx && y < G.ny;
+  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+  // bubble b's force window and reaction into slot k of the staged chunk
+  auto stage = [&](uint32_t b, int k) {
     const double* work = A.S.work + (size_t)b * kWork;
     const double xb[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
     Axis win[3];
     force_windows(G, xb, A.P.kernel_factor * A.S.d[b], win);  // valid: the bubble was listed
     for (int a = 0; a < 3; ++a) {
-      s_win[tid][a] = win[a];
-      s_psi[tid][a] = work[W_PSI + a];
+      s_win[k][a] = win[a];
+      s_psi[k][a] = work[W_PSI + a];
     }
-  }
-  __syncthreads();
-  const uint32_t tx = t % (uint32_t)G.tnx, rr = t / (uint32_t)G.tnx;
-  const uint32_t ty = rr % (uint32_t)G.tny, tz = rr / (uint32_t)G.tny;
-  const int x = (int)(tx * kTile + (tid & 7)), y = (int)(ty * kTile + ((tid >> 3) & 7));
-  const int z0 = (int)(tz * kTile + (tid >> 6));
-  if (x >= G.nx || y >= G.ny) return;
-  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+  };
   double acc[2][3] = {{0, 0, 0}, {0, 0, 0}};
-  for (uint32_t k = 0; k < n; ++k) {
-    const double* wk = A.S.work + (size_t)s_sorted[k] * kWork + W_WGT;
-    const double wx = axis_weight_at(s_win[k][0], wk, x, G.nx, px);
-    const double wy = axis_weight_at(s_win[k][1], wk + kSpan, y, G.ny, py);
-    for (int h = 0; h < 2; ++h) {
-      const double wz = axis_weight_at(s_win[k][2], wk + 2 * kSpan, z0 + 4 * h, G.nz, pz);
-      const double W = wx * wy * wz;
-      for (int q = 0; q < 3; ++q) acc[h][q] += s_psi[k][q] * W;
+  // adds the terms of the n staged bubbles s_sorted[0..n), in that order
+  auto add = [&](uint32_t n) {
+    if (!inside) return;
+    for (uint32_t k = 0; k < n; ++k) {
+      const double* wk = A.S.work + (size_t)s_sorted[k] * kWork + W_WGT;
+      const double wx = axis_weight_at(s_win[k][0], wk, x, G.nx, px);
+      const double wy = axis_weight_at(s_win[k][1], wk + kSpan, y, G.ny, py);
+      for (int h = 0; h < 2; ++h) {
+        const double wz = axis_weight_at(s_win[k][2], wk + 2 * kSpan, z0 + 4 * h, G.nz, pz);
+        const double W = wx * wy * wz;
+        for (int q = 0; q < 3; ++q) acc[h][q] += s_psi[k][q] * W;
+      }
+    }
+  };
+  if (cnt <= kTileCap) {
+    const uint32_t n = cnt;
+    if (tid < (int)n) s_list[tid] = geo.tlist[(size_t)t * kTileCap + tid];
+    __syncthreads();
+    if (tid < (int)n) {  // rank sort (ties, which the lists do not hold, would keep list order)
+      const uint32_t v = s_list[tid];
+      uint32_t r = 0;
+      for (uint32_t j = 0; j < n; ++j) r += (s_list[j] < v || (s_list[j] == v && j < (uint32_t)tid)) ? 1u : 0u;
+      s_sorted[r] = v;
+    }
+    __syncthreads();
+    if (tid < (int)n) stage(s_sorted[tid], tid);
+    __syncthreads();
+    add(n);
+  } else {
+    // the list overflowed: every bubble whose force window holds this tile, by a scan of all
+    // bubbles in index order, one chunk of 64 per pass compacted by the first wavefront
+    for (int base = 0; base < A.nb; base += kTileCap) {
+      if (tid < kTileCap) {
+        const int b = base + tid;
+        bool cov = false;
+        if (b < A.nb) {
+          const double* work = A.S.work + (size_t)b * kWork;
+          if (work[W_VALID] != 0.0) {
+            const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+            Axis win[3];
+            if (force_windows(G, x0, A.P.kernel_factor * A.S.d[b], win)) {
+              TileRanges tr[3];
+              force_tiles(G, win, tr);
+              cov = in_tile_ranges(tr[0], (int)tx) && in_tile_ranges(tr[1], (int)ty) &&
+                    in_tile_ranges(tr[2], (int)tz);
+            }
+          }
+        }
+        const uint64_t m = __ballot(cov);
+        if (cov) {
+          const int k = __popcll(m & ((1ull << tid) - 1ull));
+          s_sorted[k] = (uint32_t)b;
+          stage((uint32_t)b, k);
+        }
+        if (tid == 0) s_n = (uint32_t)__popcll(m);
+      }
+      __syncthreads();
+      add(s_n);
+      __syncthreads();
     }
   }
-  T* __restrict__ F = static_cast<T*>(geo.F);
-  for (int h = 0; h < 2; ++h) {
-    const int z = z0 + 4 * h;
-    if (z >= G.nz) continue;
-    const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
-    F[c] = (T)acc[h][0];
-    F[G.N + c] = (T)acc[h][1];
-    F[2 * (size_t)G.N + c] = (T)acc[h][2];
+  if (inside) {
+    T* __restrict__ F = static_cast<T*>(geo.F);
+    for (int h = 0; h < 2; ++h) {
+      const int z = z0 + 4 * h;
+      if (z >= G.nz) continue;
+      const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
+      F[c] = (T)acc[h][0];
+      F[G.N + c] = (T)acc[h][1];
+      F[2 * (size_t)G.N + c] = (T)acc[h][2];
+    }
   }
   if (tid == 0) geo.tcount[t] = 0u;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spread_fallback(OneColumn geo, BubbleArgs A) {
-  __shared__ double s_w[3][kSpan];
-  __shared__ double s_dw[3][kSpan];
-  if (*geo.ovf == 0u) return;
-  const int b = bubble_of_block(A.nb);
-  const int tid = threadIdx.x;
-  const ColumnView<T> col = geo.view<T>(b);
-  const double* work = A.S.work + (size_t)b * kWork;
-  if (work[W_VALID] == 0.0) return;
-  const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
-  Axis win[3];
-  if (!build_weights(col.G, x0, A.P.kernel_factor * A.S.d[b], tid, s_w, s_dw, win)) return;
-  spread_atomic<T>(col.G, col.F, win, s_w, work, tid);
 }
 
 // Region of an overlapped step (one wavefront per bubble): the tile rows (y, z) of the bubble's
@@ -706,19 +732,10 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    if (nb > 1) {  // several bubbles: deterministic spreading through per-tile lists
+    if (geo.lists) {  // several bubbles: the lists k_interp filled, summed per tile
       const uint32_t ntiles = (uint32_t)geo.G.tnx * geo.G.tny * div_up(geo.G.nz, kTile);
-      hipLaunchKernelGGL(k_spread_fill, dim3(nb), dim3(kBlock), 0, stream, geo, A);
-      e = hipGetLastError();
-      if (e == hipSuccess) {
-        hipLaunchKernelGGL((k_spread_gather<T>), dim3(ntiles), dim3(kBlock), 0, stream, geo, A);
-        e = hipGetLastError();
-      }
-      if (e == hipSuccess) {
-        hipLaunchKernelGGL((k_spread_fallback<T>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
-        e = hipGetLastError();
-      }
-      return e;
+      hipLaunchKernelGGL((k_spread_gather<T>), dim3(ntiles), dim3(kBlock), 0, stream, geo, A);
+      return hipGetLastError();
     }
   }
   hipLaunchKernelGGL((k_spread<T, Geo>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
@@ -752,7 +769,7 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
   geo.region = nullptr;
   geo.tcount = c->tcount;
   geo.tlist = c->tlist;
-  geo.ovf = c->ovf;
+  geo.lists = nb > 1;
   geo.clear_count = nullptr;
   geo.next_region = nullptr;
   geo.next_list = nullptr;

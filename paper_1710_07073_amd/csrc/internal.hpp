@@ -45,10 +45,9 @@ struct lbm_ctx {
   uint32_t* region_list[2];
   uint32_t* region_count;  // [2]
   // per-tile bubble lists of the deterministic force spreading: bubbles per tile (zero between
-  // steps), kTileCap list entries per tile, and the overflow flag
+  // steps) and kTileCap list entries per tile
   uint32_t* tcount;
   uint32_t* tlist;
-  uint32_t* ovf;
   lbm::HostState hs;
   bool overlap;               // overlap enabled (lbm_set_overlap)
   hipStream_t side;           // null if it could not be created (overlap then unavailable)
@@ -83,8 +82,8 @@ struct ColumnView {
   const uint32_t* region;  // region flags of an overlapped step (tiles the spread may force), or null
 };
 
-// A single lattice (lbm_ctx). tcount/tlist/ovf: the per-tile bubble lists of the deterministic
-// spreading (kTileCap entries per tile) and their overflow flag.
+// A single lattice (lbm_ctx). tcount/tlist: the per-tile bubble lists of the deterministic
+// spreading (kTileCap entries per tile; a count above kTileCap marks an overflowed list).
 struct OneColumn {
   Geom G;
   void* U;
@@ -94,7 +93,7 @@ struct OneColumn {
   const uint32_t* region;
   uint32_t* tcount;
   uint32_t* tlist;
-  uint32_t* ovf;
+  bool lists;  // several bubbles: spread through the per-tile lists
   // overlapped steps: the counter k_interp clears (null: none), and where the region of the next
   // step is marked after the bubble update (next_region null: not here)
   uint32_t* clear_count;

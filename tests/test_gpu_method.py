@@ -177,10 +177,10 @@ def test_many_overlapping_bubbles_are_bitwise_reproducible(prec):
 
 
 @pytest.mark.gpu
-def test_spreading_list_overflow_falls_back_and_matches_oracle():
+def test_spreading_list_overflow_is_reproducible_and_matches_oracle():
     """80 bubbles packed into one 8^3 block: the tiles around it are in more than 64 force
-    windows, more than a tile's list holds, so the step spreads by atomic adds; it still matches
-    the oracle."""
+    windows, more than a tile's list holds, so those tiles find their bubbles by a scan in bubble
+    order; the step still matches the oracle and repeats bit for bit."""
     rng = np.random.default_rng(41)
     pos = rng.uniform(20.0, 27.99, (3, 80))
     w = W.Workload("clustered_80", (48, 48, 48), 1.3, (BB,) * 6, pos, rng.uniform(2.0, 3.0, 80),
@@ -188,7 +188,13 @@ def test_spreading_list_overflow_falls_back_and_matches_oracle():
     print(f"[case] {w.name}: {w.nb} bubbles in one 8^3 block", flush=True)
     sim, lat, bub, worst = _run_both(w, w.steps, check_every=3)
     u, _ = gpu_u(sim)
+    g1 = sim.populations().cpu().numpy()
     _, u_o, _ = lat.moments()
     assert rel_l2(u, u_o) <= U_TOL["f64"]
     assert worst <= POS_TOL
+    sim.close()
+    sim = gpu_sim(w)
+    sim.step(w.steps)
+    assert np.array_equal(sim.populations().cpu().numpy(), g1)
+    sim.check()
     sim.close()
