@@ -14,6 +14,10 @@ over steps. Section / equation / table / algorithm citations are to the paper:
 * ``kernel_Z``, ``kernel_P``, ``axis_weights``, ``interpolate``, ``spread``: Sec. 3.2, eq. (18)-(21)
 * ``closures``, ``drag_lift``, ``bubble_ode``: Sec. 2.1, eq. (1)-(4), Table 1
 * ``method_step``, ``run``: Algorithm 1
+* coupling variants (``bubble_params(coupling=...)``, bits ``REACTION_SUBSTEP_MEAN``,
+  ``REACTION_NET_FORCE``, ``POINT_KERNEL``, ``EXACT_TIME``): the reaction of Sec. 3.2 against that
+  of Algorithm 1, point-sampled instead of cell-integral weights (eq. (18)-(19)), and the time
+  level of the forward coupling
 
 Populations are stored shifted, g = f - w, structure-of-arrays ``g[q, z, y, x]`` in the
 paper's velocity order (axis directions, face diagonals, rest).
@@ -51,13 +55,20 @@ class BubbleParams(ct.Structure):
     _fields_ = [("g", ct.c_double), ("rho_l", ct.c_double), ("rho_b", ct.c_double),
                 ("sigma", ct.c_double), ("c_a", ct.c_double), ("drag_scale", ct.c_double),
                 ("lift_scale", ct.c_double), ("kernel_factor", ct.c_double), ("cd_k", ct.c_double),
-                ("lift_f0", ct.c_double), ("n_sub", ct.c_int32), ("pad", ct.c_int32)]
+                ("lift_f0", ct.c_double), ("n_sub", ct.c_int32), ("coupling", ct.c_int32)]
+
+# coupling variant bits (lbm_oracle.cpp, ORC_*)
+REACTION_SUBSTEP_MEAN = 1
+REACTION_NET_FORCE = 2
+POINT_KERNEL = 4
+EXACT_TIME = 8
 
 
 def bubble_params(g=1e-5, rho_l=1.0, rho_b=1e-3, sigma=4.19e-5, c_a=0.5, drag_scale=1.0,
-                  lift_scale=1.0, kernel_factor=1.5, cd_k=0.15, lift_f0=0.474, n_sub=10):
+                  lift_scale=1.0, kernel_factor=1.5, cd_k=0.15, lift_f0=0.474, n_sub=10,
+                  coupling=0):
     return BubbleParams(g, rho_l, rho_b, sigma, c_a, drag_scale, lift_scale, kernel_factor, cd_k,
-                        lift_f0, n_sub, 0)
+                        lift_f0, n_sub, int(coupling))
 
 
 _lib = None
@@ -82,7 +93,8 @@ def lib():
         L.orc_kernel_Z.restype = ct.c_double
         L.orc_kernel_P.argtypes = [ct.c_double]
         L.orc_kernel_P.restype = ct.c_double
-        L.orc_axis_weights.argtypes = [ct.c_double, ct.c_double, ct.c_int, ct.c_int, _I, _D, ct.c_int]
+        L.orc_axis_weights.argtypes = [ct.c_double, ct.c_double, ct.c_int, ct.c_int, _I, _D, ct.c_int,
+                                       ct.c_int]
         L.orc_lbm_step.argtypes = [ct.c_int, ct.c_int, ct.c_int, _I, ct.c_double, _D, _D, _D, _D,
                                    ct.c_int]
         L.orc_stream.argtypes = [ct.c_int, ct.c_int, ct.c_int, _I, _D, _D]
@@ -97,8 +109,9 @@ def lib():
         L.orc_bubble_ode.argtypes = [ct.POINTER(BubbleParams), ct.c_double, ct.c_double, ct.c_int,
                                      ct.c_double, _D, _D, _D, _D, _D, _D, _D, _I, _I, _D, _D]
         L.orc_bubble_ode.restype = None
-        L.orc_interpolate.argtypes = [ct.c_int, ct.c_int, ct.c_int, _I, _D, _D, ct.c_double, _D, _D]
-        L.orc_spread.argtypes = [ct.c_int, ct.c_int, ct.c_int, _I, _D, ct.c_double, _D, _D]
+        L.orc_interpolate.argtypes = [ct.c_int, ct.c_int, ct.c_int, _I, _D, _D, ct.c_double, _D, _D,
+                                      ct.c_int]
+        L.orc_spread.argtypes = [ct.c_int, ct.c_int, ct.c_int, _I, _D, ct.c_double, _D, _D, ct.c_int]
         L.orc_method_step.argtypes = [ct.c_int, ct.c_int, ct.c_int, _I, ct.c_double,
                                       ct.POINTER(BubbleParams), ct.c_int, _D, _D, _D, _D, _I, _D, _D,
                                       _D, _D, _D, ct.c_int]
@@ -249,32 +262,33 @@ def kernel_P(s):
     return lib().orc_kernel_P(float(s))
 
 
-def axis_weights(xb, n, N, periodic=False):
+def axis_weights(xb, n, N, periodic=False, point=False):
     cap = 4 * int(np.ceil(n)) + 8
     idx = np.zeros(cap, np.int32)
     w = np.zeros(cap)
-    k = lib().orc_axis_weights(float(xb), float(n), int(N), int(bool(periodic)), _i(idx), _d(w), cap)
+    k = lib().orc_axis_weights(float(xb), float(n), int(N), int(bool(periodic)), _i(idx), _d(w), cap,
+                               int(bool(point)))
     if k < 0:
-        raise ValueError("axis_weights capacity")
+        raise ValueError("axis_weights capacity or empty point-sampled window")
     return idx[:k].copy(), w[:k].copy()
 
 
-def interpolate(U, bc, xb, n):
+def interpolate(U, bc, xb, n, point=False):
     U = np.ascontiguousarray(U, dtype=np.float64)
     _, nz, ny, nx = U.shape
     ul = np.zeros(3)
     wl = np.zeros(3)
     _check(lib().orc_interpolate(nx, ny, nz, _i(_bc(bc)), _d(U), _d(_vec(xb)), float(n), _d(ul),
-                                 _d(wl)), "interpolate")
+                                 _d(wl), int(bool(point))), "interpolate")
     return ul, wl
 
 
-def spread(F, bc, xb, n, psi):
+def spread(F, bc, xb, n, psi, point=False):
     """F (3, nz, ny, nx) += psi * W, in place."""
     assert F.dtype == np.float64 and F.flags.c_contiguous
     _, nz, ny, nx = F.shape
-    _check(lib().orc_spread(nx, ny, nz, _i(_bc(bc)), _d(_vec(xb)), float(n), _d(_vec(psi)), _d(F)),
-           "spread")
+    _check(lib().orc_spread(nx, ny, nz, _i(_bc(bc)), _d(_vec(xb)), float(n), _d(_vec(psi)), _d(F),
+                            int(bool(point))), "spread")
     return F
 
 

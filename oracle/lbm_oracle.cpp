@@ -181,13 +181,18 @@ double kernel_P(double s) {
 // Cell-integral weights along one axis, eq. (19) factorised: w(i) = integral of Z(x - xb) over
 // the cell [i - 1/2, i + 1/2]. Cells outside a wall are dropped and the axis is renormalised to a
 // sum of one ("clipped"); on a periodic axis the cell index wraps. Returns the count.
-int axis_weights(double xb, double n, int N, bool periodic, int* idx, double* w, int cap) {
+// point != 0 selects the point-sampled alternative of the coupling variants: w(i) = Z(i - xb) at
+// the cell centre, renormalised to a sum of one on every axis (sampled values of Z do not sum to
+// one even without a wall).
+int axis_weights(double xb, double n, int N, bool periodic, int* idx, double* w, int cap,
+                 bool point = false) {
   const int lo = (int)std::floor(xb - n - 0.5) + 1;
   const int hi = (int)std::ceil(xb + n + 0.5) - 1;
   int k = 0;
   double sum = 0.0;
   for (int i = lo; i <= hi; ++i) {
-    const double wi = kernel_P((i + 0.5 - xb) / n) - kernel_P((i - 0.5 - xb) / n);
+    const double wi = point ? kernel_Z(i - xb, n)
+                            : kernel_P((i + 0.5 - xb) / n) - kernel_P((i - 0.5 - xb) / n);
     int j = i;
     if (periodic) {
       j = wrap(i, N);
@@ -200,8 +205,9 @@ int axis_weights(double xb, double n, int N, bool periodic, int* idx, double* w,
     sum += wi;
     ++k;
   }
-  if (!periodic && sum > 0.0)
+  if ((!periodic || point) && sum > 0.0)
     for (int m = 0; m < k; ++m) w[m] /= sum;
+  if (point && !(sum > 0.0)) return -1;  // no cell centre inside the support
   return k;
 }
 
@@ -267,8 +273,19 @@ typedef struct {
   double cd_k;           // constant in 24/Re (1 + k Re^0.687)
   double lift_f0;        // constant term of the lift polynomial f(Eo_d)
   int32_t n_sub;         // bubble sub-steps per liquid step (Table 2: dt_l / dt_b = 10)
-  int32_t pad;
+  int32_t coupling;      // coupling variant bits, ORC_* below (0 = the default reading)
 } orc_bubble_params;
+
+// Coupling variants (readings R3, R13, R16 and their alternatives):
+//   reaction (bits 0-1): 0 = -(F_D + F_L) at the updated velocity (Algorithm 1);
+//     1 = the mean of -(F_D + F_L) over the sub-steps (the impulse those forces gave the bubble
+//     during the liquid step, per unit time); 2 = -sum F, the net force of eq. (1) on the bubble,
+//     averaged over the sub-steps (Sec. 3.2 states the reaction as minus the sum of the forces);
+//   point-sampled kernel (bit 2): weights Z at cell centres instead of cell integrals;
+//   exact time (bit 3): the forward coupling interpolates the velocity of the current state f^n
+//     (eq. (10), no force term) instead of the velocity of the previous collision.
+enum { ORC_REACTION_MASK = 3, ORC_REACTION_SUBSTEP_MEAN = 1, ORC_REACTION_NET_FORCE = 2,
+       ORC_POINT_KERNEL = 4, ORC_EXACT_TIME = 8 };
 
 int orc_lattice(int32_t* c /*19x3*/, double* w /*19*/, int32_t* opp /*19*/) {
   for (int q = 0; q < 19; ++q) {
@@ -297,9 +314,10 @@ void orc_collide_node(double omega, const double* g, const double* F, double* ou
 double orc_kernel_Z(double r, double n) { return kernel_Z(r, n); }
 double orc_kernel_P(double s) { return kernel_P(s); }
 
-int orc_axis_weights(double xb, double n, int N, int periodic, int32_t* idx, double* w, int cap) {
+int orc_axis_weights(double xb, double n, int N, int periodic, int32_t* idx, double* w, int cap,
+                     int point) {
   std::vector<int> tmp(cap > 0 ? cap : 1);
-  int k = axis_weights(xb, n, N, periodic != 0, tmp.data(), w, cap);
+  int k = axis_weights(xb, n, N, periodic != 0, tmp.data(), w, cap, point != 0);
   for (int i = 0; i < k; ++i) idx[i] = tmp[i];
   return k;
 }
@@ -442,21 +460,28 @@ void orc_drag_lift(const orc_bubble_params* P, double nu, double d, const double
 // (1 + C_A) rho_l V D_t u_l. Position S = dt_b * (new velocity).
 // lo/hi (nullable): per axis position bounds [lo, hi] with clamp flags clamp_lo/hi[a] != 0 which
 // clamp the position and zero that velocity component; periodic axes pass len[a] > 0 to wrap.
-// psi (nullable): the reaction -(F_D + F_L) at the final velocity (Algorithm 1).
+// psi (nullable): the reaction spread into the liquid: by default -(F_D + F_L) at the final
+// velocity (Algorithm 1); the reaction bits of P->coupling select the sub-step mean of
+// -(F_D + F_L) or minus the mean net force m_b du_b/dt.
 void orc_bubble_ode(const orc_bubble_params* P, double nu, double dt_b, int n_sub, double d,
                     const double* ul, const double* wl, const double* dul, double* ub, double* xb,
                     const double* lo, const double* hi, const int32_t* clamp_lo,
                     const int32_t* clamp_hi, const double* len, double* psi) {
   const double pi = 3.14159265358979323846;
   const double V = pi * d * d * d / 6.0;
-  const double m_eff = P->rho_b * V + P->c_a * P->rho_l * V;
+  const double m_b = P->rho_b * V;
+  const double m_eff = m_b + P->c_a * P->rho_l * V;
   const double FB = (P->rho_l - P->rho_b) * V * P->g;  // buoyancy, +z
+  const int reaction = P->coupling & ORC_REACTION_MASK;
+  double sum_dl[3] = {0.0, 0.0, 0.0}, sum_net[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < n_sub; ++k) {
     double FD[3], FL[3];
     orc_drag_lift(P, nu, d, ub, ul, wl, FD, FL);
     for (int a = 0; a < 3; ++a) {
       double f = FD[a] + FL[a] + (1.0 + P->c_a) * P->rho_l * V * dul[a];
       if (a == 2) f += FB;
+      sum_dl[a] += FD[a] + FL[a];
+      sum_net[a] += m_b * (f / m_eff);  // eq. (1): the net force is m_b times the acceleration
       ub[a] += dt_b * f / m_eff;
     }
     for (int a = 0; a < 3; ++a) {
@@ -471,25 +496,31 @@ void orc_bubble_ode(const orc_bubble_params* P, double nu, double dt_b, int n_su
     }
   }
   if (psi) {
-    double FD[3], FL[3];
-    orc_drag_lift(P, nu, d, ub, ul, wl, FD, FL);
-    for (int a = 0; a < 3; ++a) psi[a] = -(FD[a] + FL[a]);
+    if (reaction == ORC_REACTION_SUBSTEP_MEAN) {
+      for (int a = 0; a < 3; ++a) psi[a] = -sum_dl[a] / n_sub;
+    } else if (reaction == ORC_REACTION_NET_FORCE) {
+      for (int a = 0; a < 3; ++a) psi[a] = -sum_net[a] / n_sub;
+    } else {
+      double FD[3], FL[3];
+      orc_drag_lift(P, nu, d, ub, ul, wl, FD, FL);
+      for (int a = 0; a < 3; ++a) psi[a] = -(FD[a] + FL[a]);
+    }
   }
 }
 
 // Forward coupling, eq. (20): u_l = sum_j U(j) W_j and w_l = sum_j curl U(j) W_j over the
 // separable cell weights of eq. (19) around position xb with half-width n.
 int orc_interpolate(int nx, int ny, int nz, const int32_t* bc, const double* U, const double* xb,
-                    double n, double* ul, double* wl) {
+                    double n, double* ul, double* wl, int point) {
   Grid G{{nx, ny, nz}, {bc[0], bc[1], bc[2], bc[3], bc[4], bc[5]}};
   if (!grid_ok(G)) return -1;
   const long N = G.cells();
   const int cap = 4 * (int)std::ceil(n) + 8;
   std::vector<int> ix(cap), iy(cap), iz(cap);
   std::vector<double> wx(cap), wy(cap), wz(cap);
-  const int kx = axis_weights(xb[0], n, nx, G.periodic(0), ix.data(), wx.data(), cap);
-  const int ky = axis_weights(xb[1], n, ny, G.periodic(1), iy.data(), wy.data(), cap);
-  const int kz = axis_weights(xb[2], n, nz, G.periodic(2), iz.data(), wz.data(), cap);
+  const int kx = axis_weights(xb[0], n, nx, G.periodic(0), ix.data(), wx.data(), cap, point != 0);
+  const int ky = axis_weights(xb[1], n, ny, G.periodic(1), iy.data(), wy.data(), cap, point != 0);
+  const int kz = axis_weights(xb[2], n, nz, G.periodic(2), iz.data(), wz.data(), cap, point != 0);
   if (kx < 0 || ky < 0 || kz < 0) return -2;
   for (int a = 0; a < 3; ++a) ul[a] = wl[a] = 0.0;
   for (int c = 0; c < kz; ++c)
@@ -509,16 +540,16 @@ int orc_interpolate(int nx, int ny, int nz, const int32_t* bc, const double* U, 
 
 // Backward coupling, eq. (21): F(j) += psi W_j with the same weights (added in place).
 int orc_spread(int nx, int ny, int nz, const int32_t* bc, const double* xb, double n,
-               const double* psi, double* F) {
+               const double* psi, double* F, int point) {
   Grid G{{nx, ny, nz}, {bc[0], bc[1], bc[2], bc[3], bc[4], bc[5]}};
   if (!grid_ok(G)) return -1;
   const long N = G.cells();
   const int cap = 4 * (int)std::ceil(n) + 8;
   std::vector<int> ix(cap), iy(cap), iz(cap);
   std::vector<double> wx(cap), wy(cap), wz(cap);
-  const int kx = axis_weights(xb[0], n, nx, G.periodic(0), ix.data(), wx.data(), cap);
-  const int ky = axis_weights(xb[1], n, ny, G.periodic(1), iy.data(), wy.data(), cap);
-  const int kz = axis_weights(xb[2], n, nz, G.periodic(2), iz.data(), wz.data(), cap);
+  const int kx = axis_weights(xb[0], n, nx, G.periodic(0), ix.data(), wx.data(), cap, point != 0);
+  const int ky = axis_weights(xb[1], n, ny, G.periodic(1), iy.data(), wy.data(), cap, point != 0);
+  const int kz = axis_weights(xb[2], n, nz, G.periodic(2), iz.data(), wz.data(), cap, point != 0);
   if (kx < 0 || ky < 0 || kz < 0) return -2;
   for (int c = 0; c < kz; ++c)
     for (int b = 0; b < ky; ++b)
@@ -542,6 +573,9 @@ int orc_method_step(int nx, int ny, int nz, const int32_t* bc, double omega,
                     double* psi_out, int nthreads) {
   Grid G{{nx, ny, nz}, {bc[0], bc[1], bc[2], bc[3], bc[4], bc[5]}};
   if (!grid_ok(G) || P->n_sub < 1) return -1;
+  if ((P->coupling & ~(ORC_REACTION_MASK | ORC_POINT_KERNEL | ORC_EXACT_TIME)) ||
+      (P->coupling & ORC_REACTION_MASK) > ORC_REACTION_NET_FORCE)
+    return -1;
   const long N = G.cells();
   std::fill(F, F + 3 * N, 0.0);
   const double nu = (1.0 / omega - 0.5) / 3.0;  // eq. (9), dx = dt = 1
@@ -555,19 +589,29 @@ int orc_method_step(int nx, int ny, int nz, const int32_t* bc, double omega,
     clo[a] = !G.periodic(a);
     chi[a] = !G.periodic(a) && a != 2;  // the top ends the bubble's life instead
   }
+  // the velocity the forward coupling reads: that of the previous collision, or (exact time) that
+  // of the current state f^n
+  const double* Ui = U;
+  std::vector<double> Un;
+  if (P->coupling & ORC_EXACT_TIME) {
+    Un.resize(3 * N);
+    orc_moments(nx, ny, nz, g, nullptr, Un.data(), nullptr);
+    Ui = Un.data();
+  }
+  const int point = (P->coupling & ORC_POINT_KERNEL) ? 1 : 0;
   for (int b = 0; b < nb; ++b) {
     if (state[b] == 0) continue;
     double x0[3] = {pos[b], pos[nb + b], pos[2 * nb + b]};
     double ub[3] = {vel[b], vel[nb + b], vel[2 * nb + b]};
     const double n = P->kernel_factor * d[b];
     double ul[3], wl[3], dul[3] = {0.0, 0.0, 0.0};
-    int rc = orc_interpolate(nx, ny, nz, bc, U, x0, n, ul, wl);
+    int rc = orc_interpolate(nx, ny, nz, bc, Ui, x0, n, ul, wl, point);
     if (rc) return rc;
     if (state[b] == 2)
       for (int a = 0; a < 3; ++a) dul[a] = ul[a] - ulp[a * nb + b];  // / dt_l, dt_l = 1
     double xn[3] = {x0[0], x0[1], x0[2]}, psi[3];
     orc_bubble_ode(P, nu, dt_b, P->n_sub, d[b], ul, wl, dul, ub, xn, lo, hi, clo, chi, len, psi);
-    rc = orc_spread(nx, ny, nz, bc, x0, n, psi, F);
+    rc = orc_spread(nx, ny, nz, bc, x0, n, psi, F, point);
     if (rc) return rc;
     for (int a = 0; a < 3; ++a) {
       pos[a * nb + b] = xn[a];
