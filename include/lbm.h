@@ -89,8 +89,30 @@ typedef struct {
   double cd_k;          /* k in C_D = 24/Re (1 + k Re^0.687) */
   double lift_f0;       /* constant term of the lift polynomial f(Eo_d) */
   int32_t n_sub;        /* bubble sub-steps per liquid step, dt_b = 1/n_sub (Table 2: 10) */
-  int32_t reserved;     /* must be 0 */
+  int32_t coupling;     /* LBM_COUPLING_* / LBM_REACTION_* bits; 0 = the default readings */
 } bubble_params;
+
+/* Coupling variants (bubble_params.coupling). The paper states the reaction spread into the
+ * liquid twice (Sec. 3.2: minus the sum of the forces on the bubble; Algorithm 1: -(F_D + F_L)
+ * from the updated velocity), the mapping weights as cell integrals of the kernel (eq. (19)),
+ * and leaves the time level of the forward coupling open. Default (0): -(F_D + F_L) at the
+ * velocity after the sub-steps, cell-integral weights, and the liquid velocity of the previous
+ * collision (the velocity field U the liquid step writes).
+ *   reaction (bits 0-1): LBM_REACTION_SUBSTEP_MEAN, the mean of -(F_D + F_L) over the sub-steps
+ *     (the impulse those forces gave the bubble in the liquid step); LBM_REACTION_NET_FORCE,
+ *     minus the mean over the sub-steps of the net force m_b du_b/dt of eq. (1);
+ *   LBM_COUPLING_POINT_KERNEL: weights Z(x_j - x_b) at cell centres, renormalised to a sum of one
+ *     on every axis (instead of cell integrals);
+ *   LBM_COUPLING_EXACT_TIME: the forward coupling interpolates the velocity of the current state
+ *     f^n (eq. (10), no force term), recomputed from the populations on the stencil, instead of
+ *     U. Single lattices only (lbm_batch_step returns LBM_EUNSUPPORTED).
+ * lbm_adjoint_bubbles differentiates the default only (LBM_EUNSUPPORTED otherwise). Other bits,
+ * or a reaction value of 3, give LBM_EINVAL. */
+#define LBM_REACTION_MASK 3
+#define LBM_REACTION_SUBSTEP_MEAN 1
+#define LBM_REACTION_NET_FORCE 2
+#define LBM_COUPLING_POINT_KERNEL 4
+#define LBM_COUPLING_EXACT_TIME 8
 
 /* Bubble state, structure of arrays of length nb in device memory (double precision).
  * state: 0 = inactive (reached the top layer, Algorithm 1 stop test), 1 = active without a

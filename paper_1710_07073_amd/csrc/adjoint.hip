@@ -423,7 +423,8 @@ lbm_status lbm_adjoint_bubbles(lbm_ctx* ctx, const bubble_params* p, const doubl
   if (nb == 0) return LBM_OK;
   (void)scratch;  // reserved
   if (!record || !vel_prev || !lam_f || !lam_u || !lam) return LBM_EINVAL;
-  if (p->n_sub < 1 || p->n_sub > kMaxSub || p->reserved != 0) return LBM_EINVAL;
+  if (p->n_sub < 1 || p->n_sub > kMaxSub) return LBM_EINVAL;
+  if (p->coupling != 0) return LBM_EUNSUPPORTED;  // the adjoint of the default coupling only
   const hipError_t e =
       ctx->elem == 4 ? bubbles_typed<float>(ctx, p, record, vel_prev, lam_f, lam_u, lam, nb, grad)
                      : bubbles_typed<double>(ctx, p, record, vel_prev, lam_f, lam_u, lam, nb, grad);

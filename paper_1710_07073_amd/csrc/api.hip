@@ -253,7 +253,7 @@ lbm_status bubble_half(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s
                        bool in_run) {
   if (!ctx || !p || !s || nb < 0) return LBM_EINVAL;
   if (ctx->desc.flags & LBM_FLAG_STATIC_FORCE) return LBM_EINVAL;
-  if (p->n_sub < 1 || p->reserved != 0) return LBM_EINVAL;
+  if (p->n_sub < 1 || !lbm::coupling_ok(p->coupling)) return LBM_EINVAL;
   if (!(p->kernel_factor > 0.0) || !(p->sigma > 0.0) || !(p->rho_l > 0.0)) return LBM_EINVAL;
   if (nb > 0) {
     if (!s->x || !s->y || !s->z || !s->ux || !s->uy || !s->uz || !s->d || !s->ulx || !s->uly ||

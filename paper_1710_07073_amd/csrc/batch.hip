@@ -419,8 +419,10 @@ lbm_status lbm_batch_step(lbm_batch* b, const bubble_params* p, const bubble_soa
                           int32_t nsteps) {
   if (!b || !p || !s || nb != b->nb_total || nsteps < 0) return LBM_EINVAL;
   if (nb > 0 && (b->flags & LBM_FLAG_STATIC_FORCE)) return LBM_EINVAL;
-  if (p->n_sub < 1 || p->reserved != 0 || !(p->kernel_factor > 0.0) || !(p->sigma > 0.0))
+  if (p->n_sub < 1 || !lbm::coupling_ok(p->coupling) || !(p->kernel_factor > 0.0) ||
+      !(p->sigma > 0.0))
     return LBM_EINVAL;
+  if (p->coupling & LBM_COUPLING_EXACT_TIME) return LBM_EUNSUPPORTED;
   if (nb > 0 && (!s->x || !s->y || !s->z || !s->ux || !s->uy || !s->uz || !s->d || !s->ulx ||
                  !s->uly || !s->ulz || !s->state || !s->work))
     return LBM_EINVAL;

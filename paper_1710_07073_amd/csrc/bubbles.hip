@@ -20,7 +20,7 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "internal.hpp"
+#include "collide.hpp"
 
 namespace lbm {
 namespace {
@@ -49,6 +49,14 @@ __device__ __forceinline__ double kernel_P(double s) {
   if (s >= 1.0) return 1.0;
   const double s2 = s * s;
   return 0.5 + 15.0 / 16.0 * (s - 2.0 / 3.0 * s2 * s + 0.2 * s2 * s2 * s);
+}
+
+// the kernel itself, eq. (18): Z(r) = 15/16 (s^4 - 2 s^2 + 1) / n with s = r / n on |s| <= 1
+__device__ __forceinline__ double kernel_Z(double r, double n) {
+  const double s = r / n;
+  if (s < -1.0 || s > 1.0) return 0.0;
+  const double s2 = s * s;
+  return 15.0 / 16.0 * (s2 * s2 - 2.0 * s2 + 1.0) / n;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -81,36 +89,48 @@ __device__ __forceinline__ bool axis_window(double x, double n, int ext, bool pe
 
 // Weights of one axis (eq. (19)): cell integrals of the kernel over the clipped window [clo, chi],
 // indexed by (cell - lo + 1), renormalised to a sum of one when a wall clips the window. One full
-// wavefront (lane = 0..63) computes; the renormalising sum is taken in a fixed order.
-__device__ void wave_axis_weights(const Axis& A, double xa, double n, bool per, int lane,
+// wavefront (lane = 0..63) computes; the renormalising sum is taken in a fixed order. point: the
+// point-sampled variant, Z at the cell centres renormalised on every axis. Returns false if a
+// point-sampled window holds no cell centre inside the kernel's support.
+__device__ bool wave_axis_weights(const Axis& A, double xa, double n, bool per, bool point, int lane,
                                   double* s_w_a) {
   double part = 0.0;
   for (int i = lane; i < kSpan; i += 64) {
     const int v = A.lo - 1 + i;
     double w = 0.0;
-    if (v >= A.clo && v <= A.chi) w = kernel_P((v + 0.5 - xa) / n) - kernel_P((v - 0.5 - xa) / n);
+    if (v >= A.clo && v <= A.chi)
+      w = point ? kernel_Z(v - xa, n) : kernel_P((v + 0.5 - xa) / n) - kernel_P((v - 0.5 - xa) / n);
     s_w_a[i] = w;
     part += w;
   }
-  if (!per) {
+  if (!per || point) {
     const double sum = wave_sum(part);
     if (sum > 0.0)
       for (int i = lane; i < kSpan; i += 64) s_w_a[i] /= sum;
+    return sum > 0.0 || !point;
   }
+  return true;
 }
 
 // Weights w and derivative weights dw of the bubble at xb along the three axes, into LDS,
-// indexed by (cell - lo + 1). Called by the whole workgroup; the first wavefront computes.
+// indexed by (cell - lo + 1). Called by the whole workgroup; the first wavefront computes. point:
+// the point-sampled variant of the weights.
 __device__ bool build_weights(const Geom& G, const double xb[3], double n, int tid,
-                              double (*s_w)[kSpan], double (*s_dw)[kSpan], Axis win[3]) {
+                              double (*s_w)[kSpan], double (*s_dw)[kSpan], Axis win[3],
+                              bool point) {
+  __shared__ int s_empty;
   const int ext[3] = {G.nx, G.ny, G.nz};
   for (int a = 0; a < 3; ++a) {
     const bool per = G.bc[2 * a] == BC_PER;
     if (!axis_window(xb[a], n, ext[a], per, win[a])) return false;
   }
   const int lane = tid;
-  if (tid < 64)
-    for (int a = 0; a < 3; ++a) wave_axis_weights(win[a], xb[a], n, G.bc[2 * a] == BC_PER, lane, s_w[a]);
+  if (tid < 64) {
+    bool ok = true;
+    for (int a = 0; a < 3; ++a)
+      ok = wave_axis_weights(win[a], xb[a], n, G.bc[2 * a] == BC_PER, point, lane, s_w[a]) && ok;
+    if (tid == 0) s_empty = ok ? 0 : 1;
+  }
   __syncthreads();
   if (tid < 64) {
   for (int a = 0; a < 3; ++a) {
@@ -132,7 +152,7 @@ __device__ bool build_weights(const Geom& G, const double xb[3], double n, int t
   }
   }
   __syncthreads();
-  return true;
+  return s_empty == 0;
 }
 
 // Bubble handled by a workgroup: consecutive workgroups on one XCD take consecutive bubbles, so
@@ -255,10 +275,35 @@ __device__ void mark_tiles(const ColumnView<T>& col, const BubbleArgs& A, int b,
   });
 }
 
+// Velocity of the current state at a cell, eq. (10) without a force term: the populations are
+// pulled from the post-collision buffer with the face conditions, as the moments kernel does.
+template <typename T>
+__device__ __forceinline__ void state_velocity(const T* __restrict__ src, const Geom& G, int x, int y,
+                                               int z, uint32_t cell, double& ux, double& uy,
+                                               double& uz) {
+  const CellNbr nb = cell_neighbours(G, x, y, z);
+  T g[19];
+  pull_all<true>(g, src, G, layout_cell(G, cell, (uint32_t)z), nb,
+                 std::make_integer_sequence<int, 19>{});
+  double drho = 0, m[3] = {0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    drho += (double)g[q];
+    if (CX[q]) m[0] += CX[q] * (double)g[q];
+    if (CY[q]) m[1] += CY[q] * (double)g[q];
+    if (CZ[q]) m[2] += CZ[q] * (double)g[q];
+  }
+  const double r = 1.0 + drho;
+  ux = m[0] / r;
+  uy = m[1] / r;
+  uz = m[2] / r;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Forward coupling: u_l = sum W U and w_l = sum W curl U over the window.
 // ---------------------------------------------------------------------------------------------
-template <typename T, typename Geo>
+// EXACT: the exact-time coupling variant (single lattice), reading the current state's velocity.
+template <typename T, typename Geo, bool EXACT = false>
 __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   __shared__ double s_w[3][kSpan];
   __shared__ double s_dw[3][kSpan];
@@ -283,7 +328,8 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   const double n = A.P.kernel_factor * d;
   Axis win[3];
   const bool finite = isfinite(xb[0]) && isfinite(xb[1]) && isfinite(xb[2]) && d > 0.0;
-  if (!finite || !build_weights(G, xb, n, tid, s_w, s_dw, win)) {
+  const bool point = A.P.coupling & LBM_COUPLING_POINT_KERNEL;
+  if (!finite || !build_weights(G, xb, n, tid, s_w, s_dw, win, point)) {
     if (tid == 0) {
       work[W_VALID] = 0.0;
       atomicOr(A.status, (int32_t)STATUS_STENCIL_TOO_LARGE);
@@ -307,6 +353,8 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   const int Dz = win[2].dhi - win[2].dlo + 1;
   const int total = Dx * Dy * Dz;
   const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+  const T* __restrict__ S = nullptr;  // exact-time coupling: the current state
+  if constexpr (EXACT) S = static_cast<const T*>(geo.state);
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int f = tid; f < total; f += kBlock) {
     const int i = f % Dx, r = f / Dx;
@@ -317,7 +365,14 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
     const int y = py ? wrapi(vy, G.ny) : vy;
     const int z = pz ? wrapi(vz, G.nz) : vz;
     const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
-    const double ux = (double)U[c], uy = (double)U[G.N + c], uz = (double)U[2 * (size_t)G.N + c];
+    double ux, uy, uz;
+    if constexpr (EXACT) {
+      state_velocity<T>(S, G, x, y, z, c, ux, uy, uz);
+    } else {
+      ux = (double)U[c];
+      uy = (double)U[G.N + c];
+      uz = (double)U[2 * (size_t)G.N + c];
+    }
     const double wa = s_w[0][ix], da = s_dw[0][ix];
     const double wb = s_w[1][iy], db = s_dw[1][iy];
     const double wc = s_w[2][iz], dc = s_dw[2][iz];
@@ -435,8 +490,12 @@ __global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
   }
   const BubbleConst kc = bubble_constants(P, nu, d);
   const double dt = 1.0 / P.n_sub;
+  const int reaction = P.coupling & LBM_REACTION_MASK;
+  const double m_b = P.rho_b * kc.V;
   double ub[3] = {A.S.ux[b], A.S.uy[b], A.S.uz[b]};
   double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
+  // sums over the sub-steps of F_D + F_L and of the net force m_b du_b/dt (reaction variants)
+  double s_dl[3] = {0.0, 0.0, 0.0}, s_net[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < P.n_sub; ++k) {
     // (m_b + C_A rho_l V) du_b/dt = F_B + F_D + F_L + (1 + C_A) rho_l V D_t u_l
     double FD[3], FL[3];
@@ -444,6 +503,8 @@ __global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
     for (int a = 0; a < 3; ++a) {
       double f = FD[a] + FL[a] + kc.va * dul[a];
       if (a == 2) f += kc.fb;
+      s_dl[a] += FD[a] + FL[a];
+      s_net[a] += m_b * (f * kc.inv_meff);
       ub[a] += dt * f * kc.inv_meff;
     }
     for (int a = 0; a < 3; ++a) {
@@ -464,10 +525,17 @@ __global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
       }
     }
   }
-  double FD[3], FL[3];
-  drag_lift(P, kc, d, nu, ub, ul, wl, FD, FL);
+  // the reaction spread into the liquid (Algorithm 1, or a coupling variant)
   double psi[3];
-  for (int a = 0; a < 3; ++a) psi[a] = -(FD[a] + FL[a]);
+  if (reaction == LBM_REACTION_SUBSTEP_MEAN) {
+    for (int a = 0; a < 3; ++a) psi[a] = -s_dl[a] / P.n_sub;
+  } else if (reaction == LBM_REACTION_NET_FORCE) {
+    for (int a = 0; a < 3; ++a) psi[a] = -s_net[a] / P.n_sub;
+  } else {
+    double FD[3], FL[3];
+    drag_lift(P, kc, d, nu, ub, ul, wl, FD, FL);
+    for (int a = 0; a < 3; ++a) psi[a] = -(FD[a] + FL[a]);
+  }
   A.S.x[b] = xn[0];
   A.S.y[b] = xn[1];
   A.S.z[b] = xn[2];
@@ -538,7 +606,9 @@ __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
   const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
   const double n = A.P.kernel_factor * A.S.d[b];
   Axis win[3];
-  if (!build_weights(col.G, x0, n, tid, s_w, s_dw, win)) return;  // validated by k_interp
+  // validated by k_interp
+  if (!build_weights(col.G, x0, n, tid, s_w, s_dw, win, A.P.coupling & LBM_COUPLING_POINT_KERNEL))
+    return;
   spread_atomic<T>(col.G, col.F, win, s_w, work, tid);
   mark_tiles<T>(col, A, b, win, n, tid, kBlock);
 }
@@ -566,9 +636,7 @@ __device__ __forceinline__ double axis_weight_at(const Axis& A, const double* w_
 }
 
 __device__ __forceinline__ bool in_tile_ranges(const TileRanges& r, int t) {
-  for (int i = 0; i < r.n; ++i)
-    if (t >= r.lo[i] && t <= r.hi[i]) return true;
-  return false;
+  return (r.n > 0 && t >= r.lo[0] && t <= r.hi[0]) || (r.n > 1 && t >= r.lo[1] && t <= r.hi[1]);
 }
 
 template <typename T>
@@ -718,7 +786,14 @@ __global__ __launch_bounds__(64) void k_mark(Geo geo, BubbleArgs A, uint32_t* __
 template <typename T, typename Geo>
 hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_t stream) {
   const int nb = A.nb;
-  hipLaunchKernelGGL((k_interp<T, Geo>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+  bool exact = false;
+  if constexpr (std::is_same_v<Geo, OneColumn>) exact = geo.state != nullptr;
+  if (exact) {
+    if constexpr (std::is_same_v<Geo, OneColumn>)
+      hipLaunchKernelGGL((k_interp<T, Geo, true>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+  } else {
+    hipLaunchKernelGGL((k_interp<T, Geo>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_ode<Geo>), dim3(div_up(nb, 64)), dim3(64), 0, stream, geo, A);
@@ -770,6 +845,7 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
   geo.tcount = c->tcount;
   geo.tlist = c->tlist;
   geo.lists = nb > 1;
+  geo.state = (p->coupling & LBM_COUPLING_EXACT_TIME) ? c->pops[c->hs.cur] : nullptr;
   geo.clear_count = nullptr;
   geo.next_region = nullptr;
   geo.next_list = nullptr;

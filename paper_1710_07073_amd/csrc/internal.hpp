@@ -94,6 +94,8 @@ struct OneColumn {
   uint32_t* tcount;
   uint32_t* tlist;
   bool lists;  // several bubbles: spread through the per-tile lists
+  // exact-time coupling: the current state (post-collision buffer), else null
+  const void* state;
   // overlapped steps: the counter k_interp clears (null: none), and where the region of the next
   // step is marked after the bubble update (next_region null: not here)
   uint32_t* clear_count;
@@ -160,6 +162,12 @@ constexpr uint32_t kOverlapMinCells = 1u << 22;
 // Overlapped steps with at most this many bubbles update their region on the side stream,
 // alongside the bulk; with more, on the caller's stream after the bulk.
 constexpr int32_t kRegionSideMaxBubbles = 64;
+
+// A valid bubble_params.coupling: known bits and a known reaction.
+inline bool coupling_ok(int32_t c) {
+  const int32_t known = LBM_REACTION_MASK | LBM_COUPLING_POINT_KERNEL | LBM_COUPLING_EXACT_TIME;
+  return (c & ~known) == 0 && (c & LBM_REACTION_MASK) <= LBM_REACTION_NET_FORCE;
+}
 
 // Byte offsets of every population (and field) element fit in 32 bits.
 inline bool bb_fast_ok(const Geom& G, size_t esz) { return (size_t)19 * G.N * esz <= 0xffffffffull; }

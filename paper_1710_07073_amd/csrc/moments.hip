@@ -3,18 +3,12 @@
 // so both gathers apply the streaming step (with the face conditions) on the fly.
 #include <utility>
 
-#include "internal.hpp"
+#include "collide.hpp"
 
 namespace lbm {
 namespace {
 
 constexpr int kThreads = 256;
-
-template <bool GENERAL, typename T, int... Qs>
-__device__ __forceinline__ void gather(T* g, const T* __restrict__ src, const Geom& G, uint32_t lc,
-                                       const CellNbr& nb, std::integer_sequence<int, Qs...>) {
-  ((g[Qs] = pull<Qs, GENERAL>(src, G, lc, nb)), ...);
-}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -34,7 +28,7 @@ __global__ __launch_bounds__(kThreads) void k_moments(const T* __restrict__ src,
     const uint32_t x = cell % G.nx, y = (cell / G.nx) % G.ny, z = cell / G.plane;
     const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
     T g[19];
-    gather<GENERAL>(g, src, G, layout_cell(G, cell, z), nb, std::make_integer_sequence<int, 19>{});
+    pull_all<GENERAL>(g, src, G, layout_cell(G, cell, z), nb, std::make_integer_sequence<int, 19>{});
     double drho = 0, m[3] = {0, 0, 0};
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
@@ -96,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void k_populations(const T* __restrict__ 
   const uint32_t x = cell % G.nx, y = (cell / G.nx) % G.ny, z = cell / G.plane;
   const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
   T g[19];
-  gather<GENERAL>(g, src, G, layout_cell(G, cell, z), nb, std::make_integer_sequence<int, 19>{});
+  pull_all<GENERAL>(g, src, G, layout_cell(G, cell, z), nb, std::make_integer_sequence<int, 19>{});
   // exported in the plain (19, nz, ny, nx) order whatever the buffer layout
 #pragma unroll
   for (int q = 0; q < 19; ++q) out[(size_t)q * G.N + cell] = g[q];

@@ -21,6 +21,9 @@ LBM_MAX_STENCIL = 64
 LBM_BUBBLE_WORK = 216
 LBM_BUBBLE_RECORD = 24
 LBM_BUBBLE_ADJ = 12
+# coupling variants (bubble_params.coupling)
+LBM_REACTION_MASK, LBM_REACTION_SUBSTEP_MEAN, LBM_REACTION_NET_FORCE = 3, 1, 2
+LBM_COUPLING_POINT_KERNEL, LBM_COUPLING_EXACT_TIME = 4, 8
 
 # every symbol include/lbm.h declares
 EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch", "lbm_get_launch",
@@ -47,7 +50,7 @@ class BubbleParams(ct.Structure):
     _fields_ = [("g", ct.c_double), ("rho_l", ct.c_double), ("rho_b", ct.c_double),
                 ("sigma", ct.c_double), ("c_a", ct.c_double), ("drag_scale", ct.c_double),
                 ("lift_scale", ct.c_double), ("kernel_factor", ct.c_double), ("cd_k", ct.c_double),
-                ("lift_f0", ct.c_double), ("n_sub", ct.c_int32), ("reserved", ct.c_int32)]
+                ("lift_f0", ct.c_double), ("n_sub", ct.c_int32), ("coupling", ct.c_int32)]
 
 
 class BubbleSoA(ct.Structure):

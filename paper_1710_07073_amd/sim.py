@@ -55,9 +55,11 @@ class Bubbles:
 
 
 def bubble_params(g=1e-5, rho_l=1.0, rho_b=1e-3, sigma=4.19e-5, c_a=0.5, drag_scale=1.0,
-                  lift_scale=1.0, kernel_factor=1.5, cd_k=0.15, lift_f0=0.474, n_sub=10):
+                  lift_scale=1.0, kernel_factor=1.5, cd_k=0.15, lift_f0=0.474, n_sub=10,
+                  coupling=0):
+    """coupling: 0 or LBM_REACTION_* | LBM_COUPLING_* bits (lbm.py)."""
     return L.BubbleParams(g, rho_l, rho_b, sigma, c_a, drag_scale, lift_scale, kernel_factor, cd_k,
-                          lift_f0, int(n_sub), 0)
+                          lift_f0, int(n_sub), int(coupling))
 
 
 class Simulation:

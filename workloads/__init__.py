@@ -51,10 +51,12 @@ class Workload:
 
 
 def params(g=1e-5, rho_b=1e-3, sigma=4.19e-5, drag_scale=1.0, lift_scale=1.0, c_a=0.5,
-           kernel_factor=1.5, cd_k=0.15, lift_f0=0.474, n_sub=10):
+           kernel_factor=1.5, cd_k=0.15, lift_f0=0.474, n_sub=10, coupling=0):
+    """Bubble constants; coupling selects a coupling variant (the same bit values on both sides:
+    1, 2 reaction as sub-step mean or net force, 4 point-sampled weights, 8 exact time)."""
     return dict(g=g, rho_l=1.0, rho_b=rho_b, sigma=sigma, c_a=c_a, drag_scale=drag_scale,
                 lift_scale=lift_scale, kernel_factor=kernel_factor, cd_k=cd_k, lift_f0=lift_f0,
-                n_sub=n_sub)
+                n_sub=n_sub, coupling=coupling)
 
 
 def plain_fp64(steps=500):
