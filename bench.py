@@ -226,59 +226,73 @@ def bench_stability(args):
 PAPER_VT = {4: 0.2383, 8: 0.2411, 10: 0.2538}
 
 
-def bench_grid(args):
-    """Grid-independence study (Sec. 4.3, Tables 5 and 6): the nine columns of Table 5 (4, 8 and
-    10 mm bubbles at aspect ratios 1.25, 0.625, 0.3125) in physical units, FP32, one simulation per
-    column replayed from graphs of 100 steps; the bubble's rise velocity is read every 100 steps
-    (0.01 s) and the terminal velocity is its mean over 0.5 to 0.9 s, converted to m/s; the slip
-    velocity is the same mean of u_b - u_l with u_l the liquid velocity interpolated at the bubble."""
+def physical_rise(w, steps, chunk=100, params=None):
+    """One physical-unit column (a workload of grid_independence) for `steps` steps, FP32, graph
+    replays of `chunk` steps; the bubble's rise velocity read after every chunk. The terminal
+    velocity is its mean over 0.5 to 0.9 s in m/s (the second half of the run if shorter); the
+    slip velocity the same mean of u_b - u_l, u_l the liquid velocity interpolated at the bubble.
+    Returns (row, seconds of GPU stepping)."""
     import torch
     import workloads as W
     from paper_1710_07073_amd import sim as S
     from paper_1710_07073_amd import units as U
 
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    u = U.column_units(w.meta["d_mm"] * 1e-3, w.meta["aspect"])
+    sim = S.Simulation(w.shape, w.omega, precision="f32", bc=w.bc, device=dev, stream=stream)
+    sim.add_bubbles(w.pos, w.d, S.bubble_params(**(params or w.params)))
+    t_s, z_m, v_ms, ul_ms = [], [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps // chunk):
+        sim.run(chunk, graph_steps=chunk)
+        x, v, ul = sim.bubbles.positions(), sim.bubbles.velocities(), sim.bubbles.liquid_velocity()
+        t_s.append((k + 1) * chunk * u.dt)
+        z_m.append(float(x[2, 0]) * u.dx)
+        v_ms.append(u.velocity_pu(float(v[2, 0])))
+        ul_ms.append(u.velocity_pu(float(ul[2, 0])))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    state = int(sim.bubbles.state()[0])
+    sim.check()
+    sim.close()
+    t_s, v_ms, ul_ms = np.array(t_s), np.array(v_ms), np.array(ul_ms)
+    window = (t_s >= 0.5 - 1e-9) & (t_s <= 0.9 + 1e-9)
+    if not window.any():
+        window = t_s >= t_s[-1] / 2
+    vt = float(v_ms[window].mean())
+    marks = {f"{t:.2f}": round(z_m[int(round(t / (chunk * u.dt))) - 1], 5)
+             for t in (0.25, 0.5, 0.75, 1.0) if int(round(t / (chunk * u.dt))) <= len(z_m)}
+    row = dict(case=w.name, d_mm=w.meta["d_mm"], aspect=w.meta["aspect"], grid=list(w.shape),
+               d_lu=float(w.d[0]), omega=w.omega, vT_ms=round(vt, 5),
+               vT_spread_ms=round(float(np.ptp(v_ms[window])), 6),
+               ul_at_bubble_ms=round(float(ul_ms[window].mean()), 5),
+               slip_ms=round(float((v_ms - ul_ms)[window].mean()), 5),
+               re_end=round(v_ms[-1] * w.meta["d_mm"] * 1e-3 / W.WATER_NU, 1),
+               z_m=marks, active=state)
+    return row, elapsed
+
+
+def bench_grid(args):
+    """Grid-independence study (Sec. 4.3, Tables 5 and 6): the nine columns of Table 5 (4, 8 and
+    10 mm bubbles at aspect ratios 1.25, 0.625, 0.3125) in physical units, FP32, one simulation per
+    column (physical_rise)."""
+    import workloads as W
+
     chunk = 100
     steps = max(args.steps - args.steps % chunk, 2 * chunk)
     ws = W.grid_independence(steps=steps)
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
     rows, elapsed, cells = [], 0.0, 0
     for w in ws:
-        u = U.column_units(w.meta["d_mm"] * 1e-3, w.meta["aspect"])
-        sim = S.Simulation(w.shape, w.omega, precision="f32", bc=w.bc, device=dev, stream=stream)
-        sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
-        t_s, z_m, v_ms, ul_ms = [], [], [], []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(steps // chunk):
-            sim.run(chunk, graph_steps=chunk)
-            x, v, ul = sim.bubbles.positions(), sim.bubbles.velocities(), sim.bubbles.liquid_velocity()
-            t_s.append((k + 1) * chunk * u.dt)
-            z_m.append(float(x[2, 0]) * u.dx)
-            v_ms.append(u.velocity_pu(float(v[2, 0])))
-            ul_ms.append(u.velocity_pu(float(ul[2, 0])))
-        torch.cuda.synchronize()
-        elapsed += time.perf_counter() - t0
+        row, sec = physical_rise(w, steps, chunk)
+        row["paper_vT_ms"] = PAPER_VT[int(w.meta["d_mm"])]
+        rows.append(row)
+        elapsed += sec
         cells += w.cells
-        state = int(sim.bubbles.state()[0])
-        sim.check()
-        sim.close()
-        t_s, v_ms, ul_ms = np.array(t_s), np.array(v_ms), np.array(ul_ms)
-        window = (t_s >= 0.5 - 1e-9) & (t_s <= 0.9 + 1e-9)
-        if not window.any():
-            window = t_s >= t_s[-1] / 2
-        vt = float(v_ms[window].mean())
-        marks = {f"{t:.2f}": round(z_m[int(round(t / (chunk * u.dt))) - 1], 5)
-                 for t in (0.25, 0.5, 0.75, 1.0) if int(round(t / (chunk * u.dt))) <= len(z_m)}
-        rows.append(dict(case=w.name, d_mm=w.meta["d_mm"], aspect=w.meta["aspect"], grid=list(w.shape),
-                         d_lu=float(w.d[0]), omega=w.omega, vT_ms=round(vt, 5),
-                         vT_spread_ms=round(float(np.ptp(v_ms[window])), 6),
-                         ul_at_bubble_ms=round(float(ul_ms[window].mean()), 5),
-                         slip_ms=round(float((v_ms - ul_ms)[window].mean()), 5),
-                         re_end=round(v_ms[-1] * w.meta["d_mm"] * 1e-3 / W.WATER_NU, 1),
-                         z_m=marks, active=state, paper_vT_ms=PAPER_VT[int(w.meta["d_mm"])]))
-        print(f"[grid] {w.name} {w.shape} omega {w.omega:.6f}: v_T {vt:.4f} m/s "
-              f"(paper {PAPER_VT[int(w.meta['d_mm'])]})", file=sys.stderr, flush=True)
+        print(f"[grid] {w.name} {w.shape} omega {w.omega:.6f}: v_T {row['vT_ms']:.4f} m/s "
+              f"(paper {row['paper_vT_ms']})", file=sys.stderr, flush=True)
+
     def spread(key):
         by_d = {}
         for r in rows:
@@ -294,6 +308,68 @@ def bench_grid(args):
         "grid": {"cases": rows, "vT_relative_spread_over_aspect": spread("vT_ms"),
                  "slip_relative_spread_over_aspect": spread("slip_ms"),
                  "vT_window_s": [0.5, 0.9], "sample_every_steps": chunk},
+    }
+    print(json.dumps(out), flush=True)
+
+
+# coupling variants measured by bench_coupling: name -> bubble_params.coupling
+COUPLINGS = {"default": 0, "substep_mean_reaction": 1, "net_force_reaction": 2,
+             "point_kernel": 4, "exact_time": 8, "substep_point_exact": 13}
+
+
+def bench_coupling(args):
+    """Coupling variants against the default (the readings of the reaction, the kernel weights
+    and the coupling time level): the 4 mm bubble of Table 5 on the 60 x 60 x 180 column
+    (aspect ratio 0.625) in physical units for 1 s, each variant's rise, slip and height at 1 s
+    against the default's; and the whole method step of the 128 x 128 x 512 FP32 column under
+    each variant (cost)."""
+    import torch
+    import workloads as W
+    from paper_1710_07073_amd import lbm as L
+    from paper_1710_07073_amd import sim as S
+
+    chunk = 100
+    steps = max(args.steps - args.steps % chunk, 2 * chunk)
+    w = [c for c in W.grid_independence(steps=steps) if c.name == "grid_4mm_ar0.625"][0]
+    rows = {}
+    for name, coupling in COUPLINGS.items():
+        p = dict(w.params, coupling=coupling)
+        row, sec = physical_rise(w, steps, chunk, params=p)
+        row["ms_per_step"] = round(sec / steps * 1e3, 5)
+        rows[name] = row
+        print(f"[coupling] {name}: v_T {row['vT_ms']:.5f} slip {row['slip_ms']:.5f} m/s",
+              file=sys.stderr, flush=True)
+    base = rows["default"]
+    for name, row in rows.items():
+        row["vT_rel_vs_default"] = round(row["vT_ms"] / base["vT_ms"] - 1.0, 6)
+        row["slip_rel_vs_default"] = round(row["slip_ms"] / base["slip_ms"] - 1.0, 6)
+        row["z_1s_diff_m"] = round(row["z_m"].get("1.00", float("nan")) - base["z_m"].get("1.00", float("nan")), 6)
+    # cost on the timed column
+    t = W.single_fp32()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    cost = {}
+    for name, coupling in COUPLINGS.items():
+        sim = S.Simulation(t.shape, t.omega, precision="f32", bc=t.bc, device=dev, stream=stream)
+        sim.add_bubbles(t.pos, t.d, S.bubble_params(**dict(t.params, coupling=coupling)))
+        sim.run(50)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(0, 800, 8):
+            L.lbm_run(sim.ctx, sim.params, sim.bubbles.soa, sim.bubbles.nb, 8, 0)
+        torch.cuda.synchronize()
+        cost[name] = round((time.perf_counter() - t0) / 800 * 1e3, 5)
+        sim.check()
+        sim.close()
+        print(f"[coupling] {name}: {cost[name]} ms per step on {t.name}", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC, "value": round(t.cells / (cost["default"] * 1e-3) / 1e6, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": cost["default"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "coupling_variants_4mm_60x60x180", "parallelism": "single GPU"},
+        "coupling": {"column": w.name, "steps": steps, "variants": rows,
+                     "ms_per_step_single_fp32_128x128x512": cost},
     }
     print(json.dumps(out), flush=True)
 
@@ -430,7 +506,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="single_fp32",
                     choices=["single_fp32", "plain_fp64", "dense", "batched", "adjoint", "stability",
-                             "grid"])
+                             "grid", "coupling"])
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay the step loop from a HIP graph of this many steps (even)")
     ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
@@ -466,6 +542,8 @@ def main():
         return bench_stability(args)
     if args.workload == "grid":
         return bench_grid(args)
+    if args.workload == "coupling":
+        return bench_coupling(args)
     w = {"single_fp32": W.single_fp32, "plain_fp64": W.plain_fp64, "dense": W.dense}[args.workload]()
     if args.precision:
         w = W.Workload(w.name.replace("fp32", args.precision).replace("fp64", args.precision),
