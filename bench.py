@@ -312,6 +312,41 @@ def bench_grid(args):
     print(json.dumps(out), flush=True)
 
 
+# Table 4: the paper's simulated terminal velocity (m/s) per bubble diameter (mm)
+PAPER_VT_T4 = {2: 0.2898, 3: 0.2533, 4: 0.2383, 5: 0.2331, 6: 0.2332, 7: 0.2363, 8: 0.2411,
+               9: 0.2471, 10: 0.2538}
+
+
+def bench_terminal(args):
+    """Terminal-velocity sweep (Sec. 4.1, Table 4): 2 to 10 mm bubbles in the water tank at aspect
+    ratio 1.25, coupled runs in physical units (physical_rise), against the paper's simulated
+    column."""
+    import workloads as W
+
+    chunk = 100
+    steps = max(args.steps - args.steps % chunk, 2 * chunk)
+    ws = W.terminal_sweep(steps=steps)
+    rows, elapsed, cells = [], 0.0, 0
+    for w in ws:
+        row, sec = physical_rise(w, steps, chunk)
+        row["paper_simulated_vT_ms"] = PAPER_VT_T4[int(round(w.meta["d_mm"]))]
+        rows.append(row)
+        elapsed += sec
+        cells += w.cells
+        print(f"[terminal] {w.name} {w.shape}: v_T {row['vT_ms']:.4f} slip {row['slip_ms']:.4f} m/s "
+              f"(paper {row['paper_simulated_vT_ms']})", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC, "value": round(cells * steps / elapsed / 1e6, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": round(elapsed / steps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "terminal_velocity_2_10mm_ar1.25", "columns": len(ws),
+                   "parallelism": "single GPU"},
+        "terminal": {"cases": rows, "vT_window_s": [0.5, 0.9], "sample_every_steps": chunk},
+    }
+    print(json.dumps(out), flush=True)
+
+
 # coupling variants measured by bench_coupling: name -> bubble_params.coupling
 COUPLINGS = {"default": 0, "substep_mean_reaction": 1, "net_force_reaction": 2,
              "point_kernel": 4, "exact_time": 8, "substep_point_exact": 13}
@@ -506,7 +541,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="single_fp32",
                     choices=["single_fp32", "plain_fp64", "dense", "batched", "adjoint", "stability",
-                             "grid", "coupling"])
+                             "grid", "coupling", "terminal"])
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay the step loop from a HIP graph of this many steps (even)")
     ap.add_argument("--precision", default=None, choices=[None, "f32", "f64"])
@@ -544,6 +579,8 @@ def main():
         return bench_grid(args)
     if args.workload == "coupling":
         return bench_coupling(args)
+    if args.workload == "terminal":
+        return bench_terminal(args)
     w = {"single_fp32": W.single_fp32, "plain_fp64": W.plain_fp64, "dense": W.dense}[args.workload]()
     if args.precision:
         w = W.Workload(w.name.replace("fp32", args.precision).replace("fp64", args.precision),

@@ -8,6 +8,8 @@ bubble in water at omega up to 1.99999, where BGK is barely damped.
   eq. (23)-(24)); the absolute rise velocity adds the liquid the bubble entrains, which grows
   with resolution and converges: each refinement changes it by less than half the previous
   change.
+* The terminal-velocity sweep (Sec. 4.1, Table 4): 2 to 10 mm at aspect ratio 1.25, slip equal
+  to the force balance for every diameter.
 """
 import numpy as np
 import pytest
@@ -64,6 +66,31 @@ def _ode_terminal(w):
         if abs(ub[2] - prev) <= 1e-13:
             return ub[2]
     raise AssertionError("the ODE has no terminal velocity")
+
+
+@pytest.mark.gpu
+def test_slip_velocity_is_the_force_balance_for_2_to_10_mm():
+    """Table 4's diameters at aspect ratio 1.25: the coupled run's slip velocity equals the
+    oracle ODE's terminal velocity in a quiescent liquid (eq. (23)-(24)) in every drag and lift
+    regime the sweep crosses, and the entrained liquid only adds to the rise."""
+    steps, chunk = 6000, 100
+    for w in W.terminal_sweep(steps=steps):
+        print(f"[case] {w.name} {w.shape} omega {w.omega:.6f}: {steps} steps", flush=True)
+        sim = gpu_sim(_with(w, steps, "f32"))
+        ub, ul = [], []
+        for k in range(steps // chunk):
+            sim.run(chunk, graph_steps=chunk)
+            if (k + 1) * chunk >= 4000:
+                ub.append(sim.bubbles.velocities()[2, 0])
+                ul.append(sim.bubbles.liquid_velocity()[2, 0])
+        sim.check()
+        sim.close()
+        scale = w.meta["tcf"] / w.meta["lcf"]
+        rise, slip = np.mean(ub) * scale, (np.mean(ub) - np.mean(ul)) * scale
+        vt = _ode_terminal(w) * scale
+        print(f"rise {rise:.5f}, slip {slip:.5f}, ODE terminal {vt:.5f} m/s", flush=True)
+        assert abs(slip - vt) <= 1e-3 * vt
+        assert vt < rise <= 1.05 * vt
 
 
 @pytest.mark.gpu

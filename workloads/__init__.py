@@ -167,6 +167,16 @@ GRID_CASES = ((0.004, 1.25), (0.004, 0.625), (0.004, 0.3125),
               (0.010, 1.25), (0.010, 0.625), (0.010, 0.3125))
 
 
+TERMINAL_DIAMETERS_MM = (2, 3, 4, 5, 6, 7, 8, 9, 10)
+
+
+def terminal_sweep(steps=10000, aspect=1.25, diameters_mm=TERMINAL_DIAMETERS_MM):
+    """The terminal-velocity sweep of Sec. 4.1 (Table 4): air bubbles of 2 to 10 mm in the
+    0.15 x 0.15 x 0.45 m water tank at one aspect ratio dx / d_b (1.25, App. A), built as the
+    grid-independence columns (the tank rounded to whole cells)."""
+    return grid_independence(steps, cases=tuple((d * 1e-3, aspect) for d in diameters_mm))
+
+
 def grid_independence(steps=10000, cases=GRID_CASES, release=0.02):
     """The grid-independence study (Sec. 4.3, Tables 5 and 6): the 0.15 x 0.15 x 0.45 m tank for
     bubbles of 4, 8 and 10 mm at aspect ratios dx / d_b of 1.25, 0.625 and 0.3125, the Table 3
