@@ -177,7 +177,7 @@ def bench_batched(args):
 
 
 def bench_stability(args):
-    """Stability sweep (Sec. 4.4): the App. A column (30 x 30 x 90, 4 mm bubble, d = 0.8) at 16
+    """Stability sweep (Sec. 4.3): the App. A column (30 x 30 x 90, 4 mm bubble, d = 0.8) at 16
     values of omega from 1.90 to 1.9999 in one batch, FP32, graph replays of 500 steps; after each
     chunk the per-column sums tell which columns went unstable."""
     import torch
@@ -275,7 +275,7 @@ def physical_rise(w, steps, chunk=100, params=None):
 
 
 def bench_grid(args):
-    """Grid-independence study (Sec. 4.3, Tables 5 and 6): the nine columns of Table 5 (4, 8 and
+    """Grid-independence study (Sec. 4.2, Tables 5 and 6): the nine columns of Table 5 (4, 8 and
     10 mm bubbles at aspect ratios 1.25, 0.625, 0.3125) in physical units, FP32, one simulation per
     column (physical_rise)."""
     import workloads as W

@@ -118,7 +118,8 @@ typedef struct {
  * state: 0 = inactive (reached the top layer, Algorithm 1 stop test), 1 = active without a
  * previous interpolated liquid velocity (first step), 2 = active. ul* hold the liquid velocity
  * interpolated at the previous step (for the material derivative of u_l). psi* (optional) receive
- * the reaction -(F_D + F_L) spread into the liquid (0 for an inactive bubble). */
+ * the reaction spread into the liquid: -(F_D + F_L), or what bubble_params.coupling selects (0 for
+ * an inactive bubble). */
 typedef struct {
   double *x, *y, *z;
   double *ux, *uy, *uz;
@@ -130,8 +131,9 @@ typedef struct {
 } bubble_soa;
 
 /* Doubles of per-bubble device scratch that bubbles_step() needs in bubble_soa.work (the
- * interpolated liquid velocity and vorticity, the start position and the reaction of the step,
- * passed between its kernels). Its contents need no initialisation. */
+ * interpolated liquid velocity and vorticity, the start position, the reaction of the step and
+ * the stencil weights at the start position, passed between its kernels). Its contents need no
+ * initialisation. */
 #define LBM_BUBBLE_WORK 216
 
 typedef struct lbm_ctx lbm_ctx;
@@ -200,8 +202,12 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
 /* Bubble half of one step of Algorithm 1 for nb bubbles (forward coupling eq. (20) of the
  * liquid velocity and its curl with the weights of eq. (19); force closures of Table 1 and
  * eq. (3); n_sub explicit sub-steps of eq. (4); backward coupling eq. (21) of the reaction
- * -(F_D + F_L) into the force field). Uses the velocity field of the previous lbm_step(). Call
- * exactly once before each lbm_step(ctx, 1). soa: host struct of device pointers. */
+ * -(F_D + F_L) into the force field). Uses the velocity field of the previous lbm_step() (the
+ * current state's with LBM_COUPLING_EXACT_TIME; params->coupling selects the variants). With
+ * several bubbles each cell sums their forces in bubble order: the force field is
+ * bit-reproducible. Call exactly once before each lbm_step(ctx, 1). soa: host struct of device
+ * pointers. LBM_EINVAL for invalid params (n_sub < 1, unknown coupling bits, non-positive
+ * kernel_factor, sigma or rho_l) or a missing array. */
 lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* params, const bubble_soa* soa,
                         int32_t nb);
 
@@ -229,8 +235,9 @@ lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out);
 lbm_status lbm_bind_buffers(lbm_ctx* ctx, void* state, void* next_state, void* vel);
 
 /* Synchronise the stream and report a pending kernel error (LBM_EINVAL for a bubble beyond the
- * stencil limit, LBM_EUNSUPPORTED for a bubble that left the region of an overlapped step), then
- * clear it. */
+ * stencil limit, with a non-finite position, or whose point-sampled window holds no cell centre;
+ * LBM_EUNSUPPORTED for a bubble that left the region of an overlapped step), then clear it. Such
+ * a bubble is skipped for the step (no force, state unchanged). */
 lbm_status lbm_check(lbm_ctx* ctx);
 
 /* nsteps method steps (bubbles_step then lbm_step(ctx, 1), Algorithm 1) with the launches of

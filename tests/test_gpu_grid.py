@@ -1,4 +1,4 @@
-"""The paper's physical-unit columns (Sec. 4.3, Tables 3, 5 and 6; App. A): a 4 mm or 10 mm air
+"""The paper's physical-unit columns (Sec. 4.2, Tables 3, 5 and 6; App. A): a 4 mm or 10 mm air
 bubble in water at omega up to 1.99999, where BGK is barely damped.
 
 * Parity with the oracle on two of the Table 5 columns, FP64 and FP32, graph-replayed.

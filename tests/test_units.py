@@ -62,7 +62,7 @@ def test_conversions_are_consistent():
 
 def test_water_viscosity_gives_omega_near_two():
     """Water (nu = 1e-6 m^2/s) on the App. A grid: nu_lu = 4e-6 and omega = 1.99995, beyond the
-    stability limit 1.97 the paper reports (Sec. 4.4) — the paper's own runs cannot have used it."""
+    stability limit 1.97 the paper reports (Sec. 4.3) — the paper's own runs cannot have used it."""
     u = U.column_units(0.004, 1.25)
     nu = u.viscosity(1e-6)
     assert nu == pytest.approx(4e-6)

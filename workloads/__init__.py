@@ -147,7 +147,7 @@ WATER_NU, WATER_RHO, AIR_RHO, WATER_SIGMA, GRAVITY = 1e-6, 1000.0, 1.0, 0.073, 9
 
 
 def stability(steps=20000, omegas=STABILITY_OMEGAS):
-    """The stability sweep (Sec. 4.4): the App. A column (0.15 x 0.15 x 0.45 m tank at aspect ratio
+    """The stability sweep (Sec. 4.3): the App. A column (0.15 x 0.15 x 0.45 m tank at aspect ratio
     1.25 for a 4 mm bubble: 30 x 30 x 90 cells, d = 0.8) with g and sigma of air in water converted
     to lattice units (g = 9.81 m/s^2, sigma = 0.073 N/m, dt = 1e-4 s), bounce-back walls and bottom,
     free-slip top, the bubble released at the bottom centre; one column per omega."""
@@ -178,7 +178,7 @@ def terminal_sweep(steps=10000, aspect=1.25, diameters_mm=TERMINAL_DIAMETERS_MM)
 
 
 def grid_independence(steps=10000, cases=GRID_CASES, release=0.02):
-    """The grid-independence study (Sec. 4.3, Tables 5 and 6): the 0.15 x 0.15 x 0.45 m tank for
+    """The grid-independence study (Sec. 4.2, Tables 5 and 6): the 0.15 x 0.15 x 0.45 m tank for
     bubbles of 4, 8 and 10 mm at aspect ratios dx / d_b of 1.25, 0.625 and 0.3125, the Table 3
     properties (water: nu = 1e-6 m^2/s, so omega is 1.9992 to 1.99999; air at 1 kg/m^3;
     sigma = 0.073 N/m; g = 9.81 m/s^2) converted to lattice units per App. A with dt = 1e-4 s;
