@@ -57,6 +57,8 @@ __device__ __forceinline__ uint32_t div_exact(uint32_t a, uint32_t d, double inv
 template <typename T, bool GENERAL>
 __global__ __launch_bounds__(256) void k_batch_step(const ColumnDev* __restrict__ cols, int ncols,
                                                     uint32_t nitems, int cur, int flag, int flags) {
+  // each XCD takes a contiguous range of items (measured faster here than launch order, unlike
+  // the single-lattice step)
   const uint32_t item = xcd_remap(blockIdx.x, nitems);
   int lo = 0, hi = ncols - 1;
   while (lo < hi) {  // last column whose first item is <= item
