@@ -623,9 +623,9 @@ def main():
     K = args.steps
     # the library records these around the launch of the fused step that updates the lattice away
     # from the bubbles, on the stream it runs on (the side stream when the step is overlapped)
-    # every EVERY-th launch is timed (an event record costs a queue marker of a few microseconds);
-    # the steps run through lbm_run in runs of EVERY, the first of which is timed
-    EVERY = 8
+    # every EVERY-th launch is timed (a timing event record costs several microseconds of the
+    # queue); the steps run through lbm_run in runs of EVERY, the first of which is timed
+    EVERY = 64
     nt = (K + EVERY - 1) // EVERY
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]

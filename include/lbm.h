@@ -166,15 +166,13 @@ lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* vec, int32_t* block_x);
 /* Overlap of the bubble kernels with the liquid step, available when every face is bounce-back,
  * the launch shape has one cell per thread and the population buffer is below 4 GiB; on by
  * default for lattices of 2^22 cells or more, where the liquid step outlasts the bubble kernels
- * (it costs a region launch and three cross-stream waits). With it,
+ * (it costs a region launch and two cross-stream waits). With it,
  * bubbles_step() marks the region of this step (the 8^3 tiles within the bubbles' stencil windows
  * widened by the curl ring and two cells), runs the bubble kernels on a library-owned side stream
  * while the liquid update of every other tile (the bulk) runs on the caller's stream, and makes the
- * caller's stream wait for the bubble kernels; lbm_step() then updates the region (with up to 64
- * bubbles on the side stream as soon as the bubble kernels end, alongside the bulk, with more on
- * the caller's stream after the bulk). Within lbm_run() each overlapped step also marks the
- * region of the next one on the side stream. Work enqueued on the caller's stream after
- * bubbles_step() sees the bubble results. Results are identical to the
+ * caller's stream wait for the bubble kernels; lbm_step() then updates the region. Within
+ * lbm_run() each overlapped step also marks the region of the next one on the side stream. Work
+ * enqueued on the caller's stream after bubbles_step() sees the bubble results. Results are identical to the
  * serial step bit for bit. A bubble that moves more than two cells in one step would leave the region; that
  * is reported by lbm_check() / moments() with sums as LBM_EUNSUPPORTED. Not allowed while a
  * bubble half awaits its lbm_step(). available (nullable) reports whether the current

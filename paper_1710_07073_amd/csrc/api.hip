@@ -137,14 +137,13 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   // the region launch and the two cross-stream waits, is about 35 us per step)
   c->overlap = G.N >= lbm::kOverlapMinCells;
   c->side = nullptr;
-  c->ev_fork = c->ev_join = c->ev_region = nullptr;
+  c->ev_fork = c->ev_join = nullptr;
   c->t_start = c->t_end = nullptr;
   const unsigned ev_flags = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
   if (c->side && (hipEventCreateWithFlags(&c->ev_fork, ev_flags) != hipSuccess ||
-                  hipEventCreateWithFlags(&c->ev_join, ev_flags) != hipSuccess ||
-                  hipEventCreateWithFlags(&c->ev_region, ev_flags) != hipSuccess)) {
-    for (hipEvent_t ev : {c->ev_fork, c->ev_join, c->ev_region})
+                  hipEventCreateWithFlags(&c->ev_join, ev_flags) != hipSuccess)) {
+    for (hipEvent_t ev : {c->ev_fork, c->ev_join})
       if (ev) (void)hipEventDestroy(ev);
     (void)hipStreamDestroy(c->side);
     c->side = nullptr;
@@ -389,7 +388,6 @@ lbm_status lbm_destroy(lbm_ctx* ctx) {
     if (hipStreamSynchronize(ctx->side) != hipSuccess) st = LBM_EDEVICE;
     (void)hipEventDestroy(ctx->ev_fork);
     (void)hipEventDestroy(ctx->ev_join);
-    (void)hipEventDestroy(ctx->ev_region);
     (void)hipStreamDestroy(ctx->side);
   }
   delete ctx;

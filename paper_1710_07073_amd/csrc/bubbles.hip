@@ -879,10 +879,7 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
                      : launch_bubble_kernels<double>(geo, A, c->side);
     if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side);
     if (e == hipSuccess) e = launch_bulk(c);
-    // Inside lbm_run the region launch follows at once; when it goes on the side stream after the
-    // bubble kernels, the caller's stream waits for it and so for them: this wait is redundant.
-    const bool joined_by_region = mark_ahead && nb <= kRegionSideMaxBubbles;
-    if (e == hipSuccess && !joined_by_region) e = hipStreamWaitEvent(c->stream, c->ev_join, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_join, 0);
     if (e != hipSuccess) return e;
     c->hs.pending = true;
     c->pending_nb = nb;

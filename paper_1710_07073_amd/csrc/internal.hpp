@@ -51,7 +51,7 @@ struct lbm_ctx {
   lbm::HostState hs;
   bool overlap;               // overlap enabled (lbm_set_overlap)
   hipStream_t side;           // null if it could not be created (overlap then unavailable)
-  hipEvent_t ev_fork, ev_join, ev_region;
+  hipEvent_t ev_fork, ev_join;
   // caller's events recorded around the next bulk (or whole-lattice) liquid launch, one-shot
   hipEvent_t t_start, t_end;
   int32_t pending_nb;  // bubbles of the pending overlapped step
@@ -158,10 +158,6 @@ constexpr int kRegionMargin = 2;
 
 // Lattices from this size on overlap the bubble kernels with the liquid step by default.
 constexpr uint32_t kOverlapMinCells = 1u << 22;
-
-// Overlapped steps with at most this many bubbles update their region on the side stream,
-// alongside the bulk; with more, on the caller's stream after the bulk.
-constexpr int32_t kRegionSideMaxBubbles = 64;
 
 // A valid bubble_params.coupling: known bits and a known reaction.
 inline bool coupling_ok(int32_t c) {
