@@ -250,11 +250,10 @@ __device__ void force_tiles(const Geom& G, const Axis win[3], TileRanges tr[3]) 
 // Flags the tiles the liquid step must force (the force window now) or write the velocity in (the
 // velocity window, with the curl ring, that the next interpolation reads at the new position).
 template <typename T>
-__device__ void mark_tiles(const ColumnView<T>& col, const BubbleArgs& A, int b, const Axis win[3],
-                           double n, int tid, int nthreads) {
+__device__ void mark_tiles(const ColumnView<T>& col, const BubbleArgs& A, const Axis win[3],
+                           const double xn[3], double n, int tid, int nthreads) {
   const Geom& G = col.G;
   uint8_t* __restrict__ tiles = col.tiles;
-  const double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
   const int ext[3] = {G.nx, G.ny, G.nz};
   TileRanges tr[3];
   for (int a = 0; a < 3; ++a) {
@@ -460,10 +459,11 @@ __device__ __forceinline__ void drag_lift(const bubble_params& P, const BubbleCo
   for (int a = 0; a < 3; ++a) FL[a] = lpre * cr[a];
 }
 
+// The bubble update of one lane's bubble. Returns true when the bubble's tiles are left to flag
+// (several bubbles on one lattice), with its start position x0, new position xn and half-width n.
 template <typename Geo>
-__global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
-  const int b = blockIdx.x * 64 + threadIdx.x;
-  if (b >= A.nb) return;
+__device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3], double xn_out[3],
+                         double& n_out) {
   const ColumnView<float> col = geo.template view<float>(b);
   const Geom& G = col.G;
   const double nu = col.nu;
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
       A.S.psiy[b] = 0.0;
       A.S.psiz[b] = 0.0;
     }
-    return;
+    return false;
   }
   const int ext[3] = {G.nx, G.ny, G.nz};
   const double d = A.S.d[b];
@@ -555,12 +555,45 @@ __global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
     A.S.psiz[b] = psi[2];
   }
   if constexpr (std::is_same_v<Geo, OneColumn>) {
-    if (geo.lists) {  // the spreading gathers per tile: flag this bubble's tiles here, in one lane
-      const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
-      const double n = P.kernel_factor * d;
-      Axis win[3];
-      if (force_windows(G, x0, n, win)) mark_tiles<float>(col, A, b, win, n, 0, 1);
+    if (geo.lists) {  // the spreading gathers per tile: the tiles are flagged by the wavefront
+      for (int a = 0; a < 3; ++a) {
+        x0[a] = work[W_X0 + a];
+        xn_out[a] = xn[a];
+      }
+      n_out = P.kernel_factor * d;
+      return true;
     }
+  }
+  return false;
+}
+
+// Bubble dynamics, one lane per bubble (Table 1, eq. (1)-(4)). With several bubbles on one
+// lattice the tiles of each bubble (its force window at x0 and velocity window at the new
+// position) are then flagged by the whole wavefront, one bubble after the other.
+template <typename Geo>
+__global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  double x0[3] = {0.0, 0.0, 0.0}, xn[3] = {0.0, 0.0, 0.0}, n = 0.0;
+  const bool flag = b < A.nb && ode_lane(geo, A, b, x0, xn, n);
+  if constexpr (std::is_same_v<Geo, OneColumn>) {
+    if (!geo.lists) return;
+    const ColumnView<float> col = geo.template view<float>(0);
+    const int lane = threadIdx.x;
+    uint64_t todo = __ballot(flag);
+    while (todo) {
+      const int l = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1;
+      double y0[3], yn[3];
+      for (int a = 0; a < 3; ++a) {
+        y0[a] = __shfl(x0[a], l, 64);
+        yn[a] = __shfl(xn[a], l, 64);
+      }
+      const double m = __shfl(n, l, 64);
+      Axis win[3];
+      if (force_windows(col.G, y0, m, win)) mark_tiles<float>(col, A, win, yn, m, lane, 64);
+    }
+  } else {
+    (void)flag;
   }
 }
 
@@ -610,7 +643,8 @@ __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
   if (!build_weights(col.G, x0, n, tid, s_w, s_dw, win, A.P.coupling & LBM_COUPLING_POINT_KERNEL))
     return;
   spread_atomic<T>(col.G, col.F, win, s_w, work, tid);
-  mark_tiles<T>(col, A, b, win, n, tid, kBlock);
+  const double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
+  mark_tiles<T>(col, A, win, xn, n, tid, kBlock);
 }
 
 // ---- deterministic backward coupling (gather per tile), for several bubbles on one lattice ----
