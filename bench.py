@@ -15,6 +15,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -32,11 +33,20 @@ KERNEL_SOURCES = ["paper_1710_07073_amd/csrc/step.hip", "paper_1710_07073_amd/cs
                   "paper_1710_07073_amd/csrc/step_cell.hpp"]
 
 
+def code_text(src):
+    """Source text without comments and blank-space differences: what the compiler sees."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_source_sha():
+    """Hash of the fused step's code (comments and spacing ignored): counter summaries taken on
+    other code are not used."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

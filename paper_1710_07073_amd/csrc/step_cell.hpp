@@ -1,5 +1,6 @@
-// One cell of the fused liquid step on the bounce-back fast path, shared by the single-lattice
-// and the batched kernels (eq. (13)-(16) with half-way bounce-back on every face, Sec. 3.3).
+// One cell of the fused liquid step on the bounce-back fast path (eq. (13)-(16) with half-way
+// bounce-back on every face, Sec. 3.3), shared by the bulk and region kernels of the single-lattice
+// step; the liquid adjoint uses the same gather offsets.
 #pragma once
 
 #include <type_traits>

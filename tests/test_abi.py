@@ -25,6 +25,17 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
 
 
+def test_header_constants_match_the_binding():
+    """Every #define of include/lbm.h that the binding mirrors has the same value there."""
+    src = open(HEADER).read()
+    defines = dict((k, int(v)) for k, v in re.findall(r"^#define\s+(LBM_\w+)\s+(\d+)\s*$", src, flags=re.M))
+    assert {"LBM_REACTION_MASK", "LBM_REACTION_SUBSTEP_MEAN", "LBM_REACTION_NET_FORCE",
+            "LBM_COUPLING_POINT_KERNEL", "LBM_COUPLING_EXACT_TIME", "LBM_BUBBLE_WORK",
+            "LBM_MAX_STENCIL", "LBM_BUBBLE_RECORD", "LBM_BUBBLE_ADJ"} <= set(defines)
+    for k, v in defines.items():
+        assert getattr(L, k) == v, k
+
+
 def test_status_strings():
     for code in (0, -1, -2, -3, -4):
         assert L.lbm_status_string(code)
