@@ -569,7 +569,11 @@ __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3
 
 // Bubble dynamics, one lane per bubble (Table 1, eq. (1)-(4)). With several bubbles on one
 // lattice the tiles of each bubble (its force window at x0 and velocity window at the new
-// position) are then flagged by the whole wavefront, one bubble after the other.
+// position) are then flagged: each lane its own bubble's when the wavefront holds many bubbles
+// (the lanes' loops run side by side), the whole wavefront one bubble after the other when it
+// holds a few (the tiles of one bubble then spread over the lanes).
+constexpr int kWaveFlagMaxBubbles = 16;
+
 template <typename Geo>
 __global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
   const int b = blockIdx.x * 64 + threadIdx.x;
@@ -580,6 +584,11 @@ __global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
     const ColumnView<float> col = geo.template view<float>(0);
     const int lane = threadIdx.x;
     uint64_t todo = __ballot(flag);
+    if (__popcll(todo) > kWaveFlagMaxBubbles) {
+      Axis win[3];
+      if (flag && force_windows(col.G, x0, n, win)) mark_tiles<float>(col, A, win, xn, n, 0, 1);
+      return;
+    }
     while (todo) {
       const int l = __ffsll((unsigned long long)todo) - 1;
       todo &= todo - 1;
