@@ -199,6 +199,9 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
   __shared__ double s_red[kBW];
   __shared__ int s_ok;
   __shared__ double s_lpsi[3], s_gx[3], s_lul[3], s_lwl[3], s_gxode[3];
+  __shared__ double s_ubs[kMaxSub + 1][3];
+  __shared__ unsigned char s_clamped[kMaxSub][3];
+  __shared__ ForceJac s_jac[kMaxSub + 1];
   const int b = (int)xcd_remap(blockIdx.x, nb);
   const double* r = rec + (size_t)b * R_SIZE;
   double* l = lam + (size_t)b * A_SIZE;
@@ -243,7 +246,13 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
   }
   __syncthreads();
 
-  // reverse sweep of the sub-steps
+  // reverse sweep of the sub-steps: the forward sub-steps again (one lane), the force Jacobians
+  // at their velocities (one lane each), then the sweep (one lane)
+  const double* ul = r + R_UL;
+  const double* ulp = r + R_ULP;
+  double dul[3] = {0.0, 0.0, 0.0};
+  if (st == 2)
+    for (int a = 0; a < 3; ++a) dul[a] = ul[a] - ulp[a];
   if (threadIdx.x == 0) {
     OdeBounds Bd;
     const int ext[3] = {G.nx, G.ny, G.nz};
@@ -252,14 +261,18 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
       Bd.len[a] = G.bc[2 * a] == BC_PER ? (double)ext[a] : 0.0;
     }
     Bd.top = G.bc[4] != BC_PER;
-    const double* ul = r + R_UL;
-    const double* ulp = r + R_ULP;
-    double dul[3] = {0.0, 0.0, 0.0};
-    if (st == 2)
-      for (int a = 0; a < 3; ++a) dul[a] = ul[a] - ulp[a];
+    OdeOut o;
+    ode_forward(P, nu, r[R_D], r + R_X, r + R_UB, ul, r + R_WL, dul, Bd, o, s_ubs, s_clamped);
+  }
+  __syncthreads();
+  if (threadIdx.x <= P.n_sub) {
+    const ForceConst fc = force_const(P, nu, r[R_D]);
+    force_jac(P, fc, nu, r[R_D], s_ubs[threadIdx.x], ul, r + R_WL, s_jac[threadIdx.x]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     OdeAdj g;
-    ode_adjoint(P, nu, r[R_D], r + R_X, r + R_UB, ul, r + R_WL, dul, Bd, l + A_X, l + A_UB, s_lpsi,
-                g);
+    ode_adjoint_sweep(P, r[R_D], s_clamped, s_jac, l + A_X, l + A_UB, s_lpsi, g);
     for (int a = 0; a < 3; ++a) {
       // u_l enters the drag/lift, D_t u_l = u_l - u_l,prev (state 2) and u_l,prev of the next step
       s_lul[a] = g.ul[a] + (st == 2 ? g.dul[a] : 0.0) + l[A_ULP + a];

@@ -201,38 +201,57 @@ struct ForceJac {
   double dnu[3];    // d(F_D + F_L)/dnu
 };
 
-// Drag and lift of Table 1 at relative velocity u_r = ub - ul, with their derivatives.
-LBM_HD void force_jac(const bubble_params& P, double nu, double d, const double* ub,
-                      const double* ul, const double* wl, ForceJac& f) {
+// Per-bubble constants of the Table 1 closures (they depend on the diameter and nu only).
+struct ForceConst {
+  double KD, KL;     // 1/2 rho_l pi r^2 and rho_l V
+  double shape;      // 8/3 Eo / (Eo + 4)
+  double v24, v48;   // 24 nu / d and 48 nu / d
+  double Eod, fl;    // modified Eotvos number and f(Eo_d) of the lift coefficient
+};
+
+LBM_HD ForceConst force_const(const bubble_params& P, double nu, double d) {
   const double pi = 3.14159265358979323846;
   const double V = pi * d * d * d / 6.0;
   const double r = 0.5 * d;
-  const double KD = 0.5 * P.rho_l * pi * r * r;
-  const double KL = P.rho_l * V;
+  ForceConst c;
+  c.KD = 0.5 * P.rho_l * pi * r * r;
+  c.KL = P.rho_l * V;
+  const double Eo = (P.rho_l - P.rho_b) * P.g * d * d / P.sigma;
+  c.shape = 8.0 / 3.0 * Eo / (Eo + 4.0);
+  c.v24 = 24.0 * nu / d;
+  c.v48 = 48.0 * nu / d;
+  const double E = 1.0 / (1.0 + 0.163 * exp(0.757 * log(Eo)));
+  c.Eod = Eo / exp(2.0 / 3.0 * log(E));
+  c.fl = 0.00105 * c.Eod * c.Eod * c.Eod - 0.0159 * c.Eod * c.Eod - 0.0204 * c.Eod + P.lift_f0;
+  return c;
+}
+
+// Drag and lift of Table 1 at relative velocity u_r = ub - ul; with J (nullable output f.J etc.)
+// their derivatives. F alone (deriv false) takes the same operations as with the derivatives.
+template <bool DERIV>
+LBM_HD void force_eval(const bubble_params& P, const ForceConst& c, double nu, double d,
+                       const double* ub, const double* ul, const double* wl, ForceJac& f) {
   const double ur[3] = {ub[0] - ul[0], ub[1] - ul[1], ub[2] - ul[2]};
   const double m = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
   const double Re = m * d / nu;
-  const double Eo = (P.rho_l - P.rho_b) * P.g * d * d / P.sigma;
-  const double shape = 8.0 / 3.0 * Eo / (Eo + 4.0);
-  const double v24 = 24.0 * nu / d, v48 = 48.0 * nu / d;
   // viscous branch min{24/Re (1 + k Re^0.687), 48/Re} |u_r|, its m d/dm and d/dnu
-  double visc = v48, visc_m = 0.0, visc_nu = 48.0 / d;
+  double visc = c.v48, visc_m = 0.0, visc_nu = 48.0 / d;
   if (Re > 0.0) {
     const double t = P.cd_k * exp(0.687 * log(Re));
-    const double a = v24 * (1.0 + t);
-    if (a < v48) {
+    const double a = c.v24 * (1.0 + t);
+    if (a < c.v48) {
       visc = a;
-      visc_m = v24 * 0.687 * t;
+      visc_m = c.v24 * 0.687 * t;
       visc_nu = 24.0 / d * (1.0 + 0.313 * t);
     }
-  } else if (v24 < v48) {
-    visc = v24;
+  } else if (c.v24 < c.v48) {
+    visc = c.v24;
     visc_nu = 24.0 / d;
   }
   double cdu, cdu_m, cdu_nu;
-  if (shape * m > visc) {
-    cdu = shape * m;
-    cdu_m = shape * m;
+  if (c.shape * m > visc) {
+    cdu = c.shape * m;
+    cdu_m = c.shape * m;
     cdu_nu = 0.0;
   } else {
     cdu = visc;
@@ -240,43 +259,56 @@ LBM_HD void force_jac(const bubble_params& P, double nu, double d, const double*
     cdu_nu = visc_nu;
   }
   // lift coefficient and dC_L/dRe
-  const double E = 1.0 / (1.0 + 0.163 * exp(0.757 * log(Eo)));
-  const double Eod = Eo / exp(2.0 / 3.0 * log(E));
-  const double fl = 0.00105 * Eod * Eod * Eod - 0.0159 * Eod * Eod - 0.0204 * Eod + P.lift_f0;
   double cl, cl_re = 0.0;
-  if (Eod < 4.0) {
+  if (c.Eod < 4.0) {
     const double th = tanh(0.121 * Re);
-    if (0.288 * th < fl) {
+    if (0.288 * th < c.fl) {
       cl = 0.288 * th;
       cl_re = 0.288 * 0.121 * (1.0 - th * th);
     } else {
-      cl = fl;
+      cl = c.fl;
     }
-  } else if (Eod <= 10.0) {
-    cl = fl;
+  } else if (c.Eod <= 10.0) {
+    cl = c.fl;
   } else {
     cl = -0.29;
   }
   const double cr[3] = {ur[1] * wl[2] - ur[2] * wl[1], ur[2] * wl[0] - ur[0] * wl[2],
                         ur[0] * wl[1] - ur[1] * wl[0]};
   const double sD = P.drag_scale, sL = P.lift_scale;
-  const double uh[3] = {m > 0.0 ? ur[0] / m : 0.0, m > 0.0 ? ur[1] / m : 0.0, m > 0.0 ? ur[2] / m : 0.0};
-  // d(u_r x w)/du_r and d(u_r x w)/dw
-  const double dcr_du[3][3] = {{0.0, wl[2], -wl[1]}, {-wl[2], 0.0, wl[0]}, {wl[1], -wl[0], 0.0}};
-  const double dcr_dw[3][3] = {{0.0, -ur[2], ur[1]}, {ur[2], 0.0, -ur[0]}, {-ur[1], ur[0], 0.0}};
-  const double dcl_dm = cl_re * d / nu;  // dC_L/d|u_r|
+  const double KD = c.KD, KL = c.KL;
   for (int a = 0; a < 3; ++a) {
     f.FD1[a] = -KD * cdu * ur[a];
     f.FL1[a] = -KL * cl * cr[a];
     f.F[a] = sD * f.FD1[a] + sL * f.FL1[a];
-    for (int b = 0; b < 3; ++b) {
-      const double dd = -sD * KD * ((a == b ? cdu : 0.0) + cdu_m * uh[a] * uh[b]);
-      const double dl = -sL * KL * (cl * dcr_du[a][b] + cr[a] * dcl_dm * uh[b]);
-      f.J[a][b] = dd + dl;
-      f.Jw[a][b] = -sL * KL * cl * dcr_dw[a][b];
-    }
-    f.dnu[a] = -sD * KD * cdu_nu * ur[a] - sL * KL * cr[a] * cl_re * (-Re / nu);
   }
+  if constexpr (DERIV) {
+    const double uh[3] = {m > 0.0 ? ur[0] / m : 0.0, m > 0.0 ? ur[1] / m : 0.0,
+                          m > 0.0 ? ur[2] / m : 0.0};
+    // d(u_r x w)/du_r and d(u_r x w)/dw
+    const double dcr_du[3][3] = {{0.0, wl[2], -wl[1]}, {-wl[2], 0.0, wl[0]}, {wl[1], -wl[0], 0.0}};
+    const double dcr_dw[3][3] = {{0.0, -ur[2], ur[1]}, {ur[2], 0.0, -ur[0]}, {-ur[1], ur[0], 0.0}};
+    const double dcl_dm = cl_re * d / nu;  // dC_L/d|u_r|
+    for (int a = 0; a < 3; ++a) {
+      for (int b = 0; b < 3; ++b) {
+        const double dd = -sD * KD * ((a == b ? cdu : 0.0) + cdu_m * uh[a] * uh[b]);
+        const double dl = -sL * KL * (cl * dcr_du[a][b] + cr[a] * dcl_dm * uh[b]);
+        f.J[a][b] = dd + dl;
+        f.Jw[a][b] = -sL * KL * cl * dcr_dw[a][b];
+      }
+      f.dnu[a] = -sD * KD * cdu_nu * ur[a] - sL * KL * cr[a] * cl_re * (-Re / nu);
+    }
+  } else {
+    (void)cdu_m;
+    (void)cdu_nu;
+    (void)cl_re;
+  }
+}
+
+// Drag and lift of Table 1 at relative velocity u_r = ub - ul, with their derivatives.
+LBM_HD void force_jac(const bubble_params& P, const ForceConst& c, double nu, double d,
+                      const double* ub, const double* ul, const double* wl, ForceJac& f) {
+  force_eval<true>(P, c, nu, d, ub, ul, wl, f);
 }
 
 struct OdeOut {
@@ -294,12 +326,13 @@ LBM_HD void ode_forward(const bubble_params& P, double nu, double d, const doubl
   const double va = (1.0 + P.c_a) * P.rho_l * V;
   const double fb = (P.rho_l - P.rho_b) * V * P.g;
   const double dt = 1.0 / P.n_sub;
+  const ForceConst fc = force_const(P, nu, d);
   double ub[3] = {ub0[0], ub0[1], ub0[2]}, x[3] = {x0[0], x0[1], x0[2]};
   for (int k = 0; k < P.n_sub; ++k) {
     if (ubs)
       for (int a = 0; a < 3; ++a) ubs[k][a] = ub[a];
     ForceJac f;
-    force_jac(P, nu, d, ub, ul, wl, f);
+    force_eval<false>(P, fc, nu, d, ub, ul, wl, f);
     for (int a = 0; a < 3; ++a) {
       double fa = f.F[a] + va * dul[a];
       if (a == 2) fa += fb;
@@ -329,7 +362,7 @@ LBM_HD void ode_forward(const bubble_params& P, double nu, double d, const doubl
   if (ubs)
     for (int a = 0; a < 3; ++a) ubs[P.n_sub][a] = ub[a];
   ForceJac f;
-  force_jac(P, nu, d, ub, ul, wl, f);
+  force_eval<false>(P, fc, nu, d, ub, ul, wl, f);
   for (int a = 0; a < 3; ++a) {
     o.x[a] = x[a];
     o.ub[a] = ub[a];
@@ -342,16 +375,14 @@ struct OdeAdj {
   double dsD, dsL, dnu;
 };
 
-// Reverse sweep of ode_forward: given dL/dx_new, dL/dub_new, dL/dpsi, returns the derivatives in
-// the step's inputs and in drag_scale, lift_scale and nu.
-LBM_HD void ode_adjoint(const bubble_params& P, double nu, double d, const double* x0,
-                        const double* ub0, const double* ul, const double* wl, const double* dul,
-                        const OdeBounds& Bd, const double* lx_new, const double* lub_new,
-                        const double* lpsi, OdeAdj& g) {
-  double ubs[kMaxSub + 1][3];
-  unsigned char clamped[kMaxSub][3];
-  OdeOut o;
-  ode_forward(P, nu, d, x0, ub0, ul, wl, dul, Bd, o, ubs, clamped);
+// Reverse sweep of ode_forward from its record (clamp events) and the force Jacobians at the
+// sub-step velocities, jac[k] = force_jac at ubs[k] for k = 0..n_sub (jac[n_sub]: the final
+// velocity, where the reaction is taken): given dL/dx_new, dL/dub_new, dL/dpsi, returns the
+// derivatives in the step's inputs and in drag_scale, lift_scale and nu. The Jacobians do not
+// depend on the adjoint state, so a caller may evaluate them in parallel.
+LBM_HD void ode_adjoint_sweep(const bubble_params& P, double d, const unsigned char (*clamped)[3],
+                              const ForceJac* jac, const double* lx_new, const double* lub_new,
+                              const double* lpsi, OdeAdj& g) {
   const double pi = 3.14159265358979323846;
   const double V = pi * d * d * d / 6.0;
   const double inv_meff = 1.0 / (P.rho_b * V + P.c_a * P.rho_l * V);
@@ -365,8 +396,7 @@ LBM_HD void ode_adjoint(const bubble_params& P, double nu, double d, const doubl
   }
   g.dsD = g.dsL = g.dnu = 0.0;
   {  // psi = -(F_D + F_L)(ub_n)
-    ForceJac f;
-    force_jac(P, nu, d, ubs[P.n_sub], ul, wl, f);
+    const ForceJac& f = jac[P.n_sub];
     for (int b = 0; b < 3; ++b) {
       double t = 0.0, tw = 0.0;
       for (int a = 0; a < 3; ++a) {
@@ -395,8 +425,7 @@ LBM_HD void ode_adjoint(const bubble_params& P, double nu, double d, const doubl
       }
     }
     // ub' = ub_k + dt/m_eff (F(ub_k) + va dul + fb e_z)
-    ForceJac f;
-    force_jac(P, nu, d, ubs[k], ul, wl, f);
+    const ForceJac& f = jac[k];
     for (int b = 0; b < 3; ++b) {
       double t = 0.0, tw = 0.0;
       for (int a = 0; a < 3; ++a) {
@@ -418,6 +447,21 @@ LBM_HD void ode_adjoint(const bubble_params& P, double nu, double d, const doubl
     g.x[a] = lx[a];
     g.ub[a] = lub[a];
   }
+}
+
+// The whole reverse step in one thread: forward recompute, Jacobians, sweep (host checks).
+LBM_HD void ode_adjoint(const bubble_params& P, double nu, double d, const double* x0,
+                        const double* ub0, const double* ul, const double* wl, const double* dul,
+                        const OdeBounds& Bd, const double* lx_new, const double* lub_new,
+                        const double* lpsi, OdeAdj& g) {
+  double ubs[kMaxSub + 1][3];
+  unsigned char clamped[kMaxSub][3];
+  OdeOut o;
+  ode_forward(P, nu, d, x0, ub0, ul, wl, dul, Bd, o, ubs, clamped);
+  const ForceConst c = force_const(P, nu, d);
+  ForceJac jac[kMaxSub + 1];
+  for (int k = 0; k <= P.n_sub; ++k) force_jac(P, c, nu, d, ubs[k], ul, wl, jac[k]);
+  ode_adjoint_sweep(P, d, clamped, jac, lx_new, lub_new, lpsi, g);
 }
 
 }  // namespace lbm
