@@ -365,8 +365,10 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, in
                                        return hipSuccess;
                                      },
                                      &captured);
-    if (st_cap != LBM_OK) return st_cap;
-    if (e != hipSuccess) return LBM_EDEVICE;
+    if (st_cap != LBM_OK || e != hipSuccess) {
+      ctx->hs = pre;  // a failed capture ran nothing: back to the state before it
+      return st_cap != LBM_OK ? st_cap : LBM_EDEVICE;
+    }
     if (captured) ctx->graph.post() = ctx->hs;  // the capture only recorded the launches
     if (ctx->graph.launch(ctx->stream) != hipSuccess) return LBM_EDEVICE;
     ctx->hs = ctx->graph.post();

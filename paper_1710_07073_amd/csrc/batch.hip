@@ -463,13 +463,14 @@ lbm_status lbm_batch_run(lbm_batch* b, const bubble_params* p, const bubble_soa*
     const int64_t steps0 = b->steps;
     bool captured = false;
     hipError_t e = b->graph.ensure(key, b->stream, [&]() { return enqueue(graph_steps); }, &captured);
-    if (e != hipSuccess) return LBM_EDEVICE;
-    // capture only recorded the launches: rewind the host-side step state and replay
+    // a capture only records the launches (and a failed one ran nothing): rewind the host-side
+    // step state, then replay
     b->cur = cur0;
     b->flag_cur = flag0;
     b->flag_clean[0] = clean0[0];
     b->flag_clean[1] = clean0[1];
     b->steps = steps0;
+    if (e != hipSuccess) return LBM_EDEVICE;
     e = b->graph.launch(b->stream);
     if (e != hipSuccess) return LBM_EDEVICE;
     for (int i = 0; i < graph_steps; ++i) {  // advance the host state as the steps did
