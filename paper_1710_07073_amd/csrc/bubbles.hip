@@ -2,11 +2,16 @@
 //   k_interp  (one workgroup per bubble) cell-integral weights of the clipped fourth-order
 //             polynomial kernel (eq. (18)-(19)) and the forward coupling (eq. (20)) of the
 //             liquid velocity and of its curl, reduced across the workgroup in double precision;
+//             with several bubbles it also enters the bubble in the per-tile lists;
 //   k_ode     (one lane per bubble) the force closures of Table 1 and n_sub explicit sub-steps
-//             of eq. (4), in double precision;
-//   k_spread  (one workgroup per bubble) the backward coupling (eq. (21)) of the reaction
-//             -(F_D + F_L) into the force field with the same weights (atomic adds), and the
-//             tiles the liquid step must force, or must write the velocity in, are flagged.
+//             of eq. (4), in double precision; with several bubbles it flags the tiles the
+//             liquid step must force, or must write the velocity in;
+//   k_spread  (one bubble: one workgroup) the backward coupling (eq. (21)) of the reaction into
+//             the force field with the same weights (atomic adds) and the tile flags, or
+//   k_spread_gather (several bubbles: one workgroup per tile) the same sums per cell in bubble
+//             order from the lists, so that the force field is bit-reproducible.
+// The coupling variants of bubble_params.coupling (reaction, point-sampled weights, exact-time
+// forward coupling) are modes of these kernels. k_mark marks the region of an overlapped step.
 //
 // The curl is the central-difference curl of the velocity with wall ghosts (bounce-back ghost =
 // -U of the mirror cell, free-slip ghost = mirror cell with the normal component negated). Its
