@@ -117,47 +117,72 @@ __device__ bool wave_axis_weights(const Axis& A, double xa, double n, bool per, 
   return true;
 }
 
+// The weights of axis AX into s_w[AX] (one wavefront), and their derivative weights into
+// s_dw[AX] once every wavefront's weights are in LDS. AX is a constant, so the window and the
+// face conditions of the axis are plain registers.
+template <int AX>
+__device__ __forceinline__ bool axis_weights_wave(const Geom& G, const double xb[3], double n,
+                                                  bool point, int lane, const Axis win[3],
+                                                  double (*s_w)[kSpan]) {
+  return wave_axis_weights(win[AX], xb[AX], n, G.bc[2 * AX] == BC_PER, point, lane, s_w[AX]);
+}
+
+template <int AX>
+__device__ __forceinline__ void axis_dweights_wave(const Geom& G, int lane, const Axis win[3],
+                                                   const double (*s_w)[kSpan],
+                                                   double (*s_dw)[kSpan]) {
+  const int e = AX == 0 ? G.nx : (AX == 1 ? G.ny : G.nz);
+  const bool per = G.bc[2 * AX] == BC_PER;
+  const double s_lo = G.bc[2 * AX] == BC_FS ? 1.0 : -1.0;
+  const double s_hi = G.bc[2 * AX + 1] == BC_FS ? 1.0 : -1.0;
+  const Axis& A = win[AX];
+  for (int i = lane; i < kSpan; i += 64) {
+    const int v = A.lo - 1 + i;
+    const double wm = i > 0 ? s_w[AX][i - 1] : 0.0;
+    const double wp = i + 1 < kSpan ? s_w[AX][i + 1] : 0.0;
+    double dw = 0.5 * (wm - wp);
+    if (!per) {
+      if (v == 0) dw -= 0.5 * s_lo * s_w[AX][i];       // ghost below cell 0
+      if (v == e - 1) dw += 0.5 * s_hi * s_w[AX][i];  // ghost above the last cell
+    }
+    s_dw[AX][i] = dw;
+  }
+}
+
 // Weights w and derivative weights dw of the bubble at xb along the three axes, into LDS,
-// indexed by (cell - lo + 1). Called by the whole workgroup; the first wavefront computes. point:
-// the point-sampled variant of the weights.
+// indexed by (cell - lo + 1). Called by the whole workgroup; wavefront a computes axis a, the
+// three side by side. point: the point-sampled variant of the weights.
 __device__ bool build_weights(const Geom& G, const double xb[3], double n, int tid,
                               double (*s_w)[kSpan], double (*s_dw)[kSpan], Axis win[3],
                               bool point) {
-  __shared__ int s_empty;
+  static_assert(kBlock >= 192, "one wavefront per axis");
+  __shared__ int s_bad[3];
   const int ext[3] = {G.nx, G.ny, G.nz};
   for (int a = 0; a < 3; ++a) {
     const bool per = G.bc[2 * a] == BC_PER;
     if (!axis_window(xb[a], n, ext[a], per, win[a])) return false;
   }
-  const int lane = tid;
-  if (tid < 64) {
-    bool ok = true;
-    for (int a = 0; a < 3; ++a)
-      ok = wave_axis_weights(win[a], xb[a], n, G.bc[2 * a] == BC_PER, point, lane, s_w[a]) && ok;
-    if (tid == 0) s_empty = ok ? 0 : 1;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: a scalar branch
+  const int lane = tid & 63;
+  if (wave < 3) {
+    bool ok;
+    if (wave == 0)
+      ok = axis_weights_wave<0>(G, xb, n, point, lane, win, s_w);
+    else if (wave == 1)
+      ok = axis_weights_wave<1>(G, xb, n, point, lane, win, s_w);
+    else
+      ok = axis_weights_wave<2>(G, xb, n, point, lane, win, s_w);
+    if (lane == 0) s_bad[wave] = ok ? 0 : 1;
   }
   __syncthreads();
-  if (tid < 64) {
-  for (int a = 0; a < 3; ++a) {
-    const bool per = G.bc[2 * a] == BC_PER;
-    const Axis& A = win[a];
-    const double s_lo = G.bc[2 * a] == BC_FS ? 1.0 : -1.0;
-    const double s_hi = G.bc[2 * a + 1] == BC_FS ? 1.0 : -1.0;
-    for (int i = lane; i < kSpan; i += 64) {
-      const int v = A.lo - 1 + i;
-      const double wm = i > 0 ? s_w[a][i - 1] : 0.0;
-      const double wp = i + 1 < kSpan ? s_w[a][i + 1] : 0.0;
-      double dw = 0.5 * (wm - wp);
-      if (!per) {
-        if (v == 0) dw -= 0.5 * s_lo * s_w[a][i];           // ghost below cell 0
-        if (v == ext[a] - 1) dw += 0.5 * s_hi * s_w[a][i];  // ghost above the last cell
-      }
-      s_dw[a][i] = dw;
-    }
-  }
-  }
+  if (wave == 0)
+    axis_dweights_wave<0>(G, lane, win, s_w, s_dw);
+  else if (wave == 1)
+    axis_dweights_wave<1>(G, lane, win, s_w, s_dw);
+  else if (wave == 2)
+    axis_dweights_wave<2>(G, lane, win, s_w, s_dw);
   __syncthreads();
-  return s_empty == 0;
+  return (s_bad[0] | s_bad[1] | s_bad[2]) == 0;
 }
 
 // Bubble handled by a workgroup: consecutive workgroups on one XCD take consecutive bubbles, so
@@ -172,6 +197,23 @@ __device__ __forceinline__ double block_sum(double v, double* s_red, int tid) {
   double t = 0.0;
   for (int w = 0; w < kBlockWaves; ++w) t += s_red[w];
   return t;
+}
+
+// block_sum of six values at once, behind one barrier: the same butterfly in each wavefront and
+// the same order over the wavefronts, so each sum has the bits block_sum gives it.
+__device__ __forceinline__ void block_sum6(double v[6], double (*s_red6)[kBlockWaves], int tid) {
+#pragma unroll
+  for (int m = 0; m < 6; ++m) v[m] = wave_sum(v[m]);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int m = 0; m < 6; ++m) s_red6[m][tid >> 6] = v[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    double t = 0.0;
+    for (int w = 0; w < kBlockWaves; ++w) t += s_red6[m][w];
+    v[m] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -245,6 +287,41 @@ __device__ void for_tiles(const Geom& G, const TileRanges tr[3], int tid, int nt
       }
 }
 
+// Number of tiles of the ranges tr, and the k-th of them in the order for_tiles visits them
+// (k below the number).
+__device__ __forceinline__ int tile_count(const TileRanges tr[3]) {
+  int n[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    n[a] = tr[a].hi[0] - tr[a].lo[0] + 1;
+    if (tr[a].n == 2) n[a] += tr[a].hi[1] - tr[a].lo[1] + 1;
+  }
+  return tr[0].n && tr[1].n && tr[2].n ? n[0] * n[1] * n[2] : 0;
+}
+
+__device__ __forceinline__ uint32_t nth_tile(const Geom& G, const TileRanges tr[3], int k) {
+  uint32_t t = 0;
+#pragma unroll
+  for (int rz = 0; rz < 2; ++rz)
+#pragma unroll
+    for (int ry = 0; ry < 2; ++ry)
+#pragma unroll
+      for (int rx = 0; rx < 2; ++rx) {
+        if (rz >= tr[2].n || ry >= tr[1].n || rx >= tr[0].n || k < 0) continue;
+        const int nx_ = tr[0].hi[rx] - tr[0].lo[rx] + 1;
+        const int ny_ = tr[1].hi[ry] - tr[1].lo[ry] + 1;
+        const int nz_ = tr[2].hi[rz] - tr[2].lo[rz] + 1;
+        if (k < nx_ * ny_ * nz_) {
+          const int tx = tr[0].lo[rx] + k % nx_;
+          const int ty = tr[1].lo[ry] + (k / nx_) % ny_;
+          const int tz = tr[2].lo[rz] + k / (nx_ * ny_);
+          t = ((uint32_t)tz * G.tny + ty) * G.tnx + tx;
+        }
+        k -= nx_ * ny_ * nz_;
+      }
+  return t;
+}
+
 // Tiles of the force window.
 __device__ void force_tiles(const Geom& G, const Axis win[3], TileRanges tr[3]) {
   const int ext[3] = {G.nx, G.ny, G.nz};
@@ -311,7 +388,7 @@ template <typename T, typename Geo, bool EXACT = false>
 __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   __shared__ double s_w[3][kSpan];
   __shared__ double s_dw[3][kSpan];
-  __shared__ double s_red[kBlockWaves];
+  __shared__ double s_red6[6][kBlockWaves];
   const int b = bubble_of_block(A.nb);
   const int tid = threadIdx.x;
   if constexpr (std::is_same_v<Geo, OneColumn>) {
@@ -342,14 +419,23 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   }
   // the weights at x0 for the spreading of this step
   for (int i = tid; i < 3 * kSpan; i += kBlock) work[W_WGT + i] = s_w[i / kSpan][i % kSpan];
+  // enter the bubble in the list of every tile of its force window: the slot of each thread's
+  // first tile is taken now and written after the gather, so the atomic is in flight meanwhile
+  uint32_t t0 = 0, slot0 = kTileCap;
   if constexpr (std::is_same_v<Geo, OneColumn>) {
-    if (geo.lists) {  // enter the bubble in the list of every tile of its force window
+    if (geo.lists) {
       TileRanges tr[3];
       force_tiles(G, win, tr);
-      for_tiles(G, tr, tid, kBlock, [&](uint32_t t) {
+      const int nt = tile_count(tr);
+      if (tid < nt) {
+        t0 = nth_tile(G, tr, tid);
+        slot0 = atomicAdd(&geo.tcount[t0], 1u);
+      }
+      for (int k = tid + kBlock; k < nt; k += kBlock) {
+        const uint32_t t = nth_tile(G, tr, k);
         const uint32_t slot = atomicAdd(&geo.tcount[t], 1u);
         if (slot < kTileCap) geo.tlist[(size_t)t * kTileCap + slot] = (uint32_t)b;
-      });
+      }
     }
   }
   const int Dx = win[0].dhi - win[0].dlo + 1;
@@ -360,23 +446,34 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   const T* __restrict__ S = nullptr;  // exact-time coupling: the current state
   if constexpr (EXACT) S = static_cast<const T*>(geo.state);
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int f = tid; f < total; f += kBlock) {
-    const int i = f % Dx, r = f / Dx;
-    const int j = r % Dy, k = r / Dy;
-    const int vx = win[0].dlo + i, vy = win[1].dlo + j, vz = win[2].dlo + k;
-    const int ix = vx - win[0].lo + 1, iy = vy - win[1].lo + 1, iz = vz - win[2].lo + 1;
+  // The thread's window entries f = tid, tid + kBlock, ... as f = i + Dx (j + Dy k), stepped by
+  // kBlock entries with carries (one division per thread). cell_of: the lattice cell of the
+  // current entry and its weight indices; accumulate: the cell's velocity times its weight and
+  // curl weights into the six sums.
+  int ci = tid % Dx, cj = (tid / Dx) % Dy, ck = tid / Dx / Dy;
+  const int di = kBlock % Dx, dj = (kBlock / Dx) % Dy, dk = kBlock / Dx / Dy;
+  auto advance = [&]() {
+    ci += di;
+    const int carry = ci >= Dx;
+    if (carry) ci -= Dx;
+    cj += dj + carry;
+    if (cj >= Dy) {
+      cj -= Dy;
+      ++ck;
+    }
+    ck += dk;
+  };
+  auto cell_of = [&](int& ix, int& iy, int& iz) {
+    const int vx = win[0].dlo + ci, vy = win[1].dlo + cj, vz = win[2].dlo + ck;
+    ix = vx - win[0].lo + 1;
+    iy = vy - win[1].lo + 1;
+    iz = vz - win[2].lo + 1;
     const int x = px ? wrapi(vx, G.nx) : vx;
     const int y = py ? wrapi(vy, G.ny) : vy;
     const int z = pz ? wrapi(vz, G.nz) : vz;
-    const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
-    double ux, uy, uz;
-    if constexpr (EXACT) {
-      state_velocity<T>(S, G, x, y, z, c, ux, uy, uz);
-    } else {
-      ux = (double)U[c];
-      uy = (double)U[G.N + c];
-      uz = (double)U[2 * (size_t)G.N + c];
-    }
+    return ((uint32_t)z * G.ny + y) * G.nx + x;
+  };
+  auto accumulate = [&](int ix, int iy, int iz, double ux, double uy, double uz) {
     const double wa = s_w[0][ix], da = s_dw[0][ix];
     const double wb = s_w[1][iy], db = s_dw[1][iy];
     const double wc = s_w[2][iz], dc = s_dw[2][iz];
@@ -390,8 +487,46 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
     acc[3] += uz * a_dbc - uy * a_bdc;  // dUz/dy - dUy/dz
     acc[4] += ux * a_bdc - uz * da_bc;  // dUx/dz - dUz/dx
     acc[5] += uy * da_bc - ux * a_dbc;  // dUy/dx - dUx/dy
+  };
+  if constexpr (EXACT) {
+    for (int f = tid; f < total; f += kBlock) {
+      int ix, iy, iz;
+      const uint32_t c = cell_of(ix, iy, iz);
+      const int x = (int)(c % (uint32_t)G.nx), y = (int)((c / (uint32_t)G.nx) % (uint32_t)G.ny);
+      const int z = (int)(c / ((uint32_t)G.nx * G.ny));
+      double ux, uy, uz;
+      state_velocity<T>(S, G, x, y, z, c, ux, uy, uz);
+      accumulate(ix, iy, iz, ux, uy, uz);
+      advance();
+    }
+  } else {
+    // kGather cells per thread in flight: their loads issued together, then the sums in the
+    // order of the cells (each thread's terms in the same order as one cell at a time)
+    constexpr int kGather = 8;
+    for (int f0 = tid; f0 < total; f0 += kGather * kBlock) {
+      int ix[kGather], iy[kGather], iz[kGather];
+      T u[kGather][3];
+#pragma clang loop unroll(full)
+      for (int s = 0; s < kGather; ++s) {
+        if (f0 + s * kBlock < total) {
+          const uint32_t c = cell_of(ix[s], iy[s], iz[s]);
+          u[s][0] = U[c];
+          u[s][1] = U[G.N + c];
+          u[s][2] = U[2 * (size_t)G.N + c];
+          advance();
+        }
+      }
+#pragma clang loop unroll(full)
+      for (int s = 0; s < kGather; ++s) {
+        if (f0 + s * kBlock < total)
+          accumulate(ix[s], iy[s], iz[s], (double)u[s][0], (double)u[s][1], (double)u[s][2]);
+      }
+    }
   }
-  for (int m = 0; m < 6; ++m) acc[m] = block_sum(acc[m], s_red, tid);
+  if constexpr (std::is_same_v<Geo, OneColumn>) {
+    if (slot0 < kTileCap) geo.tlist[(size_t)t0 * kTileCap + slot0] = (uint32_t)b;
+  }
+  block_sum6(acc, s_red6, tid);
   if (tid == 0) {
     for (int m = 0; m < 6; ++m) work[W_UL + m] = acc[m];
     work[W_X0 + 0] = xb[0];
@@ -474,8 +609,21 @@ __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3
   const double nu = col.nu;
   const bubble_params& P = A.P;
   double* work = A.S.work + (size_t)b * kWork;
+  // every load of the update at once (one round trip; all in bounds for b < nb)
   const int st = A.S.state[b];
-  if (st == 0 || work[W_VALID] == 0.0) {
+  const double valid = work[W_VALID];
+  const double d = A.S.d[b];
+  const double ul[3] = {work[W_UL], work[W_UL + 1], work[W_UL + 2]};
+  const double wl[3] = {work[W_WL], work[W_WL + 1], work[W_WL + 2]};
+  const double ulp[3] = {A.S.ulx[b], A.S.uly[b], A.S.ulz[b]};
+  double ub[3] = {A.S.ux[b], A.S.uy[b], A.S.uz[b]};
+  double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
+  // the values as operands of an empty statement: the compiler keeps the loads above the branch
+  // below instead of moving them into the branch's live path (a second round trip)
+  asm volatile("" ::"v"(d), "v"(ul[0]), "v"(ul[1]), "v"(ul[2]), "v"(wl[0]), "v"(wl[1]), "v"(wl[2]),
+               "v"(ulp[0]), "v"(ulp[1]), "v"(ulp[2]), "v"(ub[0]), "v"(ub[1]), "v"(ub[2]),
+               "v"(xn[0]), "v"(xn[1]), "v"(xn[2]));
+  if (st == 0 || valid == 0.0) {
     if (A.S.psix) {
       A.S.psix[b] = 0.0;
       A.S.psiy[b] = 0.0;
@@ -484,21 +632,16 @@ __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3
     return false;
   }
   const int ext[3] = {G.nx, G.ny, G.nz};
-  const double d = A.S.d[b];
-  const double ul[3] = {work[W_UL], work[W_UL + 1], work[W_UL + 2]};
-  const double wl[3] = {work[W_WL], work[W_WL + 1], work[W_WL + 2]};
   double dul[3] = {0.0, 0.0, 0.0};
   if (st == 2) {  // material derivative of u_l along the path, dt_l = 1
-    dul[0] = ul[0] - A.S.ulx[b];
-    dul[1] = ul[1] - A.S.uly[b];
-    dul[2] = ul[2] - A.S.ulz[b];
+    dul[0] = ul[0] - ulp[0];
+    dul[1] = ul[1] - ulp[1];
+    dul[2] = ul[2] - ulp[2];
   }
   const BubbleConst kc = bubble_constants(P, nu, d);
   const double dt = 1.0 / P.n_sub;
   const int reaction = P.coupling & LBM_REACTION_MASK;
   const double m_b = P.rho_b * kc.V;
-  double ub[3] = {A.S.ux[b], A.S.uy[b], A.S.uz[b]};
-  double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
   // sums over the sub-steps of F_D + F_L and of the net force m_b du_b/dt (reaction variants)
   double s_dl[3] = {0.0, 0.0, 0.0}, s_net[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < P.n_sub; ++k) {

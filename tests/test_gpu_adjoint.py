@@ -115,3 +115,37 @@ def test_adjoint_full_column_against_oracle_gradient():
     # drag and omega components to 2 %, the lift component (orders of magnitude smaller at these
     # Reynolds numbers) to 2 % of the largest component
     assert np.allclose(g, fd, rtol=2e-2, atol=2e-2 * scale)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision,steps", [("f32", 130), ("f64", 120)])
+def test_graph_replayed_segments_match_eager_steps(precision, steps):
+    """Segments replayed from HIP graphs (K = 20; 130 steps leave a partial last segment that runs
+    eagerly) against the same problem stepped call by call: the same trajectory bit for bit and
+    the same gradient up to the order of the atomic additions into it. Every replay follows eager
+    work on the stream (checkpoint saves, segment restores), and the gradient pass runs twice on
+    the graph problem, the second time with one segment timed eagerly."""
+    w = _small(steps=steps)
+    th0 = w.meta["theta0"]
+    pe = A.TrajectoryProblem(w.shape, w.bc, w.pos, w.d, w.params, w.steps, precision=precision,
+                             checkpoint=20, graphs=False)
+    pg = A.TrajectoryProblem(w.shape, w.bc, w.pos, w.d, w.params, w.steps, precision=precision,
+                             checkpoint=20, graphs=True)
+    assert pg.graphs and not pe.graphs
+    print(f"[case] {precision}, {steps} steps, K = 20", flush=True)
+    te, se, _ = pe.forward(w.meta["target"], checkpoints=False)
+    tg, sg, _ = pg.forward(w.meta["target"], checkpoints=False)
+    se.close()
+    sg.close()
+    assert torch.equal(te, tg)
+    target = te
+    Le, ge = _adjoint_grad(pe, th0, target)
+    Lg, gg = _adjoint_grad(pg, th0, target)
+    pg.liquid_events = []
+    Lt, gt = _adjoint_grad(pg, th0, target)
+    print(f"eager {ge}, graphs {gg}, graphs with a timed segment {gt}", flush=True)
+    assert Le == Lg == Lt
+    assert len(pg.liquid_events) == (steps % 20 or 20)
+    scale = np.abs(ge).max()
+    assert np.allclose(gg, ge, rtol=1e-12, atol=1e-13 * scale)
+    assert np.allclose(gt, ge, rtol=1e-12, atol=1e-13 * scale)
