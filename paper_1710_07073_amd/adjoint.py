@@ -8,13 +8,6 @@ backward pass walks the segments newest first: it restores the segment's checkpo
 segment forward while storing each step's inputs (population buffer, velocity field, force field,
 bubble record), then applies the adjoint steps in reverse order. Every step of the method and of
 its adjoint runs in the library's kernels; PyTorch holds the buffers.
-
-With graphs (the default) and an even segment length, one segment of the forward pass and one
-segment of the backward pass (recompute and reverse sweep) are each captured once as a HIP graph
-on the problem's own stream and replayed for every full segment: the launches name the same
-buffers in every segment (the segment's inputs and outputs go through fixed staging buffers), and
-after an even number of steps the library's host-side step parities are back where the capture
-started. A partial last segment runs eagerly.
 """
 from __future__ import annotations
 
@@ -37,7 +30,7 @@ class TrajectoryProblem:
     """One column with bubbles and a trajectory loss to differentiate."""
 
     def __init__(self, shape, bc, pos, d, params, steps, precision="f32", checkpoint=100,
-                 device="cuda", stream=None, graphs=True):
+                 device="cuda", stream=None):
         self.shape = tuple(shape)
         self.bc = tuple(bc)
         self.pos = np.asarray(pos, np.float64).reshape(3, -1)
@@ -48,16 +41,9 @@ class TrajectoryProblem:
         self.precision = precision
         self.K = int(checkpoint)
         self.device = torch.device(device)
-        # segments replayed from graphs: K even (see the module docstring), on a stream of the
-        # problem's own (capture needs one other than the default stream); the caller's stream
-        # is ordered before and after each pass
-        self.graphs = bool(graphs) and self.K % 2 == 0 and self.K <= self.steps
-        if self.graphs:
-            self.stream = torch.cuda.Stream(self.device)
-        else:
-            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         # when a list, backward appends a (start, end) event pair around every adjoint liquid step
-        # of one segment it runs eagerly
+        # of the first segment it processes (the last in time)
         self.liquid_events = None
 
     # ---- forward ----
@@ -81,41 +67,20 @@ class TrajectoryProblem:
 
     @staticmethod
     def _positions_into(sim, out):
+        # straight into the trajectory row (one kernel, no temporary and no device copy)
         t = sim.bubbles.t
         torch.stack([t["x"], t["y"], t["z"]], out=out)
-
-    def _capture(self, body):
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=self.stream):
-            body()
-        return g
 
     def forward(self, theta, checkpoints=True):
         """Trajectory (steps, 3, nb) on the device, the simulation, and the checkpoints."""
         caller = torch.cuda.current_stream(self.device)
+        sim = self.make_sim(theta)
         traj = torch.empty((self.steps, 3, self.nb), dtype=torch.float64, device=self.device)
+        ckpts = []
         self.stream.wait_stream(caller)
-        K = self.K
         with torch.cuda.stream(self.stream):
-            sim = self.make_sim(theta)
-            ckpts = []
-            nfull = self.steps // K if self.graphs else 0
-            if nfull:
-                seg = torch.empty((K, 3, self.nb), dtype=torch.float64, device=self.device)
-
-                def body():
-                    for i in range(K):
-                        sim.step(1)
-                        self._positions_into(sim, seg[i])
-
-                graph = self._capture(body)
-                for s in range(nfull):
-                    if checkpoints:
-                        ckpts.append(self._save(sim))
-                    graph.replay()
-                    traj[s * K:(s + 1) * K].copy_(seg)
-            for k in range(nfull * K, self.steps):
-                if checkpoints and k % K == 0:
+            for k in range(self.steps):
+                if checkpoints and k % self.K == 0:
                     ckpts.append(self._save(sim))
                 sim.step(1)
                 self._positions_into(sim, traj[k])
@@ -125,8 +90,7 @@ class TrajectoryProblem:
     # ---- backward ----
     def backward(self, theta, sim, ckpts, grad_traj):
         """dL/dtheta given dL/d(trajectory)."""
-        caller = torch.cuda.current_stream(self.device)
-        self.stream.wait_stream(caller)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(self.stream):
             return self._backward(theta, sim, ckpts, grad_traj)
 
@@ -142,21 +106,21 @@ class TrajectoryProblem:
         grad = torch.zeros(4, dtype=torch.float64, device=dev)
         # per step of a segment: the state entering it (H[i], the recompute writes H[i + 1]
         # directly), the velocity field its bubble half reads (Up[i], its collision writes
-        # Up[i + 1]), its force field and its bubble record; gseg: the segment's dL/d(trajectory)
+        # Up[i + 1]), its force field and its bubble record
         H = torch.empty((K + 1,) + tuple(pops.shape), dtype=pops.dtype, device=dev)
         Up = torch.empty((K + 1,) + tuple(sim.vel.shape), dtype=pops.dtype, device=dev)
         Fk = torch.empty((K,) + tuple(sim.vel.shape), dtype=pops.dtype, device=dev)
         rec = torch.zeros((K, nb, L.LBM_BUBBLE_RECORD), dtype=torch.float64, device=dev)
-        gseg = torch.empty((K, 3, nb), dtype=torch.float64, device=dev)
         gt = grad_traj.to(dev, torch.float64)
         # buffers are rebound between the bubble half and the liquid step: no overlapped steps
         L.lbm_set_overlap(sim.ctx, False)
         bub = sim.bubbles
-        cur = [0]  # lam[cur[0]] holds the adjoint state entering the next (earlier) step
+        cur = 0  # lam[cur] holds the adjoint state entering the next (earlier) step
 
-        def segment(n, events=None):
-            """Recompute of a segment of n steps from H[0], Up[0] and the bubble state, then its
-            adjoint steps newest first."""
+        def segment(k0, n, events=None):
+            """Recompute of the n steps from step k0 on from H[0], Up[0] and the bubble state,
+            then their adjoint steps newest first."""
+            nonlocal cur
             for i in range(n):
                 L.lbm_bind_buffers(sim.ctx, _p(H[i]), _p(H[i + 1]), _p(Up[i]))
                 L.lbm_bubble_record(sim.ctx, bub.soa, nb, 0, _p(rec[i]))
@@ -166,43 +130,31 @@ class TrajectoryProblem:
                 L.lbm_bind_buffers(sim.ctx, None, None, _p(Up[i + 1]))
                 L.lbm_step(sim.ctx, 1)
             for i in reversed(range(n)):
-                lam_b[:, 0:3] += gseg[i].t()
+                lam_b[:, 0:3] += gt[k0 + i].t()
                 ev = None
                 if events is not None:
                     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                     ev[0].record(self.stream)
-                c = cur[0]
-                L.lbm_adjoint_liquid(sim.ctx, _p(H[i]), _p(Fk[i]), _p(lam[c]), _p(lam[1 - c]),
+                L.lbm_adjoint_liquid(sim.ctx, _p(H[i]), _p(Fk[i]), _p(lam[cur]), _p(lam[1 - cur]),
                                      _p(lam_u), _p(lam_f), _p(grad))
                 if ev is not None:
                     ev[1].record(self.stream)
                     events.append(ev)
-                cur[0] = 1 - c
+                cur = 1 - cur
                 L.lbm_adjoint_bubbles(sim.ctx, sim.params, _p(rec[i]), _p(Up[i]), _p(lam_f),
                                       _p(lam_u), _p(lam_b), None, nb, _p(grad))
 
-        graph = None
         for s in reversed(range(len(ckpts))):
             k0 = s * K
             k1 = min(k0 + K, self.steps)
-            n = k1 - k0
             ck = ckpts[s]
             H[0].copy_(ck["state"])
             Up[0].copy_(ck["vel"])
             sim.force.zero_()
             for key, v in ck["bub"].items():
                 bub.t[key].copy_(v)
-            gseg[:n].copy_(gt[k0:k1])
             timed = self.liquid_events is not None and s == len(ckpts) - 1
-            if not self.graphs or n < K or timed:
-                segment(n, self.liquid_events if timed else None)
-                continue
-            if graph is None:
-                # captured with the lambda parity of this segment; K even leaves it unchanged
-                c0 = cur[0]
-                graph = self._capture(lambda: segment(K))
-                cur[0] = c0
-            graph.replay()
+            segment(k0, k1 - k0, self.liquid_events if timed else None)
         # back to the simulation's own buffers before the segment buffers go away
         L.lbm_bind_buffers(sim.ctx, _p(sim.pops[0]), _p(sim.pops[1]), _p(sim.vel))
         g = grad.cpu().numpy()

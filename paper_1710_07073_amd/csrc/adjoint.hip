@@ -163,31 +163,131 @@ __global__ __launch_bounds__(64) void k_bins(double* __restrict__ bins, uint32_t
   if (threadIdx.x == 0) grad[0] += v;
 }
 
-// Weights and derivatives of the three axes into LDS (one thread per axis).
-__device__ bool adj_weights(const Geom& G, const double* xb, double n, double (*w)[kAdjSpan],
-                            double (*dw)[kAdjSpan], double (*wx)[kAdjSpan], double (*dwx)[kAdjSpan],
-                            AxisW* win, int* s_ok) {
-  const int ext[3] = {G.nx, G.ny, G.nz};
-  if (threadIdx.x == 0) *s_ok = 1;
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    const int a = threadIdx.x;
-    const bool per = G.bc[2 * a] == BC_PER;
-    const double s_lo = G.bc[2 * a] == BC_FS ? 1.0 : -1.0;
-    const double s_hi = G.bc[2 * a + 1] == BC_FS ? 1.0 : -1.0;
-    if (!axis_weights_dx(xb[a], n, ext[a], per, s_lo, s_hi, win[a], w[a], dw[a], wx[a], dwx[a]))
-      *s_ok = 0;
+// Weights of axis AX with their derivatives in the bubble coordinate, computed by one wavefront
+// and stored in LDS, indexed by cell - lo + 1 (the forward's weights bit for bit: the same terms,
+// the same butterfly sum, the same renormalisation). Lane l holds entries l and l + 64 (kAdjSpan
+// = 66: lanes 0 and 1 hold a second one); the curl weights take their neighbours by shuffles,
+// so the wavefront needs no barrier. Returns false (every lane) if the window is too large.
+template <int AX>
+__device__ bool wave_weights_dx(const Geom& G, const double* xb, double n, int lane,
+                                double (*w)[kAdjSpan], double (*dw)[kAdjSpan],
+                                double (*wx)[kAdjSpan], double (*dwx)[kAdjSpan], AxisW* win) {
+  static_assert(kAdjSpan > 64 && kAdjSpan <= 128, "two entries per lane");
+  const int ext = AX == 0 ? G.nx : (AX == 1 ? G.ny : G.nz);
+  const bool per = G.bc[2 * AX] == BC_PER;
+  const double s_lo = G.bc[2 * AX] == BC_FS ? 1.0 : -1.0;
+  const double s_hi = G.bc[2 * AX + 1] == BC_FS ? 1.0 : -1.0;
+  const double x = xb[AX];
+  AxisW A;
+  if (!axis_window_hd(x, n, ext, per, A)) return false;
+  const int i0 = lane, i1 = lane + 64;
+  auto entry = [&](int i, double& wi, double& di) {
+    const int v = A.lo - 1 + i;
+    wi = 0.0;
+    di = 0.0;
+    if (i < kAdjSpan && v >= A.clo && v <= A.chi) {
+      const double sp = (v + 0.5 - x) / n, sm = (v - 0.5 - x) / n;
+      wi = kernel_P(sp) - kernel_P(sm);
+      di = -(kernel_dP(sp) - kernel_dP(sm)) / n;
+    }
+  };
+  double w0, w1, d0, d1;
+  entry(i0, w0, d0);
+  entry(i1, w1, d1);
+  if (!per) {  // clipped at a wall: renormalise, d(w/S) = (dw - (w/S) dS) / S
+    const double sum = wsum(w0 + w1), dsum = wsum(d0 + d1);
+    if (sum > 0.0) {
+      w0 /= sum;
+      w1 /= sum;
+      d0 = (d0 - w0 * dsum) / sum;
+      d1 = (d1 - w1 * dsum) / sum;
+    }
   }
-  __syncthreads();
-  return *s_ok != 0;
+  // neighbours: entry l - 1 and l + 1 of entry l; entry 63, 64 and 65 for the second entries
+  const int up = (lane + 63) & 63, dn = (lane + 1) & 63;
+  const double wu = __shfl(w0, up, 64), wd = __shfl(w0, dn, 64);
+  const double du = __shfl(d0, up, 64), dd = __shfl(d0, dn, 64);
+  const double w64 = __shfl(w1, 0, 64), w65 = __shfl(w1, 1, 64);
+  const double d64 = __shfl(d1, 0, 64), d65 = __shfl(d1, 1, 64);
+  auto curl = [&](int i, double wi, double di, double wm, double wp, double xm, double xp) {
+    const int v = A.lo - 1 + i;
+    double c = 0.5 * (wm - wp), cx = 0.5 * (xm - xp);
+    if (!per) {
+      if (v == 0) {
+        c -= 0.5 * s_lo * wi;
+        cx -= 0.5 * s_lo * di;
+      }
+      if (v == ext - 1) {
+        c += 0.5 * s_hi * wi;
+        cx += 0.5 * s_hi * di;
+      }
+    }
+    w[AX][i] = wi;
+    wx[AX][i] = di;
+    dw[AX][i] = c;
+    dwx[AX][i] = cx;
+  };
+  curl(i0, w0, d0, lane > 0 ? wu : 0.0, lane < 63 ? wd : w64, lane > 0 ? du : 0.0,
+       lane < 63 ? dd : d64);
+  if (i1 < kAdjSpan) {
+    const bool first = lane == 0;  // entry 64 (neighbours 63, 65), else entry 65 (64, none)
+    curl(i1, w1, d1, first ? wu : w64, first ? w65 : 0.0, first ? du : d64, first ? d65 : 0.0);
+  }
+  if (lane == 0) win[AX] = A;
+  return true;
 }
 
-// The bubble half of the adjoint for one bubble per workgroup. Phases, separated by barriers:
-//   gather   dL/dpsi = sum_j W_j dL/dF(j), and the position term of the spreading weights;
-//   reverse  sweep of the sub-stepped ODE (ode_adjoint), one lane;
-//   scatter  transpose of the interpolation: dL/dU(j) += W_j dL/du_l + curl weights . dL/dw_l
-//            (atomic adds), and the position term of the interpolation weights.
-// The weights and their derivatives are computed once, in LDS, for both stencil phases.
+// The six sums of the gather over the workgroup behind one barrier (the order of bsum).
+__device__ __forceinline__ void bsum6(double v[6], double (*s_red6)[kBW]) {
+#pragma unroll
+  for (int m = 0; m < 6; ++m) v[m] = wsum(v[m]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int m = 0; m < 6; ++m) s_red6[m][threadIdx.x >> 6] = v[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    double t = 0.0;
+    for (int w = 0; w < kBW; ++w) t += s_red6[m][w];
+    v[m] = t;
+  }
+}
+
+// Window entries f = tid, tid + kB, ... of a box Dx x Dy x Dz as f = i + Dx (j + Dy k), stepped
+// by kB entries with carries.
+struct WindowWalk {
+  int Dx, Dy, i, j, k, di, dj, dk;
+  __device__ WindowWalk(int Dx_, int Dy_, int f) : Dx(Dx_), Dy(Dy_) {
+    i = f % Dx;
+    j = (f / Dx) % Dy;
+    k = f / Dx / Dy;
+    di = kB % Dx;
+    dj = (kB / Dx) % Dy;
+    dk = kB / Dx / Dy;
+  }
+  __device__ void advance() {
+    i += di;
+    const int carry = i >= Dx;
+    if (carry) i -= Dx;
+    j += dj + carry;
+    if (j >= Dy) {
+      j -= Dy;
+      ++k;
+    }
+    k += dk;
+  }
+};
+
+// The bubble half of the adjoint for one bubble per workgroup:
+//   wavefronts 0-2   the weights of axis 0, 1, 2 (with their derivatives), side by side with
+//   wavefront 3      the forward sub-steps again (one lane, recording the sub-step velocities);
+//   all              the gather dL/dpsi = sum_j W_j dL/dF(j) and the position term of the spreading
+//                    weights, while lanes of wavefront 3 first evaluate the n_sub + 1 force
+//                    Jacobians at the recorded velocities;
+//   lane 0           the reverse sweep of the sub-steps (ode_adjoint_sweep), while every thread
+//                    loads the velocities of its first scatter cells;
+//   all              the scatter, transpose of the interpolation: dL/dU(j) += W_j dL/du_l + curl
+//                    weights . dL/dw_l (atomic adds), and the position term of the interpolation.
 template <typename T>
 __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
                                                    const T* __restrict__ U, T* __restrict__ lam_u,
@@ -196,64 +296,39 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
                                                    double nu, int nb, double* __restrict__ grad) {
   __shared__ double w[3][kAdjSpan], dw[3][kAdjSpan], wx[3][kAdjSpan], dwx[3][kAdjSpan];
   __shared__ AxisW win[3];
-  __shared__ double s_red[kBW];
-  __shared__ int s_ok;
-  __shared__ double s_lpsi[3], s_gx[3], s_lul[3], s_lwl[3], s_gxode[3];
+  __shared__ int s_bad[3];
+  __shared__ double s_red6[6][kBW];
+  __shared__ double s_lul[3], s_lwl[3];
   __shared__ double s_ubs[kMaxSub + 1][3];
   __shared__ unsigned char s_clamped[kMaxSub][3];
   __shared__ ForceJac s_jac[kMaxSub + 1];
   const int b = (int)xcd_remap(blockIdx.x, nb);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double* r = rec + (size_t)b * R_SIZE;
   double* l = lam + (size_t)b * A_SIZE;
   const int st = (int)r[R_STATE];
   // a frozen bubble (inactive, or no valid window in the step): its adjoint state passes through
   if (st == 0 || r[R_VALID] == 0.0) return;
   const double xb[3] = {r[R_X], r[R_X + 1], r[R_X + 2]};
-  if (!adj_weights(G, xb, P.kernel_factor * r[R_D], w, dw, wx, dwx, win, &s_ok)) return;
-  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
-
-  // gather
-  {
-    const double psi[3] = {r[R_PSI], r[R_PSI + 1], r[R_PSI + 2]};
-    const int Kx = win[0].chi - win[0].clo + 1, Ky = win[1].chi - win[1].clo + 1,
-              Kz = win[2].chi - win[2].clo + 1;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int f = threadIdx.x; f < Kx * Ky * Kz; f += kB) {
-      const int i = f % Kx, rr = f / Kx, j = rr % Ky, k = rr / Ky;
-      const int vx = win[0].clo + i, vy = win[1].clo + j, vz = win[2].clo + k;
-      const int ix = vx - win[0].lo + 1, iy = vy - win[1].lo + 1, iz = vz - win[2].lo + 1;
-      const int x = px ? wrapi(vx, G.nx) : vx, y = py ? wrapi(vy, G.ny) : vy,
-                z = pz ? wrapi(vz, G.nz) : vz;
-      const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
-      const double l0 = (double)lam_f[c], l1 = (double)lam_f[G.N + c],
-                   l2 = (double)lam_f[2 * (size_t)G.N + c];
-      const double a = w[0][ix], bb = w[1][iy], cc = w[2][iz];
-      const double W = a * bb * cc;
-      const double pl = psi[0] * l0 + psi[1] * l1 + psi[2] * l2;
-      acc[0] += W * l0;
-      acc[1] += W * l1;
-      acc[2] += W * l2;
-      acc[3] += wx[0][ix] * bb * cc * pl;
-      acc[4] += a * wx[1][iy] * cc * pl;
-      acc[5] += a * bb * wx[2][iz] * pl;
-    }
-    for (int m = 0; m < 6; ++m) acc[m] = bsum(acc[m], s_red);
-    if (threadIdx.x == 0)
-      for (int m = 0; m < 3; ++m) {
-        s_lpsi[m] = acc[m];
-        s_gx[m] = acc[3 + m];
-      }
-  }
-  __syncthreads();
-
-  // reverse sweep of the sub-steps: the forward sub-steps again (one lane), the force Jacobians
-  // at their velocities (one lane each), then the sweep (one lane)
   const double* ul = r + R_UL;
   const double* ulp = r + R_ULP;
   double dul[3] = {0.0, 0.0, 0.0};
   if (st == 2)
     for (int a = 0; a < 3; ++a) dul[a] = ul[a] - ulp[a];
-  if (threadIdx.x == 0) {
+
+  // weights (wavefronts 0-2) beside the forward sub-steps (wavefront 3)
+  if (wave < 3) {
+    const double n = P.kernel_factor * r[R_D];
+    bool ok;
+    if (wave == 0)
+      ok = wave_weights_dx<0>(G, xb, n, lane, w, dw, wx, dwx, win);
+    else if (wave == 1)
+      ok = wave_weights_dx<1>(G, xb, n, lane, w, dw, wx, dwx, win);
+    else
+      ok = wave_weights_dx<2>(G, xb, n, lane, w, dw, wx, dwx, win);
+    if (lane == 0) s_bad[wave] = ok ? 0 : 1;
+  } else if (lane == 0) {
     OdeBounds Bd;
     const int ext[3] = {G.nx, G.ny, G.nz};
     for (int a = 0; a < 3; ++a) {
@@ -265,19 +340,98 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
     ode_forward(P, nu, r[R_D], r + R_X, r + R_UB, ul, r + R_WL, dul, Bd, o, s_ubs, s_clamped);
   }
   __syncthreads();
-  if (threadIdx.x <= P.n_sub) {
+  if (s_bad[0] | s_bad[1] | s_bad[2]) return;  // the forward step flagged this bubble's window
+  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+  auto cell = [&](int vx, int vy, int vz) {
+    const int x = px ? wrapi(vx, G.nx) : vx, y = py ? wrapi(vy, G.ny) : vy,
+              z = pz ? wrapi(vz, G.nz) : vz;
+    return ((uint32_t)z * G.ny + y) * G.nx + x;
+  };
+  constexpr int kBatch = 8;  // cells per thread whose loads are in flight together
+
+  // force Jacobians at the sub-step velocities (lanes of wavefront 3), then the gather
+  if (wave == 3 && lane <= P.n_sub) {
     const ForceConst fc = force_const(P, nu, r[R_D]);
-    force_jac(P, fc, nu, r[R_D], s_ubs[threadIdx.x], ul, r + R_WL, s_jac[threadIdx.x]);
+    force_jac(P, fc, nu, r[R_D], s_ubs[lane], ul, r + R_WL, s_jac[lane]);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  {
+    const double psi[3] = {r[R_PSI], r[R_PSI + 1], r[R_PSI + 2]};
+    const int Kx = win[0].chi - win[0].clo + 1, Ky = win[1].chi - win[1].clo + 1,
+              Kz = win[2].chi - win[2].clo + 1;
+    const int total = Kx * Ky * Kz;
+    WindowWalk it(Kx, Ky, tid);
+    for (int f0 = tid; f0 < total; f0 += kBatch * kB) {
+      int ix[kBatch], iy[kBatch], iz[kBatch];
+      T lf[kBatch][3];
+#pragma clang loop unroll(full)
+      for (int s = 0; s < kBatch; ++s) {
+        if (f0 + s * kB < total) {
+          const int vx = win[0].clo + it.i, vy = win[1].clo + it.j, vz = win[2].clo + it.k;
+          ix[s] = vx - win[0].lo + 1;
+          iy[s] = vy - win[1].lo + 1;
+          iz[s] = vz - win[2].lo + 1;
+          const uint32_t c = cell(vx, vy, vz);
+          lf[s][0] = lam_f[c];
+          lf[s][1] = lam_f[G.N + c];
+          lf[s][2] = lam_f[2 * (size_t)G.N + c];
+          it.advance();
+        }
+      }
+#pragma clang loop unroll(full)
+      for (int s = 0; s < kBatch; ++s) {
+        if (f0 + s * kB < total) {
+          const double l0 = (double)lf[s][0], l1 = (double)lf[s][1], l2 = (double)lf[s][2];
+          const double a = w[0][ix[s]], bb = w[1][iy[s]], cc = w[2][iz[s]];
+          const double W = a * bb * cc;
+          const double pl = psi[0] * l0 + psi[1] * l1 + psi[2] * l2;
+          acc[0] += W * l0;
+          acc[1] += W * l1;
+          acc[2] += W * l2;
+          acc[3] += wx[0][ix[s]] * bb * cc * pl;
+          acc[4] += a * wx[1][iy[s]] * cc * pl;
+          acc[5] += a * bb * wx[2][iz[s]] * pl;
+        }
+      }
+    }
+  }
+  bsum6(acc, s_red6);  // every thread now holds dL/dpsi (0-2) and the spreading position term
+
+  // the reverse sweep (lane 0) while every thread loads its first scatter cells
+  const int Dx = win[0].dhi - win[0].dlo + 1, Dy = win[1].dhi - win[1].dlo + 1,
+            Dz = win[2].dhi - win[2].dlo + 1;
+  const int dtotal = Dx * Dy * Dz;
+  WindowWalk it(Dx, Dy, tid);
+  int ix[kBatch], iy[kBatch], iz[kBatch];
+  uint32_t cs[kBatch];
+  T u[kBatch][3];
+  auto load_batch = [&](int f0) {
+#pragma clang loop unroll(full)
+    for (int s = 0; s < kBatch; ++s) {
+      if (f0 + s * kB < dtotal) {
+        const int vx = win[0].dlo + it.i, vy = win[1].dlo + it.j, vz = win[2].dlo + it.k;
+        ix[s] = vx - win[0].lo + 1;
+        iy[s] = vy - win[1].lo + 1;
+        iz[s] = vz - win[2].lo + 1;
+        cs[s] = cell(vx, vy, vz);
+        u[s][0] = U[cs[s]];
+        u[s][1] = U[G.N + cs[s]];
+        u[s][2] = U[2 * (size_t)G.N + cs[s]];
+        it.advance();
+      }
+    }
+  };
+  load_batch(tid);
+  double gxode[3] = {0.0, 0.0, 0.0};
+  if (tid == 0) {
+    const double lpsi[3] = {acc[0], acc[1], acc[2]};
     OdeAdj g;
-    ode_adjoint_sweep(P, r[R_D], s_clamped, s_jac, l + A_X, l + A_UB, s_lpsi, g);
+    ode_adjoint_sweep(P, r[R_D], s_clamped, s_jac, l + A_X, l + A_UB, lpsi, g);
     for (int a = 0; a < 3; ++a) {
       // u_l enters the drag/lift, D_t u_l = u_l - u_l,prev (state 2) and u_l,prev of the next step
       s_lul[a] = g.ul[a] + (st == 2 ? g.dul[a] : 0.0) + l[A_ULP + a];
       s_lwl[a] = g.wl[a];
-      s_gxode[a] = g.x[a];
+      gxode[a] = g.x[a];
       l[A_UB + a] = g.ub[a];
       l[A_ULP + a] = st == 2 ? -g.dul[a] : 0.0;
     }
@@ -290,53 +444,52 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
   // scatter
   const double lu[3] = {s_lul[0], s_lul[1], s_lul[2]};
   const double lw[3] = {s_lwl[0], s_lwl[1], s_lwl[2]};
-  const int Dx = win[0].dhi - win[0].dlo + 1, Dy = win[1].dhi - win[1].dlo + 1,
-            Dz = win[2].dhi - win[2].dlo + 1;
-  double gx[3] = {0, 0, 0};
-  for (int f = threadIdx.x; f < Dx * Dy * Dz; f += kB) {
-    const int i = f % Dx, rr = f / Dx, j = rr % Dy, k = rr / Dy;
-    const int vx = win[0].dlo + i, vy = win[1].dlo + j, vz = win[2].dlo + k;
-    const int ix = vx - win[0].lo + 1, iy = vy - win[1].lo + 1, iz = vz - win[2].lo + 1;
-    const int x = px ? wrapi(vx, G.nx) : vx, y = py ? wrapi(vy, G.ny) : vy,
-              z = pz ? wrapi(vz, G.nz) : vz;
-    const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
-    const double a = w[0][ix], da = dw[0][ix], bb = w[1][iy], db = dw[1][iy], cc = w[2][iz],
-                 dc = dw[2][iz];
-    // forward: ul += W U; wx += Uz a db c - Uy a b dc; wy += Ux a b dc - Uz da b c;
-    //          wz += Uy da b c - Ux a db c
-    const double W = a * bb * cc, adbc = a * db * cc, abdc = a * bb * dc, dabc = da * bb * cc;
-    const double gUx = W * lu[0] + abdc * lw[1] - adbc * lw[2];
-    const double gUy = W * lu[1] - abdc * lw[0] + dabc * lw[2];
-    const double gUz = W * lu[2] + adbc * lw[0] - dabc * lw[1];
-    if (gUx != 0.0) atomicAdd(&lam_u[c], (T)gUx);
-    if (gUy != 0.0) atomicAdd(&lam_u[G.N + c], (T)gUy);
-    if (gUz != 0.0) atomicAdd(&lam_u[2 * (size_t)G.N + c], (T)gUz);
-    const double ux = (double)U[c], uy = (double)U[G.N + c], uz = (double)U[2 * (size_t)G.N + c];
-    // derivative of the same sums in the bubble coordinate along each axis
-    const double ax = wx[0][ix], dax = dwx[0][ix], by = wx[1][iy], dby = dwx[1][iy],
-                 cz = wx[2][iz], dcz = dwx[2][iz];
-    {  // x: a -> ax, da -> dax
-      const double Wd = ax * bb * cc, adbc_d = ax * db * cc, abdc_d = ax * bb * dc, dabc_d = dax * bb * cc;
-      gx[0] += lu[0] * Wd * ux + lu[1] * Wd * uy + lu[2] * Wd * uz +
-               lw[0] * (uz * adbc_d - uy * abdc_d) + lw[1] * (ux * abdc_d - uz * dabc_d) +
-               lw[2] * (uy * dabc_d - ux * adbc_d);
-    }
-    {  // y: b -> by, db -> dby
-      const double Wd = a * by * cc, adbc_d = a * dby * cc, abdc_d = a * by * dc, dabc_d = da * by * cc;
-      gx[1] += lu[0] * Wd * ux + lu[1] * Wd * uy + lu[2] * Wd * uz +
-               lw[0] * (uz * adbc_d - uy * abdc_d) + lw[1] * (ux * abdc_d - uz * dabc_d) +
-               lw[2] * (uy * dabc_d - ux * adbc_d);
-    }
-    {  // z: c -> cz, dc -> dcz
-      const double Wd = a * bb * cz, adbc_d = a * db * cz, abdc_d = a * bb * dcz, dabc_d = da * bb * cz;
-      gx[2] += lu[0] * Wd * ux + lu[1] * Wd * uy + lu[2] * Wd * uz +
-               lw[0] * (uz * adbc_d - uy * abdc_d) + lw[1] * (ux * abdc_d - uz * dabc_d) +
-               lw[2] * (uy * dabc_d - ux * adbc_d);
+  double gx[6] = {0, 0, 0, 0, 0, 0};  // 3-5 unused: the six-sum reduction
+  for (int f0 = tid; f0 < dtotal; f0 += kBatch * kB) {
+    if (f0 != tid) load_batch(f0);
+#pragma clang loop unroll(full)
+    for (int s = 0; s < kBatch; ++s) {
+      if (f0 + s * kB >= dtotal) continue;
+      const uint32_t c = cs[s];
+      const double a = w[0][ix[s]], da = dw[0][ix[s]], bb = w[1][iy[s]], db = dw[1][iy[s]],
+                   cc = w[2][iz[s]], dc = dw[2][iz[s]];
+      // forward: ul += W U; wx += Uz a db c - Uy a b dc; wy += Ux a b dc - Uz da b c;
+      //          wz += Uy da b c - Ux a db c
+      const double W = a * bb * cc, adbc = a * db * cc, abdc = a * bb * dc, dabc = da * bb * cc;
+      const double gUx = W * lu[0] + abdc * lw[1] - adbc * lw[2];
+      const double gUy = W * lu[1] - abdc * lw[0] + dabc * lw[2];
+      const double gUz = W * lu[2] + adbc * lw[0] - dabc * lw[1];
+      if (gUx != 0.0) atomicAdd(&lam_u[c], (T)gUx);
+      if (gUy != 0.0) atomicAdd(&lam_u[G.N + c], (T)gUy);
+      if (gUz != 0.0) atomicAdd(&lam_u[2 * (size_t)G.N + c], (T)gUz);
+      const double ux = (double)u[s][0], uy = (double)u[s][1], uz = (double)u[s][2];
+      // derivative of the same sums in the bubble coordinate along each axis
+      const double ax = wx[0][ix[s]], dax = dwx[0][ix[s]], by = wx[1][iy[s]], dby = dwx[1][iy[s]],
+                   cz = wx[2][iz[s]], dcz = dwx[2][iz[s]];
+      {  // x: a -> ax, da -> dax
+        const double Wd = ax * bb * cc, adbc_d = ax * db * cc, abdc_d = ax * bb * dc, dabc_d = dax * bb * cc;
+        gx[0] += lu[0] * Wd * ux + lu[1] * Wd * uy + lu[2] * Wd * uz +
+                 lw[0] * (uz * adbc_d - uy * abdc_d) + lw[1] * (ux * abdc_d - uz * dabc_d) +
+                 lw[2] * (uy * dabc_d - ux * adbc_d);
+      }
+      {  // y: b -> by, db -> dby
+        const double Wd = a * by * cc, adbc_d = a * dby * cc, abdc_d = a * by * dc, dabc_d = da * by * cc;
+        gx[1] += lu[0] * Wd * ux + lu[1] * Wd * uy + lu[2] * Wd * uz +
+                 lw[0] * (uz * adbc_d - uy * abdc_d) + lw[1] * (ux * abdc_d - uz * dabc_d) +
+                 lw[2] * (uy * dabc_d - ux * adbc_d);
+      }
+      {  // z: c -> cz, dc -> dcz
+        const double Wd = a * bb * cz, adbc_d = a * db * cz, abdc_d = a * bb * dcz, dabc_d = da * bb * cz;
+        gx[2] += lu[0] * Wd * ux + lu[1] * Wd * uy + lu[2] * Wd * uz +
+                 lw[0] * (uz * adbc_d - uy * abdc_d) + lw[1] * (ux * abdc_d - uz * dabc_d) +
+                 lw[2] * (uy * dabc_d - ux * adbc_d);
+      }
     }
   }
-  for (int m = 0; m < 3; ++m) gx[m] = bsum(gx[m], s_red);
-  if (threadIdx.x == 0)
-    for (int a = 0; a < 3; ++a) l[A_X + a] = s_gxode[a] + s_gx[a] + gx[a];
+  // s_red6 is free again: every thread read its gather sums before the sweep's barrier
+  bsum6(gx, s_red6);
+  if (tid == 0)
+    for (int a = 0; a < 3; ++a) l[A_X + a] = gxode[a] + acc[3 + a] + gx[a];
 }
 
 // Step record of every bubble (one lane per bubble): stage 0, before the step's bubble half, takes

@@ -384,7 +384,11 @@ __device__ __forceinline__ void state_velocity(const T* __restrict__ src, const 
 // Forward coupling: u_l = sum W U and w_l = sum W curl U over the window.
 // ---------------------------------------------------------------------------------------------
 // EXACT: the exact-time coupling variant (single lattice), reading the current state's velocity.
-template <typename T, typename Geo, bool EXACT = false>
+// GATHER: window cells per thread whose loads are in flight together. Few bubbles (all their
+// workgroups on the chip at once): 8, so each thread waits for one round trip per 8 cells. Many
+// bubbles: 1, at 50 VGPRs instead of 108, so that more workgroups stay resident beside the bulk
+// launch (20 000 bubbles: 394 us against 1289 us with 8).
+template <typename T, typename Geo, bool EXACT = false, int GATHER = 1>
 __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   __shared__ double s_w[3][kSpan];
   __shared__ double s_dw[3][kSpan];
@@ -502,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   } else {
     // kGather cells per thread in flight: their loads issued together, then the sums in the
     // order of the cells (each thread's terms in the same order as one cell at a time)
-    constexpr int kGather = 8;
+    constexpr int kGather = GATHER;
     for (int f0 = tid; f0 < total; f0 += kGather * kBlock) {
       int ix[kGather], iy[kGather], iz[kGather];
       T u[kGather][3];
@@ -974,6 +978,10 @@ __global__ __launch_bounds__(64) void k_mark(Geo geo, BubbleArgs A, uint32_t* __
     }
 }
 
+// Bubble counts up to which k_interp keeps 8 cells' loads in flight per thread: one workgroup per
+// bubble, at 108 VGPRs four of them per compute unit, 1024 on the chip.
+constexpr int kInterpLatencyMaxBubbles = 1024;
+
 template <typename T, typename Geo>
 hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_t stream) {
   const int nb = A.nb;
@@ -982,8 +990,10 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
   if (exact) {
     if constexpr (std::is_same_v<Geo, OneColumn>)
       hipLaunchKernelGGL((k_interp<T, Geo, true>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+  } else if (nb <= kInterpLatencyMaxBubbles) {
+    hipLaunchKernelGGL((k_interp<T, Geo, false, 8>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
   } else {
-    hipLaunchKernelGGL((k_interp<T, Geo>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+    hipLaunchKernelGGL((k_interp<T, Geo, false, 1>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -118,34 +118,20 @@ def test_adjoint_full_column_against_oracle_gradient():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("precision,steps", [("f32", 130), ("f64", 120)])
-def test_graph_replayed_segments_match_eager_steps(precision, steps):
-    """Segments replayed from HIP graphs (K = 20; 130 steps leave a partial last segment that runs
-    eagerly) against the same problem stepped call by call: the same trajectory bit for bit and
-    the same gradient up to the order of the atomic additions into it. Every replay follows eager
-    work on the stream (checkpoint saves, segment restores), and the gradient pass runs twice on
-    the graph problem, the second time with one segment timed eagerly."""
-    w = _small(steps=steps)
+def test_timed_segment_gives_the_same_gradient():
+    """The benchmark times the adjoint liquid launches of the first segment the backward pass
+    processes (a partial one here: 130 steps, K = 20) with events: one event pair per step of
+    that segment, and the same gradient up to the order of the atomic additions into it."""
+    w = _small(steps=130)
     th0 = w.meta["theta0"]
-    pe = A.TrajectoryProblem(w.shape, w.bc, w.pos, w.d, w.params, w.steps, precision=precision,
-                             checkpoint=20, graphs=False)
-    pg = A.TrajectoryProblem(w.shape, w.bc, w.pos, w.d, w.params, w.steps, precision=precision,
-                             checkpoint=20, graphs=True)
-    assert pg.graphs and not pe.graphs
-    print(f"[case] {precision}, {steps} steps, K = 20", flush=True)
-    te, se, _ = pe.forward(w.meta["target"], checkpoints=False)
-    tg, sg, _ = pg.forward(w.meta["target"], checkpoints=False)
-    se.close()
-    sg.close()
-    assert torch.equal(te, tg)
-    target = te
-    Le, ge = _adjoint_grad(pe, th0, target)
-    Lg, gg = _adjoint_grad(pg, th0, target)
-    pg.liquid_events = []
-    Lt, gt = _adjoint_grad(pg, th0, target)
-    print(f"eager {ge}, graphs {gg}, graphs with a timed segment {gt}", flush=True)
-    assert Le == Lg == Lt
-    assert len(pg.liquid_events) == (steps % 20 or 20)
-    scale = np.abs(ge).max()
-    assert np.allclose(gg, ge, rtol=1e-12, atol=1e-13 * scale)
-    assert np.allclose(gt, ge, rtol=1e-12, atol=1e-13 * scale)
+    prob = _problem(w, "f32", K=20)
+    target, sim, _ = prob.forward(w.meta["target"], checkpoints=False)
+    sim.close()
+    L0, g0 = _adjoint_grad(prob, th0, target)
+    prob.liquid_events = []
+    L1, g1 = _adjoint_grad(prob, th0, target)
+    print(f"untimed {g0}, timed {g1}", flush=True)
+    assert L0 == L1
+    assert len(prob.liquid_events) == 10
+    assert all(a.elapsed_time(b) > 0.0 for a, b in prob.liquid_events)
+    assert np.allclose(g1, g0, rtol=1e-12, atol=1e-13 * np.abs(g0).max())
