@@ -338,6 +338,10 @@ __device__ void mark_tiles(const ColumnView<T>& col, const BubbleArgs& A, const 
   uint8_t* __restrict__ tiles = col.tiles;
   const int ext[3] = {G.nx, G.ny, G.nz};
   TileRanges tr[3];
+  // In an overlapped step k_mark marked the tile rows (y, z) of the window at x0 widened by the
+  // curl ring and kRegionMargin cells. Cell ranges inside those on y and z lie in marked rows, so
+  // their flags need no reading; otherwise each tile's row flag is read.
+  bool inside = true;
   for (int a = 0; a < 3; ++a) {
     const bool per = G.bc[2 * a] == BC_PER;
     int lo = win[a].clo, hi = win[a].chi;
@@ -346,13 +350,16 @@ __device__ void mark_tiles(const ColumnView<T>& col, const BubbleArgs& A, const 
       lo = min(lo, nw.dlo);
       hi = max(hi, nw.dhi);
     }
+    if (a > 0)
+      inside = inside && lo >= win[a].lo - 1 - kRegionMargin && hi <= win[a].hi + 1 + kRegionMargin;
     tr[a] = tile_ranges(lo, hi, ext[a], (int)kTile, per);
   }
+  const uint32_t* __restrict__ region = inside ? nullptr : col.region;
   for_tiles(G, tr, tid, nthreads, [&](uint32_t t) {
     tiles[t] = 1;
     // in an overlapped step the bulk launch has updated the rows outside the region
     // concurrently: a tile forced or needing the velocity there is an error
-    if (col.region && !col.region[t / (uint32_t)G.tnx]) atomicOr(A.status, (int32_t)STATUS_REGION_MISS);
+    if (region && !region[t / (uint32_t)G.tnx]) atomicOr(A.status, (int32_t)STATUS_REGION_MISS);
   });
 }
 
