@@ -395,7 +395,13 @@ __device__ __forceinline__ void state_velocity(const T* __restrict__ src, const 
 // workgroups on the chip at once): 8, so each thread waits for one round trip per 8 cells. Many
 // bubbles: 1, at 50 VGPRs instead of 108, so that more workgroups stay resident beside the bulk
 // launch (20 000 bubbles: 394 us against 1289 us with 8).
-template <typename T, typename Geo, bool EXACT = false, int GATHER = 1>
+// FUSE (few bubbles on one lattice): the workgroup then also runs its bubble's update (k_ode's
+// arithmetic, one lane) and flags its tiles, so the step has one launch less.
+template <typename Geo>
+__device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3], double xn_out[3],
+                         double& n_out);
+
+template <typename T, typename Geo, bool EXACT = false, int GATHER = 1, bool FUSE = false>
 __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   __shared__ double s_w[3][kSpan];
   __shared__ double s_dw[3][kSpan];
@@ -411,8 +417,18 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   const Geom& G = col.G;
   const T* __restrict__ U = col.U;
   double* work = A.S.work + (size_t)b * kWork;
+  // the bubble update of a bubble without a valid window: nothing but its cleared reaction
+  auto ode_skip = [&] {
+    if constexpr (FUSE) {
+      double x0[3], xn[3], m;
+      ode_lane(geo, A, b, x0, xn, m);
+    }
+  };
   if (A.S.state[b] == 0) {
-    if (tid == 0) work[W_VALID] = 0.0;
+    if (tid == 0) {
+      work[W_VALID] = 0.0;
+      ode_skip();
+    }
     return;
   }
   const double xb[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
@@ -425,6 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
     if (tid == 0) {
       work[W_VALID] = 0.0;
       atomicOr(A.status, (int32_t)STATUS_STENCIL_TOO_LARGE);
+      ode_skip();
     }
     return;
   }
@@ -544,6 +561,21 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
     work[W_X0 + 1] = xb[1];
     work[W_X0 + 2] = xb[2];
     work[W_VALID] = 1.0;
+  }
+  if constexpr (FUSE) {
+    // the update reads what lane 0 just wrote; the force window at x0 is win
+    __shared__ double s_xn[3];
+    __shared__ int s_flag;
+    if (tid == 0) {
+      double x0[3], xn[3], m = 0.0;
+      s_flag = ode_lane(geo, A, b, x0, xn, m) ? 1 : 0;
+      for (int a = 0; a < 3; ++a) s_xn[a] = xn[a];
+    }
+    __syncthreads();
+    if (s_flag) {
+      const double xn[3] = {s_xn[0], s_xn[1], s_xn[2]};
+      mark_tiles<T>(col, A, win, xn, n, tid, kBlock);
+    }
   }
 }
 
@@ -988,6 +1020,9 @@ __global__ __launch_bounds__(64) void k_mark(Geo geo, BubbleArgs A, uint32_t* __
 // Bubble counts up to which k_interp keeps 8 cells' loads in flight per thread: one workgroup per
 // bubble, at 108 VGPRs four of them per compute unit, 1024 on the chip.
 constexpr int kInterpLatencyMaxBubbles = 1024;
+// Bubble counts up to which k_interp also runs the bubble update (k_ode's ~200 VGPRs then limit
+// it to two workgroups per compute unit; up to 256 bubbles every workgroup still has its own).
+constexpr int kFuseMaxBubbles = 256;
 
 template <typename T, typename Geo>
 hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_t stream) {
@@ -997,6 +1032,9 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
   if (exact) {
     if constexpr (std::is_same_v<Geo, OneColumn>)
       hipLaunchKernelGGL((k_interp<T, Geo, true>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+  } else if (std::is_same_v<Geo, OneColumn> && nb <= kFuseMaxBubbles) {
+    if constexpr (std::is_same_v<Geo, OneColumn>)
+      hipLaunchKernelGGL((k_interp<T, Geo, false, 8, true>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
   } else if (nb <= kInterpLatencyMaxBubbles) {
     hipLaunchKernelGGL((k_interp<T, Geo, false, 8>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
   } else {
@@ -1004,9 +1042,12 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_ode<Geo>), dim3(div_up(nb, 64)), dim3(64), 0, stream, geo, A);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  const bool fused = std::is_same_v<Geo, OneColumn> && !exact && nb <= kFuseMaxBubbles;
+  if (!fused) {
+    hipLaunchKernelGGL((k_ode<Geo>), dim3(div_up(nb, 64)), dim3(64), 0, stream, geo, A);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if constexpr (std::is_same_v<Geo, OneColumn>) {
     if (geo.next_region) {
       // the region of the next step, from the bubble state this update leaves
