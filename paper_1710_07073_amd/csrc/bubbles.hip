@@ -10,6 +10,8 @@
 //             the force field with the same weights (atomic adds) and the tile flags, or
 //   k_spread_gather (several bubbles: one workgroup per tile) the same sums per cell in bubble
 //             order from the lists, so that the force field is bit-reproducible.
+// Up to 256 bubbles on one lattice (not in the exact-time variant) k_interp's workgroup also runs
+// k_ode's update of its bubble on one lane and flags the bubble's tiles, and k_ode is not launched.
 // The coupling variants of bubble_params.coupling (reaction, point-sampled weights, exact-time
 // forward coupling) are modes of these kernels. k_mark marks the region of an overlapped step.
 //
