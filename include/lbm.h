@@ -281,11 +281,13 @@ lbm_status lbm_adjoint_liquid(lbm_ctx* ctx, const void* state, const void* force
  * LBM_BUBBLE_RECORD doubles of the step; vel_prev: velocity field the step interpolated;
  * lam_f: dL/dF from lbm_adjoint_liquid; lam_u (out, accumulated): dL/d(vel_prev); lam: nb x
  * LBM_BUBBLE_ADJ adjoint bubble state, dL/d(state after the step) in, dL/d(state before) out;
- * scratch: reserved (may be NULL). grad[1..3] accumulate dL/d(drag_scale), dL/d(lift_scale),
- * dL/dnu. n_sub may be at most 32. */
+ * lam_x (may be NULL): the loss's own dL/dx of the positions after the step, 3 x nb doubles
+ * (component-major, [a * nb + b]), added to lam's dL/dx first (so a loss on every step's
+ * positions needs no separate addition). grad[1..3] accumulate dL/d(drag_scale),
+ * dL/d(lift_scale), dL/dnu. n_sub may be at most 32. */
 lbm_status lbm_adjoint_bubbles(lbm_ctx* ctx, const bubble_params* params, const double* record,
                                const void* vel_prev, const void* lam_f, void* lam_u, double* lam,
-                               double* scratch, int32_t nb, double* grad);
+                               const double* lam_x, int32_t nb, double* grad);
 
 /* Host evaluation of the arithmetic the adjoint kernels run (double precision), for checks:
  * one cell's collision (eq. (13)-(15)) and, if lam/lam_u/mu/lam_f/domega are given, its

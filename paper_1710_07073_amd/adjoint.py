@@ -111,7 +111,7 @@ class TrajectoryProblem:
         Up = torch.empty((K + 1,) + tuple(sim.vel.shape), dtype=pops.dtype, device=dev)
         Fk = torch.empty((K,) + tuple(sim.vel.shape), dtype=pops.dtype, device=dev)
         rec = torch.zeros((K, nb, L.LBM_BUBBLE_RECORD), dtype=torch.float64, device=dev)
-        gt = grad_traj.to(dev, torch.float64)
+        gt = grad_traj.to(dev, torch.float64).contiguous()
         # buffers are rebound between the bubble half and the liquid step: no overlapped steps
         L.lbm_set_overlap(sim.ctx, False)
         bub = sim.bubbles
@@ -130,7 +130,6 @@ class TrajectoryProblem:
                 L.lbm_bind_buffers(sim.ctx, None, None, _p(Up[i + 1]))
                 L.lbm_step(sim.ctx, 1)
             for i in reversed(range(n)):
-                lam_b[:, 0:3] += gt[k0 + i].t()
                 ev = None
                 if events is not None:
                     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -141,8 +140,9 @@ class TrajectoryProblem:
                     ev[1].record(self.stream)
                     events.append(ev)
                 cur = 1 - cur
+                # the loss's term in this step's positions is added by the kernel
                 L.lbm_adjoint_bubbles(sim.ctx, sim.params, _p(rec[i]), _p(Up[i]), _p(lam_f),
-                                      _p(lam_u), _p(lam_b), None, nb, _p(grad))
+                                      _p(lam_u), _p(lam_b), _p(gt[k0 + i]), nb, _p(grad))
 
         for s in reversed(range(len(ckpts))):
             k0 = s * K

@@ -294,8 +294,9 @@ template <typename T>
 __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
                                                    const T* __restrict__ U, T* __restrict__ lam_u,
                                                    const double* __restrict__ rec,
-                                                   double* __restrict__ lam, bubble_params P, Geom G,
-                                                   double nu, int nb, double* __restrict__ grad) {
+                                                   double* __restrict__ lam,
+                                                   const double* __restrict__ lam_x, bubble_params P,
+                                                   Geom G, double nu, int nb, double* __restrict__ grad) {
   __shared__ double w[3][kAdjSpan], dw[3][kAdjSpan], wx[3][kAdjSpan], dwx[3][kAdjSpan];
   __shared__ AxisW win[3];
   __shared__ int s_bad[3];
@@ -309,6 +310,9 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double* r = rec + (size_t)b * R_SIZE;
   double* l = lam + (size_t)b * A_SIZE;
+  // the loss's own term in the positions after the step (lane 0 alone reads and writes l[A_X])
+  if (lam_x && tid == 0)
+    for (int a = 0; a < 3; ++a) l[A_X + a] += lam_x[(size_t)a * nb + b];
   const int st = (int)r[R_STATE];
   // a frozen bubble (inactive, or no valid window in the step): its adjoint state passes through
   if (st == 0 || r[R_VALID] == 0.0) return;
@@ -553,11 +557,12 @@ hipError_t liquid_typed(lbm_ctx* c, const void* state, const void* force, const 
 
 template <typename T>
 hipError_t bubbles_typed(lbm_ctx* c, const bubble_params* p, const double* rec, const void* vel_prev,
-                         const void* lam_f, void* lam_u, double* lam, int32_t nb, double* grad) {
+                         const void* lam_f, void* lam_u, double* lam, const double* lam_x, int32_t nb,
+                         double* grad) {
   const double nu = (1.0 / c->desc.omega - 0.5) / 3.0;
   hipLaunchKernelGGL((k_adj_bubble<T>), dim3(nb), dim3(kB), 0, c->stream,
                      static_cast<const T*>(lam_f), static_cast<const T*>(vel_prev),
-                     static_cast<T*>(lam_u), rec, lam, *p, c->geom, nu, nb, grad);
+                     static_cast<T*>(lam_u), rec, lam, lam_x, *p, c->geom, nu, nb, grad);
   return hipGetLastError();
 }
 
@@ -586,16 +591,15 @@ lbm_status lbm_adjoint_liquid(lbm_ctx* ctx, const void* state, const void* force
 
 lbm_status lbm_adjoint_bubbles(lbm_ctx* ctx, const bubble_params* p, const double* record,
                                const void* vel_prev, const void* lam_f, void* lam_u, double* lam,
-                               double* scratch, int32_t nb, double* grad) {
+                               const double* lam_x, int32_t nb, double* grad) {
   if (!ctx || !p || nb < 0 || !grad) return LBM_EINVAL;
   if (nb == 0) return LBM_OK;
-  (void)scratch;  // reserved
   if (!record || !vel_prev || !lam_f || !lam_u || !lam) return LBM_EINVAL;
   if (p->n_sub < 1 || p->n_sub > kMaxSub) return LBM_EINVAL;
   if (p->coupling != 0) return LBM_EUNSUPPORTED;  // the adjoint of the default coupling only
   const hipError_t e =
-      ctx->elem == 4 ? bubbles_typed<float>(ctx, p, record, vel_prev, lam_f, lam_u, lam, nb, grad)
-                     : bubbles_typed<double>(ctx, p, record, vel_prev, lam_f, lam_u, lam, nb, grad);
+      ctx->elem == 4 ? bubbles_typed<float>(ctx, p, record, vel_prev, lam_f, lam_u, lam, lam_x, nb, grad)
+                     : bubbles_typed<double>(ctx, p, record, vel_prev, lam_f, lam_u, lam, lam_x, nb, grad);
   return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }
 

@@ -329,9 +329,9 @@ def lbm_adjoint_liquid(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad
         "lbm_adjoint_liquid")
 
 
-def lbm_adjoint_bubbles(ctx, params, record, vel_prev, lam_f, lam_u, lam, scratch, nb, grad):
+def lbm_adjoint_bubbles(ctx, params, record, vel_prev, lam_f, lam_u, lam, lam_x, nb, grad):
     _ok(lib().lbm_adjoint_bubbles(ctx, ct.byref(params), record, vel_prev, lam_f, lam_u, lam,
-                                  scratch, int(nb), grad), "lbm_adjoint_bubbles")
+                                  lam_x, int(nb), grad), "lbm_adjoint_bubbles")
 
 
 def lbm_bubble_record(ctx, soa, nb, stage, record):
