@@ -256,18 +256,29 @@ lbm_status lbm_destroy(lbm_ctx* ctx);
  * [2] dL/d lift_scale, [3] dL/dnu through the bubble closures (nu = (1/omega - 1/2)/3, eq. (9)).
  * ------------------------------------------------------------------------------------------- */
 
-/* Doubles per bubble in a step record: x[3] u_b[3] u_l,prev[3] state u_l[3] w_l[3] psi[3] valid d,
- * taken before the step (x, u_b, u_l,prev, state, d) and after its bubble half (u_l, w_l, psi,
- * valid = the first LBM_BUBBLE_WORK slots 0-5, 9-12 of bubble_soa.work). */
-#define LBM_BUBBLE_RECORD 24
+/* Doubles per bubble in a step record: [0, 21) x[3] u_b[3] u_l,prev[3] state u_l[3] w_l[3] psi[3]
+ * valid d, taken before the step (x, u_b, u_l,prev, state, d) and after its bubble half (u_l, w_l,
+ * psi, valid = the first LBM_BUBBLE_WORK slots 0-5, 9-12 of bubble_soa.work); [21] 1 if the
+ * sub-steps below were recorded, else 0; [24, 123) the velocity u_b at the start of each sub-step
+ * k = 0..n_sub (k = n_sub: after the last), 3 doubles each; [123, 126) the clamp flags of the
+ * sub-steps (bit 3 k + a of the 96-bit word held as three 32-bit integers in doubles: component a
+ * clamped at a wall in sub-step k). */
+#define LBM_BUBBLE_RECORD 128
 /* Doubles per bubble of adjoint state: dL/dx[3], dL/du_b[3], dL/du_l,prev[3], unused[3]. */
 #define LBM_BUBBLE_ADJ 12
 
 /* Fill the step record (nb x LBM_BUBBLE_RECORD doubles, device) from the bubble arrays: stage 0,
- * called before the step's bubble half, writes x, u_b, u_l,prev, state and d; stage 1, called
- * after it, writes u_l, w_l, psi and valid from soa->work. */
+ * called before the step's bubble half, writes x, u_b, u_l,prev, state and d (and marks the
+ * sub-steps as not recorded); stage 1, called after it, writes u_l, w_l, psi and valid from
+ * soa->work. */
 lbm_status lbm_bubble_record(lbm_ctx* ctx, const bubble_soa* soa, int32_t nb, int32_t stage,
                              double* record);
+
+/* One-shot: the next bubbles_step() writes the whole step record of every bubble into record (nb x
+ * LBM_BUBBLE_RECORD doubles, device, caller-owned), the sub-steps included when n_sub <= 32, from
+ * inside the bubble update (no launch of its own; the same values as the two stages of
+ * lbm_bubble_record). lbm_run() returns LBM_EINVAL while a record is armed. */
+lbm_status lbm_record_next_bubble_half(lbm_ctx* ctx, double* record);
 
 /* Adjoint of the liquid step (eq. (12)-(16), Sec. 3.3). state: the post-collision buffer before the
  * step (19 x N); force: the force field of the step (3 x N); lam_next: dL/d(state after the step);

@@ -123,9 +123,9 @@ class TrajectoryProblem:
             nonlocal cur
             for i in range(n):
                 L.lbm_bind_buffers(sim.ctx, _p(H[i]), _p(H[i + 1]), _p(Up[i]))
-                L.lbm_bubble_record(sim.ctx, bub.soa, nb, 0, _p(rec[i]))
+                # the bubble update fills the step record itself, sub-step velocities included
+                L.lbm_record_next_bubble_half(sim.ctx, _p(rec[i]))
                 L.bubbles_step(sim.ctx, sim.params, bub.soa, nb)
-                L.lbm_bubble_record(sim.ctx, bub.soa, nb, 1, _p(rec[i]))
                 Fk[i].copy_(sim.force)
                 L.lbm_bind_buffers(sim.ctx, None, None, _p(Up[i + 1]))
                 L.lbm_step(sim.ctx, 1)

@@ -21,9 +21,7 @@ namespace {
 
 constexpr int kB = 256;  // threads per bubble workgroup
 constexpr int kBW = kB / 64;
-// record of one bubble at the start of a step (doubles)
-constexpr int R_X = 0, R_UB = 3, R_ULP = 6, R_STATE = 9, R_UL = 10, R_WL = 13, R_PSI = 16,
-              R_VALID = 19, R_D = 20, R_SIZE = LBM_BUBBLE_RECORD;
+static_assert(kRecordMaxSub == kMaxSub, "the record holds every sub-step the adjoint allows");
 // adjoint bubble state (doubles)
 constexpr int A_X = 0, A_UB = 3, A_ULP = 6, A_SIZE = LBM_BUBBLE_ADJ;
 
@@ -282,7 +280,8 @@ struct WindowWalk {
 
 // The bubble half of the adjoint for one bubble per workgroup:
 //   wavefronts 0-2   the weights of axis 0, 1, 2 (with their derivatives), side by side with
-//   wavefront 3      the forward sub-steps again (one lane, recording the sub-step velocities);
+//   wavefront 3      the sub-step velocities and clamp flags: from the record when the forward
+//                    update wrote them, else the forward sub-steps again (one lane);
 //   all              the gather dL/dpsi = sum_j W_j dL/dF(j) and the position term of the spreading
 //                    weights, while lanes of wavefront 3 first evaluate the n_sub + 1 force
 //                    Jacobians at the recorded velocities;
@@ -334,6 +333,15 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
     else
       ok = wave_weights_dx<2>(G, xb, n, lane, w, dw, wx, dwx, win);
     if (lane == 0) s_bad[wave] = ok ? 0 : 1;
+  } else if (r[R_SUB] != 0.0) {
+    // sub-step velocities and clamp flags recorded by the forward update
+    if (lane <= P.n_sub)
+      for (int a = 0; a < 3; ++a) s_ubs[lane][a] = r[R_UBS + 3 * lane + a];
+    if (lane < P.n_sub)
+      for (int a = 0; a < 3; ++a) {
+        const int bit = 3 * lane + a;
+        s_clamped[lane][a] = (unsigned char)(((uint32_t)r[R_CLAMP + bit / 32] >> (bit % 32)) & 1u);
+      }
   } else if (lane == 0) {
     OdeBounds Bd;
     const int ext[3] = {G.nx, G.ny, G.nz};
@@ -500,7 +508,8 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
 
 // Step record of every bubble (one lane per bubble): stage 0, before the step's bubble half, takes
 // x, u_b, u_l,prev, state and d from the bubble arrays; stage 1, after it, takes u_l, w_l, psi and
-// the window flag from the bubble workspace.
+// the window flag from the bubble workspace. (An armed record is filled by the bubble update
+// itself, sub-steps included.)
 __global__ __launch_bounds__(64) void k_record(bubble_soa S, int nb, int stage, double* __restrict__ rec) {
   const int b = blockIdx.x * 64 + threadIdx.x;
   if (b >= nb) return;
@@ -517,6 +526,7 @@ __global__ __launch_bounds__(64) void k_record(bubble_soa S, int nb, int stage, 
     r[R_ULP + 2] = S.ulz[b];
     r[R_STATE] = (double)S.state[b];
     r[R_D] = S.d[b];
+    r[R_SUB] = 0.0;  // the sub-steps are not recorded: the adjoint runs them again
   } else {
     const double* wk = S.work + (size_t)b * LBM_BUBBLE_WORK;
     for (int m = 0; m < 6; ++m) r[R_UL + m] = wk[W_UL + m];  // u_l then w_l

@@ -139,6 +139,7 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->side = nullptr;
   c->ev_fork = c->ev_join = nullptr;
   c->t_start = c->t_end = nullptr;
+  c->arm_record = nullptr;
   const unsigned ev_flags = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
   if (c->side && (hipEventCreateWithFlags(&c->ev_fork, ev_flags) != hipSuccess ||
@@ -178,6 +179,12 @@ lbm_status lbm_time_next_step(lbm_ctx* ctx, void* start, void* end) {
   if (!ctx) return LBM_EINVAL;
   ctx->t_start = static_cast<hipEvent_t>(start);
   ctx->t_end = static_cast<hipEvent_t>(end);
+  return LBM_OK;
+}
+
+lbm_status lbm_record_next_bubble_half(lbm_ctx* ctx, double* record) {
+  if (!ctx || !record) return LBM_EINVAL;
+  ctx->arm_record = record;
   return LBM_OK;
 }
 
@@ -330,6 +337,8 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, in
                    int32_t nsteps, int32_t graph_steps) {
   if (!ctx || !p || !s || nb < 0 || nsteps < 0) return LBM_EINVAL;
   if (graph_steps < 0 || graph_steps % 2 || ctx->hs.pending) return LBM_EINVAL;
+  // an armed step record belongs to one call of bubbles_step (a graph would replay it)
+  if (ctx->arm_record) return LBM_EINVAL;
   ctx->hs.marked = false;  // the bubble state may have changed since the last call
   auto one = [&]() -> lbm_status {
     lbm_status st = bubble_half(ctx, p, s, nb, true);

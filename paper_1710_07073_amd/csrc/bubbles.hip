@@ -43,6 +43,7 @@ struct BubbleArgs {
   bubble_soa S;
   int nb;
   int32_t* status;
+  double* rec;  // armed step record (nb x R_SIZE), filled by the bubble update, or null
 };
 
 __device__ __forceinline__ int wrapi(int i, int n) {
@@ -668,7 +669,24 @@ __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3
   asm volatile("" ::"v"(d), "v"(ul[0]), "v"(ul[1]), "v"(ul[2]), "v"(wl[0]), "v"(wl[1]), "v"(wl[2]),
                "v"(ulp[0]), "v"(ulp[1]), "v"(ulp[2]), "v"(ub[0]), "v"(ub[1]), "v"(ub[2]),
                "v"(xn[0]), "v"(xn[1]), "v"(xn[2]));
+  // the armed step record: the state before the update (what k_record's two stages copy)
+  double* rec = A.rec ? A.rec + (size_t)b * R_SIZE : nullptr;
+  if (rec) {
+    for (int a = 0; a < 3; ++a) {
+      rec[R_X + a] = xn[a];
+      rec[R_UB + a] = ub[a];
+      rec[R_ULP + a] = ulp[a];
+      rec[R_UL + a] = ul[a];
+      rec[R_WL + a] = wl[a];
+    }
+    rec[R_STATE] = (double)st;
+    rec[R_D] = d;
+    rec[R_VALID] = valid;
+    rec[R_SUB] = 0.0;
+  }
   if (st == 0 || valid == 0.0) {
+    if (rec)
+      for (int a = 0; a < 3; ++a) rec[R_PSI + a] = work[W_PSI + a];
     if (A.S.psix) {
       A.S.psix[b] = 0.0;
       A.S.psiy[b] = 0.0;
@@ -689,7 +707,12 @@ __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3
   const double m_b = P.rho_b * kc.V;
   // sums over the sub-steps of F_D + F_L and of the net force m_b du_b/dt (reaction variants)
   double s_dl[3] = {0.0, 0.0, 0.0}, s_net[3] = {0.0, 0.0, 0.0};
+  // the record keeps the velocity at the start of each sub-step and the clamp flags
+  double* rec_ubs = rec && P.n_sub <= kRecordMaxSub ? rec + R_UBS : nullptr;
+  uint32_t clamp0 = 0u, clamp1 = 0u, clamp2 = 0u;  // bits 0-31, 32-63, 64-95
   for (int k = 0; k < P.n_sub; ++k) {
+    if (rec_ubs)
+      for (int a = 0; a < 3; ++a) rec_ubs[3 * k + a] = ub[a];
     // (m_b + C_A rho_l V) du_b/dt = F_B + F_D + F_L + (1 + C_A) rho_l V D_t u_l
     double FD[3], FL[3];
     drag_lift(P, kc, d, nu, ub, ul, wl, FD, FL);
@@ -707,16 +730,36 @@ __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3
         xn[a] = fmod(xn[a], L);
         if (xn[a] < 0.0) xn[a] += L;
       } else {
+        bool clamped = false;
         if (xn[a] < 0.0) {
           xn[a] = 0.0;
           ub[a] = 0.0;
+          clamped = true;
         }
         if (a != 2 && xn[a] > ext[a] - 1.0) {
           xn[a] = ext[a] - 1.0;
           ub[a] = 0.0;
+          clamped = true;
+        }
+        if (clamped) {
+          const int bit = 3 * k + a;
+          const uint32_t m = 1u << (bit & 31);
+          if (bit < 32)
+            clamp0 |= m;
+          else if (bit < 64)
+            clamp1 |= m;
+          else
+            clamp2 |= m;
         }
       }
     }
+  }
+  if (rec_ubs) {
+    for (int a = 0; a < 3; ++a) rec_ubs[3 * P.n_sub + a] = ub[a];
+    rec[R_CLAMP] = (double)clamp0;
+    rec[R_CLAMP + 1] = (double)clamp1;
+    rec[R_CLAMP + 2] = (double)clamp2;
+    rec[R_SUB] = 1.0;
   }
   // the reaction spread into the liquid (Algorithm 1, or a coupling variant)
   double psi[3];
@@ -742,6 +785,8 @@ __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3
   if (G.bc[4] != BC_PER && xn[2] >= ext[2] - 1.0) nst = 0;  // reached the top layer
   A.S.state[b] = nst;
   for (int a = 0; a < 3; ++a) work[W_PSI + a] = psi[a];
+  if (rec)
+    for (int a = 0; a < 3; ++a) rec[R_PSI + a] = psi[a];
   if (A.S.psix) {
     A.S.psix[b] = psi[0];
     A.S.psiy[b] = psi[1];
@@ -1077,6 +1122,8 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
   A.S = *s;
   A.nb = nb;
   A.status = c->status;
+  A.rec = c->arm_record;  // one-shot
+  c->arm_record = nullptr;
   // this step's mask: the one the last liquid step cleared (cleared here if no liquid step ran)
   const int m = c->hs.flag_cur ^ 1;
   if (!c->hs.flag_clean[m]) {
@@ -1149,6 +1196,7 @@ hipError_t launch_bubbles_batch(const ColumnDev* cols, const int32_t* bubble_col
   A.S = *s;
   A.nb = nb;
   A.status = status;
+  A.rec = nullptr;
   ManyColumns geo;
   geo.cols = cols;
   geo.bubble_col = bubble_col;

@@ -54,6 +54,8 @@ struct lbm_ctx {
   hipEvent_t ev_fork, ev_join;
   // caller's events recorded around the next bulk (or whole-lattice) liquid launch, one-shot
   hipEvent_t t_start, t_end;
+  // caller's step record the next bubble half fills (lbm_record_next_bubble_half), one-shot
+  double* arm_record;
   int32_t pending_nb;  // bubbles of the pending overlapped step
   uint32_t ntiles;
   uint32_t nrows;  // tile rows (y, z tile coordinates)
@@ -146,6 +148,12 @@ constexpr int W_UL = 0, W_WL = 3, W_X0 = 6, W_PSI = 9, W_VALID = 12;
 // like the LDS copies of the bubble kernels (cell - lo + 1).
 constexpr int W_WGT = 16;
 static_assert(W_WGT + 3 * (LBM_MAX_STENCIL + 2) <= LBM_BUBBLE_WORK, "bubble workspace too small");
+// Step record of one bubble (LBM_BUBBLE_RECORD doubles): the values the adjoint of the bubble half
+// needs, with the sub-step velocities and clamp flags of up to kRecordMaxSub sub-steps.
+constexpr int R_X = 0, R_UB = 3, R_ULP = 6, R_STATE = 9, R_UL = 10, R_WL = 13, R_PSI = 16,
+              R_VALID = 19, R_D = 20, R_SUB = 21, R_UBS = 24, kRecordMaxSub = 32,
+              R_CLAMP = R_UBS + 3 * (kRecordMaxSub + 1), R_SIZE = LBM_BUBBLE_RECORD;
+static_assert(R_CLAMP + 3 <= R_SIZE, "bubble record too small");
 // Bubbles a tile's list holds in the deterministic spreading.
 constexpr uint32_t kTileCap = 64;
 constexpr uint32_t kRedBlocks = 1024;  // upper bound of moments reduction blocks

@@ -19,7 +19,7 @@ LBM_BC_BOUNCE_BACK, LBM_BC_FREE_SLIP, LBM_BC_PERIODIC = 0, 1, 2
 LBM_FLAG_STATIC_FORCE, LBM_FLAG_WRITE_U_ALL, LBM_FLAG_PLAIN_SOA = 1, 2, 4
 LBM_MAX_STENCIL = 64
 LBM_BUBBLE_WORK = 216
-LBM_BUBBLE_RECORD = 24
+LBM_BUBBLE_RECORD = 128
 LBM_BUBBLE_ADJ = 12
 # coupling variants (bubble_params.coupling)
 LBM_REACTION_MASK, LBM_REACTION_SUBSTEP_MEAN, LBM_REACTION_NET_FORCE = 3, 1, 2
@@ -35,7 +35,8 @@ EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch",
            "lbm_batch_step", "lbm_batch_run", "lbm_batch_populations", "lbm_batch_sums",
            "lbm_batch_column",
            "lbm_batch_check", "lbm_batch_destroy",
-           "lbm_adjoint_liquid", "lbm_adjoint_bubbles", "lbm_bubble_record", "lbm_bind_buffers",
+           "lbm_adjoint_liquid", "lbm_adjoint_bubbles", "lbm_bubble_record",
+           "lbm_record_next_bubble_half", "lbm_bind_buffers",
            "lbm_host_collide",
            "lbm_host_axis_weights", "lbm_host_bubble_ode", "lbm_host_bubble_ode_adjoint")
 
@@ -122,6 +123,7 @@ def lib():
         L.lbm_adjoint_liquid.argtypes = [P, P, P, P, P, P, P, P]
         L.lbm_adjoint_bubbles.argtypes = [P, ct.POINTER(BubbleParams), P, P, P, P, P, P, ct.c_int32, P]
         L.lbm_bubble_record.argtypes = [P, ct.POINTER(BubbleSoA), ct.c_int32, ct.c_int32, P]
+        L.lbm_record_next_bubble_half.argtypes = [P, P]
         L.lbm_bind_buffers.argtypes = [P, P, P, P]
         L.lbm_host_collide.argtypes = [D, D, ct.c_double, D, D, D, D, D, D, D]
         L.lbm_host_axis_weights.argtypes = [ct.c_double, ct.c_double, ct.c_int32, ct.c_int32,
@@ -336,6 +338,10 @@ def lbm_adjoint_bubbles(ctx, params, record, vel_prev, lam_f, lam_u, lam, lam_x,
 
 def lbm_bubble_record(ctx, soa, nb, stage, record):
     _ok(lib().lbm_bubble_record(ctx, ct.byref(soa), int(nb), int(stage), record), "lbm_bubble_record")
+
+
+def lbm_record_next_bubble_half(ctx, record):
+    _ok(lib().lbm_record_next_bubble_half(ctx, record), "lbm_record_next_bubble_half")
 
 
 def lbm_bind_buffers(ctx, state=None, next_state=None, vel=None):

@@ -135,3 +135,88 @@ def test_timed_segment_gives_the_same_gradient():
     assert len(prob.liquid_events) == 10
     assert all(a.elapsed_time(b) > 0.0 for a, b in prob.liquid_events)
     assert np.allclose(g1, g0, rtol=1e-12, atol=1e-13 * np.abs(g0).max())
+
+
+def _recorded_step(w, armed, warm=6):
+    """A simulation after warm steps, then one bubble half with its step record (armed: filled by
+    the bubble update; else the two stages of lbm_bubble_record) and the velocity field it read."""
+    from paper_1710_07073_amd import lbm as L
+    from gpu_common import gpu_sim
+    sim = gpu_sim(w)
+    sim.step(warm)
+    nb = sim.bubbles.nb
+    rec = torch.full((nb, L.LBM_BUBBLE_RECORD), -7.0, dtype=torch.float64, device="cuda")
+    vel_prev = sim.vel.clone()
+    ub_before = sim.bubbles.velocities()
+    p = ctypes_ptr(rec)
+    if armed:
+        L.lbm_record_next_bubble_half(sim.ctx, p)
+        L.bubbles_step(sim.ctx, sim.params, sim.bubbles.soa, nb)
+    else:
+        L.lbm_bubble_record(sim.ctx, sim.bubbles.soa, nb, 0, p)
+        L.bubbles_step(sim.ctx, sim.params, sim.bubbles.soa, nb)
+        L.lbm_bubble_record(sim.ctx, sim.bubbles.soa, nb, 1, p)
+    L.lbm_step(sim.ctx, 1)
+    torch.cuda.synchronize()
+    return sim, rec, vel_prev, ub_before
+
+
+def ctypes_ptr(t):
+    import ctypes as ct
+    return ct.c_void_p(t.data_ptr())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("nb", [3, 300, "wall"])
+def test_armed_record_equals_staged_record(nb):
+    """The step record the bubble update fills when armed (3 bubbles: inside k_interp; 300: in
+    k_ode) holds the values of the two lbm_bubble_record stages bit for bit, plus sub-step
+    velocities that start at the velocity before the step and end at the velocity after it; the
+    bubble half's adjoint gives the same result from either record (the staged one makes the
+    kernel run the sub-steps again)."""
+    from paper_1710_07073_amd import lbm as L
+    rng = np.random.default_rng(21)
+    shape = (48, 48, 64)
+    wall = nb == "wall"  # one bubble thrown at the x = 0 wall: its x velocity is clamped
+    nb = 1 if wall else nb
+    d = rng.uniform(2.0, 3.0, nb)
+    pos = np.stack([rng.uniform(5.0, 42.0, nb), rng.uniform(5.0, 42.0, nb), rng.uniform(5.0, 30.0, nb)])
+    vel = None
+    if wall:
+        pos = np.array([[0.05], [24.0], [20.0]])
+        vel = np.array([[-1.0], [0.0], [0.0]])
+    w = W.Workload(f"record_{nb}b{'_wall' if wall else ''}", shape, 1.3, (0,) * 6, pos, d,
+                   W.params(g=1e-4, sigma=1e-4), 0, "f64", vel=vel)
+    print(f"[case] {w.name}", flush=True)
+    warm = 0 if wall else 6
+    sa, ra, vel, ub0 = _recorded_step(w, True, warm)
+    sb, rb, _, _ = _recorded_step(w, False, warm)
+    ra_h, rb_h = ra.cpu().numpy(), rb.cpu().numpy()
+    assert np.array_equal(ra_h[:, :21], rb_h[:, :21])
+    assert np.all(ra_h[:, 21] == 1.0) and np.all(rb_h[:, 21] == 0.0)
+    n_sub = W.params()["n_sub"]
+    ubs = ra_h[:, 24:24 + 3 * (n_sub + 1)].reshape(nb, n_sub + 1, 3)
+    assert np.array_equal(ubs[:, 0, :], ub0.T)
+    assert np.array_equal(ubs[:, n_sub, :], sa.bubbles.velocities().T)
+    if wall:  # the x component (a = 0) clamped in some sub-step k: bit 3 k
+        word = int(ra_h[0, 123]) | (int(ra_h[0, 124]) << 32) | (int(ra_h[0, 125]) << 64)
+        assert any((word >> (3 * k)) & 1 for k in range(n_sub))
+    else:
+        assert np.array_equal(ra_h[:, 123:126], np.zeros((nb, 3)))  # no wall contact
+    # the bubble half's adjoint from either record
+    outs = []
+    for sim, rec in ((sa, ra), (sb, rb)):
+        g = torch.Generator(device="cuda").manual_seed(5)
+        lam_f = torch.randn(sim.vel.shape, generator=g, device="cuda", dtype=sim.vel.dtype) * 1e-3
+        lam_u = torch.zeros_like(sim.vel)
+        lam = torch.randn((nb, L.LBM_BUBBLE_ADJ), generator=g, device="cuda", dtype=torch.float64)
+        grad = torch.zeros(4, dtype=torch.float64, device="cuda")
+        L.lbm_adjoint_bubbles(sim.ctx, sim.params, ctypes_ptr(rec), ctypes_ptr(vel), ctypes_ptr(lam_f),
+                              ctypes_ptr(lam_u), ctypes_ptr(lam), None, nb, ctypes_ptr(grad))
+        torch.cuda.synchronize()
+        outs.append((lam.cpu().numpy(), lam_u.cpu().numpy(), grad.cpu().numpy()))
+        sim.check()
+        sim.close()
+    for a, b in zip(outs[0], outs[1]):
+        scale = np.abs(b).max()
+        assert np.allclose(a, b, rtol=1e-11, atol=1e-12 * scale)
