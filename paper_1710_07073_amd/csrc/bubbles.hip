@@ -897,8 +897,9 @@ __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
 // ---- deterministic backward coupling (gather per tile), for several bubbles on one lattice ----
 //
 // k_interp enters each bubble in the list of every tile of its force window at x0 (kTileCap
-// entries per tile; the count keeps rising past a full list), k_ode flags the bubble's tiles for
-// the liquid step, and k_spread_gather, one workgroup per tile, sums psi_b W_b(j) over the tile's
+// entries per tile; the count keeps rising past a full list), the bubble update (k_ode, or
+// k_interp itself with few bubbles) flags the bubble's tiles for the liquid step, and
+// k_spread_gather, one workgroup per tile, sums psi_b W_b(j) over the tile's
 // bubbles in bubble order in double precision with the weights k_interp stored at x0. A tile
 // whose list overflowed finds its bubbles by a scan of all bubbles in index order instead, so the
 // sum has the same terms in the same order either way. F(j) does not depend on the order in
