@@ -277,7 +277,8 @@ lbm_status lbm_bubble_record(lbm_ctx* ctx, const bubble_soa* soa, int32_t nb, in
 /* One-shot: the next bubbles_step() writes the whole step record of every bubble into record (nb x
  * LBM_BUBBLE_RECORD doubles, device, caller-owned), the sub-steps included when n_sub <= 32, from
  * inside the bubble update (no launch of its own; the same values as the two stages of
- * lbm_bubble_record). lbm_run() returns LBM_EINVAL while a record is armed. */
+ * lbm_bubble_record). record = NULL disarms. lbm_run() returns LBM_EINVAL while a record is
+ * armed. */
 lbm_status lbm_record_next_bubble_half(lbm_ctx* ctx, double* record);
 
 /* Adjoint of the liquid step (eq. (12)-(16), Sec. 3.3). state: the post-collision buffer before the

@@ -183,8 +183,8 @@ lbm_status lbm_time_next_step(lbm_ctx* ctx, void* start, void* end) {
 }
 
 lbm_status lbm_record_next_bubble_half(lbm_ctx* ctx, double* record) {
-  if (!ctx || !record) return LBM_EINVAL;
-  ctx->arm_record = record;
+  if (!ctx) return LBM_EINVAL;
+  ctx->arm_record = record;  // null disarms
   return LBM_OK;
 }
 

@@ -220,3 +220,23 @@ def test_armed_record_equals_staged_record(nb):
     for a, b in zip(outs[0], outs[1]):
         scale = np.abs(b).max()
         assert np.allclose(a, b, rtol=1e-11, atol=1e-12 * scale)
+
+
+@pytest.mark.gpu
+def test_armed_record_blocks_lbm_run_until_disarmed():
+    from paper_1710_07073_amd import lbm as L
+    from gpu_common import gpu_sim
+    w = W.Workload("arm_run", (24, 24, 32), 1.3, (0,) * 6, np.array([[12.0], [12.0], [8.0]]),
+                   np.array([3.0]), W.params(g=1e-4, sigma=1e-4), 0, "f64")
+    print(f"[case] {w.name}", flush=True)
+    sim = gpu_sim(w)
+    rec = torch.zeros((1, L.LBM_BUBBLE_RECORD), dtype=torch.float64, device="cuda")
+    L.lbm_record_next_bubble_half(sim.ctx, ctypes_ptr(rec))
+    with pytest.raises(L.LbmError) as e:
+        sim.run(2)
+    assert e.value.code == L.LBM_EINVAL
+    L.lbm_record_next_bubble_half(sim.ctx, None)
+    sim.run(2)
+    sim.check()
+    assert torch.count_nonzero(rec).item() == 0  # disarmed before any bubble half ran
+    sim.close()
