@@ -558,7 +558,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--launch", default=None, help="vec,block_x of the liquid step (skips tuning)")
+    ap.add_argument("--launch", default=None,
+                    help="vec,block_x[,workgroups_per_cu] of the liquid step (skips tuning)")
     ap.add_argument("--layout", default="plane", choices=["plane", "soa"],
                     help="population buffer layout: plane-blocked (default) or plain structure of arrays")
     ap.add_argument("--no-overlap", action="store_true",
@@ -603,9 +604,11 @@ def main():
                        stream=stream)
     launch = {"vec": None, "bx": None, "tuned": False}
     if args.launch:
-        vec, bx = (int(v) for v in args.launch.split(","))
-        L.lbm_set_launch(sim.ctx, vec, bx)
-        launch.update(vec=vec, bx=bx)
+        parts = [int(v) for v in args.launch.split(",")]
+        L.lbm_set_launch(sim.ctx, parts[0], parts[1])
+        if len(parts) > 2:
+            L.lbm_set_step_occupancy(sim.ctx, parts[2])
+        launch.update(vec=parts[0], bx=parts[1])
     elif not args.no_autotune:
         # the liquid is at rest before the bubbles are added: tuning steps leave it unchanged
         from paper_1710_07073_amd import autotune
@@ -613,9 +616,12 @@ def main():
         launch.update(vec=vec, bx=bx, tuned=True)
         for v, b, us in entry["sweep"]:
             print(f"[autotune] vec={v} bx={b}: {us:.1f} us", file=sys.stderr, flush=True)
+        for o, us in entry["occupancy_sweep"]:
+            print(f"[autotune] occupancy {o}: {us:.1f} us", file=sys.stderr, flush=True)
     else:
         vec, bx = L.lbm_get_launch(sim.ctx)
         launch.update(vec=vec, bx=bx)
+    launch["workgroups_per_cu"] = L.lbm_get_step_occupancy(sim.ctx)
     sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
     if args.no_overlap:
         L.lbm_set_overlap(sim.ctx, False)

@@ -1,10 +1,12 @@
 """Launch-shape autotuner of the fused liquid step.
 
 The step kernel has two shape parameters (see lbm_set_launch in include/lbm.h): cells per thread
-along x (1, 2, 4) and threads per workgroup along x. Results do not depend on them; speed does,
+along x (1, 2, 4) and threads per workgroup along x; and an occupancy cap (lbm_set_step_occupancy:
+at most so many of its workgroups per compute unit). Results do not depend on them; speed does,
 and the best choice depends on the row length nx, the precision and the machine. The tuner times
-every valid candidate with HIP events on the simulation's stream, keeps the fastest, and caches
-the winner per size class (precision, nx, bucketed ny*nz) in a JSON file.
+every valid shape with HIP events on the simulation's stream, keeps the fastest, then times the
+occupancy caps with that shape, and caches the winner per size class (precision, nx, bucketed
+ny*nz) in a JSON file.
 """
 from __future__ import annotations
 
@@ -35,6 +37,9 @@ def candidates(nx):
     return out
 
 
+OCCUPANCY = (0, 4, 5, 6, 7)  # workgroups per compute unit, 0 = no cap
+
+
 def size_class(shape, precision):
     nx, ny, nz = shape
     plane = ny * nz
@@ -58,9 +63,12 @@ def _save(db):
     os.replace(tmp, CACHE)
 
 
-def time_launch(sim, vec, bx, steps=20, warmup=3):
-    """Average duration (s) of one liquid-step launch with the given shape."""
+def time_launch(sim, vec, bx, steps=20, warmup=3, occ=None):
+    """Average duration (s) of one liquid-step launch with the given shape (and occupancy cap, if
+    given)."""
     L.lbm_set_launch(sim.ctx, vec, bx)
+    if occ is not None:
+        L.lbm_set_step_occupancy(sim.ctx, occ)
     stream = sim.stream
     L.lbm_step(sim.ctx, warmup)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -78,9 +86,10 @@ def tune(sim, steps=20, use_cache=True, verbose=False):
     scratch simulation of the same shape)."""
     key = size_class(sim.shape, sim.precision)
     db = _load() if use_cache else {}
-    if key in db:
-        vec, bx = db[key]["vec"], db[key]["bx"]
+    if key in db and "occ" in db[key]:
+        vec, bx, occ = db[key]["vec"], db[key]["bx"], db[key]["occ"]
         L.lbm_set_launch(sim.ctx, vec, bx)
+        L.lbm_set_step_occupancy(sim.ctx, occ)
         return vec, bx, db[key]
     results = []
     for vec, bx in candidates(sim.shape[0]):
@@ -90,9 +99,19 @@ def tune(sim, steps=20, use_cache=True, verbose=False):
             print(f"  vec={vec} bx={bx}: {t * 1e6:.1f} us/step", flush=True)
     results.sort()
     t, vec, bx = results[0]
+    occ_results = []
+    for occ in OCCUPANCY:
+        to = time_launch(sim, vec, bx, steps, occ=occ)
+        occ_results.append((to, occ))
+        if verbose:
+            print(f"  vec={vec} bx={bx} occupancy={occ}: {to * 1e6:.1f} us/step", flush=True)
+    occ_results.sort()
+    t, occ = occ_results[0]
     L.lbm_set_launch(sim.ctx, vec, bx)
-    entry = {"vec": vec, "bx": bx, "us_per_step": t * 1e6,
-             "sweep": [[v, b, r * 1e6] for r, v, b in results], "time": time.time()}
+    L.lbm_set_step_occupancy(sim.ctx, occ)
+    entry = {"vec": vec, "bx": bx, "occ": occ, "us_per_step": t * 1e6,
+             "sweep": [[v, b, r * 1e6] for r, v, b in results],
+             "occupancy_sweep": [[o, r * 1e6] for r, o in occ_results], "time": time.time()}
     db[key] = entry
     _save(db)
     return vec, bx, entry

@@ -129,6 +129,15 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->bins_clean = false;
   c->stream = static_cast<hipStream_t>(stream);
   lbm::default_launch(G.nx, c->elem, &c->step_vec, &c->step_bx);
+  c->step_wgs = c->elem == 4 ? lbm::kDefaultStepWgsF32 : 0;
+  {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess)
+      lds = 0;  // no cap
+    c->lds_per_cu = lds > 0 ? (uint32_t)lds : 0u;
+  }
   // side stream and events of the overlapped step (default priority); without them the step
   // runs on the caller's stream only. The events order kernels of this device only: every kernel
   // dispatch already releases its writes and acquires at its start, so the events carry no
@@ -233,6 +242,19 @@ lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t vec, int32_t block_x) {
   if (ctx->desc.nx % vec != 0) return LBM_EINVAL;
   ctx->step_vec = vec;
   ctx->step_bx = (uint32_t)block_x;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_step_occupancy(lbm_ctx* ctx, int32_t workgroups_per_cu) {
+  if (!ctx || ctx->hs.pending) return LBM_EINVAL;
+  if (workgroups_per_cu < 0 || workgroups_per_cu > 32) return LBM_EINVAL;
+  ctx->step_wgs = workgroups_per_cu;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_step_occupancy(lbm_ctx* ctx, int32_t* workgroups_per_cu) {
+  if (!ctx || !workgroups_per_cu) return LBM_EINVAL;
+  *workgroups_per_cu = ctx->step_wgs;
   return LBM_OK;
 }
 
@@ -361,7 +383,8 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, in
     const uint32_t mode = (pre.flag_clean[0] ? 1u : 0u) | (pre.flag_clean[1] ? 2u : 0u) |
                           ((uint32_t)pre.rpar << 4) | (ctx->overlap ? 32u : 0u) |
                           (pre.marked ? 64u : 0u) |
-                          ((uint32_t)ctx->step_vec << 8) | (ctx->step_bx << 12);
+                          ((uint32_t)ctx->step_vec << 8) | (ctx->step_bx << 12) |
+                          ((uint32_t)ctx->step_wgs << 24);
     const lbm::GraphKey key = lbm::GraphKey::of(p, s, nb, pre.cur, pre.flag_cur, graph_steps, mode);
     lbm_status st_cap = LBM_OK;
     bool captured = false;

@@ -252,13 +252,13 @@ hipError_t launch_typed(lbm_ctx* c, uint32_t bx) {
   const T* src = static_cast<const T*>(c->pops[c->hs.cur]);
   T* dst = static_cast<T*>(c->pops[c->hs.cur ^ 1]);
   if (!GENERAL && VEC == 1 && bb_fast_ok(G, sizeof(T))) {
-    hipLaunchKernelGGL((k_step_bb<T>), dim3(nblocks), dim3(bx, by), 0, c->stream, src, dst,
+    hipLaunchKernelGGL((k_step_bb<T>), dim3(nblocks), dim3(bx, by), step_lds(c), c->stream, src, dst,
                        static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
                        c->tiles[c->hs.flag_cur ^ 1], nullptr, G, (T)c->desc.omega, c->desc.flags,
                        nbx, nby);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_step<T, VEC, GENERAL>), dim3(nblocks), dim3(bx, by), 0, c->stream, src, dst,
+  hipLaunchKernelGGL((k_step<T, VEC, GENERAL>), dim3(nblocks), dim3(bx, by), step_lds(c), c->stream, src, dst,
                      static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
                      c->tiles[c->hs.flag_cur ^ 1], G, (T)c->desc.omega, c->desc.flags, nbx, nby);
   return hipGetLastError();
@@ -290,7 +290,7 @@ hipError_t launch_bulk_typed(lbm_ctx* c) {
   const uint32_t bx = c->step_bx, by = 256 / bx;
   const uint32_t nbx = div_up(G.nx, bx), nby = div_up(G.ny, by);
   const uint32_t nblocks = nbx * nby * (uint32_t)G.nz;
-  hipLaunchKernelGGL((k_step_bb<T>), dim3(nblocks), dim3(bx, by), 0, c->stream,
+  hipLaunchKernelGGL((k_step_bb<T>), dim3(nblocks), dim3(bx, by), step_lds(c), c->stream,
                      static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(c->pops[c->hs.cur ^ 1]),
                      static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
                      c->tiles[c->hs.flag_cur ^ 1], c->region[c->hs.rpar], G, (T)c->desc.omega,
@@ -308,7 +308,7 @@ hipError_t launch_region_typed(lbm_ctx* c, int32_t nb, hipStream_t stream) {
   const uint64_t rows = std::min<uint64_t>((uint64_t)nb * 16, c->nrows);
   const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(rows * per, 16384));
   const int r = c->hs.rpar;
-  hipLaunchKernelGGL((k_region_bb<T>), dim3(blocks), dim3(bx, by), 0, stream,
+  hipLaunchKernelGGL((k_region_bb<T>), dim3(blocks), dim3(bx, by), step_lds(c), stream,
                      static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(c->pops[c->hs.cur ^ 1]),
                      static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
                      c->tiles[c->hs.flag_cur ^ 1], c->region[r], c->region_list[r], c->region_count + r,

@@ -27,6 +27,7 @@ LBM_COUPLING_POINT_KERNEL, LBM_COUPLING_EXACT_TIME = 4, 8
 
 # every symbol include/lbm.h declares
 EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch", "lbm_get_launch",
+           "lbm_set_step_occupancy", "lbm_get_step_occupancy",
            "lbm_set_overlap", "lbm_get_overlap", "lbm_time_next_step", "lbm_region_cells",
            "lbm_step", "bubbles_step",
            "moments", "lbm_populations", "lbm_state_buffer", "lbm_check", "lbm_run", "lbm_destroy",
@@ -89,6 +90,8 @@ def lib():
         L.lbm_set_stream.argtypes = [P, P]
         L.lbm_set_launch.argtypes = [P, ct.c_int32, ct.c_int32]
         L.lbm_get_launch.argtypes = [P, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]
+        L.lbm_set_step_occupancy.argtypes = [P, ct.c_int32]
+        L.lbm_get_step_occupancy.argtypes = [P, ct.POINTER(ct.c_int32)]
         L.lbm_set_overlap.argtypes = [P, ct.c_int32]
         L.lbm_time_next_step.argtypes = [P, P, P]
         L.lbm_region_cells.argtypes = [P, ct.POINTER(ct.c_int64)]
@@ -176,6 +179,16 @@ def lbm_set_stream(ctx, stream):
 
 def lbm_set_launch(ctx, vec, block_x):
     _ok(lib().lbm_set_launch(ctx, int(vec), int(block_x)), "lbm_set_launch")
+
+
+def lbm_set_step_occupancy(ctx, workgroups_per_cu):
+    _ok(lib().lbm_set_step_occupancy(ctx, int(workgroups_per_cu)), "lbm_set_step_occupancy")
+
+
+def lbm_get_step_occupancy(ctx):
+    w = ct.c_int32()
+    _ok(lib().lbm_get_step_occupancy(ctx, ct.byref(w)), "lbm_get_step_occupancy")
+    return w.value
 
 
 def lbm_get_launch(ctx):

@@ -123,15 +123,16 @@ def test_poiseuille_on_gpu():
     ((8, 6, 7), (BB, BB, PER, PER, BB, BB)),
 ])
 def test_every_launch_shape_gives_identical_results(prec, shape, bc):
-    """The launch shape (cells per thread, workgroup width) is a tuning knob only: every shape
-    the autotuner may pick reproduces the reference launch bit for bit."""
+    """The launch shape (cells per thread, workgroup width) and the occupancy cap are tuning knobs
+    only: every combination the autotuner may pick reproduces the reference launch bit for bit."""
     from paper_1710_07073_amd import autotune
     R = W.random_populations(shape, 1e-3, seed=8)
     F = W.random_field(shape, 2e-5, seed=9)
     ref = None
-    for vec, bx in autotune.candidates(shape[0]):
+    for vec, bx, occ in [(v, b, o) for v, b in autotune.candidates(shape[0]) for o in (0, 5)]:
         sim = S.Simulation(shape, 1.45, precision=prec, bc=bc, flags=FLAGS)
         L.lbm_set_launch(sim.ctx, vec, bx)
+        L.lbm_set_step_occupancy(sim.ctx, occ)
         set_post_collision_state(sim, R)
         sim.force.copy_(torch.from_numpy(F).to(sim.dtype))
         sim.liquid_steps(7)
@@ -146,8 +147,8 @@ def test_every_launch_shape_gives_identical_results(prec, shape, bc):
                 lat.step(Fo)
             assert rel_l2(out[0], lat.g) <= TOL[prec]
         else:
-            assert np.array_equal(out[0], ref[0]), (vec, bx)
-            assert np.array_equal(out[1], ref[1]), (vec, bx)
+            assert np.array_equal(out[0], ref[0]), (vec, bx, occ)
+            assert np.array_equal(out[1], ref[1]), (vec, bx, occ)
 
 
 @pytest.mark.gpu
