@@ -109,16 +109,21 @@ def leg_batched(args, steps):
     cells = sum(w.cells for w in ws)
     gsteps = args.graph_steps or 20
     batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
-    items = None
+    items = occ = None
     if not args.no_autotune:
         items, sweep = autotune.tune_batch(batch, steps=3)
         for k, cand, ms in sweep:
             print(f"[autotune] class {k} item {cand}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+        occ, osweep = autotune.tune_batch_occupancy(batch, steps=3)
+        for o, ms in osweep:
+            print(f"[autotune] batch occupancy {o}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
     batch.close()
-    # tuning stepped the columns; time a fresh batch with the tuned items
+    # tuning stepped the columns; time a fresh batch with the tuned items and occupancy
     batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
     if items is not None:
         L.lbm_batch_set_items(batch.handle, items)
+        L.lbm_batch_set_step_occupancy(batch.handle, occ)
+    wgs = L.lbm_batch_get_step_occupancy(batch.handle)
     warm = args.warmup + (-args.warmup) % gsteps
     batch.run(warm, graph_steps=gsteps)
     stream.synchronize()
@@ -165,7 +170,7 @@ def leg_batched(args, steps):
     mlups = cells * K / elapsed / 1e6
     fp64 = cells * ks / t_single / 1e6
     return {"columns": len(ws), "cells": cells, "bubbles": int(sum(w.nb for w in ws)),
-            "steps": K, "graph_steps": gsteps, "item_cells": items,
+            "steps": K, "graph_steps": gsteps, "item_cells": items, "workgroups_per_cu": wgs,
             "batched_f32_mlups": round(mlups, 1), "ms_per_step": round(elapsed / K * 1e3, 5),
             "event_ms_per_step": round(ev_s / K * 1e3, 5),
             "plain_fp64_single_mlups": round(fp64, 1), "ratio_vs_plain_fp64": round(mlups / fp64, 3),

@@ -359,6 +359,11 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
  * the tuning knob of the batch autotuner; results do not depend on it. */
 lbm_status lbm_batch_set_items(lbm_batch* batch, const int32_t* item_cells);
 lbm_status lbm_batch_get_items(lbm_batch* batch, int32_t* item_cells);
+/* Occupancy of the batched liquid step (as lbm_set_step_occupancy): at most workgroups_per_cu of
+ * its workgroups per compute unit, 0 = no cap, at most 32. lbm_batch_init() picks 3 for FP32 and 0
+ * for FP64 (held to 3 by registers). */
+lbm_status lbm_batch_set_step_occupancy(lbm_batch* batch, int32_t workgroups_per_cu);
+lbm_status lbm_batch_get_step_occupancy(lbm_batch* batch, int32_t* workgroups_per_cu);
 /* nsteps method steps of every column (eager launches). nb must equal the total bubble count. */
 lbm_status lbm_batch_step(lbm_batch* batch, const bubble_params* params, const bubble_soa* soa,
                           int32_t nb, int32_t nsteps);

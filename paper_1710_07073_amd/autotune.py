@@ -167,3 +167,21 @@ def tune_batch(batch, steps=4, verbose=False):
         items = [best[1] if classes[i] == k else items[i] for i in range(ncols)]
     L.lbm_batch_set_items(batch.handle, items)
     return items, sweep
+
+
+BATCH_OCCUPANCY = (0, 2, 3, 4)  # workgroups per compute unit of the batched step, 0 = no cap
+
+
+def tune_batch_occupancy(batch, steps=4, verbose=False):
+    """Time the occupancy caps of the batched liquid step with the batch's current items; applies
+    and returns the fastest and the sweep [(cap, ms/step)]. The batch state advances."""
+    sweep = []
+    for occ in BATCH_OCCUPANCY:
+        L.lbm_batch_set_step_occupancy(batch.handle, occ)
+        t = time_batch(batch, steps)
+        sweep.append((occ, t * 1e3))
+        if verbose:
+            print(f"  occupancy {occ}: {t * 1e3:.3f} ms/step", flush=True)
+    best = min(sweep, key=lambda e: e[1])[0]
+    L.lbm_batch_set_step_occupancy(batch.handle, best)
+    return best, sweep

@@ -34,6 +34,8 @@ struct lbm_batch {
   uint32_t nred;
   hipStream_t stream;
   int64_t steps;
+  int32_t step_wgs;     // at most this many liquid-step workgroups per compute unit (0: no cap)
+  uint32_t lds_per_cu;  // LDS bytes of one compute unit
   lbm::StepGraph graph;
 };
 
@@ -270,7 +272,8 @@ hipError_t upload_table(lbm_batch* b) {
 
 template <typename T, bool GENERAL>
 hipError_t batch_step_typed(lbm_batch* b) {
-  hipLaunchKernelGGL((k_batch_step<T, GENERAL>), dim3(b->nitems), dim3(256), 0, b->stream, b->dev,
+  hipLaunchKernelGGL((k_batch_step<T, GENERAL>), dim3(b->nitems), dim3(256),
+                     occupancy_lds(b->lds_per_cu, b->step_wgs), b->stream, b->dev,
                      b->ncols, b->nitems, b->cur, b->flag_cur, b->flags);
   return hipGetLastError();
 }
@@ -343,6 +346,17 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
   b->cols.assign(cols, cols + ncols);
   b->nb_total = L.nb_total;
   b->stream = static_cast<hipStream_t>(stream);
+  // FP32: at most kDefaultBatchWgsF32 step workgroups per compute unit (FP64 is held to 3 by its
+  // registers)
+  b->step_wgs = elem == 4 ? lbm::kDefaultBatchWgsF32 : 0;
+  {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess)
+      lds = 0;
+    b->lds_per_cu = lds > 0 ? (uint32_t)lds : 0u;
+  }
   b->cur = 0;
   b->flag_cur = 0;
   b->flag_clean[0] = b->flag_clean[1] = true;
@@ -412,6 +426,19 @@ lbm_status lbm_batch_set_items(lbm_batch* b, const int32_t* item_cells) {
   assign_items(b);
   b->graph.reset();
   return to_status(upload_table(b));
+}
+
+lbm_status lbm_batch_set_step_occupancy(lbm_batch* b, int32_t workgroups_per_cu) {
+  if (!b || workgroups_per_cu < 0 || workgroups_per_cu > 32) return LBM_EINVAL;
+  b->step_wgs = workgroups_per_cu;
+  b->graph.reset();  // captured launches hold the old setting
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_step_occupancy(lbm_batch* b, int32_t* workgroups_per_cu) {
+  if (!b || !workgroups_per_cu) return LBM_EINVAL;
+  *workgroups_per_cu = b->step_wgs;
+  return LBM_OK;
 }
 
 lbm_status lbm_batch_get_items(lbm_batch* b, int32_t* item_cells) {

@@ -206,13 +206,20 @@ inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 // 4-5). FP64 launches are held to 4 by their registers already.
 constexpr int32_t kDefaultStepWgsF32 = 5;
 
-// Dynamic LDS a liquid-step launch requests (the kernels use none) so that at most step_wgs of its
-// workgroups fit on one compute unit; LDS is allocated in 512-byte granules.
-inline size_t step_lds(const lbm_ctx* c) {
-  if (c->step_wgs <= 0 || c->lds_per_cu == 0) return 0;
-  size_t s = (size_t)c->lds_per_cu / (size_t)c->step_wgs / 512 * 512;
+// Workgroups per compute unit of the FP32 batched step (64 uneven columns: 1.716 ms uncapped,
+// 1.55 ms at 2-3; its 95 VGPRs allow 5).
+constexpr int32_t kDefaultBatchWgsF32 = 3;
+
+// Dynamic LDS a launch requests (the step kernels use none) so that at most wgs of its
+// workgroups fit on one compute unit with lds_per_cu bytes of LDS; LDS is allocated in 512-byte
+// granules, at most 64 KB per workgroup.
+inline size_t occupancy_lds(uint32_t lds_per_cu, int32_t wgs) {
+  if (wgs <= 0 || lds_per_cu == 0) return 0;
+  size_t s = (size_t)lds_per_cu / (size_t)wgs / 512 * 512;
   return s > 65536 ? 65536 : s;
 }
+
+inline size_t step_lds(const lbm_ctx* c) { return occupancy_lds(c->lds_per_cu, c->step_wgs); }
 
 inline void default_launch(int nx, size_t elem, int* vec, uint32_t* bx) {
   (void)elem;

@@ -33,6 +33,7 @@ EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch",
            "moments", "lbm_populations", "lbm_state_buffer", "lbm_check", "lbm_run", "lbm_destroy",
            "lbm_status_string",
            "lbm_batch_bytes_required", "lbm_batch_init", "lbm_batch_set_items", "lbm_batch_get_items",
+           "lbm_batch_set_step_occupancy", "lbm_batch_get_step_occupancy",
            "lbm_batch_step", "lbm_batch_run", "lbm_batch_populations", "lbm_batch_sums",
            "lbm_batch_column",
            "lbm_batch_check", "lbm_batch_destroy",
@@ -112,6 +113,8 @@ def lib():
                                      ct.POINTER(P)]
         L.lbm_batch_set_items.argtypes = [P, ct.POINTER(ct.c_int32)]
         L.lbm_batch_get_items.argtypes = [P, ct.POINTER(ct.c_int32)]
+        L.lbm_batch_set_step_occupancy.argtypes = [P, ct.c_int32]
+        L.lbm_batch_get_step_occupancy.argtypes = [P, ct.POINTER(ct.c_int32)]
         L.lbm_batch_step.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32,
                                      ct.c_int32]
         L.lbm_batch_run.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32,
@@ -289,6 +292,16 @@ def lbm_batch_init(cols, precision, flags, pool, scratch, stream):
 def lbm_batch_set_items(batch, item_cells):
     arr = (ct.c_int32 * len(item_cells))(*[int(v) for v in item_cells])
     _ok(lib().lbm_batch_set_items(batch, arr), "lbm_batch_set_items")
+
+
+def lbm_batch_set_step_occupancy(batch, workgroups_per_cu):
+    _ok(lib().lbm_batch_set_step_occupancy(batch, int(workgroups_per_cu)), "lbm_batch_set_step_occupancy")
+
+
+def lbm_batch_get_step_occupancy(batch):
+    w = ct.c_int32()
+    _ok(lib().lbm_batch_get_step_occupancy(batch, ct.byref(w)), "lbm_batch_get_step_occupancy")
+    return w.value
 
 
 def lbm_batch_get_items(batch, ncols):

@@ -83,11 +83,15 @@ def test_batch_columns_match_oracle():
 
 @pytest.mark.gpu
 def test_batch_item_sizes_are_bit_identical():
+    """Item sizes and the occupancy cap are tuning knobs only (one bubble per column, so no two
+    force additions meet in a cell and the force field has one order)."""
     cols = [dict(c, pos=c["pos"][:, :1], d=c["d"][:1]) for c in _columns(seed=23)]
     ref = None
-    for items in (256, 1024, 4096):
+    for items, occ in ((256, 3), (1024, 0), (4096, 2), (256, 0)):
         batch = S.Batch(cols, S.bubble_params(**_params()), precision="f32")
         L.lbm_batch_set_items(batch.handle, [items] * len(cols))
+        L.lbm_batch_set_step_occupancy(batch.handle, occ)
+        assert L.lbm_batch_get_step_occupancy(batch.handle) == occ
         batch.step(12)
         out = [batch.populations(c).cpu().numpy() for c in range(len(cols))]
         batch.close()
