@@ -164,8 +164,8 @@ lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t vec, int32_t block_x);
 
 /* Occupancy of the liquid-step launches (a tuning knob; results do not depend on it): at most
  * workgroups_per_cu of their workgroups run on one compute unit at a time (each launch requests
- * unused LDS to that end), 0 = no cap, at most 32. lbm_init() picks 5 for FP32 lattices and 0 for
- * FP64 (held to 4 by registers). LBM_EINVAL while a bubble half is pending. */
+ * unused LDS to that end), 0 = no cap, at most 32. lbm_init() picks 5 for FP32 lattices and 3 for
+ * FP64. LBM_EINVAL while a bubble half is pending. */
 lbm_status lbm_set_step_occupancy(lbm_ctx* ctx, int32_t workgroups_per_cu);
 lbm_status lbm_get_step_occupancy(lbm_ctx* ctx, int32_t* workgroups_per_cu);
 lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* vec, int32_t* block_x);

@@ -37,7 +37,7 @@ def candidates(nx):
     return out
 
 
-OCCUPANCY = (0, 4, 5, 6, 7)  # workgroups per compute unit, 0 = no cap
+OCCUPANCY = (0, 3, 4, 5, 6, 7)  # workgroups per compute unit, 0 = no cap
 
 
 def size_class(shape, precision):

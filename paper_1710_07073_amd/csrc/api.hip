@@ -129,7 +129,7 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->bins_clean = false;
   c->stream = static_cast<hipStream_t>(stream);
   lbm::default_launch(G.nx, c->elem, &c->step_vec, &c->step_bx);
-  c->step_wgs = c->elem == 4 ? lbm::kDefaultStepWgsF32 : 0;
+  c->step_wgs = c->elem == 4 ? lbm::kDefaultStepWgsF32 : lbm::kDefaultStepWgsF64;
   {
     int dev = 0, lds = 0;
     if (hipGetDevice(&dev) != hipSuccess ||

@@ -201,10 +201,11 @@ hipError_t launch_fill(void* ptr, size_t bytes, hipStream_t s);
 inline uint32_t div_up(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
 // Default launch shape of the liquid step: whole rows per workgroup where they fit.
-// Workgroups per compute unit the FP32 liquid-step launches are held to by default: fewer waves in
-// flight stream the populations faster (128 x 128 x 512 method step: 228.8 us uncapped, 218 us at
-// 4-5). FP64 launches are held to 4 by their registers already.
+// Workgroups per compute unit the liquid-step launches are held to by default: fewer waves in
+// flight stream the populations faster (128 x 128 x 512: FP32 method step 228.8 us uncapped,
+// 218 us at 4-5; FP64 liquid step 443.8 us at the 4 its registers allow, 417 us at 3).
 constexpr int32_t kDefaultStepWgsF32 = 5;
+constexpr int32_t kDefaultStepWgsF64 = 3;
 
 // Workgroups per compute unit of the FP32 batched step (64 uneven columns: 1.716 ms uncapped,
 // 1.55 ms at 2-3; its 95 VGPRs allow 5).
