@@ -129,8 +129,10 @@ def test_every_launch_shape_gives_identical_results(prec, shape, bc):
     R = W.random_populations(shape, 1e-3, seed=8)
     F = W.random_field(shape, 2e-5, seed=9)
     ref = None
-    for vec, bx, occ in [(v, b, o) for v, b in autotune.candidates(shape[0]) for o in (0, 5)]:
+    for vec, bx, occ in [(v, b, o) for v, b in autotune.candidates(shape[0]) for o in (0, 3, 5)]:
         sim = S.Simulation(shape, 1.45, precision=prec, bc=bc, flags=FLAGS)
+        # the default cap: 5 workgroups per compute unit in FP32, 3 in FP64
+        assert L.lbm_get_step_occupancy(sim.ctx) == (5 if prec == "f32" else 3)
         L.lbm_set_launch(sim.ctx, vec, bx)
         L.lbm_set_step_occupancy(sim.ctx, occ)
         set_post_collision_state(sim, R)
