@@ -83,4 +83,12 @@ def test_null_context_calls_are_rejected():
     assert lib.lbm_step(None, 1) == L.LBM_EINVAL
     assert lib.moments(None, None, None, None) == L.LBM_EINVAL
     assert lib.lbm_check(None) == L.LBM_EINVAL
+    out = ct.c_int32(-7)
+    assert lib.lbm_set_step_occupancy(None, 3) == L.LBM_EINVAL
+    assert lib.lbm_get_step_occupancy(None, ct.byref(out)) == L.LBM_EINVAL
+    assert lib.lbm_set_overlap(None, 1) == L.LBM_EINVAL
+    assert lib.lbm_record_next_bubble_half(None, None) == L.LBM_EINVAL
+    assert lib.lbm_batch_set_step_occupancy(None, 3) == L.LBM_EINVAL
+    assert lib.lbm_batch_get_step_occupancy(None, ct.byref(out)) == L.LBM_EINVAL
+    assert out.value == -7  # nothing written on rejection
     assert lib.lbm_destroy(None) == L.LBM_OK
