@@ -399,10 +399,60 @@ __device__ __forceinline__ void state_velocity(const T* __restrict__ src, const 
 // bubbles: 1, at 50 VGPRs instead of 108, so that more workgroups stay resident beside the bulk
 // launch (20 000 bubbles: 394 us against 1289 us with 8).
 // FUSE (few bubbles on one lattice): the workgroup then also runs its bubble's update (k_ode's
-// arithmetic, one lane) and flags its tiles, so the step has one launch less.
+// arithmetic, one lane) and flags its tiles, so the step has one launch less. The fourth wavefront,
+// idle while the other three compute the weights, prepares the update's closure constants and
+// loads, and the update takes the sums from registers instead of reading them back.
+// Per-bubble constants of the Table 1 closures (they depend on the diameter only).
+struct BubbleConst {
+  double V, r2pi, fb, inv_meff, va;  // volume, pi r^2, buoyancy, 1/m_eff, (1 + C_A) rho_l V
+  double visc24, visc48, re_sat;     // 24 nu/d, 48 nu/d, Re beyond which 48/Re wins
+  double shape;                      // 8/3 Eo/(Eo + 4)
+  double f_lift;                     // f(Eo_d)
+  double Eod;
+};
+
+__device__ BubbleConst bubble_constants(const bubble_params& P, double nu, double d) {
+  const double pi = 3.14159265358979323846;
+  BubbleConst k;
+  k.V = pi * d * d * d / 6.0;
+  const double r = 0.5 * d;
+  k.r2pi = pi * r * r;
+  k.fb = (P.rho_l - P.rho_b) * k.V * P.g;
+  k.inv_meff = 1.0 / (P.rho_b * k.V + P.c_a * P.rho_l * k.V);
+  k.va = (1.0 + P.c_a) * P.rho_l * k.V;
+  k.visc24 = 24.0 * nu / d;
+  k.visc48 = 48.0 * nu / d;
+  // 1 + k Re^0.687 >= 2 for Re >= (1/k)^(1/0.687): there the min{} of C_D is 48/Re
+  k.re_sat = P.cd_k > 0.0 ? exp(log(1.0 / P.cd_k) / 0.687) : INFINITY;
+  const double Eo = (P.rho_l - P.rho_b) * P.g * d * d / P.sigma;
+  k.shape = 8.0 / 3.0 * Eo / (Eo + 4.0);
+  const double E = 1.0 / (1.0 + 0.163 * exp(0.757 * log(Eo)));
+  k.Eod = Eo / exp(2.0 / 3.0 * log(E));
+  k.f_lift = 0.00105 * k.Eod * k.Eod * k.Eod - 0.0159 * k.Eod * k.Eod - 0.0204 * k.Eod + P.lift_f0;
+  return k;
+}
+
+// The inputs of one bubble's update: its state before the step and the coupling sums of eq. (20).
+struct OdeIn {
+  int st;
+  double valid, d;
+  double ul[3], wl[3], ulp[3], ub[3], xn[3];
+};
+
+// What the fused update takes from the start of its workgroup: the closure constants and the
+// bubble's velocity and liquid velocity of the last step.
+struct FusePre {
+  BubbleConst kc;
+  double ub[3], ulp[3];
+};
+
 template <typename Geo>
 __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3], double xn_out[3],
                          double& n_out);
+template <typename Geo>
+__device__ bool ode_update(const Geo& geo, const BubbleArgs& A, int b, const OdeIn& in,
+                           const BubbleConst* kc_in, const double* x0_in, double x0[3],
+                           double xn_out[3], double& n_out);
 
 template <typename T, typename Geo, bool EXACT = false, int GATHER = 1, bool FUSE = false>
 __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
@@ -427,7 +477,8 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
       ode_lane(geo, A, b, x0, xn, m);
     }
   };
-  if (A.S.state[b] == 0) {
+  const int st = A.S.state[b];
+  if (st == 0) {
     if (tid == 0) {
       work[W_VALID] = 0.0;
       ode_skip();
@@ -440,6 +491,20 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   Axis win[3];
   const bool finite = isfinite(xb[0]) && isfinite(xb[1]) && isfinite(xb[2]) && d > 0.0;
   const bool point = A.P.coupling & LBM_COUPLING_POINT_KERNEL;
+  __shared__ FusePre s_pre;
+  if constexpr (FUSE) {
+    // wavefront 3 has no axis to weigh: it prepares the update's constants and loads meanwhile
+    static_assert(kBlock >= 256, "a fourth wavefront");
+    if (tid == 192) {
+      s_pre.kc = bubble_constants(A.P, col.nu, d);
+      s_pre.ub[0] = A.S.ux[b];
+      s_pre.ub[1] = A.S.uy[b];
+      s_pre.ub[2] = A.S.uz[b];
+      s_pre.ulp[0] = A.S.ulx[b];
+      s_pre.ulp[1] = A.S.uly[b];
+      s_pre.ulp[2] = A.S.ulz[b];
+    }
+  }
   if (!finite || !build_weights(G, xb, n, tid, s_w, s_dw, win, point)) {
     if (tid == 0) {
       work[W_VALID] = 0.0;
@@ -566,12 +631,24 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
     work[W_VALID] = 1.0;
   }
   if constexpr (FUSE) {
-    // the update reads what lane 0 just wrote; the force window at x0 is win
+    // the update's inputs are at hand: the sums (in every thread), the position, a valid window
+    // and what wavefront 3 prepared; the force window at x0 is win
     __shared__ double s_xn[3];
     __shared__ int s_flag;
     if (tid == 0) {
+      OdeIn in;
+      in.st = st;
+      in.valid = 1.0;
+      in.d = d;
+      for (int a = 0; a < 3; ++a) {
+        in.ul[a] = acc[a];
+        in.wl[a] = acc[3 + a];
+        in.ulp[a] = s_pre.ulp[a];
+        in.ub[a] = s_pre.ub[a];
+        in.xn[a] = xb[a];
+      }
       double x0[3], xn[3], m = 0.0;
-      s_flag = ode_lane(geo, A, b, x0, xn, m) ? 1 : 0;
+      s_flag = ode_update(geo, A, b, in, &s_pre.kc, xb, x0, xn, m) ? 1 : 0;
       for (int a = 0; a < 3; ++a) s_xn[a] = xn[a];
     }
     __syncthreads();
@@ -585,35 +662,6 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
 // ---------------------------------------------------------------------------------------------
 // Bubble dynamics, one lane per bubble.
 // ---------------------------------------------------------------------------------------------
-// Per-bubble constants of the Table 1 closures (they depend on the diameter only).
-struct BubbleConst {
-  double V, r2pi, fb, inv_meff, va;  // volume, pi r^2, buoyancy, 1/m_eff, (1 + C_A) rho_l V
-  double visc24, visc48, re_sat;     // 24 nu/d, 48 nu/d, Re beyond which 48/Re wins
-  double shape;                      // 8/3 Eo/(Eo + 4)
-  double f_lift;                     // f(Eo_d)
-  double Eod;
-};
-
-__device__ BubbleConst bubble_constants(const bubble_params& P, double nu, double d) {
-  const double pi = 3.14159265358979323846;
-  BubbleConst k;
-  k.V = pi * d * d * d / 6.0;
-  const double r = 0.5 * d;
-  k.r2pi = pi * r * r;
-  k.fb = (P.rho_l - P.rho_b) * k.V * P.g;
-  k.inv_meff = 1.0 / (P.rho_b * k.V + P.c_a * P.rho_l * k.V);
-  k.va = (1.0 + P.c_a) * P.rho_l * k.V;
-  k.visc24 = 24.0 * nu / d;
-  k.visc48 = 48.0 * nu / d;
-  // 1 + k Re^0.687 >= 2 for Re >= (1/k)^(1/0.687): there the min{} of C_D is 48/Re
-  k.re_sat = P.cd_k > 0.0 ? exp(log(1.0 / P.cd_k) / 0.687) : INFINITY;
-  const double Eo = (P.rho_l - P.rho_b) * P.g * d * d / P.sigma;
-  k.shape = 8.0 / 3.0 * Eo / (Eo + 4.0);
-  const double E = 1.0 / (1.0 + 0.163 * exp(0.757 * log(Eo)));
-  k.Eod = Eo / exp(2.0 / 3.0 * log(E));
-  k.f_lift = 0.00105 * k.Eod * k.Eod * k.Eod - 0.0159 * k.Eod * k.Eod - 0.0204 * k.Eod + P.lift_f0;
-  return k;
-}
 
 // Drag and lift of Table 1 on a bubble moving at ub in liquid of velocity ul and vorticity wl,
 // with Re = |u_r| d / nu (eq. (3)). C_D is used multiplied by |u_r| so that the viscous
@@ -650,25 +698,53 @@ __device__ __forceinline__ void drag_lift(const bubble_params& P, const BubbleCo
 template <typename Geo>
 __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3], double xn_out[3],
                          double& n_out) {
+  const double* work = A.S.work + (size_t)b * kWork;
+  // every load of the update at once (one round trip; all in bounds for b < nb)
+  OdeIn in;
+  in.st = A.S.state[b];
+  in.valid = work[W_VALID];
+  in.d = A.S.d[b];
+  for (int a = 0; a < 3; ++a) {
+    in.ul[a] = work[W_UL + a];
+    in.wl[a] = work[W_WL + a];
+  }
+  in.ulp[0] = A.S.ulx[b];
+  in.ulp[1] = A.S.uly[b];
+  in.ulp[2] = A.S.ulz[b];
+  in.ub[0] = A.S.ux[b];
+  in.ub[1] = A.S.uy[b];
+  in.ub[2] = A.S.uz[b];
+  in.xn[0] = A.S.x[b];
+  in.xn[1] = A.S.y[b];
+  in.xn[2] = A.S.z[b];
+  // the values as operands of an empty statement: the compiler keeps the loads above the branch
+  // of the update instead of moving them into the branch's live path (a second round trip)
+  asm volatile("" ::"v"(in.d), "v"(in.ul[0]), "v"(in.ul[1]), "v"(in.ul[2]), "v"(in.wl[0]),
+               "v"(in.wl[1]), "v"(in.wl[2]), "v"(in.ulp[0]), "v"(in.ulp[1]), "v"(in.ulp[2]),
+               "v"(in.ub[0]), "v"(in.ub[1]), "v"(in.ub[2]), "v"(in.xn[0]), "v"(in.xn[1]),
+               "v"(in.xn[2]));
+  return ode_update(geo, A, b, in, nullptr, nullptr, x0, xn_out, n_out);
+}
+
+// The update itself from its inputs; kc_in and x0_in, when given, are the closure constants and
+// the window position already at hand (otherwise computed, and read from the bubble's work area).
+template <typename Geo>
+__device__ bool ode_update(const Geo& geo, const BubbleArgs& A, int b, const OdeIn& in,
+                           const BubbleConst* kc_in, const double* x0_in, double x0[3],
+                           double xn_out[3], double& n_out) {
   const ColumnView<float> col = geo.template view<float>(b);
   const Geom& G = col.G;
   const double nu = col.nu;
   const bubble_params& P = A.P;
   double* work = A.S.work + (size_t)b * kWork;
-  // every load of the update at once (one round trip; all in bounds for b < nb)
-  const int st = A.S.state[b];
-  const double valid = work[W_VALID];
-  const double d = A.S.d[b];
-  const double ul[3] = {work[W_UL], work[W_UL + 1], work[W_UL + 2]};
-  const double wl[3] = {work[W_WL], work[W_WL + 1], work[W_WL + 2]};
-  const double ulp[3] = {A.S.ulx[b], A.S.uly[b], A.S.ulz[b]};
-  double ub[3] = {A.S.ux[b], A.S.uy[b], A.S.uz[b]};
-  double xn[3] = {A.S.x[b], A.S.y[b], A.S.z[b]};
-  // the values as operands of an empty statement: the compiler keeps the loads above the branch
-  // below instead of moving them into the branch's live path (a second round trip)
-  asm volatile("" ::"v"(d), "v"(ul[0]), "v"(ul[1]), "v"(ul[2]), "v"(wl[0]), "v"(wl[1]), "v"(wl[2]),
-               "v"(ulp[0]), "v"(ulp[1]), "v"(ulp[2]), "v"(ub[0]), "v"(ub[1]), "v"(ub[2]),
-               "v"(xn[0]), "v"(xn[1]), "v"(xn[2]));
+  const int st = in.st;
+  const double valid = in.valid;
+  const double d = in.d;
+  const double ul[3] = {in.ul[0], in.ul[1], in.ul[2]};
+  const double wl[3] = {in.wl[0], in.wl[1], in.wl[2]};
+  const double ulp[3] = {in.ulp[0], in.ulp[1], in.ulp[2]};
+  double ub[3] = {in.ub[0], in.ub[1], in.ub[2]};
+  double xn[3] = {in.xn[0], in.xn[1], in.xn[2]};
   // the armed step record: the state before the update (what k_record's two stages copy)
   double* rec = A.rec ? A.rec + (size_t)b * R_SIZE : nullptr;
   if (rec) {
@@ -701,7 +777,11 @@ __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3
     dul[1] = ul[1] - ulp[1];
     dul[2] = ul[2] - ulp[2];
   }
-  const BubbleConst kc = bubble_constants(P, nu, d);
+  BubbleConst kc;
+  if (kc_in)
+    kc = *kc_in;
+  else
+    kc = bubble_constants(P, nu, d);
   const double dt = 1.0 / P.n_sub;
   const int reaction = P.coupling & LBM_REACTION_MASK;
   const double m_b = P.rho_b * kc.V;
@@ -795,7 +875,7 @@ __device__ bool ode_lane(const Geo& geo, const BubbleArgs& A, int b, double x0[3
   if constexpr (std::is_same_v<Geo, OneColumn>) {
     if (geo.lists) {  // the spreading gathers per tile: the tiles are flagged by the wavefront
       for (int a = 0; a < 3; ++a) {
-        x0[a] = work[W_X0 + a];
+        x0[a] = x0_in ? x0_in[a] : work[W_X0 + a];
         xn_out[a] = xn[a];
       }
       n_out = P.kernel_factor * d;
