@@ -22,7 +22,8 @@
  *     float for LBM_FP32_SHIFTED and double for LBM_FP64_SHIFTED.
  *   - Memory: every buffer is caller-owned device memory (hipMalloc / torch allocations). The
  *     library never allocates or frees device memory; the context itself is host memory owned by
- *     the library and released by lbm_destroy().
+ *     the library and released by lbm_destroy(). The one device array the library holds, the
+ *     workspace of bubbles_step_static_work(), is a static array of its code object.
  *   - Streams: every call enqueues its kernels on the stream given to lbm_init() (or
  *     lbm_set_stream()) and returns without waiting, except where stated. NULL = default stream.
  *   - Errors: argument errors are detected on the host and returned at once as LBM_EINVAL,
@@ -254,6 +255,30 @@ lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* params, const bubble_soa* 
 
 /* Release the context (not the caller's buffers). NULL is accepted. */
 lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* ---------------------------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): bubbles_step() with its per-bubble workspace held by
+ * the library instead of the caller.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Bubbles bubbles_step_static_work() accepts: its workspace array holds this many bubbles'
+ * LBM_BUBBLE_WORK doubles (1.7 MiB per GPU). */
+#define LBM_STATIC_WORK_BUBBLES 1024
+
+/* As bubbles_step(), with the nb x LBM_BUBBLE_WORK doubles of per-bubble workspace taken from a
+ * fixed device array inside the library; soa->work is ignored and may be NULL. The call allocates
+ * nothing: the array exists on every GPU the library runs on and is held until the process ends
+ * (its address on a device is resolved once, by the first lbm_init() on that device). The caller
+ * still passes the context's buffers and the bubble arrays. nb > LBM_STATIC_WORK_BUBBLES (or
+ * negative): LBM_EINVAL, nothing enqueued. LBM_EDEVICE if the array's address could not be
+ * resolved on the context's device. Every call on one GPU uses the same array and leaves its
+ * contents there; each call writes every entry before reading it, so nothing needs clearing, but
+ * bubble halves that may run at the same time on one GPU (contexts stepping on different streams
+ * with no ordering between them) race on it and must not be issued. lbm_bubble_record() stage 1
+ * reads soa->work and so cannot follow this call; arm lbm_record_next_bubble_half() instead. */
+lbm_status bubbles_step_static_work(lbm_ctx* ctx, const bubble_params* params,
+                                    const bubble_soa* soa, int32_t nb);
 
 /* ---------------------------------------------------------------------------------------------
  * Adjoint (reverse-mode derivative) of one method step, for gradients of a loss on bubble

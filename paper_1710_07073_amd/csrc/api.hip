@@ -1,6 +1,7 @@
 // C ABI (include/lbm.h): argument checking, the context, the scratch layout and the launches.
 #include <math.h>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string.h>
 #include <vector>
@@ -67,6 +68,32 @@ lbm_status from_hip(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVIC
 
 }  // namespace
 
+// Per-bubble workspace of bubbles_step_static_work(): every GPU the library runs on holds its own
+// copy until the process ends. In host code this name is only a handle for the runtime: kernels
+// receive the device address that static_work_address() resolves per device, never the name.
+static __device__ __align__(256) double scratch[LBM_STATIC_WORK_BUBBLES * LBM_BUBBLE_WORK];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex static_work_mu;
+double* static_work_ptr[kMaxDevices];  // device address of `scratch` per device, once resolved
+
+// Device address of `scratch` on device dev, which must be the current device; resolved on the
+// first call for that device. Null if dev is out of range or the runtime cannot resolve it.
+double* static_work_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(static_work_mu);
+  if (!static_work_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p)
+      static_work_ptr[dev] = static_cast<double*>(p);
+  }
+  return static_work_ptr[dev];
+}
+
+}  // namespace
+
 extern "C" {
 
 lbm_status lbm_bytes_required(const lbm_desc* desc, size_t* pop_buffer_bytes, size_t* field_bytes,
@@ -130,13 +157,17 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->stream = static_cast<hipStream_t>(stream);
   lbm::default_launch(G.nx, c->elem, &c->step_vec, &c->step_bx);
   c->step_wgs = c->elem == 4 ? lbm::kDefaultStepWgsF32 : lbm::kDefaultStepWgsF64;
+  c->static_work = nullptr;
   {
     int dev = 0, lds = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
+    const bool have_dev = hipGetDevice(&dev) == hipSuccess;
+    if (!have_dev ||
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
             hipSuccess)
       lds = 0;  // no cap
     c->lds_per_cu = lds > 0 ? (uint32_t)lds : 0u;
+    // the context's device is current here: resolve the library's workspace array on it
+    if (have_dev) c->static_work = static_work_address(dev);
   }
   // side stream and events of the overlapped step (default priority); without them the step
   // runs on the caller's stream only. The events order kernels of this device only: every kernel
@@ -301,6 +332,15 @@ lbm_status bubble_half(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s
 
 lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, int32_t nb) {
   return bubble_half(ctx, p, s, nb, false);
+}
+
+lbm_status bubbles_step_static_work(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s,
+                                    int32_t nb) {
+  if (!ctx || !s || nb < 0 || nb > LBM_STATIC_WORK_BUBBLES) return LBM_EINVAL;
+  if (!ctx->static_work) return LBM_EDEVICE;
+  bubble_soa w = *s;
+  w.work = ctx->static_work;
+  return bubble_half(ctx, p, &w, nb, false);
 }
 
 lbm_status lbm_check(lbm_ctx* ctx) {

@@ -71,6 +71,9 @@ struct lbm_ctx {
   uint32_t lds_per_cu;  // LDS bytes of one compute unit
   lbm::GraphCache<lbm::HostState> graph;  // captured method steps (lbm_run), with the host state
                                           // their replay leaves
+  // device address of the library's own per-bubble workspace on this context's device
+  // (bubbles_step_static_work), null if it could not be resolved
+  double* static_work;
 };
 
 namespace lbm {

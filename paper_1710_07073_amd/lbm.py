@@ -21,6 +21,7 @@ LBM_MAX_STENCIL = 64
 LBM_BUBBLE_WORK = 216
 LBM_BUBBLE_RECORD = 128
 LBM_BUBBLE_ADJ = 12
+LBM_STATIC_WORK_BUBBLES = 1024
 # coupling variants (bubble_params.coupling)
 LBM_REACTION_MASK, LBM_REACTION_SUBSTEP_MEAN, LBM_REACTION_NET_FORCE = 3, 1, 2
 LBM_COUPLING_POINT_KERNEL, LBM_COUPLING_EXACT_TIME = 4, 8
@@ -29,7 +30,7 @@ LBM_COUPLING_POINT_KERNEL, LBM_COUPLING_EXACT_TIME = 4, 8
 EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch", "lbm_get_launch",
            "lbm_set_step_occupancy", "lbm_get_step_occupancy",
            "lbm_set_overlap", "lbm_get_overlap", "lbm_time_next_step", "lbm_region_cells",
-           "lbm_step", "bubbles_step",
+           "lbm_step", "bubbles_step", "bubbles_step_static_work",
            "moments", "lbm_populations", "lbm_state_buffer", "lbm_check", "lbm_run", "lbm_destroy",
            "lbm_status_string",
            "lbm_batch_bytes_required", "lbm_batch_init", "lbm_batch_set_items", "lbm_batch_get_items",
@@ -99,6 +100,8 @@ def lib():
         L.lbm_get_overlap.argtypes = [P, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]
         L.lbm_step.argtypes = [P, ct.c_int32]
         L.bubbles_step.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32]
+        L.bubbles_step_static_work.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA),
+                                               ct.c_int32]
         L.moments.argtypes = [P, P, P, ct.POINTER(ct.c_double)]
         L.lbm_populations.argtypes = [P, P]
         L.lbm_state_buffer.argtypes = [P, ct.POINTER(P)]
@@ -229,6 +232,11 @@ def lbm_step(ctx, nsteps=1):
 
 def bubbles_step(ctx, params, soa, nb):
     _ok(lib().bubbles_step(ctx, ct.byref(params), ct.byref(soa), int(nb)), "bubbles_step")
+
+
+def bubbles_step_static_work(ctx, params, soa, nb):
+    _ok(lib().bubbles_step_static_work(ctx, ct.byref(params), ct.byref(soa), int(nb)),
+        "bubbles_step_static_work")
 
 
 def moments(ctx, rho_ptr=None, u_ptr=None, want_sums=True):
