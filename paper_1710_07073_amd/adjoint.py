@@ -30,7 +30,12 @@ class TrajectoryProblem:
     """One column with bubbles and a trajectory loss to differentiate."""
 
     def __init__(self, shape, bc, pos, d, params, steps, precision="f32", checkpoint=100,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, init_state=None, init_vel=None):
+        """init_state (19, nz, ny, nx), init_vel (3, nz, ny, nx): optional initial liquid, the
+        post-collision shifted populations awaiting streaming and the velocity field the first bubble
+        half interpolates (default: liquid at rest). The gradient does not flow into them."""
+        self.init_state = None if init_state is None else np.asarray(init_state, np.float64)
+        self.init_vel = None if init_vel is None else np.asarray(init_vel, np.float64)
         self.shape = tuple(shape)
         self.bc = tuple(bc)
         self.pos = np.asarray(pos, np.float64).reshape(3, -1)
@@ -54,6 +59,13 @@ class TrajectoryProblem:
         sim = S.Simulation(self.shape, omega, precision=self.precision, bc=self.bc,
                            device=self.device, stream=self.stream)
         sim.add_bubbles(self.pos, self.d, S.bubble_params(**p))
+        if self.init_state is not None:
+            st = torch.from_numpy(self.init_state).to(self.device, sim.dtype)
+            if not (sim.flags & L.LBM_FLAG_PLAIN_SOA):
+                st = st.permute(1, 0, 2, 3)  # plane-blocked buffer (nz, 19, ny, nx)
+            self.state_tensor(sim).copy_(st)
+        if self.init_vel is not None:
+            sim.vel.copy_(torch.from_numpy(self.init_vel).to(self.device, sim.dtype))
         return sim
 
     @staticmethod

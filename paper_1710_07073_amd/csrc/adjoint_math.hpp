@@ -44,6 +44,20 @@ LBM_HD void collide_cell(const T* p, const T* F, T omega, T* out, T* u) {
   }
 }
 
+// c * v for a lattice weight c given in double. In FP32, c is carried as hi + lo floats: a single
+// rounded weight is off by up to 3e-8 relative in one direction, and the transposed collision
+// would multiply the adjoint's density and momentum modes by that factor on every step (as the
+// forward collision does with its equilibrium, collide.hpp). FP64 keeps the plain product.
+template <typename T>
+LBM_HD T mul_weight_hd(double c, T v) {
+  if constexpr (sizeof(T) == 4) {
+    const float hi = (float)c, lo = (float)(c - (double)hi);
+    return fmaf(hi, v, lo * v);
+  } else {
+    return T(c) * v;
+  }
+}
+
 // Given lam = dL/d(out) and lamU = dL/du of one cell, returns mu = dL/dp, lamF = dL/dF and the
 // cell's share of dL/domega. With rho = 1 + sum p and u = (sum c p + F/2)/rho:
 //   mu_k = (1 - omega) lam_k + A + sum_a B_a (c_ka - u_a) / rho,
@@ -79,9 +93,17 @@ LBM_HD void collide_cell_adjoint(const T* p, const T* F, T omega, const T* lam, 
     const T geq = w * (drho + rho * base);
     const T X = T(3) * (cF - uF) + T(9) * cu * cF;
     const T l = lam[q];
-    A += l * w * (T(1) + base);
+    const double wd = q < 6 ? 1.0 / 18.0 : (q < 18 ? 1.0 / 36.0 : 1.0 / 3.0);
+    if constexpr (sizeof(T) == 4)
+      A += l * mul_weight_hd<T>(wd, T(1) + base);
+    else
+      A += l * w * (T(1) + base);
     for (int a = 0; a < 3; ++a) {
-      const T dgeq = w * rho * (T(3) * c[a] + T(9) * cu * c[a] - T(3) * u[a]);
+      T dgeq;
+      if constexpr (sizeof(T) == 4)
+        dgeq = mul_weight_hd<T>(wd, rho * (T(3) * c[a] + T(9) * cu * c[a] - T(3) * u[a]));
+      else
+        dgeq = w * rho * (T(3) * c[a] + T(9) * cu * c[a] - T(3) * u[a]);
       const T dS = pre * w * (T(-3) * F[a] + T(9) * c[a] * cF);
       B[a] += l * (omega * dgeq + dS);
       lf[a] += l * pre * w * (T(3) * (c[a] - u[a]) + T(9) * cu * c[a]);

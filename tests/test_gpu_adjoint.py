@@ -89,6 +89,65 @@ def test_adjoint_matches_oracle_gradient(precision):
     assert np.allclose(g, fd, rtol=tol, atol=tol * scale)
 
 
+def _shear(steps=150, u0=0.08):
+    """Two bubbles in a decaying shear flow u_x = u0 sin(pi (z + 1/2) / n_z) between bounce-back
+    plates, periodic sides, omega 1.9: the vorticity at the bubbles is large enough for the lift
+    force to move them measurably (dL/d lift_scale is about 2 % of dL/d drag_scale), so each
+    gradient component can be checked on its own. Returns the workload, the initial post-collision
+    populations (the equilibrium of the flow, from the oracle's eq. (6)) and velocity field."""
+    nx, ny, nz = 24, 24, 48
+    pos = np.array([[8.0, 15.0], [10.0, 13.0], [7.0, 10.0]])
+    w = W.Workload("adjoint_shear_24x24x48_2b", (nx, ny, nz), 1.9, (W.PER,) * 4 + (W.BB,) * 2, pos,
+                   np.array([3.0, 3.0]), W.params(g=1e-4, sigma=1e-4), steps, "f64",
+                   meta=dict(target=(1.1, 0.6, 1.88), theta0=(1.0, 1.0, 1.9)))
+    ux = u0 * np.sin(np.pi * (np.arange(nz) + 0.5) / nz)
+    _, wq, _ = O.lattice()
+    R = np.empty((19, nz, ny, nx))
+    for k in range(nz):
+        R[:, k] = (O.equilibrium(1.0, [ux[k], 0.0, 0.0]) - wq)[:, None, None]
+    U = np.zeros((3, nz, ny, nx))
+    U[0] = ux[:, None, None]
+    return w, R, U
+
+
+def _oracle_traj_from(w, theta, R, U):
+    sD, sL, om = theta
+    lat = O.Lattice(*w.shape, om, w.bc)
+    lat.g = O.stream(R, w.bc)  # the pre-collision state the post-collision buffer R streams into
+    lat.U = U.copy()
+    bub = O.Bubbles(pos=w.pos.copy(), d=w.d.copy())
+    p = dict(w.params)
+    p.update(drag_scale=sD, lift_scale=sL)
+    return O.run(lat, O.bubble_params(**p), bub, w.steps, record=True)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_adjoint_in_shear_flow_each_component_matches_oracle(precision):
+    """Every component of the gradient, lift included, against the oracle's central differences
+    (h = 1e-4: the omega component's O(h^2) error is 3.5e-4 relative at h = 1e-3) with a relative
+    bound of its own: 1e-4 in FP64, 2e-3 in FP32."""
+    w, R, U = _shear()
+    print(f"[case] {w.name} {precision}", flush=True)
+    h = 1e-4
+    th0 = np.array(w.meta["theta0"])
+    target_o = _oracle_traj_from(w, w.meta["target"], R, U)
+    lo = lambda th: float(np.sum((_oracle_traj_from(w, th, R, U) - target_o) ** 2))
+    fd = np.zeros(3)
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        fd[i] = (lo(th0 + e) - lo(th0 - e)) / (2 * h)
+    prob = A.TrajectoryProblem(w.shape, w.bc, w.pos, w.d, w.params, w.steps, precision=precision,
+                               checkpoint=40, init_state=R, init_vel=U)
+    L0, g = _adjoint_grad(prob, th0, torch.tensor(target_o, device="cuda"))
+    rel = np.abs(g - fd) / np.abs(fd)
+    print(f"{precision}: L = {L0:.6e} (oracle {lo(th0):.6e}), adjoint {g}, oracle FD {fd}, "
+          f"relative error per component {rel}", flush=True)
+    assert abs(fd[1]) > 1e-3 * np.abs(fd).max()  # lift carries weight here
+    assert np.all(rel <= (1e-4 if precision == "f64" else 2e-3)), rel
+
+
 @pytest.mark.gpu
 def test_adjoint_checkpoint_interval_does_not_change_the_gradient():
     w = _small(steps=90)
