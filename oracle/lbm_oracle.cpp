@@ -599,24 +599,47 @@ int orc_method_step(int nx, int ny, int nz, const int32_t* bc, double omega,
     Ui = Un.data();
   }
   const int point = (P->coupling & ORC_POINT_KERNEL) ? 1 : 0;
+  // Forward coupling and ODE of every bubble: each reads only the velocity field Ui and its own
+  // state, so the bubbles are independent here (threads over bubbles).
+  std::vector<double> x0s(3 * (size_t)nb), xns(3 * (size_t)nb), ubs(3 * (size_t)nb),
+      uls(3 * (size_t)nb), psis(3 * (size_t)nb);
+  std::vector<int> rcs(nb, 0);
+#pragma omp parallel for schedule(dynamic, 16)
   for (int b = 0; b < nb; ++b) {
     if (state[b] == 0) continue;
-    double x0[3] = {pos[b], pos[nb + b], pos[2 * nb + b]};
-    double ub[3] = {vel[b], vel[nb + b], vel[2 * nb + b]};
+    double* x0 = &x0s[3 * (size_t)b];
+    double* ub = &ubs[3 * (size_t)b];
+    double* ul = &uls[3 * (size_t)b];
+    double* xn = &xns[3 * (size_t)b];
+    double* psi = &psis[3 * (size_t)b];
+    for (int a = 0; a < 3; ++a) {
+      x0[a] = pos[a * nb + b];
+      ub[a] = vel[a * nb + b];
+    }
     const double n = P->kernel_factor * d[b];
-    double ul[3], wl[3], dul[3] = {0.0, 0.0, 0.0};
-    int rc = orc_interpolate(nx, ny, nz, bc, Ui, x0, n, ul, wl, point);
-    if (rc) return rc;
+    double wl[3], dul[3] = {0.0, 0.0, 0.0};
+    rcs[b] = orc_interpolate(nx, ny, nz, bc, Ui, x0, n, ul, wl, point);
+    if (rcs[b]) continue;
     if (state[b] == 2)
       for (int a = 0; a < 3; ++a) dul[a] = ul[a] - ulp[a * nb + b];  // / dt_l, dt_l = 1
-    double xn[3] = {x0[0], x0[1], x0[2]}, psi[3];
+    for (int a = 0; a < 3; ++a) xn[a] = x0[a];
     orc_bubble_ode(P, nu, dt_b, P->n_sub, d[b], ul, wl, dul, ub, xn, lo, hi, clo, chi, len, psi);
-    rc = orc_spread(nx, ny, nz, bc, x0, n, psi, F, point);
+  }
+  for (int b = 0; b < nb; ++b)
+    if (state[b] != 0 && rcs[b]) return rcs[b];
+  // Backward coupling in bubble order (each cell sums its bubbles' forces in that order), then
+  // the new bubble state.
+  for (int b = 0; b < nb; ++b) {
+    if (state[b] == 0) continue;
+    const double* x0 = &x0s[3 * (size_t)b];
+    const double* xn = &xns[3 * (size_t)b];
+    const double* psi = &psis[3 * (size_t)b];
+    const int rc = orc_spread(nx, ny, nz, bc, x0, P->kernel_factor * d[b], psi, F, point);
     if (rc) return rc;
     for (int a = 0; a < 3; ++a) {
       pos[a * nb + b] = xn[a];
-      vel[a * nb + b] = ub[a];
-      ulp[a * nb + b] = ul[a];
+      vel[a * nb + b] = ubs[3 * (size_t)b + a];
+      ulp[a * nb + b] = uls[3 * (size_t)b + a];
       if (psi_out) psi_out[a * nb + b] = psi[a];
     }
     state[b] = 2;

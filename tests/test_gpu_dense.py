@@ -1,7 +1,9 @@
 """The dense dispersed-flow workload at its full size (256 x 256 x 768 FP32 lattice, 20 000
 bubbles, lognormal diameters around 3, omega drawn in [1.2, 1.8]) in the launch configuration the
-benchmark uses: a few coupled steps compared with the oracle (all bubbles, a sample of cells), and
-properties that hold at any size (mass conservation, finiteness) over more steps."""
+benchmark uses (overlapped steps replayed from HIP graphs): a 100-step prefix compared with the
+oracle on the whole lattice and every bubble (by then the bubbles have reached their rise velocity
+and their wakes overlap), and properties that hold at any size (mass conservation, finiteness)
+over more steps."""
 import numpy as np
 import pytest
 import torch
@@ -11,39 +13,45 @@ import workloads as W
 from gpu_common import gpu_sim, oracle_state, rel_l2
 
 POS_TOL = 1e-4
+U_TOL = 2e-5
 
 
 @pytest.mark.gpu
+@pytest.mark.timeout(900)
 def test_dense_column_full_size_matches_oracle():
-    w = W.dense(steps=3)
-    print(f"[case] {w.name}: {w.cells} cells, {w.nb} bubbles, omega {w.omega:.4f}", flush=True)
+    w = W.dense(steps=100)
+    print(f"[case] {w.name}: {w.cells} cells, {w.nb} bubbles, omega {w.omega:.4f}, "
+          f"{w.steps} steps", flush=True)
     sim = gpu_sim(w)
-    sim.step(w.steps)
-    torch.cuda.synchronize()
-    g_gpu = sim.populations()
+    sim.run(w.steps, graph_steps=20)
+    _, u_gpu, sums = sim.moments()
+    u_gpu = u_gpu.double().cpu().numpy()
     pos_gpu = sim.bubbles.positions()
     vel_gpu = sim.bubbles.velocities()
     st_gpu = sim.bubbles.state()
-    _, _, sums = sim.moments(fields=False)
     sim.check()
-    rng = np.random.default_rng(99)
-    sample = rng.integers(0, w.cells, 200_000)
-    g_gpu = g_gpu.reshape(19, -1)[:, torch.from_numpy(sample).to(g_gpu.device)].double().cpu().numpy()
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    pos0 = w.pos.copy()
     lat, bub, P = oracle_state(w)
-    for _ in range(w.steps):
+    for k in range(w.steps):
         O.method_step(lat, P, bub)
-    print("oracle done", flush=True)
+        if (k + 1) % 20 == 0:
+            print(f"  oracle step {k + 1}", flush=True)
+    _, u_o, _ = lat.moments()
+    eu = rel_l2(u_gpu, u_o)
+    dx = np.abs(pos_gpu - bub.pos).max()
+    ev = rel_l2(vel_gpu, bub.vel)
+    rise = (bub.pos[2] - pos0[2]).mean()
+    print(f"u rel-L2 {eu:.3e}, max |dx_b| {dx:.2e}, u_b rel-L2 {ev:.2e}, mean rise {rise:.3f}",
+          flush=True)
     assert np.array_equal(st_gpu, bub.state)
-    assert np.abs(pos_gpu - bub.pos).max() <= POS_TOL
-    assert rel_l2(vel_gpu, bub.vel) <= 2e-5
-    g_o = lat.g.reshape(19, -1)[:, sample]
-    err = rel_l2(g_gpu, g_o)
-    print(f"sampled rel-L2(g) = {err:.3e}", flush=True)
-    assert err <= 2e-5
+    assert dx <= POS_TOL
+    assert ev <= U_TOL
+    assert eu <= U_TOL
     assert abs(sums[0] - w.cells) < 1e-3
+    assert rise > 0.002  # the bubbles rose (Stokes rise of a d = 3 bubble in 100 steps: about 0.005)
 
 
 @pytest.mark.gpu
