@@ -222,6 +222,7 @@ def bench_stability(args):
     batch.close()
     cells = sum(w.cells for w in ws)
     stable = [w.omega for w, f in zip(ws, first) if f is None]
+    swarm = swarm_map(stream)
     out = {
         "metric": METRIC, "value": round(cells * args.steps / elapsed / 1e6, 1), "unit": "MLUPS",
         "n_gpus": 1, "steps": args.steps, "warmup": 0,
@@ -233,8 +234,47 @@ def bench_stability(args):
                       "bubble_z_end": [None if not np.isfinite(v) else round(float(v), 3) for v in z],
                       "max_stable_omega": max(stable) if stable else None,
                       "check_every_steps": chunk},
+        "swarm_map": swarm,
     }
     print(json.dumps(out), flush=True)
+
+
+def swarm_map(stream, steps=3000, chunk=250):
+    """Stability map over omega and forcing (Sec. 4.3 with the forcing made strong): the App. A
+    column (30 x 30 x 90, free-slip top) holding swarms of 8 to 1024 bubbles at g = 3e-2, one
+    column per (omega, swarm size), 64 columns in one batch, FP32; a column is unstable once its
+    FP64 sums are not finite (checked every `chunk` steps)."""
+    import workloads as W
+    from paper_1710_07073_amd import sim as S
+
+    ws = W.stability_swarm(steps=steps)
+    cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d) for w in ws]
+    batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
+    first = [None] * len(ws)
+    t0 = time.perf_counter()
+    for done in range(chunk, steps + 1, chunk):
+        batch.run(chunk, graph_steps=chunk // 5 * 2)
+        _, diverged = batch.sums()
+        for k, dv in enumerate(diverged):
+            if dv and first[k] is None:
+                first[k] = done
+    elapsed = time.perf_counter() - t0
+    batch.close()
+    rows = {}
+    for w, f in zip(ws, first):
+        r = rows.setdefault(w.meta["nb"], {"stable": [], "unstable": {}})
+        if f is None:
+            r["stable"].append(w.omega)
+        else:
+            r["unstable"][str(w.omega)] = f
+    summary = {str(nb): {"max_stable_omega": max(r["stable"]) if r["stable"] else None,
+                         "min_unstable_omega": min(float(o) for o in r["unstable"]) if r["unstable"] else None,
+                         "first_unstable_step": r["unstable"]} for nb, r in rows.items()}
+    print(f"[stability] swarm map: {summary}", file=sys.stderr, flush=True)
+    return {"columns": len(ws), "lattice": [30, 30, 90], "g": W.SWARM_G, "steps": steps,
+            "check_every_steps": chunk, "omegas": list(W.SWARM_OMEGAS),
+            "swarm_sizes": list(W.SWARM_COUNTS), "by_swarm_size": summary,
+            "mlups": round(sum(w.cells for w in ws) * steps / elapsed / 1e6, 1)}
 
 
 # Table 6: the paper's terminal velocity (m/s), identical at all three aspect ratios

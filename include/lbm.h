@@ -221,7 +221,9 @@ lbm_status bubbles_step(lbm_ctx* ctx, const bubble_params* params, const bubble_
  * per cell (device buffers of N and 3 x N elements of the lattice type, each nullable), and
  * sums_out (host, 4 doubles, nullable) = (sum rho, sum rho u_x, sum rho u_y, sum rho u_z)
  * accumulated in double precision. With sums_out the call synchronises the stream and returns
- * LBM_EDIVERGED if a sum is not finite, or a pending kernel error. */
+ * LBM_EDIVERGED if a sum is not finite (the BGK step went unstable, Sec. 4.3; this takes precedence
+ * over the kernel error the bubbles of a diverged liquid then raise), else a pending kernel error
+ * (cleared, as by lbm_check()); sums_out is written in every case but LBM_EDEVICE. */
 lbm_status moments(lbm_ctx* ctx, void* rho_out, void* u_out, double* sums_out);
 
 /* Write the current pre-collision populations g = f - w (19 x N, lattice type, plain order

@@ -364,12 +364,14 @@ lbm_status moments(lbm_ctx* ctx, void* rho_out, void* u_out, double* sums_out) {
   double r[4];
   if (hipMemcpyAsync(r, ctx->result, sizeof(r), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
     return LBM_EDEVICE;
-  const lbm_status st = lbm_check(ctx);
-  if (st != LBM_OK) return st;
+  const lbm_status st = lbm_check(ctx);  // synchronises; reports and clears a kernel error
+  if (st == LBM_EDEVICE) return st;
   for (int k = 0; k < 4; ++k) sums_out[k] = r[k];
+  // a diverged liquid also gives its bubbles non-finite positions (a kernel error): the
+  // divergence is the cause and is what gets reported
   for (int k = 0; k < 4; ++k)
     if (!isfinite(r[k])) return LBM_EDIVERGED;
-  return LBM_OK;
+  return st;
 }
 
 lbm_status lbm_populations(lbm_ctx* ctx, void* out) {

@@ -162,6 +162,40 @@ def stability(steps=20000, omegas=STABILITY_OMEGAS):
                      np.array([col.d_b]), params(g=g, sigma=sigma), steps, "f32") for om in omegas]
 
 
+# gravity (lattice units) of the bubble swarms that drive the liquid hard enough for the BGK step
+# to go unstable near omega = 2: 32 swarm bubbles in 16 x 16 x 48 raise a plume of |u| ~ 0.25
+SWARM_G = 3e-2
+
+
+def swarm(nb=32, omega=1.995, shape=(16, 16, 48), g=SWARM_G, seed=5, bc=(BB,) * 6, steps=1000,
+          dtype="f64"):
+    """A swarm of nb bubbles, diameters uniform in [2, 3], placed uniformly in the lower 5/12 of
+    the column at least 3 cells from the side walls and the bottom. With g = 3e-2 their buoyancy
+    drives a plume fast enough (|u| ~ 0.2-0.4) that the BGK liquid loses stability as omega
+    approaches 2: the stability test of Sec. 4.3 with the forcing made strong."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    d = rng.uniform(2.0, 3.0, nb)
+    pos = np.stack([rng.uniform(3, nx - 4, nb), rng.uniform(3, ny - 4, nb),
+                    rng.uniform(3, nz * 5 / 12, nb)])
+    return Workload(f"swarm_{nx}x{ny}x{nz}_{nb}b_omega{omega}", tuple(shape), float(omega), tuple(bc),
+                    pos, d, params(g=g, sigma=sigma_for(g, 2.5)), steps, dtype,
+                    meta=dict(nb=nb))
+
+
+SWARM_OMEGAS = (1.95, 1.96, 1.97, 1.975, 1.98, 1.985, 1.99, 1.995)
+SWARM_COUNTS = (8, 16, 32, 64, 128, 256, 512, 1024)
+
+
+def stability_swarm(steps=3000, omegas=SWARM_OMEGAS, counts=SWARM_COUNTS):
+    """The stability map (Sec. 4.3) over omega and forcing: the App. A column (30 x 30 x 90,
+    bounce-back walls and bottom, free-slip top) holding a swarm of 8 to 1024 bubbles (the forcing
+    axis: one batch shares g, so the swarm size varies), one column per (omega, swarm size)."""
+    return [swarm(nb=n, omega=om, shape=(30, 30, 90), bc=(BB, BB, BB, BB, BB, FS), steps=steps,
+                  dtype="f32", seed=SEED + n)
+            for n in counts for om in omegas]
+
+
 GRID_CASES = ((0.004, 1.25), (0.004, 0.625), (0.004, 0.3125),
               (0.008, 1.25), (0.008, 0.625), (0.008, 0.3125),
               (0.010, 1.25), (0.010, 0.625), (0.010, 0.3125))
