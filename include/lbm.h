@@ -171,7 +171,7 @@ lbm_status lbm_set_step_occupancy(lbm_ctx* ctx, int32_t workgroups_per_cu);
 lbm_status lbm_get_step_occupancy(lbm_ctx* ctx, int32_t* workgroups_per_cu);
 lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* vec, int32_t* block_x);
 
-/* Overlap of the bubble kernels with the liquid step, available when every face is bounce-back,
+/* Overlap of the bubble kernels with the liquid step, available when no face is periodic,
  * the launch shape has one cell per thread and the population buffer is below 4 GiB; on by
  * default for lattices of 2^22 cells or more, where the liquid step outlasts the bubble kernels
  * (it costs a region launch and two cross-stream waits). With it,

@@ -128,8 +128,11 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   G.tnx = (int)L.tnx;
   G.tny = (int)L.tny;
   c->general = false;
-  for (int f = 0; f < 6; ++f)
+  c->periodic = false;
+  for (int f = 0; f < 6; ++f) {
     if (desc->bc[f] != LBM_BC_BOUNCE_BACK) c->general = true;
+    if (desc->bc[f] == LBM_BC_PERIODIC) c->periodic = true;
+  }
   c->elem = desc->precision == LBM_FP32_SHIFTED ? 4 : 8;
   c->pops[0] = pops_a;
   c->pops[1] = pops_b;

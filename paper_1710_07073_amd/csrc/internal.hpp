@@ -27,6 +27,7 @@ struct lbm_ctx {
   lbm_desc desc;
   lbm::Geom geom;
   bool general;     // any free-slip or periodic face
+  bool periodic;    // any periodic face
   size_t elem;      // 4 or 8
   void* pops[2];    // population buffers; pops[hs.cur] holds the current post-collision state
   void* force;

@@ -178,8 +178,8 @@ __global__ __launch_bounds__(256) void k_step(const T* __restrict__ src, T* __re
 }
 
 // The whole lattice (region == nullptr), or the bulk of an overlapped step: every cell whose tile
-// row is not in the region.
-template <typename T>
+// row is not in the region. No face periodic; FS: some face free slip.
+template <typename T, bool FS>
 __global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* __restrict__ dst,
                                                  T* __restrict__ F, T* __restrict__ U,
                                                  const uint8_t* __restrict__ tiles,
@@ -205,13 +205,14 @@ __global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* _
   if (!static_force) forced = tiles[tile] != 0;
   // the corner cell of each tile clears that tile in the mask of the next bubble step
   if (((x | y | (int)z) & 7) == 0) tiles_next[tile] = 0;
-  step_cell_bb<T>(src, dst, F, U, G, omega, flags, x, y, z, forced, __any(forced));
+  step_cell_bb<T, FS>(src, dst, F, U, G, omega, flags, x, y, z, forced, __any(forced),
+                      FS ? free_slip_faces(G) : 0u);
 }
 
 // The region of an overlapped step: the tile rows of its list, each cut into the same workgroups
 // as the bulk launch (bx by by cells of one z-plane). It runs after the bubble kernels, alongside
 // the bulk launch; it clears the flags of its rows.
-template <typename T>
+template <typename T, bool FS>
 __global__ __launch_bounds__(256) void k_region_bb(const T* __restrict__ src, T* __restrict__ dst,
                                                    T* __restrict__ F, T* __restrict__ U,
                                                    const uint8_t* __restrict__ tiles,
@@ -237,7 +238,8 @@ __global__ __launch_bounds__(256) void k_region_bb(const T* __restrict__ src, T*
       const uint32_t tile = ((z >> 3) * G.tny + ((uint32_t)y >> 3)) * G.tnx + ((uint32_t)x >> 3);
       const bool forced = tiles[tile] != 0;
       if (((x | y | (int)z) & 7) == 0) tiles_next[tile] = 0;
-      step_cell_bb<T>(src, dst, F, U, G, omega, flags, x, y, z, forced, __any(forced));
+      step_cell_bb<T, FS>(src, dst, F, U, G, omega, flags, x, y, z, forced, __any(forced),
+                          FS ? free_slip_faces(G) : 0u);
     }
     if (sub == 0 && threadIdx.x == 0 && threadIdx.y == 0) region[u] = 0u;
   }
@@ -251,8 +253,9 @@ hipError_t launch_typed(lbm_ctx* c, uint32_t bx) {
   const uint32_t nblocks = nbx * nby * (uint32_t)G.nz;
   const T* src = static_cast<const T*>(c->pops[c->hs.cur]);
   T* dst = static_cast<T*>(c->pops[c->hs.cur ^ 1]);
-  if (!GENERAL && VEC == 1 && bb_fast_ok(G, sizeof(T))) {
-    hipLaunchKernelGGL((k_step_bb<T>), dim3(nblocks), dim3(bx, by), step_lds(c), c->stream, src, dst,
+  if (VEC == 1 && !c->periodic && bb_fast_ok(G, sizeof(T))) {
+    // walls only: GENERAL then means some face is free slip
+    hipLaunchKernelGGL((k_step_bb<T, GENERAL>), dim3(nblocks), dim3(bx, by), step_lds(c), c->stream, src, dst,
                        static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
                        c->tiles[c->hs.flag_cur ^ 1], nullptr, G, (T)c->desc.omega, c->desc.flags,
                        nbx, nby);
@@ -284,13 +287,13 @@ hipError_t timed(lbm_ctx* c, hipStream_t s, F&& launch) {
   return e;
 }
 
-template <typename T>
+template <typename T, bool FS>
 hipError_t launch_bulk_typed(lbm_ctx* c) {
   const Geom& G = c->geom;
   const uint32_t bx = c->step_bx, by = 256 / bx;
   const uint32_t nbx = div_up(G.nx, bx), nby = div_up(G.ny, by);
   const uint32_t nblocks = nbx * nby * (uint32_t)G.nz;
-  hipLaunchKernelGGL((k_step_bb<T>), dim3(nblocks), dim3(bx, by), step_lds(c), c->stream,
+  hipLaunchKernelGGL((k_step_bb<T, FS>), dim3(nblocks), dim3(bx, by), step_lds(c), c->stream,
                      static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(c->pops[c->hs.cur ^ 1]),
                      static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
                      c->tiles[c->hs.flag_cur ^ 1], c->region[c->hs.rpar], G, (T)c->desc.omega,
@@ -298,7 +301,7 @@ hipError_t launch_bulk_typed(lbm_ctx* c) {
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool FS>
 hipError_t launch_region_typed(lbm_ctx* c, int32_t nb, hipStream_t stream) {
   const Geom& G = c->geom;
   const uint32_t bx = c->step_bx, by = 256 / bx;
@@ -308,7 +311,7 @@ hipError_t launch_region_typed(lbm_ctx* c, int32_t nb, hipStream_t stream) {
   const uint64_t rows = std::min<uint64_t>((uint64_t)nb * 16, c->nrows);
   const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(rows * per, 16384));
   const int r = c->hs.rpar;
-  hipLaunchKernelGGL((k_region_bb<T>), dim3(blocks), dim3(bx, by), step_lds(c), stream,
+  hipLaunchKernelGGL((k_region_bb<T, FS>), dim3(blocks), dim3(bx, by), step_lds(c), stream,
                      static_cast<const T*>(c->pops[c->hs.cur]), static_cast<T*>(c->pops[c->hs.cur ^ 1]),
                      static_cast<T*>(c->force), static_cast<T*>(c->vel), c->tiles[c->hs.flag_cur],
                      c->tiles[c->hs.flag_cur ^ 1], c->region[r], c->region_list[r], c->region_count + r,
@@ -320,12 +323,14 @@ hipError_t launch_region_typed(lbm_ctx* c, int32_t nb, hipStream_t stream) {
 }  // namespace
 
 bool can_overlap(const lbm_ctx* c) {
-  return c->side && !c->general && c->step_vec == 1 && bb_fast_ok(c->geom, c->elem);
+  return c->side && !c->periodic && c->step_vec == 1 && bb_fast_ok(c->geom, c->elem);
 }
 
 hipError_t launch_bulk(lbm_ctx* c) {
   return timed(c, c->stream, [&] {
-    return c->elem == 4 ? launch_bulk_typed<float>(c) : launch_bulk_typed<double>(c);
+    if (c->elem == 4)
+      return c->general ? launch_bulk_typed<float, true>(c) : launch_bulk_typed<float, false>(c);
+    return c->general ? launch_bulk_typed<double, true>(c) : launch_bulk_typed<double, false>(c);
   });
 }
 
@@ -336,8 +341,12 @@ hipError_t launch_step(lbm_ctx* c) {
     // for the bubble kernels; the region runs after the bulk, alone on the chip. (Launched on the
     // side stream right after the spread, beside the bulk, it slowed the bulk by more than it
     // saved: both measured on 128 x 128 x 512 with one bubble and with 20 000.)
-    e = c->elem == 4 ? launch_region_typed<float>(c, c->pending_nb, c->stream)
-                     : launch_region_typed<double>(c, c->pending_nb, c->stream);
+    if (c->elem == 4)
+      e = c->general ? launch_region_typed<float, true>(c, c->pending_nb, c->stream)
+                     : launch_region_typed<float, false>(c, c->pending_nb, c->stream);
+    else
+      e = c->general ? launch_region_typed<double, true>(c, c->pending_nb, c->stream)
+                     : launch_region_typed<double, false>(c, c->pending_nb, c->stream);
     if (e != hipSuccess) return e;
     c->hs.pending = false;
     c->hs.rpar ^= 1;

@@ -118,13 +118,17 @@ def test_poiseuille_on_gpu():
 @pytest.mark.parametrize("shape,bc", [
     ((128, 12, 10), (BB,) * 6),
     ((36, 10, 9), (BB, BB, BB, BB, BB, FS)),
+    ((30, 12, 10), (FS, BB, FS, BB, BB, FS)),  # free-slip faces meeting at edges
+    ((24, 8, 9), (FS,) * 6),
     ((40, 9, 11), (PER, PER, PER, PER, FS, FS)),
     ((64, 8, 8), (PER,) * 6),
     ((8, 6, 7), (BB, BB, PER, PER, BB, BB)),
 ])
 def test_every_launch_shape_gives_identical_results(prec, shape, bc):
     """The launch shape (cells per thread, workgroup width) and the occupancy cap are tuning knobs
-    only: every combination the autotuner may pick reproduces the reference launch bit for bit."""
+    only: every combination the autotuner may pick reproduces the reference launch bit for bit
+    (with walls only, one cell per thread runs the wall fast path, wider launches the general
+    kernel)."""
     from paper_1710_07073_amd import autotune
     R = W.random_populations(shape, 1e-3, seed=8)
     F = W.random_field(shape, 2e-5, seed=9)

@@ -12,10 +12,11 @@ from paper_1710_07073_amd import sim as S
 BB, FS, PER = 0, 1, 2
 
 
-def _run(shape, prec, pos, d, overlap, steps, graph_steps=0, vel=None, run=False, **pkw):
+def _run(shape, prec, pos, d, overlap, steps, graph_steps=0, vel=None, run=False, bc=(BB,) * 6,
+         **pkw):
     """steps method steps: through lbm_run (graph replay if graph_steps) or, unless run is set and
     graph_steps is 0, one bubbles_step + lbm_step pair at a time."""
-    sim = S.Simulation(shape, 1.35, precision=prec, bc=(BB,) * 6)
+    sim = S.Simulation(shape, 1.35, precision=prec, bc=bc)
     L.lbm_set_overlap(sim.ctx, overlap)
     sim.add_bubbles(pos, d, S.bubble_params(**pkw), vel=vel)
     if graph_steps or run:
@@ -89,8 +90,30 @@ def test_many_bubbles_overlapped_match_serial(graph_steps):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_overlap_with_the_papers_faces(prec):
+    """Bounce-back walls and bottom with a free-slip top (Sec. 3.3): the wall fast path overlaps
+    too, bit for bit the serial step, with bubbles rising into the top layer."""
+    shape = (40, 36, 30)
+    pos = np.array([[20.0, 8.0, 30.0], [18.0, 27.5, 9.0], [24.0, 28.7, 12.0]])
+    d = [3.0, 2.5, 4.0]
+    print(f"overlap vs serial, free-slip top {prec}", flush=True)
+    kw = dict(g=3e-3, sigma=1e-3)
+    bc = (BB, BB, BB, BB, BB, FS)
+    sim = S.Simulation(shape, 1.35, precision=prec, bc=bc)
+    assert L.lbm_get_overlap(sim.ctx) == (False, True)
+    sim.close()
+    a = _run(shape, prec, pos, d, False, 60, bc=bc, **kw)
+    b = _run(shape, prec, pos, d, True, 60, bc=bc, **kw)
+    _same(a, b)
+    c = _run(shape, prec, pos, d, True, 60, graph_steps=6, bc=bc, **kw)
+    _same(a, c)
+    assert (a["st"] == 0).any()  # a bubble reached the top layer
+
+
+@pytest.mark.gpu
 def test_overlap_unavailable_is_the_serial_step():
-    """Periodic or free-slip faces take the general step: no overlap, and asking for it is a no-op."""
+    """Periodic faces take the general step: no overlap, and asking for it is a no-op."""
     sim = S.Simulation((24, 24, 32), 1.2, precision="f32", bc=(PER, PER, PER, PER, BB, FS))
     L.lbm_set_overlap(sim.ctx, True)
     assert L.lbm_get_overlap(sim.ctx) == (True, False)
