@@ -29,6 +29,9 @@ struct lbm_batch {
   int flag_cur;     // current tile mask, same for all columns
   bool flag_clean[2];
   int32_t* status;
+  uint32_t* jobs;       // tile jobs of the deterministic spreading, two step parities
+  uint32_t* job_count;  // [2]
+  uint32_t job_cap;     // tiles of all columns: each is noted at most once per step
   double* partials;
   double* result;
   uint32_t nred;
@@ -202,9 +205,10 @@ bool column_ok(const lbm_column& c) {
 }
 
 struct BatchLayout {
-  std::vector<size_t> pops0, pops1, force, vel, tiles0, tiles1;
+  std::vector<size_t> pops0, pops1, force, vel, tiles0, tiles1, tcount, tlist;
   std::vector<uint32_t> ntiles;
-  size_t pool, table, bcol, partials, result, status, scratch;
+  size_t pool, table, bcol, jobs, job_count, partials, result, status, scratch;
+  uint32_t total_tiles;
   int32_t nb_total;
 };
 
@@ -234,7 +238,18 @@ bool layout_batch(const lbm_column* cols, int ncols, size_t elem, BatchLayout& L
     L.tiles1.push_back(tiles);
     tiles = align_up(tiles + nt);
   }
-  L.table = tiles;
+  // per-tile bubble lists of each column (counts zero between steps)
+  L.total_tiles = 0;
+  for (int c = 0; c < ncols; ++c) {
+    L.tcount.push_back(tiles);
+    tiles = align_up(tiles + (size_t)L.ntiles[c] * sizeof(uint32_t));
+    L.tlist.push_back(tiles);
+    tiles = align_up(tiles + (size_t)L.ntiles[c] * kTileCap * sizeof(uint32_t));
+    L.total_tiles += L.ntiles[c];
+  }
+  L.jobs = tiles;
+  L.job_count = align_up(L.jobs + (size_t)2 * L.total_tiles * 2 * sizeof(uint32_t));
+  L.table = align_up(L.job_count + 2 * sizeof(uint32_t));
   L.bcol = align_up(L.table + (size_t)ncols * sizeof(ColumnDev));
   L.partials = align_up(L.bcol + (size_t)(L.nb_total > 0 ? L.nb_total : 1) * sizeof(int32_t));
   const size_t nparts = std::max<size_t>(kRedBlocks, (size_t)ncols * kSumBlocks);
@@ -292,8 +307,15 @@ hipError_t batch_method_step(lbm_batch* b, const bubble_params* p, const bubble_
   }
   b->flag_clean[m] = false;
   b->flag_cur = m;
-  hipError_t e = launch_bubbles_batch(b->dev, b->bubble_col, m, b->elem, p, s, nb, b->status,
-                                      b->stream);
+  ManyColumns geo;
+  geo.cols = b->dev;
+  geo.bubble_col = b->bubble_col;
+  geo.flag = m;
+  geo.jobs = b->jobs;
+  geo.job_count = b->job_count;
+  geo.job_cap = b->job_cap;
+  geo.par = b->cur;  // alternates every step, like the tile jobs' lists
+  hipError_t e = launch_bubbles_batch(geo, b->elem, p, s, nb, b->status, b->stream);
   if (e != hipSuccess) return e;
   if (b->elem == 4)
     e = b->general ? batch_step_typed<float, true>(b) : batch_step_typed<float, false>(b);
@@ -368,6 +390,9 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
   b->partials = reinterpret_cast<double*>(S + L.partials);
   b->result = reinterpret_cast<double*>(S + L.result);
   b->status = reinterpret_cast<int32_t*>(S + L.status);
+  b->jobs = reinterpret_cast<uint32_t*>(S + L.jobs);
+  b->job_count = reinterpret_cast<uint32_t*>(S + L.job_count);
+  b->job_cap = L.total_tiles;
   b->nred = kRedBlocks;
   b->host.resize(ncols);
   std::vector<int32_t> bcol(L.nb_total > 0 ? L.nb_total : 1, 0);
@@ -397,6 +422,8 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
     D.U = P + L.vel[c];
     D.tiles[0] = S + L.tiles0[c];
     D.tiles[1] = S + L.tiles1[c];
+    D.tcount = reinterpret_cast<uint32_t*>(S + L.tcount[c]);
+    D.tlist = reinterpret_cast<uint32_t*>(S + L.tlist[c]);
     D.item_cells = default_item_cells(k);
     D.bubble_begin = k.bubble_begin;
     D.nb = k.nb;

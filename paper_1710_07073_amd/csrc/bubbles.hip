@@ -461,10 +461,13 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   __shared__ double s_red6[6][kBlockWaves];
   const int b = bubble_of_block(A.nb);
   const int tid = threadIdx.x;
-  if constexpr (std::is_same_v<Geo, OneColumn>) {
-    // in an overlapped step, the other parity's region list (its region launch ran before)
-    // starts empty
-    if (blockIdx.x == 0 && tid == 0 && geo.clear_count) *geo.clear_count = 0u;
+  if (blockIdx.x == 0 && tid == 0) {
+    if constexpr (std::is_same_v<Geo, OneColumn>) {
+      // in an overlapped step, the other parity's region list (its region launch ran before)
+      // starts empty
+      if (geo.clear_count) *geo.clear_count = 0u;
+    }
+    geo.clear_other_jobs();  // many columns: the next step's tile jobs start empty
   }
   const ColumnView<T> col = geo.template view<T>(b);
   const Geom& G = col.G;
@@ -518,20 +521,22 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
   // enter the bubble in the list of every tile of its force window: the slot of each thread's
   // first tile is taken now and written after the gather, so the atomic is in flight meanwhile
   uint32_t t0 = 0, slot0 = kTileCap;
-  if constexpr (std::is_same_v<Geo, OneColumn>) {
-    if (geo.lists) {
-      TileRanges tr[3];
-      force_tiles(G, win, tr);
-      const int nt = tile_count(tr);
-      if (tid < nt) {
-        t0 = nth_tile(G, tr, tid);
-        slot0 = atomicAdd(&geo.tcount[t0], 1u);
-      }
-      for (int k = tid + kBlock; k < nt; k += kBlock) {
-        const uint32_t t = nth_tile(G, tr, k);
-        const uint32_t slot = atomicAdd(&geo.tcount[t], 1u);
-        if (slot < kTileCap) geo.tlist[(size_t)t * kTileCap + slot] = (uint32_t)b;
-      }
+  uint32_t* const tcount = geo.tcount_of(b);
+  uint32_t* const tlist = geo.tlist_of(b);
+  if (geo.use_lists()) {
+    TileRanges tr[3];
+    force_tiles(G, win, tr);
+    const int nt = tile_count(tr);
+    if (tid < nt) {
+      t0 = nth_tile(G, tr, tid);
+      slot0 = atomicAdd(&tcount[t0], 1u);
+      if (slot0 == 0u) geo.note_tile(b, t0);
+    }
+    for (int k = tid + kBlock; k < nt; k += kBlock) {
+      const uint32_t t = nth_tile(G, tr, k);
+      const uint32_t slot = atomicAdd(&tcount[t], 1u);
+      if (slot == 0u) geo.note_tile(b, t);
+      if (slot < kTileCap) tlist[(size_t)t * kTileCap + slot] = (uint32_t)b;
     }
   }
   const int Dx = win[0].dhi - win[0].dlo + 1;
@@ -619,9 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
       }
     }
   }
-  if constexpr (std::is_same_v<Geo, OneColumn>) {
-    if (slot0 < kTileCap) geo.tlist[(size_t)t0 * kTileCap + slot0] = (uint32_t)b;
-  }
+  if (slot0 < kTileCap) tlist[(size_t)t0 * kTileCap + slot0] = (uint32_t)b;
   block_sum6(acc, s_red6, tid);
   if (tid == 0) {
     for (int m = 0; m < 6; ++m) work[W_UL + m] = acc[m];
@@ -872,15 +875,13 @@ __device__ bool ode_update(const Geo& geo, const BubbleArgs& A, int b, const Ode
     A.S.psiy[b] = psi[1];
     A.S.psiz[b] = psi[2];
   }
-  if constexpr (std::is_same_v<Geo, OneColumn>) {
-    if (geo.lists) {  // the spreading gathers per tile: the tiles are flagged by the wavefront
-      for (int a = 0; a < 3; ++a) {
-        x0[a] = x0_in ? x0_in[a] : work[W_X0 + a];
-        xn_out[a] = xn[a];
-      }
-      n_out = P.kernel_factor * d;
-      return true;
+  if (geo.use_lists()) {  // the spreading gathers per tile: the tiles are flagged by the wavefront
+    for (int a = 0; a < 3; ++a) {
+      x0[a] = x0_in ? x0_in[a] : work[W_X0 + a];
+      xn_out[a] = xn[a];
     }
+    n_out = P.kernel_factor * d;
+    return true;
   }
   return false;
 }
@@ -897,30 +898,29 @@ __global__ __launch_bounds__(64) void k_ode(Geo geo, BubbleArgs A) {
   const int b = blockIdx.x * 64 + threadIdx.x;
   double x0[3] = {0.0, 0.0, 0.0}, xn[3] = {0.0, 0.0, 0.0}, n = 0.0;
   const bool flag = b < A.nb && ode_lane(geo, A, b, x0, xn, n);
-  if constexpr (std::is_same_v<Geo, OneColumn>) {
-    if (!geo.lists) return;
-    const ColumnView<float> col = geo.template view<float>(0);
-    const int lane = threadIdx.x;
-    uint64_t todo = __ballot(flag);
-    if (__popcll(todo) > kWaveFlagMaxBubbles) {
-      Axis win[3];
-      if (flag && force_windows(col.G, x0, n, win)) mark_tiles<float>(col, A, win, xn, n, 0, 1);
-      return;
+  if (!geo.use_lists()) return;
+  const int lane = threadIdx.x;
+  uint64_t todo = __ballot(flag);
+  if (__popcll(todo) > kWaveFlagMaxBubbles) {
+    Axis win[3];
+    if (flag) {
+      const ColumnView<float> col = geo.template view<float>(b);
+      if (force_windows(col.G, x0, n, win)) mark_tiles<float>(col, A, win, xn, n, 0, 1);
     }
-    while (todo) {
-      const int l = __ffsll((unsigned long long)todo) - 1;
-      todo &= todo - 1;
-      double y0[3], yn[3];
-      for (int a = 0; a < 3; ++a) {
-        y0[a] = __shfl(x0[a], l, 64);
-        yn[a] = __shfl(xn[a], l, 64);
-      }
-      const double m = __shfl(n, l, 64);
-      Axis win[3];
-      if (force_windows(col.G, y0, m, win)) mark_tiles<float>(col, A, win, yn, m, lane, 64);
+    return;
+  }
+  while (todo) {
+    const int l = __ffsll((unsigned long long)todo) - 1;
+    todo &= todo - 1;
+    double y0[3], yn[3];
+    for (int a = 0; a < 3; ++a) {
+      y0[a] = __shfl(x0[a], l, 64);
+      yn[a] = __shfl(xn[a], l, 64);
     }
-  } else {
-    (void)flag;
+    const double m = __shfl(n, l, 64);
+    const ColumnView<float> col = geo.template view<float>((int)(blockIdx.x * 64) + l);
+    Axis win[3];
+    if (force_windows(col.G, y0, m, win)) mark_tiles<float>(col, A, win, yn, m, lane, 64);
   }
 }
 
@@ -1001,110 +1001,147 @@ __device__ __forceinline__ bool in_tile_ranges(const TileRanges& r, int t) {
   return (r.n > 0 && t >= r.lo[0] && t <= r.hi[0]) || (r.n > 1 && t >= r.lo[1] && t <= r.hi[1]);
 }
 
+// One tile's share of the gather: the tile t of a lattice G with force field F, its list (tcount,
+// tlist) and the bubbles [b0, b1) that may cover it (the overflow scan's range).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spread_gather(OneColumn geo, BubbleArgs A) {
+struct GatherJob {
+  Geom G;
+  T* F;
+  uint32_t* tcount;
+  const uint32_t* tlist;
+  uint32_t t;
+  int b0, b1;
+};
+
+// Jobs of the gather. One lattice: every tile, one per workgroup (an empty list returns at once).
+// Many columns: the (column, tile) pairs noted this step, over the workgroups in turn.
+__device__ __forceinline__ uint32_t gather_jobs(const OneColumn&) { return gridDim.x; }
+__device__ __forceinline__ uint32_t gather_jobs(const ManyColumns& geo) {
+  return min(geo.job_count[geo.par], geo.job_cap);
+}
+template <typename T>
+__device__ __forceinline__ GatherJob<T> gather_job(const OneColumn& geo, const BubbleArgs& A,
+                                                   uint32_t j) {
+  return {geo.G, static_cast<T*>(geo.F), geo.tcount, geo.tlist, j, 0, A.nb};
+}
+template <typename T>
+__device__ __forceinline__ GatherJob<T> gather_job(const ManyColumns& geo, const BubbleArgs&,
+                                                   uint32_t j) {
+  const uint32_t* e = geo.jobs + 2 * ((size_t)geo.par * geo.job_cap + j);
+  const ColumnDev& C = geo.cols[e[0]];
+  return {C.G, static_cast<T*>(C.F), C.tcount, C.tlist, e[1], C.bubble_begin,
+          C.bubble_begin + C.nb};
+}
+
+template <typename T, typename Geo>
+__global__ __launch_bounds__(kBlock) void k_spread_gather(Geo geo, BubbleArgs A) {
   static_assert(kTileCap == 64, "one wavefront compacts a chunk of the overflow scan");
   __shared__ uint32_t s_list[kTileCap];
   __shared__ uint32_t s_sorted[kTileCap];
   __shared__ Axis s_win[kTileCap][3];
   __shared__ double s_psi[kTileCap][3];
   __shared__ uint32_t s_n;
-  const uint32_t t = blockIdx.x;
   const int tid = threadIdx.x;
-  const Geom& G = geo.G;
-  const uint32_t cnt = geo.tcount[t];
-  if (cnt == 0u) return;
-  const uint32_t tx = t % (uint32_t)G.tnx, rr = t / (uint32_t)G.tnx;
-  const uint32_t ty = rr % (uint32_t)G.tny, tz = rr / (uint32_t)G.tny;
-  const int x = (int)(tx * kTile + (tid & 7)), y = (int)(ty * kTile + ((tid >> 3) & 7));
-  const int z0 = (int)(tz * kTile + (tid >> 6));
-  const bool inside = x < G.nx && y < G.ny;
-  const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
-  // bubble b's force window and reaction into slot k of the staged chunk
-  auto stage = [&](uint32_t b, int k) {
-    const double* work = A.S.work + (size_t)b * kWork;
-    const double xb[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
-    Axis win[3];
-    force_windows(G, xb, A.P.kernel_factor * A.S.d[b], win);  // valid: the bubble was listed
-    for (int a = 0; a < 3; ++a) {
-      s_win[k][a] = win[a];
-      s_psi[k][a] = work[W_PSI + a];
-    }
-  };
-  double acc[2][3] = {{0, 0, 0}, {0, 0, 0}};
-  // adds the terms of the n staged bubbles s_sorted[0..n), in that order
-  auto add = [&](uint32_t n) {
-    if (!inside) return;
-    for (uint32_t k = 0; k < n; ++k) {
-      const double* wk = A.S.work + (size_t)s_sorted[k] * kWork + W_WGT;
-      const double wx = axis_weight_at(s_win[k][0], wk, x, G.nx, px);
-      const double wy = axis_weight_at(s_win[k][1], wk + kSpan, y, G.ny, py);
-      for (int h = 0; h < 2; ++h) {
-        const double wz = axis_weight_at(s_win[k][2], wk + 2 * kSpan, z0 + 4 * h, G.nz, pz);
-        const double W = wx * wy * wz;
-        for (int q = 0; q < 3; ++q) acc[h][q] += s_psi[k][q] * W;
+  const uint32_t njobs = gather_jobs(geo);
+  for (uint32_t j = blockIdx.x; j < njobs; j += gridDim.x) {
+    const GatherJob<T> J = gather_job<T>(geo, A, j);
+    const Geom& G = J.G;
+    const uint32_t t = J.t;
+    const uint32_t cnt = J.tcount[t];
+    if (cnt == 0u) continue;  // uniform over the workgroup
+    const uint32_t tx = t % (uint32_t)G.tnx, rr = t / (uint32_t)G.tnx;
+    const uint32_t ty = rr % (uint32_t)G.tny, tz = rr / (uint32_t)G.tny;
+    const int x = (int)(tx * kTile + (tid & 7)), y = (int)(ty * kTile + ((tid >> 3) & 7));
+    const int z0 = (int)(tz * kTile + (tid >> 6));
+    const bool inside = x < G.nx && y < G.ny;
+    const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
+    // bubble b's force window and reaction into slot k of the staged chunk
+    auto stage = [&](uint32_t b, int k) {
+      const double* work = A.S.work + (size_t)b * kWork;
+      const double xb[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+      Axis win[3];
+      force_windows(G, xb, A.P.kernel_factor * A.S.d[b], win);  // valid: the bubble was listed
+      for (int a = 0; a < 3; ++a) {
+        s_win[k][a] = win[a];
+        s_psi[k][a] = work[W_PSI + a];
       }
-    }
-  };
-  if (cnt <= kTileCap) {
-    const uint32_t n = cnt;
-    if (tid < (int)n) s_list[tid] = geo.tlist[(size_t)t * kTileCap + tid];
-    __syncthreads();
-    if (tid < (int)n) {  // rank sort (ties, which the lists do not hold, would keep list order)
-      const uint32_t v = s_list[tid];
-      uint32_t r = 0;
-      for (uint32_t j = 0; j < n; ++j) r += (s_list[j] < v || (s_list[j] == v && j < (uint32_t)tid)) ? 1u : 0u;
-      s_sorted[r] = v;
-    }
-    __syncthreads();
-    if (tid < (int)n) stage(s_sorted[tid], tid);
-    __syncthreads();
-    add(n);
-  } else {
-    // the list overflowed: every bubble whose force window holds this tile, by a scan of all
-    // bubbles in index order, one chunk of 64 per pass compacted by the first wavefront
-    for (int base = 0; base < A.nb; base += kTileCap) {
-      if (tid < kTileCap) {
-        const int b = base + tid;
-        bool cov = false;
-        if (b < A.nb) {
-          const double* work = A.S.work + (size_t)b * kWork;
-          if (work[W_VALID] != 0.0) {
-            const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
-            Axis win[3];
-            if (force_windows(G, x0, A.P.kernel_factor * A.S.d[b], win)) {
-              TileRanges tr[3];
-              force_tiles(G, win, tr);
-              cov = in_tile_ranges(tr[0], (int)tx) && in_tile_ranges(tr[1], (int)ty) &&
-                    in_tile_ranges(tr[2], (int)tz);
+    };
+    double acc[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    // adds the terms of the n staged bubbles s_sorted[0..n), in that order
+    auto add = [&](uint32_t n) {
+      if (!inside) return;
+      for (uint32_t k = 0; k < n; ++k) {
+        const double* wk = A.S.work + (size_t)s_sorted[k] * kWork + W_WGT;
+        const double wx = axis_weight_at(s_win[k][0], wk, x, G.nx, px);
+        const double wy = axis_weight_at(s_win[k][1], wk + kSpan, y, G.ny, py);
+        for (int h = 0; h < 2; ++h) {
+          const double wz = axis_weight_at(s_win[k][2], wk + 2 * kSpan, z0 + 4 * h, G.nz, pz);
+          const double W = wx * wy * wz;
+          for (int q = 0; q < 3; ++q) acc[h][q] += s_psi[k][q] * W;
+        }
+      }
+    };
+    if (cnt <= kTileCap) {
+      const uint32_t n = cnt;
+      if (tid < (int)n) s_list[tid] = J.tlist[(size_t)t * kTileCap + tid];
+      __syncthreads();
+      if (tid < (int)n) {  // rank sort (ties, which the lists do not hold, would keep list order)
+        const uint32_t v = s_list[tid];
+        uint32_t r = 0;
+        for (uint32_t i = 0; i < n; ++i) r += (s_list[i] < v || (s_list[i] == v && i < (uint32_t)tid)) ? 1u : 0u;
+        s_sorted[r] = v;
+      }
+      __syncthreads();
+      if (tid < (int)n) stage(s_sorted[tid], tid);
+      __syncthreads();
+      add(n);
+    } else {
+      // the list overflowed: every bubble whose force window holds this tile, by a scan of the
+      // lattice's bubbles in index order, one chunk of 64 per pass compacted by the first wavefront
+      for (int base = J.b0; base < J.b1; base += kTileCap) {
+        if (tid < kTileCap) {
+          const int b = base + tid;
+          bool cov = false;
+          if (b < J.b1) {
+            const double* work = A.S.work + (size_t)b * kWork;
+            if (work[W_VALID] != 0.0) {
+              const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+              Axis win[3];
+              if (force_windows(G, x0, A.P.kernel_factor * A.S.d[b], win)) {
+                TileRanges tr[3];
+                force_tiles(G, win, tr);
+                cov = in_tile_ranges(tr[0], (int)tx) && in_tile_ranges(tr[1], (int)ty) &&
+                      in_tile_ranges(tr[2], (int)tz);
+              }
             }
           }
+          const uint64_t m = __ballot(cov);
+          if (cov) {
+            const int k = __popcll(m & ((1ull << tid) - 1ull));
+            s_sorted[k] = (uint32_t)b;
+            stage((uint32_t)b, k);
+          }
+          if (tid == 0) s_n = (uint32_t)__popcll(m);
         }
-        const uint64_t m = __ballot(cov);
-        if (cov) {
-          const int k = __popcll(m & ((1ull << tid) - 1ull));
-          s_sorted[k] = (uint32_t)b;
-          stage((uint32_t)b, k);
-        }
-        if (tid == 0) s_n = (uint32_t)__popcll(m);
+        __syncthreads();
+        add(s_n);
+        __syncthreads();
       }
-      __syncthreads();
-      add(s_n);
-      __syncthreads();
     }
-  }
-  if (inside) {
-    T* __restrict__ F = static_cast<T*>(geo.F);
-    for (int h = 0; h < 2; ++h) {
-      const int z = z0 + 4 * h;
-      if (z >= G.nz) continue;
-      const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
-      F[c] = (T)acc[h][0];
-      F[G.N + c] = (T)acc[h][1];
-      F[2 * (size_t)G.N + c] = (T)acc[h][2];
+    if (inside) {
+      for (int h = 0; h < 2; ++h) {
+        const int z = z0 + 4 * h;
+        if (z >= G.nz) continue;
+        const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
+        J.F[c] = (T)acc[h][0];
+        J.F[G.N + c] = (T)acc[h][1];
+        J.F[2 * (size_t)G.N + c] = (T)acc[h][2];
+      }
     }
+    // every thread has read the count and the shared arrays: the next job may reuse them
+    __syncthreads();
+    if (tid == 0) J.tcount[t] = 0u;
   }
-  if (tid == 0) geo.tcount[t] = 0u;
 }
 
 // Region of an overlapped step (one wavefront per bubble): the tile rows (y, z) of the bubble's
@@ -1144,6 +1181,9 @@ __global__ __launch_bounds__(64) void k_mark(Geo geo, BubbleArgs A, uint32_t* __
       }
     }
 }
+
+// Workgroups of the many-column gather (each takes the noted tiles in turn).
+constexpr uint32_t kGatherMaxBlocks = 2048;
 
 // Bubble counts up to which k_interp keeps 8 cells' loads in flight per thread: one workgroup per
 // bubble, at 108 VGPRs four of them per compute unit, 1024 on the chip.
@@ -1186,12 +1226,19 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
     }
     if (geo.lists) {  // several bubbles: the lists k_interp filled, summed per tile
       const uint32_t ntiles = (uint32_t)geo.G.tnx * geo.G.tny * div_up(geo.G.nz, kTile);
-      hipLaunchKernelGGL((k_spread_gather<T>), dim3(ntiles), dim3(kBlock), 0, stream, geo, A);
+      hipLaunchKernelGGL((k_spread_gather<T, OneColumn>), dim3(ntiles), dim3(kBlock), 0, stream,
+                         geo, A);
       return hipGetLastError();
     }
+    hipLaunchKernelGGL((k_spread<T, Geo>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+    return hipGetLastError();
+  } else {
+    // many columns: the tiles noted this step, gathered by the workgroups in turn
+    const uint32_t blocks = std::max(1u, std::min(geo.job_cap, kGatherMaxBlocks));
+    hipLaunchKernelGGL((k_spread_gather<T, ManyColumns>), dim3(blocks), dim3(kBlock), 0, stream,
+                       geo, A);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_spread<T, Geo>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
-  return hipGetLastError();
 }
 
 }  // namespace
@@ -1268,9 +1315,9 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
   return launch_bubble_kernels<double>(geo, A, c->stream);
 }
 
-hipError_t launch_bubbles_batch(const ColumnDev* cols, const int32_t* bubble_col, int flag,
-                                size_t elem, const bubble_params* p, const bubble_soa* s,
-                                int32_t nb, int32_t* status, hipStream_t stream) {
+hipError_t launch_bubbles_batch(const ManyColumns& geo, size_t elem, const bubble_params* p,
+                                const bubble_soa* s, int32_t nb, int32_t* status,
+                                hipStream_t stream) {
   if (nb == 0) return hipSuccess;
   BubbleArgs A;
   A.P = *p;
@@ -1278,10 +1325,6 @@ hipError_t launch_bubbles_batch(const ColumnDev* cols, const int32_t* bubble_col
   A.nb = nb;
   A.status = status;
   A.rec = nullptr;
-  ManyColumns geo;
-  geo.cols = cols;
-  geo.bubble_col = bubble_col;
-  geo.flag = flag;
   if (elem == 4) return launch_bubble_kernels<float>(geo, A, stream);
   return launch_bubble_kernels<double>(geo, A, stream);
 }

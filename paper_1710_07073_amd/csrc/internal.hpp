@@ -115,6 +115,13 @@ struct OneColumn {
   __device__ ColumnView<T> view(int) const {
     return {G, static_cast<const T*>(U), static_cast<T*>(F), tiles, nu, region};
   }
+  // the deterministic spreading: per-tile lists of this lattice (every tile is gathered, so the
+  // tiles entered need no note)
+  __device__ bool use_lists() const { return lists; }
+  __device__ uint32_t* tcount_of(int) const { return tcount; }
+  __device__ uint32_t* tlist_of(int) const { return tlist; }
+  __device__ void note_tile(int, uint32_t) const {}
+  __device__ void clear_other_jobs() const {}
 };
 
 // One column of a batch, in device memory: geometry, relaxation rate, buffers, and its share of
@@ -131,18 +138,41 @@ struct ColumnDev {
   uint32_t item_cells;  // cells per work item
   int32_t bubble_begin, nb;
   int32_t pad;
+  // per-tile bubble lists of the deterministic spreading (kTileCap entries per tile)
+  uint32_t* tcount;
+  uint32_t* tlist;
 };
 
-// Many columns: each bubble's column comes from a per-bubble index.
+// Many columns: each bubble's column comes from a per-bubble index. The spreading gathers in
+// bubble order per tile from each column's lists; the tiles entered in a step are noted as jobs
+// (column, tile) for the gather, in a list per step parity (par): each step's first bubble kernel
+// empties the other parity's list, which the next step fills.
 struct ManyColumns {
   const ColumnDev* cols;
   const int32_t* bubble_col;
   int flag;
+  uint32_t* jobs;       // [2][job_cap][2]: (column, tile)
+  uint32_t* job_count;  // [2]
+  uint32_t job_cap;
+  int par;
   template <typename T>
   __device__ ColumnView<T> view(int b) const {
     const ColumnDev& c = cols[bubble_col[b]];
     return {c.G, static_cast<const T*>(c.U), static_cast<T*>(c.F), c.tiles[flag], c.nu, nullptr};
   }
+  __device__ bool use_lists() const { return true; }
+  __device__ uint32_t* tcount_of(int b) const { return cols[bubble_col[b]].tcount; }
+  __device__ uint32_t* tlist_of(int b) const { return cols[bubble_col[b]].tlist; }
+  // tile t of bubble b's column received its first bubble of the step
+  __device__ void note_tile(int b, uint32_t t) const {
+    const uint32_t i = atomicAdd(&job_count[par], 1u);
+    if (i < job_cap) {
+      uint32_t* j = jobs + 2 * ((size_t)par * job_cap + i);
+      j[0] = (uint32_t)bubble_col[b];
+      j[1] = t;
+    }
+  }
+  __device__ void clear_other_jobs() const { job_count[par ^ 1] = 0u; }
 };
 
 constexpr uint32_t kTile = 8;
@@ -194,9 +224,9 @@ hipError_t launch_bulk(lbm_ctx* c);
 // bubble update, on the side stream
 hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb,
                           bool overlap, bool mark_ahead);
-hipError_t launch_bubbles_batch(const ColumnDev* cols, const int32_t* bubble_col, int flag,
-                                size_t elem, const bubble_params* p, const bubble_soa* s,
-                                int32_t nb, int32_t* status, hipStream_t stream);
+hipError_t launch_bubbles_batch(const ManyColumns& geo, size_t elem, const bubble_params* p,
+                                const bubble_soa* s, int32_t nb, int32_t* status,
+                                hipStream_t stream);
 // moments.hip
 hipError_t launch_moments(lbm_ctx* c, void* rho, void* u, bool sums);
 hipError_t launch_populations(lbm_ctx* c, void* out);

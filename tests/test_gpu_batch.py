@@ -63,6 +63,64 @@ def test_batch_columns_match_single_lattice_runs(prec):
     batch.close()
 
 
+def _crowded_columns(seed=31, nb=6):
+    """Columns whose bubbles sit close together (overlapping windows), one of each face set."""
+    rng = np.random.default_rng(seed)
+    specs = [((24, 30, 50), 0.9, (BB,) * 6), ((33, 33, 70), 1.5, (BB, BB, BB, BB, BB, FS)),
+             ((20, 28, 44), 1.2, (PER, PER, PER, PER, BB, BB))]
+    cols = []
+    for shape, omega, bc in specs:
+        nx, ny, nz = shape
+        d = rng.uniform(2.0, 3.5, nb)
+        pos = np.stack([rng.uniform(nx / 2 - 3, nx / 2 + 3, nb), rng.uniform(ny / 2 - 3, ny / 2 + 3, nb),
+                        rng.uniform(6, 14, nb)])
+        cols.append(dict(shape=shape, omega=omega, bc=bc, pos=pos, d=d))
+    return cols
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_is_bitwise_identical_to_single_lattice_runs(prec):
+    """Each cell sums its bubbles' forces in bubble order in the batch as on a single lattice, so a
+    column of crowded bubbles reproduces its own single-lattice run bit for bit."""
+    cols = _crowded_columns()
+    print(f"[case] crowded batch {prec}", flush=True)
+    batch = S.Batch(cols, S.bubble_params(**_params()), precision=prec)
+    steps = 30
+    batch.step(10)
+    batch.run(steps - 10, graph_steps=10)
+    pos = batch.bubbles.positions()
+    for c, col in enumerate(cols):
+        g_ref, pos_ref = _single(col, prec, steps)
+        b0, b1 = batch.bubble_range(c)
+        assert np.array_equal(batch.populations(c).double().cpu().numpy(), g_ref), c
+        assert np.array_equal(pos[:, b0:b1], pos_ref), c
+        assert np.abs(pos_ref[2] - col["pos"][2]).max() > 1e-3  # the bubbles moved
+    batch.check()
+    batch.close()
+
+
+@pytest.mark.gpu
+def test_batched_sweep_rerun_is_bitwise_identical():
+    """The 64-column sweep (1-8 bubbles per column, 50 M sites) run twice: same bits everywhere."""
+    ws = W.batched()
+    cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d) for w in ws]
+    print(f"[case] batched sweep rerun: {len(cols)} columns", flush=True)
+    runs = []
+    for _ in range(2):
+        b = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32")
+        b.run(40, graph_steps=20)
+        torch.cuda.synchronize()
+        runs.append(b)
+    a, b = runs
+    assert np.array_equal(a.bubbles.positions(), b.bubbles.positions())
+    for c in range(len(cols)):
+        assert torch.equal(a.populations(c), b.populations(c)), c
+    for r in runs:
+        r.check()
+        r.close()
+
+
 @pytest.mark.gpu
 def test_batch_columns_match_oracle():
     cols = _columns(seed=22, nb_max=2)[:3]
@@ -83,9 +141,8 @@ def test_batch_columns_match_oracle():
 
 @pytest.mark.gpu
 def test_batch_item_sizes_are_bit_identical():
-    """Item sizes and the occupancy cap are tuning knobs only (one bubble per column, so no two
-    force additions meet in a cell and the force field has one order)."""
-    cols = [dict(c, pos=c["pos"][:, :1], d=c["d"][:1]) for c in _columns(seed=23)]
+    """Item sizes and the occupancy cap are tuning knobs only."""
+    cols = _crowded_columns(seed=23)
     ref = None
     for items, occ in ((256, 3), (1024, 0), (4096, 2), (256, 0)):
         batch = S.Batch(cols, S.bubble_params(**_params()), precision="f32")
