@@ -31,8 +31,8 @@ def candidates(nx):
             continue
         per_row = nx // vec
         for bx in (16, 32, 64, 128, 256):
-            if bx > 2 * per_row and bx > 64:
-                continue  # mostly idle lanes
+            if bx > 16 and bx > per_row and bx // 2 >= per_row:
+                continue  # half the workgroup or more would idle past the end of the row
             out.append((vec, bx))
     return out
 
@@ -115,6 +115,29 @@ def tune(sim, steps=20, use_cache=True, verbose=False):
     db[key] = entry
     _save(db)
     return vec, bx, entry
+
+
+def tune_method_occupancy(sim, steps=8, caps=OCCUPANCY):
+    """The occupancy cap timed on whole method steps (bubble half and liquid step, overlapped where
+    the lattice overlaps) rather than on the liquid step alone: beside the bubble kernels the best
+    cap can differ. Applies the fastest and returns (cap, [[cap, us per step]], method steps run).
+    The simulation advances by len(caps) * (steps + 2) steps (callers count them as warm-up)."""
+    stream = sim.stream
+    bub = sim.bubbles
+    sweep = []
+    for occ in caps:
+        L.lbm_set_step_occupancy(sim.ctx, occ)
+        L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, 2, 0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, steps, 0)
+        e1.record(stream)
+        e1.synchronize()
+        sweep.append([occ, e0.elapsed_time(e1) * 1e3 / steps])
+    best = min(sweep, key=lambda r: r[1])[0]
+    L.lbm_set_step_occupancy(sim.ctx, best)
+    return best, sweep, len(caps) * (steps + 2)
 
 
 # ---------------------------------------------------------------------------------------------

@@ -12,16 +12,20 @@
 
 #include "collide.hpp"
 #include "graph.hpp"
+#include "step_cell.hpp"
 
 struct lbm_batch {
   int ncols;
   int32_t precision;
   size_t elem;
   bool general;
+  int faces;  // FACES_* of the liquid kernel
   int flags;
   std::vector<lbm_column> cols;       // as given
   std::vector<lbm::ColumnDev> host;   // device-side table, host copy
   lbm::ColumnDev* dev;                // device table (scratch)
+  std::vector<uint32_t> item_col;     // column of each work item, host copy
+  uint32_t* item_col_dev;             // the same (scratch), room for items of 256 cells
   int32_t* bubble_col;                // bubble -> column (scratch)
   int32_t nb_total;
   uint32_t nitems;
@@ -50,79 +54,102 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 constexpr uint32_t kSumBlocks = 16;  // workgroups per column of the per-column sums
 
-// Exact x = cell % nx, y = (cell / nx) % ny, z = cell / (nx ny) for cell < 2^31, through a
-// double-precision reciprocal and one correction step each.
-__device__ __forceinline__ uint32_t div_exact(uint32_t a, uint32_t d, double inv) {
-  uint32_t q = (uint32_t)((double)a * inv);
+// q = a / d for a < 2^24 with rd the float nearest to 1 / d: the float quotient is off by at most
+// one, which one correction in each direction removes.
+__device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t d, float rd) {
+  uint32_t q = (uint32_t)((float)a * rd);
   if (q * d > a) --q;
   if ((q + 1) * d <= a) ++q;
   return q;
 }
 
-template <typename T, bool GENERAL>
-__global__ __launch_bounds__(256) void k_batch_step(const ColumnDev* __restrict__ cols, int ncols,
+// The general pull (any face rule) from a global pointer.
+template <typename T, int... Qs>
+__device__ __forceinline__ void pull_all_g(T* g, const gmem<T>* src, const Geom& G, uint32_t lc,
+                                           const CellNbr& nb, std::integer_sequence<int, Qs...>) {
+  ((g[Qs] = src[pull_index<Qs, true>(G, lc, nb)]), ...);
+}
+
+// Faces of a batch (the liquid kernel's template parameter): every face of every column
+// bounce-back, walls only (bounce-back or free slip), or some face periodic.
+enum : int { FACES_BB = 0, FACES_WALLS = 1, FACES_GENERAL = 2 };
+
+// One liquid step of every column: a workgroup per work item (item_col names its column), one
+// cell per thread per pass. The coordinates of the item's first cell are found once (uniform);
+// each thread carries its own offset into x, y and z with two small divisions. With walls only,
+// the cell is the single-lattice fast path (step_cell_bb: scalar bases, 32-bit byte offsets).
+template <typename T, int FACES>
+__global__ __launch_bounds__(256) void k_batch_step(const ColumnDev* __restrict__ cols,
+                                                    const uint32_t* __restrict__ item_col,
                                                     uint32_t nitems, int cur, int flag, int flags) {
   // each XCD takes a contiguous range of items (measured faster here than launch order, unlike
   // the single-lattice step)
   const uint32_t item = xcd_remap(blockIdx.x, nitems);
-  int lo = 0, hi = ncols - 1;
-  while (lo < hi) {  // last column whose first item is <= item
-    const int mid = (lo + hi + 1) >> 1;
-    if (cols[mid].item_begin <= item)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const ColumnDev& C = cols[lo];
+  const ColumnDev& C = cols[item_col[item]];
   const Geom G = C.G;
-  const T* __restrict__ src = static_cast<const T*>(C.pops[cur]);
-  T* __restrict__ dst = static_cast<T*>(C.pops[cur ^ 1]);
-  T* __restrict__ F = static_cast<T*>(C.F);
-  T* __restrict__ U = static_cast<T*>(C.U);
-  const uint8_t* __restrict__ tiles = C.tiles[flag];
-  uint8_t* __restrict__ tiles_next = C.tiles[flag ^ 1];
+  // the column's buffers, as pointers into global memory (the table is not a kernel argument,
+  // so the compiler would otherwise address them as flat memory)
+  const gmem<T>* src = reinterpret_cast<const gmem<T>*>(gbytes<T>(C.pops[cur]));
+  gmem<T>* dst = reinterpret_cast<gmem<T>*>(gbytes<T>(C.pops[cur ^ 1]));
+  gmem<T>* F = reinterpret_cast<gmem<T>*>(gbytes<T>(C.F));
+  gmem<T>* U = reinterpret_cast<gmem<T>*>(gbytes<T>(C.U));
+  const gmem<uint8_t>* tiles = reinterpret_cast<const gmem<uint8_t>*>(gbytes<uint8_t>(C.tiles[flag]));
+  gmem<uint8_t>* tiles_next = reinterpret_cast<gmem<uint8_t>*>(gbytes<uint8_t>(C.tiles[flag ^ 1]));
   const T omega = (T)C.omega;
-  const double inv_nx = 1.0 / G.nx, inv_plane = 1.0 / G.plane;
   const uint32_t first = (item - C.item_begin) * C.item_cells;
   const uint32_t last = min(first + C.item_cells, G.N);
-  for (uint32_t cell = first + threadIdx.x; cell < last; cell += 256) {
-    const uint32_t z = div_exact(cell, G.plane, inv_plane);
-    const uint32_t rem = cell - z * G.plane;
-    const uint32_t y = div_exact(rem, (uint32_t)G.nx, inv_nx);
-    const uint32_t x = rem - y * G.nx;
-    const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
-    const uint32_t lc = layout_cell(G, cell, z);
-    T g[19];
-    pull_all<GENERAL>(g, src, G, lc, nb, std::make_integer_sequence<int, 19>{});
-    const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
+  const uint32_t z0 = first / G.plane, r0 = first - z0 * G.plane;
+  const uint32_t y0 = r0 / (uint32_t)G.nx, x0 = r0 - y0 * (uint32_t)G.nx;
+  const float rnx = C.rnx, rny = C.rny;
+  const uint32_t fs = FACES == FACES_WALLS ? free_slip_faces(G) : 0u;
+  const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
+  for (uint32_t k = threadIdx.x; first + k < last; k += 256) {
+    const uint32_t xs = x0 + k;
+    const uint32_t qy = div_small(xs, (uint32_t)G.nx, rnx);
+    const uint32_t x = xs - qy * (uint32_t)G.nx;
+    const uint32_t ys = y0 + qy;
+    const uint32_t qz = div_small(ys, (uint32_t)G.ny, rny);
+    const uint32_t y = ys - qz * (uint32_t)G.ny;
+    const uint32_t z = z0 + qz;
     const uint32_t tile = ((z >> 3) * G.tny + (y >> 3)) * G.tnx + (x >> 3);
-    bool forced = static_force;
-    if (!static_force) forced = tiles[tile] != 0;
-    if (((x | y | z) & 7) == 0) tiles_next[tile] = 0;
-    T ux, uy, uz;
-    if (__any(forced)) {
-      T Fx = 0, Fy = 0, Fz = 0;
-      if (forced) {
-        Fx = F[cell];
-        Fy = F[G.N + cell];
-        Fz = F[2 * (size_t)G.N + cell];
-      }
-      collide<T, true>(g, Fx, Fy, Fz, omega, ux, uy, uz);
+    if constexpr (FACES != FACES_GENERAL) {
+      step_cell_bb<T, FACES == FACES_WALLS>((const gchar*)src, (gchar*)dst, (gchar*)F, (gchar*)U,
+                                            (const gchar*)tiles, tile, G, omega, flags, (int)x,
+                                            (int)y, z, fs);
     } else {
-      collide<T, false>(g, T(0), T(0), T(0), omega, ux, uy, uz);
-    }
+      const uint32_t cell = first + k;
+      const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
+      const uint32_t lc = layout_cell(G, cell, z);
+      T g[19];
+      pull_all_g<T>(g, src, G, lc, nb, std::make_integer_sequence<int, 19>{});
+      const bool forced = static_force || tiles[tile] != 0;
+      T ux, uy, uz;
+      if (__any(forced)) {
+        T Fx = 0, Fy = 0, Fz = 0;
+        if (forced) {
+          Fx = F[cell];
+          Fy = F[G.N + cell];
+          Fz = F[2 * (size_t)G.N + cell];
+        }
+        collide<T, true>(g, Fx, Fy, Fz, omega, ux, uy, uz);
+      } else {
+        collide<T, false>(g, T(0), T(0), T(0), omega, ux, uy, uz);
+      }
 #pragma unroll
-    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(g[q], &dst[(size_t)q * G.qs + lc]);
-    if (forced || (flags & LBM_FLAG_WRITE_U_ALL)) {
-      U[cell] = ux;
-      U[G.N + cell] = uy;
-      U[2 * (size_t)G.N + cell] = uz;
+      for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(g[q], &dst[(size_t)q * G.qs + lc]);
+      if (forced || (flags & LBM_FLAG_WRITE_U_ALL)) {
+        U[cell] = ux;
+        U[G.N + cell] = uy;
+        U[2 * (size_t)G.N + cell] = uz;
+      }
+      if (forced && !static_force) {
+        F[cell] = T(0);
+        F[G.N + cell] = T(0);
+        F[2 * (size_t)G.N + cell] = T(0);
+      }
     }
-    if (forced && !static_force) {
-      F[cell] = T(0);
-      F[G.N + cell] = T(0);
-      F[2 * (size_t)G.N + cell] = T(0);
-    }
+    // the corner cell of each tile clears that tile in the mask of the next bubble step
+    if (((x | y | z) & 7) == 0) tiles_next[tile] = 0;
   }
 }
 
@@ -207,8 +234,8 @@ bool column_ok(const lbm_column& c) {
 struct BatchLayout {
   std::vector<size_t> pops0, pops1, force, vel, tiles0, tiles1, tcount, tlist;
   std::vector<uint32_t> ntiles;
-  size_t pool, table, bcol, jobs, job_count, partials, result, status, scratch;
-  uint32_t total_tiles;
+  size_t pool, table, bcol, jobs, job_count, item_col, partials, result, status, scratch;
+  uint32_t total_tiles, max_items;
   int32_t nb_total;
 };
 
@@ -249,7 +276,11 @@ bool layout_batch(const lbm_column* cols, int ncols, size_t elem, BatchLayout& L
   }
   L.jobs = tiles;
   L.job_count = align_up(L.jobs + (size_t)2 * L.total_tiles * 2 * sizeof(uint32_t));
-  L.table = align_up(L.job_count + 2 * sizeof(uint32_t));
+  L.max_items = 0;
+  for (int c = 0; c < ncols; ++c)
+    L.max_items += div_up((uint32_t)cols[c].nx * cols[c].ny * cols[c].nz, 256u);
+  L.item_col = align_up(L.job_count + 2 * sizeof(uint32_t));
+  L.table = align_up(L.item_col + (size_t)L.max_items * sizeof(uint32_t));
   L.bcol = align_up(L.table + (size_t)ncols * sizeof(ColumnDev));
   L.partials = align_up(L.bcol + (size_t)(L.nb_total > 0 ? L.nb_total : 1) * sizeof(int32_t));
   const size_t nparts = std::max<size_t>(kRedBlocks, (size_t)ncols * kSumBlocks);
@@ -269,11 +300,13 @@ uint32_t default_item_cells(const lbm_column& c) {
 
 void assign_items(lbm_batch* b) {
   uint32_t item = 0;
+  b->item_col.clear();
   for (int c = 0; c < b->ncols; ++c) {
     ColumnDev& D = b->host[c];
     D.item_begin = item;
     D.items = div_up(D.G.N, D.item_cells);
     item += D.items;
+    b->item_col.insert(b->item_col.end(), D.items, (uint32_t)c);
   }
   b->nitems = item;
 }
@@ -281,16 +314,28 @@ void assign_items(lbm_batch* b) {
 hipError_t upload_table(lbm_batch* b) {
   hipError_t e = hipMemcpyAsync(b->dev, b->host.data(), b->host.size() * sizeof(ColumnDev),
                                 hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->item_col_dev, b->item_col.data(), b->item_col.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, b->stream);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(b->stream);
 }
 
-template <typename T, bool GENERAL>
-hipError_t batch_step_typed(lbm_batch* b) {
-  hipLaunchKernelGGL((k_batch_step<T, GENERAL>), dim3(b->nitems), dim3(256),
-                     occupancy_lds(b->lds_per_cu, b->step_wgs), b->stream, b->dev,
-                     b->ncols, b->nitems, b->cur, b->flag_cur, b->flags);
+template <typename T, int FACES>
+hipError_t batch_step_faces(lbm_batch* b) {
+  hipLaunchKernelGGL((k_batch_step<T, FACES>), dim3(b->nitems), dim3(256),
+                     occupancy_lds(b->lds_per_cu, b->step_wgs), b->stream, b->dev, b->item_col_dev,
+                     b->nitems, b->cur, b->flag_cur, b->flags);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t batch_step_typed(lbm_batch* b) {
+  switch (b->faces) {
+    case FACES_BB: return batch_step_faces<T, FACES_BB>(b);
+    case FACES_WALLS: return batch_step_faces<T, FACES_WALLS>(b);
+    default: return batch_step_faces<T, FACES_GENERAL>(b);
+  }
 }
 
 // One method step of every column: bubble half, then the liquid step.
@@ -317,10 +362,7 @@ hipError_t batch_method_step(lbm_batch* b, const bubble_params* p, const bubble_
   geo.par = b->cur;  // alternates every step, like the tile jobs' lists
   hipError_t e = launch_bubbles_batch(geo, b->elem, p, s, nb, b->status, b->stream);
   if (e != hipSuccess) return e;
-  if (b->elem == 4)
-    e = b->general ? batch_step_typed<float, true>(b) : batch_step_typed<float, false>(b);
-  else
-    e = b->general ? batch_step_typed<double, true>(b) : batch_step_typed<double, false>(b);
+  e = b->elem == 4 ? batch_step_typed<float>(b) : batch_step_typed<double>(b);
   if (e != hipSuccess) return e;
   b->cur ^= 1;
   b->flag_clean[b->flag_cur ^ 1] = true;
@@ -365,6 +407,7 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
   b->elem = elem;
   b->flags = flags;
   b->general = false;
+  b->faces = FACES_BB;
   b->cols.assign(cols, cols + ncols);
   b->nb_total = L.nb_total;
   b->stream = static_cast<hipStream_t>(stream);
@@ -386,6 +429,7 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
   uint8_t* P = static_cast<uint8_t*>(pool);
   uint8_t* S = static_cast<uint8_t*>(scratch);
   b->dev = reinterpret_cast<ColumnDev*>(S + L.table);
+  b->item_col_dev = reinterpret_cast<uint32_t*>(S + L.item_col);
   b->bubble_col = reinterpret_cast<int32_t*>(S + L.bcol);
   b->partials = reinterpret_cast<double*>(S + L.partials);
   b->result = reinterpret_cast<double*>(S + L.result);
@@ -411,7 +455,13 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
     for (int f = 0; f < 6; ++f) {
       D.G.bc[f] = k.bc[f];
       if (k.bc[f] != LBM_BC_BOUNCE_BACK) b->general = true;
+      if (k.bc[f] == LBM_BC_FREE_SLIP) b->faces = std::max(b->faces, (int)FACES_WALLS);
+      if (k.bc[f] == LBM_BC_PERIODIC) b->faces = FACES_GENERAL;
     }
+    // the wall fast path addresses populations by 32-bit byte offsets
+    if (!bb_fast_ok(D.G, elem)) b->faces = FACES_GENERAL;
+    D.rnx = 1.0f / (float)k.nx;
+    D.rny = 1.0f / (float)k.ny;
     D.G.tnx = (int)div_up(k.nx, kTile);
     D.G.tny = (int)div_up(k.ny, kTile);
     D.omega = k.omega;

@@ -141,6 +141,7 @@ struct ColumnDev {
   // per-tile bubble lists of the deterministic spreading (kTileCap entries per tile)
   uint32_t* tcount;
   uint32_t* tlist;
+  float rnx, rny;  // 1 / nx and 1 / ny rounded to float (cell coordinates of the batched step)
 };
 
 // Many columns: each bubble's column comes from a per-bubble index. The spreading gathers in

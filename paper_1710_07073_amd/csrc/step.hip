@@ -200,13 +200,11 @@ __global__ __launch_bounds__(256) void k_step_bb(const T* __restrict__ src, T* _
   if (x >= G.nx || y >= G.ny) return;
   const uint32_t tile = ((z >> 3) * G.tny + ((uint32_t)y >> 3)) * G.tnx + ((uint32_t)x >> 3);
   if (region && region[(z >> 3) * G.tny + ((uint32_t)y >> 3)]) return;  // the region launch's
-  const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
-  bool forced = static_force;
-  if (!static_force) forced = tiles[tile] != 0;
+  step_cell_bb<T, FS>(gbytes<T>(src), gbytes<T>(dst), gbytes<T>(F), gbytes<T>(U),
+                      gbytes<uint8_t>(tiles), tile, G, omega, flags, x, y, z,
+                      FS ? free_slip_faces(G) : 0u);
   // the corner cell of each tile clears that tile in the mask of the next bubble step
   if (((x | y | (int)z) & 7) == 0) tiles_next[tile] = 0;
-  step_cell_bb<T, FS>(src, dst, F, U, G, omega, flags, x, y, z, forced, __any(forced),
-                      FS ? free_slip_faces(G) : 0u);
 }
 
 // The region of an overlapped step: the tile rows of its list, each cut into the same workgroups
@@ -236,10 +234,10 @@ __global__ __launch_bounds__(256) void k_region_bb(const T* __restrict__ src, T*
     const uint32_t z = tz * kTile + zz;
     if (x < G.nx && y < G.ny && yr < kTile && z < (uint32_t)G.nz) {
       const uint32_t tile = ((z >> 3) * G.tny + ((uint32_t)y >> 3)) * G.tnx + ((uint32_t)x >> 3);
-      const bool forced = tiles[tile] != 0;
-      if (((x | y | (int)z) & 7) == 0) tiles_next[tile] = 0;
-      step_cell_bb<T, FS>(src, dst, F, U, G, omega, flags, x, y, z, forced, __any(forced),
+      step_cell_bb<T, FS>(gbytes<T>(src), gbytes<T>(dst), gbytes<T>(F), gbytes<T>(U),
+                          gbytes<uint8_t>(tiles), tile, G, omega, flags, x, y, z,
                           FS ? free_slip_faces(G) : 0u);
+      if (((x | y | (int)z) & 7) == 0) tiles_next[tile] = 0;
     }
     if (sub == 0 && threadIdx.x == 0 && threadIdx.y == 0) region[u] = 0u;
   }

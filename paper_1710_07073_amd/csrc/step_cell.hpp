@@ -59,10 +59,34 @@ __device__ __forceinline__ uint32_t free_slip_faces(const Geom& G) {
   return fs;
 }
 
+// Byte pointers into device global memory: loads and stores through them are global
+// instructions (a scalar base plus a 32-bit lane offset where the base is uniform), also when the
+// base comes from a table in memory rather than a kernel argument.
+using gchar = __attribute__((address_space(1))) char;
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ const gchar* gbytes(const void* p) {
+  return (const gchar*)p;
+}
+template <typename T>
+__device__ __forceinline__ gchar* gbytes(void* p) {
+  return (gchar*)p;
+}
+template <typename T>
+__device__ __forceinline__ T load_at(const gchar* b, uint32_t off) {
+  return *reinterpret_cast<const gmem<T>*>(b + off);
+}
+template <typename T>
+__device__ __forceinline__ void store_at(gchar* b, uint32_t off, T v) {
+  *reinterpret_cast<gmem<T>*>(b + off) = v;
+}
+
 template <int Q, typename T, bool FS>
-__device__ __forceinline__ T pull_bb(const char* __restrict__ sb, const Geom& G, uint32_t lc4,
-                                     uint32_t walls, uint32_t fs) {
-  return *reinterpret_cast<const T*>(sb + pull_off_bb<Q, T, FS>(G, lc4, walls, fs));
+__device__ __forceinline__ T pull_bb(const gchar* sb, const Geom& G, uint32_t lc4, uint32_t walls,
+                                     uint32_t fs) {
+  return load_at<T>(sb, pull_off_bb<Q, T, FS>(G, lc4, walls, fs));
 }
 
 __device__ __forceinline__ uint32_t wall_bits(const Geom& G, int x, int y, uint32_t z) {
@@ -71,8 +95,8 @@ __device__ __forceinline__ uint32_t wall_bits(const Geom& G, int x, int y, uint3
 }
 
 template <typename T, bool FS, int... Qs>
-__device__ __forceinline__ void pull_bb_all(T* g, const char* __restrict__ sb, const Geom& G,
-                                            uint32_t lc4, uint32_t walls, uint32_t fs,
+__device__ __forceinline__ void pull_bb_all(T* g, const gchar* sb, const Geom& G, uint32_t lc4,
+                                            uint32_t walls, uint32_t fs,
                                             std::integer_sequence<int, Qs...>) {
   ((g[Qs] = pull_bb<Qs, T, FS>(sb, G, lc4, walls, fs)), ...);
 }
@@ -83,30 +107,34 @@ __device__ __forceinline__ T* at_bytes(T* base, uint32_t off) {
   return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + off);
 }
 
-// One cell of the wall fast path: gather, collision, stores. forced: the cell's tile holds force
-// (read F, write U, clear F). FS: some face is free slip (fs: free_slip_faces(G)).
+// One cell of the wall fast path: gather, collision, stores. sb, db: the post-collision buffers
+// (source and destination), Fb, Ub: the force and velocity fields, tb: the tile mask of the step
+// (tile: the cell's tile), as global byte pointers. A flagged tile holds force (read F, write U,
+// clear F); the flag is read after the 19 gathers are issued, so that its round trip overlaps
+// theirs. FS: some face is free slip (fs: free_slip_faces(G)).
 template <typename T, bool FS>
-__device__ __forceinline__ void step_cell_bb(const T* __restrict__ src, T* __restrict__ dst,
-                                             T* __restrict__ F, T* __restrict__ U, const Geom& G,
+__device__ __forceinline__ void step_cell_bb(const gchar* sb, gchar* db, gchar* Fb, gchar* Ub,
+                                             const gchar* tb, uint32_t tile, const Geom& G,
                                              T omega, int flags, int x, int y, uint32_t z,
-                                             bool forced, bool wave_forced, uint32_t fs) {
+                                             uint32_t fs) {
   const uint32_t cell = ((uint32_t)z * G.ny + y) * G.nx + x;
   constexpr uint32_t esz = sizeof(T);
   const uint32_t lc4 = layout_cell(G, cell, z) * esz;
   const uint32_t walls = wall_bits(G, x, y, z);
   T g[19];
-  pull_bb_all<T, FS>(g, reinterpret_cast<const char*>(src), G, lc4, walls, fs,
-                     std::make_integer_sequence<int, 19>{});
+  pull_bb_all<T, FS>(g, sb, G, lc4, walls, fs, std::make_integer_sequence<int, 19>{});
   const uint32_t c4 = cell * esz;
   const uint32_t n4 = G.N * esz;
   const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
+  const bool forced = static_force || tb[tile] != 0;
+  const bool wave_forced = __any(forced);
   T ux, uy, uz;
   if (wave_forced) {
     T Fx = T(0), Fy = T(0), Fz = T(0);
     if (forced) {
-      Fx = *at_bytes(F, c4);
-      Fy = *at_bytes(F, c4 + n4);
-      Fz = *at_bytes(F, c4 + 2 * n4);
+      Fx = load_at<T>(Fb, c4);
+      Fy = load_at<T>(Fb, c4 + n4);
+      Fz = load_at<T>(Fb, c4 + 2 * n4);
     }
     collide<T, true>(g, Fx, Fy, Fz, omega, ux, uy, uz);
   } else {
@@ -115,16 +143,17 @@ __device__ __forceinline__ void step_cell_bb(const T* __restrict__ src, T* __res
   // one scalar base and a 32-bit offset per store (a 32-bit sum cannot be widened by the compiler)
   const uint32_t qs4 = G.qs * esz;
 #pragma unroll
-  for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(g[q], at_bytes(dst, lc4 + (uint32_t)q * qs4));
+  for (int q = 0; q < 19; ++q)
+    __builtin_nontemporal_store(g[q], reinterpret_cast<gmem<T>*>(db + (lc4 + (uint32_t)q * qs4)));
   if (forced || (flags & LBM_FLAG_WRITE_U_ALL)) {
-    *at_bytes(U, c4) = ux;
-    *at_bytes(U, c4 + n4) = uy;
-    *at_bytes(U, c4 + 2 * n4) = uz;
+    store_at<T>(Ub, c4, ux);
+    store_at<T>(Ub, c4 + n4, uy);
+    store_at<T>(Ub, c4 + 2 * n4, uz);
   }
   if (forced && !static_force) {
-    *at_bytes(F, c4) = T(0);
-    *at_bytes(F, c4 + n4) = T(0);
-    *at_bytes(F, c4 + 2 * n4) = T(0);
+    store_at<T>(Fb, c4, T(0));
+    store_at<T>(Fb, c4 + n4, T(0));
+    store_at<T>(Fb, c4 + 2 * n4, T(0));
   }
 }
 
