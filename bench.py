@@ -95,8 +95,9 @@ def cpu_baseline(w, budget_s=12.0):
 
 def leg_batched(args, steps):
     """64 uneven columns stepped together (FP32, graph replays), against the same columns run one
-    at a time as plain single-lattice FP64 simulations; error of the FP32 batch against FP64
-    single-column runs of the same number of steps on four of the columns."""
+    at a time as plain single-lattice FP64 simulations (also replayed from graphs); error of the
+    FP32 batch against FP64 single-column runs of the same number of steps on four of the columns;
+    and the time of the same steps as persistent launches."""
     import torch
     import workloads as W
     from paper_1710_07073_amd import autotune
@@ -138,16 +139,17 @@ def leg_batched(args, steps):
     ev_s = e0.elapsed_time(e1) * 1e-3
     batch.check()
     total = warm + K
-    # plain single-lattice FP64 form: every column on its own, eager launches, a few steps each
-    ks = 4
+    # plain single-lattice FP64 form: every column on its own, its steps replayed from a HIP graph
+    # as the batch's are (the graph captured and replayed once before the timed replays)
+    ks = 2 * gsteps
     t_single = 0.0
     for w in ws:
         sim = S.Simulation(w.shape, w.omega, precision="f64", bc=w.bc, stream=stream)
         sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
-        sim.step(1)
+        sim.run(gsteps, graph_steps=gsteps)
         stream.synchronize()
         a = time.perf_counter()
-        sim.step(ks)
+        sim.run(ks, graph_steps=gsteps)
         stream.synchronize()
         t_single += time.perf_counter() - a
         sim.close()
@@ -166,6 +168,18 @@ def leg_batched(args, steps):
         x32 = batch.bubbles.positions()[:, b0:b1]
         err_g = max(err_g, float(((g32.double() - g64).norm() / g64.norm()).item()))
         err_x = max(err_x, float(np.abs(x32 - x64).max()))
+    # the same steps as persistent launches (one kernel of gsteps steps per graph), for comparison
+    L.lbm_batch_set_persistent(batch.handle, True)
+    batch.run(gsteps, graph_steps=gsteps)
+    stream.synchronize()
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    batch.run(K, graph_steps=gsteps)
+    p1.record(stream)
+    stream.synchronize()
+    batch.check()
+    persistent_ms = p0.elapsed_time(p1) / K
+    persistent_grid = L.lbm_batch_get_persistent(batch.handle)[1]
     batch.close()
     mlups = cells * K / elapsed / 1e6
     fp64 = cells * ks / t_single / 1e6
@@ -174,6 +188,7 @@ def leg_batched(args, steps):
             "batched_f32_mlups": round(mlups, 1), "ms_per_step": round(elapsed / K * 1e3, 5),
             "event_ms_per_step": round(ev_s / K * 1e3, 5),
             "plain_fp64_single_mlups": round(fp64, 1), "ratio_vs_plain_fp64": round(mlups / fp64, 3),
+            "persistent_ms_per_step": round(persistent_ms, 5), "persistent_grid": persistent_grid,
             "error_vs_fp64": {"after_steps": total, "columns_checked": [0, 17, 40, 63],
                               "populations_rel_l2_max": err_g,
                               "bubble_pos_max_abs": err_x}}

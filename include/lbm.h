@@ -391,6 +391,16 @@ lbm_status lbm_batch_get_items(lbm_batch* batch, int32_t* item_cells);
  * for FP64 (held to 3 by registers). */
 lbm_status lbm_batch_set_step_occupancy(lbm_batch* batch, int32_t workgroups_per_cu);
 lbm_status lbm_batch_get_step_occupancy(lbm_batch* batch, int32_t* workgroups_per_cu);
+/* Persistent launches (the sweep of Sec. 4.2-4.3 as one kernel per run of steps): with enable,
+ * lbm_batch_step runs its nsteps method steps as one kernel and lbm_batch_run captures one such
+ * kernel of graph_steps steps per graph. The kernel holds as many workgroups as stay resident
+ * together (at most the batch occupancy cap per compute unit) and separates the phases of each step
+ * (bubble half, force gather, liquid step) by grid-wide barriers; results are those of the
+ * per-step launches. Should the workgroups not all be resident (other work on the device), its
+ * barriers time out after about a second, the launch ends early and lbm_batch_check() returns
+ * LBM_EDEVICE. grid (nullable) receives the workgroups of the last persistent launch. */
+lbm_status lbm_batch_set_persistent(lbm_batch* batch, int32_t enable);
+lbm_status lbm_batch_get_persistent(lbm_batch* batch, int32_t* enabled, int32_t* grid);
 /* nsteps method steps of every column (eager launches). nb must equal the total bubble count. */
 lbm_status lbm_batch_step(lbm_batch* batch, const bubble_params* params, const bubble_soa* soa,
                           int32_t nb, int32_t nsteps);

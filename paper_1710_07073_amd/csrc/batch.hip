@@ -10,9 +10,9 @@
 #include <string.h>
 #include <vector>
 
+#include "batch_cell.hpp"
 #include "collide.hpp"
 #include "graph.hpp"
-#include "step_cell.hpp"
 
 struct lbm_batch {
   int ncols;
@@ -33,6 +33,9 @@ struct lbm_batch {
   int flag_cur;     // current tile mask, same for all columns
   bool flag_clean[2];
   int32_t* status;
+  bool persistent;      // method steps as persistent launches (lbm_batch_set_persistent)
+  uint32_t* barrier;    // grid-barrier words of the persistent launch
+  uint32_t last_grid;   // workgroups of the last persistent launch
   uint32_t* jobs;       // tile jobs of the deterministic spreading, two step parities
   uint32_t* job_count;  // [2]
   uint32_t job_cap;     // tiles of all columns: each is noted at most once per step
@@ -54,103 +57,14 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 constexpr uint32_t kSumBlocks = 16;  // workgroups per column of the per-column sums
 
-// q = a / d for a < 2^24 with rd the float nearest to 1 / d: the float quotient is off by at most
-// one, which one correction in each direction removes.
-__device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t d, float rd) {
-  uint32_t q = (uint32_t)((float)a * rd);
-  if (q * d > a) --q;
-  if ((q + 1) * d <= a) ++q;
-  return q;
-}
-
-// The general pull (any face rule) from a global pointer.
-template <typename T, int... Qs>
-__device__ __forceinline__ void pull_all_g(T* g, const gmem<T>* src, const Geom& G, uint32_t lc,
-                                           const CellNbr& nb, std::integer_sequence<int, Qs...>) {
-  ((g[Qs] = src[pull_index<Qs, true>(G, lc, nb)]), ...);
-}
-
-// Faces of a batch (the liquid kernel's template parameter): every face of every column
-// bounce-back, walls only (bounce-back or free slip), or some face periodic.
-enum : int { FACES_BB = 0, FACES_WALLS = 1, FACES_GENERAL = 2 };
-
-// One liquid step of every column: a workgroup per work item (item_col names its column), one
-// cell per thread per pass. The coordinates of the item's first cell are found once (uniform);
-// each thread carries its own offset into x, y and z with two small divisions. With walls only,
-// the cell is the single-lattice fast path (step_cell_bb: scalar bases, 32-bit byte offsets).
+// One liquid step of every column: a workgroup per work item.
 template <typename T, int FACES>
 __global__ __launch_bounds__(256) void k_batch_step(const ColumnDev* __restrict__ cols,
                                                     const uint32_t* __restrict__ item_col,
                                                     uint32_t nitems, int cur, int flag, int flags) {
   // each XCD takes a contiguous range of items (measured faster here than launch order, unlike
   // the single-lattice step)
-  const uint32_t item = xcd_remap(blockIdx.x, nitems);
-  const ColumnDev& C = cols[item_col[item]];
-  const Geom G = C.G;
-  // the column's buffers, as pointers into global memory (the table is not a kernel argument,
-  // so the compiler would otherwise address them as flat memory)
-  const gmem<T>* src = reinterpret_cast<const gmem<T>*>(gbytes<T>(C.pops[cur]));
-  gmem<T>* dst = reinterpret_cast<gmem<T>*>(gbytes<T>(C.pops[cur ^ 1]));
-  gmem<T>* F = reinterpret_cast<gmem<T>*>(gbytes<T>(C.F));
-  gmem<T>* U = reinterpret_cast<gmem<T>*>(gbytes<T>(C.U));
-  const gmem<uint8_t>* tiles = reinterpret_cast<const gmem<uint8_t>*>(gbytes<uint8_t>(C.tiles[flag]));
-  gmem<uint8_t>* tiles_next = reinterpret_cast<gmem<uint8_t>*>(gbytes<uint8_t>(C.tiles[flag ^ 1]));
-  const T omega = (T)C.omega;
-  const uint32_t first = (item - C.item_begin) * C.item_cells;
-  const uint32_t last = min(first + C.item_cells, G.N);
-  const uint32_t z0 = first / G.plane, r0 = first - z0 * G.plane;
-  const uint32_t y0 = r0 / (uint32_t)G.nx, x0 = r0 - y0 * (uint32_t)G.nx;
-  const float rnx = C.rnx, rny = C.rny;
-  const uint32_t fs = FACES == FACES_WALLS ? free_slip_faces(G) : 0u;
-  const bool static_force = flags & LBM_FLAG_STATIC_FORCE;
-  for (uint32_t k = threadIdx.x; first + k < last; k += 256) {
-    const uint32_t xs = x0 + k;
-    const uint32_t qy = div_small(xs, (uint32_t)G.nx, rnx);
-    const uint32_t x = xs - qy * (uint32_t)G.nx;
-    const uint32_t ys = y0 + qy;
-    const uint32_t qz = div_small(ys, (uint32_t)G.ny, rny);
-    const uint32_t y = ys - qz * (uint32_t)G.ny;
-    const uint32_t z = z0 + qz;
-    const uint32_t tile = ((z >> 3) * G.tny + (y >> 3)) * G.tnx + (x >> 3);
-    if constexpr (FACES != FACES_GENERAL) {
-      step_cell_bb<T, FACES == FACES_WALLS>((const gchar*)src, (gchar*)dst, (gchar*)F, (gchar*)U,
-                                            (const gchar*)tiles, tile, G, omega, flags, (int)x,
-                                            (int)y, z, fs);
-    } else {
-      const uint32_t cell = first + k;
-      const CellNbr nb = cell_neighbours(G, (int)x, (int)y, (int)z);
-      const uint32_t lc = layout_cell(G, cell, z);
-      T g[19];
-      pull_all_g<T>(g, src, G, lc, nb, std::make_integer_sequence<int, 19>{});
-      const bool forced = static_force || tiles[tile] != 0;
-      T ux, uy, uz;
-      if (__any(forced)) {
-        T Fx = 0, Fy = 0, Fz = 0;
-        if (forced) {
-          Fx = F[cell];
-          Fy = F[G.N + cell];
-          Fz = F[2 * (size_t)G.N + cell];
-        }
-        collide<T, true>(g, Fx, Fy, Fz, omega, ux, uy, uz);
-      } else {
-        collide<T, false>(g, T(0), T(0), T(0), omega, ux, uy, uz);
-      }
-#pragma unroll
-      for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(g[q], &dst[(size_t)q * G.qs + lc]);
-      if (forced || (flags & LBM_FLAG_WRITE_U_ALL)) {
-        U[cell] = ux;
-        U[G.N + cell] = uy;
-        U[2 * (size_t)G.N + cell] = uz;
-      }
-      if (forced && !static_force) {
-        F[cell] = T(0);
-        F[G.N + cell] = T(0);
-        F[2 * (size_t)G.N + cell] = T(0);
-      }
-    }
-    // the corner cell of each tile clears that tile in the mask of the next bubble step
-    if (((x | y | z) & 7) == 0) tiles_next[tile] = 0;
-  }
+  batch_item<T, FACES>(cols, item_col, xcd_remap(blockIdx.x, nitems), cur, flag, flags);
 }
 
 // Per-column sums (eq. (10)) of the current state: kSumBlocks workgroups per column accumulate
@@ -234,7 +148,7 @@ bool column_ok(const lbm_column& c) {
 struct BatchLayout {
   std::vector<size_t> pops0, pops1, force, vel, tiles0, tiles1, tcount, tlist;
   std::vector<uint32_t> ntiles;
-  size_t pool, table, bcol, jobs, job_count, item_col, partials, result, status, scratch;
+  size_t pool, table, bcol, jobs, job_count, item_col, barrier, partials, result, status, scratch;
   uint32_t total_tiles, max_items;
   int32_t nb_total;
 };
@@ -280,7 +194,8 @@ bool layout_batch(const lbm_column* cols, int ncols, size_t elem, BatchLayout& L
   for (int c = 0; c < ncols; ++c)
     L.max_items += div_up((uint32_t)cols[c].nx * cols[c].ny * cols[c].nz, 256u);
   L.item_col = align_up(L.job_count + 2 * sizeof(uint32_t));
-  L.table = align_up(L.item_col + (size_t)L.max_items * sizeof(uint32_t));
+  L.barrier = align_up(L.item_col + (size_t)L.max_items * sizeof(uint32_t));
+  L.table = align_up(L.barrier + 4 * sizeof(uint32_t));
   L.bcol = align_up(L.table + (size_t)ncols * sizeof(ColumnDev));
   L.partials = align_up(L.bcol + (size_t)(L.nb_total > 0 ? L.nb_total : 1) * sizeof(int32_t));
   const size_t nparts = std::max<size_t>(kRedBlocks, (size_t)ncols * kSumBlocks);
@@ -370,6 +285,58 @@ hipError_t batch_method_step(lbm_batch* b, const bubble_params* p, const bubble_
   return hipSuccess;
 }
 
+// Polls of a persistent launch's barrier before it aborts (about a second of waiting).
+constexpr uint32_t kBarrierSpinLimit = 1u << 20;
+
+// n method steps of every column as one persistent launch.
+hipError_t batch_persistent_steps(lbm_batch* b, const bubble_params* p, const bubble_soa* s,
+                                  int32_t nb, int32_t n) {
+  if (n <= 0) return hipSuccess;
+  const int m0 = b->flag_cur ^ 1;  // tile mask of the first step
+  if (!b->flag_clean[m0]) {
+    for (int c = 0; c < b->ncols; ++c) {
+      const hipError_t e = launch_fill(b->host[c].tiles[m0],
+                                       (size_t)b->host[c].G.tnx * b->host[c].G.tny *
+                                           div_up(b->host[c].G.nz, kTile),
+                                       b->stream);
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipError_t e = launch_fill(b->barrier, 4 * sizeof(uint32_t), b->stream);
+  if (e != hipSuccess) return e;
+  ManyColumns geo;
+  geo.cols = b->dev;
+  geo.bubble_col = b->bubble_col;
+  geo.flag = m0;
+  geo.jobs = b->jobs;
+  geo.job_count = b->job_count;
+  geo.job_cap = b->job_cap;
+  geo.par = b->cur;
+  PersistArgs P;
+  P.cols = b->dev;
+  P.item_col = b->item_col_dev;
+  P.nitems = b->nitems;
+  P.cur0 = b->cur;
+  P.flag0 = m0;
+  P.flags = b->flags;
+  P.nsteps = n;
+  P.faces = b->faces;
+  P.barrier = b->barrier;
+  P.spin_limit = kBarrierSpinLimit;
+  e = launch_batch_persistent(geo, b->elem, p, s, nb, b->status, P, b->step_wgs, &b->last_grid,
+                              b->stream);
+  if (e != hipSuccess) return e;
+  for (int32_t i = 0; i < n; ++i) {  // the host step state the n steps leave
+    const int m = b->flag_cur ^ 1;
+    b->flag_clean[m] = false;
+    b->flag_cur = m;
+    b->cur ^= 1;
+    b->flag_clean[b->flag_cur ^ 1] = true;
+    ++b->steps;
+  }
+  return hipSuccess;
+}
+
 lbm_status to_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
 
 }  // namespace
@@ -437,6 +404,9 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
   b->jobs = reinterpret_cast<uint32_t*>(S + L.jobs);
   b->job_count = reinterpret_cast<uint32_t*>(S + L.job_count);
   b->job_cap = L.total_tiles;
+  b->persistent = false;
+  b->barrier = reinterpret_cast<uint32_t*>(S + L.barrier);
+  b->last_grid = 0;
   b->nred = kRedBlocks;
   b->host.resize(ncols);
   std::vector<int32_t> bcol(L.nb_total > 0 ? L.nb_total : 1, 0);
@@ -535,10 +505,25 @@ lbm_status lbm_batch_step(lbm_batch* b, const bubble_params* p, const bubble_soa
   if (nb > 0 && (!s->x || !s->y || !s->z || !s->ux || !s->uy || !s->uz || !s->d || !s->ulx ||
                  !s->uly || !s->ulz || !s->state || !s->work))
     return LBM_EINVAL;
+  if (b->persistent) return to_status(batch_persistent_steps(b, p, s, nb, nsteps));
   for (int32_t i = 0; i < nsteps; ++i) {
     const hipError_t e = batch_method_step(b, p, s, nb);
     if (e != hipSuccess) return LBM_EDEVICE;
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_persistent(lbm_batch* b, int32_t enable) {
+  if (!b) return LBM_EINVAL;
+  b->persistent = enable != 0;
+  b->graph.reset();  // captured launches hold the other mode
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_persistent(lbm_batch* b, int32_t* enabled, int32_t* grid) {
+  if (!b) return LBM_EINVAL;
+  if (enabled) *enabled = b->persistent ? 1 : 0;
+  if (grid) *grid = (int32_t)b->last_grid;
   return LBM_OK;
 }
 
@@ -552,6 +537,7 @@ lbm_status lbm_batch_run(lbm_batch* b, const bubble_params* p, const bubble_soa*
   const lbm_status st = lbm_batch_step(b, p, s, nb, 0);
   if (st != LBM_OK) return st;
   auto enqueue = [&](int n) -> hipError_t {
+    if (b->persistent) return batch_persistent_steps(b, p, s, nb, n);  // one launch
     for (int i = 0; i < n; ++i) {
       const hipError_t e = batch_method_step(b, p, s, nb);
       if (e != hipSuccess) return e;
@@ -560,7 +546,8 @@ lbm_status lbm_batch_run(lbm_batch* b, const bubble_params* p, const bubble_soa*
   };
   int32_t done = 0;
   while (nsteps - done >= graph_steps) {
-    const uint32_t mode = (b->flag_clean[0] ? 1u : 0u) | (b->flag_clean[1] ? 2u : 0u);
+    const uint32_t mode = (b->flag_clean[0] ? 1u : 0u) | (b->flag_clean[1] ? 2u : 0u) |
+                          (b->persistent ? 4u : 0u);
     const GraphKey key = GraphKey::of(p, s, nb, b->cur, b->flag_cur, graph_steps, mode);
     const int cur0 = b->cur, flag0 = b->flag_cur;
     const bool clean0[2] = {b->flag_clean[0], b->flag_clean[1]};
@@ -661,7 +648,8 @@ lbm_status lbm_batch_check(lbm_batch* b) {
   if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_EDEVICE;
   if (st != 0) {
     if (launch_fill(b->status, 256, b->stream) != hipSuccess) return LBM_EDEVICE;
-    return LBM_EINVAL;
+    // a persistent launch that could not hold all its workgroups resident aborted its steps
+    return (st & STATUS_BARRIER_TIMEOUT) ? LBM_EDEVICE : LBM_EINVAL;
   }
   return LBM_OK;
 }

@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "batch_cell.hpp"
 #include "collide.hpp"
 
 namespace lbm {
@@ -454,21 +455,24 @@ __device__ bool ode_update(const Geo& geo, const BubbleArgs& A, int b, const Ode
                            const BubbleConst* kc_in, const double* x0_in, double x0[3],
                            double xn_out[3], double& n_out);
 
-template <typename T, typename Geo, bool EXACT = false, int GATHER = 1, bool FUSE = false>
-__global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
+// What the first workgroup of a step's first bubble kernel clears for the step.
+template <typename Geo>
+__device__ __forceinline__ void clear_for_step(const Geo& geo) {
+  if constexpr (std::is_same_v<Geo, OneColumn>) {
+    // in an overlapped step, the other parity's region list (its region launch ran before)
+    // starts empty
+    if (geo.clear_count) *geo.clear_count = 0u;
+  }
+  geo.clear_other_jobs();  // many columns: the next step's tile jobs start empty
+}
+
+// Forward coupling of bubble b by the whole workgroup (and, FUSE, its update and tile flags).
+template <typename T, typename Geo, bool EXACT, int GATHER, bool FUSE>
+__device__ void interp_bubble(const Geo& geo, const BubbleArgs& A, const int b) {
   __shared__ double s_w[3][kSpan];
   __shared__ double s_dw[3][kSpan];
   __shared__ double s_red6[6][kBlockWaves];
-  const int b = bubble_of_block(A.nb);
   const int tid = threadIdx.x;
-  if (blockIdx.x == 0 && tid == 0) {
-    if constexpr (std::is_same_v<Geo, OneColumn>) {
-      // in an overlapped step, the other parity's region list (its region launch ran before)
-      // starts empty
-      if (geo.clear_count) *geo.clear_count = 0u;
-    }
-    geo.clear_other_jobs();  // many columns: the next step's tile jobs start empty
-  }
   const ColumnView<T> col = geo.template view<T>(b);
   const Geom& G = col.G;
   const T* __restrict__ U = col.U;
@@ -660,6 +664,12 @@ __global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
       mark_tiles<T>(col, A, win, xn, n, tid, kBlock);
     }
   }
+}
+
+template <typename T, typename Geo, bool EXACT = false, int GATHER = 1, bool FUSE = false>
+__global__ __launch_bounds__(kBlock) void k_interp(Geo geo, BubbleArgs A) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) clear_for_step(geo);
+  interp_bubble<T, Geo, EXACT, GATHER, FUSE>(geo, A, bubble_of_block(A.nb));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1015,7 +1025,9 @@ struct GatherJob {
 
 // Jobs of the gather. One lattice: every tile, one per workgroup (an empty list returns at once).
 // Many columns: the (column, tile) pairs noted this step, over the workgroups in turn.
-__device__ __forceinline__ uint32_t gather_jobs(const OneColumn&) { return gridDim.x; }
+__device__ __forceinline__ uint32_t gather_jobs(const OneColumn& geo) {
+  return (uint32_t)geo.G.tnx * geo.G.tny * (((uint32_t)geo.G.nz + kTile - 1) / kTile);
+}
 __device__ __forceinline__ uint32_t gather_jobs(const ManyColumns& geo) {
   return min(geo.job_count[geo.par], geo.job_cap);
 }
@@ -1033,8 +1045,9 @@ __device__ __forceinline__ GatherJob<T> gather_job(const ManyColumns& geo, const
           C.bubble_begin + C.nb};
 }
 
+// The jobs first, first + stride, ... of the step's gather, by the whole workgroup.
 template <typename T, typename Geo>
-__global__ __launch_bounds__(kBlock) void k_spread_gather(Geo geo, BubbleArgs A) {
+__device__ void gather_tiles(const Geo& geo, const BubbleArgs& A, uint32_t first, uint32_t stride) {
   static_assert(kTileCap == 64, "one wavefront compacts a chunk of the overflow scan");
   __shared__ uint32_t s_list[kTileCap];
   __shared__ uint32_t s_sorted[kTileCap];
@@ -1043,7 +1056,7 @@ __global__ __launch_bounds__(kBlock) void k_spread_gather(Geo geo, BubbleArgs A)
   __shared__ uint32_t s_n;
   const int tid = threadIdx.x;
   const uint32_t njobs = gather_jobs(geo);
-  for (uint32_t j = blockIdx.x; j < njobs; j += gridDim.x) {
+  for (uint32_t j = first; j < njobs; j += stride) {
     const GatherJob<T> J = gather_job<T>(geo, A, j);
     const Geom& G = J.G;
     const uint32_t t = J.t;
@@ -1144,6 +1157,11 @@ __global__ __launch_bounds__(kBlock) void k_spread_gather(Geo geo, BubbleArgs A)
   }
 }
 
+template <typename T, typename Geo>
+__global__ __launch_bounds__(kBlock) void k_spread_gather(Geo geo, BubbleArgs A) {
+  gather_tiles<T, Geo>(geo, A, blockIdx.x, gridDim.x);
+}
+
 // Region of an overlapped step (one wavefront per bubble): the tile rows (y, z) of the bubble's
 // stencil window at its current position widened by the curl ring and by kRegionMargin cells.
 // They hold every tile k_spread flags in this step (the force window at this position, the
@@ -1241,6 +1259,111 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Persistent batched launch: many method steps of every column in one kernel.
+// ---------------------------------------------------------------------------------------------
+// Barrier of every workgroup of a persistent launch (all resident: the grid is sized from the
+// occupancy the kernel allows). The first thread of each workgroup makes the workgroup's writes
+// visible at agent scope and counts itself in; the last arrival resets the count and advances the
+// generation the others poll. The wait is bounded: after spin_limit polls a workgroup raises the
+// abort word and the status, and every workgroup leaves the kernel at its next barrier, so a
+// launch whose workgroups were not all resident ends (with an error) instead of hanging. Returns
+// false once the launch is aborted.
+__device__ bool grid_barrier(uint32_t* bar, uint32_t nblocks, uint32_t spin_limit,
+                             int32_t* status) {
+  __shared__ uint32_t s_go;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t go = 1u;
+    const uint32_t gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();  // this workgroup's writes, before its arrival
+    const uint32_t n =
+        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (n == nblocks) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t polls = 0;
+      // relaxed polls (an acquire per poll would invalidate the caches each time); the fence
+      // below orders what follows
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+        if (++polls > spin_limit) {
+          __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          atomicOr(status, (int32_t)STATUS_BARRIER_TIMEOUT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();  // the other workgroups' writes, after the barrier
+    if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) go = 0u;
+    s_go = go;
+  }
+  __syncthreads();
+  return s_go != 0u;
+}
+
+// P.nsteps method steps of every column, each in three phases separated by grid barriers: the
+// bubbles (forward coupling, update and tile flags, one bubble per workgroup in turn), the gather
+// of the reactions per noted tile, and the liquid step per work item. The same device code as
+// the per-step launches (k_interp with the fused update, k_spread_gather, k_batch_step), so the
+// results are the same.
+template <typename T, int FACES>
+__global__ __launch_bounds__(kBlock, 2) void k_batch_persistent(ManyColumns geo, BubbleArgs A,
+                                                             PersistArgs P) {
+  for (int s = 0; s < P.nsteps; ++s) {
+    const int odd = s & 1;
+    ManyColumns g = geo;
+    g.flag = P.flag0 ^ odd;
+    g.par = P.cur0 ^ odd;
+    if (A.nb > 0) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) clear_for_step(g);
+      for (int b = blockIdx.x; b < A.nb; b += gridDim.x) {
+        interp_bubble<T, ManyColumns, false, 8, true>(g, A, b);
+        __syncthreads();  // the next bubble reuses the workgroup's shared arrays
+      }
+      if (!grid_barrier(P.barrier, gridDim.x, P.spin_limit, A.status)) return;
+      gather_tiles<T, ManyColumns>(g, A, blockIdx.x, gridDim.x);
+      if (!grid_barrier(P.barrier, gridDim.x, P.spin_limit, A.status)) return;
+    }
+    for (uint32_t k = blockIdx.x; k < P.nitems; k += gridDim.x)
+      batch_item<T, FACES>(P.cols, P.item_col, xcd_remap(k, P.nitems), P.cur0 ^ odd, g.flag,
+                           P.flags);
+    if (!grid_barrier(P.barrier, gridDim.x, P.spin_limit, A.status)) return;
+  }
+}
+
+template <typename T, int FACES>
+hipError_t launch_persistent_typed(const ManyColumns& geo, const BubbleArgs& A,
+                                   const PersistArgs& P, int wgs_per_cu, uint32_t* grid,
+                                   hipStream_t stream) {
+  const auto kern = k_batch_persistent<T, FACES>;
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1 || cus < 1) return hipErrorInvalidConfiguration;
+  if (wgs_per_cu > 0 && wgs_per_cu < per_cu) per_cu = wgs_per_cu;
+  const uint32_t blocks = (uint32_t)per_cu * (uint32_t)cus;
+  *grid = blocks;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, stream, geo, A, P);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_persistent_faces(const ManyColumns& geo, const BubbleArgs& A,
+                                   const PersistArgs& P, int wgs_per_cu, uint32_t* grid,
+                                   hipStream_t stream) {
+  switch (P.faces) {
+    case FACES_BB: return launch_persistent_typed<T, FACES_BB>(geo, A, P, wgs_per_cu, grid, stream);
+    case FACES_WALLS:
+      return launch_persistent_typed<T, FACES_WALLS>(geo, A, P, wgs_per_cu, grid, stream);
+    default: return launch_persistent_typed<T, FACES_GENERAL>(geo, A, P, wgs_per_cu, grid, stream);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* s, int32_t nb,
@@ -1327,6 +1450,20 @@ hipError_t launch_bubbles_batch(const ManyColumns& geo, size_t elem, const bubbl
   A.rec = nullptr;
   if (elem == 4) return launch_bubble_kernels<float>(geo, A, stream);
   return launch_bubble_kernels<double>(geo, A, stream);
+}
+
+hipError_t launch_batch_persistent(const ManyColumns& geo, size_t elem, const bubble_params* p,
+                                   const bubble_soa* s, int32_t nb, int32_t* status,
+                                   const PersistArgs& P, int wgs_per_cu, uint32_t* grid,
+                                   hipStream_t stream) {
+  BubbleArgs A;
+  A.P = *p;
+  A.S = *s;
+  A.nb = nb;
+  A.status = status;
+  A.rec = nullptr;
+  if (elem == 4) return launch_persistent_faces<float>(geo, A, P, wgs_per_cu, grid, stream);
+  return launch_persistent_faces<double>(geo, A, P, wgs_per_cu, grid, stream);
 }
 
 }  // namespace lbm

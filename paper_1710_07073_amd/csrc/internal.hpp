@@ -195,7 +195,19 @@ static_assert(R_CLAMP + 3 <= R_SIZE, "bubble record too small");
 constexpr uint32_t kTileCap = 64;
 constexpr uint32_t kRedBlocks = 1024;  // upper bound of moments reduction blocks
 
-enum : int32_t { STATUS_STENCIL_TOO_LARGE = 1, STATUS_REGION_MISS = 2 };
+enum : int32_t { STATUS_STENCIL_TOO_LARGE = 1, STATUS_REGION_MISS = 2, STATUS_BARRIER_TIMEOUT = 4 };
+
+// A persistent batched launch: nsteps method steps of every column in one kernel (see
+// launch_batch_persistent). Step s uses tile mask flag0 ^ (s & 1), reads population buffer
+// cur0 ^ (s & 1) and note list parity cur0 ^ (s & 1).
+struct PersistArgs {
+  const ColumnDev* cols;
+  const uint32_t* item_col;
+  uint32_t nitems;
+  int cur0, flag0, flags, nsteps, faces;
+  uint32_t* barrier;    // [0] arrivals, [1] generation, [2] abort; zero at launch
+  uint32_t spin_limit;  // polls a workgroup waits at a barrier before it aborts the launch
+};
 
 // Cells the region of an overlapped step extends beyond a bubble's stencil window widened by the
 // curl ring: covers the bubble's displacement in one step.
@@ -228,6 +240,13 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
 hipError_t launch_bubbles_batch(const ManyColumns& geo, size_t elem, const bubble_params* p,
                                 const bubble_soa* s, int32_t nb, int32_t* status,
                                 hipStream_t stream);
+// The persistent launch of P.nsteps method steps (bubble half and liquid step of every column).
+// wgs_per_cu: workgroups per compute unit (0: as many as fit); *grid receives the workgroups
+// launched. The barrier words must be zero (the caller clears them before each launch).
+hipError_t launch_batch_persistent(const ManyColumns& geo, size_t elem, const bubble_params* p,
+                                   const bubble_soa* s, int32_t nb, int32_t* status,
+                                   const PersistArgs& P, int wgs_per_cu, uint32_t* grid,
+                                   hipStream_t stream);
 // moments.hip
 hipError_t launch_moments(lbm_ctx* c, void* rho, void* u, bool sums);
 hipError_t launch_populations(lbm_ctx* c, void* out);

@@ -35,6 +35,7 @@ EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch",
            "lbm_status_string",
            "lbm_batch_bytes_required", "lbm_batch_init", "lbm_batch_set_items", "lbm_batch_get_items",
            "lbm_batch_set_step_occupancy", "lbm_batch_get_step_occupancy",
+           "lbm_batch_set_persistent", "lbm_batch_get_persistent",
            "lbm_batch_step", "lbm_batch_run", "lbm_batch_populations", "lbm_batch_sums",
            "lbm_batch_column",
            "lbm_batch_check", "lbm_batch_destroy",
@@ -118,6 +119,8 @@ def lib():
         L.lbm_batch_get_items.argtypes = [P, ct.POINTER(ct.c_int32)]
         L.lbm_batch_set_step_occupancy.argtypes = [P, ct.c_int32]
         L.lbm_batch_get_step_occupancy.argtypes = [P, ct.POINTER(ct.c_int32)]
+        L.lbm_batch_set_persistent.argtypes = [P, ct.c_int32]
+        L.lbm_batch_get_persistent.argtypes = [P, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]
         L.lbm_batch_step.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32,
                                      ct.c_int32]
         L.lbm_batch_run.argtypes = [P, ct.POINTER(BubbleParams), ct.POINTER(BubbleSoA), ct.c_int32,
@@ -330,6 +333,17 @@ def lbm_batch_run(batch, params, soa, nb, nsteps, graph_steps=0):
 
 def lbm_batch_populations(batch, col, out_ptr):
     _ok(lib().lbm_batch_populations(batch, int(col), out_ptr), "lbm_batch_populations")
+
+
+def lbm_batch_set_persistent(batch, enable):
+    _ok(lib().lbm_batch_set_persistent(batch, 1 if enable else 0), "lbm_batch_set_persistent")
+
+
+def lbm_batch_get_persistent(batch):
+    """(enabled, workgroups of the last persistent launch)"""
+    e, g = ct.c_int32(), ct.c_int32()
+    _ok(lib().lbm_batch_get_persistent(batch, ct.byref(e), ct.byref(g)), "lbm_batch_get_persistent")
+    return bool(e.value), g.value
 
 
 def lbm_batch_sums(batch, ncols):

@@ -102,13 +102,15 @@ def test_batch_is_bitwise_identical_to_single_lattice_runs(prec):
 
 @pytest.mark.gpu
 def test_batched_sweep_rerun_is_bitwise_identical():
-    """The 64-column sweep (1-8 bubbles per column, 50 M sites) run twice: same bits everywhere."""
+    """The 64-column sweep (1-8 bubbles per column, 50 M sites) run twice, per-step launches and
+    persistent launches: same bits everywhere."""
     ws = W.batched()
     cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d) for w in ws]
     print(f"[case] batched sweep rerun: {len(cols)} columns", flush=True)
     runs = []
-    for _ in range(2):
+    for persistent in (False, True):  # the second run as persistent launches
         b = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32")
+        L.lbm_batch_set_persistent(b.handle, persistent)
         b.run(40, graph_steps=20)
         torch.cuda.synchronize()
         runs.append(b)
@@ -119,6 +121,33 @@ def test_batched_sweep_rerun_is_bitwise_identical():
     for r in runs:
         r.check()
         r.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_persistent_launch_matches_per_step_launches(prec):
+    """The persistent launch (phases of every step in one kernel, grid barriers between them), eager
+    and captured in graphs, gives the per-step launches' results bit for bit."""
+    cols = _crowded_columns(seed=41)
+    print(f"[case] persistent batch {prec}", flush=True)
+    out = []
+    for persistent, graph in ((False, 0), (True, 0), (True, 6)):
+        b = S.Batch(cols, S.bubble_params(**_params()), precision=prec)
+        L.lbm_batch_set_persistent(b.handle, persistent)
+        if graph:
+            b.run(24, graph_steps=graph)
+        else:
+            b.step(24)
+        b.check()
+        if persistent:
+            assert L.lbm_batch_get_persistent(b.handle)[1] > 0
+        out.append(([b.populations(c).cpu().numpy() for c in range(len(cols))],
+                    b.bubbles.positions(), b.bubbles.velocities()))
+        b.close()
+    for o in out[1:]:
+        for a, r in zip(o[0], out[0][0]):
+            assert np.array_equal(a, r)
+        assert np.array_equal(o[1], out[0][1]) and np.array_equal(o[2], out[0][2])
 
 
 @pytest.mark.gpu
