@@ -286,8 +286,10 @@ lbm_status bubbles_step_static_work(lbm_ctx* ctx, const bubble_params* params,
  * Adjoint (reverse-mode derivative) of one method step, for gradients of a loss on bubble
  * trajectories with respect to drag_scale, lift_scale and omega. The caller keeps the forward
  * data of the step (a checkpoint-and-recompute schedule) and walks the steps backwards.
- * grad (device, 4 doubles, accumulated): [0] dL/domega through the collision, [1] dL/d drag_scale,
- * [2] dL/d lift_scale, [3] dL/dnu through the bubble closures (nu = (1/omega - 1/2)/3, eq. (9)).
+ * grad (device, 4 doubles, accumulated): [0] dL/domega, through the collision (lbm_adjoint_liquid)
+ * and through the bubble closures (lbm_adjoint_bubbles adds dL/dnu dnu/domega, nu = (1/omega - 1/2)/3,
+ * eq. (9)); [1] dL/d drag_scale, [2] dL/d lift_scale; [3] dL/dnu of the closures alone (already
+ * contained in [0]).
  * ------------------------------------------------------------------------------------------- */
 
 /* Doubles per bubble in a step record: [0, 21) x[3] u_b[3] u_l,prev[3] state u_l[3] w_l[3] psi[3]
@@ -307,6 +309,14 @@ lbm_status bubbles_step_static_work(lbm_ctx* ctx, const bubble_params* params,
  * soa->work. */
 lbm_status lbm_bubble_record(lbm_ctx* ctx, const bubble_soa* soa, int32_t nb, int32_t stage,
                              double* record);
+
+/* Trajectory recording for callers that run many steps without returning to the host between
+ * them (lbm_run, graph replays): from this call on, every bubble half writes each bubble's position
+ * after its update into the next row of traj (device, rows x 3 x nb doubles, row-major, a row
+ * component-major [a * nb + b]; inactive bubbles keep their position) until rows rows are written;
+ * the row counter is device memory and starts at 0 here. traj = NULL (rows 0) disarms. Drops the
+ * captured lbm_run() graph. LBM_EINVAL while a bubble half awaits its lbm_step(). */
+lbm_status lbm_record_positions(lbm_ctx* ctx, double* traj, int32_t rows);
 
 /* One-shot: the next bubbles_step() writes the whole step record of every bubble into record (nb x
  * LBM_BUBBLE_RECORD doubles, device, caller-owned), the sub-steps included when n_sub <= 32, from
@@ -330,7 +340,7 @@ lbm_status lbm_adjoint_liquid(lbm_ctx* ctx, const void* state, const void* force
  * lam_x (may be NULL): the loss's own dL/dx of the positions after the step, 3 x nb doubles
  * (component-major, [a * nb + b]), added to lam's dL/dx first (so a loss on every step's
  * positions needs no separate addition). grad[1..3] accumulate dL/d(drag_scale),
- * dL/d(lift_scale), dL/dnu. n_sub may be at most 32. */
+ * dL/d(lift_scale), dL/dnu, and grad[0] dL/dnu dnu/domega. n_sub may be at most 32. */
 lbm_status lbm_adjoint_bubbles(lbm_ctx* ctx, const bubble_params* params, const double* record,
                                const void* vel_prev, const void* lam_f, void* lam_u, double* lam,
                                const double* lam_x, int32_t nb, double* grad);

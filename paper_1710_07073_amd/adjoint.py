@@ -77,25 +77,23 @@ class TrajectoryProblem:
         return dict(state=self.state_tensor(sim).clone(), vel=sim.vel.clone(),
                     bub={k: sim.bubbles.t[k].clone() for k in _PRE + ("state",)})
 
-    @staticmethod
-    def _positions_into(sim, out):
-        # straight into the trajectory row (one kernel, no temporary and no device copy)
-        t = sim.bubbles.t
-        torch.stack([t["x"], t["y"], t["z"]], out=out)
-
     def forward(self, theta, checkpoints=True):
-        """Trajectory (steps, 3, nb) on the device, the simulation, and the checkpoints."""
+        """Trajectory (steps, 3, nb) on the device, the simulation, and the checkpoints. The steps
+        of each checkpoint segment run as one library call (lbm_run); the bubble update writes
+        the positions after every step into the trajectory itself (lbm_record_positions)."""
         caller = torch.cuda.current_stream(self.device)
         sim = self.make_sim(theta)
         traj = torch.empty((self.steps, 3, self.nb), dtype=torch.float64, device=self.device)
         ckpts = []
         self.stream.wait_stream(caller)
         with torch.cuda.stream(self.stream):
-            for k in range(self.steps):
-                if checkpoints and k % self.K == 0:
+            L.lbm_record_positions(sim.ctx, _p(traj), self.steps)
+            bub = sim.bubbles
+            for k0 in range(0, self.steps, self.K):
+                if checkpoints:
                     ckpts.append(self._save(sim))
-                sim.step(1)
-                self._positions_into(sim, traj[k])
+                L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, min(self.K, self.steps - k0), 0)
+            L.lbm_record_positions(sim.ctx, None, 0)
         caller.wait_stream(self.stream)
         return traj, sim, ckpts
 
@@ -107,7 +105,6 @@ class TrajectoryProblem:
             return self._backward(theta, sim, ckpts, grad_traj)
 
     def _backward(self, theta, sim, ckpts, grad_traj):
-        omega = float(theta[2])
         nb, K = self.nb, self.K
         pops = self.state_tensor(sim)
         dev = self.device
@@ -170,8 +167,9 @@ class TrajectoryProblem:
         # back to the simulation's own buffers before the segment buffers go away
         L.lbm_bind_buffers(sim.ctx, _p(sim.pops[0]), _p(sim.pops[1]), _p(sim.vel))
         g = grad.cpu().numpy()
-        # omega enters the collision directly and the bubble closures through nu = (1/omega - 1/2)/3
-        return np.array([g[1], g[2], g[0] + g[3] * (-1.0 / (3.0 * omega * omega))])
+        # grad[0] holds dL/domega through the collision and, added by the library, through the
+        # bubble closures' nu
+        return np.array([g[1], g[2], g[0]])
 
 
 class BubbleTrajectory(torch.autograd.Function):

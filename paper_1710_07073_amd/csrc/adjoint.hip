@@ -295,7 +295,8 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
                                                    const double* __restrict__ rec,
                                                    double* __restrict__ lam,
                                                    const double* __restrict__ lam_x, bubble_params P,
-                                                   Geom G, double nu, int nb, double* __restrict__ grad) {
+                                                   Geom G, double nu, double dnu_domega, int nb,
+                                                   double* __restrict__ grad) {
   __shared__ double w[3][kAdjSpan], dw[3][kAdjSpan], wx[3][kAdjSpan], dwx[3][kAdjSpan];
   __shared__ AxisW win[3];
   __shared__ int s_bad[3];
@@ -452,6 +453,8 @@ __global__ __launch_bounds__(kB) void k_adj_bubble(const T* __restrict__ lam_f,
     atomicAdd(&grad[1], g.dsD);
     atomicAdd(&grad[2], g.dsL);
     atomicAdd(&grad[3], g.dnu);
+    // omega reaches the closures through nu = (1/omega - 1/2)/3 (eq. (9))
+    atomicAdd(&grad[0], g.dnu * dnu_domega);
   }
   __syncthreads();
 
@@ -570,9 +573,10 @@ hipError_t bubbles_typed(lbm_ctx* c, const bubble_params* p, const double* rec, 
                          const void* lam_f, void* lam_u, double* lam, const double* lam_x, int32_t nb,
                          double* grad) {
   const double nu = (1.0 / c->desc.omega - 0.5) / 3.0;
+  const double dnu_domega = -1.0 / (3.0 * c->desc.omega * c->desc.omega);
   hipLaunchKernelGGL((k_adj_bubble<T>), dim3(nb), dim3(kB), 0, c->stream,
                      static_cast<const T*>(lam_f), static_cast<const T*>(vel_prev),
-                     static_cast<T*>(lam_u), rec, lam, lam_x, *p, c->geom, nu, nb, grad);
+                     static_cast<T*>(lam_u), rec, lam, lam_x, *p, c->geom, nu, dnu_domega, nb, grad);
   return hipGetLastError();
 }
 

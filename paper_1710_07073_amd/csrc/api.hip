@@ -16,7 +16,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t tiles[2], region[2], region_list[2], region_count, tcount, tlist, partials, result,
-      status, total;
+      status, traj_row, total;
   uint32_t ntiles, nred, tnx, tny, tnz;
 };
 
@@ -60,7 +60,8 @@ Layout layout_of(const lbm_desc* d) {
   L.partials = align_up(L.tlist + (size_t)L.ntiles * lbm::kTileCap * 4);
   L.result = align_up(L.partials + (size_t)L.nred * 4 * sizeof(double));
   L.status = align_up(L.result + 4 * sizeof(double));
-  L.total = align_up(L.status + sizeof(int32_t));
+  L.traj_row = align_up(L.status + sizeof(int32_t));
+  L.total = align_up(L.traj_row + sizeof(uint32_t));
   return L;
 }
 
@@ -155,6 +156,9 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->partials = reinterpret_cast<double*>(s + L.partials);
   c->result = reinterpret_cast<double*>(s + L.result);
   c->status = reinterpret_cast<int32_t*>(s + L.status);
+  c->traj = nullptr;
+  c->traj_rows = 0;
+  c->traj_row = reinterpret_cast<uint32_t*>(s + L.traj_row);
   c->nred = L.nred;
   c->bins_clean = false;
   c->stream = static_cast<hipStream_t>(stream);
@@ -222,6 +226,16 @@ lbm_status lbm_time_next_step(lbm_ctx* ctx, void* start, void* end) {
   if (!ctx) return LBM_EINVAL;
   ctx->t_start = static_cast<hipEvent_t>(start);
   ctx->t_end = static_cast<hipEvent_t>(end);
+  return LBM_OK;
+}
+
+lbm_status lbm_record_positions(lbm_ctx* ctx, double* traj, int32_t rows) {
+  if (!ctx || rows < 0 || (traj && rows == 0) || ctx->hs.pending) return LBM_EINVAL;
+  ctx->traj = traj;
+  ctx->traj_rows = traj ? rows : 0;
+  ctx->graph.reset();  // captured bubble kernels hold the previous setting
+  if (traj && lbm::launch_fill(ctx->traj_row, sizeof(uint32_t), ctx->stream) != hipSuccess)
+    return LBM_EDEVICE;
   return LBM_OK;
 }
 

@@ -45,7 +45,18 @@ struct BubbleArgs {
   int nb;
   int32_t* status;
   double* rec;  // armed step record (nb x R_SIZE), filled by the bubble update, or null
+  // trajectory recording: the update writes each bubble's position after the step into row
+  // *traj_row of traj (3 x nb doubles per row, [a * nb + b]) while the row is below traj_rows; the
+  // kernel that ends the bubble half then advances the row
+  double* traj;
+  int traj_rows;
+  uint32_t* traj_row;
 };
+
+// The bubble half's last kernel advances the trajectory row (every update of the step has run).
+__device__ __forceinline__ void advance_traj_row(const BubbleArgs& A) {
+  if (A.traj && blockIdx.x == 0 && threadIdx.x == 0) *A.traj_row += 1u;
+}
 
 __device__ __forceinline__ int wrapi(int i, int n) {
   i %= n;
@@ -773,7 +784,15 @@ __device__ bool ode_update(const Geo& geo, const BubbleArgs& A, int b, const Ode
     rec[R_VALID] = valid;
     rec[R_SUB] = 0.0;
   }
+  auto record_position = [&](const double* xp) {
+    if (A.traj) {
+      const uint32_t row = *A.traj_row;
+      if (row < (uint32_t)A.traj_rows)
+        for (int a = 0; a < 3; ++a) A.traj[(size_t)row * 3 * A.nb + (size_t)a * A.nb + b] = xp[a];
+    }
+  };
   if (st == 0 || valid == 0.0) {
+    record_position(xn);  // unchanged
     if (rec)
       for (int a = 0; a < 3; ++a) rec[R_PSI + a] = work[W_PSI + a];
     if (A.S.psix) {
@@ -868,6 +887,7 @@ __device__ bool ode_update(const Geo& geo, const BubbleArgs& A, int b, const Ode
   A.S.x[b] = xn[0];
   A.S.y[b] = xn[1];
   A.S.z[b] = xn[2];
+  record_position(xn);
   A.S.ux[b] = ub[0];
   A.S.uy[b] = ub[1];
   A.S.uz[b] = ub[2];
@@ -968,6 +988,7 @@ template <typename T, typename Geo>
 __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
   __shared__ double s_w[3][kSpan];
   __shared__ double s_dw[3][kSpan];
+  advance_traj_row(A);
   const int b = bubble_of_block(A.nb);
   const int tid = threadIdx.x;
   const ColumnView<T> col = geo.template view<T>(b);
@@ -1159,6 +1180,7 @@ __device__ void gather_tiles(const Geo& geo, const BubbleArgs& A, uint32_t first
 
 template <typename T, typename Geo>
 __global__ __launch_bounds__(kBlock) void k_spread_gather(Geo geo, BubbleArgs A) {
+  advance_traj_row(A);
   gather_tiles<T, Geo>(geo, A, blockIdx.x, gridDim.x);
 }
 
@@ -1375,6 +1397,9 @@ hipError_t launch_bubbles(lbm_ctx* c, const bubble_params* p, const bubble_soa* 
   A.status = c->status;
   A.rec = c->arm_record;  // one-shot
   c->arm_record = nullptr;
+  A.traj = c->traj;
+  A.traj_rows = c->traj_rows;
+  A.traj_row = c->traj_row;
   // this step's mask: the one the last liquid step cleared (cleared here if no liquid step ran)
   const int m = c->hs.flag_cur ^ 1;
   if (!c->hs.flag_clean[m]) {
@@ -1448,6 +1473,9 @@ hipError_t launch_bubbles_batch(const ManyColumns& geo, size_t elem, const bubbl
   A.nb = nb;
   A.status = status;
   A.rec = nullptr;
+  A.traj = nullptr;
+  A.traj_rows = 0;
+  A.traj_row = nullptr;
   if (elem == 4) return launch_bubble_kernels<float>(geo, A, stream);
   return launch_bubble_kernels<double>(geo, A, stream);
 }
@@ -1462,6 +1490,9 @@ hipError_t launch_batch_persistent(const ManyColumns& geo, size_t elem, const bu
   A.nb = nb;
   A.status = status;
   A.rec = nullptr;
+  A.traj = nullptr;
+  A.traj_rows = 0;
+  A.traj_row = nullptr;
   if (elem == 4) return launch_persistent_faces<float>(geo, A, P, wgs_per_cu, grid, stream);
   return launch_persistent_faces<double>(geo, A, P, wgs_per_cu, grid, stream);
 }

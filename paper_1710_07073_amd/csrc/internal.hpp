@@ -75,6 +75,10 @@ struct lbm_ctx {
   // device address of the library's own per-bubble workspace on this context's device
   // (bubbles_step_static_work), null if it could not be resolved
   double* static_work;
+  // trajectory recording (lbm_record_positions): rows of 3 x nb positions, the device row counter
+  double* traj;
+  int32_t traj_rows;
+  uint32_t* traj_row;
 };
 
 namespace lbm {

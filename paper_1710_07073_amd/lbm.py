@@ -40,7 +40,7 @@ EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch",
            "lbm_batch_column",
            "lbm_batch_check", "lbm_batch_destroy",
            "lbm_adjoint_liquid", "lbm_adjoint_bubbles", "lbm_bubble_record",
-           "lbm_record_next_bubble_half", "lbm_bind_buffers",
+           "lbm_record_next_bubble_half", "lbm_record_positions", "lbm_bind_buffers",
            "lbm_host_collide",
            "lbm_host_axis_weights", "lbm_host_bubble_ode", "lbm_host_bubble_ode_adjoint")
 
@@ -136,6 +136,7 @@ def lib():
         L.lbm_adjoint_bubbles.argtypes = [P, ct.POINTER(BubbleParams), P, P, P, P, P, P, ct.c_int32, P]
         L.lbm_bubble_record.argtypes = [P, ct.POINTER(BubbleSoA), ct.c_int32, ct.c_int32, P]
         L.lbm_record_next_bubble_half.argtypes = [P, P]
+        L.lbm_record_positions.argtypes = [P, P, ct.c_int32]
         L.lbm_bind_buffers.argtypes = [P, P, P, P]
         L.lbm_host_collide.argtypes = [D, D, ct.c_double, D, D, D, D, D, D, D]
         L.lbm_host_axis_weights.argtypes = [ct.c_double, ct.c_double, ct.c_int32, ct.c_int32,
@@ -390,6 +391,10 @@ def lbm_bubble_record(ctx, soa, nb, stage, record):
 
 def lbm_record_next_bubble_half(ctx, record):
     _ok(lib().lbm_record_next_bubble_half(ctx, record), "lbm_record_next_bubble_half")
+
+
+def lbm_record_positions(ctx, traj_ptr, rows):
+    _ok(lib().lbm_record_positions(ctx, traj_ptr, int(rows)), "lbm_record_positions")
 
 
 def lbm_bind_buffers(ctx, state=None, next_state=None, vel=None):

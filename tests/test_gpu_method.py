@@ -198,3 +198,45 @@ def test_spreading_list_overflow_is_reproducible_and_matches_oracle():
     assert np.array_equal(sim.populations().cpu().numpy(), g1)
     sim.check()
     sim.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("graph_steps", [0, 4])
+def test_recorded_trajectory_equals_step_by_step_positions(graph_steps):
+    """lbm_record_positions: the bubble update writes every step's positions into the trajectory
+    (device row counter, so graph replays record too); the rows equal the positions read after each
+    step of a step-by-step run, including a bubble that stops at the top, and recording stops at
+    the row limit."""
+    import torch
+    from paper_1710_07073_amd import lbm as L
+    rng = np.random.default_rng(12)
+    nb = 5
+    pos = np.stack([rng.uniform(6, 18, nb), rng.uniform(6, 18, nb), rng.uniform(6, 20, nb)])
+    pos[2, 0] = 22.6  # reaches the top layer (z >= 23) within the run
+    d = rng.uniform(2.0, 3.0, nb)
+    kw = dict(g=1e-2, sigma=1e-3)
+    steps, rows = 24, 20
+    print(f"[case] trajectory recording, graph_steps {graph_steps}", flush=True)
+    a = S.Simulation((24, 24, 24), 1.3, precision="f64")
+    a.add_bubbles(pos, d, S.bubble_params(**kw))
+    ref = []
+    for _ in range(steps):
+        a.step(1)
+        ref.append(a.bubbles.positions())
+    b = S.Simulation((24, 24, 24), 1.3, precision="f64")
+    b.add_bubbles(pos, d, S.bubble_params(**kw))
+    traj = torch.full((rows, 3, nb), -1.0, dtype=torch.float64, device="cuda")
+    L.lbm_record_positions(b.ctx, ctypes_ptr(traj), rows)
+    b.run(steps, graph_steps=graph_steps)
+    L.lbm_record_positions(b.ctx, None, 0)
+    got = traj.cpu().numpy()
+    assert np.array_equal(got, np.stack(ref[:rows]))
+    assert np.array_equal(b.bubbles.positions(), ref[-1])
+    assert b.bubbles.state()[0] == 0 and a.bubbles.state()[0] == 0
+    a.close()
+    b.close()
+
+
+def ctypes_ptr(t):
+    import ctypes as ct
+    return ct.c_void_p(t.data_ptr())
