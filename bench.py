@@ -256,7 +256,7 @@ def bench_stability(args):
 
 def swarm_map(stream, steps=3000, chunk=250):
     """Stability map over omega and forcing (Sec. 4.3 with the forcing made strong): the App. A
-    column (30 x 30 x 90, free-slip top) holding swarms of 8 to 1024 bubbles at g = 3e-2, one
+    column (30 x 30 x 90, free-slip top) holding swarms of 16 to 768 bubbles at g = 3e-2, one
     column per (omega, swarm size), 64 columns in one batch, FP32; a column is unstable once its
     FP64 sums are not finite (checked every `chunk` steps)."""
     import workloads as W

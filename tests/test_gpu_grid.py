@@ -9,7 +9,9 @@ bubble in water at omega up to 1.99999, where BGK is barely damped.
   with resolution and converges: each refinement changes it by less than half the previous
   change.
 * The terminal-velocity sweep (Sec. 4.1, Table 4): 2 to 10 mm at aspect ratio 1.25, slip equal
-  to the force balance for every diameter.
+  to the force balance for every diameter and to Mendelson's closed form (eq. (25)).
+* The relative velocity over time (eq. (22)): the 4 mm bubble's u_b - u_l from release against
+  the solution of the relative-velocity equation with the coupled run's effective mass.
 """
 import numpy as np
 import pytest
@@ -54,6 +56,11 @@ def test_physical_column_matches_oracle(name, dtype):
     assert v[2, 0] > 0
 
 
+def _mendelson(d):
+    """Mendelson's terminal velocity (eq. (25)), SI units, water and air of Table 3."""
+    return float(np.sqrt(2.0 * W.WATER_SIGMA / (W.WATER_RHO * d) + W.GRAVITY * d / 2.0))
+
+
 def _ode_terminal(w):
     """Terminal rise velocity (lattice units) of the oracle's bubble ODE in a quiescent liquid."""
     P = O.bubble_params(**w.params)
@@ -88,8 +95,11 @@ def test_slip_velocity_is_the_force_balance_for_2_to_10_mm():
         scale = w.meta["tcf"] / w.meta["lcf"]
         rise, slip = np.mean(ub) * scale, (np.mean(ub) - np.mean(ul)) * scale
         vt = _ode_terminal(w) * scale
-        print(f"rise {rise:.5f}, slip {slip:.5f}, ODE terminal {vt:.5f} m/s", flush=True)
+        vm = _mendelson(w.meta["d_mm"] * 1e-3)
+        print(f"rise {rise:.5f}, slip {slip:.5f}, ODE terminal {vt:.5f}, Mendelson {vm:.5f} m/s",
+              flush=True)
         assert abs(slip - vt) <= 1e-3 * vt
+        assert abs(slip - vm) <= 1e-3 * vm
         assert vt < rise <= 1.05 * vt
 
 
@@ -128,3 +138,49 @@ def test_slip_velocity_grid_independent_and_rise_velocity_converges():
     d1, d2 = rise[1] - rise[0], rise[2] - rise[1]
     assert d1 > 0 and d2 > 0 and d2 < 0.5 * d1
     assert np.all(rise <= 1.05 * vt_ode)
+
+
+@pytest.mark.gpu
+def test_relative_velocity_follows_eq22():
+    """Sec. 4.1, eq. (22): the relative velocity v_r = u_b - u_l of the 4 mm bubble released from
+    rest (Table 5 column, aspect ratio 1.25, FP64) against the solution of
+    m dv_r/dt = F_B + F_D(v_r), with m the effective mass m_b + C_A rho_l V of the coupled run
+    (eq. (4) with the added mass on the left, reading R7), integrated by scipy with the oracle's
+    drag closure (Table 1). The coupled run differs from that equation by the acceleration of the
+    liquid at the bubble it entrains, (rho_l V - m_b) du_l/dt on the right."""
+    from scipy.integrate import solve_ivp
+    w = _with(CASES["grid_4mm_ar1.25"], 600, "f64")
+    print(f"[case] eq. (22) on {w.name} {w.shape}: {w.steps} steps", flush=True)
+    sim = gpu_sim(w)
+    vr = []
+    for _ in range(w.steps):
+        sim.step(1)
+        vr.append(sim.bubbles.velocities()[2, 0] - sim.bubbles.liquid_velocity()[2, 0])
+    sim.check()
+    sim.close()
+    vr = np.array(vr)
+    P = O.bubble_params(**w.params)
+    p = w.params
+    d = float(w.d[0])
+    nu = (1.0 / w.omega - 0.5) / 3.0
+    V = np.pi * d ** 3 / 6.0
+    m = p["rho_b"] * V + p["c_a"] * p["rho_l"] * V
+    FB = (p["rho_l"] - p["rho_b"]) * V * p["g"]
+
+    def rhs(t, y):
+        cdu, _, _ = O.closures(P, nu, d, abs(y[0]))
+        return [(FB - np.pi * d * d / 8.0 * p["rho_l"] * cdu * y[0]) / m]
+
+    # v_r after liquid step k (k = 1..steps) is the equation's value at t = k - 1: the first
+    # step's bubble half starts the bubble from rest
+    t = np.arange(w.steps, dtype=np.float64)
+    sol = solve_ivp(rhs, (0.0, t[-1] + 1.0), [0.0], t_eval=t + 1.0, rtol=1e-10, atol=1e-14)
+    ve = sol.y[0]
+    vt = _ode_terminal(w)
+    dev = np.abs(vr - ve) / vt
+    t63 = lambda v: np.argmax(v >= 0.632 * vt)
+    print(f"v_T {vt:.4e} lu; max |v_r - eq.(22)| {dev.max():.3e} v_T; 63 % rise at step "
+          f"{t63(vr)} (eq. (22): {t63(ve)}); v_r / v_T at the end {vr[-1] / vt:.4f}", flush=True)
+    # measured: 5.2e-3 of v_T at most, 63 % of v_T one step before the equation
+    assert dev.max() <= 0.015
+    assert abs(t63(vr) - t63(ve)) <= 3

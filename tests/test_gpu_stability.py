@@ -81,3 +81,25 @@ def test_batch_flags_only_the_unstable_swarm_column():
     assert list(diverged) == [False, False, False, True]
     assert np.all(np.abs(sums[:3, 0] - np.array([w.cells for w in ws[:3]])) < 1e-2)
     batch.close()
+
+
+@pytest.mark.gpu
+def test_swarm_of_384_reproduces_the_papers_stability_limit():
+    """Sec. 4.3 (Fig. 5): stable up to omega = 1.97, unstable at 1.98. The App. A column (30 x 30 x
+    90, free-slip top) with the 384-bubble swarm of the stability map, FP32 batch (bit-reproducible
+    spreading): the column at 1.98 diverges within 2000 steps, those at 1.96 and 1.97 do not."""
+    omegas = (1.96, 1.97, 1.98)
+    ws = [w for w in W.stability_swarm(steps=2000, omegas=omegas, counts=(384,))]
+    print(f"[case] 384-bubble swarm, App. A column, omega {omegas}", flush=True)
+    cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d) for w in ws]
+    batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32")
+    first = [None] * len(ws)
+    for done in range(250, 2001, 250):
+        batch.run(250, graph_steps=50)
+        _, diverged = batch.sums()
+        for k, dv in enumerate(diverged):
+            if dv and first[k] is None:
+                first[k] = done
+    print(f"first flagged step per column: {first}", flush=True)
+    assert first[0] is None and first[1] is None and first[2] is not None
+    batch.close()

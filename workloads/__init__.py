@@ -183,13 +183,13 @@ def swarm(nb=32, omega=1.995, shape=(16, 16, 48), g=SWARM_G, seed=5, bc=(BB,) * 
                     meta=dict(nb=nb))
 
 
-SWARM_OMEGAS = (1.95, 1.96, 1.97, 1.975, 1.98, 1.985, 1.99, 1.995)
-SWARM_COUNTS = (8, 16, 32, 64, 128, 256, 512, 1024)
+SWARM_OMEGAS = (1.90, 1.93, 1.95, 1.96, 1.97, 1.98, 1.99, 1.995)
+SWARM_COUNTS = (16, 64, 256, 320, 384, 448, 512, 768)
 
 
 def stability_swarm(steps=3000, omegas=SWARM_OMEGAS, counts=SWARM_COUNTS):
     """The stability map (Sec. 4.3) over omega and forcing: the App. A column (30 x 30 x 90,
-    bounce-back walls and bottom, free-slip top) holding a swarm of 8 to 1024 bubbles (the forcing
+    bounce-back walls and bottom, free-slip top) holding a swarm of 16 to 768 bubbles (the forcing
     axis: one batch shares g, so the swarm size varies), one column per (omega, swarm size)."""
     return [swarm(nb=n, omega=om, shape=(30, 30, 90), bc=(BB, BB, BB, BB, BB, FS), steps=steps,
                   dtype="f32", seed=SEED + n)
