@@ -194,7 +194,20 @@ def leg_batched(args, steps):
                               "bubble_pos_max_abs": err_x}}
 
 
+def copy_calibration():
+    """One device copy of 1 GiB (torch copy_): the HBM counters of the same run read it as a
+    reference for the scale of the kernels' counters."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)  # 1 GiB read + 1 GiB write
+    torch.cuda.synchronize()
+
+
 def bench_batched(args):
+    if args.copy_calibration:
+        copy_calibration()
     leg = leg_batched(args, args.steps)
     out = {
         "metric": METRIC, "value": leg["batched_f32_mlups"], "unit": "MLUPS", "n_gpus": 1,
@@ -622,6 +635,9 @@ def main():
                     help="vec,block_x[,workgroups_per_cu] of the liquid step (skips tuning)")
     ap.add_argument("--layout", default="plane", choices=["plane", "soa"],
                     help="population buffer layout: plane-blocked (default) or plain structure of arrays")
+    ap.add_argument("--top", default="bounce-back", choices=["bounce-back", "free-slip"],
+                    help="top face of the single-lattice workloads (free-slip: the paper's face set, "
+                         "Sec. 3.3)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the bubble kernels and the liquid step one after the other")
     ap.add_argument("--no-legs", action="store_true",
@@ -653,6 +669,9 @@ def main():
     if args.workload == "terminal":
         return bench_terminal(args)
     w = {"single_fp32": W.single_fp32, "plain_fp64": W.plain_fp64, "dense": W.dense}[args.workload]()
+    if args.top == "free-slip":
+        w = W.Workload(w.name + "_fstop", w.shape, w.omega, tuple(w.bc[:5]) + (W.FS,), w.pos, w.d,
+                       w.params, w.steps, w.dtype)
     if args.precision:
         w = W.Workload(w.name.replace("fp32", args.precision).replace("fp64", args.precision),
                        w.shape, w.omega, w.bc, w.pos, w.d, w.params, w.steps, args.precision)
@@ -701,10 +720,7 @@ def main():
         sim.step(1)
     warm_done = tune_steps + args.warmup
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        b.copy_(a)  # 1 GiB read + 1 GiB write
+        copy_calibration()
     torch.cuda.synchronize()
 
     K = args.steps
@@ -772,7 +788,8 @@ def main():
         "overlap": {"enabled": overlap_on and overlap_avail, "region_sites_last_step": region_cells},
         "mass_drift": sums[0] - w.cells,
     }
-    legs = args.workload == "single_fp32" and not args.no_legs and not args.precision
+    legs = (args.workload == "single_fp32" and not args.no_legs and not args.precision
+            and args.top == "bounce-back")
     if legs:
         print("[bench] precision leg", file=sys.stderr, flush=True)
         out["precision"] = leg_precision(w, sim, warm_done + K)

@@ -240,3 +240,24 @@ def test_recorded_trajectory_equals_step_by_step_positions(graph_steps):
 def ctypes_ptr(t):
     import ctypes as ct
     return ct.c_void_p(t.data_ptr())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_neutrally_buoyant_bubble_follows_a_uniformly_accelerating_liquid(prec):
+    """The oracle pin of the fluid-acceleration terms (test_oracle_method) on the GPU: the liquid
+    velocity each bubble half reads is prescribed uniform, growing by a every step; a neutrally
+    buoyant bubble without drag then moves at (n - 1) a after step n."""
+    a = np.array([2e-4, -1e-4, 3e-4])
+    sim = S.Simulation((16, 16, 16), 1.2, precision=prec, bc=(2,) * 6)
+    sim.add_bubbles(np.array([[7.3], [8.1], [6.7]]), [2.0],
+                    S.bubble_params(rho_b=1.0, drag_scale=0.0, g=1e-3, sigma=1e-3))
+    tol = 1e-15 if prec == "f64" else 1e-8  # the liquid velocity is stored in the lattice type
+    for n in range(1, 13):
+        sim.vel.copy_(torch.tensor(a * n, dtype=sim.dtype, device="cuda")[:, None, None, None]
+                      .expand_as(sim.vel))
+        sim.step(1)
+        v = sim.bubbles.velocities()[:, 0]
+        assert np.allclose(v, (n - 1) * a, rtol=0, atol=tol), (n, v)
+    sim.check()
+    sim.close()

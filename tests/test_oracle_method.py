@@ -64,3 +64,33 @@ def test_bubble_deactivates_at_top_and_stops_forcing():
     z_stop = bub.pos[2, 0]
     psi2 = O.method_step(lat, P, bub)
     assert np.all(psi2 == 0) and bub.pos[2, 0] == z_stop
+
+
+def test_neutrally_buoyant_bubble_follows_a_uniformly_accelerating_liquid():
+    """Pins the fluid-acceleration terms of the bubble ODE in the coupled step (readings R7, R9): a
+    neutrally buoyant bubble (rho_b = rho_l) without drag in a liquid whose velocity grows by the
+    same vector a every step accelerates exactly with the liquid, since the stress-gradient and
+    added-mass force (1 + C_A) rho_l V D_t u_l equals m_eff a with m_eff = (rho_b + C_A rho_l) V.
+    The liquid velocity of each step is prescribed (the field the previous collision leaves,
+    uniform in a periodic box, so the interpolated vorticity is exactly 0); D_t u_l is the change
+    of the interpolated velocity since the previous step and 0 on the bubble's first step. So after
+    step n the bubble moves at (n - 1) a, and its position gains dt_b sum of its sub-step
+    velocities."""
+    a = np.array([2e-4, -1e-4, 3e-4])
+    lat = O.Lattice(8, 8, 8, 1.2, (PER,) * 6)
+    x0 = np.array([3.3, 4.1, 2.7])
+    bub = O.Bubbles(pos=x0.reshape(3, 1), d=[2.0])
+    P = _params(rho_b=1.0, drag_scale=0.0, g=1e-3, sigma=1e-3)
+    x = x0.copy()
+    for n in range(1, 13):
+        lat.U[:] = (a * n)[:, None, None, None]  # the liquid velocity this step's bubble half reads
+        O.method_step(lat, P, bub)
+        v_expect = (n - 1) * a
+        assert np.allclose(bub.vel[:, 0], v_expect, rtol=0, atol=1e-15)
+        # ten sub-steps of dt_b = 0.1, each moving the bubble by dt_b times its new velocity, which
+        # gains a / 10 per sub-step from (n - 2) a: sum_k 0.1 ((n - 2) a + k a / 10) over k = 1..10
+        # is (n - 1) a - 0.45 a (no motion on the first step)
+        if n > 1:
+            x = x + v_expect - 0.45 * a
+        assert np.allclose(bub.pos[:, 0], np.mod(x, 8.0), rtol=0, atol=1e-12)
+        assert np.allclose(bub.ulp[:, 0], a * n, rtol=0, atol=1e-16)
