@@ -8,7 +8,7 @@
 //             liquid step must force, or must write the velocity in;
 //   k_spread  (one bubble: one workgroup) the backward coupling (eq. (21)) of the reaction into
 //             the force field with the same weights (atomic adds) and the tile flags, or
-//   k_spread_gather (several bubbles: one workgroup per tile) the same sums per cell in bubble
+//   k_spread_gather (several bubbles: one wavefront per tile) the same sums per cell in bubble
 //             order from the lists, so that the force field is bit-reproducible.
 // Up to 256 bubbles on one lattice (not in the exact-time variant) k_interp's workgroup also runs
 // k_ode's update of its bubble on one lane and flags the bubble's tiles, and k_ode is not launched.
@@ -1010,11 +1010,11 @@ __global__ __launch_bounds__(kBlock) void k_spread(Geo geo, BubbleArgs A) {
 // k_interp enters each bubble in the list of every tile of its force window at x0 (kTileCap
 // entries per tile; the count keeps rising past a full list), the bubble update (k_ode, or
 // k_interp itself with few bubbles) flags the bubble's tiles for the liquid step, and
-// k_spread_gather, one workgroup per tile, sums psi_b W_b(j) over the tile's
+// k_spread_gather, one wavefront per tile, sums psi_b W_b(j) over the tile's
 // bubbles in bubble order in double precision with the weights k_interp stored at x0. A tile
 // whose list overflowed finds its bubbles by a scan of all bubbles in index order instead, so the
 // sum has the same terms in the same order either way. F(j) does not depend on the order in
-// which workgroups ran; with one bubble per cell the sum is the atomic path's single addition,
+// which wavefronts ran; with one bubble per cell the sum is the atomic path's single addition,
 // bit for bit.
 // Sum of the weights of axis a (global copy, indexed cell - lo + 1) at the window cells congruent
 // to cell v (one cell unless a periodic window is wider than the lattice).
@@ -1066,122 +1066,147 @@ __device__ __forceinline__ GatherJob<T> gather_job(const ManyColumns& geo, const
           C.bubble_begin + C.nb};
 }
 
-// The jobs first, first + stride, ... of the step's gather, by the whole workgroup.
+// Bubbles staged at once in the gather: 8 bubbles x kTile cells, one per lane of a wavefront.
+constexpr uint32_t kGatherChunk = 64 / kTile;
+
+// Value of v in lane l (l the same in every lane).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// One staged bubble as one lane of the wavefront holds it: the bubble's weights at the i-th cell
+// of the tile along each axis, and its reaction component i mod 3.
+struct GatherLane {
+  double wx, wy, wz, psi;
+};
+
+__device__ __forceinline__ GatherLane gather_lane(const Geom& G, const BubbleArgs& A, uint32_t b,
+                                                  bool valid, int i, const int org[3],
+                                                  const bool per[3]) {
+  GatherLane s = {0.0, 0.0, 0.0, 0.0};
+  if (!valid) return s;
+  const double* work = A.S.work + (size_t)b * kWork;
+  const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+  s.psi = work[W_PSI + i % 3];
+  Axis win[3];
+  force_windows(G, x0, A.P.kernel_factor * A.S.d[b], win);  // valid: the bubble was listed
+  s.wx = axis_weight_at(win[0], work + W_WGT, org[0] + i, G.nx, per[0]);
+  s.wy = axis_weight_at(win[1], work + W_WGT + kSpan, org[1] + i, G.ny, per[1]);
+  s.wz = axis_weight_at(win[2], work + W_WGT + 2 * kSpan, org[2] + i, G.nz, per[2]);
+  return s;
+}
+
+// The jobs first, first + stride, ... of the step's gather, one per wavefront (first and stride
+// count wavefronts). Lane (lx, ly) = (lane mod kTile, lane / kTile) holds the tile's column of
+// kTile cells along z and their 24 sums in registers. The tile's bubbles, in index order (the
+// list sorted by rank, or the overflow scan compacted by ballot), are staged kGatherChunk at a
+// time: lane (k, i) loads the chunk's k-th bubble and forms its weights at the tile's i-th cell of
+// each axis; every lane then adds the chunk's terms in order, reading its cells' weights from the
+// lanes that hold them. The terms and their order per cell are those of the eq. (21) sum in
+// bubble order; only lanes whose cells exist store.
 template <typename T, typename Geo>
 __device__ void gather_tiles(const Geo& geo, const BubbleArgs& A, uint32_t first, uint32_t stride) {
-  static_assert(kTileCap == 64, "one wavefront compacts a chunk of the overflow scan");
-  __shared__ uint32_t s_list[kTileCap];
-  __shared__ uint32_t s_sorted[kTileCap];
-  __shared__ Axis s_win[kTileCap][3];
-  __shared__ double s_psi[kTileCap][3];
-  __shared__ uint32_t s_n;
-  const int tid = threadIdx.x;
+  static_assert(kTileCap == 64 && kTile == 8, "a wavefront holds a tile's list and its 8 x 8 columns");
+  const int lane = (int)(threadIdx.x & 63u);
+  const int lx = lane % (int)kTile, ly = lane / (int)kTile;
+  const uint64_t below = (1ull << lane) - 1ull;
   const uint32_t njobs = gather_jobs(geo);
   for (uint32_t j = first; j < njobs; j += stride) {
     const GatherJob<T> J = gather_job<T>(geo, A, j);
     const Geom& G = J.G;
     const uint32_t t = J.t;
     const uint32_t cnt = J.tcount[t];
-    if (cnt == 0u) continue;  // uniform over the workgroup
+    if (cnt == 0u) continue;  // uniform over the wavefront
     const uint32_t tx = t % (uint32_t)G.tnx, rr = t / (uint32_t)G.tnx;
     const uint32_t ty = rr % (uint32_t)G.tny, tz = rr / (uint32_t)G.tny;
-    const int x = (int)(tx * kTile + (tid & 7)), y = (int)(ty * kTile + ((tid >> 3) & 7));
-    const int z0 = (int)(tz * kTile + (tid >> 6));
-    const bool inside = x < G.nx && y < G.ny;
-    const bool px = G.bc[0] == BC_PER, py = G.bc[2] == BC_PER, pz = G.bc[4] == BC_PER;
-    // bubble b's force window and reaction into slot k of the staged chunk
-    auto stage = [&](uint32_t b, int k) {
-      const double* work = A.S.work + (size_t)b * kWork;
-      const double xb[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
-      Axis win[3];
-      force_windows(G, xb, A.P.kernel_factor * A.S.d[b], win);  // valid: the bubble was listed
-      for (int a = 0; a < 3; ++a) {
-        s_win[k][a] = win[a];
-        s_psi[k][a] = work[W_PSI + a];
-      }
-    };
-    double acc[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    // adds the terms of the n staged bubbles s_sorted[0..n), in that order
-    auto add = [&](uint32_t n) {
-      if (!inside) return;
-      for (uint32_t k = 0; k < n; ++k) {
-        const double* wk = A.S.work + (size_t)s_sorted[k] * kWork + W_WGT;
-        const double wx = axis_weight_at(s_win[k][0], wk, x, G.nx, px);
-        const double wy = axis_weight_at(s_win[k][1], wk + kSpan, y, G.ny, py);
-        for (int h = 0; h < 2; ++h) {
-          const double wz = axis_weight_at(s_win[k][2], wk + 2 * kSpan, z0 + 4 * h, G.nz, pz);
-          const double W = wx * wy * wz;
-          for (int q = 0; q < 3; ++q) acc[h][q] += s_psi[k][q] * W;
+    const int org[3] = {(int)(tx * kTile), (int)(ty * kTile), (int)(tz * kTile)};
+    const bool per[3] = {G.bc[0] == BC_PER, G.bc[2] == BC_PER, G.bc[4] == BC_PER};
+    double acc[kTile][3];
+#pragma unroll
+    for (int i = 0; i < (int)kTile; ++i) acc[i][0] = acc[i][1] = acc[i][2] = 0.0;
+    // adds the terms of the n bubbles lanes 0..n-1 of ids name, in that order
+    auto add = [&](uint32_t ids, uint32_t n) {
+      for (uint32_t k0 = 0; k0 < n; k0 += kGatherChunk) {
+        const uint32_t m = min(n - k0, kGatherChunk);
+        const int ck = ly, ci = lx;  // this lane stages cell ci of the chunk's bubble ck
+        const uint32_t b = (uint32_t)__shfl((int)ids, (int)k0 + ck, 64);
+        const GatherLane st = gather_lane(G, A, b, (uint32_t)ck < m, ci, org, per);
+        for (uint32_t k = 0; k < m; ++k) {
+          const int l0 = (int)(k * kTile);
+          const double wx = __shfl(st.wx, l0 + lx, 64);
+          const double wy = __shfl(st.wy, l0 + ly, 64);
+          const double psi[3] = {lane_value(st.psi, l0), lane_value(st.psi, l0 + 1),
+                                 lane_value(st.psi, l0 + 2)};
+#pragma unroll
+          for (int i = 0; i < (int)kTile; ++i) {
+            const double wz = lane_value(st.wz, l0 + i);
+            const double W = wx * wy * wz;
+            for (int q = 0; q < 3; ++q) acc[i][q] += psi[q] * W;
+          }
         }
       }
     };
     if (cnt <= kTileCap) {
       const uint32_t n = cnt;
-      if (tid < (int)n) s_list[tid] = J.tlist[(size_t)t * kTileCap + tid];
-      __syncthreads();
-      if (tid < (int)n) {  // rank sort (ties, which the lists do not hold, would keep list order)
-        const uint32_t v = s_list[tid];
-        uint32_t r = 0;
-        for (uint32_t i = 0; i < n; ++i) r += (s_list[i] < v || (s_list[i] == v && i < (uint32_t)tid)) ? 1u : 0u;
-        s_sorted[r] = v;
+      const uint32_t v = (uint32_t)lane < n ? J.tlist[(size_t)t * kTileCap + lane] : 0xffffffffu;
+      // rank of the lane's entry (ties, which the lists do not hold, would keep list order); the
+      // lanes past the list keep their own index, so the ranks are a permutation of the lanes
+      uint32_t r = 0;
+      for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t vi = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)i);
+        r += (vi < v || (vi == v && i < (uint32_t)lane)) ? 1u : 0u;
       }
-      __syncthreads();
-      if (tid < (int)n) stage(s_sorted[tid], tid);
-      __syncthreads();
-      add(n);
+      if ((uint32_t)lane >= n) r = (uint32_t)lane;
+      add((uint32_t)__builtin_amdgcn_ds_permute((int)(r * 4u), (int)v), n);
     } else {
       // the list overflowed: every bubble whose force window holds this tile, by a scan of the
-      // lattice's bubbles in index order, one chunk of 64 per pass compacted by the first wavefront
-      for (int base = J.b0; base < J.b1; base += kTileCap) {
-        if (tid < kTileCap) {
-          const int b = base + tid;
-          bool cov = false;
-          if (b < J.b1) {
-            const double* work = A.S.work + (size_t)b * kWork;
-            if (work[W_VALID] != 0.0) {
-              const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
-              Axis win[3];
-              if (force_windows(G, x0, A.P.kernel_factor * A.S.d[b], win)) {
-                TileRanges tr[3];
-                force_tiles(G, win, tr);
-                cov = in_tile_ranges(tr[0], (int)tx) && in_tile_ranges(tr[1], (int)ty) &&
-                      in_tile_ranges(tr[2], (int)tz);
-              }
+      // lattice's bubbles in index order, 64 per pass compacted by ballot
+      for (int base = J.b0; base < J.b1; base += 64) {
+        const int b = base + lane;
+        bool cov = false;
+        if (b < J.b1) {
+          const double* work = A.S.work + (size_t)b * kWork;
+          if (work[W_VALID] != 0.0) {
+            const double x0[3] = {work[W_X0], work[W_X0 + 1], work[W_X0 + 2]};
+            Axis win[3];
+            if (force_windows(G, x0, A.P.kernel_factor * A.S.d[b], win)) {
+              TileRanges tr[3];
+              force_tiles(G, win, tr);
+              cov = in_tile_ranges(tr[0], (int)tx) && in_tile_ranges(tr[1], (int)ty) &&
+                    in_tile_ranges(tr[2], (int)tz);
             }
           }
-          const uint64_t m = __ballot(cov);
-          if (cov) {
-            const int k = __popcll(m & ((1ull << tid) - 1ull));
-            s_sorted[k] = (uint32_t)b;
-            stage((uint32_t)b, k);
-          }
-          if (tid == 0) s_n = (uint32_t)__popcll(m);
         }
-        __syncthreads();
-        add(s_n);
-        __syncthreads();
+        const uint64_t mask = __ballot(cov);
+        const uint32_t nc = (uint32_t)__popcll(mask);
+        const uint32_t pos = cov ? (uint32_t)__popcll(mask & below)
+                                 : nc + (uint32_t)__popcll(~mask & below);
+        add((uint32_t)__builtin_amdgcn_ds_permute((int)(pos * 4u), b), nc);
       }
     }
-    if (inside) {
-      for (int h = 0; h < 2; ++h) {
-        const int z = z0 + 4 * h;
-        if (z >= G.nz) continue;
+    const int x = org[0] + lx, y = org[1] + ly;
+    if (x < G.nx && y < G.ny) {
+      for (int i = 0; i < (int)kTile; ++i) {
+        const int z = org[2] + i;
+        if (z >= G.nz) break;
         const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
-        J.F[c] = (T)acc[h][0];
-        J.F[G.N + c] = (T)acc[h][1];
-        J.F[2 * (size_t)G.N + c] = (T)acc[h][2];
+        J.F[c] = (T)acc[i][0];
+        J.F[G.N + c] = (T)acc[i][1];
+        J.F[2 * (size_t)G.N + c] = (T)acc[i][2];
       }
     }
-    // every thread has read the count and the shared arrays: the next job may reuse them
-    __syncthreads();
-    if (tid == 0) J.tcount[t] = 0u;
+    // every lane has read the count
+    if (lane == 0) J.tcount[t] = 0u;
   }
 }
 
 template <typename T, typename Geo>
 __global__ __launch_bounds__(kBlock) void k_spread_gather(Geo geo, BubbleArgs A) {
   advance_traj_row(A);
-  gather_tiles<T, Geo>(geo, A, blockIdx.x, gridDim.x);
+  gather_tiles<T, Geo>(geo, A, blockIdx.x * kBlockWaves + threadIdx.x / 64, gridDim.x * kBlockWaves);
 }
 
 // Region of an overlapped step (one wavefront per bubble): the tile rows (y, z) of the bubble's
@@ -1222,7 +1247,7 @@ __global__ __launch_bounds__(64) void k_mark(Geo geo, BubbleArgs A, uint32_t* __
     }
 }
 
-// Workgroups of the many-column gather (each takes the noted tiles in turn).
+// Workgroups of the many-column gather (their wavefronts take the noted tiles in turn).
 constexpr uint32_t kGatherMaxBlocks = 2048;
 
 // Bubble counts up to which k_interp keeps 8 cells' loads in flight per thread: one workgroup per
@@ -1266,7 +1291,8 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
     }
     if (geo.lists) {  // several bubbles: the lists k_interp filled, summed per tile
       const uint32_t ntiles = (uint32_t)geo.G.tnx * geo.G.tny * div_up(geo.G.nz, kTile);
-      hipLaunchKernelGGL((k_spread_gather<T, OneColumn>), dim3(ntiles), dim3(kBlock), 0, stream,
+      hipLaunchKernelGGL((k_spread_gather<T, OneColumn>), dim3(div_up(ntiles, kBlockWaves)),
+                         dim3(kBlock), 0, stream,
                          geo, A);
       return hipGetLastError();
     }
@@ -1274,7 +1300,8 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
     return hipGetLastError();
   } else {
     // many columns: the tiles noted this step, gathered by the workgroups in turn
-    const uint32_t blocks = std::max(1u, std::min(geo.job_cap, kGatherMaxBlocks));
+    const uint32_t blocks =
+        std::max(1u, std::min(div_up(geo.job_cap, (uint32_t)kBlockWaves), kGatherMaxBlocks));
     hipLaunchKernelGGL((k_spread_gather<T, ManyColumns>), dim3(blocks), dim3(kBlock), 0, stream,
                        geo, A);
     return hipGetLastError();
@@ -1346,7 +1373,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch_persistent(ManyColumns geo,
         __syncthreads();  // the next bubble reuses the workgroup's shared arrays
       }
       if (!grid_barrier(P.barrier, gridDim.x, P.spin_limit, A.status)) return;
-      gather_tiles<T, ManyColumns>(g, A, blockIdx.x, gridDim.x);
+      gather_tiles<T, ManyColumns>(g, A, blockIdx.x * kBlockWaves + threadIdx.x / 64,
+                                   gridDim.x * kBlockWaves);
       if (!grid_barrier(P.barrier, gridDim.x, P.spin_limit, A.status)) return;
     }
     for (uint32_t k = blockIdx.x; k < P.nitems; k += gridDim.x)
