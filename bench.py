@@ -108,7 +108,7 @@ def leg_batched(args, steps):
     cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d) for w in ws]
     stream = torch.cuda.current_stream()
     cells = sum(w.cells for w in ws)
-    gsteps = args.graph_steps or 20
+    gsteps = args.graph_steps or 100
     batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
     items = occ = None
     if not args.no_autotune:
@@ -192,6 +192,72 @@ def leg_batched(args, steps):
             "error_vs_fp64": {"after_steps": total, "columns_checked": [0, 17, 40, 63],
                               "populations_rel_l2_max": err_g,
                               "bubble_pos_max_abs": err_x}}
+
+
+def time_steps(sim, K, stream):
+    """Runs K method steps of a single-lattice simulation; returns the wall time, the mean duration
+    of the fused step's launch that updates the lattice away from the bubbles (recorded by the
+    library on the stream it runs on: the side stream when the step is overlapped), the number of
+    launches timed and the region of the last overlapped step (sites)."""
+    import torch
+    from paper_1710_07073_amd import lbm as L
+
+    # every EVERY-th launch is timed (a timing event record costs several microseconds of the
+    # queue); the steps run through lbm_run in runs of EVERY, the first of which is timed
+    EVERY = 64
+    nt = (K + EVERY - 1) // EVERY
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]
+    for e in ev0 + ev1:
+        e.record(stream)  # creates the underlying HIP event
+    bub = sim.bubbles
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(0, K, EVERY):
+        L.lbm_time_next_step(sim.ctx, ev0[k // EVERY], ev1[k // EVERY])
+        L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, min(EVERY, K - k), 0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_s = float(np.mean([a.elapsed_time(b) for a, b in zip(ev0, ev1)])) * 1e-3
+    return elapsed, kern_s, nt, L.lbm_region_cells(sim.ctx)
+
+
+def leg_dense(args, steps):
+    """The dense dispersed column (256 x 256 x 768, 20 000 bubbles, FP32) for its stated number of
+    whole method steps (overlapped), the liquid launch tuned as for the headline column."""
+    import torch
+    import workloads as W
+    from paper_1710_07073_amd import autotune
+    from paper_1710_07073_amd import lbm as L
+    from paper_1710_07073_amd import sim as S
+
+    w = W.dense()
+    stream = torch.cuda.current_stream()
+    sim = S.Simulation(w.shape, w.omega, precision=w.dtype, bc=w.bc, stream=stream)
+    if not args.no_autotune:
+        autotune.tune(sim, use_cache=False)
+    vec, bx = L.lbm_get_launch(sim.ctx)
+    sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+    if not args.no_autotune:
+        autotune.tune_method_occupancy(sim)
+    for _ in range(10):
+        sim.step(1)
+    elapsed, kern_s, nt, region = time_steps(sim, steps, stream)
+    _, _, sums = sim.moments(fields=False)
+    sim.check()
+    alg = 38 * 4 * (w.cells - region)
+    out = {"workload": w.name, "cells": w.cells, "bubbles": w.nb, "omega": w.omega,
+           "steps": steps, "mlups": round(w.cells * steps / elapsed / 1e6, 1),
+           "ms_per_step": round(elapsed / steps * 1e3, 5),
+           "roofline": {"bound": "hbm", "kernel": "k_step_bb (bulk launch of the overlapped step)",
+                        "sites_per_launch": w.cells - region, "alg_bytes_per_launch": alg,
+                        "avg_launch_ms": round(kern_s * 1e3, 5), "launches_timed": nt,
+                        "achieved": round(alg / kern_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(alg / kern_s / 1e9 / HBM_PEAK_GBS, 4)},
+           "launch": {"vec": vec, "bx": bx, "workgroups_per_cu": L.lbm_get_step_occupancy(sim.ctx)},
+           "mass_drift": sums[0] - w.cells}
+    sim.close()
+    return out
 
 
 def copy_calibration():
@@ -641,8 +707,9 @@ def main():
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the bubble kernels and the liquid step one after the other")
     ap.add_argument("--no-legs", action="store_true",
-                    help="skip the batched, adjoint and precision legs of the default line")
-    ap.add_argument("--batched-steps", type=int, default=600)
+                    help="skip the precision, batched, adjoint and dense legs of the default line")
+    ap.add_argument("--batched-steps", type=int, default=3000)
+    ap.add_argument("--dense-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()
@@ -724,28 +791,8 @@ def main():
     torch.cuda.synchronize()
 
     K = args.steps
-    # the library records these around the launch of the fused step that updates the lattice away
-    # from the bubbles, on the stream it runs on (the side stream when the step is overlapped)
-    # every EVERY-th launch is timed (a timing event record costs several microseconds of the
-    # queue); the steps run through lbm_run in runs of EVERY, the first of which is timed
-    EVERY = 64
-    nt = (K + EVERY - 1) // EVERY
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]
-    for e in ev0 + ev1:
-        e.record(stream)  # creates the underlying HIP event
-    bub = sim.bubbles
     launch["workgroups_per_cu"] = L.lbm_get_step_occupancy(sim.ctx)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(0, K, EVERY):
-        L.lbm_time_next_step(sim.ctx, ev0[k // EVERY], ev1[k // EVERY])
-        L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, min(EVERY, K - k), 0)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    step_ms = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
-    kern_s = float(np.mean(step_ms)) * 1e-3
-    region_cells = L.lbm_region_cells(sim.ctx)
+    elapsed, kern_s, nt, region_cells = time_steps(sim, K, stream)
     overlap_on, overlap_avail = L.lbm_get_overlap(sim.ctx)
 
     # the run stayed finite and conserved mass
@@ -799,6 +846,8 @@ def main():
         out["batched"] = leg_batched(args, args.batched_steps)
         print("[bench] adjoint leg", file=sys.stderr, flush=True)
         out["adjoint"] = leg_adjoint(args)
+        print("[bench] dense leg", file=sys.stderr, flush=True)
+        out["dense"] = leg_dense(args, args.dense_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
