@@ -578,6 +578,10 @@ def leg_adjoint(args):
                                checkpoint=w.meta["checkpoint"], stream=stream)
     target, sim, _ = prob.forward(w.meta["target"], checkpoints=False)
     sim.close()
+    # one untimed gradient pass first: the backward kernels' first launches (code loading) and
+    # the allocator's first requests stay out of the timed pass
+    warm = torch.tensor(w.meta["theta0"], dtype=torch.float64, requires_grad=True)
+    ((A.BubbleTrajectory.apply(warm, prob) - target) ** 2).sum().backward()
     torch.cuda.synchronize()
     prob.liquid_events = []
     theta = torch.tensor(w.meta["theta0"], dtype=torch.float64, requires_grad=True)
@@ -604,7 +608,9 @@ def leg_adjoint(args):
     cells = int(np.prod(w.shape))
     mlups = cells * w.steps / (t2 - t0) / 1e6
     fp64 = cells * w.steps / t_fp64 / 1e6
-    alg = 276 * cells  # FP32: pulled h 76 B, lambda in 76 B, lambda out 76 B, F 12 B, lambda_U 24 B, lambda_F 12 B
+    # per cell: pulled state 76 B, lambda in 76 B, lambda out 76 B (the adjoint step's own bytes);
+    # the force, the velocity adjoint (read and cleared) and dL/dF add 48 B in the flagged tiles
+    alg = 228 * cells
     out = {"workload": "adjoint_64x64x192_4b_f32", "steps": w.steps, "checkpoint": w.meta["checkpoint"],
            "gradient_pass_mlups": round(mlups, 1), "forward_s": round(t1 - t0, 4),
            "backward_s": round(t2 - t1, 4), "plain_fp64_forward_mlups": round(fp64, 1),

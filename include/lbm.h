@@ -333,6 +333,25 @@ lbm_status lbm_adjoint_liquid(lbm_ctx* ctx, const void* state, const void* force
                               const void* lam_next, void* lam_prev, void* lam_u, void* lam_f,
                               double* grad);
 
+/* Tile mask of a step (the tiles its liquid step forces or writes the velocity in, Algorithm 1's
+ * coupling windows): *ntiles (out) = number of tiles, ceil(nx/8) ceil(ny/8) ceil(nz/8); with
+ * tiles != NULL (device, *ntiles bytes, caller-owned) the mask the last bubbles_step() flagged is
+ * copied there, asynchronously on the context's stream, entry ((z/8) ceil(ny/8) + y/8) ceil(nx/8)
+ * + x/8 nonzero for a flagged tile. Call it between the step's bubbles_step() and its lbm_step(),
+ * which reads the mask and clears it for a later step. */
+lbm_status lbm_step_tiles(lbm_ctx* ctx, uint8_t* tiles, int64_t* ntiles);
+
+/* lbm_adjoint_liquid() with the step's tile mask from lbm_step_tiles() (NULL: every tile). Outside
+ * the flagged tiles the step's force and the velocity adjoint lam_u are zero (the step neither
+ * forced nor wrote the velocity there, and lbm_adjoint_bubbles() scatters only into the velocity
+ * windows the step flagged), so those cells take them as zero without reading them and leave
+ * lam_u and lam_f unwritten (lam_f there keeps what it held): the same lam_prev and grad as
+ * lbm_adjoint_liquid(), from 228 instead of 276 bytes per FP32 cell. A lattice with
+ * LBM_FLAG_STATIC_FORCE ignores the mask. */
+lbm_status lbm_adjoint_liquid_tiles(lbm_ctx* ctx, const void* state, const void* force,
+                                    const void* lam_next, void* lam_prev, void* lam_u, void* lam_f,
+                                    const uint8_t* tiles, double* grad);
+
 /* Adjoint of the bubble half (eq. (18)-(21), Table 1, eq. (1)-(4)). record: nb x
  * LBM_BUBBLE_RECORD doubles of the step; vel_prev: velocity field the step interpolated;
  * lam_f: dL/dF from lbm_adjoint_liquid; lam_u (out, accumulated): dL/d(vel_prev); lam: nb x

@@ -50,6 +50,9 @@ class TrajectoryProblem:
         # when a list, backward appends a (start, end) event pair around every adjoint liquid step
         # of the first segment it processes (the last in time)
         self.liquid_events = None
+        # pass each step's tile mask to the adjoint liquid step (False: every cell reads the force
+        # and the velocity adjoint; the gradient is the same)
+        self.use_tiles = True
 
     # ---- forward ----
     def make_sim(self, theta):
@@ -79,8 +82,10 @@ class TrajectoryProblem:
 
     def forward(self, theta, checkpoints=True):
         """Trajectory (steps, 3, nb) on the device, the simulation, and the checkpoints. The steps
-        of each checkpoint segment run as one library call (lbm_run); the bubble update writes
-        the positions after every step into the trajectory itself (lbm_record_positions)."""
+        of each checkpoint segment run as one library call (lbm_run, replaying one HIP graph of a
+        whole segment when the segment length is even); the bubble update writes the positions
+        after every step into the trajectory itself (lbm_record_positions), at the row a device
+        counter holds, so the replays fill successive rows."""
         caller = torch.cuda.current_stream(self.device)
         sim = self.make_sim(theta)
         traj = torch.empty((self.steps, 3, self.nb), dtype=torch.float64, device=self.device)
@@ -92,7 +97,8 @@ class TrajectoryProblem:
             for k0 in range(0, self.steps, self.K):
                 if checkpoints:
                     ckpts.append(self._save(sim))
-                L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, min(self.K, self.steps - k0), 0)
+                L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, min(self.K, self.steps - k0),
+                          self.K if self.K % 2 == 0 else 0)
             L.lbm_record_positions(sim.ctx, None, 0)
         caller.wait_stream(self.stream)
         return traj, sim, ckpts
@@ -120,6 +126,11 @@ class TrajectoryProblem:
         Up = torch.empty((K + 1,) + tuple(sim.vel.shape), dtype=pops.dtype, device=dev)
         Fk = torch.empty((K,) + tuple(sim.vel.shape), dtype=pops.dtype, device=dev)
         rec = torch.zeros((K, nb, L.LBM_BUBBLE_RECORD), dtype=torch.float64, device=dev)
+        # the tile mask of each step: the adjoint liquid step reads the force and the velocity
+        # adjoint only in its flagged tiles
+        Tk = None
+        if self.use_tiles:
+            Tk = torch.empty((K, L.lbm_step_tiles(sim.ctx)), dtype=torch.uint8, device=dev)
         gt = grad_traj.to(dev, torch.float64).contiguous()
         # buffers are rebound between the bubble half and the liquid step: no overlapped steps
         L.lbm_set_overlap(sim.ctx, False)
@@ -136,6 +147,8 @@ class TrajectoryProblem:
                 L.lbm_record_next_bubble_half(sim.ctx, _p(rec[i]))
                 L.bubbles_step(sim.ctx, sim.params, bub.soa, nb)
                 Fk[i].copy_(sim.force)
+                if Tk is not None:
+                    L.lbm_step_tiles(sim.ctx, _p(Tk[i]))
                 L.lbm_bind_buffers(sim.ctx, None, None, _p(Up[i + 1]))
                 L.lbm_step(sim.ctx, 1)
             for i in reversed(range(n)):
@@ -143,8 +156,9 @@ class TrajectoryProblem:
                 if events is not None:
                     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                     ev[0].record(self.stream)
-                L.lbm_adjoint_liquid(sim.ctx, _p(H[i]), _p(Fk[i]), _p(lam[cur]), _p(lam[1 - cur]),
-                                     _p(lam_u), _p(lam_f), _p(grad))
+                L.lbm_adjoint_liquid_tiles(sim.ctx, _p(H[i]), _p(Fk[i]), _p(lam[cur]),
+                                           _p(lam[1 - cur]), _p(lam_u), _p(lam_f),
+                                           _p(Tk[i]) if Tk is not None else None, _p(grad))
                 if ev is not None:
                     ev[1].record(self.stream)
                     events.append(ev)

@@ -107,14 +107,17 @@ __device__ __forceinline__ void push_bb(T* __restrict__ dst, const T* mu, const 
 // access is a scalar base plus a 32-bit byte offset, and the push goes to the byte offsets the
 // pull read from. The dL/domega partial of each workgroup goes to one of nbins bins (atomic adds
 // spread over the bins instead of one address), summed by k_bins. In FP32 the compiler is held to
-// four wavefronts per SIMD (120 VGPRs instead of 144, no spills): 43.5 us instead of 49.4 us on
-// 786 k sites; in FP64 any such bound spills.
+// four wavefronts per SIMD (116 VGPRs, no spills; a bound of five spills); in FP64 any such bound
+// spills. tiles (or null: every tile): the step's tile mask; outside its flagged tiles F and lam_u
+// are zero (the step neither forced nor wrote the velocity there), so a cell there takes them as
+// zero without reading them and leaves lam_u and lam_f alone: 228 bytes per cell instead of 276.
 template <typename T>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_adj_liquid_bb(const T* __restrict__ h,
                                                        const T* __restrict__ F,
                                                        const T* __restrict__ lam_next,
                                                        T* __restrict__ lam_prev,
                                                        T* __restrict__ lam_u, T* __restrict__ lam_f,
+                                                       const uint8_t* __restrict__ tiles,
                                                        Geom G, T omega, double* __restrict__ bins,
                                                        uint32_t nbins) {
   __shared__ double s_red[4];
@@ -131,18 +134,29 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_adj_liquid_bb(c
     pull_push_bb<T>(p, h, G, lc4, walls, std::make_integer_sequence<int, 19>{});
 #pragma unroll
     for (int q = 0; q < 19; ++q) lam[q] = *at_bytes(lam_next, lc4 + (uint32_t)q * qs4);
-    const T f[3] = {*at_bytes(F, c4), *at_bytes(F, c4 + n4), *at_bytes(F, c4 + 2 * n4)};
-    const T lu[3] = {*at_bytes(lam_u, c4), *at_bytes(lam_u, c4 + n4), *at_bytes(lam_u, c4 + 2 * n4)};
+    const bool touched =
+        !tiles || tiles[((z >> 3) * (uint32_t)G.tny + (y >> 3)) * (uint32_t)G.tnx + (x >> 3)] != 0;
+    T f[3] = {T(0), T(0), T(0)}, lu[3] = {T(0), T(0), T(0)};
+    if (touched) {
+      f[0] = *at_bytes(F, c4);
+      f[1] = *at_bytes(F, c4 + n4);
+      f[2] = *at_bytes(F, c4 + 2 * n4);
+      lu[0] = *at_bytes(lam_u, c4);
+      lu[1] = *at_bytes(lam_u, c4 + n4);
+      lu[2] = *at_bytes(lam_u, c4 + 2 * n4);
+    }
     T lf[3];
     collide_cell_adjoint<T>(p, f, omega, lam, lu, mu, lf, &dom);
     push_bb<T>(lam_prev, mu, G, lc4, walls, std::make_integer_sequence<int, 19>{});
-    *at_bytes(lam_f, c4) = lf[0];
-    *at_bytes(lam_f, c4 + n4) = lf[1];
-    *at_bytes(lam_f, c4 + 2 * n4) = lf[2];
-    // consumed: the next (earlier) step accumulates its own velocity adjoint here
-    *at_bytes(lam_u, c4) = T(0);
-    *at_bytes(lam_u, c4 + n4) = T(0);
-    *at_bytes(lam_u, c4 + 2 * n4) = T(0);
+    if (touched) {
+      *at_bytes(lam_f, c4) = lf[0];
+      *at_bytes(lam_f, c4 + n4) = lf[1];
+      *at_bytes(lam_f, c4 + 2 * n4) = lf[2];
+      // consumed: the next (earlier) step accumulates its own velocity adjoint here
+      *at_bytes(lam_u, c4) = T(0);
+      *at_bytes(lam_u, c4 + n4) = T(0);
+      *at_bytes(lam_u, c4 + 2 * n4) = T(0);
+    }
   }
   dom = wsum(dom);
   if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = dom;
@@ -540,7 +554,8 @@ __global__ __launch_bounds__(64) void k_record(bubble_soa S, int nb, int stage, 
 
 template <typename T, bool GENERAL>
 hipError_t liquid_typed(lbm_ctx* c, const void* state, const void* force, const void* lam_next,
-                        void* lam_prev, void* lam_u, void* lam_f, double* grad) {
+                        void* lam_prev, void* lam_u, void* lam_f, const uint8_t* tiles,
+                        double* grad) {
   if (!GENERAL && bb_fast_ok(c->geom, sizeof(T))) {
     // bins for the dL/domega partials: the moments reduction scratch (at least 64 doubles for
     // lattices of 4096 cells or more)
@@ -551,8 +566,8 @@ hipError_t liquid_typed(lbm_ctx* c, const void* state, const void* force, const 
     hipLaunchKernelGGL((k_adj_liquid_bb<T>), dim3(div_up(c->geom.N, 256)), dim3(256), 0, c->stream,
                        static_cast<const T*>(state), static_cast<const T*>(force),
                        static_cast<const T*>(lam_next), static_cast<T*>(lam_prev),
-                       static_cast<T*>(lam_u), static_cast<T*>(lam_f), c->geom, (T)c->desc.omega,
-                       c->partials, nbins);
+                       static_cast<T*>(lam_u), static_cast<T*>(lam_f), tiles, c->geom,
+                       (T)c->desc.omega, c->partials, nbins);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bins, dim3(1), dim3(64), 0, c->stream, c->partials, nbins, grad);
@@ -587,20 +602,31 @@ using namespace lbm;
 
 extern "C" {
 
-lbm_status lbm_adjoint_liquid(lbm_ctx* ctx, const void* state, const void* force,
-                              const void* lam_next, void* lam_prev, void* lam_u, void* lam_f,
-                              double* grad) {
+lbm_status lbm_adjoint_liquid_tiles(lbm_ctx* ctx, const void* state, const void* force,
+                                    const void* lam_next, void* lam_prev, void* lam_u, void* lam_f,
+                                    const uint8_t* tiles, double* grad) {
   if (!ctx || !state || !force || !lam_next || !lam_prev || !lam_u || !lam_f || !grad)
     return LBM_EINVAL;
   if (lam_next == lam_prev) return LBM_EINVAL;
+  // a static force field is read everywhere: the mask does not bound it
+  if (ctx->desc.flags & LBM_FLAG_STATIC_FORCE) tiles = nullptr;
   hipError_t e;
   if (ctx->elem == 4)
-    e = ctx->general ? liquid_typed<float, true>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad)
-                     : liquid_typed<float, false>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad);
+    e = ctx->general
+            ? liquid_typed<float, true>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, tiles, grad)
+            : liquid_typed<float, false>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, tiles, grad);
   else
-    e = ctx->general ? liquid_typed<double, true>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad)
-                     : liquid_typed<double, false>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad);
+    e = ctx->general
+            ? liquid_typed<double, true>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, tiles, grad)
+            : liquid_typed<double, false>(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, tiles, grad);
   return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+lbm_status lbm_adjoint_liquid(lbm_ctx* ctx, const void* state, const void* force,
+                              const void* lam_next, void* lam_prev, void* lam_u, void* lam_f,
+                              double* grad) {
+  return lbm_adjoint_liquid_tiles(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, nullptr,
+                                  grad);
 }
 
 lbm_status lbm_adjoint_bubbles(lbm_ctx* ctx, const bubble_params* p, const double* record,

@@ -58,6 +58,27 @@ LBM_HD T mul_weight_hd(double c, T v) {
   }
 }
 
+// s += c v for a lattice component c in {-1, 0, 1} (no arithmetic when c = 0).
+template <typename T>
+LBM_HD void add_c(T& s, int c, T v) {
+  if (c > 0) s += v;
+  else if (c < 0) s -= v;
+}
+
+// sum_a c_a v_a for a lattice velocity c.
+template <typename T>
+LBM_HD T dot_c(int cx, int cy, int cz, const T* v) {
+  T s = T(0);
+  bool first = true;
+  const int c[3] = {cx, cy, cz};
+  for (int a = 0; a < 3; ++a) {
+    if (c[a] == 0) continue;
+    s = first ? (c[a] > 0 ? v[a] : -v[a]) : (c[a] > 0 ? s + v[a] : s - v[a]);
+    first = false;
+  }
+  return s;
+}
+
 // Given lam = dL/d(out) and lamU = dL/du of one cell, returns mu = dL/dp, lamF = dL/dF and the
 // cell's share of dL/domega. With rho = 1 + sum p and u = (sum c p + F/2)/rho:
 //   mu_k = (1 - omega) lam_k + A + sum_a B_a (c_ka - u_a) / rho,
@@ -65,6 +86,15 @@ LBM_HD T mul_weight_hd(double c, T v) {
 //   B_a  = sum_q lam_q (omega dgeq_q/du_a + dS_q/du_a) + lamU_a,
 //   lamF_a = sum_q lam_q dS_q/dF_a + B_a / (2 rho),
 //   dL/domega = sum_q lam_q (geq_q - p_q - X_q w_q / 2), S_q = (1 - omega/2) w_q X_q.
+// The sums over q are polynomials of degree at most two in c_q, so they reduce to the moments of
+// m_q = w_q lam_q: M0 = sum m, M1_a = sum m c_a, M2_ab = sum m c_a c_b. With V = M2 u, G = M2 F:
+//   A   = omega (M0 + 3 u.M1 + 4.5 u.V - 1.5 |u|^2 M0),
+//   B_a = lamU_a + omega rho (3 M1_a + 9 V_a - 3 u_a M0) + (1 - omega/2)(9 G_a - 3 F_a M0),
+//   sum_q lam_q dS_q/dF_a = (1 - omega/2)(3 M1_a - 3 u_a M0 + 9 V_a),
+//   sum_q m_q X_q = 3 (F.M1 - (u.F) M0) + 9 u.G.
+// The moments are summed per weight class (lam summed over the faces and over the edges, then
+// multiplied by the class weight, as hi + lo in FP32). Only dL/domega keeps a term per direction:
+// geq_q - p_q is the small non-equilibrium part, taken per direction before the sum.
 template <typename T>
 LBM_HD void collide_cell_adjoint(const T* p, const T* F, T omega, const T* lam, const T* lamU, T* mu,
                                  T* lamF, double* domega) {
@@ -82,41 +112,63 @@ LBM_HD void collide_cell_adjoint(const T* p, const T* F, T omega, const T* lam, 
   const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const T pre = T(1) - T(0.5) * omega;
   const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-  T A = 0, B[3] = {lamU[0], lamU[1], lamU[2]}, lf[3] = {0, 0, 0};
-  double dom = 0.0;
+  // lam summed per class (0: faces, 1: edges): s0 = sum lam, s1_a = sum lam c_a, s2_a = sum lam
+  // c_a^2, sx = sum lam c_a c_b over the edges (xy, xz, yz); dsum = sum lam (geq - p)
+  T s0[2] = {0, 0}, s1[2][3] = {{0, 0, 0}, {0, 0, 0}}, s2[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  T sx[3] = {0, 0, 0}, dsum = 0;
+#pragma unroll
   for (int q = 0; q < 19; ++q) {
-    const T w = weight<T>(q);
-    const T c[3] = {T(CX[q]), T(CY[q]), T(CZ[q])};
-    const T cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
-    const T cF = c[0] * F[0] + c[1] * F[1] + c[2] * F[2];
-    const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-    const T geq = w * (drho + rho * base);
-    const T X = T(3) * (cF - uF) + T(9) * cu * cF;
+    const int cx = CX[q], cy = CY[q], cz = CZ[q];
     const T l = lam[q];
-    const double wd = q < 6 ? 1.0 / 18.0 : (q < 18 ? 1.0 / 36.0 : 1.0 / 3.0);
-    if constexpr (sizeof(T) == 4)
-      A += l * mul_weight_hd<T>(wd, T(1) + base);
-    else
-      A += l * w * (T(1) + base);
-    for (int a = 0; a < 3; ++a) {
-      T dgeq;
-      if constexpr (sizeof(T) == 4)
-        dgeq = mul_weight_hd<T>(wd, rho * (T(3) * c[a] + T(9) * cu * c[a] - T(3) * u[a]));
-      else
-        dgeq = w * rho * (T(3) * c[a] + T(9) * cu * c[a] - T(3) * u[a]);
-      const T dS = pre * w * (T(-3) * F[a] + T(9) * c[a] * cF);
-      B[a] += l * (omega * dgeq + dS);
-      lf[a] += l * pre * w * (T(3) * (c[a] - u[a]) + T(9) * cu * c[a]);
-    }
-    dom += (double)l * ((double)geq - (double)p[q] - 0.5 * (double)(w * X));
+    const T cu = dot_c<T>(cx, cy, cz, u);
+    const T geq = weight<T>(q) * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
+    dsum += l * (geq - p[q]);
+    if (q == 18) continue;
+    const int k = q < 6 ? 0 : 1;
+    s0[k] += l;
+    add_c(s1[k][0], cx, l);
+    add_c(s1[k][1], cy, l);
+    add_c(s1[k][2], cz, l);
+    if (cx) s2[k][0] += l;
+    if (cy) s2[k][1] += l;
+    if (cz) s2[k][2] += l;
+    add_c(sx[0], cx * cy, l);
+    add_c(sx[1], cx * cz, l);
+    add_c(sx[2], cy * cz, l);
   }
-  A *= omega;
-  for (int k = 0; k < 19; ++k) {
-    mu[k] = (T(1) - omega) * lam[k] + A +
-            (B[0] * (T(CX[k]) - u[0]) + B[1] * (T(CY[k]) - u[1]) + B[2] * (T(CZ[k]) - u[2])) * inv;
+  constexpr double wf = 1.0 / 18.0, we = 1.0 / 36.0;
+  const T M0 = mul_weight_hd<T>(1.0 / 3.0, lam[18]) + mul_weight_hd<T>(wf, s0[0]) +
+               mul_weight_hd<T>(we, s0[1]);
+  T M1[3], M2[3][3];
+  for (int a = 0; a < 3; ++a) {
+    M1[a] = mul_weight_hd<T>(wf, s1[0][a]) + mul_weight_hd<T>(we, s1[1][a]);
+    M2[a][a] = mul_weight_hd<T>(wf, s2[0][a]) + mul_weight_hd<T>(we, s2[1][a]);
   }
-  for (int a = 0; a < 3; ++a) lamF[a] = lf[a] + B[a] * T(0.5) * inv;
-  *domega = dom;
+  M2[0][1] = M2[1][0] = mul_weight_hd<T>(we, sx[0]);
+  M2[0][2] = M2[2][0] = mul_weight_hd<T>(we, sx[1]);
+  M2[1][2] = M2[2][1] = mul_weight_hd<T>(we, sx[2]);
+  T V[3], G[3];
+  for (int a = 0; a < 3; ++a) {
+    V[a] = M2[a][0] * u[0] + M2[a][1] * u[1] + M2[a][2] * u[2];
+    G[a] = M2[a][0] * F[0] + M2[a][1] * F[1] + M2[a][2] * F[2];
+  }
+  const T uM1 = u[0] * M1[0] + u[1] * M1[1] + u[2] * M1[2];
+  const T uV = u[0] * V[0] + u[1] * V[1] + u[2] * V[2];
+  const T FM1 = F[0] * M1[0] + F[1] * M1[1] + F[2] * M1[2];
+  const T uG = u[0] * G[0] + u[1] * G[1] + u[2] * G[2];
+  const T A = omega * (M0 + T(3) * uM1 + T(4.5) * uV - T(1.5) * usq * M0);
+  T b[3];
+  for (int a = 0; a < 3; ++a) {
+    const T B = lamU[a] + omega * rho * (T(3) * M1[a] + T(9) * V[a] - T(3) * u[a] * M0) +
+                pre * (T(9) * G[a] - T(3) * F[a] * M0);
+    lamF[a] = pre * (T(3) * M1[a] - T(3) * u[a] * M0 + T(9) * V[a]) + B * T(0.5) * inv;
+    b[a] = B * inv;
+  }
+  const T K0 = A - (b[0] * u[0] + b[1] * u[1] + b[2] * u[2]);
+  const T decay = T(1) - omega;
+#pragma unroll
+  for (int k = 0; k < 19; ++k) mu[k] = decay * lam[k] + (K0 + dot_c<T>(CX[k], CY[k], CZ[k], b));
+  *domega = (double)dsum - 0.5 * (double)(T(3) * (FM1 - uF * M0) + T(9) * uG);
 }
 
 // ---------------------------------------------------------------------------------------------

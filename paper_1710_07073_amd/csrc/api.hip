@@ -239,6 +239,17 @@ lbm_status lbm_record_positions(lbm_ctx* ctx, double* traj, int32_t rows) {
   return LBM_OK;
 }
 
+lbm_status lbm_step_tiles(lbm_ctx* ctx, uint8_t* tiles, int64_t* ntiles) {
+  if (!ctx || !ntiles) return LBM_EINVAL;
+  *ntiles = (int64_t)ctx->ntiles;
+  if (!tiles) return LBM_OK;
+  // the mask the last bubble half flagged, which its lbm_step() reads
+  return hipMemcpyAsync(tiles, ctx->tiles[ctx->hs.flag_cur], ctx->ntiles, hipMemcpyDeviceToDevice,
+                        ctx->stream) == hipSuccess
+             ? LBM_OK
+             : LBM_EDEVICE;
+}
+
 lbm_status lbm_record_next_bubble_half(lbm_ctx* ctx, double* record) {
   if (!ctx) return LBM_EINVAL;
   ctx->arm_record = record;  // null disarms

@@ -39,7 +39,8 @@ EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch",
            "lbm_batch_step", "lbm_batch_run", "lbm_batch_populations", "lbm_batch_sums",
            "lbm_batch_column",
            "lbm_batch_check", "lbm_batch_destroy",
-           "lbm_adjoint_liquid", "lbm_adjoint_bubbles", "lbm_bubble_record",
+           "lbm_adjoint_liquid", "lbm_adjoint_liquid_tiles", "lbm_step_tiles",
+           "lbm_adjoint_bubbles", "lbm_bubble_record",
            "lbm_record_next_bubble_half", "lbm_record_positions", "lbm_bind_buffers",
            "lbm_host_collide",
            "lbm_host_axis_weights", "lbm_host_bubble_ode", "lbm_host_bubble_ode_adjoint")
@@ -133,6 +134,8 @@ def lib():
         D = ct.POINTER(ct.c_double)
         I = ct.POINTER(ct.c_int32)
         L.lbm_adjoint_liquid.argtypes = [P, P, P, P, P, P, P, P]
+        L.lbm_adjoint_liquid_tiles.argtypes = [P, P, P, P, P, P, P, P, P]
+        L.lbm_step_tiles.argtypes = [P, P, ct.POINTER(ct.c_int64)]
         L.lbm_adjoint_bubbles.argtypes = [P, ct.POINTER(BubbleParams), P, P, P, P, P, P, ct.c_int32, P]
         L.lbm_bubble_record.argtypes = [P, ct.POINTER(BubbleSoA), ct.c_int32, ct.c_int32, P]
         L.lbm_record_next_bubble_half.argtypes = [P, P]
@@ -378,6 +381,18 @@ def lbm_batch_destroy(batch):
 def lbm_adjoint_liquid(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad):
     _ok(lib().lbm_adjoint_liquid(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad),
         "lbm_adjoint_liquid")
+
+
+def lbm_adjoint_liquid_tiles(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, tiles, grad):
+    _ok(lib().lbm_adjoint_liquid_tiles(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, tiles,
+                                       grad), "lbm_adjoint_liquid_tiles")
+
+
+def lbm_step_tiles(ctx, tiles=None):
+    """Number of tiles; with a device pointer, also copies the step's tile mask there."""
+    n = ct.c_int64()
+    _ok(lib().lbm_step_tiles(ctx, tiles, ct.byref(n)), "lbm_step_tiles")
+    return n.value
 
 
 def lbm_adjoint_bubbles(ctx, params, record, vel_prev, lam_f, lam_u, lam, lam_x, nb, grad):

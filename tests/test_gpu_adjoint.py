@@ -299,3 +299,47 @@ def test_armed_record_blocks_lbm_run_until_disarmed():
     sim.check()
     assert torch.count_nonzero(rec).item() == 0  # disarmed before any bubble half ran
     sim.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tile_mask_gives_the_same_gradient(precision):
+    """lbm_adjoint_liquid_tiles with each step's tile mask (lbm_step_tiles) reads the force and the
+    velocity adjoint only in the tiles the step flagged and takes them as zero elsewhere: the same
+    gradient as lbm_adjoint_liquid reading every cell, up to the order of the atomic additions into
+    dL/domega."""
+    w = _small(steps=120)
+    th0 = w.meta["theta0"]
+    target, sim, _ = _problem(w, precision, 40).forward(w.meta["target"], checkpoints=False)
+    sim.close()
+    grads = []
+    for use in (False, True):
+        prob = _problem(w, precision, 40)
+        prob.use_tiles = use
+        grads.append(_adjoint_grad(prob, th0, target)[1])
+    print(f"every cell {grads[0]}, tile mask {grads[1]}", flush=True)
+    assert np.allclose(grads[1], grads[0], rtol=1e-12, atol=1e-13 * np.abs(grads[0]).max())
+
+
+@pytest.mark.gpu
+def test_step_tiles_flags_the_bubble_windows():
+    """The mask lbm_step_tiles copies after a bubble half flags the tiles of each bubble's force
+    window and nothing far from the bubbles."""
+    from paper_1710_07073_amd import lbm as L
+    from paper_1710_07073_amd import sim as S
+    w = _small()
+    sim = S.Simulation(w.shape, w.omega, precision="f64", bc=w.bc)
+    sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+    n = L.lbm_step_tiles(sim.ctx)
+    nx, ny, nz = w.shape
+    assert n == -(-nx // 8) * -(-ny // 8) * -(-nz // 8)
+    mask = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    L.bubbles_step(sim.ctx, sim.params, sim.bubbles.soa, sim.bubbles.nb)
+    L.lbm_step_tiles(sim.ctx, A._p(mask))
+    L.lbm_step(sim.ctx, 1)
+    m = mask.cpu().numpy().reshape(-(-nz // 8), -(-ny // 8), -(-nx // 8))
+    for b in range(w.pos.shape[1]):
+        x, y, z = (int(v) // 8 for v in w.pos[:, b])
+        assert m[z, y, x] != 0
+    assert m[-1].sum() == 0  # the top tiles are far from every bubble
+    sim.close()
