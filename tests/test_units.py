@@ -68,3 +68,23 @@ def test_water_viscosity_gives_omega_near_two():
     assert nu == pytest.approx(4e-6)
     assert U.omega_of(nu) == pytest.approx(1.0 / (1.2e-5 + 0.5))
     assert U.omega_of(nu) > 1.9999
+
+
+def test_input_generator_converts_like_the_units_module():
+    """The synthetic physical-unit columns convert App. A units on their own (the input generator
+    imports nothing from the package): shapes, diameters, omega, g and sigma equal what the
+    package's units module gives for every grid case, bit for bit."""
+    import workloads as W
+    for w in W.grid_independence(steps=1):
+        d_b, aspect = w.meta["d_mm"] * 1e-3, w.meta["aspect"]
+        u = U.column_units(d_b, aspect)
+        col = U.column(u, d_b)
+        assert w.shape == (col.nx, col.ny, col.nz)
+        assert w.d[0] == col.d_b
+        assert w.omega == U.omega_of(u.viscosity(W.WATER_NU))
+        assert w.params["g"] == u.acceleration(W.GRAVITY)
+        assert w.params["sigma"] == u.surface_tension(W.WATER_SIGMA)
+        assert w.pos[2, 0] == u.length(0.02)
+    s = W.stability(steps=1, omegas=(1.9,))[0]
+    u = U.column_units(0.004, 1.25)
+    assert s.params["g"] == u.acceleration(W.GRAVITY) and s.d[0] == U.column(u, 0.004).d_b

@@ -146,20 +146,66 @@ STABILITY_OMEGAS = (1.90, 1.92, 1.94, 1.95, 1.96, 1.965, 1.97, 1.975, 1.98, 1.98
 WATER_NU, WATER_RHO, AIR_RHO, WATER_SIGMA, GRAVITY = 1e-6, 1000.0, 1.0, 0.073, 9.81
 
 
+@dataclass(frozen=True)
+class _Column:
+    """The paper's tank (App. A: 0.15 x 0.15 m, water level 0.45 m) resolving a bubble of d_b
+    metres at grid spacing dx = aspect d_b, liquid step dt = 1e-4 s, water at 1000 kg/m^3 and 1 in
+    lattice units. The conversion factors (lattice over physical) are LCF = 1/dx, TCF = 1/dt and
+    MCF = LCF^3 / 1000 (App. A); the columns' inputs are converted here, independently of the
+    package's own units module."""
+    d_b: float
+    aspect: float
+    dt: float = 1e-4
+
+    @property
+    def lcf(self):
+        return 1.0 / (self.aspect * self.d_b)
+
+    @property
+    def tcf(self):
+        return 1.0 / self.dt
+
+    @property
+    def mcf(self):
+        return self.lcf ** 3 / WATER_RHO
+
+    def cells(self, metres):
+        return round(metres * self.lcf)
+
+    @property
+    def shape(self):
+        return (self.cells(0.15), self.cells(0.15), self.cells(0.45))
+
+    @property
+    def d_lu(self):
+        return self.d_b * self.lcf
+
+    @property
+    def g(self):
+        return GRAVITY * self.lcf / self.tcf ** 2
+
+    @property
+    def sigma(self):
+        return WATER_SIGMA * self.mcf / self.tcf ** 2
+
+    @property
+    def omega(self):
+        # nu = (1/omega - 1/2) / 3 in lattice units (eq. (9))
+        return 1.0 / (3.0 * WATER_NU * self.lcf ** 2 / self.tcf + 0.5)
+
+
 def stability(steps=20000, omegas=STABILITY_OMEGAS):
     """The stability sweep (Sec. 4.3): the App. A column (0.15 x 0.15 x 0.45 m tank at aspect ratio
     1.25 for a 4 mm bubble: 30 x 30 x 90 cells, d = 0.8) with g and sigma of air in water converted
     to lattice units (g = 9.81 m/s^2, sigma = 0.073 N/m, dt = 1e-4 s), bounce-back walls and bottom,
     free-slip top, the bubble released at the bottom centre; one column per omega."""
-    from paper_1710_07073_amd import units as U
-    u = U.column_units(0.004, 1.25)
-    col = U.column(u, 0.004)
-    g = u.acceleration(GRAVITY)
-    sigma = u.surface_tension(WATER_SIGMA)
-    pos = np.array([[col.nx / 2 - 0.5], [col.ny / 2 - 0.5], [3.0]])
+    col = _Column(0.004, 1.25)
+    nx, ny, nz = col.shape
+    pos = np.array([[nx / 2 - 0.5], [ny / 2 - 0.5], [3.0]])
     bc = (BB, BB, BB, BB, BB, FS)
-    return [Workload(f"stability_omega{om}", (col.nx, col.ny, col.nz), float(om), bc, pos.copy(),
-                     np.array([col.d_b]), params(g=g, sigma=sigma), steps, "f32") for om in omegas]
+    return [Workload(f"stability_omega{om}", (nx, ny, nz), float(om), bc, pos.copy(),
+                     np.array([col.d_lu]), params(g=col.g, sigma=col.sigma), steps, "f32")
+            for om in omegas]
 
 
 # gravity (lattice units) of the bubble swarms that drive the liquid hard enough for the BGK step
@@ -218,18 +264,15 @@ def grid_independence(steps=10000, cases=GRID_CASES, release=0.02):
     sigma = 0.073 N/m; g = 9.81 m/s^2) converted to lattice units per App. A with dt = 1e-4 s;
     bounce-back walls and bottom, free-slip top; the bubble released at rest `release` metres
     above the bottom on the axis. 10000 steps are 1 s of rise."""
-    from paper_1710_07073_amd import units as U
     out = []
     for d_b, aspect in cases:
-        u = U.column_units(d_b, aspect)
-        col = U.column(u, d_b)
-        om = U.omega_of(u.viscosity(WATER_NU))
-        pos = np.array([[col.nx / 2 - 0.5], [col.ny / 2 - 0.5], [u.length(release)]])
-        p = params(g=u.acceleration(GRAVITY), sigma=u.surface_tension(WATER_SIGMA),
-                   rho_b=AIR_RHO / WATER_RHO)
-        out.append(Workload(f"grid_{int(d_b * 1000)}mm_ar{aspect}", (col.nx, col.ny, col.nz), float(om),
-                            (BB, BB, BB, BB, BB, FS), pos, np.array([col.d_b]), p, steps, "f32",
-                            meta=dict(d_mm=d_b * 1000, aspect=aspect, lcf=u.lcf, tcf=u.tcf)))
+        col = _Column(d_b, aspect)
+        nx, ny, nz = col.shape
+        pos = np.array([[nx / 2 - 0.5], [ny / 2 - 0.5], [release * col.lcf]])
+        p = params(g=col.g, sigma=col.sigma, rho_b=AIR_RHO / WATER_RHO)
+        out.append(Workload(f"grid_{int(d_b * 1000)}mm_ar{aspect}", (nx, ny, nz), float(col.omega),
+                            (BB, BB, BB, BB, BB, FS), pos, np.array([col.d_lu]), p, steps, "f32",
+                            meta=dict(d_mm=d_b * 1000, aspect=aspect, lcf=col.lcf, tcf=col.tcf)))
     return out
 
 
