@@ -391,7 +391,9 @@ lbm_status lbm_host_bubble_ode_adjoint(const bubble_params* params, double nu, d
 /* ---------------------------------------------------------------------------------------------
  * Batched columns: many independent lattices (uneven extents, each with its own omega and faces)
  * stepped together, as in the paper's grid-independence and stability sweeps (Sec. 4.2, 4.3).
- * All columns share the precision and the bubble constants; column c owns bubbles
+ * All columns share the precision and the bubble constants except that a column may carry its own
+ * gravity and surface tension in lattice units (one physical setup resolved at several grid
+ * spacings, App. A: g and sigma scale with the spacing); column c owns bubbles
  * [bubble_begin, bubble_begin + nb) of one shared bubble_soa, ranges consecutive in column order.
  * Every buffer lives in one caller-owned pool and one caller-owned scratch block.
  * ------------------------------------------------------------------------------------------- */
@@ -399,8 +401,10 @@ typedef struct {
   int32_t nx, ny, nz;
   int32_t bubble_begin, nb;
   int32_t bc[6];
-  int32_t reserved;
+  int32_t reserved;  /* 0 */
   double omega;
+  /* this column's bubbles' g and sigma (bubble_params units); 0: the batch's bubble_params value */
+  double g, sigma;
 } lbm_column;
 
 typedef struct lbm_batch lbm_batch;

@@ -135,6 +135,7 @@ __global__ __launch_bounds__(256) void k_batch_populations(const ColumnDev* __re
 bool column_ok(const lbm_column& c) {
   if (c.nx < 1 || c.ny < 1 || c.nz < 1 || c.reserved != 0) return false;
   if (!(c.omega > 0.0 && c.omega < 2.0)) return false;
+  if (!(c.g >= 0.0 && c.g < INFINITY) || !(c.sigma >= 0.0 && c.sigma < INFINITY)) return false;
   if (c.nb < 0 || c.bubble_begin < 0) return false;
   for (int a = 0; a < 3; ++a) {
     const int lo = c.bc[2 * a], hi = c.bc[2 * a + 1];
@@ -436,6 +437,8 @@ lbm_status lbm_batch_init(const lbm_column* cols, int32_t ncols, int32_t precisi
     D.G.tny = (int)div_up(k.ny, kTile);
     D.omega = k.omega;
     D.nu = (1.0 / k.omega - 0.5) / 3.0;  // eq. (9), dx = dt_l = 1
+    D.g = k.g;
+    D.sigma = k.sigma;
     D.pops[0] = P + L.pops0[c];
     D.pops[1] = P + L.pops1[c];
     D.F = P + L.force[c];

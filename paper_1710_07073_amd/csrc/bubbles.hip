@@ -514,7 +514,7 @@ __device__ void interp_bubble(const Geo& geo, const BubbleArgs& A, const int b) 
     // wavefront 3 has no axis to weigh: it prepares the update's constants and loads meanwhile
     static_assert(kBlock >= 256, "a fourth wavefront");
     if (tid == 192) {
-      s_pre.kc = bubble_constants(A.P, col.nu, d);
+      s_pre.kc = bubble_constants(geo.params(A.P, b), col.nu, d);
       s_pre.ub[0] = A.S.ux[b];
       s_pre.ub[1] = A.S.uy[b];
       s_pre.ub[2] = A.S.uz[b];
@@ -759,7 +759,7 @@ __device__ bool ode_update(const Geo& geo, const BubbleArgs& A, int b, const Ode
   const ColumnView<float> col = geo.template view<float>(b);
   const Geom& G = col.G;
   const double nu = col.nu;
-  const bubble_params& P = A.P;
+  const bubble_params P = geo.params(A.P, b);
   double* work = A.S.work + (size_t)b * kWork;
   const int st = in.st;
   const double valid = in.valid;

@@ -122,6 +122,8 @@ struct OneColumn {
   // the deterministic spreading: per-tile lists of this lattice (every tile is gathered, so the
   // tiles entered need no note)
   __device__ bool use_lists() const { return lists; }
+  // the bubble constants of bubble b: the shared ones
+  __device__ bubble_params params(const bubble_params& P, int) const { return P; }
   __device__ uint32_t* tcount_of(int) const { return tcount; }
   __device__ uint32_t* tlist_of(int) const { return tlist; }
   __device__ void note_tile(int, uint32_t) const {}
@@ -146,6 +148,7 @@ struct ColumnDev {
   uint32_t* tcount;
   uint32_t* tlist;
   float rnx, rny;  // 1 / nx and 1 / ny rounded to float (cell coordinates of the batched step)
+  double g, sigma;  // the column's bubbles' gravity and surface tension (0: the shared value)
 };
 
 // Many columns: each bubble's column comes from a per-bubble index. The spreading gathers in
@@ -166,6 +169,14 @@ struct ManyColumns {
     return {c.G, static_cast<const T*>(c.U), static_cast<T*>(c.F), c.tiles[flag], c.nu, nullptr};
   }
   __device__ bool use_lists() const { return true; }
+  // the bubble constants of bubble b: the shared ones with its column's g and sigma where set
+  __device__ bubble_params params(const bubble_params& P, int b) const {
+    bubble_params q = P;
+    const ColumnDev& c = cols[bubble_col[b]];
+    if (c.g != 0.0) q.g = c.g;
+    if (c.sigma != 0.0) q.sigma = c.sigma;
+    return q;
+  }
   __device__ uint32_t* tcount_of(int b) const { return cols[bubble_col[b]].tcount; }
   __device__ uint32_t* tlist_of(int b) const { return cols[bubble_col[b]].tlist; }
   // tile t of bubble b's column received its first bubble of the step

@@ -67,7 +67,8 @@ class BubbleSoA(ct.Structure):
 class LbmColumn(ct.Structure):
     _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32),
                 ("bubble_begin", ct.c_int32), ("nb", ct.c_int32), ("bc", ct.c_int32 * 6),
-                ("reserved", ct.c_int32), ("omega", ct.c_double)]
+                ("reserved", ct.c_int32), ("omega", ct.c_double), ("g", ct.c_double),
+                ("sigma", ct.c_double)]
 
 
 class LbmError(RuntimeError):
@@ -278,14 +279,18 @@ def lbm_run(ctx, params, soa, nb, nsteps, graph_steps=0):
 
 # ---- batched columns ----
 def make_columns(specs):
-    """specs: iterable of (shape, omega, bc, nb); bubble ranges are assigned consecutively."""
+    """specs: iterable of (shape, omega, bc, nb[, g, sigma]); bubble ranges are assigned
+    consecutively; g, sigma (0 or absent: the batch's bubble_params values) per column."""
     specs = list(specs)
     arr = (LbmColumn * len(specs))()
     begin = 0
-    for i, (shape, omega, bc, nb) in enumerate(specs):
+    for i, spec in enumerate(specs):
+        shape, omega, bc, nb = spec[:4]
+        g, sigma = (tuple(spec[4:6]) + (0.0, 0.0))[:2]
         nx, ny, nz = shape
         arr[i] = LbmColumn(int(nx), int(ny), int(nz), begin, int(nb),
-                           (ct.c_int32 * 6)(*[int(b) for b in bc]), 0, float(omega))
+                           (ct.c_int32 * 6)(*[int(b) for b in bc]), 0, float(omega), float(g or 0.0),
+                           float(sigma or 0.0))
         begin += int(nb)
     return arr
 

@@ -152,14 +152,15 @@ class Batch:
     """Many columns (each a Workload-like spec) stepped together through the batched C ABI."""
 
     def __init__(self, columns, params, precision="f32", flags=0, device="cuda", stream=None):
-        """columns: list of dicts with shape, omega, bc, pos (3, nb), d (nb)."""
+        """columns: list of dicts with shape, omega, bc, pos (3, nb), d (nb), and optionally g
+        and sigma (the column's bubbles' gravity and surface tension; default: params')."""
         self.columns = columns
         self.precision = L.LBM_FP64_SHIFTED if precision in ("f64", "fp64") else L.LBM_FP32_SHIFTED
         self.dtype = torch.float64 if self.precision == L.LBM_FP64_SHIFTED else torch.float32
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.cols = L.make_columns([(c["shape"], c["omega"], c["bc"], np.asarray(c["d"]).size)
-                                    for c in columns])
+        self.cols = L.make_columns([(c["shape"], c["omega"], c["bc"], np.asarray(c["d"]).size,
+                                     c.get("g", 0.0), c.get("sigma", 0.0)) for c in columns])
         pool_b, scratch_b = L.lbm_batch_bytes_required(self.cols, self.precision)
         self.pool = torch.empty(pool_b, dtype=torch.uint8, device=self.device)
         self.scratch = torch.empty(scratch_b, dtype=torch.uint8, device=self.device)

@@ -101,6 +101,46 @@ def test_batch_is_bitwise_identical_to_single_lattice_runs(prec):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_per_column_gravity_and_surface_tension(prec):
+    """Columns carrying their own g and sigma (one physical setup at several grid spacings) step
+    like single lattices run with those constants, bit for bit; a column without them takes the
+    batch's."""
+    cols = _crowded_columns()
+    consts = [(3e-4, W.sigma_for(3e-4, 2.5)), (0.0, 0.0), (5e-5, W.sigma_for(5e-5, 3.5))]
+    for col, (g, sigma) in zip(cols, consts):
+        col.update(g=g, sigma=sigma)
+    print(f"[case] per-column g, sigma batch {prec}", flush=True)
+    batch = S.Batch(cols, S.bubble_params(**_params()), precision=prec)
+    steps = 24
+    batch.step(8)
+    batch.run(steps - 8, graph_steps=8)
+    pos = batch.bubbles.positions()
+    for c, (col, (g, sigma)) in enumerate(zip(cols, consts)):
+        p = _params()
+        if g:
+            p.update(g=g, sigma=sigma)
+        sim = S.Simulation(col["shape"], col["omega"], precision=prec, bc=col["bc"])
+        sim.add_bubbles(col["pos"], col["d"], S.bubble_params(**p))
+        sim.step(steps)
+        b0, b1 = batch.bubble_range(c)
+        assert np.array_equal(batch.populations(c).double().cpu().numpy(),
+                              sim.populations().double().cpu().numpy()), c
+        assert np.array_equal(pos[:, b0:b1], sim.bubbles.positions()), c
+        sim.close()
+    # the columns with their own constants move otherwise than with the batch's
+    for c in (0, 2):
+        col = cols[c]
+        sim = S.Simulation(col["shape"], col["omega"], precision=prec, bc=col["bc"])
+        sim.add_bubbles(col["pos"], col["d"], S.bubble_params(**_params()))
+        sim.step(steps)
+        assert np.abs(pos[:, slice(*batch.bubble_range(c))] - sim.bubbles.positions()).max() > 1e-4
+        sim.close()
+    batch.check()
+    batch.close()
+
+
+@pytest.mark.gpu
 def test_batched_sweep_rerun_is_bitwise_identical():
     """The 64-column sweep (1-8 bubbles per column, 50 M sites) run twice, per-step launches and
     persistent launches: same bits everywhere."""

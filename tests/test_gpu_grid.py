@@ -184,3 +184,27 @@ def test_relative_velocity_follows_eq22():
     # measured: 5.2e-3 of v_T at most, 63 % of v_T one step before the equation
     assert dev.max() <= 0.015
     assert abs(t63(vr) - t63(ve)) <= 3
+
+
+@pytest.mark.gpu
+def test_table5_columns_in_one_batch_match_their_single_runs():
+    """The nine Table 5 columns as one batch (each column with its own lattice-unit g and sigma,
+    as the grid spacing sets them) reproduce the nine single-lattice runs bit for bit, so the
+    grid study and the terminal-velocity sweep run through the batched path."""
+    from paper_1710_07073_amd import sim as S
+    ws = [_with(w, 100, "f32") for w in CASES.values()]
+    print(f"[case] Table 5 batch of {len(ws)} columns, 100 steps", flush=True)
+    cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d, g=w.params["g"],
+                 sigma=w.params["sigma"]) for w in ws]
+    batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32")
+    batch.run(100, graph_steps=50)
+    pos = batch.bubbles.positions()
+    for c, w in enumerate(ws):
+        sim = gpu_sim(w)
+        sim.run(100, graph_steps=50)
+        b0, b1 = batch.bubble_range(c)
+        assert torch.equal(batch.populations(c), sim.populations()), w.name
+        assert np.array_equal(pos[:, b0:b1], sim.bubbles.positions()), w.name
+        sim.close()
+    batch.check()
+    batch.close()
