@@ -203,8 +203,9 @@ def time_steps(sim, K, stream):
     from paper_1710_07073_amd import lbm as L
 
     # every EVERY-th launch is timed (a timing event record costs several microseconds of the
-    # queue); the steps run through lbm_run in runs of EVERY, the first of which is timed
-    EVERY = 64
+    # queue), at least five launches of a short run; the steps run through lbm_run in runs of
+    # EVERY, the first of which is timed
+    EVERY = max(4, min(64, K // 16))
     nt = (K + EVERY - 1) // EVERY
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(nt)]

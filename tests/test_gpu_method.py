@@ -261,3 +261,24 @@ def test_neutrally_buoyant_bubble_follows_a_uniformly_accelerating_liquid(prec):
         assert np.allclose(v, (n - 1) * a, rtol=0, atol=tol), (n, v)
     sim.check()
     sim.close()
+
+
+@pytest.mark.gpu
+def test_lateral_wall_clamp_matches_oracle():
+    """The lateral clamp (R14) on the GPU: a bubble driven into the x = 0 wall ends the step at
+    x = 0 with u_x = 0 exactly, its y and z motion as the oracle's."""
+    pos = np.array([[0.02, 14.98], [7.4, 7.4], [8.2, 12.0]])
+    vel = np.array([[-0.1, 0.1], [0.003, 0.003], [0.002, 0.002]])
+    kw = dict(g=1e-5, rho_b=1e-3, sigma=1e-5, cd_k=0.0)
+    sim = S.Simulation((16, 16, 24), 1.0, precision="f64")
+    sim.add_bubbles(pos, [2.0, 2.0], S.bubble_params(**kw), vel=vel)
+    lat = O.Lattice(16, 16, 24, 1.0)
+    bub = O.Bubbles(pos=pos.copy(), d=[2.0, 2.0], vel=vel.copy())
+    P = O.bubble_params(**kw)
+    for _ in range(3):
+        sim.step(1)
+        O.method_step(lat, P, bub)
+    x, v = sim.bubbles.positions(), sim.bubbles.velocities()
+    assert x[0, 0] == 0.0 and v[0, 0] == 0.0 and x[0, 1] == 15.0 and v[0, 1] == 0.0
+    assert np.allclose(x, bub.pos, rtol=0, atol=1e-12) and np.allclose(v, bub.vel, rtol=0, atol=1e-14)
+    sim.close()

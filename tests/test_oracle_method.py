@@ -94,3 +94,30 @@ def test_neutrally_buoyant_bubble_follows_a_uniformly_accelerating_liquid():
             x = x + v_expect - 0.45 * a
         assert np.allclose(bub.pos[:, 0], np.mod(x, 8.0), rtol=0, atol=1e-12)
         assert np.allclose(bub.ulp[:, 0], a * n, rtol=0, atol=1e-16)
+
+
+def test_lateral_wall_clamp_stops_only_the_normal_motion():
+    """Pins the lateral clamp (reading R14): a bubble driven into the x = 0 wall ends the step at
+    x = 0 exactly with u_x = 0, while its y and z motion is that of the same bubble without the
+    lateral velocity. In quiescent liquid (the first step: U = 0, so u_l = w_l = 0 and no lift)
+    with the Stokes drag alone (cd_k = 0, |u_r| d / nu small, so C_D |u_r| = 24 nu / d) every
+    force on the bubble is linear and acts per component, so the clamped x motion cannot reach y
+    or z; an error that zeroed the wrong component, clamped to the wrong cell or moved the bubble
+    back by another rule fails one of the equalities."""
+    lat_a = O.Lattice(16, 16, 24, 1.0)
+    lat_b = O.Lattice(16, 16, 24, 1.0)
+    P = _params(cd_k=0.0, g=1e-5, sigma=1e-5)
+    pos = [[0.02], [7.4], [8.2]]
+    a = O.Bubbles(pos=pos, d=[2.0], vel=[[-0.1], [0.003], [0.002]])
+    b = O.Bubbles(pos=pos, d=[2.0], vel=[[0.0], [0.003], [0.002]])
+    O.method_step(lat_a, P, a)
+    O.method_step(lat_b, P, b)
+    assert a.pos[0, 0] == 0.0 and a.vel[0, 0] == 0.0
+    assert b.pos[0, 0] == 0.02 and b.vel[0, 0] == 0.0
+    assert np.array_equal(a.pos[1:], b.pos[1:]) and np.array_equal(a.vel[1:], b.vel[1:])
+    assert a.pos[1, 0] != 7.4 and a.pos[2, 0] != 8.2  # the other components moved
+    # the same at the far wall, x = nx - 1
+    c = O.Bubbles(pos=[[14.98], [7.4], [8.2]], d=[2.0], vel=[[0.1], [0.003], [0.002]])
+    O.method_step(O.Lattice(16, 16, 24, 1.0), P, c)
+    assert c.pos[0, 0] == 15.0 and c.vel[0, 0] == 0.0
+    assert np.array_equal(c.pos[1:], b.pos[1:]) and np.array_equal(c.vel[1:], b.vel[1:])
