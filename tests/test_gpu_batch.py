@@ -141,6 +141,37 @@ def test_per_column_gravity_and_surface_tension(prec):
 
 
 @pytest.mark.gpu
+def test_columns_without_bubbles_and_a_bubble_free_batch():
+    """A column holding no bubble (an empty bubble range between two others) steps as a plain
+    lattice; a batch with no bubble at all runs the liquid step alone."""
+    cols = _crowded_columns(nb=3)
+    cols[1] = dict(cols[1], pos=np.zeros((3, 0)), d=np.zeros(0))
+    print("[case] batch with an empty middle column", flush=True)
+    batch = S.Batch(cols, S.bubble_params(**_params()), precision="f64")
+    assert batch.bubble_range(1) == (3, 3)
+    batch.step(6)
+    batch.run(10, graph_steps=10)
+    pos = batch.bubbles.positions()
+    for c, col in enumerate(cols):
+        g_ref, pos_ref = _single(col, "f64", 16)
+        b0, b1 = batch.bubble_range(c)
+        assert np.array_equal(batch.populations(c).double().cpu().numpy(), g_ref), c
+        assert np.array_equal(pos[:, b0:b1], pos_ref), c
+    g1 = batch.populations(1).double().cpu().numpy()
+    assert np.abs(g1).max() == 0.0  # no force ever reached the empty column: still at rest
+    batch.check()
+    batch.close()
+    empty = [dict(col, pos=np.zeros((3, 0)), d=np.zeros(0)) for col in cols]
+    batch = S.Batch(empty, S.bubble_params(**_params()), precision="f32")
+    batch.run(8, graph_steps=4)
+    sums, diverged = batch.sums()
+    assert not diverged.any()
+    assert np.allclose(sums[:, 0], [np.prod(c["shape"]) for c in empty], rtol=0, atol=1e-6)
+    batch.check()
+    batch.close()
+
+
+@pytest.mark.gpu
 def test_batched_sweep_rerun_is_bitwise_identical():
     """The 64-column sweep (1-8 bubbles per column, 50 M sites) run twice, per-step launches and
     persistent launches: same bits everywhere."""
