@@ -92,3 +92,21 @@ def test_null_context_calls_are_rejected():
     assert lib.lbm_batch_get_step_occupancy(None, ct.byref(out)) == L.LBM_EINVAL
     assert out.value == -7  # nothing written on rejection
     assert lib.lbm_destroy(None) == L.LBM_OK
+
+
+@pytest.mark.parametrize("g,sigma,ok", [(0.0, 0.0, True), (3e-4, 1e-4, True), (-1e-5, 0.0, False),
+                                        (0.0, -1.0, False), (float("nan"), 0.0, False),
+                                        (0.0, float("inf"), False)])
+def test_batch_column_constants_are_checked(g, sigma, ok):
+    """A batched column's own gravity and surface tension: 0 takes the batch's value; negative or
+    non-finite values are rejected before any device work."""
+    cols = L.make_columns([((24, 24, 48), 1.2, (0,) * 6, 1, g, sigma),
+                           ((16, 20, 40), 0.9, (0,) * 6, 2)])
+    assert ct.sizeof(L.LbmColumn) == 72 and cols[1].bubble_begin == 1
+    if ok:
+        pool, scratch = L.lbm_batch_bytes_required(cols, L.LBM_FP32_SHIFTED)
+        assert pool > 0 and scratch > 0
+    else:
+        with pytest.raises(L.LbmError) as e:
+            L.lbm_batch_bytes_required(cols, L.LBM_FP32_SHIFTED)
+        assert e.value.code == L.LBM_EINVAL
