@@ -225,7 +225,8 @@ def time_steps(sim, K, stream):
 
 def leg_dense(args, steps):
     """The dense dispersed column (256 x 256 x 768, 20 000 bubbles, FP32) for its stated number of
-    whole method steps (overlapped), the liquid launch tuned as for the headline column."""
+    whole method steps (overlapped), the liquid launch tuned as for the headline column; then a
+    shorter run of the serial step for the fused kernel's rate when it has the chip alone."""
     import torch
     import workloads as W
     from paper_1710_07073_amd import autotune
@@ -257,6 +258,23 @@ def leg_dense(args, steps):
                         "unit": "GB/s", "frac": round(alg / kern_s / 1e9 / HBM_PEAK_GBS, 4)},
            "launch": {"vec": vec, "bx": bx, "workgroups_per_cu": L.lbm_get_step_occupancy(sim.ctx)},
            "mass_drift": sums[0] - w.cells}
+    # the same column with the bubble half and the liquid step one after the other: the fused
+    # step then updates the whole lattice alone on the chip (its 152 B per site are a lower bound
+    # of what it moves: forced tiles add 36 B per site)
+    L.lbm_set_overlap(sim.ctx, False)
+    for _ in range(4):
+        sim.step(1)
+    ks = min(steps, 256)
+    s_el, s_kern, s_nt, _ = time_steps(sim, ks, stream)
+    sim.check()
+    alg_full = 38 * 4 * w.cells
+    out["serial"] = {"steps": ks, "ms_per_step": round(s_el / ks * 1e3, 5),
+                     "roofline": {"bound": "hbm", "kernel": "k_step_bb (whole lattice, alone)",
+                                  "sites_per_launch": w.cells, "alg_bytes_per_launch": alg_full,
+                                  "avg_launch_ms": round(s_kern * 1e3, 5), "launches_timed": s_nt,
+                                  "achieved": round(alg_full / s_kern / 1e9, 1),
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(alg_full / s_kern / 1e9 / HBM_PEAK_GBS, 4)}}
     sim.close()
     return out
 
