@@ -10,8 +10,9 @@
 //             the force field with the same weights (atomic adds) and the tile flags, or
 //   k_spread_gather (several bubbles: one wavefront per tile) the same sums per cell in bubble
 //             order from the lists, so that the force field is bit-reproducible.
-// Up to 256 bubbles on one lattice (not in the exact-time variant) k_interp's workgroup also runs
-// k_ode's update of its bubble on one lane and flags the bubble's tiles, and k_ode is not launched.
+// Up to 256 bubbles on one lattice and 512 over many columns (not in the exact-time variant)
+// k_interp's workgroup also runs k_ode's update of its bubble on one lane and flags the bubble's
+// tiles, and k_ode is not launched.
 // The coupling variants of bubble_params.coupling (reaction, point-sampled weights, exact-time
 // forward coupling) are modes of these kernels. k_mark marks the region of an overlapped step.
 //
@@ -1254,8 +1255,16 @@ constexpr uint32_t kGatherMaxBlocks = 2048;
 // bubble, at 108 VGPRs four of them per compute unit, 1024 on the chip.
 constexpr int kInterpLatencyMaxBubbles = 1024;
 // Bubble counts up to which k_interp also runs the bubble update (k_ode's ~200 VGPRs then limit
-// it to two workgroups per compute unit; up to 256 bubbles every workgroup still has its own).
+// it to two workgroups per compute unit): on one lattice, whose bubble kernels share the chip with
+// the bulk launch, 256; for many columns, whose bubble kernels have the chip, every workgroup
+// resident at once (two per compute unit).
 constexpr int kFuseMaxBubbles = 256;
+constexpr int kFuseMaxBubblesBatch = 512;
+
+template <typename Geo>
+constexpr int fuse_max_bubbles() {
+  return std::is_same_v<Geo, OneColumn> ? kFuseMaxBubbles : kFuseMaxBubblesBatch;
+}
 
 template <typename T, typename Geo>
 hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_t stream) {
@@ -1265,9 +1274,8 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
   if (exact) {
     if constexpr (std::is_same_v<Geo, OneColumn>)
       hipLaunchKernelGGL((k_interp<T, Geo, true>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
-  } else if (std::is_same_v<Geo, OneColumn> && nb <= kFuseMaxBubbles) {
-    if constexpr (std::is_same_v<Geo, OneColumn>)
-      hipLaunchKernelGGL((k_interp<T, Geo, false, 8, true>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+  } else if (nb <= fuse_max_bubbles<Geo>()) {
+    hipLaunchKernelGGL((k_interp<T, Geo, false, 8, true>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
   } else if (nb <= kInterpLatencyMaxBubbles) {
     hipLaunchKernelGGL((k_interp<T, Geo, false, 8>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
   } else {
@@ -1275,7 +1283,7 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const bool fused = std::is_same_v<Geo, OneColumn> && !exact && nb <= kFuseMaxBubbles;
+  const bool fused = !exact && nb <= fuse_max_bubbles<Geo>();
   if (!fused) {
     hipLaunchKernelGGL((k_ode<Geo>), dim3(div_up(nb, 64)), dim3(64), 0, stream, geo, A);
     e = hipGetLastError();
