@@ -307,29 +307,29 @@ def test_single_lattice_graph_run_matches_eager():
 @pytest.mark.gpu
 def test_batched_sweep_full_size():
     """The 64-column sweep (cross-sections 24-96, heights 2-4 times the width, omega from 0.6 to
-    1.9, 1-8 bubbles each) in the benchmark's launch configuration (graph replays): a sample of
-    columns against their single-lattice runs, and mass conservation of every column."""
-    ws = W.batched(steps=4)
+    1.9, 1-8 bubbles each) in the benchmark's launch configuration (graph replays, at most 3
+    workgroups per compute unit): every column reproduces its single-lattice run bit for bit
+    (forces gathered in bubble order on both), and every column conserves mass."""
+    ws = W.batched(steps=20)
     cols = [dict(shape=w.shape, omega=w.omega, bc=w.bc, pos=w.pos, d=w.d) for w in ws]
+    print(f"[case] 64-column sweep, 20 steps in graphs of 10, every column against its own run",
+          flush=True)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         batch = S.Batch(cols, S.bubble_params(**ws[0].params), precision="f32", stream=stream)
-        batch.run(4, graph_steps=2)
+        L.lbm_batch_set_step_occupancy(batch.handle, 3)
+        batch.run(20, graph_steps=10)
         stream.synchronize()
         batch.check()
-        sizes = [np.prod(w.shape) for w in ws]
-        sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17})
         pos = batch.bubbles.positions()
-        for c in sample:
-            sim = S.Simulation(ws[c].shape, ws[c].omega, precision="f32", bc=ws[c].bc, stream=stream)
-            sim.add_bubbles(ws[c].pos, ws[c].d, S.bubble_params(**ws[c].params))
-            sim.step(4)
-            g_ref = sim.populations().double().cpu().numpy()
-            b0, b1 = batch.bubble_range(c)
-            assert np.abs(pos[:, b0:b1] - sim.bubbles.positions()).max() <= 1e-4
-            sim.close()
-            assert rel_l2(batch.populations(c).double().cpu().numpy(), g_ref) <= 2e-5
         for c, w in enumerate(ws):
+            sim = S.Simulation(w.shape, w.omega, precision="f32", bc=w.bc, stream=stream)
+            sim.add_bubbles(w.pos, w.d, S.bubble_params(**w.params))
+            sim.run(20, graph_steps=10)
+            b0, b1 = batch.bubble_range(c)
+            assert torch.equal(batch.populations(c), sim.populations()), c
+            assert np.array_equal(pos[:, b0:b1], sim.bubbles.positions()), c
+            sim.close()
             mass = batch.populations(c).double().sum().item()  # sum of g = sum rho - N
             assert abs(mass) < 1e-6 * w.cells
         batch.close()
