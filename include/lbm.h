@@ -234,6 +234,17 @@ lbm_status lbm_populations(lbm_ctx* ctx, void* out);
  * context's population layout. */
 lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out);
 
+/* Checkpoint and resume at a step boundary: everything the method carries from one step to the
+ * next besides the caller's bubble arrays is the post-collision buffer and the velocity field of
+ * the last collision (Algorithm 1; the force field is zero between steps). lbm_checkpoint copies
+ * them (19 x N and 3 x N elements of the lattice type, the buffer in the library's layout) into
+ * caller-owned device buffers, lbm_restore copies them back into a lattice of the same
+ * description, asynchronously on the context's stream; the caller saves and restores the bubble
+ * arrays itself. A restored lattice continues bit for bit as the one checkpointed. LBM_EINVAL
+ * while a bubble half awaits its lbm_step(), or for a NULL buffer. */
+lbm_status lbm_checkpoint(lbm_ctx* ctx, void* state_out, void* vel_out);
+lbm_status lbm_restore(lbm_ctx* ctx, const void* state, const void* vel);
+
 /* Rebind the context to other caller-owned buffers (each nullable: keep the current one). state:
  * a population buffer (layout of the context) that already holds the current state; next_state:
  * the buffer the next liquid step writes into (then the current state); vel: the velocity field

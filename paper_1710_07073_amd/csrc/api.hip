@@ -425,6 +425,28 @@ lbm_status lbm_state_buffer(lbm_ctx* ctx, void** out) {
   return LBM_OK;
 }
 
+lbm_status lbm_checkpoint(lbm_ctx* ctx, void* state_out, void* vel_out) {
+  if (!ctx || !state_out || !vel_out || ctx->hs.pending) return LBM_EINVAL;
+  const size_t n = (size_t)ctx->geom.N * ctx->elem;
+  hipError_t e = hipMemcpyAsync(state_out, ctx->pops[ctx->hs.cur], 19 * n, hipMemcpyDeviceToDevice,
+                                ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(vel_out, ctx->vel, 3 * n, hipMemcpyDeviceToDevice, ctx->stream);
+  return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+lbm_status lbm_restore(lbm_ctx* ctx, const void* state, const void* vel) {
+  if (!ctx || !state || !vel || ctx->hs.pending) return LBM_EINVAL;
+  const size_t n = (size_t)ctx->geom.N * ctx->elem;
+  hipError_t e = hipMemcpyAsync(ctx->pops[ctx->hs.cur], state, 19 * n, hipMemcpyDeviceToDevice,
+                                ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->vel, vel, 3 * n, hipMemcpyDeviceToDevice, ctx->stream);
+  // the next overlapped step marks its region from the bubbles it is given
+  ctx->hs.marked = false;
+  return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
 lbm_status lbm_run(lbm_ctx* ctx, const bubble_params* p, const bubble_soa* s, int32_t nb,
                    int32_t nsteps, int32_t graph_steps) {
   if (!ctx || !p || !s || nb < 0 || nsteps < 0) return LBM_EINVAL;

@@ -39,6 +39,7 @@ EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch",
            "lbm_batch_step", "lbm_batch_run", "lbm_batch_populations", "lbm_batch_sums",
            "lbm_batch_column",
            "lbm_batch_check", "lbm_batch_destroy",
+           "lbm_checkpoint", "lbm_restore",
            "lbm_adjoint_liquid", "lbm_adjoint_liquid_tiles", "lbm_step_tiles",
            "lbm_adjoint_bubbles", "lbm_bubble_record",
            "lbm_record_next_bubble_half", "lbm_record_positions", "lbm_bind_buffers",
@@ -137,6 +138,8 @@ def lib():
         L.lbm_adjoint_liquid.argtypes = [P, P, P, P, P, P, P, P]
         L.lbm_adjoint_liquid_tiles.argtypes = [P, P, P, P, P, P, P, P, P]
         L.lbm_step_tiles.argtypes = [P, P, ct.POINTER(ct.c_int64)]
+        L.lbm_checkpoint.argtypes = [P, P, P]
+        L.lbm_restore.argtypes = [P, P, P]
         L.lbm_adjoint_bubbles.argtypes = [P, ct.POINTER(BubbleParams), P, P, P, P, P, P, ct.c_int32, P]
         L.lbm_bubble_record.argtypes = [P, ct.POINTER(BubbleSoA), ct.c_int32, ct.c_int32, P]
         L.lbm_record_next_bubble_half.argtypes = [P, P]
@@ -391,6 +394,14 @@ def lbm_adjoint_liquid(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, grad
 def lbm_adjoint_liquid_tiles(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, tiles, grad):
     _ok(lib().lbm_adjoint_liquid_tiles(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, tiles,
                                        grad), "lbm_adjoint_liquid_tiles")
+
+
+def lbm_checkpoint(ctx, state_out, vel_out):
+    _ok(lib().lbm_checkpoint(ctx, state_out, vel_out), "lbm_checkpoint")
+
+
+def lbm_restore(ctx, state, vel):
+    _ok(lib().lbm_restore(ctx, state, vel), "lbm_restore")
 
 
 def lbm_step_tiles(ctx, tiles=None):

@@ -147,6 +147,27 @@ class Simulation:
     def check(self):
         L.lbm_check(self.ctx)
 
+    # ---- checkpoint and resume ----
+    _SAVED = ("x", "y", "z", "ux", "uy", "uz", "ulx", "uly", "ulz", "state")
+
+    def checkpoint(self):
+        """Device copies of what the next step needs: the post-collision buffer, the velocity
+        field of the last collision (lbm_checkpoint) and the bubble arrays."""
+        state = torch.empty_like(self.pops[0])
+        vel = torch.empty_like(self.vel)
+        L.lbm_checkpoint(self.ctx, _ptr(state), _ptr(vel))
+        bub = None
+        if self.bubbles is not None:
+            bub = {k: self.bubbles.t[k].clone() for k in self._SAVED}
+        return dict(state=state, vel=vel, bubbles=bub)
+
+    def restore(self, ckpt):
+        """Continue from a checkpoint of a lattice of the same description (lbm_restore)."""
+        L.lbm_restore(self.ctx, _ptr(ckpt["state"]), _ptr(ckpt["vel"]))
+        if ckpt["bubbles"] is not None:
+            for k, v in ckpt["bubbles"].items():
+                self.bubbles.t[k].copy_(v)
+
 
 class Batch:
     """Many columns (each a Workload-like spec) stepped together through the batched C ABI."""
