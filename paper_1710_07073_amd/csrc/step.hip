@@ -337,8 +337,10 @@ hipError_t launch_step(lbm_ctx* c) {
   if (c->hs.pending) {
     // overlapped step: the bulk and the bubble kernels are enqueued and the caller's stream waits
     // for the bubble kernels; the region runs after the bulk, alone on the chip. (Launched on the
-    // side stream right after the spread, beside the bulk, it slowed the bulk by more than it
-    // saved: both measured on 128 x 128 x 512 with one bubble and with 20 000.)
+    // side stream right after the bubble kernels, with its row flags cleared by the next step
+    // rather than by the region kernel, it was bitwise identical and 0.7 % faster on 128 x 128 x
+    // 512 with one bubble, 0.4 % on 256 x 256 x 768 with 20 000: too little for flags that
+    // outlive their step and must then be cleared on every switch between serial and overlapped.)
     if (c->elem == 4)
       e = c->general ? launch_region_typed<float, true>(c, c->pending_nb, c->stream)
                      : launch_region_typed<float, false>(c, c->pending_nb, c->stream);
