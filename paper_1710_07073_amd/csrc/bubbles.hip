@@ -407,10 +407,11 @@ __device__ __forceinline__ void state_velocity(const T* __restrict__ src, const 
 // Forward coupling: u_l = sum W U and w_l = sum W curl U over the window.
 // ---------------------------------------------------------------------------------------------
 // EXACT: the exact-time coupling variant (single lattice), reading the current state's velocity.
-// GATHER: window cells per thread whose loads are in flight together. Few bubbles (all their
-// workgroups on the chip at once): 8, so each thread waits for one round trip per 8 cells. Many
-// bubbles: 1, at 50 VGPRs instead of 108, so that more workgroups stay resident beside the bulk
-// launch (20 000 bubbles: 394 us against 1289 us with 8).
+// GATHER: cells of a thread's window column whose loads are in flight together. Few bubbles (all
+// their workgroups on the chip at once): 8, so each thread waits for one round trip per 8 cells.
+// Many bubbles: 4, at fewer VGPRs, so that more workgroups stay resident beside the bulk launch
+// (20 000 bubbles with the earlier cell-by-cell loop: 394 us against 1289 us with 8 beside the
+// bulk launch; with the column sums, alone on the chip, 154 us with 4 against 177 us with 1).
 // FUSE (few bubbles on one lattice): the workgroup then also runs its bubble's update (k_ode's
 // arithmetic, one lane) and flags its tiles, so the step has one launch less. The fourth wavefront,
 // idle while the other three compute the weights, prepares the update's closure constants and
@@ -563,81 +564,108 @@ __device__ void interp_bubble(const Geo& geo, const BubbleArgs& A, const int b) 
   const T* __restrict__ S = nullptr;  // exact-time coupling: the current state
   if constexpr (EXACT) S = static_cast<const T*>(geo.state);
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  // The thread's window entries f = tid, tid + kBlock, ... as f = i + Dx (j + Dy k), stepped by
-  // kBlock entries with carries (one division per thread). cell_of: the lattice cell of the
-  // current entry and its weight indices; accumulate: the cell's velocity times its weight and
-  // curl weights into the six sums.
-  int ci = tid % Dx, cj = (tid / Dx) % Dy, ck = tid / Dx / Dy;
-  const int di = kBlock % Dx, dj = (kBlock / Dx) % Dy, dk = kBlock / Dx / Dy;
-  auto advance = [&]() {
-    ci += di;
-    const int carry = ci >= Dx;
-    if (carry) ci -= Dx;
-    cj += dj + carry;
-    if (cj >= Dy) {
-      cj -= Dy;
-      ++ck;
-    }
-    ck += dk;
-  };
-  auto cell_of = [&](int& ix, int& iy, int& iz) {
-    const int vx = win[0].dlo + ci, vy = win[1].dlo + cj, vz = win[2].dlo + ck;
-    ix = vx - win[0].lo + 1;
-    iy = vy - win[1].lo + 1;
-    iz = vz - win[2].lo + 1;
-    const int x = px ? wrapi(vx, G.nx) : vx;
-    const int y = py ? wrapi(vy, G.ny) : vy;
-    const int z = pz ? wrapi(vz, G.nz) : vz;
-    return ((uint32_t)z * G.ny + y) * G.nx + x;
-  };
-  auto accumulate = [&](int ix, int iy, int iz, double ux, double uy, double uz) {
-    const double wa = s_w[0][ix], da = s_dw[0][ix];
-    const double wb = s_w[1][iy], db = s_dw[1][iy];
-    const double wc = s_w[2][iz], dc = s_dw[2][iz];
-    const double W = wa * wb * wc;
-    const double a_dbc = wa * db * wc;  // weight of d/dy
-    const double a_bdc = wa * wb * dc;  // weight of d/dz
-    const double da_bc = da * wb * wc;  // weight of d/dx
-    acc[0] += W * ux;
-    acc[1] += W * uy;
-    acc[2] += W * uz;
-    acc[3] += uz * a_dbc - uy * a_bdc;  // dUz/dy - dUy/dz
-    acc[4] += ux * a_bdc - uz * da_bc;  // dUx/dz - dUz/dx
-    acc[5] += uy * da_bc - ux * a_dbc;  // dUy/dx - dUx/dy
-  };
   if constexpr (EXACT) {
+    // The thread's window entries f = tid, tid + kBlock, ... as f = i + Dx (j + Dy k), stepped by
+    // kBlock entries with carries (one division per thread); each cell's velocity (from the
+    // state) times its weight and curl weights into the six sums.
+    int ci = tid % Dx, cj = (tid / Dx) % Dy, ck = tid / Dx / Dy;
+    const int di = kBlock % Dx, dj = (kBlock / Dx) % Dy, dk = kBlock / Dx / Dy;
     for (int f = tid; f < total; f += kBlock) {
-      int ix, iy, iz;
-      const uint32_t c = cell_of(ix, iy, iz);
-      const int x = (int)(c % (uint32_t)G.nx), y = (int)((c / (uint32_t)G.nx) % (uint32_t)G.ny);
-      const int z = (int)(c / ((uint32_t)G.nx * G.ny));
+      const int vx = win[0].dlo + ci, vy = win[1].dlo + cj, vz = win[2].dlo + ck;
+      const int ix = vx - win[0].lo + 1, iy = vy - win[1].lo + 1, iz = vz - win[2].lo + 1;
+      const int x = px ? wrapi(vx, G.nx) : vx;
+      const int y = py ? wrapi(vy, G.ny) : vy;
+      const int z = pz ? wrapi(vz, G.nz) : vz;
+      const uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
       double ux, uy, uz;
       state_velocity<T>(S, G, x, y, z, c, ux, uy, uz);
-      accumulate(ix, iy, iz, ux, uy, uz);
-      advance();
+      const double wa = s_w[0][ix], da = s_dw[0][ix];
+      const double wb = s_w[1][iy], db = s_dw[1][iy];
+      const double wc = s_w[2][iz], dc = s_dw[2][iz];
+      const double W = wa * wb * wc;
+      const double a_dbc = wa * db * wc;  // weight of d/dy
+      const double a_bdc = wa * wb * dc;  // weight of d/dz
+      const double da_bc = da * wb * wc;  // weight of d/dx
+      acc[0] += W * ux;
+      acc[1] += W * uy;
+      acc[2] += W * uz;
+      acc[3] += uz * a_dbc - uy * a_bdc;  // dUz/dy - dUy/dz
+      acc[4] += ux * a_bdc - uz * da_bc;  // dUx/dz - dUz/dx
+      acc[5] += uy * da_bc - ux * a_dbc;  // dUy/dx - dUx/dy
+      ci += di;
+      const int carry = ci >= Dx;
+      if (carry) ci -= Dx;
+      cj += dj + carry;
+      if (cj >= Dy) {
+        cj -= Dy;
+        ++ck;
+      }
+      ck += dk;
     }
   } else {
-    // kGather cells per thread in flight: their loads issued together, then the sums in the
-    // order of the cells (each thread's terms in the same order as one cell at a time)
-    constexpr int kGather = GATHER;
-    for (int f0 = tid; f0 < total; f0 += kGather * kBlock) {
-      int ix[kGather], iy[kGather], iz[kGather];
-      T u[kGather][3];
+    // Separable sums by window column: a thread takes the column (i, j) of the window over a
+    // slab of z (one slab unless the window has fewer columns than the workgroup has threads)
+    // and sums along z the velocity times the z weight and times the z derivative weight; the
+    // column's x and y weights then enter once:
+    //   sum_k wa wb wc_k u = wa wb Sw,  curl terms from wa db Sw, wa wb Sd and da wb Sw,
+    // with Sw = sum_k wc_k u_k and Sd = sum_k dc_k u_k. Consecutive lanes take consecutive x, and
+    // the three components are read at one 32-bit offset from their planes' bases. The loads of
+    // GATHER z cells are issued together, the sums then taken in z order.
+    constexpr int kZ = GATHER;
+    const int cols = Dx * Dy;
+    const int slabs = min(max(1, kBlock / cols), Dz);
+    const uint32_t plane = (uint32_t)G.nx * (uint32_t)G.ny;
+    const uint32_t wrap_back = (uint32_t)G.nz * plane;
+    const T* __restrict__ Ux = U;
+    const T* __restrict__ Uy = U + G.N;
+    const T* __restrict__ Uz = U + 2 * (size_t)G.N;
+    const int iz_base = win[2].dlo - win[2].lo + 1;
+    for (int t = tid; t < cols * slabs; t += kBlock) {
+      const int colm = t % cols, slab = t / cols;
+      const int ci = colm % Dx, cj = colm / Dx;
+      const int k0 = slab * Dz / slabs, k1 = (slab + 1) * Dz / slabs;
+      const int vx = win[0].dlo + ci, vy = win[1].dlo + cj, vz = win[2].dlo + k0;
+      const int x = px ? wrapi(vx, G.nx) : vx;
+      const int y = py ? wrapi(vy, G.ny) : vy;
+      int z = pz ? wrapi(vz, G.nz) : vz;
+      uint32_t c = ((uint32_t)z * G.ny + y) * G.nx + x;
+      double sw[3] = {0.0, 0.0, 0.0}, sd[3] = {0.0, 0.0, 0.0};
+      for (int k = k0; k < k1; k += kZ) {
+        T u[kZ][3];
 #pragma clang loop unroll(full)
-      for (int s = 0; s < kGather; ++s) {
-        if (f0 + s * kBlock < total) {
-          const uint32_t c = cell_of(ix[s], iy[s], iz[s]);
-          u[s][0] = U[c];
-          u[s][1] = U[G.N + c];
-          u[s][2] = U[2 * (size_t)G.N + c];
-          advance();
+        for (int s = 0; s < kZ; ++s) {
+          if (k + s < k1) {
+            u[s][0] = Ux[c];
+            u[s][1] = Uy[c];
+            u[s][2] = Uz[c];
+            c += plane;
+            if (++z == G.nz) {  // periodic z only: a clipped window ends inside the domain
+              z = 0;
+              c -= wrap_back;
+            }
+          }
+        }
+#pragma clang loop unroll(full)
+        for (int s = 0; s < kZ; ++s) {
+          if (k + s < k1) {
+            const double wc = s_w[2][iz_base + k + s], dc = s_dw[2][iz_base + k + s];
+            for (int m = 0; m < 3; ++m) {
+              sw[m] += wc * (double)u[s][m];
+              sd[m] += dc * (double)u[s][m];
+            }
+          }
         }
       }
-#pragma clang loop unroll(full)
-      for (int s = 0; s < kGather; ++s) {
-        if (f0 + s * kBlock < total)
-          accumulate(ix[s], iy[s], iz[s], (double)u[s][0], (double)u[s][1], (double)u[s][2]);
-      }
+      const int ix = vx - win[0].lo + 1, iy = vy - win[1].lo + 1;
+      const double wa = s_w[0][ix], da = s_dw[0][ix];
+      const double wb = s_w[1][iy], db = s_dw[1][iy];
+      const double w_ab = wa * wb, w_adb = wa * db, w_dab = da * wb;
+      acc[0] += w_ab * sw[0];
+      acc[1] += w_ab * sw[1];
+      acc[2] += w_ab * sw[2];
+      acc[3] += w_adb * sw[2] - w_ab * sd[1];  // dUz/dy - dUy/dz
+      acc[4] += w_ab * sd[0] - w_dab * sw[2];  // dUx/dz - dUz/dx
+      acc[5] += w_dab * sw[1] - w_adb * sw[0];  // dUy/dx - dUx/dy
     }
   }
   if (slot0 < kTileCap) tlist[(size_t)t0 * kTileCap + slot0] = (uint32_t)b;
@@ -1252,7 +1280,7 @@ __global__ __launch_bounds__(64) void k_mark(Geo geo, BubbleArgs A, uint32_t* __
 constexpr uint32_t kGatherMaxBlocks = 2048;
 
 // Bubble counts up to which k_interp keeps 8 cells' loads in flight per thread: one workgroup per
-// bubble, at 108 VGPRs four of them per compute unit, 1024 on the chip.
+// bubble, all resident at once (at 76 VGPRs six per compute unit).
 constexpr int kInterpLatencyMaxBubbles = 1024;
 // Bubble counts up to which k_interp also runs the bubble update (k_ode's ~200 VGPRs then limit
 // it to two workgroups per compute unit): on one lattice, whose bubble kernels share the chip with
@@ -1279,7 +1307,7 @@ hipError_t launch_bubble_kernels(const Geo& geo, const BubbleArgs& A, hipStream_
   } else if (nb <= kInterpLatencyMaxBubbles) {
     hipLaunchKernelGGL((k_interp<T, Geo, false, 8>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
   } else {
-    hipLaunchKernelGGL((k_interp<T, Geo, false, 1>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
+    hipLaunchKernelGGL((k_interp<T, Geo, false, 4>), dim3(nb), dim3(kBlock), 0, stream, geo, A);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
