@@ -1,6 +1,6 @@
 """The dense dispersed-flow workload at its full size (256 x 256 x 768 FP32 lattice, 20 000
 bubbles, lognormal diameters around 3, omega drawn in [1.2, 1.8]) in the launch configuration the
-benchmark uses (overlapped steps replayed from HIP graphs): a 100-step prefix compared with the
+benchmark uses (overlapped steps replayed from HIP graphs): a 200-step prefix compared with the
 oracle on the whole lattice and every bubble (by then the bubbles have reached their rise velocity
 and their wakes overlap), and properties that hold at any size (mass conservation, finiteness)
 over more steps."""
@@ -19,7 +19,7 @@ U_TOL = 2e-5
 @pytest.mark.gpu
 @pytest.mark.timeout(900)
 def test_dense_column_full_size_matches_oracle():
-    w = W.dense(steps=100)
+    w = W.dense(steps=200)
     print(f"[case] {w.name}: {w.cells} cells, {w.nb} bubbles, omega {w.omega:.4f}, "
           f"{w.steps} steps", flush=True)
     sim = gpu_sim(w)
@@ -37,7 +37,7 @@ def test_dense_column_full_size_matches_oracle():
     lat, bub, P = oracle_state(w)
     for k in range(w.steps):
         O.method_step(lat, P, bub)
-        if (k + 1) % 20 == 0:
+        if (k + 1) % 25 == 0:
             print(f"  oracle step {k + 1}", flush=True)
     _, u_o, _ = lat.moments()
     eu = rel_l2(u_gpu, u_o)
@@ -51,7 +51,7 @@ def test_dense_column_full_size_matches_oracle():
     assert ev <= U_TOL
     assert eu <= U_TOL
     assert abs(sums[0] - w.cells) < 1e-3
-    assert rise > 0.002  # the bubbles rose (Stokes rise of a d = 3 bubble in 100 steps: about 0.005)
+    assert rise > 0.004  # the bubbles rose (Stokes rise of a d = 3 bubble in 200 steps: about 0.01)
 
 
 @pytest.mark.gpu
