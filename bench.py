@@ -275,8 +275,45 @@ def leg_dense(args, steps):
                                   "achieved": round(alg_full / s_kern / 1e9, 1),
                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                   "frac": round(alg_full / s_kern / 1e9 / HBM_PEAK_GBS, 4)}}
+    # the bubble half alone (serial step: its kernels on the caller's stream), events around it
+    out["bubbles"] = time_bubble_half(sim, stream, 32)
     sim.close()
     return out
+
+
+def window_cells(pos, d, shape, kernel_factor):
+    """Cells of the bubbles' kernel windows (eq. (18)-(19): the cells whose extent overlaps
+    [x - n, x + n], n = kernel_factor d), clipped to a lattice with walls on every face."""
+    n = kernel_factor * np.asarray(d)
+    cells = np.ones(len(n))
+    for a, ext in enumerate(shape):
+        lo = np.maximum(np.floor(pos[a] - n - 0.5) + 1, 0)
+        hi = np.minimum(np.ceil(pos[a] + n + 0.5) - 1, ext - 1)
+        cells *= np.maximum(hi - lo + 1, 0)
+    return int(cells.sum())
+
+
+def time_bubble_half(sim, stream, k):
+    """Median over k serial method steps of the bubble half's GPU time (events on the caller's
+    stream around bubbles_step; each step's liquid update follows), and the window cells it
+    touches per second."""
+    import torch
+    from paper_1710_07073_amd import lbm as L
+    bub = sim.bubbles
+    touches = window_cells(bub.positions(), bub.t["d"].cpu().numpy(), sim.shape,
+                           sim.params.kernel_factor)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(k)]
+    for a, b in evs:
+        a.record(stream)
+        L.bubbles_step(sim.ctx, sim.params, bub.soa, bub.nb)
+        b.record(stream)
+        L.lbm_step(sim.ctx, 1)
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in evs)[k // 2] / 1e3
+    return {"kernels": "k_interp, k_ode, k_spread_gather (serial step)", "steps_timed": k,
+            "us_per_step_median": round(t * 1e6, 1), "window_cells_per_step": touches,
+            "cell_touches_per_s": round(touches / t, 1)}
 
 
 def copy_calibration():
