@@ -117,27 +117,36 @@ def tune(sim, steps=20, use_cache=True, verbose=False):
     return vec, bx, entry
 
 
-def tune_method_occupancy(sim, steps=8, caps=OCCUPANCY):
-    """The occupancy cap timed on whole method steps (bubble half and liquid step, overlapped where
-    the lattice overlaps) rather than on the liquid step alone: beside the bubble kernels the best
-    cap can differ. Applies the fastest and returns (cap, [[cap, us per step]], method steps run).
-    The simulation advances by len(caps) * (steps + 2) steps (callers count them as warm-up)."""
+def tune_method_occupancy(sim, steps=8, caps=OCCUPANCY, modes=None):
+    """The occupancy cap timed on whole method steps (bubble half and liquid step) rather than on
+    the liquid step alone: beside the bubble kernels the best cap can differ. Where the lattice
+    can overlap, the overlapped and the serial step are both timed (the same results bit for bit;
+    which is faster depends on how long the bubble half is against the liquid step). Applies the
+    fastest (cap, overlap) and returns (cap, [[cap, us per step, overlap]], method steps run).
+    The simulation advances by len(modes) * len(caps) * (steps + 2) steps (callers count them as
+    warm-up)."""
     stream = sim.stream
     bub = sim.bubbles
+    on, avail = L.lbm_get_overlap(sim.ctx)
+    if modes is None:
+        modes = (True, False) if avail else (bool(on),)
     sweep = []
-    for occ in caps:
-        L.lbm_set_step_occupancy(sim.ctx, occ)
-        L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, 2, 0)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, steps, 0)
-        e1.record(stream)
-        e1.synchronize()
-        sweep.append([occ, e0.elapsed_time(e1) * 1e3 / steps])
-    best = min(sweep, key=lambda r: r[1])[0]
-    L.lbm_set_step_occupancy(sim.ctx, best)
-    return best, sweep, len(caps) * (steps + 2)
+    for ov in modes:
+        L.lbm_set_overlap(sim.ctx, ov)
+        for occ in caps:
+            L.lbm_set_step_occupancy(sim.ctx, occ)
+            L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, 2, 0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            L.lbm_run(sim.ctx, sim.params, bub.soa, bub.nb, steps, 0)
+            e1.record(stream)
+            e1.synchronize()
+            sweep.append([occ, e0.elapsed_time(e1) * 1e3 / steps, bool(ov)])
+    best = min(sweep, key=lambda r: r[1])
+    L.lbm_set_overlap(sim.ctx, best[2])
+    L.lbm_set_step_occupancy(sim.ctx, best[0])
+    return best[0], sweep, len(modes) * len(caps) * (steps + 2)
 
 
 # ---------------------------------------------------------------------------------------------

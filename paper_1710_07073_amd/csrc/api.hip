@@ -260,6 +260,7 @@ lbm_status lbm_region_cells(lbm_ctx* ctx, int64_t* cells) {
   if (!ctx || !cells) return LBM_EINVAL;
   *cells = 0;
   if (ctx->hs.pending) return LBM_EINVAL;
+  if (!ctx->hs.last_overlapped) return LBM_OK;  // a serial step came after it
   // the list of the last overlapped step stays until the next step of the same parity
   const int r = ctx->hs.rpar ^ 1;
   uint32_t count = 0;

@@ -19,6 +19,7 @@ struct HostState {
   int rpar;               // parity of the next overlapped step (its region flags, list, counter)
   bool pending;           // bubbles_step() enqueued the bulk; lbm_step() must update the region
   bool marked;            // the region of the next overlapped step is marked (within lbm_run)
+  bool last_overlapped;   // the last liquid step was overlapped (its region list is current)
   int64_t steps;
 };
 }  // namespace lbm

@@ -334,7 +334,8 @@ hipError_t launch_bulk(lbm_ctx* c) {
 
 hipError_t launch_step(lbm_ctx* c) {
   hipError_t e;
-  if (c->hs.pending) {
+  const bool overlapped = c->hs.pending;
+  if (overlapped) {
     // overlapped step: the bulk and the bubble kernels are enqueued and the caller's stream waits
     // for the bubble kernels; the region runs after the bulk, alone on the chip. (Launched on the
     // side stream right after the bubble kernels, with its row flags cleared by the next step
@@ -359,6 +360,7 @@ hipError_t launch_step(lbm_ctx* c) {
   if (e == hipSuccess) {
     c->hs.cur ^= 1;
     c->hs.flag_clean[c->hs.flag_cur ^ 1] = true;
+    c->hs.last_overlapped = overlapped;
     ++c->hs.steps;
   }
   return e;

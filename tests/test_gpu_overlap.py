@@ -182,3 +182,29 @@ def test_bubbles_moved_between_runs_are_marked_afresh(graph_steps):
     a = _run_with_moves(False, graph_steps)
     b = _run_with_moves(True, graph_steps)
     _same(a, b)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("graph_steps", [0, 4])
+def test_region_cells_reports_only_an_overlapped_last_step(graph_steps):
+    """lbm_region_cells: the region of the last step if it was overlapped, 0 once a serial step
+    (with bubbles, or a liquid step alone) has come after it, eager and through graph replays."""
+    shape = (48, 40, 64)
+    print(f"[case] {shape}, graph_steps {graph_steps}", flush=True)
+    sim = S.Simulation(shape, 1.35, precision="f32")
+    sim.add_bubbles([[20.0], [20.0], [12.0]], [3.0], S.bubble_params())
+    assert L.lbm_get_overlap(sim.ctx)[1]
+    L.lbm_set_overlap(sim.ctx, True)
+    sim.run(8, graph_steps=graph_steps)
+    overlapped = L.lbm_region_cells(sim.ctx)
+    assert 0 < overlapped < sim.cells
+    L.lbm_set_overlap(sim.ctx, False)
+    sim.run(8, graph_steps=graph_steps)
+    assert L.lbm_region_cells(sim.ctx) == 0
+    L.lbm_set_overlap(sim.ctx, True)
+    sim.run(8, graph_steps=graph_steps)
+    assert L.lbm_region_cells(sim.ctx) == overlapped  # the bubble barely moved: the same rows
+    sim.liquid_steps(1)
+    assert L.lbm_region_cells(sim.ctx) == 0
+    sim.check()
+    sim.close()
