@@ -363,6 +363,14 @@ lbm_status lbm_adjoint_liquid_tiles(lbm_ctx* ctx, const void* state, const void*
                                     const void* lam_next, void* lam_prev, void* lam_u, void* lam_f,
                                     const uint8_t* tiles, double* grad);
 
+/* Timing hook for profiling the adjoint liquid step (the transposed step above, no equation of
+ * its own): start and end (hipEvent_t, each nullable) are recorded on the caller's stream
+ * immediately before and after the next launch of the adjoint liquid kernel made by
+ * lbm_adjoint_liquid() / lbm_adjoint_liquid_tiles(); the clearing and the final sum of the
+ * dL/domega bins stay outside. One-shot: the events are forgotten after that launch. The caller
+ * owns the events. */
+lbm_status lbm_time_next_adjoint_liquid(lbm_ctx* ctx, void* start, void* end);
+
 /* Adjoint of the bubble half (eq. (18)-(21), Table 1, eq. (1)-(4)). record: nb x
  * LBM_BUBBLE_RECORD doubles of the step; vel_prev: velocity field the step interpolated;
  * lam_f: dL/dF from lbm_adjoint_liquid; lam_u (out, accumulated): dL/d(vel_prev); lam: nb x

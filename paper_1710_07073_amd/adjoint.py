@@ -47,8 +47,8 @@ class TrajectoryProblem:
         self.K = int(checkpoint)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        # when a list, backward appends a (start, end) event pair around every adjoint liquid step
-        # of the first segment it processes (the last in time)
+        # when a list, backward appends a (start, end) event pair around the adjoint liquid kernel
+        # of every step of the first segment it processes (the last in time)
         self.liquid_events = None
         # pass each step's tile mask to the adjoint liquid step (False: every cell reads the force
         # and the velocity adjoint; the gradient is the same)
@@ -152,16 +152,16 @@ class TrajectoryProblem:
                 L.lbm_bind_buffers(sim.ctx, None, None, _p(Up[i + 1]))
                 L.lbm_step(sim.ctx, 1)
             for i in reversed(range(n)):
-                ev = None
                 if events is not None:
+                    # recorded by the library around the adjoint liquid kernel's launch alone
                     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                    ev[0].record(self.stream)
+                    for e in ev:
+                        e.record(self.stream)  # creates the underlying event
+                    L.lbm_time_next_adjoint_liquid(sim.ctx, ev[0], ev[1])
+                    events.append(ev)
                 L.lbm_adjoint_liquid_tiles(sim.ctx, _p(H[i]), _p(Fk[i]), _p(lam[cur]),
                                            _p(lam[1 - cur]), _p(lam_u), _p(lam_f),
                                            _p(Tk[i]) if Tk is not None else None, _p(grad))
-                if ev is not None:
-                    ev[1].record(self.stream)
-                    events.append(ev)
                 cur = 1 - cur
                 # the loss's term in this step's positions is added by the kernel
                 L.lbm_adjoint_bubbles(sim.ctx, sim.params, _p(rec[i]), _p(Up[i]), _p(lam_f),

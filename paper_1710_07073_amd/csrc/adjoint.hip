@@ -552,6 +552,17 @@ __global__ __launch_bounds__(64) void k_record(bubble_soa S, int nb, int stage, 
   }
 }
 
+// Records the armed timing events (lbm_time_next_adjoint_liquid) around one launch, then disarms.
+template <typename F>
+hipError_t timed_adjoint(lbm_ctx* c, F&& launch) {
+  hipEvent_t a = c->ta_start, b = c->ta_end;
+  c->ta_start = c->ta_end = nullptr;
+  hipError_t e = a ? hipEventRecord(a, c->stream) : hipSuccess;
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess && b) e = hipEventRecord(b, c->stream);
+  return e;
+}
+
 template <typename T, bool GENERAL>
 hipError_t liquid_typed(lbm_ctx* c, const void* state, const void* force, const void* lam_next,
                         void* lam_prev, void* lam_u, void* lam_f, const uint8_t* tiles,
@@ -563,24 +574,28 @@ hipError_t liquid_typed(lbm_ctx* c, const void* state, const void* force, const 
     hipError_t e = hipSuccess;
     if (!c->bins_clean) e = launch_fill(c->partials, nbins * sizeof(double), c->stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_adj_liquid_bb<T>), dim3(div_up(c->geom.N, 256)), dim3(256), 0, c->stream,
-                       static_cast<const T*>(state), static_cast<const T*>(force),
-                       static_cast<const T*>(lam_next), static_cast<T*>(lam_prev),
-                       static_cast<T*>(lam_u), static_cast<T*>(lam_f), tiles, c->geom,
-                       (T)c->desc.omega, c->partials, nbins);
-    e = hipGetLastError();
+    e = timed_adjoint(c, [&] {
+      hipLaunchKernelGGL((k_adj_liquid_bb<T>), dim3(div_up(c->geom.N, 256)), dim3(256), 0,
+                         c->stream, static_cast<const T*>(state), static_cast<const T*>(force),
+                         static_cast<const T*>(lam_next), static_cast<T*>(lam_prev),
+                         static_cast<T*>(lam_u), static_cast<T*>(lam_f), tiles, c->geom,
+                         (T)c->desc.omega, c->partials, nbins);
+      return hipGetLastError();
+    });
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bins, dim3(1), dim3(64), 0, c->stream, c->partials, nbins, grad);
     e = hipGetLastError();
     c->bins_clean = e == hipSuccess;
     return e;
   }
-  hipLaunchKernelGGL((k_adj_liquid<T, GENERAL>), dim3(div_up(c->geom.N, 256)), dim3(256), 0,
-                     c->stream, static_cast<const T*>(state), static_cast<const T*>(force),
-                     static_cast<const T*>(lam_next), static_cast<T*>(lam_prev),
-                     static_cast<T*>(lam_u), static_cast<T*>(lam_f), c->geom, (T)c->desc.omega,
-                     grad);
-  return hipGetLastError();
+  return timed_adjoint(c, [&] {
+    hipLaunchKernelGGL((k_adj_liquid<T, GENERAL>), dim3(div_up(c->geom.N, 256)), dim3(256), 0,
+                       c->stream, static_cast<const T*>(state), static_cast<const T*>(force),
+                       static_cast<const T*>(lam_next), static_cast<T*>(lam_prev),
+                       static_cast<T*>(lam_u), static_cast<T*>(lam_f), c->geom, (T)c->desc.omega,
+                       grad);
+    return hipGetLastError();
+  });
 }
 
 template <typename T>
@@ -627,6 +642,13 @@ lbm_status lbm_adjoint_liquid(lbm_ctx* ctx, const void* state, const void* force
                               double* grad) {
   return lbm_adjoint_liquid_tiles(ctx, state, force, lam_next, lam_prev, lam_u, lam_f, nullptr,
                                   grad);
+}
+
+lbm_status lbm_time_next_adjoint_liquid(lbm_ctx* ctx, void* start, void* end) {
+  if (!ctx) return LBM_EINVAL;
+  ctx->ta_start = static_cast<hipEvent_t>(start);
+  ctx->ta_end = static_cast<hipEvent_t>(end);
+  return LBM_OK;
 }
 
 lbm_status lbm_adjoint_bubbles(lbm_ctx* ctx, const bubble_params* p, const double* record,

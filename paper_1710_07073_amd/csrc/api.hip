@@ -186,6 +186,7 @@ lbm_status lbm_init(const lbm_desc* desc, void* pops_a, void* pops_b, void* forc
   c->side = nullptr;
   c->ev_fork = c->ev_join = nullptr;
   c->t_start = c->t_end = nullptr;
+  c->ta_start = c->ta_end = nullptr;
   c->arm_record = nullptr;
   const unsigned ev_flags = hipEventDisableTiming | hipEventDisableSystemFence;
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;

@@ -56,6 +56,7 @@ struct lbm_ctx {
   hipEvent_t ev_fork, ev_join;
   // caller's events recorded around the next bulk (or whole-lattice) liquid launch, one-shot
   hipEvent_t t_start, t_end;
+  hipEvent_t ta_start, ta_end;  // one-shot events around the next adjoint liquid launch
   // caller's step record the next bubble half fills (lbm_record_next_bubble_half), one-shot
   double* arm_record;
   int32_t pending_nb;  // bubbles of the pending overlapped step

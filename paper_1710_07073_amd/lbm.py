@@ -29,7 +29,8 @@ LBM_COUPLING_POINT_KERNEL, LBM_COUPLING_EXACT_TIME = 4, 8
 # every symbol include/lbm.h declares
 EXPORTS = ("lbm_bytes_required", "lbm_init", "lbm_set_stream", "lbm_set_launch", "lbm_get_launch",
            "lbm_set_step_occupancy", "lbm_get_step_occupancy",
-           "lbm_set_overlap", "lbm_get_overlap", "lbm_time_next_step", "lbm_region_cells",
+           "lbm_set_overlap", "lbm_get_overlap", "lbm_time_next_step", "lbm_time_next_adjoint_liquid",
+           "lbm_region_cells",
            "lbm_step", "bubbles_step", "bubbles_step_static_work",
            "moments", "lbm_populations", "lbm_state_buffer", "lbm_check", "lbm_run", "lbm_destroy",
            "lbm_status_string",
@@ -100,6 +101,7 @@ def lib():
         L.lbm_get_step_occupancy.argtypes = [P, ct.POINTER(ct.c_int32)]
         L.lbm_set_overlap.argtypes = [P, ct.c_int32]
         L.lbm_time_next_step.argtypes = [P, P, P]
+        L.lbm_time_next_adjoint_liquid.argtypes = [P, P, P]
         L.lbm_region_cells.argtypes = [P, ct.POINTER(ct.c_int64)]
         L.lbm_get_overlap.argtypes = [P, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]
         L.lbm_step.argtypes = [P, ct.c_int32]
@@ -229,6 +231,12 @@ def lbm_time_next_step(ctx, start, end):
     """start, end: torch.cuda.Event objects (already recorded once, so that they exist) or None."""
     h = lambda e: None if e is None else ct.c_void_p(e.cuda_event)
     _ok(lib().lbm_time_next_step(ctx, h(start), h(end)), "lbm_time_next_step")
+
+
+def lbm_time_next_adjoint_liquid(ctx, start, end):
+    """start, end: torch.cuda.Event objects (already recorded once, so that they exist) or None."""
+    h = lambda e: None if e is None else ct.c_void_p(e.cuda_event)
+    _ok(lib().lbm_time_next_adjoint_liquid(ctx, h(start), h(end)), "lbm_time_next_adjoint_liquid")
 
 
 def lbm_region_cells(ctx):
