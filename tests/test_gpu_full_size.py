@@ -47,16 +47,20 @@ def test_single_fp32_full_size_matches_oracle():
     assert x[2, 0] > w.pos[2, 0]  # the bubble rose
 
 
-def _gpu_run(w, precision, steps):
-    """steps coupled method steps of w in the benchmark's launch configuration (one cell per
-    thread, x-width 128, overlapped steps replayed from 20-step graphs)."""
+def _gpu_run(w, precision, checkpoints):
+    """Coupled method steps of w in the benchmark's launch configuration (one cell per thread,
+    x-width 128, overlapped steps replayed from 20-step graphs): the state after each of the
+    step counts in checkpoints."""
     import dataclasses
     sim = gpu_sim(dataclasses.replace(w, dtype=precision))
     L.lbm_set_launch(sim.ctx, 1, 128)
-    sim.run(steps, graph_steps=20)
-    _, u, sums = sim.moments()
-    out = dict(u=u.double().cpu().numpy(), x=sim.bubbles.positions(),
-               v=sim.bubbles.velocities(), sums=np.asarray(sums))
+    out, done = {}, 0
+    for k in checkpoints:
+        sim.run(k - done, graph_steps=20)
+        done = k
+        _, u, sums = sim.moments()
+        out[k] = dict(u=u.double().cpu().numpy(), x=sim.bubbles.positions(),
+                      v=sim.bubbles.velocities(), sums=np.asarray(sums))
     sim.check()
     sim.close()
     del sim
@@ -64,28 +68,41 @@ def _gpu_run(w, precision, steps):
     return out
 
 
-@pytest.mark.gpu
-@pytest.mark.timeout(900)
-def test_single_column_1000_steps_fp32_and_fp64_match_oracle():
-    """1000 coupled steps of the full 128 x 128 x 512 column, FP32 and FP64, against one oracle
-    run: u relative L2 <= 2e-5 (FP32) and <= 1e-12 (FP64), bubble position <= 1e-4 lattice units."""
+@pytest.fixture(scope="module")
+def long_run():
+    """FP32 and FP64 GPU runs of the full column (state after 500 and after 1000 steps) and the
+    oracle at step 0; the tests advance the oracle in turn, so each reports within about a
+    minute."""
     w = W.single_fp32(steps=1000)
     print(f"[case] {w.name}: {w.cells} sites, {w.steps} steps, FP32 and FP64", flush=True)
-    r32 = _gpu_run(w, "f32", w.steps)
-    r64 = _gpu_run(w, "f64", w.steps)
+    runs = {"f32": _gpu_run(w, "f32", (500, 1000)), "f64": _gpu_run(w, "f64", (500, 1000))}
     lat, bub, P = oracle_state(w)
-    for k in range(w.steps):
+    return dict(w=w, runs=runs, lat=lat, bub=bub, P=P, done=[0])
+
+
+@pytest.mark.gpu
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("upto", [500, 1000])
+def test_single_column_1000_steps_fp32_and_fp64_match_oracle(long_run, upto):
+    """1000 coupled steps of the full 128 x 128 x 512 column, FP32 and FP64, against one oracle
+    run, checked after 500 and after 1000 steps: u relative L2 <= 2e-5 (FP32) and <= 1e-12
+    (FP64), bubble position <= 1e-4 lattice units (FP64: 1e-10)."""
+    r = long_run
+    w, lat, bub, P = r["w"], r["lat"], r["bub"], r["P"]
+    for k in range(r["done"][0], upto):
         O.method_step(lat, P, bub)
-        if (k + 1) % 200 == 0:
+        if (k + 1) % 100 == 0:
             print(f"  oracle step {k + 1}", flush=True)
+    r["done"][0] = upto
     _, u_o, sums_o = lat.moments()
-    for name, r, utol, xtol in (("f32", r32, U_TOL, POS_TOL), ("f64", r64, 1e-12, 1e-10)):
-        eu = rel_l2(r["u"], u_o)
-        dx = np.abs(r["x"] - bub.pos).max()
-        dv = np.abs(r["v"] - bub.vel).max() / np.abs(bub.vel).max()
-        dm = abs(r["sums"][0] - sums_o[0])
-        print(f"{name}: u rel-L2 {eu:.2e}, |dx_b| {dx:.2e}, u_b rel {dv:.2e}, mass {dm:.1e}",
-              flush=True)
+    for name, utol, xtol in (("f32", U_TOL, POS_TOL), ("f64", 1e-12, 1e-10)):
+        g = r["runs"][name][upto]
+        eu = rel_l2(g["u"], u_o)
+        dx = np.abs(g["x"] - bub.pos).max()
+        dv = np.abs(g["v"] - bub.vel).max() / np.abs(bub.vel).max()
+        dm = abs(g["sums"][0] - sums_o[0])
+        print(f"{name} step {upto}: u rel-L2 {eu:.2e}, |dx_b| {dx:.2e}, u_b rel {dv:.2e}, "
+              f"mass {dm:.1e}", flush=True)
         assert eu <= utol, (name, eu)
         assert dx <= xtol, (name, dx)
-    assert bub.pos[2, 0] > w.pos[2, 0] + 0.01  # the bubble rose
+    assert bub.pos[2, 0] > w.pos[2, 0] + 0.005 * upto / 500  # the bubble rose
