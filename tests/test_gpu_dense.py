@@ -11,6 +11,7 @@ import torch
 import oracle as O
 import workloads as W
 from gpu_common import gpu_sim, oracle_state, rel_l2
+from paper_1710_07073_amd import lbm as L
 
 POS_TOL = 1e-4
 U_TOL = 2e-5
@@ -25,6 +26,8 @@ def dense_run():
     print(f"[case] {w.name}: {w.cells} cells, {w.nb} bubbles, omega {w.omega:.4f}, "
           f"{w.steps} steps", flush=True)
     sim = gpu_sim(w)
+    L.lbm_set_launch(sim.ctx, 1, 256)  # the width the benchmark's tuning keeps on this column
+    assert L.lbm_get_overlap(sim.ctx)[0]
     snaps = {}
     for k in (100, 200):
         sim.run(100, graph_steps=20)
@@ -65,6 +68,24 @@ def test_dense_column_full_size_matches_oracle(dense_run, upto):
     assert abs(g["sums"][0] - w.cells) < 1e-3
     # the bubbles rose (Stokes rise of a d = 3 bubble: about 0.005 in 100 steps)
     assert rise > 0.002 * upto / 100
+
+
+@pytest.mark.gpu
+def test_dense_column_serial_step_is_the_overlapped_step(dense_run):
+    """The serial method step (the benchmark's tuning keeps it when it is the faster) reproduces
+    the overlapped run of the first 200 steps bit for bit at full size."""
+    w = dense_run["w"]
+    sim = gpu_sim(w)
+    L.lbm_set_launch(sim.ctx, 1, 256)
+    L.lbm_set_overlap(sim.ctx, False)
+    sim.run(200, graph_steps=20)
+    _, u, _ = sim.moments()
+    g = dense_run["snaps"][200]
+    assert np.array_equal(u.double().cpu().numpy(), g["u"])
+    assert np.array_equal(sim.bubbles.positions(), g["pos"])
+    assert np.array_equal(sim.bubbles.velocities(), g["vel"])
+    sim.check()
+    sim.close()
 
 
 @pytest.mark.gpu
