@@ -208,3 +208,34 @@ def test_region_cells_reports_only_an_overlapped_last_step(graph_steps):
     assert L.lbm_region_cells(sim.ctx) == 0
     sim.check()
     sim.close()
+
+
+@pytest.mark.gpu
+def test_method_step_tuning_keeps_the_results():
+    """The method-step tuning (overlapped and serial steps, every occupancy cap) changes how the
+    steps run, not what they compute: the tuned run continues bit for bit like an untuned run of
+    the same number of steps."""
+    from paper_1710_07073_amd import autotune
+    shape = (128, 128, 256)  # 2^22 sites: the overlapped step is available and on by default
+    rng = np.random.default_rng(11)
+    nb = 200
+    pos = np.stack([rng.uniform(8, 119, nb), rng.uniform(8, 119, nb), rng.uniform(8, 60, nb)])
+    d = rng.uniform(2.0, 4.0, nb)
+    print(f"[case] {shape}, {nb} bubbles", flush=True)
+    a = S.Simulation(shape, 1.6, precision="f32")
+    a.add_bubbles(pos, d, S.bubble_params())
+    assert L.lbm_get_overlap(a.ctx) == (True, True)
+    cap, sweep, n = autotune.tune_method_occupancy(a, steps=2)
+    assert len(sweep) == 2 * len(autotune.OCCUPANCY)
+    assert {r[2] for r in sweep} == {True, False}
+    best = min(sweep, key=lambda r: r[1])
+    assert L.lbm_get_overlap(a.ctx)[0] == best[2] and L.lbm_get_step_occupancy(a.ctx) == cap
+    a.run(10, graph_steps=10)
+    b = S.Simulation(shape, 1.6, precision="f32")
+    b.add_bubbles(pos, d, S.bubble_params())
+    b.step(n + 10)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+    assert np.array_equal(a.bubbles.positions(), b.bubbles.positions())
+    for s in (a, b):
+        s.check()
+        s.close()
