@@ -88,6 +88,11 @@ def test_null_context_calls_are_rejected():
     assert lib.lbm_get_step_occupancy(None, ct.byref(out)) == L.LBM_EINVAL
     assert lib.lbm_set_overlap(None, 1) == L.LBM_EINVAL
     assert lib.lbm_record_next_bubble_half(None, None) == L.LBM_EINVAL
+    assert lib.lbm_time_next_step(None, None, None) == L.LBM_EINVAL
+    assert lib.lbm_time_next_adjoint_liquid(None, None, None) == L.LBM_EINVAL
+    assert lib.lbm_step_tiles(None, None, None) == L.LBM_EINVAL
+    assert lib.lbm_checkpoint(None, None, None) == L.LBM_EINVAL
+    assert lib.lbm_restore(None, None, None) == L.LBM_EINVAL
     assert lib.lbm_batch_set_step_occupancy(None, 3) == L.LBM_EINVAL
     assert lib.lbm_batch_get_step_occupancy(None, ct.byref(out)) == L.LBM_EINVAL
     assert out.value == -7  # nothing written on rejection
